@@ -1,0 +1,179 @@
+"""Benchmark: plain FP64 one-cell inversion on one MI355X.
+
+One bench step = one full solve of the workload from its initial condition:
+rebuild and LU-factor every region's operator (oci_refactor), reset the state,
+then 100 MB time steps of OCI iterations to tolerance (oci_solve).  The metric
+is OCI cell-angle updates per second: sum over iterations of J*N, divided by
+wall time.  Source iteration on the same problem and the time to a 1e-6
+tolerance are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "OCI cell·angle updates/s + time-to-1e-6 per step: learned/mixed vs plain OCI"
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_bytes_per_cell_iteration(n_angles):
+    """Values one OCI iteration must move per cell, 8 bytes each: incident
+    fluxes in (2N), the step constant [g; h] in (2N+4), outgoing fluxes out
+    (2N), new scalar flux out (4) and old scalar flux in (4) for the residual."""
+    return 8 * (6 * n_angles + 12)
+
+
+def cpu_baseline(prob, n_steps, gpu_phi):
+    """The oracle's OCI (per-region LU + multi-right-hand-side solves) timed on
+    the host for the first n_steps of the workload."""
+    from oracle import oci as ooci
+    from oracle.problem import cell_data
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    cd = cell_data(prob)
+    t0 = time.perf_counter()
+    res = ooci.run_oci(prob, cd, n_steps, tol=prob.tol, max_iters=prob.max_iters)
+    dt = time.perf_counter() - t0
+    its = sum(r["iterations"] for r in res)
+    updates = its * cd.J * cd.n
+    err = None
+    if gpu_phi is not None:
+        err = max(float(np.max(np.abs(gpu_phi[k] - res[k]["phi"])) / np.max(np.abs(res[k]["phi"])))
+                  for k in range(n_steps))
+    return {"value": updates / dt, "unit": "cell·angle updates/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "first %d of %d time steps of the same workload (%d iterations, %.1f s), "
+                      "operator factorisation included" % (n_steps, prob.n_steps, its, dt),
+            "host_cpu_count": os.cpu_count()}, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the OCI path here is single-GPU "
+              "(multi-GPU sharding is described, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_13555_amd import oci, workloads
+
+    torch.cuda.set_device(0)
+    prob = workloads.config2()
+    J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
+    stream = torch.cuda.current_stream()
+    ctx = oci.OciContext(prob, stream=stream)
+    phi_dev = torch.zeros((T, J, 4), dtype=torch.float64, device="cuda")
+
+    def one_solve():
+        ctx.refactor(prob)
+        ctx.set_state(None, 0)
+        rc, infos = ctx.solve(T, phi_dev)
+        if rc < 0 or any(i["status"] != oci.OCI_OK for i in infos):
+            raise RuntimeError("solve failed: rc=%d" % rc)
+        return infos
+
+    for _ in range(args.warmup):
+        one_solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_infos = []
+    for _ in range(args.steps):
+        all_infos.append(one_solve())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    iters = sum(i["iterations"] for infos in all_infos for i in infos)
+    launches = sum(i["launches"] for infos in all_infos for i in infos)
+    iter_ms = sum(i["iter_ms"] for infos in all_infos for i in infos)
+    value = iters * J * N / wall
+    per_launch_s = iter_ms * 1e-3 / max(iters, 1)
+    bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J
+    achieved = bytes_launch / per_launch_s / 1e9
+    gpu_phi = phi_dev.cpu().numpy()
+
+    # time to a 1e-6 tolerance per step, and source iteration, same problem
+    def per_step_ms(tol, method, n):
+        with oci.OciContext(prob, stream=stream, tol=tol) as c2:
+            ms, its = [], []
+            for _ in range(n):
+                rc, info = c2.step() if method == "oci" else c2.si_step()
+                ms.append(info["ms"])
+                its.append(info["iterations"])
+        return float(np.mean(ms)), float(np.mean(its))
+
+    t6_ms, t6_its = per_step_ms(1e-6, "oci", T)
+    si_ms, si_its = per_step_ms(prob.tol, "si", 10)
+    oci_ms = wall * 1e3 / (args.steps * T)
+
+    cpu, err = (None, None)
+    if not args.no_cpu:
+        cpu, err = cpu_baseline(prob, args.cpu_steps, gpu_phi[:args.cpu_steps])
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell·angle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain FP64 OCI vs SI: %s; sigma_t lognormal(0,1) clipped to "
+                        "[0.01, 10] with dx = 1, c ~ U[0.5, 0.99], Q ~ U[0, 1], dt = 0.05, "
+                        "v = 1, tol 1e-10 (seeded)" % prob.name,
+            "cells": J, "angles": N, "regions": prob.n_regions, "time_steps": T,
+            "tol": prob.tol, "step": "operator rebuild + LU + %d MB time steps" % T,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_oci_iterate",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_launch,
+            "us_per_launch": per_launch_s * 1e6,
+            "launches": launches,
+            "iterations": iters,
+        },
+        "cpu_baseline": cpu,
+        "iterations_per_time_step": iters / (args.steps * T),
+        "oci_ms_per_time_step": oci_ms,
+        "time_to_1e-6_ms_per_step": t6_ms,
+        "time_to_1e-6_iterations_per_step": t6_its,
+        "si_ms_per_time_step": si_ms,
+        "si_iterations_per_time_step": si_its,
+        "oci_over_si_speedup": si_ms / oci_ms,
+        "parity_vs_oracle_rel": err,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * oci.h -- C ABI of the MI355X one-cell-inversion (OCI) transport library.
+ *
+ * The library solves transient, mono-energetic, isotropically scattering
+ * slab-geometry S_N transport (Sec. "Derivation of MB-SCB", the S_N equation
+ * with its initial and boundary conditions), discretised with simple corner
+ * balance in space and multiple balance in time (eq:scb-mb-a .. eq:scb-mb-d,
+ * with the cell-midpoint average closure and the upstream cell-edge closure).
+ * Each time step is iterated to tolerance either by one-cell inversion
+ * (Sec. "One-Cell Inversion (OCI)": every cell solves its dense 4N x 4N
+ * all-angle system (A - S) Psi = c with the incident fluxes of its neighbours
+ * from the previous iterate -- parallel block Jacobi) or by source iteration
+ * (Sec. "Source Iteration (SI)": 4x4 solves per cell and angle in transport
+ * sweeps with a lagged scalar flux).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Angles: N even, Gauss-Legendre (Sec. "ONE-CELL INVERSION": Gauss-Legendre
+ *   in all explorations), ascending mu, so angles 0 .. N/2-1 have mu < 0 and
+ *   angle N-1-m mirrors angle m; weights sum to 2.
+ * Cells: J = sum of the region cell counts, numbered left to right; region r
+ *   has uniform width dx_r = width_r / cells_r and data Sigma_r, Sigma_s,r, Q_r.
+ * Scalar flux phi: [J][4] per cell, components
+ *   phi_{k,L}, phi_{k,R}, phi_{k+1/2,L}, phi_{k+1/2,R}
+ *   (time-average and time-edge values on the left and right half cells),
+ *   phi = sum_n w_n psi_n (SI subsection).
+ * Time-edge state psi_edge: [J][N][2] = psi_{m,k+1/2} on the L and R half
+ *   cells of every cell and angle; it is the psi_{k-1/2} of the next step.
+ * Stopping rule (the paper iterates "until the flux stops changing" without
+ *   naming a norm; reading taken here): iterate l is accepted when
+ *   e_l = max|phi^(l) - phi^(l-1)| / max|phi^(l)| <= tol over all cells and
+ *   components; with OCI_FLAG_STRICT also e_l*rho/(1-rho) <= tol with
+ *   rho = e_l/e_{l-1} clamped to [0, 0.9999].  OCI's first iterate of a step
+ *   has no predecessor and is never accepted.
+ * Warm start: the first step starts OCI from zero incident fluxes and SI from
+ *   zero scalar flux; later steps start from the previous step's last iterate.
+ * Reflecting edges: the incoming flux of angle m equals the outgoing flux of
+ *   angle N-1-m at the same edge and time level; OCI takes it from the
+ *   previous iterate (like every incident flux), SI sweeps the reflected
+ *   direction second and takes it from the same iteration (when both edges
+ *   reflect, the right edge is lagged by one iteration).
+ * Streams: a context is bound to the HIP stream given to oci_setup; all GPU
+ *   work is enqueued on it.  Calls on one context are not thread-safe;
+ *   separate contexts are independent.
+ * Memory: the library owns every device allocation it makes (in oci_setup,
+ *   released by oci_destroy).  Caller buffers are only read or written during
+ *   the call that receives them.  A pointer argument documented as "host or
+ *   device" is a device pointer when the matching on_device flag is nonzero.
+ * Errors: every int-returning call returns an OCI_* code; no C++ exception
+ *   crosses this boundary.  oci_last_error() gives a message for the last
+ *   failure on a context.  OCI_NOT_CONVERGED is positive: the step finished
+ *   with its last iterate and the state advanced.
+ */
+#ifndef OCI_H
+#define OCI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  OCI_OK = 0,
+  OCI_NOT_CONVERGED = 1, /* max_iters reached; state advanced with the last iterate */
+  OCI_EINVAL = -1,       /* invalid argument; nothing was changed */
+  OCI_ENOMEM = -2,       /* device allocation failed */
+  OCI_EDEVICE = -3,      /* a HIP call failed */
+  OCI_ENONFINITE = -4,   /* the scalar flux became NaN or Inf; the step is abandoned */
+  OCI_ESTATE = -5        /* call not valid in the context's current state */
+};
+
+enum { OCI_BC_VACUUM = 0, OCI_BC_REFLECT = 1, OCI_BC_INCIDENT = 2 };
+
+enum { OCI_PREC_FP64 = 0 };
+
+/* flags */
+#define OCI_FLAG_STRICT 1u /* add the a-posteriori error bound to the stopping rule */
+
+#define OCI_MAX_ANGLES 256
+
+typedef struct oci_ctx oci_ctx;
+
+/* Problem description, read only during oci_setup (which copies it). */
+typedef struct {
+  int32_t n_angles;          /* N: even, 2 .. OCI_MAX_ANGLES */
+  const double *mu, *w;      /* [N] quadrature override (ascending, mirror-symmetric,
+                                nonzero mu), or both NULL for Gauss-Legendre */
+  int32_t n_regions;         /* R >= 1 */
+  const int32_t *cells;      /* [R] cells per region, each >= 1 */
+  const double *width;       /* [R] region widths, > 0 */
+  const double *sigma_t;     /* [R] total cross sections, > 0 */
+  const double *sigma_s;     /* [R] scattering cross sections, >= 0 */
+  const double *source;      /* [R] isotropic sources Q, >= 0, time-constant */
+  double dt;                 /* time step, > 0 */
+  double speed;              /* particle speed v, > 0; +inf gives the steady equations */
+  int32_t bc_left, bc_right; /* OCI_BC_* */
+  const double *inc_left;    /* [N/2] incident psi at x = 0 for the mu > 0 angles
+                                (ascending), time-constant; required iff bc_left is
+                                OCI_BC_INCIDENT */
+  const double *inc_right;   /* [N/2] incident psi at x = X for the mu < 0 angles */
+  const double *psi0;        /* [J][N][2] initial psi on the L and R half cells, or NULL = 0 */
+  double tol;                /* stopping tolerance, >= 0 */
+  int32_t max_iters;         /* >= 1 iterations per step */
+  int32_t precision;         /* OCI_PREC_FP64 */
+  uint32_t flags;            /* OCI_FLAG_* */
+} oci_problem;
+
+typedef struct {
+  int32_t iterations;  /* iterations done in the step */
+  int32_t status;      /* OCI_OK, OCI_NOT_CONVERGED or OCI_ENONFINITE */
+  double residual;     /* e of the accepted (or last) iterate; -1 if undefined */
+  double ms;           /* time of the whole step on the stream, milliseconds */
+  double iter_ms;      /* stream time of the iteration launches alone (events
+                          around each batch of iteration kernels), milliseconds */
+  int32_t launches;    /* iteration kernels launched (>= iterations; the extra
+                          ones find the step decided and exit at once) */
+  int32_t pad;
+} oci_step_info;
+
+/* Build a context: validates *p, computes the quadrature, uploads the region
+ * table, builds and LU-factors every region's cell matrix A - S on the GPU
+ * (Sec. "PERFORMANCE ANALYSIS": dense solves by LU with partial pivoting;
+ * one factorisation per region because all cells of a region share it), and
+ * forms the operators applied each iteration.  hip_stream is a hipStream_t
+ * (NULL = the null stream).  On success *out owns all device memory.
+ * Errors: OCI_EINVAL (bad problem, out == NULL), OCI_ENOMEM, OCI_EDEVICE. */
+int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out);
+
+/* Rebuild every region's operator for new region data (widths, cross
+ * sections, sources, dt, speed, tolerance) without reallocating: p must have
+ * the same n_angles, n_regions, cells, boundary-condition kinds and quadrature
+ * as the problem the context was built with (else OCI_EINVAL, context
+ * unchanged).  The time-edge state and the warm-start iterate are kept; psi0
+ * and the incident fluxes of p are ignored. */
+int oci_refactor(oci_ctx *c, const oci_problem *p);
+
+/* Advance one MB time step with OCI iterations to the stopping rule
+ * (Sec. "One-Cell Inversion (OCI)").  info may be NULL.
+ * Returns OCI_OK, OCI_NOT_CONVERGED, OCI_ENONFINITE or a negative error. */
+int oci_step(oci_ctx *c, oci_step_info *info);
+
+/* Advance one MB time step with source iteration (Sec. "Source Iteration
+ * (SI)"): the same step, the same stopping rule, on the same state, so OCI
+ * and SI steps may be mixed on one context.  max_iters = 1 gives one sweep. */
+int si_step(oci_ctx *c, oci_step_info *info);
+
+/* n_steps >= 0 calls of oci_step.  phi_out (host or device, per
+ * phi_out_on_device) receives [n_steps][J][4] scalar fluxes, or is NULL;
+ * infos receives [n_steps] records, or is NULL.  Stops early at the first
+ * negative code and returns it; otherwise returns OCI_NOT_CONVERGED if any
+ * step did not converge, else OCI_OK. */
+int oci_solve(oci_ctx *c, int32_t n_steps, double *phi_out, int32_t phi_out_on_device,
+              oci_step_info *infos);
+
+/* Scalar flux of the last completed step, [J][4] (host or device).
+ * OCI_ESTATE before the first step. */
+int oci_get_flux(oci_ctx *c, double *phi, int32_t on_device);
+
+/* Copy out the time-edge state [J][N][2] (host) and the number of completed
+ * steps.  Together with the warm-start iterate kept inside the context this
+ * is everything a later step reads; set_state restarts from psi_edge with a
+ * cold iterate (zero incident fluxes, zero scalar flux), exactly like the
+ * first step.  Either pointer may be NULL. */
+int oci_get_state(oci_ctx *c, double *psi_edge, int64_t *step);
+int oci_set_state(oci_ctx *c, const double *psi_edge, int64_t step);
+
+/* Quadrature and problem sizes of a context (host outputs; any may be NULL). */
+int oci_get_quadrature(const oci_ctx *c, double *mu, double *w);
+int oci_get_sizes(const oci_ctx *c, int32_t *n_angles, int32_t *n_cells, int32_t *n_regions);
+
+/* Per-region operator, for inspection and tests: [2N+4+2N][4N+1] row-major,
+ * rows = (outgoing flux 2N, phi 4, psi_edge 2N), columns = (incident flux 2N,
+ * psi_{k-1/2} 2N, source 1), i.e. the needed rows of (A - S)^{-1} applied to
+ * the columns through which the cell's right-hand side c enters.
+ * Outgoing / incident order: index 2m+t, t = 0 level k, 1 level k+1/2; the
+ * first N entries are the mu < 0 angles (left-half flux leaving / right
+ * neighbour's left-half flux entering), the last N the mu > 0 angles. */
+int oci_get_operator(oci_ctx *c, int32_t region, double *op);
+
+/* Release everything the context owns (waits for its stream).  NULL is a no-op. */
+void oci_destroy(oci_ctx *c);
+
+const char *oci_strerror(int code);
+const char *oci_last_error(const oci_ctx *c);
+
+/* Host-only helper: the N-point Gauss-Legendre rule, ascending (no GPU use).
+ * Returns OCI_EINVAL for n < 1 or n > 4096 or NULL outputs. */
+int oci_gauss_legendre(int32_t n, double *mu, double *w);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCI_H */

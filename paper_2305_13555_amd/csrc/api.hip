@@ -1,0 +1,730 @@
+// Host driver behind the C ABI declared in include/oci.h.
+//
+// One context = one slab problem bound to one HIP stream.  oci_setup builds
+// every region's operator on the GPU; oci_step launches the per-step constant
+// kernel, then chunks of iteration kernels as pre-instantiated HIP graphs
+// (each iteration kernel is a no-op once the device-side stopping decision
+// is taken, so a chunk may overshoot harmlessly), reads the 32-byte control
+// word back after each chunk, and finishes with the end-of-step kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "oci.h"
+#include "oci_kernels.h"
+
+using namespace ocik;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int kGraphSizes[] = {1, 2, 4, 8, 16, 32, 64};
+constexpr int kNumGraphSizes = sizeof(kGraphSizes) / sizeof(kGraphSizes[0]);
+
+}  // namespace
+
+struct oci_ctx {
+  hipStream_t stream = nullptr;
+  int N = 0, J = 0, R = 0, bcl = 0, bcr = 0, max_iters = 0, strict = 0;
+  double tol = 0.0, a = 0.0;
+  std::vector<double> mu, w;
+  std::vector<int> cells;
+  std::vector<double> ghost_left, ghost_right;   // [2N] each
+  int Mt = 0, Met = 0, ntiles = 0, grid = 0, W_it = 1, W_ed = 1, W_pv = 1;
+  size_t lds_it = 0, lds_pv = 0, lds_ed = 0;
+  int si_blocks = 0;
+  std::vector<void *> allocs;
+  double *d_mu = nullptr, *d_w = nullptr;
+  RegionDev *d_regions = nullptr;
+  TileDev *d_tiles = nullptr;
+  int *d_cell_region = nullptr;
+  double *d_op = nullptr;
+  double *d_fi = nullptr, *d_fp = nullptr, *d_cp = nullptr, *d_fe = nullptr, *d_ce = nullptr;
+  size_t fi_stride = 0, fp_stride = 0, cp_stride = 0, fe_stride = 0, ce_stride = 0;
+  double *d_gh = nullptr, *d_out[2] = {nullptr, nullptr}, *d_phi[2] = {nullptr, nullptr};
+  double *d_psi[2] = {nullptr, nullptr}, *d_phi_res = nullptr, *d_partial = nullptr;
+  double *d_ainv = nullptr, *d_contrib = nullptr, *d_lag = nullptr, *d_si_partial = nullptr;
+  StepState *d_st = nullptr;
+  StepState *h_st = nullptr;   // pinned host copy of the control word
+  int parity = 0;
+  int64_t steps = 0;
+  bool have_flux = false;
+  int last_oci_iters = 0, last_si_iters = 0;
+  hipGraphExec_t oci_graph[kNumGraphSizes] = {};
+  hipGraphExec_t si_graph[kNumGraphSizes] = {};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evA = nullptr, evB = nullptr;
+  bool quad_override = false;
+  double *ws_M = nullptr, *ws_X = nullptr;   // setup workspace, kept for oci_refactor
+  int *d_bad = nullptr;
+  double iter_ms = 0.0;                      // accumulated by run_chunks
+  int launches = 0;
+  std::string err;
+  StepArgs sa{};
+  SiArgs si{};
+};
+
+#define OCI_CK(ctx, call)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      char b_[256];                                                                   \
+      snprintf(b_, sizeof b_, "%s failed: %s", #call, hipGetErrorString(e_));         \
+      (ctx)->err = b_;                                                                \
+      g_last_error = b_;                                                              \
+      return e_ == hipErrorOutOfMemory ? OCI_ENOMEM : OCI_EDEVICE;                    \
+    }                                                                                 \
+  } while (0)
+
+static int fail(oci_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  g_last_error = msg;
+  return code;
+}
+
+template <class T>
+static int dalloc(oci_ctx *c, T **p, size_t count) {
+  void *q = nullptr;
+  OCI_CK(c, hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)));
+  c->allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return OCI_OK;
+}
+
+static int validate(const oci_problem *p, std::string *why) {
+  auto bad = [&](const char *m) { *why = m; return OCI_EINVAL; };
+  if (!p) return bad("problem is NULL");
+  const int N = p->n_angles;
+  if (N < 2 || N > OCI_MAX_ANGLES || (N & 1))
+    return bad("n_angles must be even and in [2, 256] (odd Gauss-Legendre sets contain mu = 0)");
+  if ((p->mu == nullptr) != (p->w == nullptr)) return bad("mu and w must be given together");
+  if (p->mu) {
+    for (int m = 0; m < N; ++m) {
+      if (!(std::isfinite(p->mu[m]) && std::isfinite(p->w[m]) && p->w[m] > 0.0))
+        return bad("quadrature weights must be positive and finite");
+      if (p->mu[m] == 0.0 || std::fabs(p->mu[m]) > 1.0) return bad("mu must be nonzero, |mu| <= 1");
+      if (m > 0 && !(p->mu[m] > p->mu[m - 1])) return bad("mu must be ascending");
+      if (std::fabs(p->mu[m] + p->mu[N - 1 - m]) > 1e-12) return bad("mu must be mirror-symmetric");
+    }
+  }
+  if (p->n_regions < 1 || !p->cells || !p->width || !p->sigma_t || !p->sigma_s || !p->source)
+    return bad("n_regions >= 1 and the region arrays are required");
+  long long J = 0;
+  for (int r = 0; r < p->n_regions; ++r) {
+    if (p->cells[r] < 1) return bad("every region needs >= 1 cell");
+    if (!(p->width[r] > 0.0) || !std::isfinite(p->width[r])) return bad("region width must be > 0");
+    if (!(p->sigma_t[r] > 0.0) || !std::isfinite(p->sigma_t[r])) return bad("sigma_t must be > 0");
+    if (!(p->sigma_s[r] >= 0.0) || !std::isfinite(p->sigma_s[r])) return bad("sigma_s must be >= 0");
+    if (!(p->source[r] >= 0.0) || !std::isfinite(p->source[r])) return bad("source must be >= 0");
+    J += p->cells[r];
+  }
+  if (J > (1LL << 28)) return bad("too many cells");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return bad("dt must be > 0");
+  if (!(p->speed > 0.0)) return bad("speed must be > 0 (inf for steady)");
+  for (int s = 0; s < 2; ++s) {
+    const int bc = s ? p->bc_right : p->bc_left;
+    const double *inc = s ? p->inc_right : p->inc_left;
+    if (bc < OCI_BC_VACUUM || bc > OCI_BC_INCIDENT) return bad("unknown boundary condition");
+    if (bc == OCI_BC_INCIDENT) {
+      if (!inc) return bad("incident boundary needs its [N/2] flux array");
+      for (int i = 0; i < N / 2; ++i)
+        if (!std::isfinite(inc[i])) return bad("incident flux must be finite");
+    }
+  }
+  if (!(p->tol >= 0.0)) return bad("tol must be >= 0");
+  if (p->max_iters < 1) return bad("max_iters must be >= 1");
+  if (p->precision != OCI_PREC_FP64) return bad("only OCI_PREC_FP64 is available");
+  if (p->flags & ~OCI_FLAG_STRICT) return bad("unknown flags");
+  if (p->psi0) {
+    for (long long i = 0; i < J * N * 2; ++i)
+      if (!std::isfinite(p->psi0[i])) return bad("psi0 must be finite");
+  }
+  return OCI_OK;
+}
+
+static int upload_ghosts(oci_ctx *c) {
+  const int K = 2 * c->N;
+  for (int b = 0; b < 2; ++b) {
+    OCI_CK(c, hipMemcpyAsync(c->d_out[b], c->ghost_left.data(), K * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    OCI_CK(c, hipMemcpyAsync(c->d_out[b] + (size_t)(c->J + 1) * K, c->ghost_right.data(),
+                             K * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
+  return OCI_OK;
+}
+
+// Cold iterate: zero outgoing fluxes (boundary rows kept), zero scalar flux,
+// zero lagged reflection, iteration parity 0.
+static int reset_iterate(oci_ctx *c) {
+  const int K = 2 * c->N;
+  for (int b = 0; b < 2; ++b) {
+    OCI_CK(c, hipMemsetAsync(c->d_out[b], 0, (size_t)(c->J + 2) * K * sizeof(double), c->stream));
+    OCI_CK(c, hipMemsetAsync(c->d_phi[b], 0, (size_t)c->J * 4 * sizeof(double), c->stream));
+  }
+  OCI_CK(c, hipMemsetAsync(c->d_lag, 0, (size_t)c->N * sizeof(double), c->stream));
+  OCI_CK(c, hipMemsetAsync(c->d_st, 0, sizeof(StepState), c->stream));
+  int rc = upload_ghosts(c);
+  if (rc) return rc;
+  c->last_oci_iters = 0;
+  c->last_si_iters = 0;
+  return OCI_OK;
+}
+
+static int build_graph(oci_ctx *c, bool si, int gi) {
+  hipGraphExec_t *slot = si ? &c->si_graph[gi] : &c->oci_graph[gi];
+  if (*slot) return OCI_OK;
+  const int count = kGraphSizes[gi];
+  hipGraph_t g;
+  OCI_CK(c, hipGraphCreate(&g, 0));
+  hipGraphNode_t prev = nullptr;
+  auto add = [&](void *fn, dim3 grid, dim3 block, size_t lds, void **args) -> hipError_t {
+    hipKernelNodeParams kp{};
+    kp.func = fn;
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e == hipSuccess) prev = node;
+    return e;
+  };
+  void *oci_args[] = {&c->sa};
+  void *si_args[] = {&c->si};
+  for (int i = 0; i < count; ++i) {
+    hipError_t e;
+    if (!si) {
+      e = add((void *)k_oci_iterate, dim3(c->grid), dim3(64 * c->W_it), c->lds_it, oci_args);
+    } else {
+      e = add((void *)k_si_sweep, dim3(c->N / 2), dim3(1024), 0, si_args);
+      if (e == hipSuccess) e = add((void *)k_si_reduce, dim3(c->si_blocks), dim3(256), 0, si_args);
+    }
+    if (e != hipSuccess) {
+      hipGraphDestroy(g);
+      return fail(c, OCI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipGraphInstantiate(slot, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    *slot = nullptr;
+    return fail(c, OCI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return OCI_OK;
+}
+
+static int pick_graph(int want) {
+  for (int i = 0; i < kNumGraphSizes; ++i)
+    if (kGraphSizes[i] >= want) return i;
+  return kNumGraphSizes - 1;
+}
+
+// Build, factor and pack every region's operator (region table, mu, w and a
+// already on the device / in the context).
+static int build_operators(oci_ctx *c) {
+  const int N = c->N, K = 2 * N, R = c->R;
+  double *ws_M = c->ws_M, *ws_X = c->ws_X;
+  int *d_bad = c->d_bad;
+  OCI_CK(c, hipMemsetAsync(d_bad, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_build_system, dim3(R), dim3(256), 0, c->stream, c->d_regions, c->d_mu,
+                     c->d_w, N, c->a, ws_M, ws_X);
+  hipLaunchKernelGGL(k_lu_solve, dim3(R), dim3(1024), 0, c->stream, N, ws_M, ws_X, d_bad);
+  hipLaunchKernelGGL(k_select_rows, dim3(R), dim3(256), 0, c->stream, N, c->d_w, ws_X, c->d_op);
+  // iteration operator G: rows [0, 2N+4), columns [0, 2N) (incident)
+  hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, 0, K,
+                     c->Mt, c->d_fi, c->fi_stride, (double *)nullptr, (size_t)0);
+  // per-step operator P: rows [0, 2N+4), columns [2N, 4N) (psi_{k-1/2}); source column
+  hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, K, K,
+                     c->Mt, c->d_fp, c->fp_stride, c->d_cp, c->cp_stride);
+  // end-of-step operator E: rows [2N+4, 4N+4), columns [0, 4N)
+  hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N + 4, K, 0,
+                     2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride);
+  hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
+                     c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
+  OCI_CK(c, hipGetLastError());
+  int bad = 0;
+  OCI_CK(c, hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  OCI_CK(c, hipStreamSynchronize(c->stream));
+  if (bad) return fail(c, OCI_EINVAL, "a region's cell matrix A - S is singular");
+  return OCI_OK;
+}
+
+static void drop_graphs(oci_ctx *c) {
+  for (int i = 0; i < kNumGraphSizes; ++i) {
+    if (c->oci_graph[i]) hipGraphExecDestroy(c->oci_graph[i]);
+    if (c->si_graph[i]) hipGraphExecDestroy(c->si_graph[i]);
+    c->oci_graph[i] = nullptr;
+    c->si_graph[i] = nullptr;
+  }
+}
+
+extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) {
+  if (!out) return fail(nullptr, OCI_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (validate(p, &why) != OCI_OK) return fail(nullptr, OCI_EINVAL, why);
+
+  oci_ctx *c = new oci_ctx();
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  const int N = p->n_angles, K = 2 * N, R = p->n_regions;
+  c->N = N;
+  c->R = R;
+  c->bcl = p->bc_left;
+  c->bcr = p->bc_right;
+  c->tol = p->tol;
+  c->max_iters = p->max_iters;
+  c->strict = (p->flags & OCI_FLAG_STRICT) ? 1 : 0;
+  c->a = std::isinf(p->speed) ? 0.0 : 1.0 / (p->speed * p->dt);
+  c->mu.resize(N);
+  c->w.resize(N);
+  c->quad_override = p->mu != nullptr;
+  if (p->mu) {
+    std::copy(p->mu, p->mu + N, c->mu.begin());
+    std::copy(p->w, p->w + N, c->w.begin());
+  } else {
+    oci_gauss_legendre(N, c->mu.data(), c->w.data());
+  }
+  // region table and 16-cell tiles (a tile never straddles a region)
+  std::vector<RegionDev> regions(R);
+  std::vector<TileDev> tiles;
+  std::vector<int> cell_region;
+  int j0 = 0;
+  for (int r = 0; r < R; ++r) {
+    const int nc = p->cells[r];
+    regions[r] = RegionDev{j0, nc, p->width[r] / nc, p->sigma_t[r], p->sigma_s[r], p->source[r]};
+    for (int t0 = 0; t0 < nc; t0 += kTileCells)
+      tiles.push_back(TileDev{r, j0 + t0, std::min(kTileCells, nc - t0), 0});
+    cell_region.insert(cell_region.end(), nc, r);
+    c->cells.push_back(nc);
+    j0 += nc;
+  }
+  const int J = j0;
+  c->J = J;
+  c->ntiles = (int)tiles.size();
+  c->grid = 8 * ((c->ntiles + 7) / 8);
+  c->Mt = (2 * N + 4 + 15) / 16;
+  c->Met = (2 * N + 15) / 16;
+  c->W_it = std::min(c->Mt, kMaxWaves);
+  c->W_pv = std::min(c->Mt, kMaxWaves);
+  c->W_ed = std::min(c->Met, kMaxWaves);
+  const int P = K + 2;
+  c->lds_it = (size_t)(kTileCells + 2) * P * sizeof(double);
+  c->lds_pv = (size_t)kTileCells * P * sizeof(double);
+  c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
+  c->si_blocks = (J * 4 + 255) / 256;
+  c->ghost_left.assign(K, 0.0);
+  c->ghost_right.assign(K, 0.0);
+  if (p->bc_left == OCI_BC_INCIDENT)
+    for (int i = 0; i < N / 2; ++i) {
+      const int m = N / 2 + i;
+      c->ghost_left[2 * m] = c->ghost_left[2 * m + 1] = p->inc_left[i];
+    }
+  if (p->bc_right == OCI_BC_INCIDENT)
+    for (int m = 0; m < N / 2; ++m) c->ghost_right[2 * m] = c->ghost_right[2 * m + 1] = p->inc_right[m];
+
+  int rc = OCI_OK;
+  auto cleanup = [&](int code) {
+    oci_destroy(c);
+    return code;
+  };
+#define OCI_TRY(x)                    \
+  do {                                \
+    rc = (x);                         \
+    if (rc != OCI_OK) {               \
+      g_last_error = c->err;          \
+      return cleanup(rc);             \
+    }                                 \
+  } while (0)
+
+  const int n = 4 * N, nr = n + 1, oprows = 4 * N + 4;
+  c->fi_stride = (size_t)c->Mt * (K / 4) * 64;
+  c->fp_stride = c->fi_stride;
+  c->cp_stride = (size_t)c->Mt * 16;
+  c->fe_stride = (size_t)c->Met * (2 * K / 4) * 64;
+  c->ce_stride = (size_t)c->Met * 16;
+  OCI_TRY(dalloc(c, &c->d_mu, N));
+  OCI_TRY(dalloc(c, &c->d_w, N));
+  OCI_TRY(dalloc(c, &c->d_regions, R));
+  OCI_TRY(dalloc(c, &c->d_tiles, c->ntiles));
+  OCI_TRY(dalloc(c, &c->d_cell_region, J));
+  OCI_TRY(dalloc(c, &c->d_op, (size_t)R * oprows * nr));
+  OCI_TRY(dalloc(c, &c->d_fi, (size_t)R * c->fi_stride));
+  OCI_TRY(dalloc(c, &c->d_fp, (size_t)R * c->fp_stride));
+  OCI_TRY(dalloc(c, &c->d_cp, (size_t)R * c->cp_stride));
+  OCI_TRY(dalloc(c, &c->d_fe, (size_t)R * c->fe_stride));
+  OCI_TRY(dalloc(c, &c->d_ce, (size_t)R * c->ce_stride));
+  OCI_TRY(dalloc(c, &c->d_gh, (size_t)J * c->Mt * 16));
+  for (int b = 0; b < 2; ++b) {
+    OCI_TRY(dalloc(c, &c->d_out[b], (size_t)(J + 2) * K));
+    OCI_TRY(dalloc(c, &c->d_phi[b], (size_t)J * 4));
+    OCI_TRY(dalloc(c, &c->d_psi[b], (size_t)J * K));
+  }
+  OCI_TRY(dalloc(c, &c->d_phi_res, (size_t)J * 4));
+  OCI_TRY(dalloc(c, &c->d_partial, (size_t)c->ntiles * 4));
+  OCI_TRY(dalloc(c, &c->d_ainv, (size_t)R * N * 16));
+  OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(N / 2) * J * 4));
+  OCI_TRY(dalloc(c, &c->d_lag, (size_t)N));
+  OCI_TRY(dalloc(c, &c->d_si_partial, (size_t)c->si_blocks * 4));
+  OCI_TRY(dalloc(c, &c->d_st, 1));
+  {
+    void *h = nullptr;
+    if (hipHostMalloc(&h, sizeof(StepState), hipHostMallocDefault) != hipSuccess)
+      return cleanup(fail(c, OCI_ENOMEM, "hipHostMalloc failed"));
+    c->h_st = static_cast<StepState *>(h);
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreate(&c->evA) != hipSuccess || hipEventCreate(&c->evB) != hipSuccess)
+    return cleanup(fail(c, OCI_EDEVICE, "hipEventCreate failed"));
+
+  auto up = [&](void *dst, const void *src, size_t bytes) -> int {
+    OCI_CK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return OCI_OK;
+  };
+  OCI_TRY(up(c->d_mu, c->mu.data(), N * sizeof(double)));
+  OCI_TRY(up(c->d_w, c->w.data(), N * sizeof(double)));
+  OCI_TRY(up(c->d_regions, regions.data(), R * sizeof(RegionDev)));
+  OCI_TRY(up(c->d_tiles, tiles.data(), tiles.size() * sizeof(TileDev)));
+  OCI_TRY(up(c->d_cell_region, cell_region.data(), (size_t)J * sizeof(int)));
+
+  OCI_TRY(dalloc(c, &c->ws_M, (size_t)R * n * n));
+  OCI_TRY(dalloc(c, &c->ws_X, (size_t)R * n * nr));
+  OCI_TRY(dalloc(c, &c->d_bad, 1));
+  OCI_TRY(build_operators(c));
+
+  // ---- state ----
+  OCI_TRY(reset_iterate(c));
+  if (p->psi0) {
+    OCI_TRY(up(c->d_psi[0], p->psi0, (size_t)J * K * sizeof(double)));
+  } else {
+    OCI_CK(c, hipMemsetAsync(c->d_psi[0], 0, (size_t)J * K * sizeof(double), c->stream));
+  }
+  OCI_CK(c, hipMemsetAsync(c->d_psi[1], 0, (size_t)J * K * sizeof(double), c->stream));
+  OCI_CK(c, hipMemsetAsync(c->d_phi_res, 0, (size_t)J * 4 * sizeof(double), c->stream));
+
+  // ---- kernel argument blocks ----
+  StepArgs &s = c->sa;
+  s.tiles = c->d_tiles;
+  s.ntiles = c->ntiles;
+  s.N = N;
+  s.J = J;
+  s.Mt = c->Mt;
+  s.Met = c->Met;
+  s.bcl = c->bcl;
+  s.bcr = c->bcr;
+  s.max_iters = c->max_iters;
+  s.strict = c->strict;
+  s.tol = c->tol;
+  s.frag_it = c->d_fi;
+  s.frag_it_stride = c->fi_stride;
+  s.frag_pv = c->d_fp;
+  s.frag_pv_stride = c->fp_stride;
+  s.c_pv = c->d_cp;
+  s.c_pv_stride = c->cp_stride;
+  s.frag_ed = c->d_fe;
+  s.frag_ed_stride = c->fe_stride;
+  s.c_ed = c->d_ce;
+  s.c_ed_stride = c->ce_stride;
+  s.gh = c->d_gh;
+  s.out0 = c->d_out[0];
+  s.out1 = c->d_out[1];
+  s.phi0 = c->d_phi[0];
+  s.phi1 = c->d_phi[1];
+  s.psi0 = c->d_psi[0];
+  s.psi1 = c->d_psi[1];
+  s.phi_res = c->d_phi_res;
+  s.partial = c->d_partial;
+  s.st = c->d_st;
+  s.step_parity = 0;
+  SiArgs &q = c->si;
+  q.N = N;
+  q.J = J;
+  q.bcl = c->bcl;
+  q.bcr = c->bcr;
+  q.max_iters = c->max_iters;
+  q.strict = c->strict;
+  q.tol = c->tol;
+  q.a = c->a;
+  q.regions = c->d_regions;
+  q.cell_region = c->d_cell_region;
+  q.mu = c->d_mu;
+  q.w = c->d_w;
+  q.ainv = c->d_ainv;
+  q.out0 = c->d_out[0];
+  q.out1 = c->d_out[1];
+  q.phi0 = c->d_phi[0];
+  q.phi1 = c->d_phi[1];
+  q.psi0 = c->d_psi[0];
+  q.psi1 = c->d_psi[1];
+  q.contrib = c->d_contrib;
+  q.lag = c->d_lag;
+  q.phi_res = c->d_phi_res;
+  q.partial = c->d_si_partial;
+  q.nparts = c->si_blocks;
+  q.st = c->d_st;
+
+  // kernels with more than 64 KiB of dynamic LDS must say so
+  hipFuncSetAttribute((const void *)k_oci_iterate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)c->lds_it);
+  hipFuncSetAttribute((const void *)k_step_begin, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)c->lds_pv);
+  hipFuncSetAttribute((const void *)k_step_end, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)c->lds_ed);
+  OCI_CK(c, hipStreamSynchronize(c->stream));
+#undef OCI_TRY
+  *out = c;
+  return OCI_OK;
+}
+
+static void fill_info(oci_ctx *c, oci_step_info *info, const StepState &st, int status, float ms) {
+  if (!info) return;
+  info->iterations = st.it;
+  info->status = status;
+  info->residual = st.e_last;
+  info->ms = ms;
+  info->iter_ms = c->iter_ms;
+  info->launches = c->launches;
+  info->pad = 0;
+}
+
+// Run graph chunks until the device says the step is decided.
+static int run_chunks(oci_ctx *c, bool si) {
+  c->iter_ms = 0.0;
+  c->launches = 0;
+  int want = std::max(si ? c->last_si_iters : c->last_oci_iters, si ? 1 : 2);
+  int launched = 0, extra = 0;
+  for (;;) {
+    const int gi = pick_graph(want);
+    int rc = build_graph(c, si, gi);
+    if (rc) return rc;
+    OCI_CK(c, hipEventRecord(c->evA, c->stream));
+    OCI_CK(c, hipGraphLaunch(si ? c->si_graph[gi] : c->oci_graph[gi], c->stream));
+    OCI_CK(c, hipEventRecord(c->evB, c->stream));
+    launched += kGraphSizes[gi];
+    OCI_CK(c, hipMemcpyAsync(c->h_st, c->d_st, sizeof(StepState), hipMemcpyDeviceToHost, c->stream));
+    OCI_CK(c, hipStreamSynchronize(c->stream));
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, c->evA, c->evB);
+    c->iter_ms += ms;
+    c->launches += kGraphSizes[gi];
+    if (c->h_st->done != kRunning) return OCI_OK;
+    if (launched > c->max_iters + 1)
+      return fail(c, OCI_EDEVICE, "iteration control word did not reach a decision");
+    // the previous step's count was short: continue one iteration at a time
+    // twice, then in doubling batches
+    ++extra;
+    want = extra <= 2 ? 1 : std::min(64, 1 << (extra - 2));
+  }
+}
+
+static int finish_step(oci_ctx *c, oci_step_info *info, bool si) {
+  const StepState st = *c->h_st;
+  if (st.done == kNonFinite) {
+    // abandon the step: keep psi_{k-1/2}, restart from a cold iterate
+    int rc = reset_iterate(c);
+    OCI_CK(c, hipStreamSynchronize(c->stream));
+    fill_info(c, info, st, OCI_ENONFINITE, 0.0f);
+    if (rc) return rc;
+    return fail(c, OCI_ENONFINITE, "the scalar flux became NaN or Inf");
+  }
+  (si ? c->last_si_iters : c->last_oci_iters) = st.it;
+  c->parity ^= 1;
+  c->steps += 1;
+  c->have_flux = true;
+  OCI_CK(c, hipEventRecord(c->ev1, c->stream));
+  OCI_CK(c, hipEventSynchronize(c->ev1));
+  float ms = 0.0f;
+  hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  const int status = st.done == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
+  fill_info(c, info, st, status, ms);
+  return status;
+}
+
+extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  std::string why;
+  if (validate(p, &why) != OCI_OK) return fail(c, OCI_EINVAL, why);
+  if (p->n_angles != c->N || p->n_regions != c->R || p->bc_left != c->bcl ||
+      p->bc_right != c->bcr || (p->mu != nullptr) != c->quad_override)
+    return fail(c, OCI_EINVAL, "refactor needs the same angles, regions and boundary kinds");
+  for (int r = 0; r < c->R; ++r)
+    if (p->cells[r] != c->cells[r]) return fail(c, OCI_EINVAL, "refactor needs the same cells");
+  if (p->mu)
+    for (int m = 0; m < c->N; ++m)
+      if (p->mu[m] != c->mu[m] || p->w[m] != c->w[m])
+        return fail(c, OCI_EINVAL, "refactor needs the same quadrature");
+  std::vector<RegionDev> regions(c->R);
+  int j0 = 0;
+  for (int r = 0; r < c->R; ++r) {
+    const int nc = c->cells[r];
+    regions[r] = RegionDev{j0, nc, p->width[r] / nc, p->sigma_t[r], p->sigma_s[r], p->source[r]};
+    j0 += nc;
+  }
+  OCI_CK(c, hipMemcpyAsync(c->d_regions, regions.data(), c->R * sizeof(RegionDev),
+                           hipMemcpyHostToDevice, c->stream));
+  c->a = std::isinf(p->speed) ? 0.0 : 1.0 / (p->speed * p->dt);
+  c->tol = p->tol;
+  c->max_iters = p->max_iters;
+  c->strict = (p->flags & OCI_FLAG_STRICT) ? 1 : 0;
+  c->sa.tol = c->si.tol = c->tol;
+  c->sa.max_iters = c->si.max_iters = c->max_iters;
+  c->sa.strict = c->si.strict = c->strict;
+  c->si.a = c->a;
+  drop_graphs(c);   // the argument blocks baked into the graphs changed
+  return build_operators(c);
+}
+
+extern "C" int oci_step(oci_ctx *c, oci_step_info *info) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  OCI_CK(c, hipEventRecord(c->ev0, c->stream));
+  c->sa.step_parity = c->parity;
+  hipLaunchKernelGGL(k_step_begin, dim3(c->grid), dim3(64 * c->W_pv), c->lds_pv, c->stream, c->sa);
+  OCI_CK(c, hipGetLastError());
+  int rc = run_chunks(c, false);
+  if (rc) return rc;
+  if (c->h_st->done != kNonFinite) {
+    hipLaunchKernelGGL(k_step_end, dim3(c->grid), dim3(64 * c->W_ed), c->lds_ed, c->stream, c->sa);
+    OCI_CK(c, hipGetLastError());
+  }
+  return finish_step(c, info, false);
+}
+
+extern "C" int si_step(oci_ctx *c, oci_step_info *info) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  OCI_CK(c, hipEventRecord(c->ev0, c->stream));
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, c->stream, c->d_st, c->parity);
+  OCI_CK(c, hipGetLastError());
+  int rc = run_chunks(c, true);
+  if (rc) return rc;
+  if (c->h_st->done != kNonFinite) {
+    const int n = c->J * 4;
+    hipLaunchKernelGGL(k_copy_phi, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, c->stream,
+                       (const StepState *)c->d_st, (const double *)c->d_phi[0],
+                       (const double *)c->d_phi[1], c->d_phi_res, n);
+    OCI_CK(c, hipGetLastError());
+  }
+  return finish_step(c, info, true);
+}
+
+extern "C" int oci_solve(oci_ctx *c, int32_t n_steps, double *phi_out, int32_t phi_out_on_device,
+                         oci_step_info *infos) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (n_steps < 0) return fail(c, OCI_EINVAL, "n_steps must be >= 0");
+  int worst = OCI_OK;
+  const size_t per = (size_t)c->J * 4;
+  for (int k = 0; k < n_steps; ++k) {
+    int rc = oci_step(c, infos ? &infos[k] : nullptr);
+    if (rc < 0) return rc;
+    if (rc == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
+    if (phi_out) {
+      OCI_CK(c, hipMemcpyAsync(phi_out + k * per, c->d_phi_res, per * sizeof(double),
+                               phi_out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               c->stream));
+    }
+  }
+  if (phi_out) OCI_CK(c, hipStreamSynchronize(c->stream));
+  return worst;
+}
+
+extern "C" int oci_get_flux(oci_ctx *c, double *phi, int32_t on_device) {
+  if (!c || !phi) return fail(c, OCI_EINVAL, "NULL argument");
+  if (!c->have_flux) return fail(c, OCI_ESTATE, "no step has completed yet");
+  OCI_CK(c, hipMemcpyAsync(phi, c->d_phi_res, (size_t)c->J * 4 * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  OCI_CK(c, hipStreamSynchronize(c->stream));
+  return OCI_OK;
+}
+
+extern "C" int oci_get_state(oci_ctx *c, double *psi_edge, int64_t *step) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (psi_edge) {
+    OCI_CK(c, hipMemcpyAsync(psi_edge, c->d_psi[c->parity], (size_t)c->J * 2 * c->N * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    OCI_CK(c, hipStreamSynchronize(c->stream));
+  }
+  if (step) *step = c->steps;
+  return OCI_OK;
+}
+
+extern "C" int oci_set_state(oci_ctx *c, const double *psi_edge, int64_t step) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (step < 0) return fail(c, OCI_EINVAL, "step must be >= 0");
+  const size_t cnt = (size_t)c->J * 2 * c->N;
+  if (psi_edge) {
+    for (size_t i = 0; i < cnt; ++i)
+      if (!std::isfinite(psi_edge[i])) return fail(c, OCI_EINVAL, "psi_edge must be finite");
+  }
+  int rc = reset_iterate(c);
+  if (rc) return rc;
+  c->parity = 0;
+  if (psi_edge) {
+    OCI_CK(c, hipMemcpyAsync(c->d_psi[0], psi_edge, cnt * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+  } else {
+    OCI_CK(c, hipMemsetAsync(c->d_psi[0], 0, cnt * sizeof(double), c->stream));
+  }
+  OCI_CK(c, hipStreamSynchronize(c->stream));
+  c->steps = step;
+  c->have_flux = false;
+  return OCI_OK;
+}
+
+extern "C" int oci_get_quadrature(const oci_ctx *c, double *mu, double *w) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (mu) std::copy(c->mu.begin(), c->mu.end(), mu);
+  if (w) std::copy(c->w.begin(), c->w.end(), w);
+  return OCI_OK;
+}
+
+extern "C" int oci_get_sizes(const oci_ctx *c, int32_t *n_angles, int32_t *n_cells,
+                             int32_t *n_regions) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (n_angles) *n_angles = c->N;
+  if (n_cells) *n_cells = c->J;
+  if (n_regions) *n_regions = c->R;
+  return OCI_OK;
+}
+
+extern "C" int oci_get_operator(oci_ctx *c, int32_t region, double *op) {
+  if (!c || !op) return fail(c, OCI_EINVAL, "NULL argument");
+  if (region < 0 || region >= c->R) return fail(c, OCI_EINVAL, "region out of range");
+  const size_t per = (size_t)(4 * c->N + 4) * (4 * c->N + 1);
+  OCI_CK(c, hipMemcpyAsync(op, c->d_op + region * per, per * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  OCI_CK(c, hipStreamSynchronize(c->stream));
+  return OCI_OK;
+}
+
+extern "C" void oci_destroy(oci_ctx *c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  for (void *q : c->allocs) hipFree(q);
+  if (c->h_st) hipHostFree(c->h_st);
+  for (hipEvent_t e : {c->ev0, c->ev1, c->evA, c->evB})
+    if (e) hipEventDestroy(e);
+  delete c;
+}
+
+extern "C" const char *oci_strerror(int code) {
+  switch (code) {
+    case OCI_OK: return "ok";
+    case OCI_NOT_CONVERGED: return "iteration limit reached before the stopping rule";
+    case OCI_EINVAL: return "invalid argument";
+    case OCI_ENOMEM: return "device memory allocation failed";
+    case OCI_EDEVICE: return "HIP runtime error";
+    case OCI_ENONFINITE: return "scalar flux became NaN or Inf";
+    case OCI_ESTATE: return "call not valid in the current state";
+    default: return "unknown error code";
+  }
+}
+
+extern "C" const char *oci_last_error(const oci_ctx *c) {
+  if (c) return c->err.c_str();
+  return g_last_error.c_str();
+}

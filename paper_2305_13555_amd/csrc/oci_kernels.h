@@ -1,0 +1,75 @@
+// Kernel argument blocks and kernel declarations shared by the host driver
+// (api.hip) and the kernel translation units.
+#pragma once
+
+#include "oci_device.h"
+
+namespace ocik {
+
+struct StepArgs {
+  const TileDev *tiles;
+  int ntiles;
+  int N, J, Mt, Met;
+  int bcl, bcr;
+  int max_iters, strict;
+  double tol;
+  const double *frag_it;   // G (iteration), per region stride frag_it_stride
+  size_t frag_it_stride;
+  const double *frag_pv;   // P (per-step constant)
+  size_t frag_pv_stride;
+  const double *c_pv;      // p
+  size_t c_pv_stride;
+  const double *frag_ed;   // E (end of step)
+  size_t frag_ed_stride;
+  const double *c_ed;      // e
+  size_t c_ed_stride;
+  double *gh;              // [J][Mt*16]
+  double *out0, *out1;     // [J+2][2N]
+  double *phi0, *phi1;     // [J][4]
+  double *psi0, *psi1;     // [J][2N]
+  double *phi_res;         // [J][4]
+  double *partial;         // [ntiles][4]
+  StepState *st;
+  int step_parity;         // set into the state by k_step_begin
+};
+
+struct SiArgs {
+  int N, J, bcl, bcr, max_iters, strict;
+  double tol, a;
+  const RegionDev *regions;
+  const int *cell_region;   // [J]
+  const double *mu, *w;
+  const double *ainv;       // [R][N][16]
+  double *out0, *out1;      // [J+2][2N], ghost rows hold incident values
+  double *phi0, *phi1;      // [J][4]
+  double *psi0, *psi1;      // [J][2N]
+  double *contrib;          // [N/2][J][4] pair sums of w_m psi_m
+  double *lag;              // [N/2][2] right-edge outgoing flux of the mu > 0 angle
+  double *phi_res;          // [J][4]
+  double *partial;          // [nblocks][4]
+  int nparts;
+  StepState *st;
+};
+
+// setup.hip
+__global__ void k_build_system(const RegionDev *regions, const double *mu, const double *w,
+                               int N, double a, double *ws_M, double *ws_X);
+__global__ void k_lu_solve(int N, double *ws_M, double *ws_X, int *bad);
+__global__ void k_select_rows(int N, const double *w, const double *ws_X, double *op_all);
+__global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
+                       int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
+                       size_t cvec_stride);
+// oci_step.hip
+__global__ void k_step_begin(StepArgs a);
+__global__ void k_oci_iterate(StepArgs a);
+__global__ void k_step_end(StepArgs a);
+// si.hip
+__global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,
+                            double *ainv);
+__global__ void k_si_sweep(SiArgs a);
+__global__ void k_si_reduce(SiArgs a);
+__global__ void k_state_reset(StepState *st, int parity);
+__global__ void k_copy_phi(const StepState *st, const double *phi0, const double *phi1,
+                           double *phi_res, int n);
+
+}  // namespace ocik

@@ -1,0 +1,219 @@
+// Setup kernels: per-region cell matrix, its LU factorisation, and the packed
+// operators applied on the hot path.
+//
+// The cell system of one-cell inversion (Sec. "One-Cell Inversion (OCI)") is
+// (A - S) Psi = c with A = blockdiag(A_m), A_m the 4x4 matrix printed for
+// mu > 0 (A^+) and mu < 0 (A^-) in the SI subsection, and S the scattering
+// matrix with entries (dx Sigma_s / 4) w_n coupling equal components of all
+// angles.  Both signs of A_m are one formula: diagonal (|mu| + dx Sigma)/2,
+// off-diagonal +-mu/2 with the signed mu, and the time terms dx/(2 v dt),
+// dx/(v dt).  All cells of a region share A - S.
+//
+// c enters through three sets of columns: the incident fluxes (coefficient
+// |mu_m| in the c^+ / c^- rows that carry them), the previous time edge
+// psi_{k-1/2} (coefficient dx/(2 v dt) in the two time-average rows) and the
+// source (dx Q / 4 in every row).  Setup solves (A - S) Y = [B | T | q] once
+// per region by LU with partial pivoting (the paper's dense solver, LAPACK
+// gesv, hoisted out of the iteration) and keeps only the rows the iteration
+// needs: the outgoing fluxes, the scalar flux and the time-edge values.
+#include "oci_kernels.h"
+
+namespace ocik {
+
+// One work-group per region: M (n x n, n = 4N) and the right-hand sides
+// X (n x (n+1)) into the workspace.
+__global__ void k_build_system(const RegionDev *regions, const double *mu, const double *w,
+                               int N, double a, double *ws_M, double *ws_X) {
+  const int r = blockIdx.x;
+  const int n = 4 * N, nr = n + 1;
+  const RegionDev g = regions[r];
+  double *M = ws_M + (size_t)r * n * n;
+  double *X = ws_X + (size_t)r * n * nr;
+  const double dx = g.dx;
+  const double t = dx * a;               // dx / (v dt)
+  const double s = dx * g.sigs / 4.0;    // scattering coefficient
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int row = idx / n, col = idx % n;
+    const int m = row >> 2, c = row & 3, mm = col >> 2, cc = col & 3;
+    double v = 0.0;
+    if (m == mm) {
+      const double mum = mu[m];
+      const double d = (fabs(mum) + dx * g.sig) / 2.0;
+      const double h = mum / 2.0;
+      // rows: (k,L) (k,R) (k+1/2,L) (k+1/2,R)
+      const double A[4][4] = {{d, h, t / 2.0, 0.0},
+                              {-h, d, 0.0, t / 2.0},
+                              {-t, 0.0, t + d, h},
+                              {0.0, -t, -h, t + d}};
+      v = A[c][cc];
+    }
+    if (c == cc) v -= s * w[mm];
+    M[idx] = v;
+  }
+  for (int idx = threadIdx.x; idx < n * nr; idx += blockDim.x) {
+    const int row = idx / nr, col = idx % nr;
+    const int m = row >> 2, c = row & 3;
+    double v = 0.0;
+    if (col < 2 * N) {
+      // incident entry 2m'+tl: enters row (m', c_in) with |mu|
+      const int mi = col >> 1, tl = col & 1;
+      if (mi == m) {
+        const int cin = (m < N / 2) ? (tl == 0 ? 1 : 3) : (tl == 0 ? 0 : 2);
+        if (c == cin) v = fabs(mu[m]);
+      }
+    } else if (col < 4 * N) {
+      // previous time edge 2m'+side: enters the time-average row of that side
+      const int p = col - 2 * N;
+      if ((p >> 1) == m && (p & 1) == c) v = t / 2.0;
+    } else {
+      v = dx * g.q / 4.0;
+    }
+    X[idx] = v;
+  }
+}
+
+// LU with partial pivoting of M, applied to X at the same time, then back
+// substitution: X <- M^{-1} X.  One work-group per region; singular pivots set
+// *bad.
+__global__ __launch_bounds__(1024) void k_lu_solve(int N, double *ws_M, double *ws_X, int *bad) {
+  const int r = blockIdx.x;
+  const int n = 4 * N, nr = n + 1;
+  double *M = ws_M + (size_t)r * n * n;
+  double *X = ws_X + (size_t)r * n * nr;
+  __shared__ double s_val[1024];
+  __shared__ int s_idx[1024];
+  __shared__ double s_l[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = 0; k < n; ++k) {
+    // pivot search on column k (first maximum, like LAPACK's idamax)
+    double best = -1.0;
+    int bi = n;
+    for (int i = k + tid; i < n; i += nt) {
+      const double v = fabs(M[(size_t)i * n + k]);
+      if (v > best) { best = v; bi = i; }
+    }
+    s_val[tid] = best;
+    s_idx[tid] = bi;
+    __syncthreads();
+    for (int o = nt / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        const double v2 = s_val[tid + o];
+        const int i2 = s_idx[tid + o];
+        if (v2 > s_val[tid] || (v2 == s_val[tid] && i2 < s_idx[tid])) {
+          s_val[tid] = v2;
+          s_idx[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = s_idx[0];
+    const double pv = s_val[0];
+    if (!(pv > 0.0)) {
+      if (tid == 0) atomicOr(bad, 1);
+      return;   // uniform: every thread saw the same s_val[0]
+    }
+    if (p != k) {
+      for (int j = k + tid; j < n; j += nt) {
+        const double tmp = M[(size_t)k * n + j];
+        M[(size_t)k * n + j] = M[(size_t)p * n + j];
+        M[(size_t)p * n + j] = tmp;
+      }
+      for (int j = tid; j < nr; j += nt) {
+        const double tmp = X[(size_t)k * nr + j];
+        X[(size_t)k * nr + j] = X[(size_t)p * nr + j];
+        X[(size_t)p * nr + j] = tmp;
+      }
+    }
+    __syncthreads();
+    const double piv = M[(size_t)k * n + k];
+    for (int i = k + 1 + tid; i < n; i += nt) s_l[i - k - 1] = M[(size_t)i * n + k] / piv;
+    __syncthreads();
+    const int rows = n - k - 1;
+    const int wM = n - k - 1;     // columns k+1 .. n-1 of M
+    const int wT = wM + nr;       // followed by every column of X
+    for (int idx = tid; idx < rows * wT; idx += nt) {
+      const int ii = idx / wT, jj = idx % wT;
+      const int i = k + 1 + ii;
+      const double l = s_l[ii];
+      if (jj < wM) {
+        const int j = k + 1 + jj;
+        M[(size_t)i * n + j] -= l * M[(size_t)k * n + j];
+      } else {
+        const int j = jj - wM;
+        X[(size_t)i * nr + j] -= l * X[(size_t)k * nr + j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double piv = M[(size_t)k * n + k];
+    for (int j = tid; j < nr; j += nt) X[(size_t)k * nr + j] /= piv;
+    __syncthreads();
+    for (int idx = tid; idx < k * nr; idx += nt) {
+      const int i = idx / nr, j = idx % nr;
+      X[(size_t)i * nr + j] -= M[(size_t)i * n + k] * X[(size_t)k * nr + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Row selection of Y = M^{-1}[B|T|q] into the per-region operator
+// op [2N+4+2N][4N+1]: outgoing fluxes, scalar flux (sum_n w_n psi_n),
+// time-edge values.
+__global__ void k_select_rows(int N, const double *w, const double *ws_X, double *op_all) {
+  const int r = blockIdx.x;
+  const int n = 4 * N, nr = n + 1;
+  const int rows = 4 * N + 4;
+  const double *Y = ws_X + (size_t)r * n * nr;
+  double *op = op_all + (size_t)r * rows * nr;
+  for (int idx = threadIdx.x; idx < rows * nr; idx += blockDim.x) {
+    const int row = idx / nr, col = idx % nr;
+    double v;
+    if (row < 2 * N) {
+      const int m = row >> 1, tl = row & 1;
+      const int c = (m < N / 2) ? (tl == 0 ? 0 : 2) : (tl == 0 ? 1 : 3);
+      v = Y[(size_t)(4 * m + c) * nr + col];
+    } else if (row < 2 * N + 4) {
+      const int c = row - 2 * N;
+      double acc = 0.0;
+      for (int m = 0; m < N; ++m) acc += w[m] * Y[(size_t)(4 * m + c) * nr + col];
+      v = acc;
+    } else {
+      const int p = row - 2 * N - 4;
+      const int m = p >> 1, side = p & 1;
+      v = Y[(size_t)(4 * m + 2 + side) * nr + col];
+    }
+    op[idx] = v;
+  }
+}
+
+// Pack a rows x K block of the operator (first row row0, first column col0)
+// into MFMA A-fragment order: frag[(rt*KS + ks)*64 + lane] =
+// A[rt*16 + lane%16][ks*4 + lane/16] (zero beyond `rows`), KS = K/4, and the
+// constant column into cvec[rt*16 + i] (zero-padded to Mt*16).
+__global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
+                       int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
+                       size_t cvec_stride) {
+  const int r = blockIdx.x;
+  const int nr = 4 * N + 1;
+  const int oprows = 4 * N + 4;
+  const double *op = op_all + (size_t)r * oprows * nr;
+  double *frag = frag_all + (size_t)r * frag_stride;
+  const int KS = K / 4;
+  const int total = Mt * KS * 64;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int lane = idx & 63;
+    const int blk = idx >> 6;
+    const int rt = blk / KS, ks = blk % KS;
+    const int row = rt * 16 + (lane & 15);
+    const int col = ks * 4 + (lane >> 4);
+    frag[idx] = row < rows ? op[(size_t)(row0 + row) * nr + col0 + col] : 0.0;
+  }
+  if (cvec_all) {
+    double *cv = cvec_all + (size_t)r * cvec_stride;
+    for (int i = threadIdx.x; i < Mt * 16; i += blockDim.x)
+      cv[i] = i < rows ? op[(size_t)(row0 + i) * nr + 4 * N] : 0.0;
+  }
+}
+
+}  // namespace ocik
