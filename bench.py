@@ -33,6 +33,47 @@ def algorithmic_bytes_per_cell_iteration(n_angles):
     return 8 * (6 * n_angles + 12)
 
 
+def algorithmic_bytes_per_cell_step(n_angles):
+    """Per cell and time step outside the iterations: the step constant reads
+    psi_{k-1/2} (2N) and writes [g; h] (2N+4); the end of step reads the
+    incident fluxes (2N) and psi_{k-1/2} (2N), writes psi_{k+1/2} (2N) and
+    copies the accepted scalar flux (4 in, 4 out)."""
+    return 8 * (10 * n_angles + 12)
+
+
+def roofline_launch_seconds(oci, prob, stream, batches=5):
+    """Per-launch time of k_oci_iterate on the workload's cells, regions and
+    angles, with v = inf and tol = 0 so that every one of a batch of 32
+    iteration launches does the full work (the kernel's work does not depend
+    on the values).  The first step reaches the batch length; each later step
+    replays its 32 launches as one graph, timed with HIP events on the
+    library's stream around the batch alone (dispatch gaps included).
+    Returns the median over `batches` steps of batch time / 32."""
+    import dataclasses
+    roof = dataclasses.replace(prob, speed=float("inf"), name=prob.name + ", v = inf")
+    per = []
+    with oci.OciContext(roof, stream=stream, tol=0.0, max_iters=32) as cr:
+        cr.step()
+        for _ in range(batches):
+            rc, info = cr.step()
+            if info["launches"] != 32 or info["iterations"] != 32:
+                raise RuntimeError("roofline batch did not run 32 full launches: %r" % (info,))
+            per.append(info["iter_ms"] * 1e-3 / info["launches"])
+    return float(np.median(per))
+
+
+def copy_calibration(torch, mib):
+    """A plain device-to-device copy of `mib` MiB (3 times), the reference
+    kernel for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    n = mib * (1 << 20) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return n * 8
+
+
 def cpu_baseline(prob, n_steps, gpu_phi):
     """The oracle's OCI (per-region LU + multi-right-hand-side solves) timed on
     the host for the first n_steps of the workload."""
@@ -65,8 +106,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the k_oci_iterate roofline batches and a 64 MiB copy "
+                         "(for hardware-counter runs)")
+
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the OCI path here is single-GPU "
@@ -80,6 +125,14 @@ def main():
     prob = workloads.config2()
     J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
     stream = torch.cuda.current_stream()
+    if args.roofline_only:
+        t = roofline_launch_seconds(oci, prob, stream, batches=2)
+        nbytes = copy_calibration(torch, 64)
+        b = algorithmic_bytes_per_cell_iteration(N) * J
+        print(json.dumps({"kernel": "k_oci_iterate", "us_per_launch": t * 1e6,
+                          "algorithmic_bytes_per_launch": b, "GB/s": b / t / 1e9,
+                          "copy_bytes": nbytes}))
+        return
     ctx = oci.OciContext(prob, stream=stream)
     phi_dev = torch.zeros((T, J, 4), dtype=torch.float64, device="cuda")
 
@@ -102,31 +155,36 @@ def main():
     wall = time.perf_counter() - t0
 
     iters = sum(i["iterations"] for infos in all_infos for i in infos)
-    launches = sum(i["launches"] for infos in all_infos for i in infos)
-    iter_ms = sum(i["iter_ms"] for infos in all_infos for i in infos)
     value = iters * J * N / wall
-    per_launch_s = iter_ms * 1e-3 / max(iters, 1)
+    gpu_phi = phi_dev.cpu().numpy()
+    kernel, per_launch_s = "k_oci_iterate", roofline_launch_seconds(oci, prob, stream)
     bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J
     achieved = bytes_launch / per_launch_s / 1e9
-    gpu_phi = phi_dev.cpu().numpy()
 
-    # time to a 1e-6 tolerance per step, and source iteration, same problem
-    def per_step_ms(tol, method, n):
-        with oci.OciContext(prob, stream=stream, tol=tol) as c2:
-            ms, its = [], []
-            for _ in range(n):
-                rc, info = c2.step() if method == "oci" else c2.si_step()
-                ms.append(info["ms"])
-                its.append(info["iterations"])
-        return float(np.mean(ms)), float(np.mean(its))
-
-    t6_ms, t6_its = per_step_ms(1e-6, "oci", T)
-    si_ms, si_its = per_step_ms(prob.tol, "si", 10)
+    # time to a 1e-6 tolerance per step (whole solve at tol 1e-6), and source
+    # iteration step by step, same problem
+    with oci.OciContext(prob, stream=stream, tol=1e-6) as c6:
+        c6.solve(T, phi_dev)
+        torch.cuda.synchronize()
+        c6.set_state(None, 0)
+        t = time.perf_counter()
+        rc6, inf6 = c6.solve(T, phi_dev)
+        torch.cuda.synchronize()
+        t6_ms = (time.perf_counter() - t) * 1e3 / T
+        t6_its = float(np.mean([i["iterations"] for i in inf6]))
+    with oci.OciContext(prob, stream=stream) as cs:
+        ms, its = [], []
+        for _ in range(10):
+            rc, info = cs.si_step()
+            ms.append(info["ms"])
+            its.append(info["iterations"])
+        si_ms, si_its = float(np.mean(ms)), float(np.mean(its))
     oci_ms = wall * 1e3 / (args.steps * T)
 
     cpu, err = (None, None)
     if not args.no_cpu:
-        cpu, err = cpu_baseline(prob, args.cpu_steps, gpu_phi[:args.cpu_steps])
+        ncpu = min(args.cpu_steps, T)
+        cpu, err = cpu_baseline(prob, ncpu, gpu_phi[:ncpu])
 
     line = {
         "metric": METRIC,
@@ -147,10 +205,11 @@ def main():
                         "v = 1, tol 1e-10 (seeded)" % prob.name,
             "cells": J, "angles": N, "regions": prob.n_regions, "time_steps": T,
             "tol": prob.tol, "step": "operator rebuild + LU + %d MB time steps" % T,
+            "driver": "queued solve (one batch of iteration launches per step)",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_oci_iterate",
+            "kernel": kernel,
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
@@ -158,8 +217,7 @@ def main():
             "traffic": None,
             "bytes_per_launch": bytes_launch,
             "us_per_launch": per_launch_s * 1e6,
-            "launches": launches,
-            "iterations": iters,
+            "measured": "median of 5 batches of 32 launches",
         },
         "cpu_baseline": cpu,
         "iterations_per_time_step": iters / (args.steps * T),

@@ -1,16 +1,21 @@
 // Host driver behind the C ABI declared in include/oci.h.
 //
 // One context = one slab problem bound to one HIP stream.  oci_setup builds
-// every region's operator on the GPU; oci_step launches the per-step constant
-// kernel, then chunks of iteration kernels as pre-instantiated HIP graphs
-// (each iteration kernel is a no-op once the device-side stopping decision
-// is taken, so a chunk may overshoot harmlessly), reads the 32-byte control
-// word back after each chunk, and finishes with the end-of-step kernel.
+// every region's operator on the GPU.  An OCI time step is: the step-start
+// kernel (per-step constant), a batch of iteration launches replayed from a
+// HIP graph (each launch decides the previous iterate from the residual
+// records the launch before it left, and exits at once once the step is
+// decided), and the end-of-step kernel, which decides the batch's last
+// iterate itself when no launch did.  oci_solve and oci_step queue every step
+// without waiting; a step not decided within its batch stalls the queue on the
+// device, the host resumes it with further launches and queues the rest.
+// Source iteration runs one step at a time with host-read decisions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -24,8 +29,7 @@ namespace {
 
 thread_local std::string g_last_error;
 
-constexpr int kGraphSizes[] = {1, 2, 4, 8, 16, 32, 64};
-constexpr int kNumGraphSizes = sizeof(kGraphSizes) / sizeof(kGraphSizes[0]);
+constexpr int kMaxBatch = 64;   // iteration launches per replayed batch
 
 }  // namespace
 
@@ -36,7 +40,7 @@ struct oci_ctx {
   std::vector<double> mu, w;
   std::vector<int> cells;
   std::vector<double> ghost_left, ghost_right;   // [2N] each
-  int Mt = 0, Met = 0, ntiles = 0, grid = 0, W_it = 1, W_ed = 1, W_pv = 1;
+  int Mt = 0, Met = 0, Mto = 0, ntiles = 0, grid = 0, W_it = 1, W_ed = 1, W_pv = 1;
   size_t lds_it = 0, lds_pv = 0, lds_ed = 0;
   int si_blocks = 0;
   std::vector<void *> allocs;
@@ -46,24 +50,30 @@ struct oci_ctx {
   int *d_cell_region = nullptr;
   double *d_op = nullptr;
   double *d_fi = nullptr, *d_fp = nullptr, *d_cp = nullptr, *d_fe = nullptr, *d_ce = nullptr;
+  double *d_hphi = nullptr;
   size_t fi_stride = 0, fp_stride = 0, cp_stride = 0, fe_stride = 0, ce_stride = 0;
+  size_t hphi_stride = 0;
   double *d_gh = nullptr, *d_out[2] = {nullptr, nullptr}, *d_phi[2] = {nullptr, nullptr};
   double *d_psi[2] = {nullptr, nullptr}, *d_phi_res = nullptr, *d_partial = nullptr;
   double *d_ainv = nullptr, *d_contrib = nullptr, *d_lag = nullptr, *d_si_partial = nullptr;
-  StepState *d_st = nullptr;
-  StepState *h_st = nullptr;   // pinned host copy of the control word
+  StepCtl *d_ctl = nullptr;
+  StepCtl *h_ctl = nullptr;                  // pinned host copy of the control block
+  StepRecord *d_rec = nullptr, *h_rec = nullptr;
+  int rec_cap = 0;
   int parity = 0;
   int64_t steps = 0;
   bool have_flux = false;
   int last_oci_iters = 0, last_si_iters = 0;
-  hipGraphExec_t oci_graph[kNumGraphSizes] = {};
-  hipGraphExec_t si_graph[kNumGraphSizes] = {};
+  hipGraphExec_t oci_graph[kMaxBatch + 1] = {};   // indexed by batch length
+  hipGraphExec_t si_graph[kMaxBatch + 1] = {};
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evA = nullptr, evB = nullptr;
+  hipEvent_t evC = nullptr, evD = nullptr;   // around a lone step's iteration batch
   bool quad_override = false;
   double *ws_M = nullptr, *ws_X = nullptr;   // setup workspace, kept for oci_refactor
   int *d_bad = nullptr;
-  double iter_ms = 0.0;                      // accumulated by run_chunks
-  int launches = 0;
+  // kernels for the chosen operator batch width CH
+  int CH = 16;
+  void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr;
   std::string err;
   StepArgs sa{};
   SiArgs si{};
@@ -159,7 +169,7 @@ static int upload_ghosts(oci_ctx *c) {
 }
 
 // Cold iterate: zero outgoing fluxes (boundary rows kept), zero scalar flux,
-// zero lagged reflection, iteration parity 0.
+// zero lagged reflection, control block cleared (iteration parity 0).
 static int reset_iterate(oci_ctx *c) {
   const int K = 2 * c->N;
   for (int b = 0; b < 2; ++b) {
@@ -167,7 +177,7 @@ static int reset_iterate(oci_ctx *c) {
     OCI_CK(c, hipMemsetAsync(c->d_phi[b], 0, (size_t)c->J * 4 * sizeof(double), c->stream));
   }
   OCI_CK(c, hipMemsetAsync(c->d_lag, 0, (size_t)c->N * sizeof(double), c->stream));
-  OCI_CK(c, hipMemsetAsync(c->d_st, 0, sizeof(StepState), c->stream));
+  OCI_CK(c, hipMemsetAsync(c->d_ctl, 0, sizeof(StepCtl), c->stream));
   int rc = upload_ghosts(c);
   if (rc) return rc;
   c->last_oci_iters = 0;
@@ -175,10 +185,12 @@ static int reset_iterate(oci_ctx *c) {
   return OCI_OK;
 }
 
-static int build_graph(oci_ctx *c, bool si, int gi) {
-  hipGraphExec_t *slot = si ? &c->si_graph[gi] : &c->oci_graph[gi];
+// The first batch of a step as a replayable graph: `count` iteration
+// launches (nodes 1..count; OCI), or `count` source iterations of sweep,
+// reduce and decide launches (SI).
+static int build_graph(oci_ctx *c, bool si, int count) {
+  hipGraphExec_t *slot = si ? &c->si_graph[count] : &c->oci_graph[count];
   if (*slot) return OCI_OK;
-  const int count = kGraphSizes[gi];
   hipGraph_t g;
   OCI_CK(c, hipGraphCreate(&g, 0));
   hipGraphNode_t prev = nullptr;
@@ -195,22 +207,24 @@ static int build_graph(oci_ctx *c, bool si, int gi) {
     if (e == hipSuccess) prev = node;
     return e;
   };
-  void *oci_args[] = {&c->sa};
-  void *si_args[] = {&c->si};
-  for (int i = 0; i < count; ++i) {
-    hipError_t e;
+  hipError_t e = hipSuccess;
+  for (int i = 1; i <= count && e == hipSuccess; ++i) {
+    int node = i, cb = 0;
     if (!si) {
-      e = add((void *)k_oci_iterate, dim3(c->grid), dim3(64 * c->W_it), c->lds_it, oci_args);
+      void *args[] = {&c->sa, &node, &cb};
+      e = add(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), c->lds_it, args);
     } else {
-      e = add((void *)k_si_sweep, dim3(c->N / 2), dim3(1024), 0, si_args);
-      if (e == hipSuccess) e = add((void *)k_si_reduce, dim3(c->si_blocks), dim3(256), 0, si_args);
-    }
-    if (e != hipSuccess) {
-      hipGraphDestroy(g);
-      return fail(c, OCI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+      void *args[] = {&c->si, &node, &cb};
+      e = add((void *)k_si_sweep, dim3(c->N / 2), dim3(1024), 0, args);
+      if (e == hipSuccess) e = add((void *)k_si_reduce, dim3(c->si_blocks), dim3(256), 0, args);
+      if (e == hipSuccess) e = add((void *)k_si_decide, dim3(1), dim3(256), 0, args);
     }
   }
-  hipError_t e = hipGraphInstantiate(slot, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(c, OCI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+  }
+  e = hipGraphInstantiate(slot, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) {
     *slot = nullptr;
@@ -219,11 +233,6 @@ static int build_graph(oci_ctx *c, bool si, int gi) {
   return OCI_OK;
 }
 
-static int pick_graph(int want) {
-  for (int i = 0; i < kNumGraphSizes; ++i)
-    if (kGraphSizes[i] >= want) return i;
-  return kNumGraphSizes - 1;
-}
 
 // Build, factor and pack every region's operator (region table, mu, w and a
 // already on the device / in the context).
@@ -245,6 +254,9 @@ static int build_operators(oci_ctx *c) {
   // end-of-step operator E: rows [2N+4, 4N+4), columns [0, 4N)
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N + 4, K, 0,
                      2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride);
+  // scalar-flux rows of G for the dot products of the iteration
+  hipLaunchKernelGGL(k_pack_rows, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N, 4, 0, K,
+                     c->d_hphi, c->hphi_stride);
   hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
                      c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
   OCI_CK(c, hipGetLastError());
@@ -256,7 +268,7 @@ static int build_operators(oci_ctx *c) {
 }
 
 static void drop_graphs(oci_ctx *c) {
-  for (int i = 0; i < kNumGraphSizes; ++i) {
+  for (int i = 0; i <= kMaxBatch; ++i) {
     if (c->oci_graph[i]) hipGraphExecDestroy(c->oci_graph[i]);
     if (c->si_graph[i]) hipGraphExecDestroy(c->si_graph[i]);
     c->oci_graph[i] = nullptr;
@@ -310,11 +322,17 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->grid = 8 * ((c->ntiles + 7) / 8);
   c->Mt = (2 * N + 4 + 15) / 16;
   c->Met = (2 * N + 15) / 16;
-  c->W_it = std::min(c->Mt, kMaxWaves);
-  c->W_pv = std::min(c->Mt, kMaxWaves);
-  c->W_ed = std::min(c->Met, kMaxWaves);
+  c->Mto = (2 * N + 15) / 16;
+  // at most four waves per work-group: the hardware places a work-group's
+  // waves from the first SIMD of a CU onwards, so with five waves the first
+  // SIMD fills first and fewer work-groups stay resident than registers
+  // allow.  The iteration splits its scalar-flux dot products over W threads,
+  // so there W is a power of two.
+  c->W_it = c->Mto >= 4 ? 4 : (c->Mto >= 2 ? 2 : 1);
+  c->W_pv = std::min(c->Mt, 4);
+  c->W_ed = std::min(c->Met, 4);
   const int P = K + 2;
-  c->lds_it = (size_t)(kTileCells + 2) * P * sizeof(double);
+  c->lds_it = (size_t)(kTileCells + 2 + 4) * P * sizeof(double);
   c->lds_pv = (size_t)kTileCells * P * sizeof(double);
   c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
   c->si_blocks = (J * 4 + 255) / 256;
@@ -348,6 +366,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->cp_stride = (size_t)c->Mt * 16;
   c->fe_stride = (size_t)c->Met * (2 * K / 4) * 64;
   c->ce_stride = (size_t)c->Met * 16;
+  c->hphi_stride = (size_t)4 * K;
   OCI_TRY(dalloc(c, &c->d_mu, N));
   OCI_TRY(dalloc(c, &c->d_w, N));
   OCI_TRY(dalloc(c, &c->d_regions, R));
@@ -359,6 +378,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_cp, (size_t)R * c->cp_stride));
   OCI_TRY(dalloc(c, &c->d_fe, (size_t)R * c->fe_stride));
   OCI_TRY(dalloc(c, &c->d_ce, (size_t)R * c->ce_stride));
+  OCI_TRY(dalloc(c, &c->d_hphi, (size_t)R * c->hphi_stride));
   OCI_TRY(dalloc(c, &c->d_gh, (size_t)J * c->Mt * 16));
   for (int b = 0; b < 2; ++b) {
     OCI_TRY(dalloc(c, &c->d_out[b], (size_t)(J + 2) * K));
@@ -366,20 +386,21 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
     OCI_TRY(dalloc(c, &c->d_psi[b], (size_t)J * K));
   }
   OCI_TRY(dalloc(c, &c->d_phi_res, (size_t)J * 4));
-  OCI_TRY(dalloc(c, &c->d_partial, (size_t)c->ntiles * 4));
+  OCI_TRY(dalloc(c, &c->d_partial, (size_t)3 * c->ntiles * 4));
   OCI_TRY(dalloc(c, &c->d_ainv, (size_t)R * N * 16));
   OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(N / 2) * J * 4));
   OCI_TRY(dalloc(c, &c->d_lag, (size_t)N));
-  OCI_TRY(dalloc(c, &c->d_si_partial, (size_t)c->si_blocks * 4));
-  OCI_TRY(dalloc(c, &c->d_st, 1));
+  OCI_TRY(dalloc(c, &c->d_si_partial, (size_t)3 * c->si_blocks * 4));
+  OCI_TRY(dalloc(c, &c->d_ctl, 1));
   {
     void *h = nullptr;
-    if (hipHostMalloc(&h, sizeof(StepState), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc(&h, sizeof(StepCtl), hipHostMallocDefault) != hipSuccess)
       return cleanup(fail(c, OCI_ENOMEM, "hipHostMalloc failed"));
-    c->h_st = static_cast<StepState *>(h);
+    c->h_ctl = static_cast<StepCtl *>(h);
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-      hipEventCreate(&c->evA) != hipSuccess || hipEventCreate(&c->evB) != hipSuccess)
+      hipEventCreate(&c->evA) != hipSuccess || hipEventCreate(&c->evB) != hipSuccess ||
+      hipEventCreate(&c->evC) != hipSuccess || hipEventCreate(&c->evD) != hipSuccess)
     return cleanup(fail(c, OCI_EDEVICE, "hipEventCreate failed"));
 
   auto up = [&](void *dst, const void *src, size_t bytes) -> int {
@@ -415,6 +436,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.J = J;
   s.Mt = c->Mt;
   s.Met = c->Met;
+  s.Mto = c->Mto;
   s.bcl = c->bcl;
   s.bcr = c->bcr;
   s.max_iters = c->max_iters;
@@ -422,6 +444,8 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.tol = c->tol;
   s.frag_it = c->d_fi;
   s.frag_it_stride = c->fi_stride;
+  s.hphi = c->d_hphi;
+  s.hphi_stride = c->hphi_stride;
   s.frag_pv = c->d_fp;
   s.frag_pv_stride = c->fp_stride;
   s.c_pv = c->d_cp;
@@ -439,8 +463,8 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.psi1 = c->d_psi[1];
   s.phi_res = c->d_phi_res;
   s.partial = c->d_partial;
-  s.st = c->d_st;
-  s.step_parity = 0;
+  s.ctl = c->d_ctl;
+  s.rec = nullptr;
   SiArgs &q = c->si;
   q.N = N;
   q.J = J;
@@ -466,14 +490,29 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   q.phi_res = c->d_phi_res;
   q.partial = c->d_si_partial;
   q.nparts = c->si_blocks;
-  q.st = c->d_st;
+  q.ctl = c->d_ctl;
 
+  // kernels for this N: operator fragments are fetched CH k-steps at a time
+  c->CH = (N / 2 >= 16) ? 16 : (N / 2 >= 8 ? 8 : 4);
+  if (c->CH == 16) {
+    c->fn_begin = (void *)k_step_begin<16>;
+    c->fn_iter = (void *)k_oci_iterate<16>;
+    c->fn_end = (void *)k_step_end<16>;
+  } else if (c->CH == 8) {
+    c->fn_begin = (void *)k_step_begin<8>;
+    c->fn_iter = (void *)k_oci_iterate<8>;
+    c->fn_end = (void *)k_step_end<8>;
+  } else {
+    c->fn_begin = (void *)k_step_begin<4>;
+    c->fn_iter = (void *)k_oci_iterate<4>;
+    c->fn_end = (void *)k_step_end<4>;
+  }
   // kernels with more than 64 KiB of dynamic LDS must say so
-  hipFuncSetAttribute((const void *)k_oci_iterate, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipFuncSetAttribute((const void *)c->fn_iter, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)c->lds_it);
-  hipFuncSetAttribute((const void *)k_step_begin, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipFuncSetAttribute((const void *)c->fn_begin, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)c->lds_pv);
-  hipFuncSetAttribute((const void *)k_step_end, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipFuncSetAttribute((const void *)c->fn_end, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)c->lds_ed);
   OCI_CK(c, hipStreamSynchronize(c->stream));
 #undef OCI_TRY
@@ -481,68 +520,262 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   return OCI_OK;
 }
 
-static void fill_info(oci_ctx *c, oci_step_info *info, const StepState &st, int status, float ms) {
+static int read_ctl(oci_ctx *c) {
+  OCI_CK(c, hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(StepCtl), hipMemcpyDeviceToHost, c->stream));
+  OCI_CK(c, hipStreamSynchronize(c->stream));
+  return OCI_OK;
+}
+
+// Resume a stalled queue: clear the stall flag so the open step can continue.
+static int clear_stall(oci_ctx *c) {
+  c->h_ctl->stalled = 0;
+  OCI_CK(c, hipMemcpyAsync(&c->d_ctl->stalled, &c->h_ctl->stalled, sizeof(int32_t),
+                           hipMemcpyHostToDevice, c->stream));
+  return OCI_OK;
+}
+
+// A later batch of a step: `count` launches after iterate cb (one by one:
+// only needed when the first batch was too short).  For SI each iteration
+// also decides.
+static int launch_batch(oci_ctx *c, bool si, int cb, int count) {
+  for (int i = 1; i <= count; ++i) {
+    int node = i;
+    if (!si) {
+      void *args[] = {&c->sa, &node, &cb};
+      OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), args, c->lds_it,
+                                c->stream));
+    } else {
+      void *args[] = {&c->si, &node, &cb};
+      OCI_CK(c, hipLaunchKernel((const void *)k_si_sweep, dim3(c->N / 2), dim3(1024), args, 0,
+                                c->stream));
+      OCI_CK(c, hipLaunchKernel((const void *)k_si_reduce, dim3(c->si_blocks), dim3(256), args, 0,
+                                c->stream));
+      OCI_CK(c, hipLaunchKernel((const void *)k_si_decide, dim3(1), dim3(256), args, 0,
+                                c->stream));
+    }
+  }
+  return OCI_OK;
+}
+
+static void fill_info(oci_step_info *info, int iterations, int status, double residual, double ms,
+                      double iter_ms, int launches) {
   if (!info) return;
-  info->iterations = st.it;
+  info->iterations = iterations;
   info->status = status;
-  info->residual = st.e_last;
+  info->residual = residual;
   info->ms = ms;
-  info->iter_ms = c->iter_ms;
-  info->launches = c->launches;
+  info->iter_ms = iter_ms;
+  info->launches = launches;
   info->pad = 0;
 }
 
-// Run graph chunks until the device says the step is decided.
-static int run_chunks(oci_ctx *c, bool si) {
-  c->iter_ms = 0.0;
-  c->launches = 0;
-  int want = std::max(si ? c->last_si_iters : c->last_oci_iters, si ? 1 : 2);
-  int launched = 0, extra = 0;
-  for (;;) {
-    const int gi = pick_graph(want);
-    int rc = build_graph(c, si, gi);
-    if (rc) return rc;
-    OCI_CK(c, hipEventRecord(c->evA, c->stream));
-    OCI_CK(c, hipGraphLaunch(si ? c->si_graph[gi] : c->oci_graph[gi], c->stream));
-    OCI_CK(c, hipEventRecord(c->evB, c->stream));
-    launched += kGraphSizes[gi];
-    OCI_CK(c, hipMemcpyAsync(c->h_st, c->d_st, sizeof(StepState), hipMemcpyDeviceToHost, c->stream));
-    OCI_CK(c, hipStreamSynchronize(c->stream));
-    float ms = 0.0f;
-    hipEventElapsedTime(&ms, c->evA, c->evB);
-    c->iter_ms += ms;
-    c->launches += kGraphSizes[gi];
-    if (c->h_st->done != kRunning) return OCI_OK;
-    if (launched > c->max_iters + 1)
-      return fail(c, OCI_EDEVICE, "iteration control word did not reach a decision");
-    // the previous step's count was short: continue one iteration at a time
-    // twice, then in doubling batches
-    ++extra;
-    want = extra <= 2 ? 1 : std::min(64, 1 << (extra - 2));
-  }
+// A non-finite step is abandoned: psi_{k-1/2} is kept, the iterate restarts cold.
+static int abandon_step(oci_ctx *c, oci_step_info *info, int iterations) {
+  int rc = reset_iterate(c);
+  OCI_CK(c, hipStreamSynchronize(c->stream));
+  fill_info(info, iterations, OCI_ENONFINITE, -1.0, 0.0, 0.0, 0);
+  if (rc) return rc;
+  return fail(c, OCI_ENONFINITE, "the scalar flux became NaN or Inf");
 }
 
-static int finish_step(oci_ctx *c, oci_step_info *info, bool si) {
-  const StepState st = *c->h_st;
-  if (st.done == kNonFinite) {
-    // abandon the step: keep psi_{k-1/2}, restart from a cold iterate
-    int rc = reset_iterate(c);
-    OCI_CK(c, hipStreamSynchronize(c->stream));
-    fill_info(c, info, st, OCI_ENONFINITE, 0.0f);
+// ---------------------------------------------------------------------------
+// Source iteration: one step at a time, host-driven batches.
+// ---------------------------------------------------------------------------
+static int si_run(oci_ctx *c, oci_step_info *info) {
+  OCI_CK(c, hipEventRecord(c->ev0, c->stream));
+  const int nb = (int)std::min<size_t>(1024, ((size_t)c->J * 2 * c->N + 255) / 256);
+  hipLaunchKernelGGL(k_si_begin, dim3(nb), dim3(256), 0, c->stream, c->si, c->parity);
+  OCI_CK(c, hipGetLastError());
+  int launched = 0, extra = 0, launches = 0;
+  double iter_ms = 0.0;
+  for (;;) {
+    int count, rc;
+    OCI_CK(c, hipEventRecord(c->evA, c->stream));
+    if (launched == 0) {
+      count = std::min(std::max(c->last_si_iters, 1), std::min(kMaxBatch, c->max_iters));
+      rc = build_graph(c, true, count);
+      if (rc) return rc;
+      OCI_CK(c, hipGraphLaunch(c->si_graph[count], c->stream));
+    } else {
+      ++extra;
+      count = extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2));
+      rc = launch_batch(c, true, launched, count);
+      if (rc) return rc;
+    }
+    OCI_CK(c, hipEventRecord(c->evB, c->stream));
+    launched += count;
+    rc = read_ctl(c);
     if (rc) return rc;
-    return fail(c, OCI_ENONFINITE, "the scalar flux became NaN or Inf");
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, c->evA, c->evB);
+    iter_ms += ms;
+    launches += count;
+    if (c->h_ctl->status != kRunning) break;
+    if (launched > c->max_iters + 1)
+      return fail(c, OCI_EDEVICE, "the step control block did not reach a decision");
   }
-  (si ? c->last_si_iters : c->last_oci_iters) = st.it;
-  c->parity ^= 1;
-  c->steps += 1;
-  c->have_flux = true;
+  const StepCtl st = *c->h_ctl;
+  if (st.status == kNonFinite) return abandon_step(c, info, st.accepted);
+  const int n = c->J * 4;
+  hipLaunchKernelGGL(k_si_end, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, c->stream,
+                     c->si);
+  OCI_CK(c, hipGetLastError());
   OCI_CK(c, hipEventRecord(c->ev1, c->stream));
   OCI_CK(c, hipEventSynchronize(c->ev1));
   float ms = 0.0f;
   hipEventElapsedTime(&ms, c->ev0, c->ev1);
-  const int status = st.done == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
-  fill_info(c, info, st, status, ms);
+  c->last_si_iters = st.accepted;
+  c->parity ^= 1;
+  c->steps += 1;
+  c->have_flux = true;
+  const int status = st.status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
+  fill_info(info, st.accepted, status, st.e_last, ms, iter_ms, launches);
   return status;
+}
+
+// ---------------------------------------------------------------------------
+// One-cell inversion: queued steps.
+// ---------------------------------------------------------------------------
+static int grow_records(oci_ctx *c, int n) {
+  if (n <= c->rec_cap) return OCI_OK;
+  if (c->d_rec) hipFree(c->d_rec);
+  if (c->h_rec) hipHostFree(c->h_rec);
+  c->d_rec = nullptr;
+  c->h_rec = nullptr;
+  c->rec_cap = 0;
+  const int cap = std::max(n, 128);
+  OCI_CK(c, hipMalloc(&c->d_rec, cap * sizeof(StepRecord)));
+  OCI_CK(c, hipHostMalloc((void **)&c->h_rec, cap * sizeof(StepRecord), hipHostMallocDefault));
+  c->rec_cap = cap;
+  return OCI_OK;
+}
+
+static int launch_end(oci_ctx *c, int step, double *phi_dev, int last) {
+  void *args[] = {&c->sa, &step, &phi_dev, &last};
+  OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
+                            c->stream));
+  return OCI_OK;
+}
+
+// Queue steps first .. n_steps-1 without waiting: step start, the first
+// batch of `batch` iteration launches (a replayed graph), end of step (which
+// decides the batch's last iterate when no launch decided earlier).
+static int enqueue_steps(oci_ctx *c, int first, int n_steps, int batch, double *phi_dev) {
+  int rc = build_graph(c, false, batch);
+  if (rc) return rc;
+  for (int k = first; k < n_steps; ++k) {
+    int parity = c->parity ^ ((k - first) & 1);
+    void *bargs[] = {&c->sa, &parity};
+    OCI_CK(c, hipLaunchKernel(c->fn_begin, dim3(c->grid), dim3(64 * c->W_pv), bargs, c->lds_pv,
+                              c->stream));
+    const bool lone = first + 1 == n_steps;
+    if (lone) OCI_CK(c, hipEventRecord(c->evC, c->stream));
+    OCI_CK(c, hipGraphLaunch(c->oci_graph[batch], c->stream));
+    if (lone) OCI_CK(c, hipEventRecord(c->evD, c->stream));
+    rc = launch_end(c, k, phi_dev, batch);
+    if (rc) return rc;
+  }
+  return OCI_OK;
+}
+
+static void complete_step(oci_ctx *c, int accepted) {
+  c->last_oci_iters = accepted;
+  c->parity ^= 1;
+  c->steps += 1;
+  c->have_flux = true;
+}
+
+// Every step is queued at once; a step not decided within its first batch
+// stalls the queue on the device, is resumed here with further launches, and
+// the rest is queued again.  phi_dev may be null.
+static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info *infos) {
+  int rc = grow_records(c, n_steps);
+  if (rc) return rc;
+  c->sa.rec = c->d_rec;
+  int worst = OCI_OK;
+  int k = 0;
+  while (k < n_steps) {
+    const int batch = std::min({std::max(c->last_oci_iters, 2), c->max_iters, kMaxBatch});
+    OCI_CK(c, hipEventRecord(c->evA, c->stream));
+    rc = enqueue_steps(c, k, n_steps, batch, phi_dev);
+    if (rc) break;
+    OCI_CK(c, hipEventRecord(c->evB, c->stream));
+    OCI_CK(c, hipMemcpyAsync(c->h_rec + k, c->d_rec + k, (n_steps - k) * sizeof(StepRecord),
+                             hipMemcpyDeviceToHost, c->stream));
+    rc = read_ctl(c);
+    if (rc) break;
+    float ms = 0.0f, lone_ms = 0.0f;
+    hipEventElapsedTime(&ms, c->evA, c->evB);
+    if (k + 1 == n_steps) hipEventElapsedTime(&lone_ms, c->evC, c->evD);
+    // steps before the first undecided one are complete
+    int done = k;
+    while (done < n_steps && !c->h_ctl->stalled) ++done;
+    if (c->h_ctl->stalled) {
+      done = k;
+      while (done < n_steps && (c->h_rec[done].status == kConverged ||
+                                c->h_rec[done].status == kIterLimit))
+        ++done;
+    }
+    const int ndone = done - k;
+    for (int q = k; q < done; ++q) {
+      const StepRecord &r = c->h_rec[q];
+      const int status = r.status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
+      if (status == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
+      // one queue for every step: its time split over the steps it completed;
+      // a lone step also reports the time of its batch of iteration launches
+      const double share = ms / std::max(ndone, 1);
+      fill_info(infos ? &infos[q] : nullptr, r.accepted, status, r.e_last, share,
+                k + 1 == n_steps ? lone_ms : share, k + 1 == n_steps ? batch : 0);
+      complete_step(c, r.accepted);
+    }
+    k = done;
+    if (k == n_steps) break;
+    // step k stalled: undecided after `batch` launches, or non-finite
+    if (c->h_ctl->fin_status == kNonFinite) {
+      rc = abandon_step(c, infos ? &infos[k] : nullptr, c->h_ctl->fin_accepted);
+      break;
+    }
+    OCI_CK(c, hipEventRecord(c->ev0, c->stream));
+    int launched = batch, extra = 0, launches = batch;
+    for (;;) {
+      rc = clear_stall(c);
+      if (rc) break;
+      ++extra;
+      const int count = std::min(extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2)),
+                                 std::max(c->max_iters - launched, 1));
+      rc = launch_batch(c, false, launched, count);
+      if (rc) break;
+      launched += count;
+      launches += count;
+      rc = launch_end(c, k, phi_dev, launched);
+      if (rc) break;
+      rc = read_ctl(c);
+      if (rc) break;
+      if (!c->h_ctl->stalled) break;
+      if (c->h_ctl->fin_status == kNonFinite) break;
+      if (launched > c->max_iters + 1) {
+        rc = fail(c, OCI_EDEVICE, "the step control block did not reach a decision");
+        break;
+      }
+    }
+    if (rc) break;
+    if (c->h_ctl->fin_status == kNonFinite) {
+      rc = abandon_step(c, infos ? &infos[k] : nullptr, c->h_ctl->fin_accepted);
+      break;
+    }
+    OCI_CK(c, hipEventRecord(c->ev1, c->stream));
+    OCI_CK(c, hipEventSynchronize(c->ev1));
+    float ms2 = 0.0f;
+    hipEventElapsedTime(&ms2, c->ev0, c->ev1);
+    const StepCtl st = *c->h_ctl;
+    const int status = st.fin_status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
+    if (status == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
+    fill_info(infos ? &infos[k] : nullptr, st.fin_accepted, status, st.fin_e, ms2, ms2, launches);
+    complete_step(c, st.fin_accepted);
+    ++k;
+  }
+  c->sa.rec = nullptr;
+  return rc ? rc : worst;
 }
 
 extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
@@ -581,53 +814,31 @@ extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
 
 extern "C" int oci_step(oci_ctx *c, oci_step_info *info) {
   if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
-  OCI_CK(c, hipEventRecord(c->ev0, c->stream));
-  c->sa.step_parity = c->parity;
-  hipLaunchKernelGGL(k_step_begin, dim3(c->grid), dim3(64 * c->W_pv), c->lds_pv, c->stream, c->sa);
-  OCI_CK(c, hipGetLastError());
-  int rc = run_chunks(c, false);
-  if (rc) return rc;
-  if (c->h_st->done != kNonFinite) {
-    hipLaunchKernelGGL(k_step_end, dim3(c->grid), dim3(64 * c->W_ed), c->lds_ed, c->stream, c->sa);
-    OCI_CK(c, hipGetLastError());
-  }
-  return finish_step(c, info, false);
+  return solve_queued(c, 1, nullptr, info);
 }
 
 extern "C" int si_step(oci_ctx *c, oci_step_info *info) {
   if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
-  OCI_CK(c, hipEventRecord(c->ev0, c->stream));
-  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, c->stream, c->d_st, c->parity);
-  OCI_CK(c, hipGetLastError());
-  int rc = run_chunks(c, true);
-  if (rc) return rc;
-  if (c->h_st->done != kNonFinite) {
-    const int n = c->J * 4;
-    hipLaunchKernelGGL(k_copy_phi, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, c->stream,
-                       (const StepState *)c->d_st, (const double *)c->d_phi[0],
-                       (const double *)c->d_phi[1], c->d_phi_res, n);
-    OCI_CK(c, hipGetLastError());
-  }
-  return finish_step(c, info, true);
+  return si_run(c, info);
 }
 
 extern "C" int oci_solve(oci_ctx *c, int32_t n_steps, double *phi_out, int32_t phi_out_on_device,
                          oci_step_info *infos) {
   if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
   if (n_steps < 0) return fail(c, OCI_EINVAL, "n_steps must be >= 0");
+  if (n_steps == 0) return OCI_OK;
+  if (phi_out == nullptr || phi_out_on_device) return solve_queued(c, n_steps, phi_out, infos);
+  // host output: step by step, copying each step's flux
   int worst = OCI_OK;
   const size_t per = (size_t)c->J * 4;
   for (int k = 0; k < n_steps; ++k) {
     int rc = oci_step(c, infos ? &infos[k] : nullptr);
     if (rc < 0) return rc;
     if (rc == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
-    if (phi_out) {
-      OCI_CK(c, hipMemcpyAsync(phi_out + k * per, c->d_phi_res, per * sizeof(double),
-                               phi_out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                               c->stream));
-    }
+    OCI_CK(c, hipMemcpyAsync(phi_out + k * per, c->d_phi_res, per * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
   }
-  if (phi_out) OCI_CK(c, hipStreamSynchronize(c->stream));
+  OCI_CK(c, hipStreamSynchronize(c->stream));
   return worst;
 }
 
@@ -705,8 +916,10 @@ extern "C" void oci_destroy(oci_ctx *c) {
   hipStreamSynchronize(c->stream);
   drop_graphs(c);
   for (void *q : c->allocs) hipFree(q);
-  if (c->h_st) hipHostFree(c->h_st);
-  for (hipEvent_t e : {c->ev0, c->ev1, c->evA, c->evB})
+  if (c->h_ctl) hipHostFree(c->h_ctl);
+  if (c->h_rec) hipHostFree(c->h_rec);
+  if (c->d_rec) hipFree(c->d_rec);
+  for (hipEvent_t e : {c->ev0, c->ev1, c->evA, c->evB, c->evC, c->evD})
     if (e) hipEventDestroy(e);
   delete c;
 }

@@ -38,16 +38,36 @@ struct TileDev {
   int32_t region, c0, nc, pad;   // cells c0 .. c0+nc-1, all in one region, nc <= 16
 };
 
-// Iteration control word, one per context, in device memory.
-struct StepState {
-  int32_t it;        // iterations completed in the current step
-  int32_t done;      // 0 running, 1 converged, 2 iteration limit, 3 non-finite
-  uint32_t arrive;   // tiles that finished the current launch
-  int32_t total;     // iterations since the last state reset (ping-pong parity)
-  int32_t step_parity;  // which psi buffer holds psi_{k-1/2} in the current step
-  int32_t pad;
-  double e_last;     // e of the last iterate (-1: undefined)
-  double e_prev;     // e of the iterate before it (-1: undefined)
+// Step control block, one per context, in device memory.  Every field has
+// one writer (the first thread of work-group 0 of some launch, or the host
+// between launches), and a launch only relies on values written by earlier
+// launches: the kernel boundary orders them.  No kernel uses device-scope
+// fences or atomics (on this GPU a device-scope release after a kernel's
+// writes costs far more than a kernel boundary).
+struct StepCtl {
+  int32_t total0;        // iterations completed before this step (bookkeeping only)
+  int32_t accepted;      // written by the iteration launch that decides the step
+  int32_t status;        // kRunning from the step start; the decision once taken
+  int32_t step_parity;   // psi buffer holding psi_{k-1/2}
+  int32_t stalled;       // a queued step was not decided within its launches
+  int32_t fin_accepted;  // the step's outcome, written by the end-of-step kernel
+  int32_t fin_status;    //   (read by later launches and the host only, never by
+  int32_t pad;           //   the launch that writes it)
+  double e_last;         // e of the accepted iterate (-1: undefined)
+  double e_prev;         // source iteration: e of the previous iterate
+  double fin_e;
+};
+
+// Iterate l of a step (1-based) reads the outgoing fluxes and scalar flux of
+// iterate l-1 from buffer (l-1)&1 and writes buffer l&1; the step-start
+// kernel moves the previous step's last iterate into buffer 0 when it sits
+// in buffer 1, so buffer choice never depends on device data.
+
+// Per-step record of a queued solve.
+struct StepRecord {
+  int32_t accepted;
+  int32_t status;
+  double e_last;
 };
 
 enum { kRunning = 0, kConverged = 1, kIterLimit = 2, kNonFinite = 3 };
@@ -74,46 +94,101 @@ __device__ __forceinline__ int wave_or(int v) {
   return v;
 }
 
-__device__ __forceinline__ void store_agent(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double *p) {
-  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// e_l = max|phi^(l) - phi^(l-1)| / max|phi^(l)| (0/0 -> 0, x/0 -> inf).
+__device__ __forceinline__ double rel_change(double dphi, double phimax) {
+  if (phimax == 0.0) return dphi == 0.0 ? 0.0 : __builtin_inf();
+  return dphi / phimax;
 }
 
-// Shared stopping decision, taken by the last tile to finish an iteration.
-// dphi = max|phi^(l) - phi^(l-1)|, phimax = max|phi^(l)|, nonfinite flag.
-// first_defined: the first iteration (1-based) whose e is defined
-// (2 for OCI, 1 for SI).
-__device__ inline void decide(StepState *st, double dphi, double phimax, int nonfinite,
-                              int max_iters, double tol, int strict, int first_defined) {
-  const int l = st->it + 1;
+// Stopping rule for iterate l (1-based) given its residual maxima and the e
+// of iterate l-1 (-1 if undefined).  first_defined is the first iterate
+// whose e exists (2 for OCI: its first iterate has no predecessor in the
+// step; 1 for SI).  Returns the status and stores e_l (or -1) in *e_out.
+__device__ inline int stop_rule(int l, double dphi, double phimax, int nonfinite,
+                                double e_before, int first_defined, double tol, int strict,
+                                int max_iters, double *e_out) {
   double e = -1.0;
   int done = kRunning;
   if (nonfinite || !(dphi == dphi) || !(phimax == phimax)) {
     done = kNonFinite;
   } else if (l >= first_defined) {
-    if (phimax == 0.0) e = (dphi == 0.0) ? 0.0 : __builtin_inf();
-    else e = dphi / phimax;
+    e = rel_change(dphi, phimax);
     if (e <= tol) {
       if (!strict) {
         done = kConverged;
-      } else if (st->e_last >= 0.0) {
-        const double prev = st->e_last;
-        double rho = prev == 0.0 ? 0.0 : e / prev;
+      } else if (e_before >= 0.0) {
+        double rho = e_before == 0.0 ? 0.0 : e / e_before;
         rho = fmin(fmax(rho, 0.0), 0.9999);
         if (e * rho / (1.0 - rho) <= tol) done = kConverged;
       }
     }
   }
   if (done == kRunning && l >= max_iters) done = kIterLimit;
-  st->e_prev = st->e_last;
-  st->e_last = e;
-  st->it = l;
-  st->total = st->total + 1;
-  st->arrive = 0;
-  __threadfence();
-  st->done = done;
+  *e_out = e;
+  return done;
+}
+
+// max that propagates NaN (a non-finite residual travels as NaN).
+__device__ __forceinline__ double nan_max(double a, double b) {
+  return (a != a || a > b) ? a : b;
+}
+
+__device__ __forceinline__ double wave_nan_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// Residual records: one double2 per tile or block, (max|phi^(l) - phi^(l-1)|,
+// max|phi^(l)|), the first set to NaN when any value of phi^(l) is not
+// finite.  Slot s of a record array holds iterate l with l % 3 == s.
+//
+// Work-group reduction of n records: each thread's first kRecBatch records are
+// loaded by rec_issue (so the loads can start at kernel entry) and combined
+// with the rest by rec_finish into out[0..1] in LDS (ends with a barrier; every
+// thread of the work-group must take part).
+constexpr int kRecBatch = 4;
+struct RecRegs {
+  double2 v[kRecBatch];
+};
+
+__device__ __forceinline__ void rec_issue(RecRegs &r, const double2 *rec, int n) {
+#pragma unroll
+  for (int q = 0; q < kRecBatch; ++q) {
+    const int i = threadIdx.x + q * blockDim.x;
+    r.v[q] = i < n ? rec[i] : make_double2(0.0, 0.0);
+  }
+}
+
+__device__ inline void rec_finish(const RecRegs &r, const double2 *rec, int n, double *out,
+                                  double *scratch) {
+  double d = 0.0, f = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRecBatch; ++q) {
+    d = nan_max(d, r.v[q].x);
+    f = nan_max(f, r.v[q].y);
+  }
+  for (int i = threadIdx.x + kRecBatch * blockDim.x; i < n; i += blockDim.x) {
+    const double2 v = rec[i];
+    d = nan_max(d, v.x);
+    f = nan_max(f, v.y);
+  }
+  d = wave_nan_max(d);
+  f = wave_nan_max(f);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  if (lane == 0) {
+    scratch[wave * 2 + 0] = d;
+    scratch[wave * 2 + 1] = f;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < W; ++w) {
+      d = nan_max(d, scratch[w * 2 + 0]);
+      f = nan_max(f, scratch[w * 2 + 1]);
+    }
+    out[0] = d;
+    out[1] = f;
+  }
+  __syncthreads();
 }
 
 }  // namespace ocik

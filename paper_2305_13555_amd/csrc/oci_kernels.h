@@ -10,11 +10,14 @@ struct StepArgs {
   const TileDev *tiles;
   int ntiles;
   int N, J, Mt, Met;
+  int Mto;                 // row tiles of the outgoing rows alone (the GEMM of an iteration)
   int bcl, bcr;
   int max_iters, strict;
   double tol;
   const double *frag_it;   // G (iteration), per region stride frag_it_stride
   size_t frag_it_stride;
+  const double *hphi;      // H: the scalar-flux rows of G, [R][4][2N] row-major
+  size_t hphi_stride;
   const double *frag_pv;   // P (per-step constant)
   size_t frag_pv_stride;
   const double *c_pv;      // p
@@ -28,9 +31,9 @@ struct StepArgs {
   double *phi0, *phi1;     // [J][4]
   double *psi0, *psi1;     // [J][2N]
   double *phi_res;         // [J][4]
-  double *partial;         // [ntiles][4]
-  StepState *st;
-  int step_parity;         // set into the state by k_step_begin
+  double *partial;         // [3][ntiles] double2 residual records, slot = iterate % 3
+  StepCtl *ctl;
+  StepRecord *rec;         // [steps] records of a queued solve
 };
 
 struct SiArgs {
@@ -46,9 +49,9 @@ struct SiArgs {
   double *contrib;          // [N/2][J][4] pair sums of w_m psi_m
   double *lag;              // [N/2][2] right-edge outgoing flux of the mu > 0 angle
   double *phi_res;          // [J][4]
-  double *partial;          // [nblocks][4]
+  double *partial;          // [3][nparts] double2 residual records
   int nparts;
-  StepState *st;
+  StepCtl *ctl;
 };
 
 // setup.hip
@@ -59,17 +62,19 @@ __global__ void k_select_rows(int N, const double *w, const double *ws_X, double
 __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
                        int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
                        size_t cvec_stride);
-// oci_step.hip
-__global__ void k_step_begin(StepArgs a);
-__global__ void k_oci_iterate(StepArgs a);
-__global__ void k_step_end(StepArgs a);
+__global__ void k_pack_rows(int N, const double *op_all, int row0, int rows, int col0, int ncols,
+                            double *dst_all, size_t dst_stride);
+// oci_step.hip (CH = operator k-steps fetched per batch: 4, 8 or 16)
+template <int CH> __global__ void k_step_begin(StepArgs a, int parity);
+template <int CH> __global__ void k_oci_iterate(StepArgs a, int node, int cb);
+template <int CH> __global__ void k_step_end(StepArgs a, int step, double *phi_out, int last);
 // si.hip
 __global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,
                             double *ainv);
-__global__ void k_si_sweep(SiArgs a);
-__global__ void k_si_reduce(SiArgs a);
-__global__ void k_state_reset(StepState *st, int parity);
-__global__ void k_copy_phi(const StepState *st, const double *phi0, const double *phi1,
-                           double *phi_res, int n);
+__global__ void k_si_sweep(SiArgs a, int node, int cb);
+__global__ void k_si_reduce(SiArgs a, int node, int cb);
+__global__ void k_si_decide(SiArgs a, int node, int cb);
+__global__ void k_si_begin(SiArgs a, int parity);
+__global__ void k_si_end(SiArgs a);
 
 }  // namespace ocik

@@ -99,13 +99,16 @@ __device__ __forceinline__ CellSolve cell_solve(const SiArgs &a, const double *p
   return s;
 }
 
-__global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a) {
-  StepState *st = a.st;
-  if (st->done != kRunning || st->it >= a.max_iters) return;
-  const int total = st->total;
-  const int parity = st->step_parity;
-  const double *phi_old = (total & 1) ? a.phi1 : a.phi0;
-  double *out_dst = (total & 1) ? a.out0 : a.out1;
+// Iteration l = cb + node: sweep every angle pair with the scalar flux of
+// iterate l-1.
+__global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a, int node, int cbase) {
+  const StepCtl c = *a.ctl;
+  if (c.stalled || c.status != kRunning) return;
+  const int l = cbase + node;
+  const int par = (l - 1) & 1;
+  const int parity = c.step_parity;
+  const double *phi_old = par ? a.phi1 : a.phi0;
+  double *out_dst = par ? a.out0 : a.out1;
   const double *ghosts = a.out0;   // ghost rows are identical in both buffers
   const double *psi_prev = parity ? a.psi1 : a.psi0;
   double *psi_next = parity ? a.psi0 : a.psi1;
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a) {
   const int m_neg = p, m_pos = N - 1 - p;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int C = (J + nt - 1) / nt;
-  const int cb = min(J, tid * C), ce = min(J, (tid + 1) * C);
+  const int jb = min(J, tid * C), je = min(J, (tid + 1) * C);
 
   __shared__ Affine s_map[1024];
   __shared__ double s_exit[2];
@@ -143,8 +146,8 @@ __global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a) {
     const int o0 = pos ? 1 : 0, o1 = pos ? 3 : 2;
     // phase 1: compose this thread's chunk in sweep order
     Affine f = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
-    for (int q = 0; q < ce - cb; ++q) {
-      const int j = pos ? cb + q : ce - 1 - q;
+    for (int q = 0; q < je - jb; ++q) {
+      const int j = pos ? jb + q : je - 1 - q;
       const CellSolve s = cell_solve(a, phi_old, psi_prev, j, m, pos, amu);
       const Affine g = {s.c0[o0], s.c1[o0], s.c0[o1], s.c1[o1], s.y[o0], s.y[o1]};
       f = compose(g, f);
@@ -168,8 +171,8 @@ __global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a) {
       x1 = e.m10 * xb0 + e.m11 * xb1 + e.v1;
     }
     // phase 3: re-sweep the chunk from its entering flux
-    for (int q = 0; q < ce - cb; ++q) {
-      const int j = pos ? cb + q : ce - 1 - q;
+    for (int q = 0; q < je - jb; ++q) {
+      const int j = pos ? jb + q : je - 1 - q;
       const CellSolve s = cell_solve(a, phi_old, psi_prev, j, m, pos, amu);
       double x[4];
       for (int i = 0; i < 4; ++i) x[i] = s.y[i] + s.c0[i] * x0 + s.c1[i] * x1;
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a) {
     }
     __syncthreads();
     // the thread owning the last cell of the sweep publishes the leaving flux
-    const bool owns_last = ce > cb && (pos ? ce == J : cb == 0);
+    const bool owns_last = je > jb && (pos ? je == J : jb == 0);
     if (owns_last) { s_exit[0] = x0; s_exit[1] = x1; }
     __syncthreads();
   }
@@ -200,85 +203,105 @@ __global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a) {
   }
 }
 
-// phi^(l) = sum over pairs of the contributions; residual; last block decides.
-__global__ __launch_bounds__(256) void k_si_reduce(SiArgs a) {
-  StepState *st = a.st;
-  if (st->done != kRunning || st->it >= a.max_iters) return;
-  const int total = st->total;
-  const double *phi_old = (total & 1) ? a.phi1 : a.phi0;
-  double *phi_new = (total & 1) ? a.phi0 : a.phi1;
+// phi^(l) = sum over the angle pairs' contributions (fixed order), and each
+// block's residual record.
+__global__ __launch_bounds__(256) void k_si_reduce(SiArgs a, int node, int cb) {
+  const StepCtl c = *a.ctl;
+  if (c.stalled || c.status != kRunning) return;
+  const int l = cb + node;
+  const int par = (l - 1) & 1;
+  const double *phi_old = par ? a.phi1 : a.phi0;
+  double *phi_new = par ? a.phi0 : a.phi1;
   const int npairs = a.N / 2;
   const int J = a.J;
   double d = 0.0, f = 0.0;
-  int nf = 0;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < J * 4) {
     double s = 0.0;
     for (int p = 0; p < npairs; ++p) s += a.contrib[(size_t)p * J * 4 + idx];
     phi_new[idx] = s;
-    d = fabs(s - phi_old[idx]);
+    d = isfinite(s) ? fabs(s - phi_old[idx]) : __builtin_nan("");
     f = fabs(s);
-    nf = !isfinite(s);
   }
   __shared__ double sd[4], sf[4];
-  __shared__ int snf[4];
-  d = wave_max(d);
+  d = wave_nan_max(d);
   f = wave_max(f);
-  nf = wave_or(nf);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) { sd[wave] = d; sf[wave] = f; snf[wave] = nf; }
+  if (lane == 0) { sd[wave] = d; sf[wave] = f; }
   __syncthreads();
-  if (wave != 0) return;
-  const int nw = blockDim.x >> 6;
-  d = lane < nw ? sd[lane] : 0.0;
-  f = lane < nw ? sf[lane] : 0.0;
-  nf = lane < nw ? snf[lane] : 0;
-  d = wave_max(d);
-  f = wave_max(f);
-  nf = wave_or(nf);
-  unsigned prev = 0;
-  if (lane == 0) {
-    double *pp = a.partial + (size_t)blockIdx.x * 4;
-    store_agent(pp + 0, d);
-    store_agent(pp + 1, f);
-    store_agent(pp + 2, (double)nf);
-    __threadfence();
-    prev = atomicAdd(&st->arrive, 1u);
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int w = 1; w < nw; ++w) {
+      d = nan_max(d, sd[w]);
+      f = fmax(f, sf[w]);
+    }
+    reinterpret_cast<double2 *>(a.partial)[(size_t)(l % 3) * a.nparts + blockIdx.x] =
+        make_double2(d, f);
   }
-  prev = __shfl(prev, 0, kWave);
-  if (prev != (unsigned)(a.nparts - 1)) return;
-  __threadfence();
-  double dd = 0.0, ff = 0.0, nn = 0.0;
-  for (int i = lane; i < a.nparts; i += kWave) {
-    const double *pp = a.partial + (size_t)i * 4;
-    dd = fmax(dd, load_agent(pp + 0));
-    ff = fmax(ff, load_agent(pp + 1));
-    nn = fmax(nn, load_agent(pp + 2));
-  }
-  dd = wave_max(dd);
-  ff = wave_max(ff);
-  nn = wave_max(nn);
-  if (lane == 0) decide(st, dd, ff, nn != 0.0, a.max_iters, a.tol, a.strict, 1);
 }
 
-__global__ void k_state_reset(StepState *st, int parity) {
+// Stopping decision for iterate l (one work-group).
+__global__ __launch_bounds__(256) void k_si_decide(SiArgs a, int node, int cb) {
+  __shared__ double red[2], scratch[2 * 4];
+  const StepCtl c = *a.ctl;
+  if (c.stalled || c.status != kRunning) return;
+  const int l = cb + node;
+  const double2 *recs = reinterpret_cast<const double2 *>(a.partial) + (size_t)(l % 3) * a.nparts;
+  RecRegs r;
+  rec_issue(r, recs, a.nparts);
+  rec_finish(r, recs, a.nparts, red, scratch);
+  if (threadIdx.x != 0) return;
+  double e;
+  const int dn = stop_rule(l, red[0], red[1], 0, c.e_prev, 1, a.tol, a.strict, a.max_iters, &e);
+  StepCtl *ct = a.ctl;
+  if (dn != kRunning) {
+    ct->accepted = l;
+    ct->e_last = e;
+    ct->status = dn;
+  } else {
+    ct->e_prev = e;
+  }
+}
+
+// Start of a source-iteration step: the previous step's last iterate moved
+// into buffer 0 when it sits in buffer 1, and the step opened (the first
+// thread leaves the fields the other work-groups read here alone).
+__global__ void k_si_begin(SiArgs a, int parity) {
+  const StepCtl c = *a.ctl;
+  if (c.stalled) return;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->it = 0;
-    st->done = kRunning;
-    st->arrive = 0;
-    st->step_parity = parity;
-    st->e_last = -1.0;
-    st->e_prev = -1.0;
+    StepCtl *ct = a.ctl;
+    ct->total0 = c.total0 + c.fin_accepted;
+    ct->status = kRunning;
+    ct->step_parity = parity;
+    ct->e_last = -1.0;
+    ct->e_prev = -1.0;
   }
+  if (!(c.fin_accepted & 1)) return;
+  const int K = 2 * a.N;
+  const size_t nout = (size_t)a.J * K, nphi = (size_t)a.J * 4;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nout; i += stride)
+    a.out0[K + i] = a.out1[K + i];
+  for (size_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nphi; i += stride)
+    a.phi0[i] = a.phi1[i];
 }
 
-// Copy the accepted scalar flux of the step (the buffer the last iteration
-// wrote) to the result buffer.
-__global__ void k_copy_phi(const StepState *st, const double *phi0, const double *phi1,
-                           double *phi_res, int n) {
-  const double *src = (st->total & 1) ? phi1 : phi0;
+// End of a decided step: the accepted scalar flux to the result buffer (the
+// last sweep already wrote psi_{k+1/2}).
+__global__ void k_si_end(SiArgs a) {
+  const StepCtl c = *a.ctl;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    StepCtl *ct = a.ctl;
+    ct->fin_accepted = c.accepted;
+    ct->fin_status = c.status;
+    ct->fin_e = c.e_last;
+  }
+  if (c.stalled || c.status == kRunning || c.status == kNonFinite) return;
+  const double *src = (c.accepted & 1) ? a.phi1 : a.phi0;
+  const int n = a.J * 4;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    phi_res[i] = src[i];
+    a.phi_res[i] = src[i];
 }
 
 }  // namespace ocik

@@ -262,3 +262,28 @@ def test_quadrature_and_steady(lib):
         np.testing.assert_allclose(mu, cd.mu, atol=1e-15)
         ctx.step()
         assert rel(ctx.flux(), direct[0]["phi"]) < 1e-10
+
+
+@pytest.mark.parametrize("which", ["config1", "config2_small"])
+def test_queued_solve_matches_step_by_step(lib, which):
+    """oci_solve queues every step with a fixed batch of iteration launches;
+    steps that need more stall the queue and are resumed from the host.  The
+    result must equal stepping one at a time, bit for bit (same tile
+    arithmetic, same decisions).  config1 needs ~19 iterations per step, so
+    the first queue (batch 2) stalls at every step."""
+    import torch
+    p = W.config1() if which == "config1" else W.config2(n_steps=4, n_cells=700, n_regions=5,
+                                                           n_angles=16)
+    steps = 4
+    a = gpu_run(lib, p, steps)
+    with lib.OciContext(p) as ctx:
+        out = torch.zeros((steps, ctx.n_cells, 4), dtype=torch.float64, device="cuda")
+        rc, infos = ctx.solve(steps, out)
+        assert rc == lib.OCI_OK
+        got = out.cpu().numpy()
+        psi = ctx.state()[0]
+        assert ctx.state()[1] == steps
+    for k in range(steps):
+        assert infos[k]["iterations"] == a[k]["iterations"]
+        assert np.array_equal(got[k], a[k]["phi"])
+    assert np.array_equal(psi, a[-1]["psi_edge"])
