@@ -41,25 +41,29 @@ def algorithmic_bytes_per_cell_step(n_angles):
     return 8 * (10 * n_angles + 12)
 
 
-def roofline_launch_seconds(oci, prob, stream, batches=5):
+def roofline_launch_seconds(oci, prob, stream, steps=5):
     """Per-launch time of k_oci_iterate on the workload's cells, regions and
-    angles, with v = inf and tol = 0 so that every one of a batch of 32
-    iteration launches does the full work (the kernel's work does not depend
-    on the values).  The first step reaches the batch length; each later step
-    replays its 32 launches as one graph, timed with HIP events on the
-    library's stream around the batch alone (dispatch gaps included).
-    Returns the median over `batches` steps of batch time / 32."""
+    angles, with v = inf and tol = 0 so that every iteration launch does the
+    full work (the kernel's work does not depend on the values).  Steps of 32
+    and of 16 iteration launches each run as one replayed graph (step start,
+    the launches, end of step), timed with HIP events on the library's stream;
+    the per-launch time is the difference of the median step times over the
+    16 extra launches, which removes the step start and end."""
     import dataclasses
     roof = dataclasses.replace(prob, speed=float("inf"), name=prob.name + ", v = inf")
-    per = []
-    with oci.OciContext(roof, stream=stream, tol=0.0, max_iters=32) as cr:
-        cr.step()
-        for _ in range(batches):
-            rc, info = cr.step()
-            if info["launches"] != 32 or info["iterations"] != 32:
-                raise RuntimeError("roofline batch did not run 32 full launches: %r" % (info,))
-            per.append(info["iter_ms"] * 1e-3 / info["launches"])
-    return float(np.median(per))
+    med = {}
+    for n in (32, 16):
+        with oci.OciContext(roof, stream=stream, tol=0.0, max_iters=n) as cr:
+            cr.step()
+            ms = []
+            for _ in range(steps):
+                rc, info = cr.step()
+                if info["launches"] != n or info["iterations"] != n:
+                    raise RuntimeError("roofline step did not run %d full launches: %r"
+                                       % (n, info))
+                ms.append(info["ms"])
+            med[n] = float(np.median(ms))
+    return (med[32] - med[16]) * 1e-3 / 16
 
 
 def copy_calibration(torch, mib):
@@ -126,7 +130,7 @@ def main():
     J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
     stream = torch.cuda.current_stream()
     if args.roofline_only:
-        t = roofline_launch_seconds(oci, prob, stream, batches=2)
+        t = roofline_launch_seconds(oci, prob, stream, steps=3)
         nbytes = copy_calibration(torch, 64)
         b = algorithmic_bytes_per_cell_iteration(N) * J
         print(json.dumps({"kernel": "k_oci_iterate", "us_per_launch": t * 1e6,
@@ -217,7 +221,7 @@ def main():
             "traffic": None,
             "bytes_per_launch": bytes_launch,
             "us_per_launch": per_launch_s * 1e6,
-            "measured": "median of 5 batches of 32 launches",
+            "measured": "(median step time at 32 launches - at 16) / 16, 5 steps each",
         },
         "cpu_baseline": cpu,
         "iterations_per_time_step": iters / (args.steps * T),

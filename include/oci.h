@@ -111,15 +111,13 @@ typedef struct {
   int32_t status;      /* OCI_OK, OCI_NOT_CONVERGED or OCI_ENONFINITE */
   double residual;     /* e of the accepted (or last) iterate; -1 if undefined */
   double ms;           /* stream time of the step, milliseconds; steps queued
-                          together by oci_solve share their queue's time evenly */
-  double iter_ms;      /* a step queued alone (oci_step, or the last step of a
-                          solve when it had to be re-queued): stream time of its
-                          first batch of iteration launches alone (events around
-                          the batch); a step resumed after its batch: time of the
-                          resumed part; otherwise equal to ms */
-  int32_t launches;    /* iteration kernels launched in the timed batch (>=
-                          iterations there; launches after the decision exit at
-                          once); 0 when iter_ms is a share of a queue */
+                          together share their window's time evenly */
+  double iter_ms;      /* source iteration: stream time of the iteration
+                          launches alone; OCI: for a step resumed after its
+                          queued launches left it undecided, the time of the
+                          resumed part, otherwise equal to ms */
+  int32_t launches;    /* iteration kernels launched for the step (>=
+                          iterations; launches after the decision exit at once) */
   int32_t pad;
 } oci_step_info;
 

@@ -1,21 +1,24 @@
 // Host driver behind the C ABI declared in include/oci.h.
 //
 // One context = one slab problem bound to one HIP stream.  oci_setup builds
-// every region's operator on the GPU.  An OCI time step is: the step-start
-// kernel (per-step constant), a batch of iteration launches replayed from a
-// HIP graph (each launch decides the previous iterate from the residual
-// records the launch before it left, and exits at once once the step is
-// decided), and the end-of-step kernel, which decides the batch's last
-// iterate itself when no launch did.  oci_solve and oci_step queue every step
-// without waiting; a step not decided within its batch stalls the queue on the
-// device, the host resumes it with further launches and queues the rest.
-// Source iteration runs one step at a time with host-read decisions.
+// every region's operator on the GPU.  An OCI time step is the step-start
+// kernel (per-step constant), L iteration launches (each decides the previous
+// iterate from the residual records the launch before it left, and exits at
+// once once the step is decided), and the end-of-step kernel, which decides
+// the last iterate itself when no launch did.  Every argument of these
+// kernels is static (the step index and buffers come from the device control
+// block), so whole steps are replayed from cached HIP graphs.  oci_solve and
+// oci_step queue windows of steps without waiting, L = the iteration count of
+// the latest completed window; a step not decided within its L launches
+// stalls the queue on the device and the host resumes it.  Source iteration
+// runs one step at a time with host-read decisions.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -42,7 +45,9 @@ struct oci_ctx {
   std::vector<double> ghost_left, ghost_right;   // [2N] each
   int Mt = 0, Met = 0, Mto = 0, ntiles = 0, grid = 0, W_it = 1, W_ed = 1, W_pv = 1;
   size_t lds_it = 0, lds_pv = 0, lds_ed = 0;
-  int si_blocks = 0;
+  int lu_cb = 0, lu_pitch = 0;   // LDS LU: right-hand-side columns per work-group, row pitch
+  size_t lds_lu = 0;
+  int si_blocks = 0, si_segs = 1;
   std::vector<void *> allocs;
   double *d_mu = nullptr, *d_w = nullptr;
   RegionDev *d_regions = nullptr;
@@ -56,6 +61,7 @@ struct oci_ctx {
   double *d_gh = nullptr, *d_out[2] = {nullptr, nullptr}, *d_phi[2] = {nullptr, nullptr};
   double *d_psi[2] = {nullptr, nullptr}, *d_phi_res = nullptr, *d_partial = nullptr;
   double *d_ainv = nullptr, *d_contrib = nullptr, *d_lag = nullptr, *d_si_partial = nullptr;
+  Affine *d_segmap = nullptr;
   StepCtl *d_ctl = nullptr;
   StepCtl *h_ctl = nullptr;                  // pinned host copy of the control block
   StepRecord *d_rec = nullptr, *h_rec = nullptr;
@@ -63,11 +69,17 @@ struct oci_ctx {
   int parity = 0;
   int64_t steps = 0;
   bool have_flux = false;
-  int last_oci_iters = 0, last_si_iters = 0;
-  hipGraphExec_t oci_graph[kMaxBatch + 1] = {};   // indexed by batch length
-  hipGraphExec_t si_graph[kMaxBatch + 1] = {};
+  int last_si_iters = 0;
+  hipGraphExec_t si_graph[kMaxBatch + 1] = {};    // indexed by batch length
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evA = nullptr, evB = nullptr;
-  hipEvent_t evC = nullptr, evD = nullptr;   // around a lone step's iteration batch
+  hipEvent_t evW[2][2] = {};                 // start / end of the windows in flight
+  struct StepGraph {
+    int L, G;
+    double *phi;
+    hipGraphExec_t exec;
+  };
+  std::vector<StepGraph> step_graphs;        // G whole steps of L iteration launches
+  int batch_hint = 0;                        // iteration launches per queued step
   bool quad_override = false;
   double *ws_M = nullptr, *ws_X = nullptr;   // setup workspace, kept for oci_refactor
   int *d_bad = nullptr;
@@ -176,20 +188,19 @@ static int reset_iterate(oci_ctx *c) {
     OCI_CK(c, hipMemsetAsync(c->d_out[b], 0, (size_t)(c->J + 2) * K * sizeof(double), c->stream));
     OCI_CK(c, hipMemsetAsync(c->d_phi[b], 0, (size_t)c->J * 4 * sizeof(double), c->stream));
   }
-  OCI_CK(c, hipMemsetAsync(c->d_lag, 0, (size_t)c->N * sizeof(double), c->stream));
+  OCI_CK(c, hipMemsetAsync(c->d_lag, 0, (size_t)2 * c->N * sizeof(double), c->stream));
   OCI_CK(c, hipMemsetAsync(c->d_ctl, 0, sizeof(StepCtl), c->stream));
   int rc = upload_ghosts(c);
   if (rc) return rc;
-  c->last_oci_iters = 0;
   c->last_si_iters = 0;
+  c->batch_hint = 0;
   return OCI_OK;
 }
 
-// The first batch of a step as a replayable graph: `count` iteration
-// launches (nodes 1..count; OCI), or `count` source iterations of sweep,
-// reduce and decide launches (SI).
-static int build_graph(oci_ctx *c, bool si, int count) {
-  hipGraphExec_t *slot = si ? &c->si_graph[count] : &c->oci_graph[count];
+// The first batch of a source-iteration step as a replayable graph: `count`
+// iterations of sweep, reduce and decide launches.
+static int build_si_graph(oci_ctx *c, int count) {
+  hipGraphExec_t *slot = &c->si_graph[count];
   if (*slot) return OCI_OK;
   hipGraph_t g;
   OCI_CK(c, hipGraphCreate(&g, 0));
@@ -210,15 +221,11 @@ static int build_graph(oci_ctx *c, bool si, int count) {
   hipError_t e = hipSuccess;
   for (int i = 1; i <= count && e == hipSuccess; ++i) {
     int node = i, cb = 0;
-    if (!si) {
-      void *args[] = {&c->sa, &node, &cb};
-      e = add(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), c->lds_it, args);
-    } else {
-      void *args[] = {&c->si, &node, &cb};
-      e = add((void *)k_si_sweep, dim3(c->N / 2), dim3(1024), 0, args);
-      if (e == hipSuccess) e = add((void *)k_si_reduce, dim3(c->si_blocks), dim3(256), 0, args);
-      if (e == hipSuccess) e = add((void *)k_si_decide, dim3(1), dim3(256), 0, args);
-    }
+    void *args[] = {&c->si, &node, &cb};
+    e = add((void *)k_si_maps, dim3(c->N / 2, c->si_segs), dim3(256), 0, args);
+    if (e == hipSuccess) e = add((void *)k_si_sweep, dim3(c->N / 2, c->si_segs), dim3(256), 0, args);
+    if (e == hipSuccess) e = add((void *)k_si_reduce, dim3(c->si_blocks), dim3(256), 0, args);
+    if (e == hipSuccess) e = add((void *)k_si_decide, dim3(1), dim3(256), 0, args);
   }
   if (e != hipSuccess) {
     hipGraphDestroy(g);
@@ -243,7 +250,13 @@ static int build_operators(oci_ctx *c) {
   OCI_CK(c, hipMemsetAsync(d_bad, 0, sizeof(int), c->stream));
   hipLaunchKernelGGL(k_build_system, dim3(R), dim3(256), 0, c->stream, c->d_regions, c->d_mu,
                      c->d_w, N, c->a, ws_M, ws_X);
-  hipLaunchKernelGGL(k_lu_solve, dim3(R), dim3(1024), 0, c->stream, N, ws_M, ws_X, d_bad);
+  if (c->lu_cb > 0) {
+    const int n = 4 * N, nr = n + 1;
+    hipLaunchKernelGGL(k_lu_solve_lds, dim3(R, (nr + c->lu_cb - 1) / c->lu_cb), dim3(1024),
+                       c->lds_lu, c->stream, N, c->lu_cb, c->lu_pitch, ws_M, ws_X, d_bad);
+  } else {
+    hipLaunchKernelGGL(k_lu_solve, dim3(R), dim3(1024), 0, c->stream, N, ws_M, ws_X, d_bad);
+  }
   hipLaunchKernelGGL(k_select_rows, dim3(R), dim3(256), 0, c->stream, N, c->d_w, ws_X, c->d_op);
   // iteration operator G: rows [0, 2N+4), columns [0, 2N) (incident)
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, 0, K,
@@ -267,11 +280,15 @@ static int build_operators(oci_ctx *c) {
   return OCI_OK;
 }
 
+static void drop_step_graphs(oci_ctx *c) {
+  for (auto &g : c->step_graphs) hipGraphExecDestroy(g.exec);
+  c->step_graphs.clear();
+}
+
 static void drop_graphs(oci_ctx *c) {
+  drop_step_graphs(c);
   for (int i = 0; i <= kMaxBatch; ++i) {
-    if (c->oci_graph[i]) hipGraphExecDestroy(c->oci_graph[i]);
     if (c->si_graph[i]) hipGraphExecDestroy(c->si_graph[i]);
-    c->oci_graph[i] = nullptr;
     c->si_graph[i] = nullptr;
   }
 }
@@ -336,6 +353,9 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->lds_pv = (size_t)kTileCells * P * sizeof(double);
   c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
   c->si_blocks = (J * 4 + 255) / 256;
+  // source-iteration sweep segments: about two cells per thread of a
+  // 256-thread work-group, at most 64 segments
+  c->si_segs = std::max(1, std::min(64, (J + 511) / 512));
   c->ghost_left.assign(K, 0.0);
   c->ghost_right.assign(K, 0.0);
   if (p->bc_left == OCI_BC_INCIDENT)
@@ -389,7 +409,8 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_partial, (size_t)3 * c->ntiles * 4));
   OCI_TRY(dalloc(c, &c->d_ainv, (size_t)R * N * 16));
   OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(N / 2) * J * 4));
-  OCI_TRY(dalloc(c, &c->d_lag, (size_t)N));
+  OCI_TRY(dalloc(c, &c->d_lag, (size_t)2 * N));
+  OCI_TRY(dalloc(c, &c->d_segmap, (size_t)(N / 2) * c->si_segs * 2));
   OCI_TRY(dalloc(c, &c->d_si_partial, (size_t)3 * c->si_blocks * 4));
   OCI_TRY(dalloc(c, &c->d_ctl, 1));
   {
@@ -400,7 +421,8 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreate(&c->evA) != hipSuccess || hipEventCreate(&c->evB) != hipSuccess ||
-      hipEventCreate(&c->evC) != hipSuccess || hipEventCreate(&c->evD) != hipSuccess)
+      hipEventCreate(&c->evW[0][0]) != hipSuccess || hipEventCreate(&c->evW[0][1]) != hipSuccess ||
+      hipEventCreate(&c->evW[1][0]) != hipSuccess || hipEventCreate(&c->evW[1][1]) != hipSuccess)
     return cleanup(fail(c, OCI_EDEVICE, "hipEventCreate failed"));
 
   auto up = [&](void *dst, const void *src, size_t bytes) -> int {
@@ -413,6 +435,21 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(up(c->d_tiles, tiles.data(), tiles.size() * sizeof(TileDev)));
   OCI_TRY(up(c->d_cell_region, cell_region.data(), (size_t)J * sizeof(int)));
 
+  // LU in LDS when M and a block of >= 8 right-hand sides fit in 160 KiB
+  {
+    const size_t cap = 160 * 1024 - 64;
+    const int maxw = (int)(cap / ((size_t)n * sizeof(double)));   // widest odd-pitch row
+    int cb = std::min(nr, maxw - n - 1);
+    if (cb >= 8) {
+      int pitch = n + cb;
+      if (!(pitch & 1)) pitch += 1;
+      c->lu_cb = cb;
+      c->lu_pitch = pitch;
+      c->lds_lu = (size_t)n * pitch * sizeof(double);
+      hipFuncSetAttribute((const void *)k_lu_solve_lds,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_lu);
+    }
+  }
   OCI_TRY(dalloc(c, &c->ws_M, (size_t)R * n * n));
   OCI_TRY(dalloc(c, &c->ws_X, (size_t)R * n * nr));
   OCI_TRY(dalloc(c, &c->d_bad, 1));
@@ -487,6 +524,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   q.psi1 = c->d_psi[1];
   q.contrib = c->d_contrib;
   q.lag = c->d_lag;
+  q.segmap = c->d_segmap;
   q.phi_res = c->d_phi_res;
   q.partial = c->d_si_partial;
   q.nparts = c->si_blocks;
@@ -546,8 +584,10 @@ static int launch_batch(oci_ctx *c, bool si, int cb, int count) {
                                 c->stream));
     } else {
       void *args[] = {&c->si, &node, &cb};
-      OCI_CK(c, hipLaunchKernel((const void *)k_si_sweep, dim3(c->N / 2), dim3(1024), args, 0,
-                                c->stream));
+      OCI_CK(c, hipLaunchKernel((const void *)k_si_maps, dim3(c->N / 2, c->si_segs), dim3(256),
+                                args, 0, c->stream));
+      OCI_CK(c, hipLaunchKernel((const void *)k_si_sweep, dim3(c->N / 2, c->si_segs), dim3(256),
+                                args, 0, c->stream));
       OCI_CK(c, hipLaunchKernel((const void *)k_si_reduce, dim3(c->si_blocks), dim3(256), args, 0,
                                 c->stream));
       OCI_CK(c, hipLaunchKernel((const void *)k_si_decide, dim3(1), dim3(256), args, 0,
@@ -593,7 +633,7 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
     OCI_CK(c, hipEventRecord(c->evA, c->stream));
     if (launched == 0) {
       count = std::min(std::max(c->last_si_iters, 1), std::min(kMaxBatch, c->max_iters));
-      rc = build_graph(c, true, count);
+      rc = build_si_graph(c, count);
       if (rc) return rc;
       OCI_CK(c, hipGraphLaunch(c->si_graph[count], c->stream));
     } else {
@@ -636,146 +676,245 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
 // ---------------------------------------------------------------------------
 // One-cell inversion: queued steps.
 // ---------------------------------------------------------------------------
+constexpr int kWindow = 8;   // steps per queued window (one graph of whole steps)
+constexpr int kColdBatch = 8;  // launches of a step with no previous step to go by
+
+// Per-step records of a solve; the step graphs hold the device pointer, so
+// growing the buffer drops them.
 static int grow_records(oci_ctx *c, int n) {
   if (n <= c->rec_cap) return OCI_OK;
+  drop_step_graphs(c);
   if (c->d_rec) hipFree(c->d_rec);
   if (c->h_rec) hipHostFree(c->h_rec);
   c->d_rec = nullptr;
   c->h_rec = nullptr;
   c->rec_cap = 0;
-  const int cap = std::max(n, 128);
+  c->sa.rec = nullptr;
+  const int cap = std::max(n, 1024);
   OCI_CK(c, hipMalloc(&c->d_rec, cap * sizeof(StepRecord)));
   OCI_CK(c, hipHostMalloc((void **)&c->h_rec, cap * sizeof(StepRecord), hipHostMallocDefault));
   c->rec_cap = cap;
+  c->sa.rec = c->d_rec;
   return OCI_OK;
 }
 
-static int launch_end(oci_ctx *c, int step, double *phi_dev, int last) {
-  void *args[] = {&c->sa, &step, &phi_dev, &last};
+// G whole steps as one replayable graph: step start, L iteration launches,
+// end of step (which writes phi_out[step] when phi is given).  Every argument
+// is static: the step index and psi buffer come from the control block.
+static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out) {
+  for (auto &g : c->step_graphs)
+    if (g.L == L && g.G == G && g.phi == phi) {
+      *out = g.exec;
+      return OCI_OK;
+    }
+  if (c->step_graphs.size() >= 16) drop_step_graphs(c);
+  hipGraph_t g;
+  OCI_CK(c, hipGraphCreate(&g, 0));
+  hipGraphNode_t prev = nullptr;
+  auto add = [&](void *fn, int W, size_t lds, void **args) -> hipError_t {
+    hipKernelNodeParams kp{};
+    kp.func = fn;
+    kp.gridDim = dim3(c->grid);
+    kp.blockDim = dim3(64 * W);
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e == hipSuccess) prev = node;
+    return e;
+  };
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < G && e == hipSuccess; ++s) {
+    void *bargs[] = {&c->sa};
+    e = add(c->fn_begin, c->W_pv, c->lds_pv, bargs);
+    for (int i = 1; i <= L && e == hipSuccess; ++i) {
+      int node = i, cb = 0;
+      void *args[] = {&c->sa, &node, &cb};
+      e = add(c->fn_iter, c->W_it, c->lds_it, args);
+    }
+    if (e == hipSuccess) {
+      int last = L;
+      void *eargs[] = {&c->sa, &phi, &last};
+      e = add(c->fn_end, c->W_ed, c->lds_ed, eargs);
+    }
+  }
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(c, OCI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess)
+    return fail(c, OCI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  c->step_graphs.push_back({L, G, phi, exec});
+  *out = exec;
+  return OCI_OK;
+}
+
+static int launch_end(oci_ctx *c, double *phi_dev, int last) {
+  void *args[] = {&c->sa, &phi_dev, &last};
   OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
                             c->stream));
   return OCI_OK;
 }
 
-// Queue steps first .. n_steps-1 without waiting: step start, the first
-// batch of `batch` iteration launches (a replayed graph), end of step (which
-// decides the batch's last iterate when no launch decided earlier).
-static int enqueue_steps(oci_ctx *c, int first, int n_steps, int batch, double *phi_dev) {
-  int rc = build_graph(c, false, batch);
-  if (rc) return rc;
-  for (int k = first; k < n_steps; ++k) {
-    int parity = c->parity ^ ((k - first) & 1);
-    void *bargs[] = {&c->sa, &parity};
-    OCI_CK(c, hipLaunchKernel(c->fn_begin, dim3(c->grid), dim3(64 * c->W_pv), bargs, c->lds_pv,
-                              c->stream));
-    const bool lone = first + 1 == n_steps;
-    if (lone) OCI_CK(c, hipEventRecord(c->evC, c->stream));
-    OCI_CK(c, hipGraphLaunch(c->oci_graph[batch], c->stream));
-    if (lone) OCI_CK(c, hipEventRecord(c->evD, c->stream));
-    rc = launch_end(c, k, phi_dev, batch);
+// Queue steps first .. first+count-1 (whole-step graphs of `batch` iteration
+// launches), then their records' copy to the host, between two events.
+static int enqueue_window(oci_ctx *c, int first, int count, int batch, double *phi_dev,
+                          hipEvent_t ev_start, hipEvent_t ev_end) {
+  OCI_CK(c, hipEventRecord(ev_start, c->stream));
+  int left = count;
+  while (left > 0) {
+    const int G = left >= kWindow ? kWindow : 1;
+    hipGraphExec_t exec;
+    int rc = step_graph(c, batch, G, phi_dev, &exec);
     if (rc) return rc;
+    OCI_CK(c, hipGraphLaunch(exec, c->stream));
+    left -= G;
   }
+  OCI_CK(c, hipMemcpyAsync(c->h_rec + first, c->d_rec + first, count * sizeof(StepRecord),
+                           hipMemcpyDeviceToHost, c->stream));
+  OCI_CK(c, hipEventRecord(ev_end, c->stream));
   return OCI_OK;
 }
 
 static void complete_step(oci_ctx *c, int accepted) {
-  c->last_oci_iters = accepted;
   c->parity ^= 1;
   c->steps += 1;
   c->have_flux = true;
 }
 
-// Every step is queued at once; a step not decided within its first batch
-// stalls the queue on the device, is resumed here with further launches, and
-// the rest is queued again.  phi_dev may be null.
+// Resume step k after its queued launches left it undecided: further
+// iteration launches (1, 1, 2, 4, ... at a time) each followed by the end of
+// step, until the end decides.  `launched` = iteration launches so far.
+static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_launches,
+                       float *ms) {
+  OCI_CK(c, hipEventRecord(c->ev0, c->stream));
+  int extra = 0, launches = launched;
+  for (;;) {
+    int rc = clear_stall(c);
+    if (rc) return rc;
+    ++extra;
+    const int count = std::min(extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2)),
+                               std::max(c->max_iters - launched, 1));
+    rc = launch_batch(c, false, launched, count);
+    if (rc) return rc;
+    launched += count;
+    launches += count;
+    rc = launch_end(c, phi_dev, launched);
+    if (rc) return rc;
+    rc = read_ctl(c);
+    if (rc) return rc;
+    if (!c->h_ctl->stalled || c->h_ctl->fin_status == kNonFinite) break;
+    if (launched > c->max_iters + 1)
+      return fail(c, OCI_EDEVICE, "the step control block did not reach a decision");
+  }
+  OCI_CK(c, hipEventRecord(c->ev1, c->stream));
+  OCI_CK(c, hipEventSynchronize(c->ev1));
+  hipEventElapsedTime(ms, c->ev0, c->ev1);
+  *total_launches = launches;
+  return OCI_OK;
+}
+
+// Steps 0 .. n_steps-1 of a solve are queued in windows of kWindow steps, two
+// windows in flight, each step with the iteration count of the latest
+// completed window as its launch count.  A step not decided within its
+// launches stalls the queue on the device (the rest of the queue becomes
+// no-ops); the host drains the stream, resumes that step and queues again
+// from the next.  A step with no previous step to go by is queued alone.
+// phi_dev may be null.
 static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info *infos) {
   int rc = grow_records(c, n_steps);
   if (rc) return rc;
-  c->sa.rec = c->d_rec;
+  // open the solve: step counter 0, psi buffer of step 0
+  c->h_ctl->cur = 0;
+  c->h_ctl->psi_base = c->parity;
+  static_assert(offsetof(StepCtl, psi_base) == offsetof(StepCtl, cur) + sizeof(int32_t),
+                "cur and psi_base are copied together");
+  OCI_CK(c, hipMemcpyAsync(&c->d_ctl->cur, &c->h_ctl->cur, 2 * sizeof(int32_t),
+                           hipMemcpyHostToDevice, c->stream));
+  struct Win {
+    int first, count, batch, ev;
+  };
+  Win wins[2];
+  int nwin = 0, next_ev = 0;
   int worst = OCI_OK;
-  int k = 0;
+  int k = 0, q = 0;   // first step not complete, next step to queue
   while (k < n_steps) {
-    const int batch = std::min({std::max(c->last_oci_iters, 2), c->max_iters, kMaxBatch});
-    OCI_CK(c, hipEventRecord(c->evA, c->stream));
-    rc = enqueue_steps(c, k, n_steps, batch, phi_dev);
-    if (rc) break;
-    OCI_CK(c, hipEventRecord(c->evB, c->stream));
-    OCI_CK(c, hipMemcpyAsync(c->h_rec + k, c->d_rec + k, (n_steps - k) * sizeof(StepRecord),
-                             hipMemcpyDeviceToHost, c->stream));
-    rc = read_ctl(c);
-    if (rc) break;
-    float ms = 0.0f, lone_ms = 0.0f;
-    hipEventElapsedTime(&ms, c->evA, c->evB);
-    if (k + 1 == n_steps) hipEventElapsedTime(&lone_ms, c->evC, c->evD);
-    // steps before the first undecided one are complete
-    int done = k;
-    while (done < n_steps && !c->h_ctl->stalled) ++done;
-    if (c->h_ctl->stalled) {
-      done = k;
-      while (done < n_steps && (c->h_rec[done].status == kConverged ||
-                                c->h_rec[done].status == kIterLimit))
-        ++done;
+    // a cold step (no previous count) goes alone; nothing is queued behind it
+    while (q < n_steps && nwin < 2 && c->batch_hint > 0) {
+      const int batch = std::min({c->batch_hint, c->max_iters, kMaxBatch});
+      const int count = std::min(kWindow, n_steps - q);
+      const int ev = next_ev;
+      next_ev ^= 1;
+      rc = enqueue_window(c, q, count, batch, phi_dev, c->evW[ev][0], c->evW[ev][1]);
+      if (rc) return rc;
+      wins[nwin++] = Win{q, count, batch, ev};
+      q += count;
     }
-    const int ndone = done - k;
-    for (int q = k; q < done; ++q) {
-      const StepRecord &r = c->h_rec[q];
+    if (nwin == 0) {
+      const int batch = std::min({kColdBatch, c->max_iters, kMaxBatch});
+      const int ev = next_ev;
+      next_ev ^= 1;
+      rc = enqueue_window(c, q, 1, batch, phi_dev, c->evW[ev][0], c->evW[ev][1]);
+      if (rc) return rc;
+      wins[nwin++] = Win{q, 1, batch, ev};
+      q += 1;
+    }
+    const Win w = wins[0];
+    OCI_CK(c, hipEventSynchronize(c->evW[w.ev][1]));
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, c->evW[w.ev][0], c->evW[w.ev][1]);
+    int done = w.first, hint = 0;
+    while (done < w.first + w.count && (c->h_rec[done].status == kConverged ||
+                                        c->h_rec[done].status == kIterLimit))
+      ++done;
+    const int ndone = done - w.first;
+    for (int s = w.first; s < done; ++s) {
+      const StepRecord &r = c->h_rec[s];
       const int status = r.status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
       if (status == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
-      // one queue for every step: its time split over the steps it completed;
-      // a lone step also reports the time of its batch of iteration launches
-      const double share = ms / std::max(ndone, 1);
-      fill_info(infos ? &infos[q] : nullptr, r.accepted, status, r.e_last, share,
-                k + 1 == n_steps ? lone_ms : share, k + 1 == n_steps ? batch : 0);
+      // the window's stream time split evenly over its steps
+      const double share = ms / w.count;
+      fill_info(infos ? &infos[s] : nullptr, r.accepted, status, r.e_last, share, share,
+                w.batch);
       complete_step(c, r.accepted);
+      hint = std::max(hint, r.accepted);
     }
     k = done;
-    if (k == n_steps) break;
-    // step k stalled: undecided after `batch` launches, or non-finite
-    if (c->h_ctl->fin_status == kNonFinite) {
-      rc = abandon_step(c, infos ? &infos[k] : nullptr, c->h_ctl->fin_accepted);
-      break;
+    if (ndone > 0) c->batch_hint = std::max(hint, 1);
+    if (ndone == w.count) {
+      wins[0] = wins[1];
+      --nwin;
+      continue;
     }
-    OCI_CK(c, hipEventRecord(c->ev0, c->stream));
-    int launched = batch, extra = 0, launches = batch;
-    for (;;) {
-      rc = clear_stall(c);
-      if (rc) break;
-      ++extra;
-      const int count = std::min(extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2)),
-                                 std::max(c->max_iters - launched, 1));
-      rc = launch_batch(c, false, launched, count);
-      if (rc) break;
-      launched += count;
-      launches += count;
-      rc = launch_end(c, k, phi_dev, launched);
-      if (rc) break;
-      rc = read_ctl(c);
-      if (rc) break;
-      if (!c->h_ctl->stalled) break;
-      if (c->h_ctl->fin_status == kNonFinite) break;
-      if (launched > c->max_iters + 1) {
-        rc = fail(c, OCI_EDEVICE, "the step control block did not reach a decision");
-        break;
-      }
-    }
-    if (rc) break;
-    if (c->h_ctl->fin_status == kNonFinite) {
-      rc = abandon_step(c, infos ? &infos[k] : nullptr, c->h_ctl->fin_accepted);
-      break;
-    }
-    OCI_CK(c, hipEventRecord(c->ev1, c->stream));
-    OCI_CK(c, hipEventSynchronize(c->ev1));
-    float ms2 = 0.0f;
-    hipEventElapsedTime(&ms2, c->ev0, c->ev1);
+    // step k stalled: undecided after w.batch launches, or non-finite.  The
+    // queue behind it is all no-ops; drain it and resume.
+    OCI_CK(c, hipStreamSynchronize(c->stream));
+    nwin = 0;
+    rc = read_ctl(c);
+    if (rc) return rc;
+    if (c->h_ctl->fin_status == kNonFinite)
+      return abandon_step(c, infos ? &infos[k] : nullptr, c->h_ctl->fin_accepted);
+    int launches = 0;
+    float rms = 0.0f;
+    rc = resume_step(c, w.batch, phi_dev, &launches, &rms);
+    if (rc) return rc;
+    if (c->h_ctl->fin_status == kNonFinite)
+      return abandon_step(c, infos ? &infos[k] : nullptr, c->h_ctl->fin_accepted);
     const StepCtl st = *c->h_ctl;
     const int status = st.fin_status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
     if (status == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
-    fill_info(infos ? &infos[k] : nullptr, st.fin_accepted, status, st.fin_e, ms2, ms2, launches);
+    fill_info(infos ? &infos[k] : nullptr, st.fin_accepted, status, st.fin_e,
+              ms / w.count + rms, rms, launches);
     complete_step(c, st.fin_accepted);
+    c->batch_hint = std::max(st.fin_accepted, 1);
     ++k;
+    q = k;
   }
-  c->sa.rec = nullptr;
-  return rc ? rc : worst;
+  return worst;
 }
 
 extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
@@ -919,7 +1058,8 @@ extern "C" void oci_destroy(oci_ctx *c) {
   if (c->h_ctl) hipHostFree(c->h_ctl);
   if (c->h_rec) hipHostFree(c->h_rec);
   if (c->d_rec) hipFree(c->d_rec);
-  for (hipEvent_t e : {c->ev0, c->ev1, c->evA, c->evB, c->evC, c->evD})
+  for (hipEvent_t e : {c->ev0, c->ev1, c->evA, c->evB, c->evW[0][0], c->evW[0][1], c->evW[1][0],
+                       c->evW[1][1]})
     if (e) hipEventDestroy(e);
   delete c;
 }

@@ -52,7 +52,12 @@ struct StepCtl {
   int32_t stalled;       // a queued step was not decided within its launches
   int32_t fin_accepted;  // the step's outcome, written by the end-of-step kernel
   int32_t fin_status;    //   (read by later launches and the host only, never by
-  int32_t pad;           //   the launch that writes it)
+                         //   the launch that writes it)
+  int32_t open;          // index of the open step within the current solve
+                         //   (written by the step start, read by the end)
+  int32_t cur;           // index of the next step to open (written by the host at
+                         //   the start of a solve and by the end of a decided step)
+  int32_t psi_base;      // psi buffer of step 0 of the current solve (host)
   double e_last;         // e of the accepted iterate (-1: undefined)
   double e_prev;         // source iteration: e of the previous iterate
   double fin_e;

@@ -36,6 +36,11 @@ struct StepArgs {
   StepRecord *rec;         // [steps] records of a queued solve
 };
 
+// Affine map of a sweep's (level k, level k+1/2) flux pair: x -> M x + v.
+struct Affine {
+  double m00, m01, m10, m11, v0, v1;
+};
+
 struct SiArgs {
   int N, J, bcl, bcr, max_iters, strict;
   double tol, a;
@@ -47,7 +52,9 @@ struct SiArgs {
   double *phi0, *phi1;      // [J][4]
   double *psi0, *psi1;      // [J][2N]
   double *contrib;          // [N/2][J][4] pair sums of w_m psi_m
-  double *lag;              // [N/2][2] right-edge outgoing flux of the mu > 0 angle
+  double *lag;              // [2][N/2][2] right-edge outgoing flux of the mu > 0 angle,
+                            //   by iterate parity (both edges reflecting)
+  Affine *segmap;           // [N/2][S][2] segment maps of the two sweep directions
   double *phi_res;          // [J][4]
   double *partial;          // [3][nparts] double2 residual records
   int nparts;
@@ -58,6 +65,7 @@ struct SiArgs {
 __global__ void k_build_system(const RegionDev *regions, const double *mu, const double *w,
                                int N, double a, double *ws_M, double *ws_X);
 __global__ void k_lu_solve(int N, double *ws_M, double *ws_X, int *bad);
+__global__ void k_lu_solve_lds(int N, int CB, int P, const double *ws_M, double *ws_X, int *bad);
 __global__ void k_select_rows(int N, const double *w, const double *ws_X, double *op_all);
 __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
                        int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
@@ -65,12 +73,13 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
 __global__ void k_pack_rows(int N, const double *op_all, int row0, int rows, int col0, int ncols,
                             double *dst_all, size_t dst_stride);
 // oci_step.hip (CH = operator k-steps fetched per batch: 4, 8 or 16)
-template <int CH> __global__ void k_step_begin(StepArgs a, int parity);
+template <int CH> __global__ void k_step_begin(StepArgs a);
 template <int CH> __global__ void k_oci_iterate(StepArgs a, int node, int cb);
-template <int CH> __global__ void k_step_end(StepArgs a, int step, double *phi_out, int last);
+template <int CH> __global__ void k_step_end(StepArgs a, double *phi_out, int last);
 // si.hip
 __global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,
                             double *ainv);
+__global__ void k_si_maps(SiArgs a, int node, int cb);
 __global__ void k_si_sweep(SiArgs a, int node, int cb);
 __global__ void k_si_reduce(SiArgs a, int node, int cb);
 __global__ void k_si_decide(SiArgs a, int node, int cb);

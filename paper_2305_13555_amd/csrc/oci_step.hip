@@ -397,21 +397,23 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Start of a step: gh for every tile, and the previous step's last iterate
-// moved into buffer 0 when it sits in buffer 1 (each work-group moves its own
-// rows).  The first thread of work-group 0 opens the step in the control
-// block without touching the fields the other work-groups read here.  Does
-// nothing while a queued solve is stalled.
+// Start of step `cur` of the current solve: gh for every tile, and the
+// previous step's last iterate moved into buffer 0 when it sits in buffer 1
+// (each work-group moves its own rows).  The first thread of work-group 0
+// opens the step in the control block without touching the fields the other
+// work-groups read here.  Does nothing while a queued solve is stalled.
 template <int CH>
-__global__ __launch_bounds__(256) void k_step_begin(StepArgs a, int parity) {
+__global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
   extern __shared__ double lds[];
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
+  const int parity = c.psi_base ^ (c.cur & 1);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     StepCtl *ct = a.ctl;
     ct->total0 = c.total0 + c.fin_accepted;
     ct->status = kRunning;
     ct->step_parity = parity;
+    ct->open = c.cur;
     ct->e_last = -1.0;
     ct->e_prev = -1.0;
   }
@@ -480,13 +482,14 @@ __global__ __launch_bounds__(256) void k_oci_iterate(StepArgs a, int node, int c
                       reinterpret_cast<double2 *>(a.partial) + (l % 3) * slot + ti);
 }
 
-// End of a step whose last launched iterate is `last`: decides that iterate
-// if no launch has decided the step yet, then computes psi_{k+1/2} and copies
-// the accepted scalar flux.  A step that is still undecided (or went
-// non-finite) stalls the queue instead: the host resumes it.  The step's
-// record is written either way.
+// End of the open step, whose last launched iterate is `last`: decides that
+// iterate if no launch has decided the step yet, then computes psi_{k+1/2}
+// and copies the accepted scalar flux (also to phi_out[open] when phi_out is
+// given).  A step that is still undecided (or went non-finite) stalls the
+// queue instead: the host resumes it.  The step's record is written either
+// way; a decided step advances the solve's step counter.
 template <int CH>
-__global__ __launch_bounds__(256) void k_step_end(StepArgs a, int step, double *phi_out, int last) {
+__global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int last) {
   extern __shared__ double lds[];
   __shared__ double red[2], red2[2], scratch[2 * kMaxWaves];
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
@@ -498,6 +501,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, int step, double *
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  const int step = c.open;
   int status = c.status, L = c.accepted;
   double e_last = c.e_last;
   if (status == kRunning) {
@@ -511,6 +515,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, int step, double *
                        &e_last);
     L = last;
   }
+  const bool decided = status != kRunning && status != kNonFinite;
   // the outcome goes to fields no work-group of this launch reads
   if (leader) {
     StepCtl *ct = a.ctl;
@@ -522,11 +527,10 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, int step, double *
       a.rec[step].status = status;
       a.rec[step].e_last = e_last;
     }
+    if (decided) ct->cur = step + 1;
+    else ct->stalled = 1;
   }
-  if (status == kRunning || status == kNonFinite) {
-    if (leader) a.ctl->stalled = 1;
-    return;
-  }
+  if (!decided) return;
   const int parity = c.step_parity;
   const double *src = ((L - 1) & 1) ? a.out1 : a.out0;   // read by iterate L
   const double *phi_acc = (L & 1) ? a.phi1 : a.phi0;     // written by iterate L
@@ -537,14 +541,14 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, int step, double *
                phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
 }
 
-template __global__ void k_step_begin<4>(StepArgs, int);
-template __global__ void k_step_begin<8>(StepArgs, int);
-template __global__ void k_step_begin<16>(StepArgs, int);
+template __global__ void k_step_begin<4>(StepArgs);
+template __global__ void k_step_begin<8>(StepArgs);
+template __global__ void k_step_begin<16>(StepArgs);
 template __global__ void k_oci_iterate<4>(StepArgs, int, int);
 template __global__ void k_oci_iterate<8>(StepArgs, int, int);
 template __global__ void k_oci_iterate<16>(StepArgs, int, int);
-template __global__ void k_step_end<4>(StepArgs, int, double *, int);
-template __global__ void k_step_end<8>(StepArgs, int, double *, int);
-template __global__ void k_step_end<16>(StepArgs, int, double *, int);
+template __global__ void k_step_end<4>(StepArgs, double *, int);
+template __global__ void k_step_end<8>(StepArgs, double *, int);
+template __global__ void k_step_end<16>(StepArgs, double *, int);
 
 }  // namespace ocik

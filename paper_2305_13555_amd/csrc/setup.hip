@@ -72,6 +72,91 @@ __global__ void k_build_system(const RegionDev *regions, const double *mu, const
   }
 }
 
+// The same LU with partial pivoting with the work in LDS, for 4N <= 128.
+// Work-group (r, b) holds all of M (n x n) and columns [b*CB, b*CB+CB) of X
+// side by side in LDS rows of pitch P (odd, so that column walks spread over
+// the banks); every work-group of a region factors M again (cheap next to a
+// round trip to memory per pivot) and carries its own block of X along, so
+// the right-hand sides are split over several CUs.  The pivot sequence and
+// every floating-point operation are those of k_lu_solve: first maximum of
+// |column| as pivot, multipliers M[i][k] / M[k][k], rank-one updates, then
+// back substitution row by row.  Singular pivots set *bad.
+__global__ __launch_bounds__(1024) void k_lu_solve_lds(int N, int CB, int P, const double *ws_M,
+                                                       double *ws_X, int *bad) {
+  extern __shared__ double A[];
+  __shared__ int s_piv;
+  __shared__ double s_pv;
+  const int r = blockIdx.x, j0 = blockIdx.y * CB;
+  const int n = 4 * N, nr = n + 1, Wd = n + CB;
+  const int ncol = min(CB, nr - j0);
+  const double *M = ws_M + (size_t)r * n * n;
+  double *X = ws_X + (size_t)r * n * nr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int idx = tid; idx < n * Wd; idx += blockDim.x) {
+    const int i = idx / Wd, j = idx - i * Wd;
+    double v = 0.0;
+    if (j < n) v = M[(size_t)i * n + j];
+    else if (j - n < ncol) v = X[(size_t)i * nr + j0 + (j - n)];
+    A[i * P + j] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + lane; i < n; i += 64) {
+        const double v = fabs(A[i * P + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(best, o, 64);
+        const int i2 = __shfl_xor(bi, o, 64);
+        if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+      }
+      if (lane == 0) {
+        s_piv = bi;
+        s_pv = best;
+      }
+    }
+    __syncthreads();
+    const int p = s_piv;
+    if (!(s_pv > 0.0)) {
+      if (tid == 0) *bad = 1;
+      return;   // uniform: every thread read the same s_pv
+    }
+    if (p != k) {
+      for (int j = k + tid; j < Wd; j += blockDim.x) {
+        const double tmp = A[k * P + j];
+        A[k * P + j] = A[p * P + j];
+        A[p * P + j] = tmp;
+      }
+      __syncthreads();
+    }
+    const double piv = A[k * P + k];
+    for (int i = k + 1 + tid; i < n; i += blockDim.x) A[i * P + k] = A[i * P + k] / piv;
+    __syncthreads();
+    for (int i = k + 1 + wave; i < n; i += nw) {
+      const double l = A[i * P + k];
+      for (int j = k + 1 + lane; j < Wd; j += 64) A[i * P + j] -= l * A[k * P + j];
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double piv = A[k * P + k];
+    for (int j = tid; j < CB; j += blockDim.x) A[k * P + n + j] /= piv;
+    __syncthreads();
+    for (int i = wave; i < k; i += nw) {
+      const double u = A[i * P + k];
+      for (int j = lane; j < CB; j += 64) A[i * P + n + j] -= u * A[k * P + n + j];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n * ncol; idx += blockDim.x) {
+    const int i = idx / ncol, j = idx - i * ncol;
+    X[(size_t)i * nr + j0 + j] = A[i * P + n + j];
+  }
+}
+
 // LU with partial pivoting of M, applied to X at the same time, then back
 // substitution: X <- M^{-1} X.  One work-group per region; singular pivots set
 // *bad.
@@ -109,7 +194,7 @@ __global__ __launch_bounds__(1024) void k_lu_solve(int N, double *ws_M, double *
     const int p = s_idx[0];
     const double pv = s_val[0];
     if (!(pv > 0.0)) {
-      if (tid == 0) atomicOr(bad, 1);
+      if (tid == 0) *bad = 1;
       return;   // uniform: every thread saw the same s_val[0]
     }
     if (p != k) {

@@ -2,14 +2,16 @@
 // the previous iteration, every angle is swept through the mesh and each cell
 // solves its 4x4 system A^+ x = b^+ (mu > 0) or A^- x = b^- (mu < 0).
 //
-// On the GPU a sweep is parallel over angles (one work-group per mirror pair
-// m, N-1-m) and over cells by a scan: with the lagged scalar flux fixed, the
-// map from the flux entering a cell (levels k and k+1/2) to the flux leaving
-// it is affine, x_out = T x_in + t, with T = |mu| (A^{-1})[out rows, in rows]
-// and t = (A^{-1} b)[out rows].  Each thread composes the maps of a chunk of
-// consecutive cells, a work-group scan of the chunk maps gives every chunk
-// its entering flux, and each thread re-sweeps its chunk.  The result is the
-// sequential sweep up to rounding.
+// On the GPU a sweep is parallel over angles (mirror pairs m, N-1-m) and over
+// cells by a two-level scan: with the lagged scalar flux fixed, the map from
+// the flux entering a cell (levels k and k+1/2) to the flux leaving it is
+// affine, x_out = T x_in + t, with T = |mu| (A^{-1})[out rows, in rows] and
+// t = (A^{-1} b)[out rows].  The cells are split into S segments, one
+// work-group per (pair, segment).  A first launch composes every segment's
+// map (each thread a chunk of cells, a work-group scan of the chunk maps); a
+// second gives every segment its entering flux from the maps upstream of it,
+// and every thread re-sweeps its chunk from the entering flux the scan gives
+// it.  The result is the sequential sweep up to rounding.
 //
 // Reflecting edges: the pair is swept in the order that makes the reflection
 // exact within the iteration (mu < 0 first when the left edge reflects, mu > 0
@@ -54,9 +56,6 @@ __global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, i
     for (int j = 0; j < 4; ++j) o[i * 4 + j] = A[i][4 + j];
 }
 
-struct Affine {   // x -> M x + v
-  double m00, m01, m10, m11, v0, v1;
-};
 
 // (f o g)(x) = f(g(x))
 __device__ __forceinline__ Affine compose(const Affine &f, const Affine &g) {
@@ -99,9 +98,98 @@ __device__ __forceinline__ CellSolve cell_solve(const SiArgs &a, const double *p
   return s;
 }
 
-// Iteration l = cb + node: sweep every angle pair with the scalar flux of
-// iterate l-1.
-__global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a, int node, int cbase) {
+__device__ __forceinline__ void apply(const Affine &f, double &x0, double &x1) {
+  const double y0 = f.m00 * x0 + f.m01 * x1 + f.v0;
+  const double y1 = f.m10 * x0 + f.m11 * x1 + f.v1;
+  x0 = y0;
+  x1 = y1;
+}
+
+// Cells of segment s of S: an even split of [0, J).
+__device__ __forceinline__ int seg_edge(int s, int J, int S) {
+  return (int)(((long long)J * s) / S);
+}
+
+// The two sweeps of angle pair p, in their order: pass 0 is mu < 0 unless
+// only the right edge reflects.
+__device__ __forceinline__ bool pass_positive(const SiArgs &a, int pass) {
+  const bool pos_first = (a.bcr == kBcReflect && a.bcl != kBcReflect);
+  return pos_first ? (pass == 0) : (pass == 1);
+}
+
+// This thread's chunk [jb, je) of segment [lo, hi), in cells.
+__device__ __forceinline__ void chunk_of(int lo, int hi, int *jb, int *je) {
+  const int n = hi - lo, C = (n + blockDim.x - 1) / blockDim.x;
+  *jb = lo + min(n, (int)threadIdx.x * C);
+  *je = lo + min(n, ((int)threadIdx.x + 1) * C);
+}
+
+// Map from the flux entering this thread's chunk to the flux leaving it, in
+// sweep order.
+__device__ Affine chunk_map(const SiArgs &a, const double *phi_old, const double *psi_prev,
+                            int jb, int je, int m, bool pos) {
+  const double amu = fabs(a.mu[m]);
+  const int o0 = pos ? 1 : 0, o1 = pos ? 3 : 2;
+  Affine f = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+  for (int q = 0; q < je - jb; ++q) {
+    const int j = pos ? jb + q : je - 1 - q;
+    const CellSolve cs = cell_solve(a, phi_old, psi_prev, j, m, pos, amu);
+    const Affine g = {cs.c0[o0], cs.c1[o0], cs.c0[o1], cs.c1[o1], cs.y[o0], cs.y[o1]};
+    f = compose(g, f);
+  }
+  return f;
+}
+
+// Inclusive scan of the threads' chunk maps in sweep order (spos = position
+// of this thread in that order); s_map[nt-1] is then the whole segment's map.
+__device__ void scan_maps(Affine f, int spos, Affine *s_map) {
+  const int nt = blockDim.x;
+  s_map[spos] = f;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const Affine mine = s_map[spos];
+    Affine earlier = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    if (spos >= off) earlier = s_map[spos - off];
+    __syncthreads();
+    if (spos >= off) s_map[spos] = compose(mine, earlier);
+    __syncthreads();
+  }
+}
+
+constexpr int kSiThreads = 256;
+
+// Sweep, first half: for iterate l = cb + node, the map of every segment of
+// every angle pair, in both sweep directions (they depend only on the
+// previous iterate's scalar flux and on psi_{k-1/2}).  Grid (N/2, S).
+__global__ __launch_bounds__(kSiThreads) void k_si_maps(SiArgs a, int node, int cbase) {
+  const StepCtl c = *a.ctl;
+  if (c.stalled || c.status != kRunning) return;
+  const int l = cbase + node;
+  const double *phi_old = ((l - 1) & 1) ? a.phi1 : a.phi0;
+  const double *psi_prev = c.step_parity ? a.psi1 : a.psi0;
+  const int p = blockIdx.x, s = blockIdx.y, S = gridDim.y;
+  const int lo = seg_edge(s, a.J, S), hi = seg_edge(s + 1, a.J, S);
+  int jb, je;
+  chunk_of(lo, hi, &jb, &je);
+  __shared__ Affine s_map[kSiThreads];
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool pos = pass_positive(a, pass);
+    const int m = pos ? a.N - 1 - p : p;
+    const Affine f = chunk_map(a, phi_old, psi_prev, jb, je, m, pos);
+    const int spos = pos ? threadIdx.x : blockDim.x - 1 - threadIdx.x;
+    scan_maps(f, spos, s_map);
+    if (threadIdx.x == 0) a.segmap[((size_t)p * S + s) * 2 + pass] = s_map[blockDim.x - 1];
+    __syncthreads();
+  }
+}
+
+// Sweep, second half: every segment gets its entering flux from the maps of
+// the segments upstream of it (applied to the flux entering the domain; the
+// second direction starts from the first one's leaving flux where the edge
+// reflects), then every thread re-sweeps its chunk from the flux the scan of
+// the chunk maps gives it, writing the pair's contribution to the scalar
+// flux, psi_{k+1/2} and the outgoing fluxes.  Grid (N/2, S).
+__global__ __launch_bounds__(kSiThreads) void k_si_sweep(SiArgs a, int node, int cbase) {
   const StepCtl c = *a.ctl;
   if (c.stalled || c.status != kRunning) return;
   const int l = cbase + node;
@@ -112,70 +200,73 @@ __global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a, int node, int cbase
   const double *ghosts = a.out0;   // ghost rows are identical in both buffers
   const double *psi_prev = parity ? a.psi1 : a.psi0;
   double *psi_next = parity ? a.psi0 : a.psi1;
+  const double *lag_in = a.lag + (size_t)par * a.N;
+  double *lag_out = a.lag + (size_t)(l & 1) * a.N;
   const int N = a.N, J = a.J, K = 2 * N;
-  const int p = blockIdx.x;
-  const int m_neg = p, m_pos = N - 1 - p;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int C = (J + nt - 1) / nt;
-  const int jb = min(J, tid * C), je = min(J, (tid + 1) * C);
-
-  __shared__ Affine s_map[1024];
-  __shared__ double s_exit[2];
-
-  const bool pos_first = (a.bcr == kBcReflect && a.bcl != kBcReflect);
-  double *contrib = a.contrib + (size_t)p * J * 4;
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool pos = pos_first ? (pass == 0) : (pass == 1);
-    const int m = pos ? m_pos : m_neg;
-    const double mu = a.mu[m], amu = fabs(mu), wm = a.w[m];
-    // flux entering the domain for this direction
-    double xb0 = 0.0, xb1 = 0.0;
-    if (pos) {
-      if (pass == 1 && a.bcl == kBcReflect) { xb0 = s_exit[0]; xb1 = s_exit[1]; }
-      else if (a.bcl == kBcIncident) { xb0 = ghosts[2 * m]; xb1 = ghosts[2 * m + 1]; }
-    } else {
-      if (a.bcr == kBcReflect) {
-        if (pass == 1) { xb0 = s_exit[0]; xb1 = s_exit[1]; }
-        else { xb0 = a.lag[2 * p]; xb1 = a.lag[2 * p + 1]; }   // both edges reflect
-      } else if (a.bcr == kBcIncident) {
-        const double *gr = ghosts + (size_t)(J + 1) * K;
-        xb0 = gr[2 * m];
-        xb1 = gr[2 * m + 1];
+  const int p = blockIdx.x, s = blockIdx.y, S = gridDim.y;
+  const int lo = seg_edge(s, J, S), hi = seg_edge(s + 1, J, S);
+  int jb, je;
+  chunk_of(lo, hi, &jb, &je);
+  const Affine *maps = a.segmap + (size_t)p * S * 2;
+  __shared__ Affine s_map[kSiThreads];
+  __shared__ double s_in[2][2];
+  if (threadIdx.x == 0) {
+    // flux entering the domain and this segment, both passes
+    double exit0 = 0.0, exit1 = 0.0;   // pass 0's leaving flux at its far edge
+    for (int pass = 0; pass < 2; ++pass) {
+      const bool pos = pass_positive(a, pass);
+      const int m = pos ? N - 1 - p : p;
+      double x0 = 0.0, x1 = 0.0;
+      if (pos) {
+        if (pass == 1 && a.bcl == kBcReflect) { x0 = exit0; x1 = exit1; }
+        else if (a.bcl == kBcIncident) { x0 = ghosts[2 * m]; x1 = ghosts[2 * m + 1]; }
+      } else {
+        if (a.bcr == kBcReflect) {
+          if (pass == 1) { x0 = exit0; x1 = exit1; }
+          else { x0 = lag_in[2 * p]; x1 = lag_in[2 * p + 1]; }   // both edges reflect
+        } else if (a.bcr == kBcIncident) {
+          const double *gr = ghosts + (size_t)(J + 1) * K;
+          x0 = gr[2 * m];
+          x1 = gr[2 * m + 1];
+        }
+      }
+      // segments in sweep order: ascending for mu > 0, descending for mu < 0
+      for (int q = 0; q < S; ++q) {
+        const int t = pos ? q : S - 1 - q;
+        if (t == s) {
+          s_in[pass][0] = x0;
+          s_in[pass][1] = x1;
+        }
+        apply(maps[t * 2 + pass], x0, x1);
+      }
+      if (pass == 0) {
+        exit0 = x0;
+        exit1 = x1;
+      } else if (a.bcl == kBcReflect && a.bcr == kBcReflect && s == 0) {
+        // mu > 0 was swept second: its leaving flux at x = X is the next
+        // iteration's entering flux of the mirror angle
+        lag_out[2 * p] = x0;
+        lag_out[2 * p + 1] = x1;
       }
     }
+  }
+  __syncthreads();
+  double *contrib = a.contrib + (size_t)p * J * 4;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool pos = pass_positive(a, pass);
+    const int m = pos ? N - 1 - p : p;
+    const double amu = fabs(a.mu[m]), wm = a.w[m];
     const int o0 = pos ? 1 : 0, o1 = pos ? 3 : 2;
-    // phase 1: compose this thread's chunk in sweep order
-    Affine f = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    const Affine f = chunk_map(a, phi_old, psi_prev, jb, je, m, pos);
+    const int spos = pos ? threadIdx.x : blockDim.x - 1 - threadIdx.x;
+    scan_maps(f, spos, s_map);
+    double x0 = s_in[pass][0], x1 = s_in[pass][1];
+    if (spos > 0) apply(s_map[spos - 1], x0, x1);
     for (int q = 0; q < je - jb; ++q) {
       const int j = pos ? jb + q : je - 1 - q;
-      const CellSolve s = cell_solve(a, phi_old, psi_prev, j, m, pos, amu);
-      const Affine g = {s.c0[o0], s.c1[o0], s.c0[o1], s.c1[o1], s.y[o0], s.y[o1]};
-      f = compose(g, f);
-    }
-    // phase 2: inclusive scan over threads in sweep order
-    const int spos = pos ? tid : nt - 1 - tid;
-    s_map[spos] = f;
-    __syncthreads();
-    for (int off = 1; off < nt; off <<= 1) {
-      Affine mine = s_map[spos];
-      Affine earlier = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
-      if (spos >= off) earlier = s_map[spos - off];
-      __syncthreads();
-      if (spos >= off) s_map[spos] = compose(mine, earlier);
-      __syncthreads();
-    }
-    double x0 = xb0, x1 = xb1;
-    if (spos > 0) {
-      const Affine e = s_map[spos - 1];
-      x0 = e.m00 * xb0 + e.m01 * xb1 + e.v0;
-      x1 = e.m10 * xb0 + e.m11 * xb1 + e.v1;
-    }
-    // phase 3: re-sweep the chunk from its entering flux
-    for (int q = 0; q < je - jb; ++q) {
-      const int j = pos ? jb + q : je - 1 - q;
-      const CellSolve s = cell_solve(a, phi_old, psi_prev, j, m, pos, amu);
+      const CellSolve cs = cell_solve(a, phi_old, psi_prev, j, m, pos, amu);
       double x[4];
-      for (int i = 0; i < 4; ++i) x[i] = s.y[i] + s.c0[i] * x0 + s.c1[i] * x1;
+      for (int i = 0; i < 4; ++i) x[i] = cs.y[i] + cs.c0[i] * x0 + cs.c1[i] * x1;
       double *cj = contrib + (size_t)j * 4;
       if (pass == 0) {
         for (int i = 0; i < 4; ++i) cj[i] = wm * x[i];
@@ -190,16 +281,6 @@ __global__ __launch_bounds__(1024) void k_si_sweep(SiArgs a, int node, int cbase
       x1 = x[o1];
     }
     __syncthreads();
-    // the thread owning the last cell of the sweep publishes the leaving flux
-    const bool owns_last = je > jb && (pos ? je == J : jb == 0);
-    if (owns_last) { s_exit[0] = x0; s_exit[1] = x1; }
-    __syncthreads();
-  }
-  if (a.bcl == kBcReflect && a.bcr == kBcReflect && tid == 0) {
-    // mu > 0 was swept second: its leaving flux at x = X is next iteration's
-    // entering flux of the mirror angle
-    a.lag[2 * p] = s_exit[0];
-    a.lag[2 * p + 1] = s_exit[1];
   }
 }
 
@@ -288,7 +369,8 @@ __global__ void k_si_begin(SiArgs a, int parity) {
 }
 
 // End of a decided step: the accepted scalar flux to the result buffer (the
-// last sweep already wrote psi_{k+1/2}).
+// last sweep already wrote psi_{k+1/2}) and the accepted iterate's lagged
+// right-edge flux into lag buffer 0.
 __global__ void k_si_end(SiArgs a) {
   const StepCtl c = *a.ctl;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -298,6 +380,8 @@ __global__ void k_si_end(SiArgs a) {
     ct->fin_e = c.e_last;
   }
   if (c.stalled || c.status == kRunning || c.status == kNonFinite) return;
+  if ((c.accepted & 1) && blockIdx.x == 0)   // the accepted iterate's lag into buffer 0
+    for (int i = threadIdx.x; i < a.N; i += blockDim.x) a.lag[i] = a.lag[a.N + i];
   const double *src = (c.accepted & 1) ? a.phi1 : a.phi0;
   const int n = a.J * 4;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
