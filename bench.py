@@ -78,6 +78,29 @@ def copy_calibration(torch, mib):
     return n * 8
 
 
+KERNEL_SOURCES = ("oci_step.hip", "oci_device.h", "oci_kernels.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_oci_iterate_c2_hbm_traffic.txt")
+
+
+def measured_traffic():
+    """HBM bytes per k_oci_iterate launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(line.split(":", 1) for line in open(TRAFFIC_PROFILE)
+                      if line.startswith(("traffic_bytes_per_launch:", "kernel_sources_sha256:")))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_13555_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != fields.get("kernel_sources_sha256", "").strip():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(prob, n_steps, gpu_phi):
     """The oracle's OCI (per-region LU + multi-right-hand-side solves) timed on
     the host for the first n_steps of the workload."""
@@ -218,7 +241,7 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "bytes_per_launch": bytes_launch,
             "us_per_launch": per_launch_s * 1e6,
             "measured": "(median step time at 32 launches - at 16) / 16, 5 steps each",
