@@ -53,8 +53,8 @@ def build(verbose=False, jobs=8):
         if p.returncode != 0:
             failed.append(src)
             sys.stderr.write(text + "\n")
-        elif verbose and text.strip():
-            print(text)
+        elif text.strip():
+            sys.stderr.write(text + "\n")   # warnings are shown, not hidden
     if failed:
         raise RuntimeError("hipcc failed on: " + ", ".join(failed))
     tmp = LIB + ".tmp"

@@ -55,10 +55,10 @@ struct oci_ctx {
   int *d_cell_region = nullptr;
   double *d_op = nullptr;
   double *d_fi = nullptr, *d_fp = nullptr, *d_cp = nullptr, *d_fe = nullptr, *d_ce = nullptr;
-  double *d_hphi = nullptr;
   size_t fi_stride = 0, fp_stride = 0, cp_stride = 0, fe_stride = 0, ce_stride = 0;
-  size_t hphi_stride = 0;
-  double *d_gh = nullptr, *d_out[2] = {nullptr, nullptr}, *d_phi[2] = {nullptr, nullptr};
+  double *d_gh = nullptr, *d_outb = nullptr, *d_phib = nullptr, *d_dec = nullptr;
+  int nbuf = 2;                              // iterate buffers (>= 3 for OCI)
+  size_t out_stride = 0, phi_stride = 0;
   double *d_psi[2] = {nullptr, nullptr}, *d_phi_res = nullptr, *d_partial = nullptr;
   double *d_ainv = nullptr, *d_contrib = nullptr, *d_lag = nullptr, *d_si_partial = nullptr;
   Affine *d_segmap = nullptr;
@@ -80,6 +80,7 @@ struct oci_ctx {
   };
   std::vector<StepGraph> step_graphs;        // G whole steps of L iteration launches
   int batch_hint = 0;                        // iteration launches per queued step
+  int window = 1;                            // steps of the next queued window
   bool quad_override = false;
   double *ws_M = nullptr, *ws_X = nullptr;   // setup workspace, kept for oci_refactor
   int *d_bad = nullptr;
@@ -171,29 +172,29 @@ static int validate(const oci_problem *p, std::string *why) {
 
 static int upload_ghosts(oci_ctx *c) {
   const int K = 2 * c->N;
-  for (int b = 0; b < 2; ++b) {
-    OCI_CK(c, hipMemcpyAsync(c->d_out[b], c->ghost_left.data(), K * sizeof(double),
+  for (int b = 0; b < c->nbuf; ++b) {
+    double *o = c->d_outb + (size_t)b * c->out_stride;
+    OCI_CK(c, hipMemcpyAsync(o, c->ghost_left.data(), K * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+    OCI_CK(c, hipMemcpyAsync(o + (size_t)(c->J + 1) * K, c->ghost_right.data(), K * sizeof(double),
                              hipMemcpyHostToDevice, c->stream));
-    OCI_CK(c, hipMemcpyAsync(c->d_out[b] + (size_t)(c->J + 1) * K, c->ghost_right.data(),
-                             K * sizeof(double), hipMemcpyHostToDevice, c->stream));
   }
   return OCI_OK;
 }
 
-// Cold iterate: zero outgoing fluxes (boundary rows kept), zero scalar flux,
-// zero lagged reflection, control block cleared (iteration parity 0).
+// Cold iterate: zero outgoing fluxes (cell rows; the boundary rows of every
+// iterate buffer are set once at setup and never written) and scalar flux in
+// buffer 0, zero lagged reflection, control block cleared (accepted iterate
+// in buffer 0).
 static int reset_iterate(oci_ctx *c) {
   const int K = 2 * c->N;
-  for (int b = 0; b < 2; ++b) {
-    OCI_CK(c, hipMemsetAsync(c->d_out[b], 0, (size_t)(c->J + 2) * K * sizeof(double), c->stream));
-    OCI_CK(c, hipMemsetAsync(c->d_phi[b], 0, (size_t)c->J * 4 * sizeof(double), c->stream));
-  }
+  OCI_CK(c, hipMemsetAsync(c->d_outb + K, 0, (size_t)c->J * K * sizeof(double), c->stream));
+  OCI_CK(c, hipMemsetAsync(c->d_phib, 0, (size_t)c->J * 4 * sizeof(double), c->stream));
   OCI_CK(c, hipMemsetAsync(c->d_lag, 0, (size_t)2 * c->N * sizeof(double), c->stream));
   OCI_CK(c, hipMemsetAsync(c->d_ctl, 0, sizeof(StepCtl), c->stream));
-  int rc = upload_ghosts(c);
-  if (rc) return rc;
   c->last_si_iters = 0;
   c->batch_hint = 0;
+  c->window = 1;
   return OCI_OK;
 }
 
@@ -228,11 +229,11 @@ static int build_si_graph(oci_ctx *c, int count) {
     if (e == hipSuccess) e = add((void *)k_si_decide, dim3(1), dim3(256), 0, args);
   }
   if (e != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return fail(c, OCI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
   }
   e = hipGraphInstantiate(slot, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     *slot = nullptr;
     return fail(c, OCI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
@@ -267,9 +268,6 @@ static int build_operators(oci_ctx *c) {
   // end-of-step operator E: rows [2N+4, 4N+4), columns [0, 4N)
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N + 4, K, 0,
                      2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride);
-  // scalar-flux rows of G for the dot products of the iteration
-  hipLaunchKernelGGL(k_pack_rows, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N, 4, 0, K,
-                     c->d_hphi, c->hphi_stride);
   hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
                      c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
   OCI_CK(c, hipGetLastError());
@@ -281,14 +279,14 @@ static int build_operators(oci_ctx *c) {
 }
 
 static void drop_step_graphs(oci_ctx *c) {
-  for (auto &g : c->step_graphs) hipGraphExecDestroy(g.exec);
+  for (auto &g : c->step_graphs) (void)hipGraphExecDestroy(g.exec);
   c->step_graphs.clear();
 }
 
 static void drop_graphs(oci_ctx *c) {
   drop_step_graphs(c);
   for (int i = 0; i <= kMaxBatch; ++i) {
-    if (c->si_graph[i]) hipGraphExecDestroy(c->si_graph[i]);
+    if (c->si_graph[i]) (void)hipGraphExecDestroy(c->si_graph[i]);
     c->si_graph[i] = nullptr;
   }
 }
@@ -345,11 +343,11 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   // SIMD fills first and fewer work-groups stay resident than registers
   // allow.  The iteration splits its scalar-flux dot products over W threads,
   // so there W is a power of two.
-  c->W_it = c->Mto >= 4 ? 4 : (c->Mto >= 2 ? 2 : 1);
+  c->W_it = std::min(c->Mto, 4);
   c->W_pv = std::min(c->Mt, 4);
   c->W_ed = std::min(c->Met, 4);
   const int P = K + 2;
-  c->lds_it = (size_t)(kTileCells + 2 + 4) * P * sizeof(double);
+  c->lds_it = (size_t)(kTileCells + 2) * P * sizeof(double);
   c->lds_pv = (size_t)kTileCells * P * sizeof(double);
   c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
   c->si_blocks = (J * 4 + 255) / 256;
@@ -386,7 +384,6 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->cp_stride = (size_t)c->Mt * 16;
   c->fe_stride = (size_t)c->Met * (2 * K / 4) * 64;
   c->ce_stride = (size_t)c->Met * 16;
-  c->hphi_stride = (size_t)4 * K;
   OCI_TRY(dalloc(c, &c->d_mu, N));
   OCI_TRY(dalloc(c, &c->d_w, N));
   OCI_TRY(dalloc(c, &c->d_regions, R));
@@ -398,15 +395,22 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_cp, (size_t)R * c->cp_stride));
   OCI_TRY(dalloc(c, &c->d_fe, (size_t)R * c->fe_stride));
   OCI_TRY(dalloc(c, &c->d_ce, (size_t)R * c->ce_stride));
-  OCI_TRY(dalloc(c, &c->d_hphi, (size_t)R * c->hphi_stride));
   OCI_TRY(dalloc(c, &c->d_gh, (size_t)J * c->Mt * 16));
-  for (int b = 0; b < 2; ++b) {
-    OCI_TRY(dalloc(c, &c->d_out[b], (size_t)(J + 2) * K));
-    OCI_TRY(dalloc(c, &c->d_phi[b], (size_t)J * 4));
-    OCI_TRY(dalloc(c, &c->d_psi[b], (size_t)J * K));
+  // one buffer per iterate of a queued batch (at most kMaxBatch launches),
+  // within a memory budget
+  c->out_stride = (size_t)(J + 2) * K;
+  c->phi_stride = (size_t)J * 4;
+  {
+    const size_t per = (c->out_stride + c->phi_stride) * sizeof(double);
+    const size_t budget = (size_t)8 << 30;
+    c->nbuf = (int)std::max<size_t>(3, std::min<size_t>(kMaxBatch + 1, budget / per));
   }
+  OCI_TRY(dalloc(c, &c->d_outb, (size_t)c->nbuf * c->out_stride));
+  OCI_TRY(dalloc(c, &c->d_phib, (size_t)c->nbuf * c->phi_stride));
+  OCI_TRY(dalloc(c, &c->d_dec, (size_t)c->nbuf));
+  for (int b = 0; b < 2; ++b) OCI_TRY(dalloc(c, &c->d_psi[b], (size_t)J * K));
   OCI_TRY(dalloc(c, &c->d_phi_res, (size_t)J * 4));
-  OCI_TRY(dalloc(c, &c->d_partial, (size_t)3 * c->ntiles * 4));
+  OCI_TRY(dalloc(c, &c->d_partial, (size_t)c->nbuf * c->ntiles * 2));
   OCI_TRY(dalloc(c, &c->d_ainv, (size_t)R * N * 16));
   OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(N / 2) * J * 4));
   OCI_TRY(dalloc(c, &c->d_lag, (size_t)2 * N));
@@ -446,8 +450,10 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
       c->lu_cb = cb;
       c->lu_pitch = pitch;
       c->lds_lu = (size_t)n * pitch * sizeof(double);
-      hipFuncSetAttribute((const void *)k_lu_solve_lds,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_lu);
+      if (hipFuncSetAttribute((const void *)k_lu_solve_lds,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)c->lds_lu) != hipSuccess)
+        c->lu_cb = 0;   // fall back to the LU in global memory
     }
   }
   OCI_TRY(dalloc(c, &c->ws_M, (size_t)R * n * n));
@@ -456,6 +462,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(build_operators(c));
 
   // ---- state ----
+  OCI_TRY(upload_ghosts(c));
   OCI_TRY(reset_iterate(c));
   if (p->psi0) {
     OCI_TRY(up(c->d_psi[0], p->psi0, (size_t)J * K * sizeof(double)));
@@ -481,8 +488,6 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.tol = c->tol;
   s.frag_it = c->d_fi;
   s.frag_it_stride = c->fi_stride;
-  s.hphi = c->d_hphi;
-  s.hphi_stride = c->hphi_stride;
   s.frag_pv = c->d_fp;
   s.frag_pv_stride = c->fp_stride;
   s.c_pv = c->d_cp;
@@ -492,10 +497,23 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.c_ed = c->d_ce;
   s.c_ed_stride = c->ce_stride;
   s.gh = c->d_gh;
-  s.out0 = c->d_out[0];
-  s.out1 = c->d_out[1];
-  s.phi0 = c->d_phi[0];
-  s.phi1 = c->d_phi[1];
+  s.nbuf = c->nbuf;
+  s.outb = c->d_outb;
+  s.out_stride = c->out_stride;
+  s.phib = c->d_phib;
+  s.phi_stride = c->phi_stride;
+  s.dec = c->d_dec;
+  s.nreg_arg = R <= kArgRegions ? R : 0;
+  if (s.nreg_arg) {
+    int t0 = 0;
+    for (int r = 0; r < R; ++r) {
+      s.reg_j0[r] = regions[r].j0;
+      s.reg_t0[r] = t0;
+      t0 += (regions[r].nc + kTileCells - 1) / kTileCells;
+    }
+    s.reg_j0[R] = J;
+    s.reg_t0[R] = t0;
+  }
   s.psi0 = c->d_psi[0];
   s.psi1 = c->d_psi[1];
   s.phi_res = c->d_phi_res;
@@ -516,10 +534,14 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   q.mu = c->d_mu;
   q.w = c->d_w;
   q.ainv = c->d_ainv;
-  q.out0 = c->d_out[0];
-  q.out1 = c->d_out[1];
-  q.phi0 = c->d_phi[0];
-  q.phi1 = c->d_phi[1];
+  q.out0 = c->d_outb;
+  q.out1 = c->d_outb + c->out_stride;
+  q.phi0 = c->d_phib;
+  q.phi1 = c->d_phib + c->phi_stride;
+  q.outb = c->d_outb;
+  q.out_stride = c->out_stride;
+  q.phib = c->d_phib;
+  q.phi_stride = c->phi_stride;
   q.psi0 = c->d_psi[0];
   q.psi1 = c->d_psi[1];
   q.contrib = c->d_contrib;
@@ -546,12 +568,12 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
     c->fn_end = (void *)k_step_end<4>;
   }
   // kernels with more than 64 KiB of dynamic LDS must say so
-  hipFuncSetAttribute((const void *)c->fn_iter, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)c->lds_it);
-  hipFuncSetAttribute((const void *)c->fn_begin, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)c->lds_pv);
-  hipFuncSetAttribute((const void *)c->fn_end, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)c->lds_ed);
+  OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it));
+  OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_begin,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_pv));
+  OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_end,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_ed));
   OCI_CK(c, hipStreamSynchronize(c->stream));
 #undef OCI_TRY
   *out = c;
@@ -647,7 +669,7 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
     rc = read_ctl(c);
     if (rc) return rc;
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, c->evA, c->evB);
+    (void)hipEventElapsedTime(&ms, c->evA, c->evB);
     iter_ms += ms;
     launches += count;
     if (c->h_ctl->status != kRunning) break;
@@ -663,7 +685,7 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
   OCI_CK(c, hipEventRecord(c->ev1, c->stream));
   OCI_CK(c, hipEventSynchronize(c->ev1));
   float ms = 0.0f;
-  hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
   c->last_si_iters = st.accepted;
   c->parity ^= 1;
   c->steps += 1;
@@ -684,8 +706,8 @@ constexpr int kColdBatch = 8;  // launches of a step with no previous step to go
 static int grow_records(oci_ctx *c, int n) {
   if (n <= c->rec_cap) return OCI_OK;
   drop_step_graphs(c);
-  if (c->d_rec) hipFree(c->d_rec);
-  if (c->h_rec) hipHostFree(c->h_rec);
+  if (c->d_rec) (void)hipFree(c->d_rec);
+  if (c->h_rec) (void)hipHostFree(c->h_rec);
   c->d_rec = nullptr;
   c->h_rec = nullptr;
   c->rec_cap = 0;
@@ -734,18 +756,18 @@ static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out
       e = add(c->fn_iter, c->W_it, c->lds_it, args);
     }
     if (e == hipSuccess) {
-      int last = L;
-      void *eargs[] = {&c->sa, &phi, &last};
+      int first = 1, last = L;
+      void *eargs[] = {&c->sa, &phi, &first, &last};
       e = add(c->fn_end, c->W_ed, c->lds_ed, eargs);
     }
   }
   if (e != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return fail(c, OCI_EDEVICE, std::string("hipGraphAddKernelNode: ") + hipGetErrorString(e));
   }
   hipGraphExec_t exec = nullptr;
   e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (e != hipSuccess)
     return fail(c, OCI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   c->step_graphs.push_back({L, G, phi, exec});
@@ -753,8 +775,8 @@ static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out
   return OCI_OK;
 }
 
-static int launch_end(oci_ctx *c, double *phi_dev, int last) {
-  void *args[] = {&c->sa, &phi_dev, &last};
+static int launch_end(oci_ctx *c, double *phi_dev, int first, int last) {
+  void *args[] = {&c->sa, &phi_dev, &first, &last};
   OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
                             c->stream));
   return OCI_OK;
@@ -767,7 +789,8 @@ static int enqueue_window(oci_ctx *c, int first, int count, int batch, double *p
   OCI_CK(c, hipEventRecord(ev_start, c->stream));
   int left = count;
   while (left > 0) {
-    const int G = left >= kWindow ? kWindow : 1;
+    int G = kWindow;   // whole steps per graph: 8, 4, 2 or 1
+    while (G > left) G >>= 1;
     hipGraphExec_t exec;
     int rc = step_graph(c, batch, G, phi_dev, &exec);
     if (rc) return rc;
@@ -797,13 +820,13 @@ static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_lau
     int rc = clear_stall(c);
     if (rc) return rc;
     ++extra;
-    const int count = std::min(extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2)),
-                               std::max(c->max_iters - launched, 1));
+    const int count = std::min({extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2)),
+                                std::max(c->max_iters - launched, 1), c->nbuf - 1});
     rc = launch_batch(c, false, launched, count);
     if (rc) return rc;
     launched += count;
     launches += count;
-    rc = launch_end(c, phi_dev, launched);
+    rc = launch_end(c, phi_dev, launched - count + 1, launched);
     if (rc) return rc;
     rc = read_ctl(c);
     if (rc) return rc;
@@ -813,7 +836,7 @@ static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_lau
   }
   OCI_CK(c, hipEventRecord(c->ev1, c->stream));
   OCI_CK(c, hipEventSynchronize(c->ev1));
-  hipEventElapsedTime(ms, c->ev0, c->ev1);
+  (void)hipEventElapsedTime(ms, c->ev0, c->ev1);
   *total_launches = launches;
   return OCI_OK;
 }
@@ -845,8 +868,11 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
   while (k < n_steps) {
     // a cold step (no previous count) goes alone; nothing is queued behind it
     while (q < n_steps && nwin < 2 && c->batch_hint > 0) {
-      const int batch = std::min({c->batch_hint, c->max_iters, kMaxBatch});
-      const int count = std::min(kWindow, n_steps - q);
+      const int batch = std::min({c->batch_hint, c->max_iters, c->nbuf - 1});
+      // windows grow 1, 2, 4, .. kWindow steps, so that a count learnt from
+      // few steps is not applied to many
+      const int count = std::min(c->window, n_steps - q);
+      c->window = std::min(kWindow, 2 * c->window);
       const int ev = next_ev;
       next_ev ^= 1;
       rc = enqueue_window(c, q, count, batch, phi_dev, c->evW[ev][0], c->evW[ev][1]);
@@ -855,7 +881,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       q += count;
     }
     if (nwin == 0) {
-      const int batch = std::min({kColdBatch, c->max_iters, kMaxBatch});
+      const int batch = std::min({kColdBatch, c->max_iters, c->nbuf - 1});
       const int ev = next_ev;
       next_ev ^= 1;
       rc = enqueue_window(c, q, 1, batch, phi_dev, c->evW[ev][0], c->evW[ev][1]);
@@ -866,7 +892,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
     const Win w = wins[0];
     OCI_CK(c, hipEventSynchronize(c->evW[w.ev][1]));
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, c->evW[w.ev][0], c->evW[w.ev][1]);
+    (void)hipEventElapsedTime(&ms, c->evW[w.ev][0], c->evW[w.ev][1]);
     int done = w.first, hint = 0;
     while (done < w.first + w.count && (c->h_rec[done].status == kConverged ||
                                         c->h_rec[done].status == kIterLimit))
@@ -911,6 +937,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
               ms / w.count + rms, rms, launches);
     complete_step(c, st.fin_accepted);
     c->batch_hint = std::max(st.fin_accepted, 1);
+    c->window = 1;
     ++k;
     q = k;
   }
@@ -943,11 +970,15 @@ extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
   c->tol = p->tol;
   c->max_iters = p->max_iters;
   c->strict = (p->flags & OCI_FLAG_STRICT) ? 1 : 0;
+  const StepArgs sa0 = c->sa;
+  const SiArgs si0 = c->si;
   c->sa.tol = c->si.tol = c->tol;
   c->sa.max_iters = c->si.max_iters = c->max_iters;
   c->sa.strict = c->si.strict = c->strict;
   c->si.a = c->a;
-  drop_graphs(c);   // the argument blocks baked into the graphs changed
+  // graphs hold copies of the argument blocks: rebuild them only if those changed
+  if (std::memcmp(&sa0, &c->sa, sizeof sa0) != 0 || std::memcmp(&si0, &c->si, sizeof si0) != 0)
+    drop_graphs(c);
   return build_operators(c);
 }
 
@@ -1052,15 +1083,15 @@ extern "C" int oci_get_operator(oci_ctx *c, int32_t region, double *op) {
 
 extern "C" void oci_destroy(oci_ctx *c) {
   if (!c) return;
-  hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   drop_graphs(c);
-  for (void *q : c->allocs) hipFree(q);
-  if (c->h_ctl) hipHostFree(c->h_ctl);
-  if (c->h_rec) hipHostFree(c->h_rec);
-  if (c->d_rec) hipFree(c->d_rec);
+  for (void *q : c->allocs) (void)hipFree(q);
+  if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+  if (c->h_rec) (void)hipHostFree(c->h_rec);
+  if (c->d_rec) (void)hipFree(c->d_rec);
   for (hipEvent_t e : {c->ev0, c->ev1, c->evA, c->evB, c->evW[0][0], c->evW[0][1], c->evW[1][0],
                        c->evW[1][1]})
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 

@@ -1,7 +1,8 @@
 // Device-side data structures and helpers shared by the OCI / SI kernels.
 //
 // Layouts (all FP64, row-major):
-//   out  [J+2][2N]  outgoing angular flux of every cell, ping-pong pair;
+//   out  [J+2][2N]  outgoing angular flux of every cell, one buffer per
+//                   iterate of a step (modulo the buffer count);
 //                   row g = cell + 1, rows 0 and J+1 are ghost cells that
 //                   hold the boundary values (vacuum: 0; incident: the given
 //                   flux; reflecting: filled in LDS from the boundary cell).
@@ -13,7 +14,8 @@
 //   inc_j (never stored): entries 0..N-1 from out_{j+1}, N..2N-1 from
 //                   out_{j-1}: exactly the incident fluxes of c^- and c^+.
 //   psi_prev / psi_next [J][2N]  time-edge state, entry 2m+s (s = L, R).
-//   phi  [J][4]     scalar flux (k,L), (k,R), (k+1/2,L), (k+1/2,R), ping-pong.
+//   phi  [J][4]     scalar flux (k,L), (k,R), (k+1/2,L), (k+1/2,R), one buffer
+//                   per iterate like out.
 //   gh   [J][Mt*16] per-step constant part of [out; phi] (see oci_step.hip).
 //   operators: per region, packed in MFMA A-fragment order (see pack_frag).
 #pragma once
@@ -58,15 +60,18 @@ struct StepCtl {
   int32_t cur;           // index of the next step to open (written by the host at
                          //   the start of a solve and by the end of a decided step)
   int32_t psi_base;      // psi buffer of step 0 of the current solve (host)
+  int32_t fin_buf;       // iterate buffer holding the last decided step's accepted
+                         //   iterate (written with fin_accepted)
+  int32_t pad;
   double e_last;         // e of the accepted iterate (-1: undefined)
   double e_prev;         // source iteration: e of the previous iterate
   double fin_e;
 };
 
 // Iterate l of a step (1-based) reads the outgoing fluxes and scalar flux of
-// iterate l-1 from buffer (l-1)&1 and writes buffer l&1; the step-start
-// kernel moves the previous step's last iterate into buffer 0 when it sits
-// in buffer 1, so buffer choice never depends on device data.
+// iterate l-1 from buffer (l-1) % nbuf and writes buffer l % nbuf; the
+// step-start kernel moves the previous step's accepted iterate into buffer 0,
+// so no iteration launch needs device data to pick its buffers.
 
 // Per-step record of a queued solve.
 struct StepRecord {
@@ -130,6 +135,25 @@ __device__ inline int stop_rule(int l, double dphi, double phimax, int nonfinite
   }
   if (done == kRunning && l >= max_iters) done = kIterLimit;
   *e_out = e;
+  return done;
+}
+
+// The same rule from e_l itself (NaN when iterate l is not finite; the value
+// is ignored for l < first_defined).
+__device__ inline int stop_rule_e(int l, double e, double e_before, int first_defined, double tol,
+                                  int strict, int max_iters) {
+  if (e != e) return kNonFinite;
+  int done = kRunning;
+  if (l >= first_defined && e <= tol) {
+    if (!strict) {
+      done = kConverged;
+    } else if (e_before >= 0.0) {
+      double rho = e_before == 0.0 ? 0.0 : e / e_before;
+      rho = fmin(fmax(rho, 0.0), 0.9999);
+      if (e * rho / (1.0 - rho) <= tol) done = kConverged;
+    }
+  }
+  if (done == kRunning && l >= max_iters) done = kIterLimit;
   return done;
 }
 

@@ -6,18 +6,23 @@
 
 namespace ocik {
 
+// Regions whose tile layout travels in the kernel arguments (no table load
+// on the launch's critical path); problems with more regions read TileDev.
+constexpr int kArgRegions = 32;
+
 struct StepArgs {
   const TileDev *tiles;
   int ntiles;
+  int nreg_arg;            // R if R <= kArgRegions (then reg_j0 / reg_t0 are valid), else 0
+  int reg_j0[kArgRegions + 1];   // first cell of region r; reg_j0[R] = J
+  int reg_t0[kArgRegions + 1];   // first tile of region r; reg_t0[R] = ntiles
   int N, J, Mt, Met;
-  int Mto;                 // row tiles of the outgoing rows alone (the GEMM of an iteration)
+  int Mto;                 // row tiles holding the 2N outgoing rows
   int bcl, bcr;
   int max_iters, strict;
   double tol;
   const double *frag_it;   // G (iteration), per region stride frag_it_stride
   size_t frag_it_stride;
-  const double *hphi;      // H: the scalar-flux rows of G, [R][4][2N] row-major
-  size_t hphi_stride;
   const double *frag_pv;   // P (per-step constant)
   size_t frag_pv_stride;
   const double *c_pv;      // p
@@ -27,11 +32,15 @@ struct StepArgs {
   const double *c_ed;      // e
   size_t c_ed_stride;
   double *gh;              // [J][Mt*16]
-  double *out0, *out1;     // [J+2][2N]
-  double *phi0, *phi1;     // [J][4]
+  int nbuf;                // iterate buffers: iterate l lives in buffer l % nbuf
+  double *outb;            // [nbuf][J+2][2N]
+  size_t out_stride;
+  double *phib;            // [nbuf][J][4]
+  size_t phi_stride;
   double *psi0, *psi1;     // [J][2N]
   double *phi_res;         // [J][4]
-  double *partial;         // [3][ntiles] double2 residual records, slot = iterate % 3
+  double *partial;         // [nbuf][ntiles] double2 residual records of iterate l in slot l % nbuf
+  double *dec;             // [nbuf] e of iterate l in slot l % nbuf (NaN: not finite)
   StepCtl *ctl;
   StepRecord *rec;         // [steps] records of a queued solve
 };
@@ -48,8 +57,12 @@ struct SiArgs {
   const int *cell_region;   // [J]
   const double *mu, *w;
   const double *ainv;       // [R][N][16]
-  double *out0, *out1;      // [J+2][2N], ghost rows hold incident values
+  double *out0, *out1;      // [J+2][2N] iterate buffers 0 and 1, ghost rows hold incident values
   double *phi0, *phi1;      // [J][4]
+  double *outb;             // all iterate buffers (as StepArgs): the step start moves the
+  size_t out_stride;        //   previous step's last iterate from buffer fin_buf to 0
+  double *phib;
+  size_t phi_stride;
   double *psi0, *psi1;      // [J][2N]
   double *contrib;          // [N/2][J][4] pair sums of w_m psi_m
   double *lag;              // [2][N/2][2] right-edge outgoing flux of the mu > 0 angle,
@@ -70,12 +83,10 @@ __global__ void k_select_rows(int N, const double *w, const double *ws_X, double
 __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
                        int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
                        size_t cvec_stride);
-__global__ void k_pack_rows(int N, const double *op_all, int row0, int rows, int col0, int ncols,
-                            double *dst_all, size_t dst_stride);
 // oci_step.hip (CH = operator k-steps fetched per batch: 4, 8 or 16)
 template <int CH> __global__ void k_step_begin(StepArgs a);
 template <int CH> __global__ void k_oci_iterate(StepArgs a, int node, int cb);
-template <int CH> __global__ void k_step_end(StepArgs a, double *phi_out, int last);
+template <int CH> __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last);
 // si.hip
 __global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,
                             double *ainv);

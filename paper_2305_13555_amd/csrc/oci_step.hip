@@ -202,6 +202,37 @@ __device__ __forceinline__ d4 mma_rowtile(const double *Fr, int KS, bool first_l
 // Tile routines
 // ---------------------------------------------------------------------------
 
+// Tile ti: from the region table in the kernel arguments when the problem has
+// few regions (tiles are numbered region by region, 16 cells each, the last
+// tile of a region ragged), else from the tile table.
+__device__ __forceinline__ TileDev tile_desc(const StepArgs &a, int ti) {
+  if (a.nreg_arg == 0) return a.tiles[ti];
+  int r = 0;
+#pragma unroll
+  for (int q = 1; q < kArgRegions; ++q) r += (q < a.nreg_arg && a.reg_t0[q] <= ti) ? 1 : 0;
+  int j0 = 0, j1 = 0, t0 = 0;
+#pragma unroll
+  for (int q = 0; q < kArgRegions; ++q)
+    if (q == r) {
+      j0 = a.reg_j0[q];
+      j1 = a.reg_j0[q + 1];
+      t0 = a.reg_t0[q];
+    }
+  TileDev t;
+  t.region = r;
+  t.c0 = j0 + (ti - t0) * kTileCells;
+  t.nc = min(kTileCells, j1 - t.c0);
+  t.pad = 0;
+  return t;
+}
+
+__device__ __forceinline__ double *out_buf(const StepArgs &a, int l) {
+  return a.outb + (size_t)(l % a.nbuf) * a.out_stride;
+}
+__device__ __forceinline__ double *phi_buf(const StepArgs &a, int l) {
+  return a.phib + (size_t)(l % a.nbuf) * a.phi_stride;
+}
+
 // gh rows of a tile: gh_j = P_r psi_{k-1/2,j} + p_r.
 template <int CH>
 __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const double *psi_prev,
@@ -230,28 +261,38 @@ __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const dou
   }
 }
 
-// One OCI iteration of a tile, in two phases so that the caller can take
-// the stopping decision between them.  iterate_prefetch issues every load
-// that does not depend on LDS: the first operator chunk of the wave's first
-// row tile and that row tile's constants, the scalar-flux constants and old
-// values, and the neighbour rows and scalar-flux operator rows (staged into
-// LDS by iterate_compute).  iterate_compute runs the GEMM for the 2N outgoing
-// rows on MFMA, the 4 scalar-flux rows as dot products split over W threads
-// per (cell, component), and writes the tile's residual record.
+// One OCI iteration of a tile, in two phases: iterate_prefetch issues every
+// load that does not need LDS (the first operator chunks of the wave's
+// outgoing row tile and of its share of the scalar-flux rows, the tile's
+// step constants, the old scalar flux, and the neighbour rows, staged into
+// LDS by iterate_compute).  iterate_compute runs the GEMM on MFMA: each wave
+// one row tile of the 2N outgoing rows, and the 4 scalar-flux rows either
+// inside the last outgoing row tile (2N not a multiple of 16) or as one more
+// row tile whose k-steps are split over the waves and summed in LDS in a
+// fixed order.  Wave 0 then forms the 64 (cell, component) scalar fluxes and
+// the tile's residual record.
+constexpr int kPhiPre = 4;   // scalar-flux operator fragments prefetched per wave
+
 template <int CH>
 struct IterPrefetch {
-  double f0[CH], gv[4];
-  double hv, po;   // scalar-flux constant and previous value of this thread's (cell, component)
+  double f0[CH], fp[kPhiPre], gv[4];
+  double hv, po;   // scalar-flux constant and previous value of this lane's (cell, component)
   CopyRegs cr;
 };
 
-template <int CH>
-__device__ __forceinline__ void iterate_blocks(RowBlock (&blk)[2], const StepArgs &a,
-                                               const TileDev &t, const double *src, double *lds) {
+// The scalar-flux rows 2N .. 2N+3 of G: their row tile, the first of them
+// within it, and whether the tile holds outgoing rows too.
+__device__ __forceinline__ void phi_tile(const StepArgs &a, int *rt, int *off, bool *shared) {
   const int K = 2 * a.N;
-  blk[0] = neighbour_block(lds, src, t, K);
-  blk[1] = RowBlock{a.hphi + (size_t)t.region * a.hphi_stride, lds + (kTileCells + 2) * (K + 2), 4,
-                    4};
+  *rt = K / 16;
+  *off = K % 16;
+  *shared = *off != 0;
+}
+
+// k-steps of the scalar-flux row tile handled by wave w when it is split.
+__device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *ke) {
+  *kb = (w * KS) / W;
+  *ke = ((w + 1) * KS) / W;
 }
 
 template <int CH>
@@ -264,38 +305,43 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
   const int ghp = a.Mt * 16;
   const int row0 = wave * 16 + col;
   if (wave < a.Mto) load_frags<CH>(pf.f0, F + (size_t)wave * KS * 64, 0, KS);
+  int prt, poff, kb, ke;
+  bool pshared;
+  phi_tile(a, &prt, &poff, &pshared);
+  phi_ksplit(KS, W, wave, &kb, &ke);
+  if (!pshared) load_frags<kPhiPre>(pf.fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int cl = kq + 4 * i;
     const bool ok = wave < a.Mto && row0 < K && cl < t.nc;
     pf.gv[i] = ok ? a.gh[(size_t)(t.c0 + cl) * ghp + row0] : 0.0;
   }
-  const int pair = threadIdx.x / W, cl = pair >> 2, comp = pair & 3;
-  const bool pok = cl < t.nc;
+  const int cl = lane >> 2, comp = lane & 3;
+  const bool pok = wave == 0 && cl < t.nc;
   pf.hv = pok ? a.gh[(size_t)(t.c0 + cl) * ghp + K + comp] : 0.0;
   pf.po = pok ? phi_old[(size_t)(t.c0 + cl) * 4 + comp] : 0.0;
-  RowBlock blk[2];
-  iterate_blocks<CH>(blk, a, t, src, lds);
-  issue_copy(pf.cr, blk, 2, K);
+  const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
+  issue_copy(pf.cr, blk, 1, K);
 }
 
-// Writes the tile's residual record (rec); ends with a barrier.
+// Computes the tile's iterate; wave 0 writes its residual record (rec).
+// Returns early (no stores) when the queue is stalled.
 template <int CH>
 __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
-                                       double *phi_new, double *lds, double *scratch,
-                                       double2 *rec) {
+                                       double *phi_new, double *lds, double *phis, double2 *rec,
+                                       bool stalled) {
   const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
   const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
   const int ghp = a.Mt * 16;
   {
-    RowBlock blk[2];
-    iterate_blocks<CH>(blk, a, t, src, lds);
-    finish_copy(pf.cr, blk, 2, K, P);
+    const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
+    finish_copy(pf.cr, blk, 1, K, P);
   }
   __syncthreads();
+  if (stalled) return;
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
   // incident flux of cell c, entry k: k < N from the right neighbour
   // (LDS row c+2), k >= N from the left neighbour (LDS row c)
@@ -303,32 +349,56 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
     const int k = ks * 4 + kq;
     return lds[(k < N ? col + 2 : col) * P + k];
   };
+  int prt, poff, kb, ke;
+  bool pshared;
+  phi_tile(a, &prt, &poff, &pshared);
+  phi_ksplit(KS, W, wave, &kb, &ke);
+  // this wave's partial scalar flux, [cell][component] in LDS (zero if none)
+  double *my_phis = phis + wave * 64;
+  if (lane < 64) my_phis[lane] = 0.0;
   for (int rt = wave; rt < a.Mto; rt += W) {
     const d4 acc = mma_rowtile<CH>(F + (size_t)rt * KS * 64, KS, rt == wave, pf.f0, aload);
-    const int row = rt * 16 + col;      // outgoing row of this lane
-    if (row < K) {
-      for (int i = 0; i < 4; ++i) {
-        const int cl = kq + 4 * i;      // cell of element i
-        if (cl >= t.nc) continue;
+    const int row = rt * 16 + col;      // operator row of this lane
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cl = kq + 4 * i;      // cell of element i
+      if (cl >= t.nc) continue;
+      if (row < K) {
         const int cell = t.c0 + cl;
         const double g = rt == wave ? pf.gv[i] : a.gh[(size_t)cell * ghp + row];
         dst[(size_t)(cell + 1) * K + row] = acc[i] + g;
+      } else if (pshared && rt == prt && row < K + 4) {
+        my_phis[cl * 4 + (row - K)] = acc[i];
       }
     }
   }
-  // scalar flux: W threads per (cell, component), each a K/W slice of the
-  // dot product with the scalar-flux operator row (LDS rows 18..21)
-  const int q = threadIdx.x % W, pair = threadIdx.x / W, cl = pair >> 2, comp = pair & 3;
-  const int T = K / W;
-  const double *hrow = lds + (kTileCells + 2 + comp) * P;
-  double s = 0.0;
-  for (int kk = 0; kk < T; ++kk) {
-    const int k = q * T + kk;
-    s += hrow[k] * lds[(k < N ? cl + 2 : cl) * P + k];
+  if (!pshared) {
+    // k-steps kb .. ke-1 of the scalar-flux row tile; lanes col < 4 hold its rows
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const double *Fp = F + (size_t)prt * KS * 64;
+#pragma unroll
+    for (int i = 0; i < kPhiPre; ++i)
+      if (kb + i < ke) acc = mfma16x16x4(aload(kb + i), pf.fp[i], acc);
+    for (int base = kb + kPhiPre; base < ke; base += CH) {
+      double f[CH];
+      load_frags<CH>(f, Fp, base, ke);
+#pragma unroll
+      for (int i = 0; i < CH; ++i)
+        if (base + i < ke) acc = mfma16x16x4(aload(base + i), f[i], acc);
+    }
+    if (col < 4) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) my_phis[(kq + 4 * i) * 4 + col] = acc[i];
+    }
   }
-  for (int o = 1; o < W; o <<= 1) s += __shfl_xor(s, o, kWave);
+  __syncthreads();
+  if (wave != 0) return;
+  // scalar flux of (cell, component) = lane: the waves' partials in order
+  const int cl = lane >> 2, comp = lane & 3;
+  double s = 0.0;
+  for (int w = 0; w < W; ++w) s += phis[w * 64 + lane];
   double dphi = 0.0, fphi = 0.0;
-  if (q == 0 && cl < t.nc) {
+  if (cl < t.nc) {
     const double v = s + pf.hv;
     phi_new[(size_t)(t.c0 + cl) * 4 + comp] = v;
     dphi = isfinite(v) ? fabs(v - pf.po) : __builtin_nan("");
@@ -336,18 +406,7 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   }
   dphi = wave_nan_max(dphi);
   fphi = wave_max(fphi);
-  if (lane == 0) {
-    scratch[wave * 2 + 0] = dphi;
-    scratch[wave * 2 + 1] = fphi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < W; ++w) {
-      dphi = nan_max(dphi, scratch[w * 2 + 0]);
-      fphi = fmax(fphi, scratch[w * 2 + 1]);
-    }
-    *rec = make_double2(dphi, fphi);
-  }
+  if (lane == 0) *rec = make_double2(dphi, fphi);
 }
 
 // End of step for a tile: psi_{k+1/2} from the incident fluxes the accepted
@@ -398,7 +457,7 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
 // ---------------------------------------------------------------------------
 
 // Start of step `cur` of the current solve: gh for every tile, and the
-// previous step's last iterate moved into buffer 0 when it sits in buffer 1
+// previous step's accepted iterate moved from buffer fin_buf into buffer 0
 // (each work-group moves its own rows).  The first thread of work-group 0
 // opens the step in the control block without touching the fields the other
 // work-groups read here.  Does nothing while a queued solve is stalled.
@@ -419,126 +478,116 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
   }
   const int ti = tile_of_block(blockIdx.x, a.ntiles);
   if (ti < 0) return;
-  const TileDev t = a.tiles[ti];
-  if (c.fin_accepted & 1) {
+  const TileDev t = tile_desc(a, ti);
+  if (c.fin_buf != 0) {
     const int K = 2 * a.N;
-    const double2 *so = reinterpret_cast<const double2 *>(a.out1 + (size_t)(t.c0 + 1) * K);
-    double2 *dout = reinterpret_cast<double2 *>(a.out0 + (size_t)(t.c0 + 1) * K);
+    const double2 *so = reinterpret_cast<const double2 *>(
+        a.outb + (size_t)c.fin_buf * a.out_stride + (size_t)(t.c0 + 1) * K);
+    double2 *dout = reinterpret_cast<double2 *>(a.outb + (size_t)(t.c0 + 1) * K);
     for (int i = threadIdx.x; i < t.nc * K / 2; i += blockDim.x) dout[i] = so[i];
+    const double *sp = a.phib + (size_t)c.fin_buf * a.phi_stride;
     for (int i = threadIdx.x; i < t.nc * 4; i += blockDim.x)
-      a.phi0[(size_t)t.c0 * 4 + i] = a.phi1[(size_t)t.c0 * 4 + i];
+      a.phib[(size_t)t.c0 * 4 + i] = sp[(size_t)t.c0 * 4 + i];
   }
   tile_begin<CH>(a, t, parity ? a.psi1 : a.psi0, lds);
 }
 
-// Iterate l = cb + node of the current step.  Every work-group first decides
-// iterate l-1 from the residual records of the previous launch (and, for the
-// strict rule, iterate l-2); a decided step ends the launch for everyone.
-// All loads that do not depend on the decision are issued before it.
+// Iterate l = cb + node of the open step: always computed (the step's
+// decision is taken by the end-of-step kernel from the residual of every
+// iterate).  Work-group 0 also reduces the residual records iterate l-1 left
+// and stores its e in dec, off the other work-groups' path.  Nothing is
+// stored while a queued solve is stalled.
 template <int CH>
-__global__ __launch_bounds__(256) void k_oci_iterate(StepArgs a, int node, int cb) {
+__global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb) {
   extern __shared__ double lds[];
-  __shared__ double red[2], red2[2], scratch[2 * kMaxWaves];
+  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64];
   const int l = cb + node;
-  const int par = (l - 1) & 1;
-  const double *src = par ? a.out1 : a.out0;
-  double *dst = par ? a.out0 : a.out1;
-  const double *phi_old = par ? a.phi1 : a.phi0;
-  double *phi_new = par ? a.phi0 : a.phi1;
-  const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
-  const size_t slot = (size_t)a.ntiles;
-  RecRegs r1, r2;
-  if (l >= 2) rec_issue(r1, recs + ((l - 1) % 3) * slot, a.ntiles);
-  const bool strict_prev = a.strict && l - 2 >= 2;
-  if (strict_prev) rec_issue(r2, recs + ((l - 2) % 3) * slot, a.ntiles);
+  const double *src = out_buf(a, l - 1);
+  double *dst = out_buf(a, l);
+  const double *phi_old = phi_buf(a, l - 1);
+  double *phi_new = phi_buf(a, l);
   const int ti = tile_of_block(blockIdx.x, a.ntiles);
   if (ti < 0) return;
-  const TileDev t = a.tiles[ti];
-  const StepCtl c = *a.ctl;
-  IterPrefetch<CH> pf;
-  iterate_prefetch<CH>(pf, a, t, src, phi_old, lds);
-  if (c.stalled || c.status != kRunning) return;
-  if (l >= 2) {
-    rec_finish(r1, recs + ((l - 1) % 3) * slot, a.ntiles, red, scratch);
-    double e_before = -1.0;
-    if (strict_prev) {
-      rec_finish(r2, recs + ((l - 2) % 3) * slot, a.ntiles, red2, scratch);
-      e_before = rel_change(red2[0], red2[1]);
-    }
-    double e;
-    const int dn = stop_rule(l - 1, red[0], red[1], 0, e_before, 2, a.tol, a.strict, a.max_iters,
-                             &e);
-    if (dn != kRunning) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        StepCtl *ct = a.ctl;
-        ct->accepted = l - 1;
-        ct->e_last = e;
-        ct->status = dn;
-      }
-      return;
-    }
-  }
-  iterate_compute<CH>(pf, a, t, src, dst, phi_new, lds, scratch,
-                      reinterpret_cast<double2 *>(a.partial) + (l % 3) * slot + ti);
-}
-
-// End of the open step, whose last launched iterate is `last`: decides that
-// iterate if no launch has decided the step yet, then computes psi_{k+1/2}
-// and copies the accepted scalar flux (also to phi_out[open] when phi_out is
-// given).  A step that is still undecided (or went non-finite) stalls the
-// queue instead: the host resumes it.  The step's record is written either
-// way; a decided step advances the solve's step counter.
-template <int CH>
-__global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int last) {
-  extern __shared__ double lds[];
-  __shared__ double red[2], red2[2], scratch[2 * kMaxWaves];
+  const bool reducer = blockIdx.x == 0 && l >= 2;
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   const size_t slot = (size_t)a.ntiles;
-  RecRegs r1, r2;
-  rec_issue(r1, recs + (last % 3) * slot, a.ntiles);
-  const bool strict_prev = a.strict && last - 1 >= 2;
-  if (strict_prev) rec_issue(r2, recs + ((last - 1) % 3) * slot, a.ntiles);
+  RecRegs r1;
+  if (reducer) rec_issue(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles);
+  const TileDev t = tile_desc(a, ti);
+  IterPrefetch<CH> pf;
+  iterate_prefetch<CH>(pf, a, t, src, phi_old, lds);
+  const int stalled = a.ctl->stalled;
+  if (reducer) {
+    rec_finish(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles, red, scratch);
+    if (threadIdx.x == 0 && !stalled) a.dec[(l - 1) % a.nbuf] = rel_change(red[0], red[1]);
+  }
+  iterate_compute<CH>(pf, a, t, src, dst, phi_new, lds, phis,
+                      reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
+                      stalled != 0);
+}
+
+// End of the open step after iterates first .. last of it were launched
+// (iterates before `first` were already found undecided): the first of them
+// the stopping rule accepts (or stops at) is the step's iterate L.  The e of
+// iterates before `last` come from dec, the e of `last` from its records.
+// Then psi_{k+1/2} from the incident fluxes iterate L was computed from and
+// psi_{k-1/2}, and the accepted scalar flux to phi_res (and phi_out[open]
+// when given).  A step still undecided (or not finite) stalls the queue
+// instead: the host resumes it.  The step's record is written either way; a
+// decided step advances the solve's step counter.
+template <int CH>
+__global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
+                                                  int last) {
+  extern __shared__ double lds[];
+  __shared__ double red[2], scratch[2 * kMaxWaves];
+  const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
+  const size_t slot = (size_t)a.ntiles;
+  RecRegs r1;
+  rec_issue(r1, recs + (last % a.nbuf) * slot, a.ntiles);
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
-  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  rec_finish(r1, recs + (last % a.nbuf) * slot, a.ntiles, red, scratch);
+  const double e_lastv = rel_change(red[0], red[1]);
   const int step = c.open;
-  int status = c.status, L = c.accepted;
-  double e_last = c.e_last;
-  if (status == kRunning) {
-    rec_finish(r1, recs + (last % 3) * slot, a.ntiles, red, scratch);
-    double e_before = -1.0;
-    if (strict_prev) {
-      rec_finish(r2, recs + ((last - 1) % 3) * slot, a.ntiles, red2, scratch);
-      e_before = rel_change(red2[0], red2[1]);
+  int status = kRunning, L = last;
+  double e_acc = -1.0;
+  double e_before = (a.strict && first - 1 >= 2) ? a.dec[(first - 1) % a.nbuf] : -1.0;
+  for (int l = first; l <= last; ++l) {
+    const double e = l == last ? e_lastv : a.dec[l % a.nbuf];
+    status = stop_rule_e(l, e, e_before, 2, a.tol, a.strict, a.max_iters);
+    if (status != kRunning) {
+      L = l;
+      e_acc = l >= 2 ? e : -1.0;
+      break;
     }
-    status = stop_rule(last, red[0], red[1], 0, e_before, 2, a.tol, a.strict, a.max_iters,
-                       &e_last);
-    L = last;
+    e_before = l >= 2 ? e : -1.0;
   }
   const bool decided = status != kRunning && status != kNonFinite;
   // the outcome goes to fields no work-group of this launch reads
-  if (leader) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     StepCtl *ct = a.ctl;
     ct->fin_accepted = L;
     ct->fin_status = status;
-    ct->fin_e = e_last;
+    ct->fin_e = e_acc;
     if (a.rec) {
       a.rec[step].accepted = L;
       a.rec[step].status = status;
-      a.rec[step].e_last = e_last;
+      a.rec[step].e_last = e_acc;
     }
-    if (decided) ct->cur = step + 1;
-    else ct->stalled = 1;
+    if (decided) {
+      ct->fin_buf = L % a.nbuf;
+      ct->cur = step + 1;
+    } else {
+      ct->stalled = 1;
+    }
   }
   if (!decided) return;
   const int parity = c.step_parity;
-  const double *src = ((L - 1) & 1) ? a.out1 : a.out0;   // read by iterate L
-  const double *phi_acc = (L & 1) ? a.phi1 : a.phi0;     // written by iterate L
   const int ti = tile_of_block(blockIdx.x, a.ntiles);
   if (ti < 0) return;
-  const TileDev t = a.tiles[ti];
-  tile_end<CH>(a, t, src, parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1, phi_acc,
-               phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
+  const TileDev t = tile_desc(a, ti);
+  tile_end<CH>(a, t, out_buf(a, L - 1), parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
+               phi_buf(a, L), phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
 }
 
 template __global__ void k_step_begin<4>(StepArgs);
@@ -547,8 +596,8 @@ template __global__ void k_step_begin<16>(StepArgs);
 template __global__ void k_oci_iterate<4>(StepArgs, int, int);
 template __global__ void k_oci_iterate<8>(StepArgs, int, int);
 template __global__ void k_oci_iterate<16>(StepArgs, int, int);
-template __global__ void k_step_end<4>(StepArgs, double *, int);
-template __global__ void k_step_end<8>(StepArgs, double *, int);
-template __global__ void k_step_end<16>(StepArgs, double *, int);
+template __global__ void k_step_end<4>(StepArgs, double *, int, int);
+template __global__ void k_step_end<8>(StepArgs, double *, int, int);
+template __global__ void k_step_end<16>(StepArgs, double *, int, int);
 
 }  // namespace ocik

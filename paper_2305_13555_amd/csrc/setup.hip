@@ -301,19 +301,5 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
   }
 }
 
-// Rows row0 .. row0+rows-1, columns col0 .. col0+ncols-1 of each region's
-// operator, row-major.
-__global__ void k_pack_rows(int N, const double *op_all, int row0, int rows, int col0, int ncols,
-                            double *dst_all, size_t dst_stride) {
-  const int r = blockIdx.x;
-  const int nr = 4 * N + 1;
-  const int oprows = 4 * N + 4;
-  const double *op = op_all + (size_t)r * oprows * nr;
-  double *dst = dst_all + (size_t)r * dst_stride;
-  for (int idx = threadIdx.x; idx < rows * ncols; idx += blockDim.x) {
-    const int i = idx / ncols, j = idx % ncols;
-    dst[idx] = op[(size_t)(row0 + i) * nr + col0 + j];
-  }
-}
 
 }  // namespace ocik
