@@ -41,14 +41,18 @@ def algorithmic_bytes_per_cell_step(n_angles):
     return 8 * (10 * n_angles + 12)
 
 
+ITERATIONS_PER_LAUNCH = 1   # iterates per launch of the iteration kernel
+ITERATION_KERNEL = "k_oci_iterate"
+
+
 def roofline_launch_seconds(oci, prob, stream, steps=5):
-    """Per-launch time of k_oci_iterate on the workload's cells, regions and
-    angles, with v = inf and tol = 0 so that every iteration launch does the
-    full work (the kernel's work does not depend on the values).  Steps of 32
-    and of 16 iteration launches each run as one replayed graph (step start,
-    the launches, end of step), timed with HIP events on the library's stream;
-    the per-launch time is the difference of the median step times over the
-    16 extra launches, which removes the step start and end."""
+    """Per-launch time of the iteration kernel on the workload's cells, regions and
+    angles, with v = inf and tol = 0 so that every launch does the full work
+    (the kernel's work does not depend on the values).  Steps of 32 and of 16
+    iterates each run as one replayed graph (step start,
+    the launches, end of step), timed with HIP events on the library's
+    stream; the per-launch time is the difference of the median step times
+    over the extra launches, which removes the step start and end."""
     import dataclasses
     roof = dataclasses.replace(prob, speed=float("inf"), name=prob.name + ", v = inf")
     med = {}
@@ -63,7 +67,7 @@ def roofline_launch_seconds(oci, prob, stream, steps=5):
                                        % (n, info))
                 ms.append(info["ms"])
             med[n] = float(np.median(ms))
-    return (med[32] - med[16]) * 1e-3 / 16
+    return (med[32] - med[16]) * 1e-3 / (16 // ITERATIONS_PER_LAUNCH)
 
 
 def copy_calibration(torch, mib):
@@ -155,8 +159,8 @@ def main():
     if args.roofline_only:
         t = roofline_launch_seconds(oci, prob, stream, steps=3)
         nbytes = copy_calibration(torch, 64)
-        b = algorithmic_bytes_per_cell_iteration(N) * J
-        print(json.dumps({"kernel": "k_oci_iterate", "us_per_launch": t * 1e6,
+        b = algorithmic_bytes_per_cell_iteration(N) * J * ITERATIONS_PER_LAUNCH
+        print(json.dumps({"kernel": ITERATION_KERNEL, "us_per_launch": t * 1e6,
                           "algorithmic_bytes_per_launch": b, "GB/s": b / t / 1e9,
                           "copy_bytes": nbytes}))
         return
@@ -184,8 +188,8 @@ def main():
     iters = sum(i["iterations"] for infos in all_infos for i in infos)
     value = iters * J * N / wall
     gpu_phi = phi_dev.cpu().numpy()
-    kernel, per_launch_s = "k_oci_iterate", roofline_launch_seconds(oci, prob, stream)
-    bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J
+    kernel, per_launch_s = ITERATION_KERNEL, roofline_launch_seconds(oci, prob, stream)
+    bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J * ITERATIONS_PER_LAUNCH
     achieved = bytes_launch / per_launch_s / 1e9
 
     # time to a 1e-6 tolerance per step (whole solve at tol 1e-6), and source
@@ -244,7 +248,9 @@ def main():
             "traffic": measured_traffic(),
             "bytes_per_launch": bytes_launch,
             "us_per_launch": per_launch_s * 1e6,
-            "measured": "(median step time at 32 launches - at 16) / 16, 5 steps each",
+            "iterations_per_launch": ITERATIONS_PER_LAUNCH,
+            "measured": "(median step time at 32 iterates - at 16) / the extra launches, "
+                        "5 steps each",
         },
         "cpu_baseline": cpu,
         "iterations_per_time_step": iters / (args.steps * T),

@@ -33,6 +33,11 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr int kMaxBatch = 64;   // iteration launches per replayed batch
+// Whole steps use the two-iterates-per-launch kernel when set.  Off: on the
+// bench workload its second iterate (operator fragments reloaded from L2)
+// cost as much as a launch (25.2 us per two-iterate launch against 12.7 us
+// per one-iterate launch).
+constexpr bool kTwoIterates = false;
 
 }  // namespace
 
@@ -44,7 +49,7 @@ struct oci_ctx {
   std::vector<int> cells;
   std::vector<double> ghost_left, ghost_right;   // [2N] each
   int Mt = 0, Met = 0, Mto = 0, ntiles = 0, grid = 0, W_it = 1, W_ed = 1, W_pv = 1;
-  size_t lds_it = 0, lds_pv = 0, lds_ed = 0;
+  size_t lds_it = 0, lds_it2 = 0, lds_pv = 0, lds_ed = 0;
   int lu_cb = 0, lu_pitch = 0;   // LDS LU: right-hand-side columns per work-group, row pitch
   size_t lds_lu = 0;
   int si_blocks = 0, si_segs = 1;
@@ -86,7 +91,7 @@ struct oci_ctx {
   int *d_bad = nullptr;
   // kernels for the chosen operator batch width CH
   int CH = 16;
-  void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr;
+  void *fn_begin = nullptr, *fn_iter = nullptr, *fn_iter2 = nullptr, *fn_end = nullptr;
   std::string err;
   StepArgs sa{};
   SiArgs si{};
@@ -334,7 +339,18 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   const int J = j0;
   c->J = J;
   c->ntiles = (int)tiles.size();
-  c->grid = 8 * ((c->ntiles + 7) / 8);
+  c->grid = c->ntiles;   // one work-group per tile
+  {
+    // work-group order: the hardware dispatches work-groups round-robin over
+    // the 8 XCDs, so the work-groups b = x, x+8, ... of XCD x take a
+    // contiguous run of tiles (a region's operator in few L2s, neighbouring
+    // tiles in the same L2)
+    std::vector<TileDev> by_block(tiles.size());
+    size_t next = 0;
+    for (int x = 0; x < 8; ++x)
+      for (int b = x; b < c->ntiles; b += 8) by_block[b] = tiles[next++];
+    tiles.swap(by_block);
+  }
   c->Mt = (2 * N + 4 + 15) / 16;
   c->Met = (2 * N + 15) / 16;
   c->Mto = (2 * N + 15) / 16;
@@ -348,6 +364,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->W_ed = std::min(c->Met, 4);
   const int P = K + 2;
   c->lds_it = (size_t)(kTileCells + 2) * P * sizeof(double);
+  c->lds_it2 = (size_t)(kR0Rows + kR1Rows) * P * sizeof(double);
   c->lds_pv = (size_t)kTileCells * P * sizeof(double);
   c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
   c->si_blocks = (J * 4 + 255) / 256;
@@ -505,15 +522,14 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.dec = c->d_dec;
   s.nreg_arg = R <= kArgRegions ? R : 0;
   if (s.nreg_arg) {
-    int t0 = 0;
-    for (int r = 0; r < R; ++r) {
-      s.reg_j0[r] = regions[r].j0;
-      s.reg_t0[r] = t0;
-      t0 += (regions[r].nc + kTileCells - 1) / kTileCells;
-    }
+    for (int r = 0; r < R; ++r) s.reg_j0[r] = regions[r].j0;
     s.reg_j0[R] = J;
-    s.reg_t0[R] = t0;
   }
+  s.regions = c->d_regions;
+  s.tiles_in_args = (c->ntiles <= kArgTiles && J < (1 << kArgTileCellBits) && R < 1024) ? 1 : 0;
+  if (s.tiles_in_args)
+    for (int i = 0; i < c->ntiles; ++i)
+      s.tile_word[i] = pack_tile(tiles[i].region, tiles[i].c0, tiles[i].nc);
   s.psi0 = c->d_psi[0];
   s.psi1 = c->d_psi[1];
   s.phi_res = c->d_phi_res;
@@ -554,22 +570,30 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
 
   // kernels for this N: operator fragments are fetched CH k-steps at a time
   c->CH = (N / 2 >= 16) ? 16 : (N / 2 >= 8 ? 8 : 4);
-  if (c->CH == 16) {
-    c->fn_begin = (void *)k_step_begin<16>;
-    c->fn_iter = (void *)k_oci_iterate<16>;
-    c->fn_end = (void *)k_step_end<16>;
-  } else if (c->CH == 8) {
-    c->fn_begin = (void *)k_step_begin<8>;
-    c->fn_iter = (void *)k_oci_iterate<8>;
-    c->fn_end = (void *)k_step_end<8>;
+  // <CH, tiles in the kernel arguments>; two iterates per launch use at
+  // most 8-step chunks
+#define OCI_PICK(CHV, ARGT)                                         \
+  do {                                                              \
+    c->fn_begin = (void *)k_step_begin<CHV, ARGT>;                  \
+    c->fn_iter = (void *)k_oci_iterate<CHV, ARGT>;                  \
+    c->fn_iter2 = (void *)k_oci_iterate2<(CHV > 8 ? 8 : CHV), ARGT>; \
+    c->fn_end = (void *)k_step_end<CHV, ARGT>;                      \
+  } while (0)
+  if (s.tiles_in_args) {
+    if (c->CH == 16) OCI_PICK(16, true);
+    else if (c->CH == 8) OCI_PICK(8, true);
+    else OCI_PICK(4, true);
   } else {
-    c->fn_begin = (void *)k_step_begin<4>;
-    c->fn_iter = (void *)k_oci_iterate<4>;
-    c->fn_end = (void *)k_step_end<4>;
+    if (c->CH == 16) OCI_PICK(16, false);
+    else if (c->CH == 8) OCI_PICK(8, false);
+    else OCI_PICK(4, false);
   }
+#undef OCI_PICK
   // kernels with more than 64 KiB of dynamic LDS must say so
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it));
+  OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter2,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it2));
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_begin,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_pv));
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_end,
@@ -750,10 +774,15 @@ static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out
   for (int s = 0; s < G && e == hipSuccess; ++s) {
     void *bargs[] = {&c->sa};
     e = add(c->fn_begin, c->W_pv, c->lds_pv, bargs);
-    for (int i = 1; i <= L && e == hipSuccess; ++i) {
+    // L iterates: L/2 launches of two iterations each (L even), or L launches
+    const int launches = kTwoIterates ? L / 2 : L;
+    for (int i = 1; i <= launches && e == hipSuccess; ++i) {
       int node = i, cb = 0;
       void *args[] = {&c->sa, &node, &cb};
-      e = add(c->fn_iter, c->W_it, c->lds_it, args);
+      if (kTwoIterates)
+        e = add(c->fn_iter2, c->W_it, c->lds_it2, args);
+      else
+        e = add(c->fn_iter, c->W_it, c->lds_it, args);
     }
     if (e == hipSuccess) {
       int first = 1, last = L;
@@ -773,6 +802,16 @@ static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out
   c->step_graphs.push_back({L, G, phi, exec});
   *out = exec;
   return OCI_OK;
+}
+
+// Iterates queued for a step whose count is expected to be `want`: at most
+// max_iters (rounded up to even with two iterates per launch), within the
+// iterate buffers.
+static int step_batch(oci_ctx *c, int want) {
+  int b = std::min(want, c->max_iters);
+  if (!kTwoIterates) return std::max(1, std::min(b, c->nbuf - 1));
+  b += b & 1;
+  return std::max(2, std::min(b, (c->nbuf - 1) & ~1));
 }
 
 static int launch_end(oci_ctx *c, double *phi_dev, int first, int last) {
@@ -868,7 +907,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
   while (k < n_steps) {
     // a cold step (no previous count) goes alone; nothing is queued behind it
     while (q < n_steps && nwin < 2 && c->batch_hint > 0) {
-      const int batch = std::min({c->batch_hint, c->max_iters, c->nbuf - 1});
+      const int batch = step_batch(c, c->batch_hint);
       // windows grow 1, 2, 4, .. kWindow steps, so that a count learnt from
       // few steps is not applied to many
       const int count = std::min(c->window, n_steps - q);
@@ -881,7 +920,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       q += count;
     }
     if (nwin == 0) {
-      const int batch = std::min({kColdBatch, c->max_iters, c->nbuf - 1});
+      const int batch = step_batch(c, kColdBatch);
       const int ev = next_ev;
       next_ev ^= 1;
       rc = enqueue_window(c, q, 1, batch, phi_dev, c->evW[ev][0], c->evW[ev][1]);

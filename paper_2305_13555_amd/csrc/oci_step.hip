@@ -30,25 +30,14 @@
 
 namespace ocik {
 
-// Work-group index -> tile: consecutive tiles go to the same XCD (work-groups
-// are dispatched round-robin over the 8 XCDs), so a region's operator is
-// read into few L2s and neighbouring tiles share an L2.  The grid has
-// 8*ceil(ntiles/8) work-groups, on which this map is a bijection; the
-// surplus ones get -1 and exit.
-__device__ __forceinline__ int tile_of_block(int b, int ntiles) {
-  const int nx = 8;
-  const int per = (ntiles + nx - 1) / nx;
-  const int t = (b % nx) * per + b / nx;
-  return t < ntiles ? t : -1;
-}
-
 // A block of consecutive rows (row length K doubles, K even) copied from
-// global memory into LDS rows of pitch P; LDS rows rows .. cap-1 are zeroed.
+// global memory into LDS rows of pitch P; LDS rows rows .. cap-1 are filled
+// with copies (see copy_load).
 struct RowBlock {
   const double *src;   // first row in global memory
   double *dst;         // first LDS row
   int rows;            // rows to copy
-  int cap;             // LDS rows owned by the block (rows .. cap-1 are zeroed)
+  int cap;             // LDS rows owned by the block (rows .. cap-1 hold copies)
 };
 
 // Staged copy: the first batch of every thread's elements is held in
@@ -65,12 +54,18 @@ __device__ __forceinline__ int copy_total(const RowBlock *blk, int nblk, int h, 
   return nblk > 1 ? n0 + blk[1].cap * h : n0;
 }
 
+// Element i of the staged blocks.  Loads are unconditional, from a clamped
+// valid address: LDS rows past a block's rows receive copies of its last
+// element, which no kernel uses (they are the rows of cells past the tile,
+// whose results are discarded).  So a thread's loads issue back to back with
+// no branch and no use of the value before the LDS store.
 __device__ __forceinline__ double2 copy_load(const RowBlock *blk, int nblk, int h, int off1,
                                              int i) {
-  const int b = (nblk > 1 && i >= off1) ? 1 : 0;
-  const int li = b ? i - off1 : i;
-  if (li / h < blk[b].rows) return reinterpret_cast<const double2 *>(blk[b].src)[li];
-  return make_double2(0.0, 0.0);
+  const bool second = nblk > 1 && i >= off1;
+  const int li = second ? i - off1 : i;
+  const double *src = second ? blk[1].src : blk[0].src;
+  const int n = (second ? blk[1].rows : blk[0].rows) * h;
+  return reinterpret_cast<const double2 *>(src)[min(li, n - 1)];
 }
 
 __device__ __forceinline__ void copy_store(const RowBlock *blk, int nblk, int h, int off1, int P,
@@ -88,7 +83,7 @@ __device__ inline void issue_copy(CopyRegs &cr, const RowBlock *blk, int nblk, i
 #pragma unroll
   for (int q = 0; q < kCopyBatch; ++q) {
     const int i = threadIdx.x + q * blockDim.x;
-    cr.v[q] = i < total ? copy_load(blk, nblk, h, off1, i) : make_double2(0.0, 0.0);
+    cr.v[q] = copy_load(blk, nblk, h, off1, min(i, total - 1));   // stored only if i < total
   }
 }
 
@@ -108,7 +103,7 @@ __device__ inline void finish_copy(const CopyRegs &cr, const RowBlock *blk, int 
 #pragma unroll
     for (int q = 0; q < kCopyBatch; ++q) {
       const int i = base + q * blockDim.x;
-      v[q] = i < total ? copy_load(blk, nblk, h, off1, i) : make_double2(0.0, 0.0);
+      v[q] = copy_load(blk, nblk, h, off1, min(i, total - 1));
     }
 #pragma unroll
     for (int q = 0; q < kCopyBatch; ++q) {
@@ -164,9 +159,11 @@ __device__ __forceinline__ RowBlock own_block(double *lds, const double *src, co
 
 // Operator fragments for k-steps base .. base+CH-1 of one row tile (zero past KS).
 template <int CH>
+// (Fragments past KS are loads of the last valid one, never used: every MFMA
+// loop skips k-steps past KS.)
 __device__ __forceinline__ void load_frags(double (&f)[CH], const double *Fr, int base, int KS) {
 #pragma unroll
-  for (int i = 0; i < CH; ++i) f[i] = (base + i < KS) ? Fr[(size_t)(base + i) * 64] : 0.0;
+  for (int i = 0; i < CH; ++i) f[i] = Fr[(size_t)min(base + i, KS - 1) * 64];
 }
 
 // acc += A(16 cells x 4CH) * B(4CH x 16 rows) for one chunk; aload(ks) gives
@@ -202,27 +199,24 @@ __device__ __forceinline__ d4 mma_rowtile(const double *Fr, int KS, bool first_l
 // Tile routines
 // ---------------------------------------------------------------------------
 
-// Tile ti: from the region table in the kernel arguments when the problem has
-// few regions (tiles are numbered region by region, 16 cells each, the last
-// tile of a region ragged), else from the tile table.
-__device__ __forceinline__ TileDev tile_desc(const StepArgs &a, int ti) {
-  if (a.nreg_arg == 0) return a.tiles[ti];
-  int r = 0;
-#pragma unroll
-  for (int q = 1; q < kArgRegions; ++q) r += (q < a.nreg_arg && a.reg_t0[q] <= ti) ? 1 : 0;
-  int j0 = 0, j1 = 0, t0 = 0;
-#pragma unroll
-  for (int q = 0; q < kArgRegions; ++q)
-    if (q == r) {
-      j0 = a.reg_j0[q];
-      j1 = a.reg_j0[q + 1];
-      t0 = a.reg_t0[q];
-    }
+// The tile of this work-group.  Tiles are listed in work-group order (the
+// host assigns consecutive tiles to the work-groups of one XCD, which the
+// hardware dispatches round-robin over the 8 XCDs, so a region's operator is
+// read into few L2s and neighbouring tiles share an L2).  With ARGT the
+// packed descriptors travel in the kernel arguments: the descriptor load
+// issues with the other argument loads, and no data load waits on a table.
+template <bool ARGT>
+__device__ __forceinline__ TileDev blk_desc(const StepArgs &a) {
   TileDev t;
-  t.region = r;
-  t.c0 = j0 + (ti - t0) * kTileCells;
-  t.nc = min(kTileCells, j1 - t.c0);
-  t.pad = 0;
+  if (ARGT) {
+    const uint32_t w = a.tile_word[blockIdx.x];
+    t.c0 = (int)(w & ((1u << kArgTileCellBits) - 1));
+    t.nc = (int)((w >> kArgTileCellBits) & 15u) + 1;
+    t.region = (int)(w >> 22);
+    t.pad = 0;
+  } else {
+    t = a.tiles[blockIdx.x];
+  }
   return t;
 }
 
@@ -313,24 +307,24 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int cl = kq + 4 * i;
-    const bool ok = wave < a.Mto && row0 < K && cl < t.nc;
-    pf.gv[i] = ok ? a.gh[(size_t)(t.c0 + cl) * ghp + row0] : 0.0;
+    // (used only for cells < nc and rows < K)
+    pf.gv[i] = a.gh[(size_t)(t.c0 + min(cl, t.nc - 1)) * ghp + min(row0, K - 1)];
   }
   const int cl = lane >> 2, comp = lane & 3;
-  const bool pok = wave == 0 && cl < t.nc;
-  pf.hv = pok ? a.gh[(size_t)(t.c0 + cl) * ghp + K + comp] : 0.0;
-  pf.po = pok ? phi_old[(size_t)(t.c0 + cl) * 4 + comp] : 0.0;
+  const int cc = t.c0 + min(cl, t.nc - 1);   // (used by wave 0 for cells < nc)
+  pf.hv = a.gh[(size_t)cc * ghp + K + comp];
+  pf.po = phi_old[(size_t)cc * 4 + comp];
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
   issue_copy(pf.cr, blk, 1, K);
 }
 
 // Computes the tile's iterate; wave 0 writes its residual record (rec).
-// Returns early (no stores) when the queue is stalled.
+// Returns early (no stores) when `skip` is set (a stalled queue).
 template <int CH>
 __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
                                        double *phi_new, double *lds, double *phis, double2 *rec,
-                                       bool stalled) {
+                                       bool skip) {
   const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
@@ -341,7 +335,7 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
     finish_copy(pf.cr, blk, 1, K, P);
   }
   __syncthreads();
-  if (stalled) return;
+  if (skip) return;
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
   // incident flux of cell c, entry k: k < N from the right neighbour
   // (LDS row c+2), k >= N from the left neighbour (LDS row c)
@@ -409,6 +403,261 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   if (lane == 0) *rec = make_double2(dphi, fphi);
 }
 
+// ---------------------------------------------------------------------------
+// Two iterations per launch
+// ---------------------------------------------------------------------------
+// A work-group computes iterates l and l+1 of its tile.  Iterate l+1 of cells
+// c0 .. c0+nc-1 needs iterate l of cells c0-1 .. c0+nc, so the launch stages
+// iterate l-1 of cells c0-2 .. c0+nc+1 (R0, 20 LDS rows) and computes, besides
+// its own cells, the half of the two halo cells' outgoing fluxes that enters
+// the tile: the mu > 0 half of cell c0-1 and the mu < 0 half of cell c0+nc,
+// each with its own region's operator.  Iterate l of the tile's cells and the
+// two halo halves go to R1 (18 rows, the layout of the one-iteration kernel),
+// from which iterate l+1 is computed with no global load.  Both iterates are
+// stored (the end of step may accept either), each with its residual record.
+
+// Region of cell j, for a cell next to tile t (t.c0-1 or t.c0+t.nc).
+__device__ __forceinline__ int halo_region(const StepArgs &a, const TileDev &t, int j) {
+  if (j >= t.c0 && j < t.c0 + t.nc) return t.region;
+  if (a.nreg_arg == 0) {
+    const RegionDev g = a.regions[t.region];
+    return j < g.j0 ? t.region - 1 : (j >= g.j0 + g.nc ? t.region + 1 : t.region);
+  }
+  // tiles are numbered region by region: the neighbour is in the next or
+  // previous region exactly when j crosses the region's edge
+  int j0 = 0, j1 = 0;
+#pragma unroll
+  for (int q = 0; q < kArgRegions; ++q)
+    if (q == t.region) {
+      j0 = a.reg_j0[q];
+      j1 = a.reg_j0[q + 1];
+    }
+  if (j < j0) return t.region - 1;
+  if (j >= j1) return t.region + 1;
+  return t.region;
+}
+
+template <int CH>
+struct Iter2Prefetch {
+  double f0[CH], fp[kPhiPre], gv[4];
+  double gh_halo;   // step constant of this lane's halo cell (kq 0: left, 1: right), row tile = wave
+  double hv, po;
+  CopyRegs cr;
+};
+
+// Reflecting edges in R0: the ghost cell -1 (row 1-c0) or J (row J-c0+2) is
+// present when the tile or its halo touches the edge; its entering half is
+// the mirror angles of the boundary cell (the row next to it).  Ends with a
+// barrier.
+__device__ inline void reflect_r0(double *r0, int P, const TileDev &t, int N, int J, int bcl,
+                                  int bcr) {
+  const int K = 2 * N;
+  if (t.c0 <= 1 && bcl == kBcReflect) {
+    double *g = r0 + (1 - t.c0) * P;
+    const double *b = g + P;
+    for (int i = N + threadIdx.x; i < K; i += blockDim.x) {
+      const int m = i >> 1, tl = i & 1;
+      g[i] = b[2 * (N - 1 - m) + tl];
+    }
+  }
+  if (t.c0 + t.nc >= J - 1 && bcr == kBcReflect) {
+    double *g = r0 + (J - t.c0 + 2) * P;
+    const double *b = g - P;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      const int m = i >> 1, tl = i & 1;
+      g[i] = b[2 * (N - 1 - m) + tl];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ RowBlock r0_block(double *lds, const double *src, const TileDev &t,
+                                             int K, int J, int P) {
+  // LDS row i holds ghosted row c0-1+i (cell c0-2+i), i in [lo, hi)
+  const int lo = t.c0 == 0 ? 1 : 0;
+  const int hi = min(t.nc + 4, J + 2 - (t.c0 - 1));
+  return RowBlock{src + (size_t)(t.c0 - 1 + lo) * K, lds + lo * P, hi - lo, kR0Rows - lo};
+}
+
+template <int CH>
+__device__ inline void iterate2_prefetch(Iter2Prefetch<CH> &pf, const StepArgs &a,
+                                         const TileDev &t, const double *src,
+                                         const double *phi_old, double *lds) {
+  const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
+  const int ghp = a.Mt * 16;
+  const int row0 = wave * 16 + col;
+  if (wave < a.Mto) load_frags<CH>(pf.f0, F + (size_t)wave * KS * 64, 0, KS);
+  int prt, poff, kb, ke;
+  bool pshared;
+  phi_tile(a, &prt, &poff, &pshared);
+  phi_ksplit(KS, W, wave, &kb, &ke);
+  if (!pshared) load_frags<kPhiPre>(pf.fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int cl = kq + 4 * i;
+    // (used only for cells < nc and rows < K)
+    pf.gv[i] = a.gh[(size_t)(t.c0 + min(cl, t.nc - 1)) * ghp + min(row0, K - 1)];
+  }
+  {
+    const int hj = kq == 0 ? t.c0 - 1 : t.c0 + t.nc;
+    // (used only by lanes kq < 2 whose halo cell exists)
+    pf.gh_halo = a.gh[(size_t)min(max(hj, 0), a.J - 1) * ghp + min(row0, K - 1)];
+  }
+  const int cl = lane >> 2, comp = lane & 3;
+  const int cc = t.c0 + min(cl, t.nc - 1);   // (used by wave 0 for cells < nc)
+  pf.hv = a.gh[(size_t)cc * ghp + K + comp];
+  pf.po = phi_old[(size_t)cc * 4 + comp];
+  const RowBlock blk[1] = {r0_block(lds, src, t, K, a.J, P)};
+  issue_copy(pf.cr, blk, 1, K);
+}
+
+// Outgoing rows and scalar-flux partials of the tile's own cells from the
+// neighbour rows in `rows` (cell c's left neighbour in row c, right neighbour
+// in row c+2).  Writes the outgoing rows to dst (global) and, when r1 is
+// given, to rows 1 .. nc of r1; the partials to my_phis.
+template <int CH, typename PF>
+__device__ inline void own_gemm(const PF &pf, const StepArgs &a, const TileDev &t,
+                                const double *rows, double *dst, double *r1, double *my_phis) {
+  const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
+  const int ghp = a.Mt * 16;
+  auto aload = [&](int ks) {
+    const int k = ks * 4 + kq;
+    return rows[(k < N ? col + 2 : col) * P + k];
+  };
+  int prt, poff, kb, ke;
+  bool pshared;
+  phi_tile(a, &prt, &poff, &pshared);
+  phi_ksplit(KS, W, wave, &kb, &ke);
+  my_phis[lane] = 0.0;
+  for (int rt = wave; rt < a.Mto; rt += W) {
+    const d4 acc = mma_rowtile<CH>(F + (size_t)rt * KS * 64, KS, rt == wave, pf.f0, aload);
+    const int row = rt * 16 + col;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cl = kq + 4 * i;
+      if (cl >= t.nc) continue;
+      if (row < K) {
+        const int cell = t.c0 + cl;
+        const double g = rt == wave ? pf.gv[i] : a.gh[(size_t)cell * ghp + row];
+        const double v = acc[i] + g;
+        dst[(size_t)(cell + 1) * K + row] = v;
+        if (r1) r1[(cl + 1) * P + row] = v;
+      } else if (pshared && rt == prt && row < K + 4) {
+        my_phis[cl * 4 + (row - K)] = acc[i];
+      }
+    }
+  }
+  if (!pshared) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const double *Fp = F + (size_t)prt * KS * 64;
+#pragma unroll
+    for (int i = 0; i < kPhiPre; ++i)
+      if (kb + i < ke) acc = mfma16x16x4(aload(kb + i), pf.fp[i], acc);
+    for (int base = kb + kPhiPre; base < ke; base += CH) {
+      double f[CH];
+      load_frags<CH>(f, Fp, base, ke);
+#pragma unroll
+      for (int i = 0; i < CH; ++i)
+        if (base + i < ke) acc = mfma16x16x4(aload(base + i), f[i], acc);
+    }
+    if (col < 4) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) my_phis[(kq + 4 * i) * 4 + col] = acc[i];
+    }
+  }
+}
+
+// The entering halves of the two halo cells' iterate (rows 0 and nc+1 of r1)
+// from iterate l-1 in r0 (halo cell c0-1: neighbours in r0 rows 0 and 2; halo
+// cell c0+nc: rows nc+1 and nc+3).
+template <int CH>
+__device__ inline void halo_gemm(const Iter2Prefetch<CH> &pf, const StepArgs &a, const TileDev &t,
+                                 const double *r0, double *r1) {
+  const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int ghp = a.Mt * 16;
+  const bool hasL = t.c0 > 0, hasR = t.c0 + t.nc < a.J;
+  const int regL = hasL ? halo_region(a, t, t.c0 - 1) : -1;
+  const int regR = hasR ? halo_region(a, t, t.c0 + t.nc) : -1;
+  for (int rt = wave; rt < a.Mto; rt += W) {
+    const bool needL = hasL && rt * 16 + 15 >= N;   // the tile holds mu > 0 rows
+    const bool needR = hasR && rt * 16 < N;         // the tile holds mu < 0 rows
+    for (int pass = 0; pass < 2; ++pass) {
+      // pass 0: the left halo (and the right one too when it shares the
+      // operator); pass 1: the right halo when its operator differs
+      bool useL, useR;
+      int reg;
+      if (pass == 0) {
+        useL = needL;
+        useR = needR && (!needL || regR == regL);
+        reg = useL ? regL : regR;
+        if (!useL && !useR) continue;
+      } else {
+        useL = false;
+        useR = needR && needL && regR != regL;
+        reg = regR;
+        if (!useR) continue;
+      }
+      auto aload = [&](int ks) {
+        const int k = ks * 4 + kq;
+        if (col == 0 && useL) return r0[(k < N ? 2 : 0) * P + k];
+        if (col == 1 && useR) return r0[(k < N ? t.nc + 3 : t.nc + 1) * P + k];
+        return 0.0;
+      };
+      const double *F = a.frag_it + (size_t)reg * a.frag_it_stride + lane;
+      d4 acc;
+      if (reg == t.region && rt == wave) {
+        acc = mma_rowtile<CH>(F + (size_t)rt * KS * 64, KS, true, pf.f0, aload);
+      } else {
+        // another region's operator (a tile at a region edge): small chunks,
+        // so that the wave's own fragments stay in registers beside them
+        const double none[4] = {0.0, 0.0, 0.0, 0.0};
+        acc = mma_rowtile<4>(F + (size_t)rt * KS * 64, KS, false, none, aload);
+      }
+      const int row = rt * 16 + col;
+      if (row < K) {
+        // element 0 of lanes kq = 0 / 1 holds D rows 0 / 1: the left / right halo
+        if (kq == 0 && useL && row >= N) {
+          const double g = rt == wave ? pf.gh_halo : a.gh[(size_t)(t.c0 - 1) * ghp + row];
+          r1[row] = acc[0] + g;
+        } else if (kq == 1 && useR && row < N) {
+          const double g = rt == wave ? pf.gh_halo : a.gh[(size_t)(t.c0 + t.nc) * ghp + row];
+          r1[(t.nc + 1) * P + row] = acc[0] + g;
+        }
+      }
+    }
+  }
+}
+
+// Wave 0: scalar flux of the 64 (cell, component) pairs from the waves'
+// partials and the constant, stored with the tile's residual record.
+// Returns this lane's new value (the old one for the next iterate).
+__device__ inline double phi_finish(const StepArgs &a, const TileDev &t, const double *phis,
+                                    double hv, double po, double *phi_new, double2 *rec) {
+  const int lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  const int cl = lane >> 2, comp = lane & 3;
+  double s = 0.0;
+  for (int w = 0; w < W; ++w) s += phis[w * 64 + lane];
+  double dphi = 0.0, fphi = 0.0, v = 0.0;
+  if (cl < t.nc) {
+    v = s + hv;
+    phi_new[(size_t)(t.c0 + cl) * 4 + comp] = v;
+    dphi = isfinite(v) ? fabs(v - po) : __builtin_nan("");
+    fphi = fabs(v);
+  }
+  dphi = wave_nan_max(dphi);
+  fphi = wave_max(fphi);
+  if (lane == 0) *rec = make_double2(dphi, fphi);
+  return v;
+}
+
 // End of step for a tile: psi_{k+1/2} from the incident fluxes the accepted
 // iterate was computed from (src = the buffer the last iteration read) and
 // psi_{k-1/2}; copies the accepted scalar flux to phi_res (and phi_out).
@@ -461,7 +710,7 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
 // (each work-group moves its own rows).  The first thread of work-group 0
 // opens the step in the control block without touching the fields the other
 // work-groups read here.  Does nothing while a queued solve is stalled.
-template <int CH>
+template <int CH, bool ARGT>
 __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
   extern __shared__ double lds[];
   const StepCtl c = *a.ctl;
@@ -476,9 +725,7 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
     ct->e_last = -1.0;
     ct->e_prev = -1.0;
   }
-  const int ti = tile_of_block(blockIdx.x, a.ntiles);
-  if (ti < 0) return;
-  const TileDev t = tile_desc(a, ti);
+  const TileDev t = blk_desc<ARGT>(a);
   if (c.fin_buf != 0) {
     const int K = 2 * a.N;
     const double2 *so = reinterpret_cast<const double2 *>(
@@ -497,7 +744,7 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // iterate).  Work-group 0 also reduces the residual records iterate l-1 left
 // and stores its e in dec, off the other work-groups' path.  Nothing is
 // stored while a queued solve is stalled.
-template <int CH>
+template <int CH, bool ARGT>
 __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64];
@@ -506,24 +753,82 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   double *dst = out_buf(a, l);
   const double *phi_old = phi_buf(a, l - 1);
   double *phi_new = phi_buf(a, l);
-  const int ti = tile_of_block(blockIdx.x, a.ntiles);
-  if (ti < 0) return;
-  const bool reducer = blockIdx.x == 0 && l >= 2;
-  const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
-  const size_t slot = (size_t)a.ntiles;
-  RecRegs r1;
-  if (reducer) rec_issue(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles);
-  const TileDev t = tile_desc(a, ti);
+  const int ti = blockIdx.x;   // the tile's residual record
+  const TileDev t = blk_desc<ARGT>(a);
   IterPrefetch<CH> pf;
   iterate_prefetch<CH>(pf, a, t, src, phi_old, lds);
   const int stalled = a.ctl->stalled;
-  if (reducer) {
+  const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
+  const size_t slot = (size_t)a.ntiles;
+  if (blockIdx.x == 0 && l >= 2) {
+    RecRegs r1;
+    rec_issue(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles);
     rec_finish(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles, red, scratch);
     if (threadIdx.x == 0 && !stalled) a.dec[(l - 1) % a.nbuf] = rel_change(red[0], red[1]);
   }
   iterate_compute<CH>(pf, a, t, src, dst, phi_new, lds, phis,
                       reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
                       stalled != 0);
+}
+
+// Iterates l = cb + 2*node - 1 and l+1 of the open step in one launch (see
+// above).  Work-group 0 also reduces the residual records of iterates l-2
+// and l-1 into dec.  Nothing is stored while a queued solve is stalled.
+template <int CH, bool ARGT>
+__global__ __launch_bounds__(256, 3) void k_oci_iterate2(StepArgs a, int node, int cb) {
+  extern __shared__ double lds[];
+  __shared__ double red[2], scratch[2 * kMaxWaves], phisA[4 * 64], phisB[4 * 64];
+  const int l = cb + 2 * node - 1;
+  const int N = a.N, K = 2 * N, P = K + 2;
+  const double *src = out_buf(a, l - 1);
+  const double *phi_old = phi_buf(a, l - 1);
+  const int ti = blockIdx.x;
+  double *r0 = lds, *r1 = lds + kR0Rows * P;
+  const TileDev t = blk_desc<ARGT>(a);
+  Iter2Prefetch<CH> pf;
+  iterate2_prefetch<CH>(pf, a, t, src, phi_old, r0);
+  const int stalled = a.ctl->stalled;
+  {
+    const RowBlock blk[1] = {r0_block(r0, src, t, K, a.J, P)};
+    finish_copy(pf.cr, blk, 1, K, P);
+  }
+  if (blockIdx.x == 0) {
+    const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
+    for (int q = 2; q >= 1; --q) {
+      if (l - q < 1) continue;
+      RecRegs rr;
+      rec_issue(rr, recs + (size_t)((l - q) % a.nbuf) * a.ntiles, a.ntiles);
+      rec_finish(rr, recs + (size_t)((l - q) % a.nbuf) * a.ntiles, a.ntiles, red, scratch);
+      if (threadIdx.x == 0 && !stalled) a.dec[(l - q) % a.nbuf] = rel_change(red[0], red[1]);
+    }
+  }
+  __syncthreads();
+  if (stalled) return;
+  reflect_r0(r0, P, t, N, a.J, a.bcl, a.bcr);
+  const int wave = threadIdx.x >> 6;
+  double2 *recs_w = reinterpret_cast<double2 *>(a.partial);
+  // iterate l: own cells (to global and R1), halo halves (R1)
+  own_gemm<CH>(pf, a, t, r0 + P, out_buf(a, l), r1, phisA + wave * 64);
+  halo_gemm<CH>(pf, a, t, r0, r1);
+  // domain edges: R1's ghost rows hold the boundary values (reflecting
+  // edges are filled in from iterate l below)
+  if (t.c0 == 0)
+    for (int i = threadIdx.x; i < K; i += blockDim.x) r1[i] = r0[P + i];
+  if (t.c0 + t.nc == a.J)
+    for (int i = threadIdx.x; i < K; i += blockDim.x)
+      r1[(t.nc + 1) * P + i] = r0[(t.nc + 2) * P + i];
+  __syncthreads();
+  double vA = 0.0;
+  if (wave == 0)
+    vA = phi_finish(a, t, phisA, pf.hv, pf.po, phi_buf(a, l),
+                    recs_w + (size_t)(l % a.nbuf) * a.ntiles + ti);
+  reflect_ghosts(r1, P, t, N, a.J, a.bcl, a.bcr);
+  // iterate l+1 from R1
+  own_gemm<CH>(pf, a, t, r1, out_buf(a, l + 1), nullptr, phisB + wave * 64);
+  __syncthreads();
+  if (wave == 0)
+    phi_finish(a, t, phisB, pf.hv, vA, phi_buf(a, l + 1),
+               recs_w + (size_t)((l + 1) % a.nbuf) * a.ntiles + ti);
 }
 
 // End of the open step after iterates first .. last of it were launched
@@ -535,7 +840,7 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
 // when given).  A step still undecided (or not finite) stalls the queue
 // instead: the host resumes it.  The step's record is written either way; a
 // decided step advances the solve's step counter.
-template <int CH>
+template <int CH, bool ARGT>
 __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
                                                   int last) {
   extern __shared__ double lds[];
@@ -548,12 +853,22 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   if (c.stalled) return;
   rec_finish(r1, recs + (last % a.nbuf) * slot, a.ntiles, red, scratch);
   const double e_lastv = rel_change(red[0], red[1]);
+  // iterate last-1 may come from the same launch as `last` (no e in dec yet)
+  double e_prevv = -1.0;
+  if (last >= 2) {
+    rec_issue(r1, recs + ((last - 1) % a.nbuf) * slot, a.ntiles);
+    rec_finish(r1, recs + ((last - 1) % a.nbuf) * slot, a.ntiles, red, scratch);
+    e_prevv = rel_change(red[0], red[1]);
+  }
+  auto e_of = [&](int l) {
+    return l == last ? e_lastv : (l == last - 1 ? e_prevv : a.dec[l % a.nbuf]);
+  };
   const int step = c.open;
   int status = kRunning, L = last;
   double e_acc = -1.0;
-  double e_before = (a.strict && first - 1 >= 2) ? a.dec[(first - 1) % a.nbuf] : -1.0;
+  double e_before = (a.strict && first - 1 >= 2) ? e_of(first - 1) : -1.0;
   for (int l = first; l <= last; ++l) {
-    const double e = l == last ? e_lastv : a.dec[l % a.nbuf];
+    const double e = e_of(l);
     status = stop_rule_e(l, e, e_before, 2, a.tol, a.strict, a.max_iters);
     if (status != kRunning) {
       L = l;
@@ -579,25 +894,39 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
       ct->cur = step + 1;
     } else {
       ct->stalled = 1;
+      // the resumed launches and end read these
+      a.dec[last % a.nbuf] = e_lastv;
+      if (last >= 2) a.dec[(last - 1) % a.nbuf] = e_prevv;
     }
   }
   if (!decided) return;
   const int parity = c.step_parity;
-  const int ti = tile_of_block(blockIdx.x, a.ntiles);
-  if (ti < 0) return;
-  const TileDev t = tile_desc(a, ti);
+  const TileDev t = blk_desc<ARGT>(a);
   tile_end<CH>(a, t, out_buf(a, L - 1), parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
                phi_buf(a, L), phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
 }
 
-template __global__ void k_step_begin<4>(StepArgs);
-template __global__ void k_step_begin<8>(StepArgs);
-template __global__ void k_step_begin<16>(StepArgs);
-template __global__ void k_oci_iterate<4>(StepArgs, int, int);
-template __global__ void k_oci_iterate<8>(StepArgs, int, int);
-template __global__ void k_oci_iterate<16>(StepArgs, int, int);
-template __global__ void k_step_end<4>(StepArgs, double *, int, int);
-template __global__ void k_step_end<8>(StepArgs, double *, int, int);
-template __global__ void k_step_end<16>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<4, false>(StepArgs);
+template __global__ void k_oci_iterate<4, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate2<4, false>(StepArgs, int, int);
+template __global__ void k_step_end<4, false>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<4, true>(StepArgs);
+template __global__ void k_oci_iterate<4, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate2<4, true>(StepArgs, int, int);
+template __global__ void k_step_end<4, true>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<8, false>(StepArgs);
+template __global__ void k_oci_iterate<8, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate2<8, false>(StepArgs, int, int);
+template __global__ void k_step_end<8, false>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<8, true>(StepArgs);
+template __global__ void k_oci_iterate<8, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate2<8, true>(StepArgs, int, int);
+template __global__ void k_step_end<8, true>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, false>(StepArgs);
+template __global__ void k_oci_iterate<16, false>(StepArgs, int, int);
+template __global__ void k_step_end<16, false>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, true>(StepArgs);
+template __global__ void k_oci_iterate<16, true>(StepArgs, int, int);
+template __global__ void k_step_end<16, true>(StepArgs, double *, int, int);
 
 }  // namespace ocik

@@ -151,3 +151,25 @@ def random_small(seed, n_cells=None, n_regions=None, n_angles=None, bc=None,
         speed=float(speed if speed is not None else np.exp(rng.uniform(np.log(0.5), np.log(10.0)))),
         bc_left=bl, bc_right=br, inc_left=inc_l, inc_right=inc_r, psi0=p0,
         n_steps=3, tol=1e-12, max_iters=20000, name="random small #%d" % seed)
+
+
+def layout_case(seed, sizes, n_angles, bc, dt=0.3, speed=2.0, psi0=True):
+    """Multi-region problem with the given cells per region (tiny regions put
+    tile and halo edges next to region and domain edges); per-region data
+    drawn as in random_small."""
+    rng = np.random.default_rng([SEED, 77, seed])
+    cells = np.array(sizes, dtype=np.int32)
+    R, J, N = len(sizes), int(np.sum(sizes)), int(n_angles)
+    dx = np.exp(rng.uniform(np.log(0.05), np.log(2.0), R))
+    sigma_t = np.exp(rng.uniform(np.log(0.2), np.log(4.0), R))
+    c = rng.uniform(0.0, 0.99, R)
+    q = rng.uniform(0.0, 1.0, R)
+    bl, br = bc
+    inc_l = rng.uniform(0.0, 1.0, N // 2) if bl == INCIDENT else None
+    inc_r = rng.uniform(0.0, 1.0, N // 2) if br == INCIDENT else None
+    p0 = rng.uniform(0.0, 0.5, (J, N, 2)) if psi0 else None
+    return SlabProblem(
+        n_angles=N, cells=cells, width=dx * cells, sigma_t=sigma_t, sigma_s=c * sigma_t,
+        source=q, dt=dt, speed=speed, bc_left=bl, bc_right=br, inc_left=inc_l,
+        inc_right=inc_r, psi0=p0, n_steps=3, tol=1e-12, max_iters=20000,
+        name="layout case #%d (%d regions, %d cells, S%d)" % (seed, R, J, N))

@@ -115,6 +115,46 @@ def test_fixed_iterations_match_oracle_oci(lib, seed, kw, iters):
         assert rel(got[k]["psi_edge"], ref[k]["psi_edge"]) < 1e-11, (seed, k)
 
 
+# Tile layouts: regions of one or two cells (halo cells in other regions,
+# halo cells next to a reflecting edge: a tile starting at cell 1 or ending
+# at cell J-2), the four-wave split of the scalar-flux rows (N = 32), the
+# shared scalar-flux row tile (N = 12), and more regions than the region
+# table in the kernel arguments holds (tile table path).
+LAYOUTS = [
+    (0, [1, 17, 1, 2, 30, 1], 8, (W.REFLECT, W.REFLECT)),
+    (1, [3, 40, 1, 20], 32, (W.INCIDENT, W.REFLECT)),
+    (2, [1 + (r * 7) % 6 for r in range(40)], 4, (W.REFLECT, W.VACUUM)),
+    (3, [5, 33, 2], 12, (W.VACUUM, W.INCIDENT)),
+    (4, [16, 16, 1, 15], 16, (W.REFLECT, W.INCIDENT)),
+]
+
+
+@pytest.mark.parametrize("case", LAYOUTS, ids=lambda c: "layout%d" % c[0])
+@pytest.mark.parametrize("iters", [1, 2, 3, 5])
+def test_tile_layouts_fixed_iterations(lib, case, iters):
+    seed, sizes, n, bc = case
+    p = W.layout_case(seed, sizes, n, bc)
+    cd = cell_data(p)
+    ref = ooci.run_oci(p, cd, 3, tol=0.0, max_iters=iters)
+    got = gpu_run(lib, p, 3, tol=0.0, max_iters=iters)
+    for k in range(3):
+        assert got[k]["iterations"] == iters
+        assert rel(got[k]["phi"], ref[k]["phi"]) < 1e-11, (seed, iters, k)
+        assert rel(got[k]["psi_edge"], ref[k]["psi_edge"]) < 1e-11, (seed, iters, k)
+
+
+@pytest.mark.parametrize("case", LAYOUTS, ids=lambda c: "layout%d" % c[0])
+def test_tile_layouts_converged(lib, case):
+    seed, sizes, n, bc = case
+    p = W.layout_case(seed, sizes, n, bc)
+    cd = cell_data(p)
+    direct = balance.run_direct(p, cd, 2)
+    got = gpu_run(lib, p, 2, tol=1e-12, max_iters=50000, strict=True)
+    for k in range(2):
+        assert got[k]["rc"] == lib.OCI_OK
+        assert rel(got[k]["phi"], direct[k]["phi"]) < 1e-10
+
+
 @pytest.mark.parametrize("seed,kw", CASES[:12])
 def test_fixed_iterations_match_oracle_si(lib, seed, kw):
     p = W.random_small(seed, **(kw or {}))
