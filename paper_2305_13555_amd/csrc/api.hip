@@ -33,11 +33,6 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr int kMaxBatch = 64;   // iteration launches per replayed batch
-// Whole steps use the two-iterates-per-launch kernel when set.  Off: on the
-// bench workload its second iterate (operator fragments reloaded from L2)
-// cost as much as a launch (25.2 us per two-iterate launch against 12.7 us
-// per one-iterate launch).
-constexpr bool kTwoIterates = false;
 
 }  // namespace
 
@@ -49,7 +44,7 @@ struct oci_ctx {
   std::vector<int> cells;
   std::vector<double> ghost_left, ghost_right;   // [2N] each
   int Mt = 0, Met = 0, Mto = 0, ntiles = 0, grid = 0, W_it = 1, W_ed = 1, W_pv = 1;
-  size_t lds_it = 0, lds_it2 = 0, lds_pv = 0, lds_ed = 0;
+  size_t lds_it = 0, lds_pv = 0, lds_ed = 0;
   int lu_cb = 0, lu_pitch = 0;   // LDS LU: right-hand-side columns per work-group, row pitch
   size_t lds_lu = 0;
   int si_blocks = 0, si_segs = 1;
@@ -91,7 +86,7 @@ struct oci_ctx {
   int *d_bad = nullptr;
   // kernels for the chosen operator batch width CH
   int CH = 16;
-  void *fn_begin = nullptr, *fn_iter = nullptr, *fn_iter2 = nullptr, *fn_end = nullptr;
+  void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr;
   std::string err;
   StepArgs sa{};
   SiArgs si{};
@@ -264,15 +259,15 @@ static int build_operators(oci_ctx *c) {
     hipLaunchKernelGGL(k_lu_solve, dim3(R), dim3(1024), 0, c->stream, N, ws_M, ws_X, d_bad);
   }
   hipLaunchKernelGGL(k_select_rows, dim3(R), dim3(256), 0, c->stream, N, c->d_w, ws_X, c->d_op);
-  // iteration operator G: rows [0, 2N+4), columns [0, 2N) (incident)
+  // iteration operator G: rows [0, 2N+4), columns [0, 2N) (incident), k-major
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, 0, K,
-                     c->Mt, c->d_fi, c->fi_stride, (double *)nullptr, (size_t)0);
+                     c->Mt, c->d_fi, c->fi_stride, (double *)nullptr, (size_t)0, 1);
   // per-step operator P: rows [0, 2N+4), columns [2N, 4N) (psi_{k-1/2}); source column
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, K, K,
-                     c->Mt, c->d_fp, c->fp_stride, c->d_cp, c->cp_stride);
+                     c->Mt, c->d_fp, c->fp_stride, c->d_cp, c->cp_stride, 0);
   // end-of-step operator E: rows [2N+4, 4N+4), columns [0, 4N)
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N + 4, K, 0,
-                     2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride);
+                     2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride, 0);
   hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
                      c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
   OCI_CK(c, hipGetLastError());
@@ -364,7 +359,6 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->W_ed = std::min(c->Met, 4);
   const int P = K + 2;
   c->lds_it = (size_t)(kTileCells + 2) * P * sizeof(double);
-  c->lds_it2 = (size_t)(kR0Rows + kR1Rows) * P * sizeof(double);
   c->lds_pv = (size_t)kTileCells * P * sizeof(double);
   c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
   c->si_blocks = (J * 4 + 255) / 256;
@@ -520,12 +514,6 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.phib = c->d_phib;
   s.phi_stride = c->phi_stride;
   s.dec = c->d_dec;
-  s.nreg_arg = R <= kArgRegions ? R : 0;
-  if (s.nreg_arg) {
-    for (int r = 0; r < R; ++r) s.reg_j0[r] = regions[r].j0;
-    s.reg_j0[R] = J;
-  }
-  s.regions = c->d_regions;
   s.tiles_in_args = (c->ntiles <= kArgTiles && J < (1 << kArgTileCellBits) && R < 1024) ? 1 : 0;
   if (s.tiles_in_args)
     for (int i = 0; i < c->ntiles; ++i)
@@ -570,14 +558,13 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
 
   // kernels for this N: operator fragments are fetched CH k-steps at a time
   c->CH = (N / 2 >= 16) ? 16 : (N / 2 >= 8 ? 8 : 4);
-  // <CH, tiles in the kernel arguments>; two iterates per launch use at
-  // most 8-step chunks
-#define OCI_PICK(CHV, ARGT)                                         \
-  do {                                                              \
-    c->fn_begin = (void *)k_step_begin<CHV, ARGT>;                  \
-    c->fn_iter = (void *)k_oci_iterate<CHV, ARGT>;                  \
-    c->fn_iter2 = (void *)k_oci_iterate2<(CHV > 8 ? 8 : CHV), ARGT>; \
-    c->fn_end = (void *)k_step_end<CHV, ARGT>;                      \
+  // <CH, tiles in the kernel arguments, 16-byte operand reads (N % 8 == 0)>
+#define OCI_PICK(CHV, ARGT)                                                      \
+  do {                                                                           \
+    c->fn_begin = (void *)k_step_begin<CHV, ARGT>;                               \
+    c->fn_iter = N % 8 == 0 ? (void *)k_oci_iterate<CHV, ARGT, true>             \
+                            : (void *)k_oci_iterate<CHV, ARGT, false>;           \
+    c->fn_end = (void *)k_step_end<CHV, ARGT>;                                   \
   } while (0)
   if (s.tiles_in_args) {
     if (c->CH == 16) OCI_PICK(16, true);
@@ -592,8 +579,6 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   // kernels with more than 64 KiB of dynamic LDS must say so
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it));
-  OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter2,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it2));
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_begin,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_pv));
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_end,
@@ -774,15 +759,10 @@ static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out
   for (int s = 0; s < G && e == hipSuccess; ++s) {
     void *bargs[] = {&c->sa};
     e = add(c->fn_begin, c->W_pv, c->lds_pv, bargs);
-    // L iterates: L/2 launches of two iterations each (L even), or L launches
-    const int launches = kTwoIterates ? L / 2 : L;
-    for (int i = 1; i <= launches && e == hipSuccess; ++i) {
+    for (int i = 1; i <= L && e == hipSuccess; ++i) {
       int node = i, cb = 0;
       void *args[] = {&c->sa, &node, &cb};
-      if (kTwoIterates)
-        e = add(c->fn_iter2, c->W_it, c->lds_it2, args);
-      else
-        e = add(c->fn_iter, c->W_it, c->lds_it, args);
+      e = add(c->fn_iter, c->W_it, c->lds_it, args);
     }
     if (e == hipSuccess) {
       int first = 1, last = L;
@@ -805,13 +785,9 @@ static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out
 }
 
 // Iterates queued for a step whose count is expected to be `want`: at most
-// max_iters (rounded up to even with two iterates per launch), within the
-// iterate buffers.
+// max_iters, within the iterate buffers.
 static int step_batch(oci_ctx *c, int want) {
-  int b = std::min(want, c->max_iters);
-  if (!kTwoIterates) return std::max(1, std::min(b, c->nbuf - 1));
-  b += b & 1;
-  return std::max(2, std::min(b, (c->nbuf - 1) & ~1));
+  return std::max(1, std::min({want, c->max_iters, c->nbuf - 1}));
 }
 
 static int launch_end(oci_ctx *c, double *phi_dev, int first, int last) {

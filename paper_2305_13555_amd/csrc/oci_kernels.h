@@ -15,23 +15,12 @@ constexpr int kArgTileCellBits = 18;
 __host__ __device__ inline uint32_t pack_tile(int region, int c0, int nc) {
   return (uint32_t)c0 | ((uint32_t)(nc - 1) << kArgTileCellBits) | ((uint32_t)region << 22);
 }
-// Regions of the halo cells of the two-iterates kernel: the first cell of
-// region r and of region r+1, for up to kArgRegions regions.
-constexpr int kArgRegions = 32;
 
-// LDS rows of the two-iterations-per-launch kernel: iterate l-1 of the tile
-// and two cells either side (R0), iterate l of the tile and one cell either
-// side (R1).
-constexpr int kR0Rows = kTileCells + 4;
-constexpr int kR1Rows = kTileCells + 2;
 
 struct StepArgs {
   const TileDev *tiles;    // [ntiles] in work-group order (one work-group per tile)
-  const RegionDev *regions;
   int ntiles;
   int tiles_in_args;       // 1: tile_word holds every tile's descriptor (kernels <.., true>)
-  int nreg_arg;            // R if R <= kArgRegions (then reg_j0 is valid), else 0
-  int reg_j0[kArgRegions + 1];   // first cell of region r; reg_j0[R] = J
   uint32_t tile_word[kArgTiles]; // packed descriptors in work-group order (see pack_tile)
   int N, J, Mt, Met;
   int Mto;                 // row tiles holding the 2N outgoing rows
@@ -99,11 +88,10 @@ __global__ void k_lu_solve_lds(int N, int CB, int P, const double *ws_M, double 
 __global__ void k_select_rows(int N, const double *w, const double *ws_X, double *op_all);
 __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
                        int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
-                       size_t cvec_stride);
+                       size_t cvec_stride, int kmajor);
 // oci_step.hip (CH = operator k-steps fetched per batch: 4, 8 or 16)
 template <int CH, bool ARGT> __global__ void k_step_begin(StepArgs a);
-template <int CH, bool ARGT> __global__ void k_oci_iterate(StepArgs a, int node, int cb);
-template <int CH, bool ARGT> __global__ void k_oci_iterate2(StepArgs a, int node, int cb);
+template <int CH, bool ARGT, bool VEC> __global__ void k_oci_iterate(StepArgs a, int node, int cb);
 template <int CH, bool ARGT>
 __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last);
 // si.hip

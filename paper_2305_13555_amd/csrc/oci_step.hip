@@ -195,6 +195,63 @@ __device__ __forceinline__ d4 mma_rowtile(const double *Fr, int KS, bool first_l
   return acc;
 }
 
+// The iteration operator G is packed k-major per lane group: lane group kq
+// (lanes 16kq .. 16kq+15) holds k = kq*KS + ks in k-step ks, so a lane's A
+// values for consecutive k-steps are consecutive in one LDS row.  With VEC
+// (KS a multiple of 4; every k-step range starts at a multiple of 4) they are
+// read four at a time as two 16-byte reads ahead of their MFMAs.
+template <bool VEC>
+__device__ __forceinline__ void a_quad(const double *p, int ks, int KS, double (&v)[4]) {
+  if (ks < KS) {
+    const double2 x = *reinterpret_cast<const double2 *>(p + ks);
+    const double2 y = *reinterpret_cast<const double2 *>(p + ks + 2);
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = y.x;
+    v[3] = y.y;
+  }
+}
+
+// acc += A * B over k-steps kb .. min(kb+NP, ke)-1 with the fragments in f;
+// p = this lane's A values (k-step ks at p[ks]).
+template <int NP, bool VEC>
+__device__ __forceinline__ void mma_quads(d4 &acc, const double (&f)[NP], int kb, int ke,
+                                          const double *p, int KS) {
+  if (VEC) {
+#pragma unroll
+    for (int g = 0; g < NP; g += 4) {
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      a_quad<VEC>(p, kb + g, KS, v);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (kb + g + i < ke) acc = mfma16x16x4(v[i], f[g + i], acc);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+      if (kb + i < ke) acc = mfma16x16x4(p[kb + i], f[i], acc);
+  }
+}
+
+// One row tile of G over all KS k-steps; the first CH fragments may come
+// preloaded.
+template <int CH, bool VEC>
+__device__ __forceinline__ d4 mma_rowtile_g(const double *Fr, int KS, bool first_loaded,
+                                            const double (&f0)[CH], const double *p) {
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  int base = 0;
+  if (first_loaded) {
+    mma_quads<CH, VEC>(acc, f0, 0, KS, p, KS);
+    base = CH;
+  }
+  for (; base < KS; base += CH) {
+    double f[CH];
+    load_frags<CH>(f, Fr, base, KS);
+    mma_quads<CH, VEC>(acc, f, base, KS, p, KS);
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
 // Tile routines
 // ---------------------------------------------------------------------------
@@ -283,10 +340,11 @@ __device__ __forceinline__ void phi_tile(const StepArgs &a, int *rt, int *off, b
   *shared = *off != 0;
 }
 
-// k-steps of the scalar-flux row tile handled by wave w when it is split.
+// k-steps of the scalar-flux row tile handled by wave w when it is split
+// (range starts at multiples of 4).
 __device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *ke) {
-  *kb = (w * KS) / W;
-  *ke = ((w + 1) * KS) / W;
+  *kb = ((w * KS) / W) & ~3;
+  *ke = w + 1 == W ? KS : (((w + 1) * KS) / W) & ~3;
 }
 
 template <int CH>
@@ -320,7 +378,7 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
 
 // Computes the tile's iterate; wave 0 writes its residual record (rec).
 // Returns early (no stores) when `skip` is set (a stalled queue).
-template <int CH>
+template <int CH, bool VEC>
 __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
                                        double *phi_new, double *lds, double *phis, double2 *rec,
@@ -338,11 +396,9 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   if (skip) return;
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
   // incident flux of cell c, entry k: k < N from the right neighbour
-  // (LDS row c+2), k >= N from the left neighbour (LDS row c)
-  auto aload = [&](int ks) {
-    const int k = ks * 4 + kq;
-    return lds[(k < N ? col + 2 : col) * P + k];
-  };
+  // (LDS row c+2), k >= N from the left neighbour (LDS row c).  With the
+  // k-major packing k = kq*KS + ks, so k < N exactly for kq < 2.
+  const double *ap = lds + (kq < 2 ? col + 2 : col) * P + kq * KS;
   int prt, poff, kb, ke;
   bool pshared;
   phi_tile(a, &prt, &poff, &pshared);
@@ -351,7 +407,7 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   double *my_phis = phis + wave * 64;
   if (lane < 64) my_phis[lane] = 0.0;
   for (int rt = wave; rt < a.Mto; rt += W) {
-    const d4 acc = mma_rowtile<CH>(F + (size_t)rt * KS * 64, KS, rt == wave, pf.f0, aload);
+    const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)rt * KS * 64, KS, rt == wave, pf.f0, ap);
     const int row = rt * 16 + col;      // operator row of this lane
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -370,15 +426,11 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
     // k-steps kb .. ke-1 of the scalar-flux row tile; lanes col < 4 hold its rows
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     const double *Fp = F + (size_t)prt * KS * 64;
-#pragma unroll
-    for (int i = 0; i < kPhiPre; ++i)
-      if (kb + i < ke) acc = mfma16x16x4(aload(kb + i), pf.fp[i], acc);
+    mma_quads<kPhiPre, VEC>(acc, pf.fp, kb, ke, ap, KS);
     for (int base = kb + kPhiPre; base < ke; base += CH) {
       double f[CH];
       load_frags<CH>(f, Fp, base, ke);
-#pragma unroll
-      for (int i = 0; i < CH; ++i)
-        if (base + i < ke) acc = mfma16x16x4(aload(base + i), f[i], acc);
+      mma_quads<CH, VEC>(acc, f, base, ke, ap, KS);
     }
     if (col < 4) {
 #pragma unroll
@@ -401,261 +453,6 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   dphi = wave_nan_max(dphi);
   fphi = wave_max(fphi);
   if (lane == 0) *rec = make_double2(dphi, fphi);
-}
-
-// ---------------------------------------------------------------------------
-// Two iterations per launch
-// ---------------------------------------------------------------------------
-// A work-group computes iterates l and l+1 of its tile.  Iterate l+1 of cells
-// c0 .. c0+nc-1 needs iterate l of cells c0-1 .. c0+nc, so the launch stages
-// iterate l-1 of cells c0-2 .. c0+nc+1 (R0, 20 LDS rows) and computes, besides
-// its own cells, the half of the two halo cells' outgoing fluxes that enters
-// the tile: the mu > 0 half of cell c0-1 and the mu < 0 half of cell c0+nc,
-// each with its own region's operator.  Iterate l of the tile's cells and the
-// two halo halves go to R1 (18 rows, the layout of the one-iteration kernel),
-// from which iterate l+1 is computed with no global load.  Both iterates are
-// stored (the end of step may accept either), each with its residual record.
-
-// Region of cell j, for a cell next to tile t (t.c0-1 or t.c0+t.nc).
-__device__ __forceinline__ int halo_region(const StepArgs &a, const TileDev &t, int j) {
-  if (j >= t.c0 && j < t.c0 + t.nc) return t.region;
-  if (a.nreg_arg == 0) {
-    const RegionDev g = a.regions[t.region];
-    return j < g.j0 ? t.region - 1 : (j >= g.j0 + g.nc ? t.region + 1 : t.region);
-  }
-  // tiles are numbered region by region: the neighbour is in the next or
-  // previous region exactly when j crosses the region's edge
-  int j0 = 0, j1 = 0;
-#pragma unroll
-  for (int q = 0; q < kArgRegions; ++q)
-    if (q == t.region) {
-      j0 = a.reg_j0[q];
-      j1 = a.reg_j0[q + 1];
-    }
-  if (j < j0) return t.region - 1;
-  if (j >= j1) return t.region + 1;
-  return t.region;
-}
-
-template <int CH>
-struct Iter2Prefetch {
-  double f0[CH], fp[kPhiPre], gv[4];
-  double gh_halo;   // step constant of this lane's halo cell (kq 0: left, 1: right), row tile = wave
-  double hv, po;
-  CopyRegs cr;
-};
-
-// Reflecting edges in R0: the ghost cell -1 (row 1-c0) or J (row J-c0+2) is
-// present when the tile or its halo touches the edge; its entering half is
-// the mirror angles of the boundary cell (the row next to it).  Ends with a
-// barrier.
-__device__ inline void reflect_r0(double *r0, int P, const TileDev &t, int N, int J, int bcl,
-                                  int bcr) {
-  const int K = 2 * N;
-  if (t.c0 <= 1 && bcl == kBcReflect) {
-    double *g = r0 + (1 - t.c0) * P;
-    const double *b = g + P;
-    for (int i = N + threadIdx.x; i < K; i += blockDim.x) {
-      const int m = i >> 1, tl = i & 1;
-      g[i] = b[2 * (N - 1 - m) + tl];
-    }
-  }
-  if (t.c0 + t.nc >= J - 1 && bcr == kBcReflect) {
-    double *g = r0 + (J - t.c0 + 2) * P;
-    const double *b = g - P;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-      const int m = i >> 1, tl = i & 1;
-      g[i] = b[2 * (N - 1 - m) + tl];
-    }
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ RowBlock r0_block(double *lds, const double *src, const TileDev &t,
-                                             int K, int J, int P) {
-  // LDS row i holds ghosted row c0-1+i (cell c0-2+i), i in [lo, hi)
-  const int lo = t.c0 == 0 ? 1 : 0;
-  const int hi = min(t.nc + 4, J + 2 - (t.c0 - 1));
-  return RowBlock{src + (size_t)(t.c0 - 1 + lo) * K, lds + lo * P, hi - lo, kR0Rows - lo};
-}
-
-template <int CH>
-__device__ inline void iterate2_prefetch(Iter2Prefetch<CH> &pf, const StepArgs &a,
-                                         const TileDev &t, const double *src,
-                                         const double *phi_old, double *lds) {
-  const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
-  const int col = lane & 15, kq = lane >> 4;
-  const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
-  const int ghp = a.Mt * 16;
-  const int row0 = wave * 16 + col;
-  if (wave < a.Mto) load_frags<CH>(pf.f0, F + (size_t)wave * KS * 64, 0, KS);
-  int prt, poff, kb, ke;
-  bool pshared;
-  phi_tile(a, &prt, &poff, &pshared);
-  phi_ksplit(KS, W, wave, &kb, &ke);
-  if (!pshared) load_frags<kPhiPre>(pf.fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int cl = kq + 4 * i;
-    // (used only for cells < nc and rows < K)
-    pf.gv[i] = a.gh[(size_t)(t.c0 + min(cl, t.nc - 1)) * ghp + min(row0, K - 1)];
-  }
-  {
-    const int hj = kq == 0 ? t.c0 - 1 : t.c0 + t.nc;
-    // (used only by lanes kq < 2 whose halo cell exists)
-    pf.gh_halo = a.gh[(size_t)min(max(hj, 0), a.J - 1) * ghp + min(row0, K - 1)];
-  }
-  const int cl = lane >> 2, comp = lane & 3;
-  const int cc = t.c0 + min(cl, t.nc - 1);   // (used by wave 0 for cells < nc)
-  pf.hv = a.gh[(size_t)cc * ghp + K + comp];
-  pf.po = phi_old[(size_t)cc * 4 + comp];
-  const RowBlock blk[1] = {r0_block(lds, src, t, K, a.J, P)};
-  issue_copy(pf.cr, blk, 1, K);
-}
-
-// Outgoing rows and scalar-flux partials of the tile's own cells from the
-// neighbour rows in `rows` (cell c's left neighbour in row c, right neighbour
-// in row c+2).  Writes the outgoing rows to dst (global) and, when r1 is
-// given, to rows 1 .. nc of r1; the partials to my_phis.
-template <int CH, typename PF>
-__device__ inline void own_gemm(const PF &pf, const StepArgs &a, const TileDev &t,
-                                const double *rows, double *dst, double *r1, double *my_phis) {
-  const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
-  const int col = lane & 15, kq = lane >> 4;
-  const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
-  const int ghp = a.Mt * 16;
-  auto aload = [&](int ks) {
-    const int k = ks * 4 + kq;
-    return rows[(k < N ? col + 2 : col) * P + k];
-  };
-  int prt, poff, kb, ke;
-  bool pshared;
-  phi_tile(a, &prt, &poff, &pshared);
-  phi_ksplit(KS, W, wave, &kb, &ke);
-  my_phis[lane] = 0.0;
-  for (int rt = wave; rt < a.Mto; rt += W) {
-    const d4 acc = mma_rowtile<CH>(F + (size_t)rt * KS * 64, KS, rt == wave, pf.f0, aload);
-    const int row = rt * 16 + col;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int cl = kq + 4 * i;
-      if (cl >= t.nc) continue;
-      if (row < K) {
-        const int cell = t.c0 + cl;
-        const double g = rt == wave ? pf.gv[i] : a.gh[(size_t)cell * ghp + row];
-        const double v = acc[i] + g;
-        dst[(size_t)(cell + 1) * K + row] = v;
-        if (r1) r1[(cl + 1) * P + row] = v;
-      } else if (pshared && rt == prt && row < K + 4) {
-        my_phis[cl * 4 + (row - K)] = acc[i];
-      }
-    }
-  }
-  if (!pshared) {
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    const double *Fp = F + (size_t)prt * KS * 64;
-#pragma unroll
-    for (int i = 0; i < kPhiPre; ++i)
-      if (kb + i < ke) acc = mfma16x16x4(aload(kb + i), pf.fp[i], acc);
-    for (int base = kb + kPhiPre; base < ke; base += CH) {
-      double f[CH];
-      load_frags<CH>(f, Fp, base, ke);
-#pragma unroll
-      for (int i = 0; i < CH; ++i)
-        if (base + i < ke) acc = mfma16x16x4(aload(base + i), f[i], acc);
-    }
-    if (col < 4) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) my_phis[(kq + 4 * i) * 4 + col] = acc[i];
-    }
-  }
-}
-
-// The entering halves of the two halo cells' iterate (rows 0 and nc+1 of r1)
-// from iterate l-1 in r0 (halo cell c0-1: neighbours in r0 rows 0 and 2; halo
-// cell c0+nc: rows nc+1 and nc+3).
-template <int CH>
-__device__ inline void halo_gemm(const Iter2Prefetch<CH> &pf, const StepArgs &a, const TileDev &t,
-                                 const double *r0, double *r1) {
-  const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
-  const int col = lane & 15, kq = lane >> 4;
-  const int ghp = a.Mt * 16;
-  const bool hasL = t.c0 > 0, hasR = t.c0 + t.nc < a.J;
-  const int regL = hasL ? halo_region(a, t, t.c0 - 1) : -1;
-  const int regR = hasR ? halo_region(a, t, t.c0 + t.nc) : -1;
-  for (int rt = wave; rt < a.Mto; rt += W) {
-    const bool needL = hasL && rt * 16 + 15 >= N;   // the tile holds mu > 0 rows
-    const bool needR = hasR && rt * 16 < N;         // the tile holds mu < 0 rows
-    for (int pass = 0; pass < 2; ++pass) {
-      // pass 0: the left halo (and the right one too when it shares the
-      // operator); pass 1: the right halo when its operator differs
-      bool useL, useR;
-      int reg;
-      if (pass == 0) {
-        useL = needL;
-        useR = needR && (!needL || regR == regL);
-        reg = useL ? regL : regR;
-        if (!useL && !useR) continue;
-      } else {
-        useL = false;
-        useR = needR && needL && regR != regL;
-        reg = regR;
-        if (!useR) continue;
-      }
-      auto aload = [&](int ks) {
-        const int k = ks * 4 + kq;
-        if (col == 0 && useL) return r0[(k < N ? 2 : 0) * P + k];
-        if (col == 1 && useR) return r0[(k < N ? t.nc + 3 : t.nc + 1) * P + k];
-        return 0.0;
-      };
-      const double *F = a.frag_it + (size_t)reg * a.frag_it_stride + lane;
-      d4 acc;
-      if (reg == t.region && rt == wave) {
-        acc = mma_rowtile<CH>(F + (size_t)rt * KS * 64, KS, true, pf.f0, aload);
-      } else {
-        // another region's operator (a tile at a region edge): small chunks,
-        // so that the wave's own fragments stay in registers beside them
-        const double none[4] = {0.0, 0.0, 0.0, 0.0};
-        acc = mma_rowtile<4>(F + (size_t)rt * KS * 64, KS, false, none, aload);
-      }
-      const int row = rt * 16 + col;
-      if (row < K) {
-        // element 0 of lanes kq = 0 / 1 holds D rows 0 / 1: the left / right halo
-        if (kq == 0 && useL && row >= N) {
-          const double g = rt == wave ? pf.gh_halo : a.gh[(size_t)(t.c0 - 1) * ghp + row];
-          r1[row] = acc[0] + g;
-        } else if (kq == 1 && useR && row < N) {
-          const double g = rt == wave ? pf.gh_halo : a.gh[(size_t)(t.c0 + t.nc) * ghp + row];
-          r1[(t.nc + 1) * P + row] = acc[0] + g;
-        }
-      }
-    }
-  }
-}
-
-// Wave 0: scalar flux of the 64 (cell, component) pairs from the waves'
-// partials and the constant, stored with the tile's residual record.
-// Returns this lane's new value (the old one for the next iterate).
-__device__ inline double phi_finish(const StepArgs &a, const TileDev &t, const double *phis,
-                                    double hv, double po, double *phi_new, double2 *rec) {
-  const int lane = threadIdx.x & 63, W = blockDim.x >> 6;
-  const int cl = lane >> 2, comp = lane & 3;
-  double s = 0.0;
-  for (int w = 0; w < W; ++w) s += phis[w * 64 + lane];
-  double dphi = 0.0, fphi = 0.0, v = 0.0;
-  if (cl < t.nc) {
-    v = s + hv;
-    phi_new[(size_t)(t.c0 + cl) * 4 + comp] = v;
-    dphi = isfinite(v) ? fabs(v - po) : __builtin_nan("");
-    fphi = fabs(v);
-  }
-  dphi = wave_nan_max(dphi);
-  fphi = wave_max(fphi);
-  if (lane == 0) *rec = make_double2(dphi, fphi);
-  return v;
 }
 
 // End of step for a tile: psi_{k+1/2} from the incident fluxes the accepted
@@ -744,7 +541,7 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // iterate).  Work-group 0 also reduces the residual records iterate l-1 left
 // and stores its e in dec, off the other work-groups' path.  Nothing is
 // stored while a queued solve is stalled.
-template <int CH, bool ARGT>
+template <int CH, bool ARGT, bool VEC>
 __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64];
@@ -766,69 +563,9 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
     rec_finish(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles, red, scratch);
     if (threadIdx.x == 0 && !stalled) a.dec[(l - 1) % a.nbuf] = rel_change(red[0], red[1]);
   }
-  iterate_compute<CH>(pf, a, t, src, dst, phi_new, lds, phis,
+  iterate_compute<CH, VEC>(pf, a, t, src, dst, phi_new, lds, phis,
                       reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
                       stalled != 0);
-}
-
-// Iterates l = cb + 2*node - 1 and l+1 of the open step in one launch (see
-// above).  Work-group 0 also reduces the residual records of iterates l-2
-// and l-1 into dec.  Nothing is stored while a queued solve is stalled.
-template <int CH, bool ARGT>
-__global__ __launch_bounds__(256, 3) void k_oci_iterate2(StepArgs a, int node, int cb) {
-  extern __shared__ double lds[];
-  __shared__ double red[2], scratch[2 * kMaxWaves], phisA[4 * 64], phisB[4 * 64];
-  const int l = cb + 2 * node - 1;
-  const int N = a.N, K = 2 * N, P = K + 2;
-  const double *src = out_buf(a, l - 1);
-  const double *phi_old = phi_buf(a, l - 1);
-  const int ti = blockIdx.x;
-  double *r0 = lds, *r1 = lds + kR0Rows * P;
-  const TileDev t = blk_desc<ARGT>(a);
-  Iter2Prefetch<CH> pf;
-  iterate2_prefetch<CH>(pf, a, t, src, phi_old, r0);
-  const int stalled = a.ctl->stalled;
-  {
-    const RowBlock blk[1] = {r0_block(r0, src, t, K, a.J, P)};
-    finish_copy(pf.cr, blk, 1, K, P);
-  }
-  if (blockIdx.x == 0) {
-    const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
-    for (int q = 2; q >= 1; --q) {
-      if (l - q < 1) continue;
-      RecRegs rr;
-      rec_issue(rr, recs + (size_t)((l - q) % a.nbuf) * a.ntiles, a.ntiles);
-      rec_finish(rr, recs + (size_t)((l - q) % a.nbuf) * a.ntiles, a.ntiles, red, scratch);
-      if (threadIdx.x == 0 && !stalled) a.dec[(l - q) % a.nbuf] = rel_change(red[0], red[1]);
-    }
-  }
-  __syncthreads();
-  if (stalled) return;
-  reflect_r0(r0, P, t, N, a.J, a.bcl, a.bcr);
-  const int wave = threadIdx.x >> 6;
-  double2 *recs_w = reinterpret_cast<double2 *>(a.partial);
-  // iterate l: own cells (to global and R1), halo halves (R1)
-  own_gemm<CH>(pf, a, t, r0 + P, out_buf(a, l), r1, phisA + wave * 64);
-  halo_gemm<CH>(pf, a, t, r0, r1);
-  // domain edges: R1's ghost rows hold the boundary values (reflecting
-  // edges are filled in from iterate l below)
-  if (t.c0 == 0)
-    for (int i = threadIdx.x; i < K; i += blockDim.x) r1[i] = r0[P + i];
-  if (t.c0 + t.nc == a.J)
-    for (int i = threadIdx.x; i < K; i += blockDim.x)
-      r1[(t.nc + 1) * P + i] = r0[(t.nc + 2) * P + i];
-  __syncthreads();
-  double vA = 0.0;
-  if (wave == 0)
-    vA = phi_finish(a, t, phisA, pf.hv, pf.po, phi_buf(a, l),
-                    recs_w + (size_t)(l % a.nbuf) * a.ntiles + ti);
-  reflect_ghosts(r1, P, t, N, a.J, a.bcl, a.bcr);
-  // iterate l+1 from R1
-  own_gemm<CH>(pf, a, t, r1, out_buf(a, l + 1), nullptr, phisB + wave * 64);
-  __syncthreads();
-  if (wave == 0)
-    phi_finish(a, t, phisB, pf.hv, vA, phi_buf(a, l + 1),
-               recs_w + (size_t)((l + 1) % a.nbuf) * a.ntiles + ti);
 }
 
 // End of the open step after iterates first .. last of it were launched
@@ -907,26 +644,28 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
 }
 
 template __global__ void k_step_begin<4, false>(StepArgs);
-template __global__ void k_oci_iterate<4, false>(StepArgs, int, int);
-template __global__ void k_oci_iterate2<4, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, false, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, false, true>(StepArgs, int, int);
 template __global__ void k_step_end<4, false>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<4, true>(StepArgs);
-template __global__ void k_oci_iterate<4, true>(StepArgs, int, int);
-template __global__ void k_oci_iterate2<4, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, true, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, true, true>(StepArgs, int, int);
 template __global__ void k_step_end<4, true>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<8, false>(StepArgs);
-template __global__ void k_oci_iterate<8, false>(StepArgs, int, int);
-template __global__ void k_oci_iterate2<8, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, false, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, false, true>(StepArgs, int, int);
 template __global__ void k_step_end<8, false>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<8, true>(StepArgs);
-template __global__ void k_oci_iterate<8, true>(StepArgs, int, int);
-template __global__ void k_oci_iterate2<8, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, true, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, true, true>(StepArgs, int, int);
 template __global__ void k_step_end<8, true>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<16, false>(StepArgs);
-template __global__ void k_oci_iterate<16, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, false, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, false, true>(StepArgs, int, int);
 template __global__ void k_step_end<16, false>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<16, true>(StepArgs);
-template __global__ void k_oci_iterate<16, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, true, false>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, true, true>(StepArgs, int, int);
 template __global__ void k_step_end<16, true>(StepArgs, double *, int, int);
 
 }  // namespace ocik

@@ -273,12 +273,13 @@ __global__ void k_select_rows(int N, const double *w, const double *ws_X, double
 }
 
 // Pack a rows x K block of the operator (first row row0, first column col0)
-// into MFMA A-fragment order: frag[(rt*KS + ks)*64 + lane] =
-// A[rt*16 + lane%16][ks*4 + lane/16] (zero beyond `rows`), KS = K/4, and the
-// constant column into cvec[rt*16 + i] (zero-padded to Mt*16).
+// into MFMA fragment order: frag[(rt*KS + ks)*64 + lane] =
+// A[rt*16 + lane%16][k] with k = ks*4 + lane/16, or with kmajor
+// k = (lane/16)*KS + ks (zero beyond `rows`), KS = K/4, and the constant
+// column into cvec[rt*16 + i] (zero-padded to Mt*16).
 __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
                        int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
-                       size_t cvec_stride) {
+                       size_t cvec_stride, int kmajor) {
   const int r = blockIdx.x;
   const int nr = 4 * N + 1;
   const int oprows = 4 * N + 4;
@@ -291,7 +292,7 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
     const int blk = idx >> 6;
     const int rt = blk / KS, ks = blk % KS;
     const int row = rt * 16 + (lane & 15);
-    const int col = ks * 4 + (lane >> 4);
+    const int col = kmajor ? (lane >> 4) * KS + ks : ks * 4 + (lane >> 4);
     frag[idx] = row < rows ? op[(size_t)(row0 + row) * nr + col0 + col] : 0.0;
   }
   if (cvec_all) {
