@@ -558,13 +558,22 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
 
   // kernels for this N: operator fragments are fetched CH k-steps at a time
   c->CH = (N / 2 >= 16) ? 16 : (N / 2 >= 8 ? 8 : 4);
-  // <CH, tiles in the kernel arguments, 16-byte operand reads (N % 8 == 0)>
-#define OCI_PICK(CHV, ARGT)                                                      \
-  do {                                                                           \
-    c->fn_begin = (void *)k_step_begin<CHV, ARGT>;                               \
-    c->fn_iter = N % 8 == 0 ? (void *)k_oci_iterate<CHV, ARGT, true>             \
-                            : (void *)k_oci_iterate<CHV, ARGT, false>;           \
-    c->fn_end = (void *)k_step_end<CHV, ARGT>;                                   \
+  // <CH, tiles in the kernel arguments, 16-byte operand reads (N % 8 == 0),
+  // built for this N (common angle counts) or for any>
+#define OCI_ITER(CHV, ARGT)                                                        \
+  (N == 8 && CHV == 4      ? (void *)k_oci_iterate<4, ARGT, true, 8>             \
+   : N == 16 && CHV == 8   ? (void *)k_oci_iterate<8, ARGT, true, 16>            \
+   : N == 32 && CHV == 16  ? (void *)k_oci_iterate<16, ARGT, true, 32>           \
+   : N == 64 && CHV == 16  ? (void *)k_oci_iterate<16, ARGT, true, 64>           \
+   : N == 128 && CHV == 16 ? (void *)k_oci_iterate<16, ARGT, true, 128>          \
+   : N == 256 && CHV == 16 ? (void *)k_oci_iterate<16, ARGT, true, 256>          \
+   : N % 8 == 0            ? (void *)k_oci_iterate<CHV, ARGT, true, 0>           \
+                           : (void *)k_oci_iterate<CHV, ARGT, false, 0>)
+#define OCI_PICK(CHV, ARGT)                          \
+  do {                                               \
+    c->fn_begin = (void *)k_step_begin<CHV, ARGT>;   \
+    c->fn_iter = OCI_ITER(CHV, ARGT);                \
+    c->fn_end = (void *)k_step_end<CHV, ARGT>;       \
   } while (0)
   if (s.tiles_in_args) {
     if (c->CH == 16) OCI_PICK(16, true);
@@ -575,6 +584,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
     else if (c->CH == 8) OCI_PICK(8, false);
     else OCI_PICK(4, false);
   }
+#undef OCI_ITER
 #undef OCI_PICK
   // kernels with more than 64 KiB of dynamic LDS must say so
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,

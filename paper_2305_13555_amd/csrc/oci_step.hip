@@ -333,33 +333,53 @@ struct IterPrefetch {
 
 // The scalar-flux rows 2N .. 2N+3 of G: their row tile, the first of them
 // within it, and whether the tile holds outgoing rows too.
-__device__ __forceinline__ void phi_tile(const StepArgs &a, int *rt, int *off, bool *shared) {
-  const int K = 2 * a.N;
+__device__ __forceinline__ void phi_tile(int N, int *rt, int *off, bool *shared) {
+  const int K = 2 * N;
   *rt = K / 16;
   *off = K % 16;
   *shared = *off != 0;
 }
 
 // k-steps of the scalar-flux row tile handled by wave w when it is split
-// (range starts at multiples of 4).
+// (range starts at multiples of 4; equal shares when KS allows).
 __device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *ke) {
-  *kb = ((w * KS) / W) & ~3;
-  *ke = w + 1 == W ? KS : (((w + 1) * KS) / W) & ~3;
+  if (KS % (4 * W) == 0) {
+    *kb = w * (KS / W);
+    *ke = *kb + KS / W;
+  } else {
+    *kb = ((w * KS) / W) & ~3;
+    *ke = w + 1 == W ? KS : (((w + 1) * KS) / W) & ~3;
+  }
 }
 
-template <int CH>
+// Problem shape seen by the iteration kernel: compile-time constants when the
+// kernel is built for one angle count NF (> 0), else from the arguments.
+template <int NF>
+struct IterShape {
+  int N, K, KS, Mto, Mt, W;
+  __device__ __forceinline__ explicit IterShape(const StepArgs &a)
+      : N(NF ? NF : a.N),
+        K(2 * N),
+        KS(K / 4),
+        Mto(NF ? (2 * NF + 15) / 16 : a.Mto),
+        Mt(NF ? (2 * NF + 4 + 15) / 16 : a.Mt),
+        W(NF ? ((2 * NF + 15) / 16 < 4 ? (2 * NF + 15) / 16 : 4) : (int)(blockDim.x >> 6)) {}
+};
+
+template <int CH, int NF>
 __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a, const TileDev &t,
                                         const double *src, const double *phi_old, double *lds) {
-  const int N = a.N, K = 2 * N, KS = K / 4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  const IterShape<NF> sh(a);
+  const int N = sh.N, K = sh.K, KS = sh.KS, W = sh.W;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
   const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
-  const int ghp = a.Mt * 16;
+  const int ghp = sh.Mt * 16;
   const int row0 = wave * 16 + col;
-  if (wave < a.Mto) load_frags<CH>(pf.f0, F + (size_t)wave * KS * 64, 0, KS);
+  if (wave < sh.Mto) load_frags<CH>(pf.f0, F + (size_t)wave * KS * 64, 0, KS);
   int prt, poff, kb, ke;
   bool pshared;
-  phi_tile(a, &prt, &poff, &pshared);
+  phi_tile(N, &prt, &poff, &pshared);
   phi_ksplit(KS, W, wave, &kb, &ke);
   if (!pshared) load_frags<kPhiPre>(pf.fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
 #pragma unroll
@@ -378,16 +398,17 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
 
 // Computes the tile's iterate; wave 0 writes its residual record (rec).
 // Returns early (no stores) when `skip` is set (a stalled queue).
-template <int CH, bool VEC>
+template <int CH, bool VEC, int NF>
 __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
                                        double *phi_new, double *lds, double *phis, double2 *rec,
                                        bool skip) {
-  const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  const IterShape<NF> sh(a);
+  const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
   const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
-  const int ghp = a.Mt * 16;
+  const int ghp = sh.Mt * 16;
   {
     const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
     finish_copy(pf.cr, blk, 1, K, P);
@@ -401,12 +422,12 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   const double *ap = lds + (kq < 2 ? col + 2 : col) * P + kq * KS;
   int prt, poff, kb, ke;
   bool pshared;
-  phi_tile(a, &prt, &poff, &pshared);
+  phi_tile(N, &prt, &poff, &pshared);
   phi_ksplit(KS, W, wave, &kb, &ke);
   // this wave's partial scalar flux, [cell][component] in LDS (zero if none)
   double *my_phis = phis + wave * 64;
   if (lane < 64) my_phis[lane] = 0.0;
-  for (int rt = wave; rt < a.Mto; rt += W) {
+  for (int rt = wave; rt < sh.Mto; rt += W) {
     const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)rt * KS * 64, KS, rt == wave, pf.f0, ap);
     const int row = rt * 16 + col;      // operator row of this lane
 #pragma unroll
@@ -541,7 +562,7 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // iterate).  Work-group 0 also reduces the residual records iterate l-1 left
 // and stores its e in dec, off the other work-groups' path.  Nothing is
 // stored while a queued solve is stalled.
-template <int CH, bool ARGT, bool VEC>
+template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64];
@@ -553,7 +574,7 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   const int ti = blockIdx.x;   // the tile's residual record
   const TileDev t = blk_desc<ARGT>(a);
   IterPrefetch<CH> pf;
-  iterate_prefetch<CH>(pf, a, t, src, phi_old, lds);
+  iterate_prefetch<CH, NF>(pf, a, t, src, phi_old, lds);
   const int stalled = a.ctl->stalled;
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   const size_t slot = (size_t)a.ntiles;
@@ -563,7 +584,7 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
     rec_finish(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles, red, scratch);
     if (threadIdx.x == 0 && !stalled) a.dec[(l - 1) % a.nbuf] = rel_change(red[0], red[1]);
   }
-  iterate_compute<CH, VEC>(pf, a, t, src, dst, phi_new, lds, phis,
+  iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis,
                       reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
                       stalled != 0);
 }
@@ -644,28 +665,41 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
 }
 
 template __global__ void k_step_begin<4, false>(StepArgs);
-template __global__ void k_oci_iterate<4, false, false>(StepArgs, int, int);
-template __global__ void k_oci_iterate<4, false, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int);
 template __global__ void k_step_end<4, false>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<4, true>(StepArgs);
-template __global__ void k_oci_iterate<4, true, false>(StepArgs, int, int);
-template __global__ void k_oci_iterate<4, true, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int);
 template __global__ void k_step_end<4, true>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<8, false>(StepArgs);
-template __global__ void k_oci_iterate<8, false, false>(StepArgs, int, int);
-template __global__ void k_oci_iterate<8, false, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int);
 template __global__ void k_step_end<8, false>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<8, true>(StepArgs);
-template __global__ void k_oci_iterate<8, true, false>(StepArgs, int, int);
-template __global__ void k_oci_iterate<8, true, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int);
 template __global__ void k_step_end<8, true>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<16, false>(StepArgs);
-template __global__ void k_oci_iterate<16, false, false>(StepArgs, int, int);
-template __global__ void k_oci_iterate<16, false, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int);
 template __global__ void k_step_end<16, false>(StepArgs, double *, int, int);
 template __global__ void k_step_begin<16, true>(StepArgs);
-template __global__ void k_oci_iterate<16, true, false>(StepArgs, int, int);
-template __global__ void k_oci_iterate<16, true, true>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int);
 template __global__ void k_step_end<16, true>(StepArgs, double *, int, int);
+
+template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int);
+template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int);
+template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int);
+template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int);
 
 }  // namespace ocik
