@@ -264,10 +264,10 @@ static int build_operators(oci_ctx *c) {
                      c->Mt, c->d_fi, c->fi_stride, (double *)nullptr, (size_t)0, 1);
   // per-step operator P: rows [0, 2N+4), columns [2N, 4N) (psi_{k-1/2}); source column
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, K, K,
-                     c->Mt, c->d_fp, c->fp_stride, c->d_cp, c->cp_stride, 0);
+                     c->Mt, c->d_fp, c->fp_stride, c->d_cp, c->cp_stride, 1);
   // end-of-step operator E: rows [2N+4, 4N+4), columns [0, 4N)
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N + 4, K, 0,
-                     2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride, 0);
+                     2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride, 1);
   hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
                      c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
   OCI_CK(c, hipGetLastError());
@@ -560,20 +560,20 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->CH = (N / 2 >= 16) ? 16 : (N / 2 >= 8 ? 8 : 4);
   // <CH, tiles in the kernel arguments, 16-byte operand reads (N % 8 == 0),
   // built for this N (common angle counts) or for any>
-#define OCI_ITER(CHV, ARGT)                                                        \
-  (N == 8 && CHV == 4      ? (void *)k_oci_iterate<4, ARGT, true, 8>             \
-   : N == 16 && CHV == 8   ? (void *)k_oci_iterate<8, ARGT, true, 16>            \
-   : N == 32 && CHV == 16  ? (void *)k_oci_iterate<16, ARGT, true, 32>           \
-   : N == 64 && CHV == 16  ? (void *)k_oci_iterate<16, ARGT, true, 64>           \
-   : N == 128 && CHV == 16 ? (void *)k_oci_iterate<16, ARGT, true, 128>          \
-   : N == 256 && CHV == 16 ? (void *)k_oci_iterate<16, ARGT, true, 256>          \
-   : N % 8 == 0            ? (void *)k_oci_iterate<CHV, ARGT, true, 0>           \
-                           : (void *)k_oci_iterate<CHV, ARGT, false, 0>)
-#define OCI_PICK(CHV, ARGT)                          \
-  do {                                               \
-    c->fn_begin = (void *)k_step_begin<CHV, ARGT>;   \
-    c->fn_iter = OCI_ITER(CHV, ARGT);                \
-    c->fn_end = (void *)k_step_end<CHV, ARGT>;       \
+#define OCI_KERNEL(KN, CHV, ARGT)                                               \
+  (N == 8 && CHV == 4      ? (void *)KN<4, ARGT, true, 8>                       \
+   : N == 16 && CHV == 8   ? (void *)KN<8, ARGT, true, 16>                      \
+   : N == 32 && CHV == 16  ? (void *)KN<16, ARGT, true, 32>                     \
+   : N == 64 && CHV == 16  ? (void *)KN<16, ARGT, true, 64>                     \
+   : N == 128 && CHV == 16 ? (void *)KN<16, ARGT, true, 128>                    \
+   : N == 256 && CHV == 16 ? (void *)KN<16, ARGT, true, 256>                    \
+   : N % 8 == 0            ? (void *)KN<CHV, ARGT, true, 0>                     \
+                           : (void *)KN<CHV, ARGT, false, 0>)
+#define OCI_PICK(CHV, ARGT)                                       \
+  do {                                                            \
+    c->fn_begin = OCI_KERNEL(k_step_begin, CHV, ARGT);            \
+    c->fn_iter = OCI_KERNEL(k_oci_iterate, CHV, ARGT);            \
+    c->fn_end = OCI_KERNEL(k_step_end, CHV, ARGT);                \
   } while (0)
   if (s.tiles_in_args) {
     if (c->CH == 16) OCI_PICK(16, true);
@@ -584,7 +584,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
     else if (c->CH == 8) OCI_PICK(8, false);
     else OCI_PICK(4, false);
   }
-#undef OCI_ITER
+#undef OCI_KERNEL
 #undef OCI_PICK
   // kernels with more than 64 KiB of dynamic LDS must say so
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,

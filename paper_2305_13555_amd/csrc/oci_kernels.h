@@ -90,11 +90,12 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
                        int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
                        size_t cvec_stride, int kmajor);
 // oci_step.hip (CH = operator k-steps fetched per batch: 4, 8 or 16)
-template <int CH, bool ARGT> __global__ void k_step_begin(StepArgs a);
-// NF > 0: built for N = NF angles (shape loops unrolled); 0: any N.
+// ARGT: tile descriptors in the kernel arguments; VEC: 16-byte operand
+// reads (N % 8 == 0); NF > 0: built for N = NF angles, 0: any N.
+template <int CH, bool ARGT, bool VEC, int NF> __global__ void k_step_begin(StepArgs a);
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_oci_iterate(StepArgs a, int node, int cb);
-template <int CH, bool ARGT>
+template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last);
 // si.hip
 __global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,

@@ -166,35 +166,6 @@ __device__ __forceinline__ void load_frags(double (&f)[CH], const double *Fr, in
   for (int i = 0; i < CH; ++i) f[i] = Fr[(size_t)min(base + i, KS - 1) * 64];
 }
 
-// acc += A(16 cells x 4CH) * B(4CH x 16 rows) for one chunk; aload(ks) gives
-// this lane's A element of k-step ks.
-template <int CH, typename ALoad>
-__device__ __forceinline__ void mma_chunk(d4 &acc, const double (&f)[CH], int base, int KS,
-                                          ALoad aload) {
-#pragma unroll
-  for (int i = 0; i < CH; ++i)
-    if (base + i < KS) acc = mfma16x16x4(aload(base + i), f[i], acc);
-}
-
-// One row tile: chunks of CH k-steps; the first chunk's fragments may come
-// preloaded.
-template <int CH, typename ALoad>
-__device__ __forceinline__ d4 mma_rowtile(const double *Fr, int KS, bool first_loaded,
-                                          const double (&f0)[CH], ALoad aload) {
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int base = 0; base < KS; base += CH) {
-    double f[CH];
-    if (first_loaded && base == 0) {
-#pragma unroll
-      for (int i = 0; i < CH; ++i) f[i] = f0[i];
-    } else {
-      load_frags<CH>(f, Fr, base, KS);
-    }
-    mma_chunk<CH>(acc, f, base, KS, aload);
-  }
-  return acc;
-}
-
 // The iteration operator G is packed k-major per lane group: lane group kq
 // (lanes 16kq .. 16kq+15) holds k = kq*KS + ks in k-step ks, so a lane's A
 // values for consecutive k-steps are consecutive in one LDS row.  With VEC
@@ -284,27 +255,30 @@ __device__ __forceinline__ double *phi_buf(const StepArgs &a, int l) {
   return a.phib + (size_t)(l % a.nbuf) * a.phi_stride;
 }
 
-// gh rows of a tile: gh_j = P_r psi_{k-1/2,j} + p_r.
-template <int CH>
+// gh rows of a tile: gh_j = P_r psi_{k-1/2,j} + p_r.  P is packed k-major,
+// so a lane's operands are consecutive in its cell's psi row.
+template <int CH, bool VEC, int NF>
 __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const double *psi_prev,
                                   double *lds) {
-  const int N = a.N, K = 2 * N, P = K + 2, KS = K / 4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
+  const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
+  const int W = NF ? (Mt < 4 ? Mt : 4) : (int)(blockDim.x >> 6);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
   const double *F = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane;
   const double *cp = a.c_pv + (size_t)t.region * a.c_pv_stride;
-  const int ghp = a.Mt * 16;
+  const int ghp = Mt * 16;
   double f0[CH];
-  if (wave < a.Mt) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
+  if (wave < Mt) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
   const RowBlock blk[1] = {own_block(lds, psi_prev, t, K)};
   copy_blocks_to_lds(blk, 1, K, P);
   __syncthreads();
-  const double *arow = lds + col * P + kq;
-  auto aload = [&](int ks) { return arow[ks * 4]; };
-  for (int rt = wave; rt < a.Mt; rt += W) {
-    const d4 acc = mma_rowtile<CH>(F + (size_t)rt * KS * 64, KS, rt == wave, f0, aload);
+  const double *ap = lds + col * P + kq * KS;
+  for (int rt = wave; rt < Mt; rt += W) {
+    const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)rt * KS * 64, KS, rt == wave, f0, ap);
     const int row = rt * 16 + col;
     const double cv = cp[row];
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int cl = kq + 4 * i;
       if (cl < t.nc) a.gh[(size_t)(t.c0 + cl) * ghp + row] = acc[i] + cv;
@@ -478,19 +452,24 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
 
 // End of step for a tile: psi_{k+1/2} from the incident fluxes the accepted
 // iterate was computed from (src = the buffer the last iteration read) and
-// psi_{k-1/2}; copies the accepted scalar flux to phi_res (and phi_out).
-template <int CH>
+// psi_{k-1/2}; copies the accepted scalar flux to phi_res (and phi_out).  E is
+// packed k-major with N k-steps per lane group: group 0 takes the right
+// neighbour's mu < 0 half, 1 the left neighbour's mu > 0 half, 2 and 3 the two
+// halves of the cell's psi_{k-1/2} row.
+template <int CH, bool VEC, int NF>
 __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const double *src,
                                 const double *psi_prev, double *psi_next, const double *phi_acc,
                                 double *phi_out, double *lds) {
-  const int N = a.N, K = 2 * N, P = K + 2, KS = (2 * K) / 4;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = N;
+  const int Met = NF ? (2 * NF + 15) / 16 : a.Met;
+  const int W = NF ? (Met < 4 ? Met : 4) : (int)(blockDim.x >> 6);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
   const double *F = a.frag_ed + (size_t)t.region * a.frag_ed_stride + lane;
   const double *ce = a.c_ed + (size_t)t.region * a.c_ed_stride;
   double *ldp = lds + (kTileCells + 2) * P;
   double f0[CH];
-  if (wave < a.Met) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
+  if (wave < Met) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
   for (int i = threadIdx.x; i < t.nc * 4; i += blockDim.x) {
     const double v = phi_acc[(size_t)t.c0 * 4 + i];
     a.phi_res[(size_t)t.c0 * 4 + i] = v;
@@ -500,17 +479,15 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
   copy_blocks_to_lds(blk, 2, K, P);
   __syncthreads();
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
-  auto aload = [&](int ks) {
-    const int k = ks * 4 + kq;
-    if (k < N) return lds[(col + 2) * P + k];
-    if (k < K) return lds[col * P + k];
-    return ldp[col * P + (k - K)];
-  };
-  for (int rt = wave; rt < a.Met; rt += W) {
-    const d4 acc = mma_rowtile<CH>(F + (size_t)rt * KS * 64, KS, rt == wave, f0, aload);
+  const double *ap = kq == 0 ? lds + (col + 2) * P
+                   : kq == 1 ? lds + col * P + N
+                   : ldp + col * P + (kq - 2) * N;
+  for (int rt = wave; rt < Met; rt += W) {
+    const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)rt * KS * 64, KS, rt == wave, f0, ap);
     const int row = rt * 16 + col;
     if (row < K) {
       const double cv = ce[row];
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int cl = kq + 4 * i;
         if (cl < t.nc) psi_next[(size_t)(t.c0 + cl) * K + row] = acc[i] + cv;
@@ -528,7 +505,7 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
 // (each work-group moves its own rows).  The first thread of work-group 0
 // opens the step in the control block without touching the fields the other
 // work-groups read here.  Does nothing while a queued solve is stalled.
-template <int CH, bool ARGT>
+template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
   extern __shared__ double lds[];
   const StepCtl c = *a.ctl;
@@ -554,7 +531,7 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
     for (int i = threadIdx.x; i < t.nc * 4; i += blockDim.x)
       a.phib[(size_t)t.c0 * 4 + i] = sp[(size_t)t.c0 * 4 + i];
   }
-  tile_begin<CH>(a, t, parity ? a.psi1 : a.psi0, lds);
+  tile_begin<CH, VEC, NF>(a, t, parity ? a.psi1 : a.psi0, lds);
 }
 
 // Iterate l = cb + node of the open step: always computed (the step's
@@ -598,7 +575,7 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
 // when given).  A step still undecided (or not finite) stalls the queue
 // instead: the host resumes it.  The step's record is written either way; a
 // decided step advances the solve's step counter.
-template <int CH, bool ARGT>
+template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
                                                   int last) {
   extern __shared__ double lds[];
@@ -611,16 +588,8 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   if (c.stalled) return;
   rec_finish(r1, recs + (last % a.nbuf) * slot, a.ntiles, red, scratch);
   const double e_lastv = rel_change(red[0], red[1]);
-  // iterate last-1 may come from the same launch as `last` (no e in dec yet)
-  double e_prevv = -1.0;
-  if (last >= 2) {
-    rec_issue(r1, recs + ((last - 1) % a.nbuf) * slot, a.ntiles);
-    rec_finish(r1, recs + ((last - 1) % a.nbuf) * slot, a.ntiles, red, scratch);
-    e_prevv = rel_change(red[0], red[1]);
-  }
-  auto e_of = [&](int l) {
-    return l == last ? e_lastv : (l == last - 1 ? e_prevv : a.dec[l % a.nbuf]);
-  };
+  // the e of earlier iterates: work-group 0 of the launch after each
+  auto e_of = [&](int l) { return l == last ? e_lastv : a.dec[l % a.nbuf]; };
   const int step = c.open;
   int status = kRunning, L = last;
   double e_acc = -1.0;
@@ -652,54 +621,87 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
       ct->cur = step + 1;
     } else {
       ct->stalled = 1;
-      // the resumed launches and end read these
-      a.dec[last % a.nbuf] = e_lastv;
-      if (last >= 2) a.dec[(last - 1) % a.nbuf] = e_prevv;
+      a.dec[last % a.nbuf] = e_lastv;   // for the resumed end
     }
   }
   if (!decided) return;
   const int parity = c.step_parity;
   const TileDev t = blk_desc<ARGT>(a);
-  tile_end<CH>(a, t, out_buf(a, L - 1), parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
+  tile_end<CH, VEC, NF>(a, t, out_buf(a, L - 1), parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
                phi_buf(a, L), phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
 }
 
-template __global__ void k_step_begin<4, false>(StepArgs);
+template __global__ void k_step_begin<4, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int);
+template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<4, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<4, false>(StepArgs, double *, int, int);
-template __global__ void k_step_begin<4, true>(StepArgs);
-template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int);
-template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<4, true>(StepArgs, double *, int, int);
-template __global__ void k_step_begin<8, false>(StepArgs);
+template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<8, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int);
+template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<8, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<8, false>(StepArgs, double *, int, int);
-template __global__ void k_step_begin<8, true>(StepArgs);
-template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int);
-template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<8, true>(StepArgs, double *, int, int);
-template __global__ void k_step_begin<16, false>(StepArgs);
+template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int);
+template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<16, false>(StepArgs, double *, int, int);
-template __global__ void k_step_begin<16, true>(StepArgs);
-template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int);
-template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<16, true>(StepArgs, double *, int, int);
-
+template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<4, false, true, 8>(StepArgs);
 template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int);
+template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<8, false, true, 16>(StepArgs);
 template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int);
+template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, false, true, 32>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int);
+template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, false, true, 64>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int);
+template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, false, true, 128>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int);
+template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, false, true, 256>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int);
+template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<4, true, false, 0>(StepArgs);
+template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int);
+template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<4, true, true, 0>(StepArgs);
+template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int);
+template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<8, true, false, 0>(StepArgs);
+template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int);
+template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<8, true, true, 0>(StepArgs);
+template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int);
+template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, true, false, 0>(StepArgs);
+template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int);
+template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, true, true, 0>(StepArgs);
+template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int);
+template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<4, true, true, 8>(StepArgs);
 template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int);
+template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<8, true, true, 16>(StepArgs);
 template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int);
+template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, true, true, 32>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int);
+template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, true, true, 64>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int);
+template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, true, true, 128>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int);
+template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int);
+template __global__ void k_step_begin<16, true, true, 256>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int);
+template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int);
 
 }  // namespace ocik
