@@ -57,7 +57,7 @@ struct oci_ctx {
   double *d_fi = nullptr, *d_fp = nullptr, *d_cp = nullptr, *d_fe = nullptr, *d_ce = nullptr;
   size_t fi_stride = 0, fp_stride = 0, cp_stride = 0, fe_stride = 0, ce_stride = 0;
   double *d_gh = nullptr, *d_outb = nullptr, *d_phib = nullptr, *d_dec = nullptr;
-  int nbuf = 2;                              // iterate buffers (>= 3 for OCI)
+  int nbuf = 3;                              // ring slots per half (buffers: 2*nbuf + 2)
   size_t out_stride = 0, phi_stride = 0;
   double *d_psi[2] = {nullptr, nullptr}, *d_phi_res = nullptr, *d_partial = nullptr;
   double *d_ainv = nullptr, *d_contrib = nullptr, *d_lag = nullptr, *d_si_partial = nullptr;
@@ -74,11 +74,12 @@ struct oci_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evA = nullptr, evB = nullptr;
   hipEvent_t evW[2][2] = {};                 // start / end of the windows in flight
   struct StepGraph {
-    int L, G;
+    int L, G, half, begin;
     double *phi;
     hipGraphExec_t exec;
   };
   std::vector<StepGraph> step_graphs;        // G whole steps of L iteration launches
+  bool gh_valid = false;                     // gh holds P psi_{k-1/2} + p for the next step
   int batch_hint = 0;                        // iteration launches per queued step
   int window = 1;                            // steps of the next queued window
   bool quad_override = false;
@@ -172,7 +173,7 @@ static int validate(const oci_problem *p, std::string *why) {
 
 static int upload_ghosts(oci_ctx *c) {
   const int K = 2 * c->N;
-  for (int b = 0; b < c->nbuf; ++b) {
+  for (int b = 0; b < 2 * c->nbuf + 2; ++b) {
     double *o = c->d_outb + (size_t)b * c->out_stride;
     OCI_CK(c, hipMemcpyAsync(o, c->ghost_left.data(), K * sizeof(double), hipMemcpyHostToDevice,
                              c->stream));
@@ -193,6 +194,7 @@ static int reset_iterate(oci_ctx *c) {
   OCI_CK(c, hipMemsetAsync(c->d_lag, 0, (size_t)2 * c->N * sizeof(double), c->stream));
   OCI_CK(c, hipMemsetAsync(c->d_ctl, 0, sizeof(StepCtl), c->stream));
   c->last_si_iters = 0;
+  c->gh_valid = false;
   c->batch_hint = 0;
   c->window = 1;
   return OCI_OK;
@@ -360,7 +362,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   const int P = K + 2;
   c->lds_it = (size_t)(kTileCells + 2) * P * sizeof(double);
   c->lds_pv = (size_t)kTileCells * P * sizeof(double);
-  c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
+  c->lds_ed = (size_t)((end_keeps_psi(P) ? 3 : 2) * kTileCells + 2) * P * sizeof(double);
   c->si_blocks = (J * 4 + 255) / 256;
   // source-iteration sweep segments: about two cells per thread of a
   // 256-thread work-group, at most 64 segments
@@ -407,17 +409,18 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_fe, (size_t)R * c->fe_stride));
   OCI_TRY(dalloc(c, &c->d_ce, (size_t)R * c->ce_stride));
   OCI_TRY(dalloc(c, &c->d_gh, (size_t)J * c->Mt * 16));
-  // one buffer per iterate of a queued batch (at most kMaxBatch launches),
-  // within a memory budget
+  // one buffer per iterate of a queued batch (at most kMaxBatch launches) in
+  // each of two rings, one per step parity, within a memory budget
   c->out_stride = (size_t)(J + 2) * K;
   c->phi_stride = (size_t)J * 4;
   {
     const size_t per = (c->out_stride + c->phi_stride) * sizeof(double);
     const size_t budget = (size_t)8 << 30;
-    c->nbuf = (int)std::max<size_t>(3, std::min<size_t>(kMaxBatch + 1, budget / per));
+    c->nbuf = (int)std::max<size_t>(3, std::min<size_t>(kMaxBatch + 1, budget / (2 * per)));
   }
-  OCI_TRY(dalloc(c, &c->d_outb, (size_t)c->nbuf * c->out_stride));
-  OCI_TRY(dalloc(c, &c->d_phib, (size_t)c->nbuf * c->phi_stride));
+  const size_t nb_all = 2 * (size_t)c->nbuf + 2;   // two rings, two source-iteration buffers
+  OCI_TRY(dalloc(c, &c->d_outb, nb_all * c->out_stride));
+  OCI_TRY(dalloc(c, &c->d_phib, nb_all * c->phi_stride));
   OCI_TRY(dalloc(c, &c->d_dec, (size_t)c->nbuf));
   for (int b = 0; b < 2; ++b) OCI_TRY(dalloc(c, &c->d_psi[b], (size_t)J * K));
   OCI_TRY(dalloc(c, &c->d_phi_res, (size_t)J * 4));
@@ -538,10 +541,11 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   q.mu = c->d_mu;
   q.w = c->d_w;
   q.ainv = c->d_ainv;
-  q.out0 = c->d_outb;
-  q.out1 = c->d_outb + c->out_stride;
-  q.phi0 = c->d_phib;
-  q.phi1 = c->d_phib + c->phi_stride;
+  q.own_buf = 2 * c->nbuf;
+  q.out0 = c->d_outb + (size_t)q.own_buf * c->out_stride;
+  q.out1 = q.out0 + c->out_stride;
+  q.phi0 = c->d_phib + (size_t)q.own_buf * c->phi_stride;
+  q.phi1 = q.phi0 + c->phi_stride;
   q.outb = c->d_outb;
   q.out_stride = c->out_stride;
   q.phib = c->d_phib;
@@ -616,11 +620,11 @@ static int clear_stall(oci_ctx *c) {
 // A later batch of a step: `count` launches after iterate cb (one by one:
 // only needed when the first batch was too short).  For SI each iteration
 // also decides.
-static int launch_batch(oci_ctx *c, bool si, int cb, int count) {
+static int launch_batch(oci_ctx *c, bool si, int cb, int count, int half = 0) {
   for (int i = 1; i <= count; ++i) {
     int node = i;
     if (!si) {
-      void *args[] = {&c->sa, &node, &cb};
+      void *args[] = {&c->sa, &node, &cb, &half};
       OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), args, c->lds_it,
                                 c->stream));
     } else {
@@ -663,6 +667,7 @@ static int abandon_step(oci_ctx *c, oci_step_info *info, int iterations) {
 // Source iteration: one step at a time, host-driven batches.
 // ---------------------------------------------------------------------------
 static int si_run(oci_ctx *c, oci_step_info *info) {
+  c->gh_valid = false;   // psi_{k-1/2} changes under the OCI step start's gh
   OCI_CK(c, hipEventRecord(c->ev0, c->stream));
   const int nb = (int)std::min<size_t>(1024, ((size_t)c->J * 2 * c->N + 255) / 256);
   hipLaunchKernelGGL(k_si_begin, dim3(nb), dim3(256), 0, c->stream, c->si, c->parity);
@@ -739,16 +744,19 @@ static int grow_records(oci_ctx *c, int n) {
   return OCI_OK;
 }
 
-// G whole steps as one replayable graph: step start, L iteration launches,
-// end of step (which writes phi_out[step] when phi is given).  Every argument
-// is static: the step index and psi buffer come from the control block.
-static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out) {
+// G whole steps as one replayable graph: with `begin`, a step start (gh of
+// the first step; each end of step computes the next step's gh), then per
+// step L iteration launches and the end of step (which writes phi_out[step]
+// when phi is given).  Every argument is static: the step index and psi
+// buffer come from the control block, the ring half alternates from `half`.
+static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi,
+                      hipGraphExec_t *out) {
   for (auto &g : c->step_graphs)
-    if (g.L == L && g.G == G && g.phi == phi) {
+    if (g.L == L && g.G == G && g.half == half && g.begin == begin && g.phi == phi) {
       *out = g.exec;
       return OCI_OK;
     }
-  if (c->step_graphs.size() >= 16) drop_step_graphs(c);
+  if (c->step_graphs.size() >= 32) drop_step_graphs(c);
   hipGraph_t g;
   OCI_CK(c, hipGraphCreate(&g, 0));
   hipGraphNode_t prev = nullptr;
@@ -766,17 +774,18 @@ static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out
     return e;
   };
   hipError_t e = hipSuccess;
+  void *bargs[] = {&c->sa};
+  if (begin) e = add(c->fn_begin, c->W_pv, c->lds_pv, bargs);
   for (int s = 0; s < G && e == hipSuccess; ++s) {
-    void *bargs[] = {&c->sa};
-    e = add(c->fn_begin, c->W_pv, c->lds_pv, bargs);
+    int h = (half + s) & 1;
     for (int i = 1; i <= L && e == hipSuccess; ++i) {
       int node = i, cb = 0;
-      void *args[] = {&c->sa, &node, &cb};
+      void *args[] = {&c->sa, &node, &cb, &h};
       e = add(c->fn_iter, c->W_it, c->lds_it, args);
     }
     if (e == hipSuccess) {
       int first = 1, last = L;
-      void *eargs[] = {&c->sa, &phi, &first, &last};
+      void *eargs[] = {&c->sa, &phi, &first, &last, &h};
       e = add(c->fn_end, c->W_ed, c->lds_ed, eargs);
     }
   }
@@ -789,7 +798,7 @@ static int step_graph(oci_ctx *c, int L, int G, double *phi, hipGraphExec_t *out
   (void)hipGraphDestroy(g);
   if (e != hipSuccess)
     return fail(c, OCI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  c->step_graphs.push_back({L, G, phi, exec});
+  c->step_graphs.push_back({L, G, half, begin, phi, exec});
   *out = exec;
   return OCI_OK;
 }
@@ -800,27 +809,30 @@ static int step_batch(oci_ctx *c, int want) {
   return std::max(1, std::min({want, c->max_iters, c->nbuf - 1}));
 }
 
-static int launch_end(oci_ctx *c, double *phi_dev, int first, int last) {
-  void *args[] = {&c->sa, &phi_dev, &first, &last};
+static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half) {
+  void *args[] = {&c->sa, &phi_dev, &first, &last, &half};
   OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
                             c->stream));
   return OCI_OK;
 }
 
 // Queue steps first .. first+count-1 (whole-step graphs of `batch` iteration
-// launches), then their records' copy to the host, between two events.
-static int enqueue_window(oci_ctx *c, int first, int count, int batch, double *phi_dev,
-                          hipEvent_t ev_start, hipEvent_t ev_end) {
+// launches; step `first` uses ring half `half`), then their records' copy to
+// the host, between two events.
+static int enqueue_window(oci_ctx *c, int first, int count, int batch, int half,
+                          double *phi_dev, hipEvent_t ev_start, hipEvent_t ev_end) {
   OCI_CK(c, hipEventRecord(ev_start, c->stream));
   int left = count;
   while (left > 0) {
     int G = kWindow;   // whole steps per graph: 8, 4, 2 or 1
     while (G > left) G >>= 1;
     hipGraphExec_t exec;
-    int rc = step_graph(c, batch, G, phi_dev, &exec);
+    int rc = step_graph(c, batch, G, half, c->gh_valid ? 0 : 1, phi_dev, &exec);
     if (rc) return rc;
+    c->gh_valid = true;
     OCI_CK(c, hipGraphLaunch(exec, c->stream));
     left -= G;
+    half ^= G & 1;
   }
   OCI_CK(c, hipMemcpyAsync(c->h_rec + first, c->d_rec + first, count * sizeof(StepRecord),
                            hipMemcpyDeviceToHost, c->stream));
@@ -834,7 +846,7 @@ static void complete_step(oci_ctx *c, int accepted) {
   c->have_flux = true;
 }
 
-// Resume step k after its queued launches left it undecided: further
+// Resume step k (ring half = its psi parity) after its queued launches left it undecided: further
 // iteration launches (1, 1, 2, 4, ... at a time) each followed by the end of
 // step, until the end decides.  `launched` = iteration launches so far.
 static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_launches,
@@ -847,11 +859,11 @@ static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_lau
     ++extra;
     const int count = std::min({extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2)),
                                 std::max(c->max_iters - launched, 1), c->nbuf - 1});
-    rc = launch_batch(c, false, launched, count);
+    rc = launch_batch(c, false, launched, count, c->parity);
     if (rc) return rc;
     launched += count;
     launches += count;
-    rc = launch_end(c, phi_dev, launched - count + 1, launched);
+    rc = launch_end(c, phi_dev, launched - count + 1, launched, c->parity);
     if (rc) return rc;
     rc = read_ctl(c);
     if (rc) return rc;
@@ -900,7 +912,8 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       c->window = std::min(kWindow, 2 * c->window);
       const int ev = next_ev;
       next_ev ^= 1;
-      rc = enqueue_window(c, q, count, batch, phi_dev, c->evW[ev][0], c->evW[ev][1]);
+      rc = enqueue_window(c, q, count, batch, c->parity ^ ((q - k) & 1), phi_dev,
+                          c->evW[ev][0], c->evW[ev][1]);
       if (rc) return rc;
       wins[nwin++] = Win{q, count, batch, ev};
       q += count;
@@ -909,7 +922,8 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       const int batch = step_batch(c, kColdBatch);
       const int ev = next_ev;
       next_ev ^= 1;
-      rc = enqueue_window(c, q, 1, batch, phi_dev, c->evW[ev][0], c->evW[ev][1]);
+      rc = enqueue_window(c, q, 1, batch, c->parity ^ ((q - k) & 1), phi_dev, c->evW[ev][0],
+                          c->evW[ev][1]);
       if (rc) return rc;
       wins[nwin++] = Win{q, 1, batch, ev};
       q += 1;
@@ -1004,6 +1018,7 @@ extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
   // graphs hold copies of the argument blocks: rebuild them only if those changed
   if (std::memcmp(&sa0, &c->sa, sizeof sa0) != 0 || std::memcmp(&si0, &c->si, sizeof si0) != 0)
     drop_graphs(c);
+  c->gh_valid = false;   // P and p change with the cross sections and dt
   return build_operators(c);
 }
 

@@ -55,8 +55,9 @@ struct StepCtl {
   int32_t fin_accepted;  // the step's outcome, written by the end-of-step kernel
   int32_t fin_status;    //   (read by later launches and the host only, never by
                          //   the launch that writes it)
-  int32_t open;          // index of the open step within the current solve
-                         //   (written by the step start, read by the end)
+  int32_t open;          // the open step (its index in the solve) and the buffer its
+  int32_t base_buf;      //   first iterate read: written by that iteration launch,
+                         //   read by the end of the step
   int32_t cur;           // index of the next step to open (written by the host at
                          //   the start of a solve and by the end of a decided step)
   int32_t psi_base;      // psi buffer of step 0 of the current solve (host)
@@ -68,10 +69,13 @@ struct StepCtl {
   double fin_e;
 };
 
-// Iterate l of a step (1-based) reads the outgoing fluxes and scalar flux of
-// iterate l-1 from buffer (l-1) % nbuf and writes buffer l % nbuf; the
-// step-start kernel moves the previous step's accepted iterate into buffer 0,
-// so no iteration launch needs device data to pick its buffers.
+// Iterate buffers: two rings of nbuf, one per step parity (half h holds
+// buffers h*nbuf .. h*nbuf+nbuf-1), then two for source iteration.  Iterate
+// l >= 1 of a step of half h writes ring slot l % nbuf of that half and reads
+// slot (l-1) % nbuf, except iterate 1, which reads the previous step's
+// accepted iterate (buffer fin_buf, in the other half or a source-iteration
+// buffer): a step never overwrites the iterate it started from, and no
+// iteration launch but the first needs device data to pick its buffers.
 
 // Per-step record of a queued solve.
 struct StepRecord {

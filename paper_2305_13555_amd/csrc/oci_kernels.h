@@ -16,6 +16,13 @@ __host__ __device__ inline uint32_t pack_tile(int region, int c0, int nc) {
   return (uint32_t)c0 | ((uint32_t)(nc - 1) << kArgTileCellBits) | ((uint32_t)region << 22);
 }
 
+// The end of step keeps psi_{k+1/2} of its tile in LDS for the next step's
+// gh when three tiles of rows (pitch P doubles) and two halo rows fit in the
+// 160 KiB of LDS a work-group can have; otherwise it reads them back.
+constexpr int kLdsBytes = 160 * 1024;
+__host__ __device__ constexpr bool end_keeps_psi(int P) {
+  return (3 * kTileCells + 2) * P * 8 <= kLdsBytes;
+}
 
 struct StepArgs {
   const TileDev *tiles;    // [ntiles] in work-group order (one work-group per tile)
@@ -38,10 +45,10 @@ struct StepArgs {
   const double *c_ed;      // e
   size_t c_ed_stride;
   double *gh;              // [J][Mt*16]
-  int nbuf;                // iterate buffers: iterate l lives in buffer l % nbuf
-  double *outb;            // [nbuf][J+2][2N]
+  int nbuf;                // ring slots per half (iterate l of a step in slot l % nbuf)
+  double *outb;            // [2*nbuf+2][J+2][2N]
   size_t out_stride;
-  double *phib;            // [nbuf][J][4]
+  double *phib;            // [2*nbuf+2][J][4]
   size_t phi_stride;
   double *psi0, *psi1;     // [J][2N]
   double *phi_res;         // [J][4]
@@ -63,10 +70,11 @@ struct SiArgs {
   const int *cell_region;   // [J]
   const double *mu, *w;
   const double *ainv;       // [R][N][16]
-  double *out0, *out1;      // [J+2][2N] iterate buffers 0 and 1, ghost rows hold incident values
-  double *phi0, *phi1;      // [J][4]
+  double *out0, *out1;      // [J+2][2N] iterate buffers own_buf and own_buf+1 (ghost rows
+  double *phi0, *phi1;      //   hold incident values); [J][4]
+  int own_buf;
   double *outb;             // all iterate buffers (as StepArgs): the step start moves the
-  size_t out_stride;        //   previous step's last iterate from buffer fin_buf to 0
+  size_t out_stride;        //   previous step's last iterate from buffer fin_buf to own_buf
   double *phib;
   size_t phi_stride;
   double *psi0, *psi1;      // [J][2N]
@@ -93,10 +101,11 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
 // ARGT: tile descriptors in the kernel arguments; VEC: 16-byte operand
 // reads (N % 8 == 0); NF > 0: built for N = NF angles, 0: any N.
 template <int CH, bool ARGT, bool VEC, int NF> __global__ void k_step_begin(StepArgs a);
+// half: the ring half of the step's iterates
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ void k_oci_iterate(StepArgs a, int node, int cb);
+__global__ void k_oci_iterate(StepArgs a, int node, int cb, int half);
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ void k_step_end(StepArgs a, double *phi_out, int first, int last);
+__global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half);
 // si.hip
 __global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,
                             double *ainv);

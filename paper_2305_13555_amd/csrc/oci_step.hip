@@ -248,32 +248,32 @@ __device__ __forceinline__ TileDev blk_desc(const StepArgs &a) {
   return t;
 }
 
-__device__ __forceinline__ double *out_buf(const StepArgs &a, int l) {
-  return a.outb + (size_t)(l % a.nbuf) * a.out_stride;
+// ring buffer of iterate l >= 1 of a step whose iterates use ring half `half`
+__device__ __forceinline__ int ring_buf(const StepArgs &a, int l, int half) {
+  return half * a.nbuf + l % a.nbuf;
 }
-__device__ __forceinline__ double *phi_buf(const StepArgs &a, int l) {
-  return a.phib + (size_t)(l % a.nbuf) * a.phi_stride;
+__device__ __forceinline__ double *out_at(const StepArgs &a, int b) {
+  return a.outb + (size_t)b * a.out_stride;
+}
+__device__ __forceinline__ double *phi_at(const StepArgs &a, int b) {
+  return a.phib + (size_t)b * a.phi_stride;
 }
 
-// gh rows of a tile: gh_j = P_r psi_{k-1/2,j} + p_r.  P is packed k-major,
-// so a lane's operands are consecutive in its cell's psi row.
+// gh rows of a tile, gh_j = P_r psi_j + p_r, from the tile's psi rows in LDS
+// (pitch P, cell c in row c).  P is packed k-major, so a lane's operands are
+// consecutive in its cell's row.  f0: this wave's first fragments of P.
 template <int CH, bool VEC, int NF>
-__device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const double *psi_prev,
-                                  double *lds) {
+__device__ inline void gh_gemm(const StepArgs &a, const TileDev &t, const double *rows,
+                               const double (&f0)[CH]) {
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
   const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
-  const int W = NF ? (Mt < 4 ? Mt : 4) : (int)(blockDim.x >> 6);
+  const int W = (int)(blockDim.x >> 6);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
   const double *F = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane;
   const double *cp = a.c_pv + (size_t)t.region * a.c_pv_stride;
   const int ghp = Mt * 16;
-  double f0[CH];
-  if (wave < Mt) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
-  const RowBlock blk[1] = {own_block(lds, psi_prev, t, K)};
-  copy_blocks_to_lds(blk, 1, K, P);
-  __syncthreads();
-  const double *ap = lds + col * P + kq * KS;
+  const double *ap = rows + col * P + kq * KS;
   for (int rt = wave; rt < Mt; rt += W) {
     const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)rt * KS * 64, KS, rt == wave, f0, ap);
     const int row = rt * 16 + col;
@@ -284,6 +284,29 @@ __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const dou
       if (cl < t.nc) a.gh[(size_t)(t.c0 + cl) * ghp + row] = acc[i] + cv;
     }
   }
+}
+
+// The first fragments of P for this wave's first row tile.
+template <int CH, int NF>
+__device__ __forceinline__ void gh_frags(const StepArgs &a, const TileDev &t, double (&f0)[CH]) {
+  const int N = NF ? NF : a.N, KS = (2 * N) / 4;
+  const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double *F = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane;
+  if (wave < Mt) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
+}
+
+// gh of a tile from psi_{k-1/2} in global memory.
+template <int CH, bool VEC, int NF>
+__device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const double *psi_prev,
+                                  double *lds) {
+  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
+  double f0[CH];
+  gh_frags<CH, NF>(a, t, f0);
+  const RowBlock blk[1] = {own_block(lds, psi_prev, t, K)};
+  copy_blocks_to_lds(blk, 1, K, P);
+  __syncthreads();
+  gh_gemm<CH, VEC, NF>(a, t, lds, f0);
 }
 
 // One OCI iteration of a tile, in two phases: iterate_prefetch issues every
@@ -460,6 +483,8 @@ template <int CH, bool VEC, int NF>
 __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const double *src,
                                 const double *psi_prev, double *psi_next, const double *phi_acc,
                                 double *phi_out, double *lds) {
+  double fg[CH];   // P fragments for the next step's gh, issued early
+  gh_frags<CH, NF>(a, t, fg);
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = N;
   const int Met = NF ? (2 * NF + 15) / 16 : a.Met;
   const int W = NF ? (Met < 4 ? Met : 4) : (int)(blockDim.x >> 6);
@@ -468,6 +493,8 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
   const double *F = a.frag_ed + (size_t)t.region * a.frag_ed_stride + lane;
   const double *ce = a.c_ed + (size_t)t.region * a.c_ed_stride;
   double *ldp = lds + (kTileCells + 2) * P;
+  const bool keep = end_keeps_psi(P);
+  double *ldn = keep ? ldp + kTileCells * P : lds;   // psi_{k+1/2} of the tile's cells
   double f0[CH];
   if (wave < Met) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
   for (int i = threadIdx.x; i < t.nc * 4; i += blockDim.x) {
@@ -490,64 +517,62 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int cl = kq + 4 * i;
-        if (cl < t.nc) psi_next[(size_t)(t.c0 + cl) * K + row] = acc[i] + cv;
+        const double v = acc[i] + cv;
+        if (keep) ldn[cl * P + row] = v;
+        if (cl < t.nc) psi_next[(size_t)(t.c0 + cl) * K + row] = v;
       }
     }
   }
+  // the next step's gh from psi_{k+1/2}, so that a queued step that
+  // follows needs no step start
+  __syncthreads();
+  if (!keep) {   // this work-group's own psi_{k+1/2} rows, back over the halo rows
+    const RowBlock blk1[1] = {own_block(ldn, psi_next, t, K)};
+    copy_blocks_to_lds(blk1, 1, K, P);
+    __syncthreads();
+  }
+  gh_gemm<CH, VEC, NF>(a, t, ldn, fg);
 }
 
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
 
-// Start of step `cur` of the current solve: gh for every tile, and the
-// previous step's accepted iterate moved from buffer fin_buf into buffer 0
-// (each work-group moves its own rows).  The first thread of work-group 0
-// opens the step in the control block without touching the fields the other
-// work-groups read here.  Does nothing while a queued solve is stalled.
+// Start of step `cur` of the current solve: gh for every tile from
+// psi_{k-1/2}.  Needed only where no end of step has computed it (the first
+// step of a queue).  Does nothing while a queued solve is stalled.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
   extern __shared__ double lds[];
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
   const int parity = c.psi_base ^ (c.cur & 1);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    StepCtl *ct = a.ctl;
-    ct->total0 = c.total0 + c.fin_accepted;
-    ct->status = kRunning;
-    ct->step_parity = parity;
-    ct->open = c.cur;
-    ct->e_last = -1.0;
-    ct->e_prev = -1.0;
-  }
   const TileDev t = blk_desc<ARGT>(a);
-  if (c.fin_buf != 0) {
-    const int K = 2 * a.N;
-    const double2 *so = reinterpret_cast<const double2 *>(
-        a.outb + (size_t)c.fin_buf * a.out_stride + (size_t)(t.c0 + 1) * K);
-    double2 *dout = reinterpret_cast<double2 *>(a.outb + (size_t)(t.c0 + 1) * K);
-    for (int i = threadIdx.x; i < t.nc * K / 2; i += blockDim.x) dout[i] = so[i];
-    const double *sp = a.phib + (size_t)c.fin_buf * a.phi_stride;
-    for (int i = threadIdx.x; i < t.nc * 4; i += blockDim.x)
-      a.phib[(size_t)t.c0 * 4 + i] = sp[(size_t)t.c0 * 4 + i];
-  }
   tile_begin<CH, VEC, NF>(a, t, parity ? a.psi1 : a.psi0, lds);
 }
 
 // Iterate l = cb + node of the open step: always computed (the step's
 // decision is taken by the end-of-step kernel from the residual of every
-// iterate).  Work-group 0 also reduces the residual records iterate l-1 left
-// and stores its e in dec, off the other work-groups' path.  Nothing is
-// stored while a queued solve is stalled.
+// iterate).  Iterate 1 starts from the previous step's accepted iterate
+// (buffer fin_buf) and opens the step: its first thread records the step
+// index and that buffer for the end of step.  Work-group 0 also reduces the
+// residual records iterate l-1 left and stores its e in dec, off the other
+// work-groups' path.  Nothing is stored while a queued solve is stalled.
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb) {
+__global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64];
   const int l = cb + node;
-  const double *src = out_buf(a, l - 1);
-  double *dst = out_buf(a, l);
-  const double *phi_old = phi_buf(a, l - 1);
-  double *phi_new = phi_buf(a, l);
+  // iterate 0 of the step: the previous step's accepted iterate
+  int b0 = ring_buf(a, l - 1, half), cur = 0;
+  if (l == 1) {
+    b0 = a.ctl->fin_buf;
+    cur = a.ctl->cur;
+  }
+  const double *src = out_at(a, b0);
+  double *dst = out_at(a, ring_buf(a, l, half));
+  const double *phi_old = phi_at(a, b0);
+  double *phi_new = phi_at(a, ring_buf(a, l, half));
   const int ti = blockIdx.x;   // the tile's residual record
   const TileDev t = blk_desc<ARGT>(a);
   IterPrefetch<CH> pf;
@@ -555,6 +580,10 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   const int stalled = a.ctl->stalled;
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   const size_t slot = (size_t)a.ntiles;
+  if (l == 1 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
+    a.ctl->open = cur;
+    a.ctl->base_buf = b0;
+  }
   if (blockIdx.x == 0 && l >= 2) {
     RecRegs r1;
     rec_issue(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles);
@@ -577,7 +606,7 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
 // decided step advances the solve's step counter.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
-                                                  int last) {
+                                                  int last, int half) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves];
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
@@ -617,7 +646,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
       a.rec[step].e_last = e_acc;
     }
     if (decided) {
-      ct->fin_buf = L % a.nbuf;
+      ct->fin_buf = ring_buf(a, L, half);
       ct->cur = step + 1;
     } else {
       ct->stalled = 1;
@@ -625,83 +654,86 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
     }
   }
   if (!decided) return;
-  const int parity = c.step_parity;
+  const int parity = c.psi_base ^ (step & 1);
   const TileDev t = blk_desc<ARGT>(a);
-  tile_end<CH, VEC, NF>(a, t, out_buf(a, L - 1), parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
-               phi_buf(a, L), phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
+  // iterate L was computed from iterate L-1 (iterate 0: the step's start)
+  const double *src = out_at(a, L == 1 ? c.base_buf : ring_buf(a, L - 1, half));
+  tile_end<CH, VEC, NF>(a, t, src, parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
+                        phi_at(a, ring_buf(a, L, half)),
+                        phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
 }
 
 template __global__ void k_step_begin<4, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int);
-template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<4, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<8, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int);
-template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<8, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int);
-template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<4, false, true, 8>(StepArgs);
-template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int);
-template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int, int);
+template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<8, false, true, 16>(StepArgs);
-template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int);
-template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int, int);
+template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, false, true, 32>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int);
-template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, false, true, 64>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int);
-template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, false, true, 128>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int);
-template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, false, true, 256>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int);
-template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<4, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int);
-template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<4, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<8, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int);
-template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<8, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int);
-template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int);
-template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<4, true, true, 8>(StepArgs);
-template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int);
-template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int, int);
+template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<8, true, true, 16>(StepArgs);
-template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int);
-template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int, int);
+template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, true, true, 32>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int);
-template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, true, true, 64>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int);
-template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, true, true, 128>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int);
-template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int, int);
 template __global__ void k_step_begin<16, true, true, 256>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int);
-template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int);
+template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int, int);
+template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int, int);
 
 }  // namespace ocik

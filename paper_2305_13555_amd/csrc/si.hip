@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_si_decide(SiArgs a, int node, int cb) {
 }
 
 // Start of a source-iteration step: the previous step's accepted iterate
-// moved into buffer 0 from buffer fin_buf, and the step opened (the first
+// moved into buffer own_buf from buffer fin_buf, and the step opened (the first
 // thread leaves the fields the other work-groups read here alone).
 __global__ void k_si_begin(SiArgs a, int parity) {
   const StepCtl c = *a.ctl;
@@ -358,7 +358,7 @@ __global__ void k_si_begin(SiArgs a, int parity) {
     ct->e_last = -1.0;
     ct->e_prev = -1.0;
   }
-  if (c.fin_buf == 0) return;
+  if (c.fin_buf == a.own_buf) return;
   const int K = 2 * a.N;
   const size_t nout = (size_t)a.J * K, nphi = (size_t)a.J * 4;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -380,7 +380,7 @@ __global__ void k_si_end(SiArgs a) {
     ct->fin_accepted = c.accepted;
     ct->fin_status = c.status;
     ct->fin_e = c.e_last;
-    if (c.status == kConverged || c.status == kIterLimit) ct->fin_buf = c.accepted & 1;
+    if (c.status == kConverged || c.status == kIterLimit) ct->fin_buf = a.own_buf + (c.accepted & 1);
   }
   if (c.stalled || c.status == kRunning || c.status == kNonFinite) return;
   if ((c.accepted & 1) && blockIdx.x == 0)   // the accepted iterate's lag into buffer 0
