@@ -617,10 +617,19 @@ static int clear_stall(oci_ctx *c) {
   return OCI_OK;
 }
 
+// Launches in the extra-th batch after a step's first: 1, 1, 2, 4, ... up to
+// kMaxBatch (the shift is bounded: a slow step can need thousands of batches).
+static int resume_count(int extra) {
+  if (extra <= 2) return 1;
+  return extra - 2 >= 30 ? kMaxBatch : std::min(kMaxBatch, 1 << (extra - 2));
+}
+
 // A later batch of a step: `count` launches after iterate cb (one by one:
 // only needed when the first batch was too short).  For SI each iteration
 // also decides.
 static int launch_batch(oci_ctx *c, bool si, int cb, int count, int half = 0) {
+  if (cb < 0 || count < 1 || count > kMaxBatch)
+    return fail(c, OCI_EDEVICE, "internal: iteration batch out of range");
   for (int i = 1; i <= count; ++i) {
     int node = i;
     if (!si) {
@@ -684,7 +693,7 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
       OCI_CK(c, hipGraphLaunch(c->si_graph[count], c->stream));
     } else {
       ++extra;
-      count = extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2));
+      count = resume_count(extra);
       rc = launch_batch(c, true, launched, count);
       if (rc) return rc;
     }
@@ -810,6 +819,9 @@ static int step_batch(oci_ctx *c, int want) {
 }
 
 static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half) {
+  // the end reads the records of iterates first .. last, one ring of them
+  if (first < 1 || last < first || last - first >= c->nbuf - 1)
+    return fail(c, OCI_EDEVICE, "internal: end of step over an iterate range out of bounds");
   void *args[] = {&c->sa, &phi_dev, &first, &last, &half};
   OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
                             c->stream));
@@ -857,7 +869,7 @@ static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_lau
     int rc = clear_stall(c);
     if (rc) return rc;
     ++extra;
-    const int count = std::min({extra <= 2 ? 1 : std::min(kMaxBatch, 1 << (extra - 2)),
+    const int count = std::min({resume_count(extra),
                                 std::max(c->max_iters - launched, 1), c->nbuf - 1});
     rc = launch_batch(c, false, launched, count, c->parity);
     if (rc) return rc;
