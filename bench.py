@@ -49,10 +49,11 @@ def roofline_launch_seconds(oci, prob, stream, steps=5):
     """Per-launch time of the iteration kernel on the workload's cells, regions and
     angles, with v = inf and tol = 0 so that every launch does the full work
     (the kernel's work does not depend on the values).  Steps of 32 and of 16
-    iterates each run as one replayed graph (step start,
-    the launches, end of step), timed with HIP events on the library's
-    stream; the per-launch time is the difference of the median step times
-    over the extra launches, which removes the step start and end."""
+    iterates each run as one replayed graph (the launches and the end of
+    step), timed with HIP events on the library's stream; the per-launch time
+    is the difference of the median step times over the extra launches, which
+    removes the end of step.  It is launch to launch: the kernel's duration
+    plus the dispatch gap between two graph nodes."""
     import dataclasses
     roof = dataclasses.replace(prob, speed=float("inf"), name=prob.name + ", v = inf")
     med = {}
