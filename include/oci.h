@@ -72,7 +72,11 @@ enum {
 
 enum { OCI_BC_VACUUM = 0, OCI_BC_REFLECT = 1, OCI_BC_INCIDENT = 2 };
 
-enum { OCI_PREC_FP64 = 0 };
+/* OCI_PREC_FP64: every iterate in FP64.  OCI_PREC_FP32: mixed precision,
+ * FP64 defect correction with FP32 inner iterations (see oci_setup); the
+ * accepted iterate of every step is still an FP64 application of the
+ * operator, judged by the same stopping rule. */
+enum { OCI_PREC_FP64 = 0, OCI_PREC_FP32 = 1 };
 
 /* flags */
 #define OCI_FLAG_STRICT 1u /* add the a-posteriori error bound to the stopping rule */
@@ -102,12 +106,12 @@ typedef struct {
   const double *psi0;        /* [J][N][2] initial psi on the L and R half cells, or NULL = 0 */
   double tol;                /* stopping tolerance, >= 0 */
   int32_t max_iters;         /* >= 1 iterations per step */
-  int32_t precision;         /* OCI_PREC_FP64 */
+  int32_t precision;         /* OCI_PREC_FP64 or OCI_PREC_FP32 (not with OCI_FLAG_STRICT) */
   uint32_t flags;            /* OCI_FLAG_* */
 } oci_problem;
 
 typedef struct {
-  int32_t iterations;  /* iterations done in the step */
+  int32_t iterations;  /* iterations done in the step (OCI_PREC_FP32: FP64 iterates) */
   int32_t status;      /* OCI_OK, OCI_NOT_CONVERGED or OCI_ENONFINITE */
   double residual;     /* e of the accepted (or last) iterate; -1 if undefined */
   double ms;           /* stream time of the step, milliseconds; steps queued
@@ -117,7 +121,8 @@ typedef struct {
                           queued launches left it undecided, the time of the
                           resumed part, otherwise equal to ms */
   int32_t launches;    /* iteration kernels launched for the step (>=
-                          iterations; launches after the decision exit at once) */
+                          iterations; launches after the decision exit at once;
+                          OCI_PREC_FP32: FP64 and FP32 iteration launches) */
   int32_t pad;
 } oci_step_info;
 
@@ -127,6 +132,15 @@ typedef struct {
  * one factorisation per region because all cells of a region share it), and
  * forms the operators applied each iteration.  hip_stream is a hipStream_t
  * (NULL = the null stream).  On success *out owns all device memory.
+ * With precision OCI_PREC_FP32 a step is solved by defect correction: each
+ * FP64 iterate x' = T(y) (one OCI iteration of the current point y) gives the
+ * defect d = x' - y; the correction c = G c + d (the same block-Jacobi
+ * iteration without its constant part, Sec. "One-Cell Inversion (OCI)") is
+ * iterated in FP32 and y + c is the next point.  The first FP64 iterate
+ * starts from the previous step's accepted one; a step's FP64 iterates are
+ * judged by the OCI stopping rule (Sec. "One-Cell Inversion (OCI)": relative
+ * change of the scalar flux), so the result is an FP64 iterate.  max_iters then bounds
+ * the FP64 iterates.
  * Errors: OCI_EINVAL (bad problem, out == NULL), OCI_ENOMEM, OCI_EDEVICE. */
 int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out);
 

@@ -33,6 +33,7 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr int kMaxBatch = 64;   // iteration launches per replayed batch
+constexpr int kMaxInner = 64;   // FP32 inner iterations per correction (mixed precision)
 
 }  // namespace
 
@@ -74,7 +75,7 @@ struct oci_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evA = nullptr, evB = nullptr;
   hipEvent_t evW[2][2] = {};                 // start / end of the windows in flight
   struct StepGraph {
-    int L, G, half, begin;
+    int L, G, half, begin, m;
     double *phi;
     hipGraphExec_t exec;
   };
@@ -85,9 +86,15 @@ struct oci_ctx {
   bool quad_override = false;
   double *ws_M = nullptr, *ws_X = nullptr;   // setup workspace, kept for oci_refactor
   int *d_bad = nullptr;
+  // mixed precision: FP64 iterates every other launch (rstep 2) with FP32
+  // correction solves of m_inner iterations between them
+  bool mixed = false;
+  int rstep = 1, m_inner = 2;
+  float *d_fi32 = nullptr, *d_dlt = nullptr, *d_dphi32 = nullptr;
+  size_t lds_in = 0;
   // kernels for the chosen operator batch width CH
   int CH = 16;
-  void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr;
+  void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr, *fn_inner = nullptr;
   std::string err;
   StepArgs sa{};
   SiArgs si{};
@@ -162,7 +169,10 @@ static int validate(const oci_problem *p, std::string *why) {
   }
   if (!(p->tol >= 0.0)) return bad("tol must be >= 0");
   if (p->max_iters < 1) return bad("max_iters must be >= 1");
-  if (p->precision != OCI_PREC_FP64) return bad("only OCI_PREC_FP64 is available");
+  if (p->precision != OCI_PREC_FP64 && p->precision != OCI_PREC_FP32)
+    return bad("precision must be OCI_PREC_FP64 or OCI_PREC_FP32");
+  if (p->precision == OCI_PREC_FP32 && (p->flags & OCI_FLAG_STRICT))
+    return bad("OCI_FLAG_STRICT needs OCI_PREC_FP64");
   if (p->flags & ~OCI_FLAG_STRICT) return bad("unknown flags");
   if (p->psi0) {
     for (long long i = 0; i < J * N * 2; ++i)
@@ -270,6 +280,9 @@ static int build_operators(oci_ctx *c) {
   // end-of-step operator E: rows [2N+4, 4N+4), columns [0, 4N)
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N + 4, K, 0,
                      2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride, 1);
+  if (c->mixed)   // G for the FP32 inner iterations, same packing
+    hipLaunchKernelGGL(k_to_f32, dim3(256), dim3(256), 0, c->stream, (const double *)c->d_fi,
+                       c->d_fi32, (size_t)R * c->fi_stride);
   hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
                      c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
   OCI_CK(c, hipGetLastError());
@@ -309,6 +322,8 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->tol = p->tol;
   c->max_iters = p->max_iters;
   c->strict = (p->flags & OCI_FLAG_STRICT) ? 1 : 0;
+  c->mixed = p->precision == OCI_PREC_FP32;
+  c->rstep = c->mixed ? 2 : 1;
   c->a = std::isinf(p->speed) ? 0.0 : 1.0 / (p->speed * p->dt);
   c->mu.resize(N);
   c->w.resize(N);
@@ -431,6 +446,15 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_segmap, (size_t)(N / 2) * c->si_segs * 2));
   OCI_TRY(dalloc(c, &c->d_si_partial, (size_t)3 * c->si_blocks * 4));
   OCI_TRY(dalloc(c, &c->d_ctl, 1));
+  if (c->mixed) {
+    OCI_TRY(dalloc(c, &c->d_fi32, (size_t)R * c->fi_stride));
+    OCI_TRY(dalloc(c, &c->d_dlt, (size_t)3 * c->out_stride));
+    OCI_TRY(dalloc(c, &c->d_dphi32, (size_t)J * 4));
+    // the correction's ghost rows stay zero (boundary values are constants)
+    if (hipMemsetAsync(c->d_dlt, 0, (size_t)3 * c->out_stride * sizeof(float), c->stream) !=
+        hipSuccess)
+      return cleanup(fail(c, OCI_EDEVICE, "hipMemsetAsync failed"));
+  }
   {
     void *h = nullptr;
     if (hipHostMalloc(&h, sizeof(StepCtl), hipHostMallocDefault) != hipSuccess)
@@ -497,9 +521,14 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.Mto = c->Mto;
   s.bcl = c->bcl;
   s.bcr = c->bcr;
-  s.max_iters = c->max_iters;
+  // mixed precision: the FP64 iterates are 1, 3, 5, ...; max_iters of them
+  s.max_iters = c->mixed ? 2 * c->max_iters - 1 : c->max_iters;
   s.strict = c->strict;
   s.tol = c->tol;
+  s.frag_it32 = c->d_fi32;
+  s.dlt = c->d_dlt;
+  s.dlt_stride = c->out_stride;
+  s.dphi32 = c->d_dphi32;
   s.frag_it = c->d_fi;
   s.frag_it_stride = c->fi_stride;
   s.frag_pv = c->d_fp;
@@ -590,6 +619,8 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   }
 #undef OCI_KERNEL
 #undef OCI_PICK
+  c->fn_inner = s.tiles_in_args ? (void *)k_oci_inner<true> : (void *)k_oci_inner<false>;
+  c->lds_in = (size_t)(kTileCells + 2) * (K + 4) * sizeof(float);
   // kernels with more than 64 KiB of dynamic LDS must say so
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it));
@@ -633,7 +664,8 @@ static int launch_batch(oci_ctx *c, bool si, int cb, int count, int half = 0) {
   for (int i = 1; i <= count; ++i) {
     int node = i;
     if (!si) {
-      void *args[] = {&c->sa, &node, &cb, &half};
+      int rstep = 1;
+      void *args[] = {&c->sa, &node, &cb, &half, &rstep};
       OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), args, c->lds_it,
                                 c->stream));
     } else {
@@ -733,6 +765,7 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
 // ---------------------------------------------------------------------------
 constexpr int kWindow = 8;   // steps per queued window (one graph of whole steps)
 constexpr int kColdBatch = 8;  // launches of a step with no previous step to go by
+constexpr int kColdOuter = 3;  // mixed precision: FP64 iterates of such a step
 
 // Per-step records of a solve; the step graphs hold the device pointer, so
 // growing the buffer drops them.
@@ -758,10 +791,16 @@ static int grow_records(oci_ctx *c, int n) {
 // step L iteration launches and the end of step (which writes phi_out[step]
 // when phi is given).  Every argument is static: the step index and psi
 // buffer come from the control block, the ring half alternates from `half`.
+//
+// Mixed precision: L is the number of FP64 iterates per step (1, 3, .., 2L-1);
+// before each FP64 iterate after the first, m_inner FP32 inner iterations,
+// the last of which forms the even iterate the FP64 one starts from.
 static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi,
                       hipGraphExec_t *out) {
+  const int m = c->mixed ? c->m_inner : 0;
   for (auto &g : c->step_graphs)
-    if (g.L == L && g.G == G && g.half == half && g.begin == begin && g.phi == phi) {
+    if (g.L == L && g.G == G && g.half == half && g.begin == begin && g.m == m &&
+        g.phi == phi) {
       *out = g.exec;
       return OCI_OK;
     }
@@ -785,16 +824,22 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   hipError_t e = hipSuccess;
   void *bargs[] = {&c->sa};
   if (begin) e = add(c->fn_begin, c->W_pv, c->lds_pv, bargs);
+  int rstep = c->rstep;
   for (int s = 0; s < G && e == hipSuccess; ++s) {
     int h = (half + s) & 1;
-    for (int i = 1; i <= L && e == hipSuccess; ++i) {
-      int node = i, cb = 0;
-      void *args[] = {&c->sa, &node, &cb, &h};
-      e = add(c->fn_iter, c->W_it, c->lds_it, args);
+    for (int o = 1; o <= L && e == hipSuccess; ++o) {
+      for (int i = 1; o > 1 && i <= m && e == hipSuccess; ++i) {
+        int ii = i, ly = i == m ? 2 * (o - 1) : 0;
+        void *iargs[] = {&c->sa, &ii, &ly, &h};
+        e = add(c->fn_inner, c->W_it, c->lds_in, iargs);
+      }
+      int node = c->mixed ? 2 * o - 1 : o, cb = 0;
+      void *args[] = {&c->sa, &node, &cb, &h, &rstep};
+      if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args);
     }
     if (e == hipSuccess) {
-      int first = 1, last = L;
-      void *eargs[] = {&c->sa, &phi, &first, &last, &h};
+      int first = 1, last = c->mixed ? 2 * L - 1 : L;
+      void *eargs[] = {&c->sa, &phi, &first, &last, &h, &rstep};
       e = add(c->fn_end, c->W_ed, c->lds_ed, eargs);
     }
   }
@@ -807,22 +852,50 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   (void)hipGraphDestroy(g);
   if (e != hipSuccess)
     return fail(c, OCI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  c->step_graphs.push_back({L, G, half, begin, phi, exec});
+  c->step_graphs.push_back({L, G, half, begin, m, phi, exec});
   *out = exec;
   return OCI_OK;
 }
 
 // Iterates queued for a step whose count is expected to be `want`: at most
 // max_iters, within the iterate buffers.
+// (Mixed precision: FP64 iterates, 2*batch-1 iterate buffers.)
 static int step_batch(oci_ctx *c, int want) {
-  return std::max(1, std::min({want, c->max_iters, c->nbuf - 1}));
+  const int cap = c->mixed ? c->nbuf / 2 : c->nbuf - 1;
+  return std::max(1, std::min({want, c->max_iters, cap}));
+}
+
+// Iterations reported for an accepted iterate index (mixed: FP64 iterates) and
+// the iteration launches of a queued step.
+static int step_iterations(const oci_ctx *c, int accepted) {
+  return c->mixed ? (accepted + 1) / 2 : accepted;
+}
+static int step_launches(const oci_ctx *c, int batch) {
+  return c->mixed ? batch + (batch - 1) * c->m_inner : batch;
+}
+
+// Mixed precision: one more correction after FP64 iterate lprev (inner
+// iterations, the last forming iterate lprev+1) and FP64 iterate lprev+2.
+static int launch_outer(oci_ctx *c, int lprev, int half) {
+  for (int i = 1; i <= c->m_inner; ++i) {
+    int ii = i, ly = i == c->m_inner ? lprev + 1 : 0;
+    void *iargs[] = {&c->sa, &ii, &ly, &half};
+    OCI_CK(c, hipLaunchKernel(c->fn_inner, dim3(c->grid), dim3(64 * c->W_it), iargs, c->lds_in,
+                              c->stream));
+  }
+  int node = lprev + 2, cb = 0, rstep = 2;
+  void *args[] = {&c->sa, &node, &cb, &half, &rstep};
+  OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), args, c->lds_it,
+                            c->stream));
+  return OCI_OK;
 }
 
 static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half) {
   // the end reads the records of iterates first .. last, one ring of them
   if (first < 1 || last < first || last - first >= c->nbuf - 1)
     return fail(c, OCI_EDEVICE, "internal: end of step over an iterate range out of bounds");
-  void *args[] = {&c->sa, &phi_dev, &first, &last, &half};
+  int rstep = c->rstep;
+  void *args[] = {&c->sa, &phi_dev, &first, &last, &half, &rstep};
   OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
                             c->stream));
   return OCI_OK;
@@ -864,23 +937,31 @@ static void complete_step(oci_ctx *c, int accepted) {
 static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_launches,
                        float *ms) {
   OCI_CK(c, hipEventRecord(c->ev0, c->stream));
-  int extra = 0, launches = launched;
+  int extra = 0, launches = c->mixed ? step_launches(c, (launched + 1) / 2) : launched;
   for (;;) {
     int rc = clear_stall(c);
     if (rc) return rc;
     ++extra;
-    const int count = std::min({resume_count(extra),
-                                std::max(c->max_iters - launched, 1), c->nbuf - 1});
-    rc = launch_batch(c, false, launched, count, c->parity);
-    if (rc) return rc;
-    launched += count;
-    launches += count;
-    rc = launch_end(c, phi_dev, launched - count + 1, launched, c->parity);
+    if (c->mixed) {
+      rc = launch_outer(c, launched, c->parity);
+      if (rc) return rc;
+      launched += 2;
+      launches += c->m_inner + 1;
+      rc = launch_end(c, phi_dev, launched, launched, c->parity);
+    } else {
+      const int count = std::min({resume_count(extra),
+                                  std::max(c->max_iters - launched, 1), c->nbuf - 1});
+      rc = launch_batch(c, false, launched, count, c->parity);
+      if (rc) return rc;
+      launched += count;
+      launches += count;
+      rc = launch_end(c, phi_dev, launched - count + 1, launched, c->parity);
+    }
     if (rc) return rc;
     rc = read_ctl(c);
     if (rc) return rc;
     if (!c->h_ctl->stalled || c->h_ctl->fin_status == kNonFinite) break;
-    if (launched > c->max_iters + 1)
+    if (launched > c->sa.max_iters + 1)
       return fail(c, OCI_EDEVICE, "the step control block did not reach a decision");
   }
   OCI_CK(c, hipEventRecord(c->ev1, c->stream));
@@ -931,7 +1012,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       q += count;
     }
     if (nwin == 0) {
-      const int batch = step_batch(c, kColdBatch);
+      const int batch = step_batch(c, c->mixed ? kColdOuter : kColdBatch);
       const int ev = next_ev;
       next_ev ^= 1;
       rc = enqueue_window(c, q, 1, batch, c->parity ^ ((q - k) & 1), phi_dev, c->evW[ev][0],
@@ -955,13 +1036,18 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       if (status == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
       // the window's stream time split evenly over its steps
       const double share = ms / w.count;
-      fill_info(infos ? &infos[s] : nullptr, r.accepted, status, r.e_last, share, share,
-                w.batch);
+      fill_info(infos ? &infos[s] : nullptr, step_iterations(c, r.accepted), status, r.e_last,
+                share, share, step_launches(c, w.batch));
       complete_step(c, r.accepted);
-      hint = std::max(hint, r.accepted);
+      hint = std::max(hint, step_iterations(c, r.accepted));
     }
     k = done;
     if (ndone > 0) c->batch_hint = std::max(hint, 1);
+    // mixed precision: a correction that needs more FP64 iterates than a
+    // converged one (three at tol ~ 1e-10) gets more inner iterations
+    if (c->mixed && hint >= 4 && c->m_inner < kMaxInner) {
+      c->m_inner = std::min(kMaxInner, 2 * c->m_inner);
+    }
     if (ndone == w.count) {
       wins[0] = wins[1];
       --nwin;
@@ -977,17 +1063,19 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       return abandon_step(c, infos ? &infos[k] : nullptr, c->h_ctl->fin_accepted);
     int launches = 0;
     float rms = 0.0f;
-    rc = resume_step(c, w.batch, phi_dev, &launches, &rms);
+    rc = resume_step(c, c->mixed ? 2 * w.batch - 1 : w.batch, phi_dev, &launches, &rms);
     if (rc) return rc;
     if (c->h_ctl->fin_status == kNonFinite)
       return abandon_step(c, infos ? &infos[k] : nullptr, c->h_ctl->fin_accepted);
     const StepCtl st = *c->h_ctl;
     const int status = st.fin_status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
     if (status == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
-    fill_info(infos ? &infos[k] : nullptr, st.fin_accepted, status, st.fin_e,
+    fill_info(infos ? &infos[k] : nullptr, step_iterations(c, st.fin_accepted), status, st.fin_e,
               ms / w.count + rms, rms, launches);
     complete_step(c, st.fin_accepted);
-    c->batch_hint = std::max(st.fin_accepted, 1);
+    c->batch_hint = std::max(step_iterations(c, st.fin_accepted), 1);
+    if (c->mixed && c->batch_hint >= 4 && c->m_inner < kMaxInner)
+      c->m_inner = std::min(kMaxInner, 2 * c->m_inner);
     c->window = 1;
     ++k;
     q = k;
@@ -1000,8 +1088,10 @@ extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
   std::string why;
   if (validate(p, &why) != OCI_OK) return fail(c, OCI_EINVAL, why);
   if (p->n_angles != c->N || p->n_regions != c->R || p->bc_left != c->bcl ||
-      p->bc_right != c->bcr || (p->mu != nullptr) != c->quad_override)
-    return fail(c, OCI_EINVAL, "refactor needs the same angles, regions and boundary kinds");
+      p->bc_right != c->bcr || (p->mu != nullptr) != c->quad_override ||
+      (p->precision == OCI_PREC_FP32) != c->mixed)
+    return fail(c, OCI_EINVAL,
+                "refactor needs the same angles, regions, boundary kinds and precision");
   for (int r = 0; r < c->R; ++r)
     if (p->cells[r] != c->cells[r]) return fail(c, OCI_EINVAL, "refactor needs the same cells");
   if (p->mu)
@@ -1024,7 +1114,8 @@ extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
   const StepArgs sa0 = c->sa;
   const SiArgs si0 = c->si;
   c->sa.tol = c->si.tol = c->tol;
-  c->sa.max_iters = c->si.max_iters = c->max_iters;
+  c->si.max_iters = c->max_iters;
+  c->sa.max_iters = c->mixed ? 2 * c->max_iters - 1 : c->max_iters;
   c->sa.strict = c->si.strict = c->strict;
   c->si.a = c->a;
   // graphs hold copies of the argument blocks: rebuild them only if those changed

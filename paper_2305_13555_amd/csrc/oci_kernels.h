@@ -56,6 +56,11 @@ struct StepArgs {
   double *dec;             // [nbuf] e of iterate l in slot l % nbuf (NaN: not finite)
   StepCtl *ctl;
   StepRecord *rec;         // [steps] records of a queued solve
+  // mixed precision (FP64 defect correction with FP32 inner iterations)
+  const float *frag_it32;  // G in FP32, same packing and stride as frag_it
+  float *dlt;              // [3][J+2][2N] FP32: the defect d (buffer 0) and the inner
+  size_t dlt_stride;       //   iterates (1, 2); ghost rows zero
+  float *dphi32;           // [J][4] FP32 scalar-flux part of the defect
 };
 
 // Affine map of a sweep's (level k, level k+1/2) flux pair: x -> M x + v.
@@ -101,11 +106,21 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
 // ARGT: tile descriptors in the kernel arguments; VEC: 16-byte operand
 // reads (N % 8 == 0); NF > 0: built for N = NF angles, 0: any N.
 template <int CH, bool ARGT, bool VEC, int NF> __global__ void k_step_begin(StepArgs a);
-// half: the ring half of the step's iterates
+// half: the ring half of the step's iterates.  rstep: 1 for plain FP64 OCI;
+// 2 for the mixed-precision step, where the FP64 iterates are every other one
+// (iterate l even is formed by the FP32 inner iterations) and each FP64
+// iterate also writes its defect in FP32.
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ void k_oci_iterate(StepArgs a, int node, int cb, int half);
+__global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rstep);
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half);
+__global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half,
+                           int rstep);
+// FP32 inner iteration i (1-based) of a mixed-precision step; ly > 0: the last
+// one, which also forms FP64 iterate ly (the FP64 iterate ly-1 read plus the
+// correction).
+template <bool ARGT>
+__global__ void k_oci_inner(StepArgs a, int i, int ly, int half);
+__global__ void k_to_f32(const double *src, float *dst, size_t n);
 // si.hip
 __global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,
                             double *ainv);

@@ -399,7 +399,7 @@ template <int CH, bool VEC, int NF>
 __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
                                        double *phi_new, double *lds, double *phis, double2 *rec,
-                                       bool skip) {
+                                       bool skip, bool defect) {
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -434,7 +434,11 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
       if (row < K) {
         const int cell = t.c0 + cl;
         const double g = rt == wave ? pf.gv[i] : a.gh[(size_t)cell * ghp + row];
-        dst[(size_t)(cell + 1) * K + row] = acc[i] + g;
+        const double v = acc[i] + g;
+        dst[(size_t)(cell + 1) * K + row] = v;
+        // the defect against the iterate this one was computed from (its own
+        // row is staged in LDS row cl+1)
+        if (defect) a.dlt[(size_t)(cell + 1) * K + row] = (float)(v - lds[(cl + 1) * P + row]);
       } else if (pshared && rt == prt && row < K + 4) {
         my_phis[cl * 4 + (row - K)] = acc[i];
       }
@@ -465,6 +469,7 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   if (cl < t.nc) {
     const double v = s + pf.hv;
     phi_new[(size_t)(t.c0 + cl) * 4 + comp] = v;
+    if (defect) a.dphi32[(size_t)(t.c0 + cl) * 4 + comp] = (float)(v - pf.po);
     dphi = isfinite(v) ? fabs(v - pf.po) : __builtin_nan("");
     fphi = fabs(v);
   }
@@ -559,7 +564,8 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // residual records iterate l-1 left and stores its e in dec, off the other
 // work-groups' path.  Nothing is stored while a queued solve is stalled.
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half) {
+__global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half,
+                                                        int rstep) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64];
   const int l = cb + node;
@@ -584,15 +590,16 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
     a.ctl->open = cur;
     a.ctl->base_buf = b0;
   }
-  if (blockIdx.x == 0 && l >= 2) {
+  const int lp = l - rstep;   // the previous iterate with records
+  if (blockIdx.x == 0 && lp >= 1) {
     RecRegs r1;
-    rec_issue(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles);
-    rec_finish(r1, recs + ((l - 1) % a.nbuf) * slot, a.ntiles, red, scratch);
-    if (threadIdx.x == 0 && !stalled) a.dec[(l - 1) % a.nbuf] = rel_change(red[0], red[1]);
+    rec_issue(r1, recs + (lp % a.nbuf) * slot, a.ntiles);
+    rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
+    if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
   }
   iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis,
                       reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
-                      stalled != 0);
+                      stalled != 0, rstep == 2);
 }
 
 // End of the open step after iterates first .. last of it were launched
@@ -606,7 +613,7 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
 // decided step advances the solve's step counter.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
-                                                  int last, int half) {
+                                                  int last, int half, int rstep) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves];
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
@@ -623,7 +630,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   int status = kRunning, L = last;
   double e_acc = -1.0;
   double e_before = (a.strict && first - 1 >= 2) ? e_of(first - 1) : -1.0;
-  for (int l = first; l <= last; ++l) {
+  for (int l = first; l <= last; l += rstep) {
     const double e = e_of(l);
     status = stop_rule_e(l, e, e_before, 2, a.tol, a.strict, a.max_iters);
     if (status != kRunning) {
@@ -663,77 +670,195 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
                         phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision: FP64 defect correction with FP32 inner iterations
+// ---------------------------------------------------------------------------
+// The step's FP64 iterates y_o -> x'_o = T(y_o) (k_oci_iterate with rstep 2)
+// also give the defect d_o = x'_o - y_o (outgoing and scalar-flux parts) in
+// FP32.  The correction delta solves delta = G delta + d_o (the same
+// block-Jacobi map without its constant part); the inner iterations run it
+// from delta_1 = d_o in FP32 on MFMA, and the last of them forms the next FP64
+// iterate y_{o+1} = y_o + delta.  Its FP64 iterate T(y_{o+1}) is then judged
+// by the same stopping rule as plain OCI, so every accepted iterate is an FP64
+// application of the operator.
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Inner iteration i of the current correction over a tile: delta_{i+1} =
+// G delta_i + d on v_mfma_f32_16x16x4f32 (lane l holds rows 4*(l/16) ..
+// 4*(l/16)+3 of column l%16 of the product: four consecutive cells of one
+// operator row).  delta_1 = d is buffer 0; the iterates alternate between
+// buffers 1 and 2.  With ly > 0 (the last inner iteration) the scalar-flux
+// rows are formed too and the FP64 iterate ly = (iterate ly-2, or the step's
+// start for ly = 2) + delta is written to ring buffer ly instead of delta.
+template <bool ARGT>
+__global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, int half) {
+  extern __shared__ double lds_raw[];
+  float *lf = reinterpret_cast<float *>(lds_raw);
+  const int N = a.N, K = 2 * N, KS = K / 4, P = K + 4, K4 = K / 4;
+  const int W = (int)(blockDim.x >> 6);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  const TileDev t = blk_desc<ARGT>(a);
+  const float *src = a.dlt + (size_t)(i == 1 ? 0 : ((i & 1) ? 2 : 1)) * a.dlt_stride;
+  float *dst = a.dlt + (size_t)((i & 1) ? 1 : 2) * a.dlt_stride;
+  const int stalled = a.ctl->stalled;
+  {
+    // rows of cells c0-1 .. c0+nc (ghosted rows c0 .. c0+nc+1) into LDS rows 0 .. nc+1
+    const f4 *s4 = reinterpret_cast<const f4 *>(src + (size_t)t.c0 * K);
+    const int n4 = (t.nc + 2) * K4;
+    for (int e = threadIdx.x; e < n4; e += blockDim.x) {
+      const int r = e / K4, k4 = e - r * K4;
+      *reinterpret_cast<f4 *>(lf + r * P + 4 * k4) = s4[e];
+    }
+  }
+  __syncthreads();
+  if (stalled) return;
+  // reflecting edges: the correction obeys the same (homogeneous) mirror map
+  if (t.c0 == 0 && a.bcl == kBcReflect)
+    for (int e = N + threadIdx.x; e < K; e += blockDim.x) {
+      const int m = e >> 1, tl = e & 1;
+      lf[e] = lf[P + 2 * (N - 1 - m) + tl];
+    }
+  if (t.c0 + t.nc == a.J && a.bcr == kBcReflect) {
+    const int rg = t.nc + 1;
+    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+      const int m = e >> 1, tl = e & 1;
+      lf[rg * P + e] = lf[(rg - 1) * P + 2 * (N - 1 - m) + tl];
+    }
+  }
+  __syncthreads();
+  const double *yb = nullptr, *ybp = nullptr;
+  double *yo = nullptr, *yop = nullptr;
+  if (ly) {
+    const int bb = ly == 2 ? a.ctl->base_buf : ring_buf(a, ly - 2, half);
+    const int bo = ring_buf(a, ly, half);
+    yb = out_at(a, bb);
+    ybp = phi_at(a, bb);
+    yo = out_at(a, bo);
+    yop = phi_at(a, bo);
+  }
+  const float *F = a.frag_it32 + (size_t)t.region * a.frag_it_stride + lane;
+  // incident entry k of cell c: right neighbour (LDS row c+2) for k < N, left (row c) else
+  const float *ap = lf + (kq < 2 ? col + 2 : col) * P + kq * KS;
+  const int nrt = ly ? a.Mt : a.Mto;
+  for (int rt = wave; rt < nrt; rt += W) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float *Fr = F + (size_t)rt * KS * 64;
+    int ks = 0;
+    for (; ks + 8 <= KS; ks += 8) {
+      float f[8], v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        f[q] = Fr[(size_t)(ks + q) * 64];
+        v[q] = ap[ks + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[q], f[q], acc, 0, 0, 0);
+    }
+    for (; ks < KS; ++ks)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[ks], Fr[(size_t)ks * 64], acc, 0, 0, 0);
+    const int row = rt * 16 + col;   // operator row of this lane
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cl = 4 * kq + r;
+      if (cl >= t.nc) continue;
+      const size_t cell = (size_t)(t.c0 + cl);
+      if (row < K) {
+        const float dv = acc[r] + a.dlt[(cell + 1) * K + row];
+        if (ly)
+          yo[(cell + 1) * K + row] = yb[(cell + 1) * K + row] + (double)dv;
+        else
+          dst[(cell + 1) * K + row] = dv;
+      } else if (ly && row < K + 4) {
+        const int comp = row - K;
+        const float pv = acc[r] + a.dphi32[cell * 4 + comp];
+        yop[cell * 4 + comp] = ybp[cell * 4 + comp] + (double)pv;
+      }
+    }
+  }
+}
+
+__global__ void k_to_f32(const double *src, float *dst, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = (float)src[e];
+}
+
+template __global__ void k_oci_inner<true>(StepArgs, int, int, int);
+template __global__ void k_oci_inner<false>(StepArgs, int, int, int);
+
 template __global__ void k_step_begin<4, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<4, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<8, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<8, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<4, false, true, 8>(StepArgs);
-template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int, int);
-template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<8, false, true, 16>(StepArgs);
-template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int, int);
-template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 32>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 64>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 128>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 256>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<4, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<4, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<8, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<8, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<4, true, true, 8>(StepArgs);
-template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int, int);
-template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<8, true, true, 16>(StepArgs);
-template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int, int);
-template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 32>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 64>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 128>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 256>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int, int);
-template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int, int, int);
 
 }  // namespace ocik

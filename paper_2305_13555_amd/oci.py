@@ -25,6 +25,7 @@ OCI_OK, OCI_NOT_CONVERGED = 0, 1
 OCI_EINVAL, OCI_ENOMEM, OCI_EDEVICE, OCI_ENONFINITE, OCI_ESTATE = -1, -2, -3, -4, -5
 OCI_BC_VACUUM, OCI_BC_REFLECT, OCI_BC_INCIDENT = 0, 1, 2
 OCI_PREC_FP64 = 0
+OCI_PREC_FP32 = 1
 OCI_FLAG_STRICT = 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -133,7 +134,7 @@ def oci_gauss_legendre(n):
     return mu, w
 
 
-def make_problem(prob, tol=None, max_iters=None, strict=None):
+def make_problem(prob, tol=None, max_iters=None, strict=None, precision=None):
     """Marshal a problem description (attributes as in the workloads module)
     into the C struct.  Returns (struct, keepalive) - keep both alive."""
     keep = {
@@ -164,24 +165,25 @@ def make_problem(prob, tol=None, max_iters=None, strict=None):
     p.psi0 = _ptr(keep["psi0"])
     p.tol = float(prob.tol if tol is None else tol)
     p.max_iters = int(prob.max_iters if max_iters is None else max_iters)
-    p.precision = OCI_PREC_FP64
+    p.precision = int(getattr(prob, "precision", OCI_PREC_FP64) if precision is None
+                      else precision)
     st = bool(getattr(prob, "strict", False) if strict is None else strict)
     p.flags = OCI_FLAG_STRICT if st else 0
     return p, keep
 
 
-def oci_setup(prob, stream=None, tol=None, max_iters=None, strict=None):
+def oci_setup(prob, stream=None, tol=None, max_iters=None, strict=None, precision=None):
     """Build a context for the problem; returns the raw handle (c_void_p)."""
-    p, keep = make_problem(prob, tol, max_iters, strict)
+    p, keep = make_problem(prob, tol, max_iters, strict, precision)
     h = ctypes.c_void_p()
     _check(_lib.oci_setup(ctypes.byref(p), _stream_handle(stream), ctypes.byref(h)))
     del keep
     return h
 
 
-def oci_refactor(ctx, prob, tol=None, max_iters=None, strict=None):
+def oci_refactor(ctx, prob, tol=None, max_iters=None, strict=None, precision=None):
     """Rebuild the operators for new region data of the same shape."""
-    p, keep = make_problem(prob, tol, max_iters, strict)
+    p, keep = make_problem(prob, tol, max_iters, strict, precision)
     _check(_lib.oci_refactor(ctx, ctypes.byref(p)), ctx)
     del keep
 
@@ -272,12 +274,14 @@ def oci_strerror(code):
 class OciContext:
     """Owning wrapper around a context handle."""
 
-    def __init__(self, prob, stream=None, tol=None, max_iters=None, strict=None):
-        self.handle = oci_setup(prob, stream, tol, max_iters, strict)
+    def __init__(self, prob, stream=None, tol=None, max_iters=None, strict=None,
+                 precision=None):
+        self.precision = precision
+        self.handle = oci_setup(prob, stream, tol, max_iters, strict, precision)
         self.n_angles, self.n_cells, self.n_regions = oci_get_sizes(self.handle)
 
     def refactor(self, prob, tol=None, max_iters=None, strict=None):
-        oci_refactor(self.handle, prob, tol, max_iters, strict)
+        oci_refactor(self.handle, prob, tol, max_iters, strict, self.precision)
 
     def step(self):
         return oci_step(self.handle)
