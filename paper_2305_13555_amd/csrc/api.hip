@@ -90,6 +90,10 @@ struct oci_ctx {
   // correction solves of m_inner iterations between them
   bool mixed = false;
   int rstep = 1, m_inner = 2;
+  // inner-count search: FP64 iterates per step seen at m_inner, the count
+  // before a trial decrease and what it gave, no further decreases
+  int m_q = 0, m_prev = 0, m_prev_q = 0;
+  bool m_locked = false;
   float *d_fi32 = nullptr, *d_dlt = nullptr, *d_dphi32 = nullptr;
   size_t lds_in = 0;
   // kernels for the chosen operator batch width CH
@@ -294,6 +298,8 @@ static int build_operators(oci_ctx *c) {
 }
 
 static void drop_step_graphs(oci_ctx *c) {
+  // a queued window may still be running one of them
+  if (!c->step_graphs.empty()) (void)hipStreamSynchronize(c->stream);
   for (auto &g : c->step_graphs) (void)hipGraphExecDestroy(g.exec);
   c->step_graphs.clear();
 }
@@ -874,6 +880,36 @@ static int step_launches(const oci_ctx *c, int batch) {
   return c->mixed ? batch + (batch - 1) * c->m_inner : batch;
 }
 
+// Mixed precision: inner iterations per correction, from the most FP64
+// iterates a completed window's steps took (q) with m_used inner iterations.  Four or more (three suffice
+// at tol ~ 1e-10 when each correction gains the ~1e-6 that FP32 allows):
+// double them.  Otherwise try one fewer; if that costs FP64 iterates, go back
+// and stop decreasing.
+static void tune_inner(oci_ctx *c, int q, int m_used) {
+  if (m_used != c->m_inner) return;   // a window queued before the last change
+  if (q >= 4) {
+    if (c->m_inner < kMaxInner) c->m_inner = std::min(kMaxInner, 2 * c->m_inner);
+    c->m_q = 0;
+    c->m_prev = 0;
+    c->m_locked = false;
+    return;
+  }
+  if (c->m_prev && q > c->m_prev_q) {
+    c->m_inner = c->m_prev;
+    c->m_q = c->m_prev_q;
+    c->m_prev = 0;
+    c->m_locked = true;
+    return;
+  }
+  c->m_q = q;
+  c->m_prev = 0;
+  if (!c->m_locked && c->m_inner > 1) {
+    c->m_prev = c->m_inner;
+    c->m_prev_q = q;
+    c->m_inner -= 1;
+  }
+}
+
 // Mixed precision: one more correction after FP64 iterate lprev (inner
 // iterations, the last forming iterate lprev+1) and FP64 iterate lprev+2.
 static int launch_outer(oci_ctx *c, int lprev, int half) {
@@ -989,7 +1025,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
   OCI_CK(c, hipMemcpyAsync(&c->d_ctl->cur, &c->h_ctl->cur, 2 * sizeof(int32_t),
                            hipMemcpyHostToDevice, c->stream));
   struct Win {
-    int first, count, batch, ev;
+    int first, count, batch, ev, m;   // m: inner iterations (mixed precision)
   };
   Win wins[2];
   int nwin = 0, next_ev = 0;
@@ -1008,7 +1044,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       rc = enqueue_window(c, q, count, batch, c->parity ^ ((q - k) & 1), phi_dev,
                           c->evW[ev][0], c->evW[ev][1]);
       if (rc) return rc;
-      wins[nwin++] = Win{q, count, batch, ev};
+      wins[nwin++] = Win{q, count, batch, ev, c->m_inner};
       q += count;
     }
     if (nwin == 0) {
@@ -1018,7 +1054,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       rc = enqueue_window(c, q, 1, batch, c->parity ^ ((q - k) & 1), phi_dev, c->evW[ev][0],
                           c->evW[ev][1]);
       if (rc) return rc;
-      wins[nwin++] = Win{q, 1, batch, ev};
+      wins[nwin++] = Win{q, 1, batch, ev, c->m_inner};
       q += 1;
     }
     const Win w = wins[0];
@@ -1043,11 +1079,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
     }
     k = done;
     if (ndone > 0) c->batch_hint = std::max(hint, 1);
-    // mixed precision: a correction that needs more FP64 iterates than a
-    // converged one (three at tol ~ 1e-10) gets more inner iterations
-    if (c->mixed && hint >= 4 && c->m_inner < kMaxInner) {
-      c->m_inner = std::min(kMaxInner, 2 * c->m_inner);
-    }
+    if (c->mixed && ndone > 0) tune_inner(c, hint, w.m);
     if (ndone == w.count) {
       wins[0] = wins[1];
       --nwin;
@@ -1074,8 +1106,7 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
               ms / w.count + rms, rms, launches);
     complete_step(c, st.fin_accepted);
     c->batch_hint = std::max(step_iterations(c, st.fin_accepted), 1);
-    if (c->mixed && c->batch_hint >= 4 && c->m_inner < kMaxInner)
-      c->m_inner = std::min(kMaxInner, 2 * c->m_inner);
+    if (c->mixed) tune_inner(c, c->batch_hint, c->m_inner);
     c->window = 1;
     ++k;
     q = k;

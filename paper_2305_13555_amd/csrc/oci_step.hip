@@ -693,6 +693,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // start for ly = 2) + delta is written to ring buffer ly instead of delta.
 template <bool ARGT>
 __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, int half) {
+  constexpr int kPre = 16;   // operator k-steps of the wave's first row tile loaded up front
   extern __shared__ double lds_raw[];
   float *lf = reinterpret_cast<float *>(lds_raw);
   const int N = a.N, K = 2 * N, KS = K / 4, P = K + 4, K4 = K / 4;
@@ -702,6 +703,22 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
   const TileDev t = blk_desc<ARGT>(a);
   const float *src = a.dlt + (size_t)(i == 1 ? 0 : ((i & 1) ? 2 : 1)) * a.dlt_stride;
   float *dst = a.dlt + (size_t)((i & 1) ? 1 : 2) * a.dlt_stride;
+  const int nrt = ly ? a.Mt : a.Mto;
+  const float *F = a.frag_it32 + (size_t)t.region * a.frag_it_stride + lane;
+  // loads that need no LDS first: the first operator k-steps and the defect
+  // values (constant part) of the wave's first row tile
+  float f0[kPre], dv0[4];
+  {
+    const float *Fr = F + (size_t)wave * KS * 64;
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) f0[q] = Fr[(size_t)min(q, KS - 1) * 64];
+    const int row = min(wave * 16 + col, K - 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cl = min(4 * kq + r, t.nc - 1);
+      dv0[r] = a.dlt[(size_t)(t.c0 + cl + 1) * K + row];
+    }
+  }
   const int stalled = a.ctl->stalled;
   {
     // rows of cells c0-1 .. c0+nc (ghosted rows c0 .. c0+nc+1) into LDS rows 0 .. nc+1
@@ -715,19 +732,21 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
   __syncthreads();
   if (stalled) return;
   // reflecting edges: the correction obeys the same (homogeneous) mirror map
-  if (t.c0 == 0 && a.bcl == kBcReflect)
+  const bool rl = t.c0 == 0 && a.bcl == kBcReflect;
+  const bool rr = t.c0 + t.nc == a.J && a.bcr == kBcReflect;
+  if (rl)
     for (int e = N + threadIdx.x; e < K; e += blockDim.x) {
       const int m = e >> 1, tl = e & 1;
       lf[e] = lf[P + 2 * (N - 1 - m) + tl];
     }
-  if (t.c0 + t.nc == a.J && a.bcr == kBcReflect) {
+  if (rr) {
     const int rg = t.nc + 1;
     for (int e = threadIdx.x; e < N; e += blockDim.x) {
       const int m = e >> 1, tl = e & 1;
       lf[rg * P + e] = lf[(rg - 1) * P + 2 * (N - 1 - m) + tl];
     }
   }
-  __syncthreads();
+  if (rl || rr) __syncthreads();
   const double *yb = nullptr, *ybp = nullptr;
   double *yo = nullptr, *yop = nullptr;
   if (ly) {
@@ -738,14 +757,18 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
     yo = out_at(a, bo);
     yop = phi_at(a, bo);
   }
-  const float *F = a.frag_it32 + (size_t)t.region * a.frag_it_stride + lane;
   // incident entry k of cell c: right neighbour (LDS row c+2) for k < N, left (row c) else
   const float *ap = lf + (kq < 2 ? col + 2 : col) * P + kq * KS;
-  const int nrt = ly ? a.Mt : a.Mto;
   for (int rt = wave; rt < nrt; rt += W) {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
     const float *Fr = F + (size_t)rt * KS * 64;
     int ks = 0;
+    if (rt == wave) {
+#pragma unroll
+      for (int q = 0; q < kPre; ++q)
+        if (q < KS) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[q], f0[q], acc, 0, 0, 0);
+      ks = kPre;
+    }
     for (; ks + 8 <= KS; ks += 8) {
       float f[8], v[8];
 #pragma unroll
@@ -765,7 +788,8 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
       if (cl >= t.nc) continue;
       const size_t cell = (size_t)(t.c0 + cl);
       if (row < K) {
-        const float dv = acc[r] + a.dlt[(cell + 1) * K + row];
+        const float d = rt == wave ? dv0[r] : a.dlt[(cell + 1) * K + row];
+        const float dv = acc[r] + d;
         if (ly)
           yo[(cell + 1) * K + row] = yb[(cell + 1) * K + row] + (double)dv;
         else
