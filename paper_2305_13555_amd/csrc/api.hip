@@ -55,8 +55,8 @@ struct oci_ctx {
   TileDev *d_tiles = nullptr;
   int *d_cell_region = nullptr;
   double *d_op = nullptr;
-  double *d_fi = nullptr, *d_fp = nullptr, *d_cp = nullptr, *d_fe = nullptr, *d_ce = nullptr;
-  size_t fi_stride = 0, fp_stride = 0, cp_stride = 0, fe_stride = 0, ce_stride = 0;
+  double *d_fi = nullptr, *d_fp = nullptr, *d_cp = nullptr;
+  size_t fi_stride = 0, fp_stride = 0, cp_stride = 0;
   double *d_gh = nullptr, *d_outb = nullptr, *d_phib = nullptr, *d_dec = nullptr;
   int nbuf = 3;                              // ring slots per half (buffers: 2*nbuf + 2)
   size_t out_stride = 0, phi_stride = 0;
@@ -281,9 +281,6 @@ static int build_operators(oci_ctx *c) {
   // per-step operator P: rows [0, 2N+4), columns [2N, 4N) (psi_{k-1/2}); source column
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, K, K,
                      c->Mt, c->d_fp, c->fp_stride, c->d_cp, c->cp_stride, 1);
-  // end-of-step operator E: rows [2N+4, 4N+4), columns [0, 4N)
-  hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 2 * N + 4, K, 0,
-                     2 * K, c->Met, c->d_fe, c->fe_stride, c->d_ce, c->ce_stride, 1);
   if (c->mixed)   // G for the FP32 inner iterations, same packing
     hipLaunchKernelGGL(k_to_f32, dim3(256), dim3(256), 0, c->stream, (const double *)c->d_fi,
                        c->d_fi32, (size_t)R * c->fi_stride);
@@ -383,7 +380,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   const int P = K + 2;
   c->lds_it = (size_t)(kTileCells + 2) * P * sizeof(double);
   c->lds_pv = (size_t)kTileCells * P * sizeof(double);
-  c->lds_ed = (size_t)((end_keeps_psi(P) ? 3 : 2) * kTileCells + 2) * P * sizeof(double);
+  c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
   c->si_blocks = (J * 4 + 255) / 256;
   // source-iteration sweep segments: about two cells per thread of a
   // 256-thread work-group, at most 64 segments
@@ -416,8 +413,6 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->fi_stride = (size_t)c->Mt * (K / 4) * 64;
   c->fp_stride = c->fi_stride;
   c->cp_stride = (size_t)c->Mt * 16;
-  c->fe_stride = (size_t)c->Met * (2 * K / 4) * 64;
-  c->ce_stride = (size_t)c->Met * 16;
   OCI_TRY(dalloc(c, &c->d_mu, N));
   OCI_TRY(dalloc(c, &c->d_w, N));
   OCI_TRY(dalloc(c, &c->d_regions, R));
@@ -427,8 +422,6 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_fi, (size_t)R * c->fi_stride));
   OCI_TRY(dalloc(c, &c->d_fp, (size_t)R * c->fp_stride));
   OCI_TRY(dalloc(c, &c->d_cp, (size_t)R * c->cp_stride));
-  OCI_TRY(dalloc(c, &c->d_fe, (size_t)R * c->fe_stride));
-  OCI_TRY(dalloc(c, &c->d_ce, (size_t)R * c->ce_stride));
   OCI_TRY(dalloc(c, &c->d_gh, (size_t)J * c->Mt * 16));
   // one buffer per iterate of a queued batch (at most kMaxBatch launches) in
   // each of two rings, one per step parity, within a memory budget
@@ -541,10 +534,10 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.frag_pv_stride = c->fp_stride;
   s.c_pv = c->d_cp;
   s.c_pv_stride = c->cp_stride;
-  s.frag_ed = c->d_fe;
-  s.frag_ed_stride = c->fe_stride;
-  s.c_ed = c->d_ce;
-  s.c_ed_stride = c->ce_stride;
+  s.regions = c->d_regions;
+  s.mu = c->d_mu;
+  s.ainv = c->d_ainv;
+  s.at = c->a;
   s.gh = c->d_gh;
   s.nbuf = c->nbuf;
   s.outb = c->d_outb;
@@ -1149,6 +1142,7 @@ extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
   c->sa.max_iters = c->mixed ? 2 * c->max_iters - 1 : c->max_iters;
   c->sa.strict = c->si.strict = c->strict;
   c->si.a = c->a;
+  c->sa.at = c->a;
   // graphs hold copies of the argument blocks: rebuild them only if those changed
   if (std::memcmp(&sa0, &c->sa, sizeof sa0) != 0 || std::memcmp(&si0, &c->si, sizeof si0) != 0)
     drop_graphs(c);

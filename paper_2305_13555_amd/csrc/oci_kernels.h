@@ -16,14 +16,6 @@ __host__ __device__ inline uint32_t pack_tile(int region, int c0, int nc) {
   return (uint32_t)c0 | ((uint32_t)(nc - 1) << kArgTileCellBits) | ((uint32_t)region << 22);
 }
 
-// The end of step keeps psi_{k+1/2} of its tile in LDS for the next step's
-// gh when three tiles of rows (pitch P doubles) and two halo rows fit in the
-// 160 KiB of LDS a work-group can have; otherwise it reads them back.
-constexpr int kLdsBytes = 160 * 1024;
-__host__ __device__ constexpr bool end_keeps_psi(int P) {
-  return (3 * kTileCells + 2) * P * 8 <= kLdsBytes;
-}
-
 struct StepArgs {
   const TileDev *tiles;    // [ntiles] in work-group order (one work-group per tile)
   int ntiles;
@@ -40,10 +32,10 @@ struct StepArgs {
   size_t frag_pv_stride;
   const double *c_pv;      // p
   size_t c_pv_stride;
-  const double *frag_ed;   // E (end of step)
-  size_t frag_ed_stride;
-  const double *c_ed;      // e
-  size_t c_ed_stride;
+  const RegionDev *regions; // [R] cell width and cross sections (end of step)
+  const double *mu;        // [N]
+  const double *ainv;      // [R][N][16] A_m^{-1} per region and angle
+  double at;               // 1/(v dt), 0 for v = inf
   double *gh;              // [J][Mt*16]
   int nbuf;                // ring slots per half (iterate l of a step in slot l % nbuf)
   double *outb;            // [2*nbuf+2][J+2][2N]

@@ -478,70 +478,67 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   if (lane == 0) *rec = make_double2(dphi, fphi);
 }
 
-// End of step for a tile: psi_{k+1/2} from the incident fluxes the accepted
-// iterate was computed from (src = the buffer the last iteration read) and
-// psi_{k-1/2}; copies the accepted scalar flux to phi_res (and phi_out).  E is
-// packed k-major with N k-steps per lane group: group 0 takes the right
-// neighbour's mu < 0 half, 1 the left neighbour's mu > 0 half, 2 and 3 the two
-// halves of the cell's psi_{k-1/2} row.
+// End of step for a tile.  The accepted iterate L solved every cell's
+// system (A - S) psi = c with the incident fluxes of iterate L-1 (src = the
+// buffer iterate L read) and gave its scalar flux phi_L = W psi.  With the
+// scattering source s phi_L known, each angle's 4x4 block separates:
+// A_m psi_m = c_m + s phi_L (Sec. "One-Cell Inversion (OCI)", the cell
+// equations with the scattering term moved to the right-hand side), so
+// psi_{k+1/2} (rows (k+1/2)L, (k+1/2)R of psi_m) is two rows of A_m^{-1} times
+// a 4-vector per (cell, angle): O(N) per cell instead of a 2N x 4N product.
+// Also copies the accepted scalar flux to phi_res (and phi_out), and forms
+// the next step's gh from psi_{k+1/2} (kept in LDS).
 template <int CH, bool VEC, int NF>
 __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const double *src,
                                 const double *psi_prev, double *psi_next, const double *phi_acc,
                                 double *phi_out, double *lds) {
+  __shared__ double sphi[4 * kTileCells];
   double fg[CH];   // P fragments for the next step's gh, issued early
   gh_frags<CH, NF>(a, t, fg);
-  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = N;
-  const int Met = NF ? (2 * NF + 15) / 16 : a.Met;
-  const int W = NF ? (Met < 4 ? Met : 4) : (int)(blockDim.x >> 6);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col = lane & 15, kq = lane >> 4;
-  const double *F = a.frag_ed + (size_t)t.region * a.frag_ed_stride + lane;
-  const double *ce = a.c_ed + (size_t)t.region * a.c_ed_stride;
-  double *ldp = lds + (kTileCells + 2) * P;
-  const bool keep = end_keeps_psi(P);
-  double *ldn = keep ? ldp + kTileCells * P : lds;   // psi_{k+1/2} of the tile's cells
-  double f0[CH];
-  if (wave < Met) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
+  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
+  double *ldn = lds + (kTileCells + 2) * P;   // psi_{k+1/2} of the tile's cells
   for (int i = threadIdx.x; i < t.nc * 4; i += blockDim.x) {
     const double v = phi_acc[(size_t)t.c0 * 4 + i];
     a.phi_res[(size_t)t.c0 * 4 + i] = v;
     if (phi_out) phi_out[(size_t)t.c0 * 4 + i] = v;
+    sphi[i] = v;
   }
-  const RowBlock blk[2] = {neighbour_block(lds, src, t, K), own_block(ldp, psi_prev, t, K)};
-  copy_blocks_to_lds(blk, 2, K, P);
+  const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
+  copy_blocks_to_lds(blk, 1, K, P);
   __syncthreads();
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
-  const double *ap = kq == 0 ? lds + (col + 2) * P
-                   : kq == 1 ? lds + col * P + N
-                   : ldp + col * P + (kq - 2) * N;
-  for (int rt = wave; rt < Met; rt += W) {
-    const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)rt * KS * 64, KS, rt == wave, f0, ap);
-    const int row = rt * 16 + col;
-    if (row < K) {
-      const double cv = ce[row];
+  const RegionDev g = a.regions[t.region];
+  const double qs = 0.25 * g.dx, ts = 0.5 * a.at * g.dx;   // dx/4; tau/2
+  const double *Ar = a.ainv + (size_t)t.region * N * 16;
+  for (int p = threadIdx.x; p < t.nc * N; p += blockDim.x) {
+    const int cl = p / N, m = p - cl * N;
+    const double *Ai = Ar + (size_t)m * 16;
+    const double *pp = psi_prev + (size_t)(t.c0 + cl) * K + 2 * m;
+    const double *ph = sphi + cl * 4;
+    double b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int cl = kq + 4 * i;
-        const double v = acc[i] + cv;
-        if (keep) ldn[cl * P + row] = v;
-        if (cl < t.nc) psi_next[(size_t)(t.c0 + cl) * K + row] = v;
-      }
-    }
+    for (int c = 0; c < 4; ++c) b[c] = qs * (g.sigs * ph[c] + g.q);
+    b[0] += ts * pp[0];
+    b[1] += ts * pp[1];
+    // entering flux: mu > 0 (m >= N/2) from the left neighbour's row into
+    // rows kL, (k+1/2)L; mu < 0 from the right neighbour's into kR, (k+1/2)R
+    const bool pos = 2 * m >= N;
+    const double amu = fabs(a.mu[m]);
+    const double *in = lds + (pos ? cl : cl + 2) * P + 2 * m;
+    b[pos ? 0 : 1] += amu * in[0];
+    b[pos ? 2 : 3] += amu * in[1];
+    const double x2 = Ai[8] * b[0] + Ai[9] * b[1] + Ai[10] * b[2] + Ai[11] * b[3];
+    const double x3 = Ai[12] * b[0] + Ai[13] * b[1] + Ai[14] * b[2] + Ai[15] * b[3];
+    psi_next[(size_t)(t.c0 + cl) * K + 2 * m] = x2;
+    psi_next[(size_t)(t.c0 + cl) * K + 2 * m + 1] = x3;
+    ldn[cl * P + 2 * m] = x2;
+    ldn[cl * P + 2 * m + 1] = x3;
   }
   // the next step's gh from psi_{k+1/2}, so that a queued step that
   // follows needs no step start
   __syncthreads();
-  if (!keep) {   // this work-group's own psi_{k+1/2} rows, back over the halo rows
-    const RowBlock blk1[1] = {own_block(ldn, psi_next, t, K)};
-    copy_blocks_to_lds(blk1, 1, K, P);
-    __syncthreads();
-  }
   gh_gemm<CH, VEC, NF>(a, t, ldn, fg);
 }
-
-// ---------------------------------------------------------------------------
-// Kernels
-// ---------------------------------------------------------------------------
 
 // Start of step `cur` of the current solve: gh for every tile from
 // psi_{k-1/2}.  Needed only where no end of step has computed it (the first
