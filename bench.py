@@ -45,7 +45,7 @@ ITERATIONS_PER_LAUNCH = 1   # iterates per launch of the iteration kernel
 ITERATION_KERNEL = "k_oci_iterate"
 
 
-def roofline_launch_seconds(oci, prob, stream, steps=5):
+def roofline_launch_seconds(oci, prob, stream, steps=9):
     """Per-launch time of the iteration kernel on the workload's cells, regions and
     angles, with v = inf and tol = 0 so that every launch does the full work
     (the kernel's work does not depend on the values).  Steps of 32 and of 16
@@ -285,7 +285,7 @@ def main():
             "us_per_launch": per_launch_s * 1e6,
             "iterations_per_launch": ITERATIONS_PER_LAUNCH,
             "measured": "(median step time at 32 iterates - at 16) / the extra launches, "
-                        "5 steps each",
+                        "9 steps each (launch to launch, dispatch gap included)",
         },
         "cpu_baseline": cpu,
         "iterations_per_time_step": iters / (args.steps * T),
