@@ -62,6 +62,7 @@ struct oci_ctx {
   size_t out_stride = 0, phi_stride = 0;
   double *d_psi[2] = {nullptr, nullptr}, *d_phi_res = nullptr, *d_partial = nullptr;
   double *d_ainv = nullptr, *d_contrib = nullptr, *d_lag = nullptr, *d_si_partial = nullptr;
+  double *d_coef = nullptr;
   Affine *d_segmap = nullptr;
   StepCtl *d_ctl = nullptr;
   StepCtl *h_ctl = nullptr;                  // pinned host copy of the control block
@@ -286,6 +287,8 @@ static int build_operators(oci_ctx *c) {
                        c->d_fi32, (size_t)R * c->fi_stride);
   hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
                      c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
+  hipLaunchKernelGGL(k_out_coef, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
+                     c->d_regions, c->d_mu, c->d_ainv, N, R, c->a, c->d_coef);
   OCI_CK(c, hipGetLastError());
   int bad = 0;
   OCI_CK(c, hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -440,6 +443,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_phi_res, (size_t)J * 4));
   OCI_TRY(dalloc(c, &c->d_partial, (size_t)c->nbuf * c->ntiles * 2));
   OCI_TRY(dalloc(c, &c->d_ainv, (size_t)R * N * 16));
+  OCI_TRY(dalloc(c, &c->d_coef, (size_t)R * N * kCoef));
   OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(N / 2) * J * 4));
   OCI_TRY(dalloc(c, &c->d_lag, (size_t)2 * N));
   OCI_TRY(dalloc(c, &c->d_segmap, (size_t)(N / 2) * c->si_segs * 2));
@@ -537,6 +541,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.regions = c->d_regions;
   s.mu = c->d_mu;
   s.ainv = c->d_ainv;
+  s.coef = c->d_coef;
   s.at = c->a;
   s.gh = c->d_gh;
   s.nbuf = c->nbuf;

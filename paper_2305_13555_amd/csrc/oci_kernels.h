@@ -15,6 +15,8 @@ constexpr int kArgTileCellBits = 18;
 __host__ __device__ inline uint32_t pack_tile(int region, int c0, int nc) {
   return (uint32_t)c0 | ((uint32_t)(nc - 1) << kArgTileCellBits) | ((uint32_t)region << 22);
 }
+// Per (region, angle) coefficients of the structured apply (see oci_step.hip).
+constexpr int kCoef = 18;
 
 struct StepArgs {
   const TileDev *tiles;    // [ntiles] in work-group order (one work-group per tile)
@@ -35,6 +37,7 @@ struct StepArgs {
   const RegionDev *regions; // [R] cell width and cross sections (end of step)
   const double *mu;        // [N]
   const double *ainv;      // [R][N][16] A_m^{-1} per region and angle
+  const double *coef;      // [R][N][kCoef] outgoing-pair and step-constant coefficients
   double at;               // 1/(v dt), 0 for v = inf
   double *gh;              // [J][Mt*16]
   int nbuf;                // ring slots per half (iterate l of a step in slot l % nbuf)
@@ -91,6 +94,8 @@ __global__ void k_build_system(const RegionDev *regions, const double *mu, const
 __global__ void k_lu_solve(int N, double *ws_M, double *ws_X, int *bad);
 __global__ void k_lu_solve_lds(int N, int CB, int P, const double *ws_M, double *ws_X, int *bad);
 __global__ void k_select_rows(int N, const double *w, const double *ws_X, double *op_all);
+__global__ void k_out_coef(const RegionDev *regions, const double *mu, const double *ainv, int N,
+                           int R, double a, double *coef);
 __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
                        int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
                        size_t cvec_stride, int kmajor);

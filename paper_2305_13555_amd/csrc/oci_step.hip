@@ -259,41 +259,108 @@ __device__ __forceinline__ double *phi_at(const StepArgs &a, int b) {
   return a.phib + (size_t)b * a.phi_stride;
 }
 
-// gh rows of a tile, gh_j = P_r psi_j + p_r, from the tile's psi rows in LDS
-// (pitch P, cell c in row c).  P is packed k-major, so a lane's operands are
-// consecutive in its cell's row.  f0: this wave's first fragments of P.
-template <int CH, bool VEC, int NF>
-__device__ inline void gh_gemm(const StepArgs &a, const TileDev &t, const double *rows,
-                               const double (&f0)[CH]) {
-  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
-  const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
-  const int W = (int)(blockDim.x >> 6);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col = lane & 15, kq = lane >> 4;
-  const double *F = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane;
-  const double *cp = a.c_pv + (size_t)t.region * a.c_pv_stride;
-  const int ghp = Mt * 16;
-  const double *ap = rows + col * P + kq * KS;
-  for (int rt = wave; rt < Mt; rt += W) {
-    const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)rt * KS * 64, KS, rt == wave, f0, ap);
-    const int row = rt * 16 + col;
-    const double cv = cp[row];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int cl = kq + 4 * i;
-      if (cl < t.nc) a.gh[(size_t)(t.c0 + cl) * ghp + row] = acc[i] + cv;
-    }
+// ---------------------------------------------------------------------------
+// The structured apply
+// ---------------------------------------------------------------------------
+// Cell j's solution of (A - S) psi = c satisfies A_m psi_m = c_m + s phi
+// angle by angle, phi = W psi its scalar flux (4 values: the scattering
+// coupling of the angles has rank 4).  An OCI iteration therefore needs the
+// dense reduced operator only for the new scalar flux,
+//   phi^(l+1) = H inc^(l) + h            (H: the 4 scalar-flux rows of G),
+// and each outgoing pair of angle m then follows from two rows of A_m^{-1}:
+//   out_{m,t} = g'_{m,t} + A_m^{-1}[o_t,:] (s phi^(l+1) + |mu| inc_m)
+// with g'_{m,t} = A_m^{-1}[o_t,:] c_m(psi_{k-1/2}, Q) the step constant
+// (o_t: the outgoing-corner rows at levels k and k+1/2).  This is the same
+// iteration as [out; phi] = G inc + [g; h] with the products associated
+// differently: O(N) work per cell for the outgoing fluxes instead of 4N^2.
+// The per (region, angle) coefficients (kCoef doubles, built at setup):
+//   [6t + c]  s A^{-1}[o_t][c], c = 0..3   [6t + 4]  |mu| A^{-1}[o_t][in_0]
+//   [6t + 5]  |mu| A^{-1}[o_t][in_1]       [12 + 3t] (dx Q / 4) sum_c A^{-1}[o_t][c]
+//   [13 + 3t] (dx / (2 v dt)) A^{-1}[o_t][0]   [14 + 3t] (dx / (2 v dt)) A^{-1}[o_t][1]
+// (in_0, in_1: the entering-corner rows at levels k and k+1/2.)
+
+// Angle and cells of this thread in the per-(cell, angle) loops: angle
+// tid mod N, cells tid / N + j * cstep (threads past cstep * N idle).
+struct PairMap {
+  int m, cl0, cstep;
+  bool active;
+  __device__ __forceinline__ explicit PairMap(int N) {
+    const int tid = threadIdx.x;
+    cstep = (int)blockDim.x / N;
+    m = tid % N;
+    cl0 = tid / N;
+    active = tid < cstep * N;
+  }
+};
+
+// The scalar-flux rows 2N .. 2N+3 of G and P: their row tile and the first of
+// them within it (2N is a multiple of 4, so all four share one row tile).
+__device__ __forceinline__ void phi_tile(int N, int *rt, int *off) {
+  const int K = 2 * N;
+  *rt = K / 16;
+  *off = K % 16;
+}
+
+// k-steps of a row tile handled by wave w when it is split over W waves
+// (range starts at multiples of 4; equal shares when KS allows).
+__device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *ke) {
+  if (KS % (4 * W) == 0) {
+    *kb = w * (KS / W);
+    *ke = *kb + KS / W;
+  } else {
+    *kb = ((w * KS) / W) & ~3;
+    *ke = w + 1 == W ? KS : (((w + 1) * KS) / W) & ~3;
   }
 }
 
-// The first fragments of P for this wave's first row tile.
+// The step constant of a tile from its psi rows in LDS (pitch P, cell c in
+// row c): h (rows 2N .. 2N+3 of gh) = the scalar-flux rows of P psi + p on
+// MFMA (wave 0; f0 its first fragments), g' (rows 0 .. 2N-1) per (cell, angle).
+template <int CH, bool VEC, int NF>
+__device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const double *rows,
+                                  const double (&f0)[CH]) {
+  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
+  const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  const int ghp = Mt * 16;
+  int prt, poff;
+  phi_tile(N, &prt, &poff);
+  if (wave == 0) {
+    const double *F = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane;
+    const double *cp = a.c_pv + (size_t)t.region * a.c_pv_stride;
+    const double *ap = rows + col * P + kq * KS;
+    const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)prt * KS * 64, KS, true, f0, ap);
+    if (col >= poff && col < poff + 4) {
+      const double cv = cp[K + col - poff];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int cl = kq + 4 * i;
+        if (cl < t.nc) a.gh[(size_t)(t.c0 + cl) * ghp + K + col - poff] = acc[i] + cv;
+      }
+    }
+  }
+  const PairMap pm(N);
+  if (!pm.active) return;
+  const double *cf = a.coef + ((size_t)t.region * N + pm.m) * kCoef + 12;
+  const double c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3], c4 = cf[4], c5 = cf[5];
+  for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep) {
+    const double pl = rows[cl * P + 2 * pm.m], pr = rows[cl * P + 2 * pm.m + 1];
+    double *g = a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m;
+    g[0] = c0 + c1 * pl + c2 * pr;
+    g[1] = c3 + c4 * pl + c5 * pr;
+  }
+}
+
+// The first fragments of P's scalar-flux row tile (wave 0).
 template <int CH, int NF>
 __device__ __forceinline__ void gh_frags(const StepArgs &a, const TileDev &t, double (&f0)[CH]) {
   const int N = NF ? NF : a.N, KS = (2 * N) / 4;
-  const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
+  int prt, poff;
+  phi_tile(N, &prt, &poff);
   const double *F = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane;
-  if (wave < Mt) load_frags<CH>(f0, F + (size_t)wave * KS * 64, 0, KS);
+  if ((threadIdx.x >> 6) == 0) load_frags<CH>(f0, F + (size_t)prt * KS * 64, 0, KS);
 }
 
 // gh of a tile from psi_{k-1/2} in global memory.
@@ -306,48 +373,28 @@ __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const dou
   const RowBlock blk[1] = {own_block(lds, psi_prev, t, K)};
   copy_blocks_to_lds(blk, 1, K, P);
   __syncthreads();
-  gh_gemm<CH, VEC, NF>(a, t, lds, f0);
+  gh_compute<CH, VEC, NF>(a, t, lds, f0);
 }
 
 // One OCI iteration of a tile, in two phases: iterate_prefetch issues every
-// load that does not need LDS (the first operator chunks of the wave's
-// outgoing row tile and of its share of the scalar-flux rows, the tile's
-// step constants, the old scalar flux, and the neighbour rows, staged into
-// LDS by iterate_compute).  iterate_compute runs the GEMM on MFMA: each wave
-// one row tile of the 2N outgoing rows, and the 4 scalar-flux rows either
-// inside the last outgoing row tile (2N not a multiple of 16) or as one more
-// row tile whose k-steps are split over the waves and summed in LDS in a
-// fixed order.  Wave 0 then forms the 64 (cell, component) scalar fluxes and
-// the tile's residual record.
+// load that does not need LDS (the first operator chunk of the wave's share
+// of the scalar-flux row tile, this thread's out coefficients and step
+// constants, the old scalar flux, and the neighbour rows, staged into LDS by
+// iterate_compute).  iterate_compute runs the scalar-flux rows on MFMA with
+// their k-steps split over the waves and summed in LDS in a fixed order;
+// wave 0 forms the 64 (cell, component) scalar fluxes and the tile's
+// residual record; then every thread forms its outgoing pairs.
 constexpr int kPhiPre = 4;   // scalar-flux operator fragments prefetched per wave
+constexpr int kGPre = 2;     // cells whose step constants a thread prefetches
 
 template <int CH>
 struct IterPrefetch {
-  double f0[CH], fp[kPhiPre], gv[4];
-  double hv, po;   // scalar-flux constant and previous value of this lane's (cell, component)
+  double fp[kPhiPre];
+  double cf[12];          // out coefficients of this thread's angle
+  double gq[kGPre][2];    // g' of its first cells
+  double hv, po;          // scalar-flux constant and previous value of this lane's (cell, component)
   CopyRegs cr;
 };
-
-// The scalar-flux rows 2N .. 2N+3 of G: their row tile, the first of them
-// within it, and whether the tile holds outgoing rows too.
-__device__ __forceinline__ void phi_tile(int N, int *rt, int *off, bool *shared) {
-  const int K = 2 * N;
-  *rt = K / 16;
-  *off = K % 16;
-  *shared = *off != 0;
-}
-
-// k-steps of the scalar-flux row tile handled by wave w when it is split
-// (range starts at multiples of 4; equal shares when KS allows).
-__device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *ke) {
-  if (KS % (4 * W) == 0) {
-    *kb = w * (KS / W);
-    *ke = *kb + KS / W;
-  } else {
-    *kb = ((w * KS) / W) & ~3;
-    *ke = w + 1 == W ? KS : (((w + 1) * KS) / W) & ~3;
-  }
-}
 
 // Problem shape seen by the iteration kernel: compile-time constants when the
 // kernel is built for one angle count NF (> 0), else from the arguments.
@@ -369,21 +416,21 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col = lane & 15, kq = lane >> 4;
   const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
   const int ghp = sh.Mt * 16;
-  const int row0 = wave * 16 + col;
-  if (wave < sh.Mto) load_frags<CH>(pf.f0, F + (size_t)wave * KS * 64, 0, KS);
   int prt, poff, kb, ke;
-  bool pshared;
-  phi_tile(N, &prt, &poff, &pshared);
+  phi_tile(N, &prt, &poff);
   phi_ksplit(KS, W, wave, &kb, &ke);
-  if (!pshared) load_frags<kPhiPre>(pf.fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
+  load_frags<kPhiPre>(pf.fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
+  const PairMap pm(N);
+  const double *cf = a.coef + ((size_t)t.region * N + pm.m) * kCoef;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int cl = kq + 4 * i;
-    // (used only for cells < nc and rows < K)
-    pf.gv[i] = a.gh[(size_t)(t.c0 + min(cl, t.nc - 1)) * ghp + min(row0, K - 1)];
+  for (int i = 0; i < 12; ++i) pf.cf[i] = cf[i];
+#pragma unroll
+  for (int j = 0; j < kGPre; ++j) {
+    const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
+    pf.gq[j][0] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m];
+    pf.gq[j][1] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m + 1];
   }
   const int cl = lane >> 2, comp = lane & 3;
   const int cc = t.c0 + min(cl, t.nc - 1);   // (used by wave 0 for cells < nc)
@@ -394,12 +441,13 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
 }
 
 // Computes the tile's iterate; wave 0 writes its residual record (rec).
-// Returns early (no stores) when `skip` is set (a stalled queue).
+// Returns early (no stores) when `skip` is set (a stalled queue).  With
+// `defect`, also the FP32 defect against the iterate this one started from.
 template <int CH, bool VEC, int NF>
 __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
-                                       double *phi_new, double *lds, double *phis, double2 *rec,
-                                       bool skip, bool defect) {
+                                       double *phi_new, double *lds, double *phis, double *phif,
+                                       double2 *rec, bool skip, bool defect) {
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -418,34 +466,12 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   // k-major packing k = kq*KS + ks, so k < N exactly for kq < 2.
   const double *ap = lds + (kq < 2 ? col + 2 : col) * P + kq * KS;
   int prt, poff, kb, ke;
-  bool pshared;
-  phi_tile(N, &prt, &poff, &pshared);
+  phi_tile(N, &prt, &poff);
   phi_ksplit(KS, W, wave, &kb, &ke);
   // this wave's partial scalar flux, [cell][component] in LDS (zero if none)
   double *my_phis = phis + wave * 64;
-  if (lane < 64) my_phis[lane] = 0.0;
-  for (int rt = wave; rt < sh.Mto; rt += W) {
-    const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)rt * KS * 64, KS, rt == wave, pf.f0, ap);
-    const int row = rt * 16 + col;      // operator row of this lane
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int cl = kq + 4 * i;      // cell of element i
-      if (cl >= t.nc) continue;
-      if (row < K) {
-        const int cell = t.c0 + cl;
-        const double g = rt == wave ? pf.gv[i] : a.gh[(size_t)cell * ghp + row];
-        const double v = acc[i] + g;
-        dst[(size_t)(cell + 1) * K + row] = v;
-        // the defect against the iterate this one was computed from (its own
-        // row is staged in LDS row cl+1)
-        if (defect) a.dlt[(size_t)(cell + 1) * K + row] = (float)(v - lds[(cl + 1) * P + row]);
-      } else if (pshared && rt == prt && row < K + 4) {
-        my_phis[cl * 4 + (row - K)] = acc[i];
-      }
-    }
-  }
-  if (!pshared) {
-    // k-steps kb .. ke-1 of the scalar-flux row tile; lanes col < 4 hold its rows
+  my_phis[lane] = 0.0;
+  {
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     const double *Fp = F + (size_t)prt * KS * 64;
     mma_quads<kPhiPre, VEC>(acc, pf.fp, kb, ke, ap, KS);
@@ -454,28 +480,63 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
       load_frags<CH>(f, Fp, base, ke);
       mma_quads<CH, VEC>(acc, f, base, ke, ap, KS);
     }
-    if (col < 4) {
+    if (col >= poff && col < poff + 4) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) my_phis[(kq + 4 * i) * 4 + col] = acc[i];
+      for (int i = 0; i < 4; ++i) my_phis[(kq + 4 * i) * 4 + col - poff] = acc[i];
     }
   }
   __syncthreads();
-  if (wave != 0) return;
-  // scalar flux of (cell, component) = lane: the waves' partials in order
-  const int cl = lane >> 2, comp = lane & 3;
-  double s = 0.0;
-  for (int w = 0; w < W; ++w) s += phis[w * 64 + lane];
-  double dphi = 0.0, fphi = 0.0;
-  if (cl < t.nc) {
+  if (wave == 0) {
+    // scalar flux of (cell, component) = lane: the waves' partials in order
+    const int cl = lane >> 2, comp = lane & 3;
+    double s = 0.0;
+    for (int w = 0; w < W; ++w) s += phis[w * 64 + lane];
     const double v = s + pf.hv;
-    phi_new[(size_t)(t.c0 + cl) * 4 + comp] = v;
-    if (defect) a.dphi32[(size_t)(t.c0 + cl) * 4 + comp] = (float)(v - pf.po);
-    dphi = isfinite(v) ? fabs(v - pf.po) : __builtin_nan("");
-    fphi = fabs(v);
+    phif[lane] = v;
+    double dphi = 0.0, fphi = 0.0;
+    if (cl < t.nc) {
+      phi_new[(size_t)(t.c0 + cl) * 4 + comp] = v;
+      if (defect) a.dphi32[(size_t)(t.c0 + cl) * 4 + comp] = (float)(v - pf.po);
+      dphi = isfinite(v) ? fabs(v - pf.po) : __builtin_nan("");
+      fphi = fabs(v);
+    }
+    dphi = wave_nan_max(dphi);
+    fphi = wave_max(fphi);
+    if (lane == 0) *rec = make_double2(dphi, fphi);
   }
-  dphi = wave_nan_max(dphi);
-  fphi = wave_max(fphi);
-  if (lane == 0) *rec = make_double2(dphi, fphi);
+  __syncthreads();
+  // outgoing pairs of this thread's angle for its cells
+  const PairMap pm(N);
+  if (!pm.active) return;
+  const int m = pm.m;
+  const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
+  int j = 0;
+  for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
+    const double *in = lds + (pos ? cl : cl + 2) * P + 2 * m;
+    const double *ph = phif + cl * 4;
+    const double i0 = in[0], i1 = in[1];
+    const double f0 = ph[0], f1 = ph[1], f2 = ph[2], f3 = ph[3];
+    const size_t cell = (size_t)(t.c0 + cl);
+    double g0, g1;
+    if (j < kGPre) {
+      g0 = pf.gq[j < kGPre ? j : 0][0];
+      g1 = pf.gq[j < kGPre ? j : 0][1];
+    } else {
+      g0 = a.gh[cell * ghp + 2 * m];
+      g1 = a.gh[cell * ghp + 2 * m + 1];
+    }
+    const double *c = pf.cf;
+    const double o0 = g0 + c[0] * f0 + c[1] * f1 + c[2] * f2 + c[3] * f3 + c[4] * i0 + c[5] * i1;
+    const double o1 = g1 + c[6] * f0 + c[7] * f1 + c[8] * f2 + c[9] * f3 + c[10] * i0 + c[11] * i1;
+    dst[(cell + 1) * K + 2 * m] = o0;
+    dst[(cell + 1) * K + 2 * m + 1] = o1;
+    // the defect against the iterate this one was computed from (its own
+    // row is staged in LDS row cl+1)
+    if (defect) {
+      a.dlt[(cell + 1) * K + 2 * m] = (float)(o0 - lds[(cl + 1) * P + 2 * m]);
+      a.dlt[(cell + 1) * K + 2 * m + 1] = (float)(o1 - lds[(cl + 1) * P + 2 * m + 1]);
+    }
+  }
 }
 
 // End of step for a tile.  The accepted iterate L solved every cell's
@@ -537,7 +598,7 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
   // the next step's gh from psi_{k+1/2}, so that a queued step that
   // follows needs no step start
   __syncthreads();
-  gh_gemm<CH, VEC, NF>(a, t, ldn, fg);
+  gh_compute<CH, VEC, NF>(a, t, ldn, fg);
 }
 
 // Start of step `cur` of the current solve: gh for every tile from
@@ -564,7 +625,7 @@ template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half,
                                                         int rstep) {
   extern __shared__ double lds[];
-  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64];
+  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
   const int l = cb + node;
   // iterate 0 of the step: the previous step's accepted iterate
   int b0 = ring_buf(a, l - 1, half), cur = 0;
@@ -594,7 +655,7 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
     rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
     if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
   }
-  iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis,
+  iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis, phif,
                       reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
                       stalled != 0, rstep == 2);
 }

@@ -303,4 +303,34 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
 }
 
 
+// Coefficients of the structured OCI apply for every (region, angle), from
+// A_m^{-1}: the outgoing corner rows o_t (levels t = k, k+1/2) act on the
+// scattering source s phi (s = dx Sigma_s / 4), the entering fluxes |mu| inc
+// (entering-corner columns in_t), and give the step constant from the source
+// (dx Q / 4 in every row) and the time edge (dx / (2 v dt) psi_{k-1/2} in the
+// two level-k rows).  Layout and use: oci_step.hip, "The structured apply".
+__global__ void k_out_coef(const RegionDev *regions, const double *mu, const double *ainv, int N,
+                           int R, double a, double *coef) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= R * N) return;
+  const int r = idx / N, m = idx % N;
+  const RegionDev g = regions[r];
+  const bool pos = 2 * m >= N;   // mu > 0: outgoing at the right corner
+  const int o[2] = {pos ? 1 : 0, pos ? 3 : 2};
+  const int in0 = pos ? 0 : 1, in1 = pos ? 2 : 3;
+  const double s = g.dx * g.sigs / 4.0, amu = fabs(mu[m]);
+  const double qq = g.dx * g.q / 4.0, ts = a * g.dx / 2.0;
+  const double *Ai = ainv + (size_t)idx * 16;
+  double *cf = coef + (size_t)idx * kCoef;
+  for (int t = 0; t < 2; ++t) {
+    const double *row = Ai + o[t] * 4;
+    for (int c = 0; c < 4; ++c) cf[6 * t + c] = s * row[c];
+    cf[6 * t + 4] = amu * row[in0];
+    cf[6 * t + 5] = amu * row[in1];
+    cf[12 + 3 * t] = qq * (row[0] + row[1] + row[2] + row[3]);
+    cf[13 + 3 * t] = ts * row[0];
+    cf[14 + 3 * t] = ts * row[1];
+  }
+}
+
 }  // namespace ocik
