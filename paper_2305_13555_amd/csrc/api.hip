@@ -91,6 +91,7 @@ struct oci_ctx {
   // correction solves of m_inner iterations between them
   bool mixed = false;
   int rstep = 1, m_inner = 2;
+  int pre_reduce = 0;   // the end of step reads the last iterate's e from k_reduce_rec
   // inner-count search: FP64 iterates per step seen at m_inner, the count
   // before a trial decrease and what it gave, no further decreases
   int m_q = 0, m_prev = 0, m_prev_q = 0;
@@ -624,6 +625,9 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
 #undef OCI_KERNEL
 #undef OCI_PICK
   c->fn_inner = s.tiles_in_args ? (void *)k_oci_inner<true> : (void *)k_oci_inner<false>;
+  // past a few thousand tiles one reduction of the last iterate's records
+  // beats every work-group of the end of step reducing them all
+  c->pre_reduce = c->ntiles > 2048 ? 1 : 0;
   c->lds_in = (size_t)(kTileCells + 2) * (K + 4) * sizeof(float);
   // kernels with more than 64 KiB of dynamic LDS must say so
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,
@@ -841,9 +845,22 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
       void *args[] = {&c->sa, &node, &cb, &h, &rstep};
       if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args);
     }
+    int first = 1, last = c->mixed ? 2 * L - 1 : L, pre = c->pre_reduce;
+    if (e == hipSuccess && pre) {
+      void *rargs[] = {&c->sa, &last};
+      hipKernelNodeParams kp{};
+      kp.func = (void *)k_reduce_rec;
+      kp.gridDim = dim3(1);
+      kp.blockDim = dim3(256);
+      kp.sharedMemBytes = 0;
+      kp.kernelParams = rargs;
+      kp.extra = nullptr;
+      hipGraphNode_t node;
+      e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+      if (e == hipSuccess) prev = node;
+    }
     if (e == hipSuccess) {
-      int first = 1, last = c->mixed ? 2 * L - 1 : L;
-      void *eargs[] = {&c->sa, &phi, &first, &last, &h, &rstep};
+      void *eargs[] = {&c->sa, &phi, &first, &last, &h, &rstep, &pre};
       e = add(c->fn_end, c->W_ed, c->lds_ed, eargs);
     }
   }
@@ -928,8 +945,12 @@ static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half
   // the end reads the records of iterates first .. last, one ring of them
   if (first < 1 || last < first || last - first >= c->nbuf - 1)
     return fail(c, OCI_EDEVICE, "internal: end of step over an iterate range out of bounds");
-  int rstep = c->rstep;
-  void *args[] = {&c->sa, &phi_dev, &first, &last, &half, &rstep};
+  int rstep = c->rstep, pre = c->pre_reduce;
+  if (pre) {
+    void *rargs[] = {&c->sa, &last};
+    OCI_CK(c, hipLaunchKernel((const void *)k_reduce_rec, dim3(1), dim3(256), rargs, 0, c->stream));
+  }
+  void *args[] = {&c->sa, &phi_dev, &first, &last, &half, &rstep, &pre};
   OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
                             c->stream));
   return OCI_OK;

@@ -16,7 +16,7 @@ __host__ __device__ inline uint32_t pack_tile(int region, int c0, int nc) {
   return (uint32_t)c0 | ((uint32_t)(nc - 1) << kArgTileCellBits) | ((uint32_t)region << 22);
 }
 // Per (region, angle) coefficients of the structured apply (see oci_step.hip).
-constexpr int kCoef = 18;
+constexpr int kCoef = 36;
 
 struct StepArgs {
   const TileDev *tiles;    // [ntiles] in work-group order (one work-group per tile)
@@ -109,9 +109,11 @@ template <int CH, bool ARGT, bool VEC, int NF> __global__ void k_step_begin(Step
 // iterate also writes its defect in FP32.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rstep);
+// pre: the e of iterate `last` is already in dec (k_reduce_rec ran before).
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half,
-                           int rstep);
+                           int rstep, int pre);
+__global__ void k_reduce_rec(StepArgs a, int l);
 // FP32 inner iteration i (1-based) of a mixed-precision step; ly > 0: the last
 // one, which also forms FP64 iterate ly (the FP64 iterate ly-1 read plus the
 // correction).

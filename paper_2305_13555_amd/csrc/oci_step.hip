@@ -277,7 +277,11 @@ __device__ __forceinline__ double *phi_at(const StepArgs &a, int b) {
 //   [6t + c]  s A^{-1}[o_t][c], c = 0..3   [6t + 4]  |mu| A^{-1}[o_t][in_0]
 //   [6t + 5]  |mu| A^{-1}[o_t][in_1]       [12 + 3t] (dx Q / 4) sum_c A^{-1}[o_t][c]
 //   [13 + 3t] (dx / (2 v dt)) A^{-1}[o_t][0]   [14 + 3t] (dx / (2 v dt)) A^{-1}[o_t][1]
-// (in_0, in_1: the entering-corner rows at levels k and k+1/2.)
+// (in_0, in_1: the entering-corner rows at levels k and k+1/2), and for the
+// end of step, rows r = 2, 3 of A^{-1} (psi_{k+1/2} at L and R), u = r - 2:
+//   [18 + 9u + c] s A^{-1}[r][c]   [22 + 9u] (dx/(2 v dt)) A^{-1}[r][0]
+//   [23 + 9u] (dx/(2 v dt)) A^{-1}[r][1]   [24 + 9u] |mu| A^{-1}[r][in_0]
+//   [25 + 9u] |mu| A^{-1}[r][in_1]   [26 + 9u] (dx Q / 4) sum_c A^{-1}[r][c]
 
 // Angle and cells of this thread in the per-(cell, angle) loops: angle
 // tid mod N, cells tid / N + j * cstep (threads past cstep * N idle).
@@ -315,52 +319,71 @@ __device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *k
 
 // The step constant of a tile from its psi rows in LDS (pitch P, cell c in
 // row c): h (rows 2N .. 2N+3 of gh) = the scalar-flux rows of P psi + p on
-// MFMA (wave 0; f0 its first fragments), g' (rows 0 .. 2N-1) per (cell, angle).
+// MFMA, k-steps split over the waves (f0: this wave's first fragments) and
+// summed in a fixed order; g' (rows 0 .. 2N-1) per (cell, angle).
 template <int CH, bool VEC, int NF>
 __device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const double *rows,
                                   const double (&f0)[CH]) {
+  __shared__ double hp[kMaxWaves * 64];
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
   const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
+  const int W = (int)(blockDim.x >> 6);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
   const int ghp = Mt * 16;
-  int prt, poff;
+  int prt, poff, kb, ke;
   phi_tile(N, &prt, &poff);
-  if (wave == 0) {
-    const double *F = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane;
-    const double *cp = a.c_pv + (size_t)t.region * a.c_pv_stride;
+  phi_ksplit(KS, W, wave, &kb, &ke);
+  {
+    const double *Fp = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane +
+                       (size_t)prt * KS * 64;
     const double *ap = rows + col * P + kq * KS;
-    const d4 acc = mma_rowtile_g<CH, VEC>(F + (size_t)prt * KS * 64, KS, true, f0, ap);
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    mma_quads<CH, VEC>(acc, f0, kb, ke, ap, KS);
+    for (int base = kb + CH; base < ke; base += CH) {
+      double f[CH];
+      load_frags<CH>(f, Fp, base, ke);
+      mma_quads<CH, VEC>(acc, f, base, ke, ap, KS);
+    }
+    hp[wave * 64 + lane] = 0.0;
     if (col >= poff && col < poff + 4) {
-      const double cv = cp[K + col - poff];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int cl = kq + 4 * i;
-        if (cl < t.nc) a.gh[(size_t)(t.c0 + cl) * ghp + K + col - poff] = acc[i] + cv;
-      }
+      for (int i = 0; i < 4; ++i) hp[wave * 64 + (kq + 4 * i) * 4 + col - poff] = acc[i];
     }
   }
   const PairMap pm(N);
-  if (!pm.active) return;
-  const double *cf = a.coef + ((size_t)t.region * N + pm.m) * kCoef + 12;
-  const double c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3], c4 = cf[4], c5 = cf[5];
-  for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep) {
-    const double pl = rows[cl * P + 2 * pm.m], pr = rows[cl * P + 2 * pm.m + 1];
-    double *g = a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m;
-    g[0] = c0 + c1 * pl + c2 * pr;
-    g[1] = c3 + c4 * pl + c5 * pr;
+  if (pm.active) {
+    const double *cf = a.coef + ((size_t)t.region * N + pm.m) * kCoef + 12;
+    const double c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3], c4 = cf[4], c5 = cf[5];
+    for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep) {
+      const double pl = rows[cl * P + 2 * pm.m], pr = rows[cl * P + 2 * pm.m + 1];
+      double *g = a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m;
+      g[0] = c0 + c1 * pl + c2 * pr;
+      g[1] = c3 + c4 * pl + c5 * pr;
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int cl = lane >> 2, comp = lane & 3;
+    double v = 0.0;
+    for (int w = 0; w < W; ++w) v += hp[w * 64 + lane];
+    if (cl < t.nc)
+      a.gh[(size_t)(t.c0 + cl) * ghp + K + comp] =
+          v + a.c_pv[(size_t)t.region * a.c_pv_stride + K + comp];
   }
 }
 
-// The first fragments of P's scalar-flux row tile (wave 0).
+// The first fragments of this wave's share of P's scalar-flux row tile.
 template <int CH, int NF>
 __device__ __forceinline__ void gh_frags(const StepArgs &a, const TileDev &t, double (&f0)[CH]) {
   const int N = NF ? NF : a.N, KS = (2 * N) / 4;
+  const int W = (int)(blockDim.x >> 6);
   const int lane = threadIdx.x & 63;
-  int prt, poff;
+  int prt, poff, kb, ke;
   phi_tile(N, &prt, &poff);
+  phi_ksplit(KS, W, threadIdx.x >> 6, &kb, &ke);
   const double *F = a.frag_pv + (size_t)t.region * a.frag_pv_stride + lane;
-  if ((threadIdx.x >> 6) == 0) load_frags<CH>(f0, F + (size_t)prt * KS * 64, 0, KS);
+  load_frags<CH>(f0, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
 }
 
 // gh of a tile from psi_{k-1/2} in global memory.
@@ -564,36 +587,37 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
     if (phi_out) phi_out[(size_t)t.c0 * 4 + i] = v;
     sphi[i] = v;
   }
+  // this thread's angle: the coefficients of psi_{k+1/2} at L and R (loaded
+  // while the neighbour rows are staged)
+  const PairMap pm(N);
+  const int m = pm.m;
+  const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
+  double e[18];
+  {
+    const double *cf = a.coef + ((size_t)t.region * N + m) * kCoef + 18;
+#pragma unroll
+    for (int i = 0; i < 18; ++i) e[i] = cf[i];
+  }
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
   copy_blocks_to_lds(blk, 1, K, P);
   __syncthreads();
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
-  const RegionDev g = a.regions[t.region];
-  const double qs = 0.25 * g.dx, ts = 0.5 * a.at * g.dx;   // dx/4; tau/2
-  const double *Ar = a.ainv + (size_t)t.region * N * 16;
-  for (int p = threadIdx.x; p < t.nc * N; p += blockDim.x) {
-    const int cl = p / N, m = p - cl * N;
-    const double *Ai = Ar + (size_t)m * 16;
-    const double *pp = psi_prev + (size_t)(t.c0 + cl) * K + 2 * m;
-    const double *ph = sphi + cl * 4;
-    double b[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) b[c] = qs * (g.sigs * ph[c] + g.q);
-    b[0] += ts * pp[0];
-    b[1] += ts * pp[1];
-    // entering flux: mu > 0 (m >= N/2) from the left neighbour's row into
-    // rows kL, (k+1/2)L; mu < 0 from the right neighbour's into kR, (k+1/2)R
-    const bool pos = 2 * m >= N;
-    const double amu = fabs(a.mu[m]);
-    const double *in = lds + (pos ? cl : cl + 2) * P + 2 * m;
-    b[pos ? 0 : 1] += amu * in[0];
-    b[pos ? 2 : 3] += amu * in[1];
-    const double x2 = Ai[8] * b[0] + Ai[9] * b[1] + Ai[10] * b[2] + Ai[11] * b[3];
-    const double x3 = Ai[12] * b[0] + Ai[13] * b[1] + Ai[14] * b[2] + Ai[15] * b[3];
-    psi_next[(size_t)(t.c0 + cl) * K + 2 * m] = x2;
-    psi_next[(size_t)(t.c0 + cl) * K + 2 * m + 1] = x3;
-    ldn[cl * P + 2 * m] = x2;
-    ldn[cl * P + 2 * m + 1] = x3;
+  if (pm.active) {
+    for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep) {
+      const double *pp = psi_prev + (size_t)(t.c0 + cl) * K + 2 * m;
+      const double *ph = sphi + cl * 4;
+      const double *in = lds + (pos ? cl : cl + 2) * P + 2 * m;
+      const double f0 = ph[0], f1 = ph[1], f2 = ph[2], f3 = ph[3];
+      const double pl = pp[0], pr = pp[1], i0 = in[0], i1 = in[1];
+      const double x2 = e[8] + e[0] * f0 + e[1] * f1 + e[2] * f2 + e[3] * f3 + e[4] * pl +
+                        e[5] * pr + e[6] * i0 + e[7] * i1;
+      const double x3 = e[17] + e[9] * f0 + e[10] * f1 + e[11] * f2 + e[12] * f3 + e[13] * pl +
+                        e[14] * pr + e[15] * i0 + e[16] * i1;
+      psi_next[(size_t)(t.c0 + cl) * K + 2 * m] = x2;
+      psi_next[(size_t)(t.c0 + cl) * K + 2 * m + 1] = x3;
+      ldn[cl * P + 2 * m] = x2;
+      ldn[cl * P + 2 * m + 1] = x3;
+    }
   }
   // the next step's gh from psi_{k+1/2}, so that a queued step that
   // follows needs no step start
@@ -660,6 +684,19 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
                       stalled != 0, rstep == 2);
 }
 
+// The e of iterate l from its residual records into dec (one work-group),
+// for problems with many tiles, where every work-group of the end of step
+// reducing all records would cost ntiles^2 loads.
+__global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l) {
+  __shared__ double red[2], scratch[2 * kMaxWaves];
+  const double2 *recs = reinterpret_cast<const double2 *>(a.partial) + (size_t)(l % a.nbuf) * a.ntiles;
+  RecRegs r1;
+  rec_issue(r1, recs, a.ntiles);
+  const int stalled = a.ctl->stalled;
+  rec_finish(r1, recs, a.ntiles, red, scratch);
+  if (threadIdx.x == 0 && !stalled) a.dec[l % a.nbuf] = rel_change(red[0], red[1]);
+}
+
 // End of the open step after iterates first .. last of it were launched
 // (iterates before `first` were already found undecided): the first of them
 // the stopping rule accepts (or stops at) is the step's iterate L.  The e of
@@ -671,17 +708,22 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
 // decided step advances the solve's step counter.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
-                                                  int last, int half, int rstep) {
+                                                  int last, int half, int rstep, int pre) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves];
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   const size_t slot = (size_t)a.ntiles;
   RecRegs r1;
-  rec_issue(r1, recs + (last % a.nbuf) * slot, a.ntiles);
+  if (!pre) rec_issue(r1, recs + (last % a.nbuf) * slot, a.ntiles);
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
-  rec_finish(r1, recs + (last % a.nbuf) * slot, a.ntiles, red, scratch);
-  const double e_lastv = rel_change(red[0], red[1]);
+  double e_lastv;
+  if (pre) {   // reduced by k_reduce_rec (many tiles: one reduction, not one per work-group)
+    e_lastv = a.dec[last % a.nbuf];
+  } else {
+    rec_finish(r1, recs + (last % a.nbuf) * slot, a.ntiles, red, scratch);
+    e_lastv = rel_change(red[0], red[1]);
+  }
   // the e of earlier iterates: work-group 0 of the launch after each
   auto e_of = [&](int l) { return l == last ? e_lastv : a.dec[l % a.nbuf]; };
   const int step = c.open;
@@ -872,75 +914,75 @@ template __global__ void k_oci_inner<false>(StepArgs, int, int, int);
 
 template __global__ void k_step_begin<4, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, false, true, 8>(StepArgs);
 template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, true, 16>(StepArgs);
 template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 32>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 64>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 128>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 256>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, true, 8>(StepArgs);
 template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, true, 16>(StepArgs);
 template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 32>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 64>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 128>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 256>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int, int, int);
-template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int, int, int);
+template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int, int, int, int);
 
 }  // namespace ocik

@@ -331,6 +331,16 @@ __global__ void k_out_coef(const RegionDev *regions, const double *mu, const dou
     cf[13 + 3 * t] = ts * row[0];
     cf[14 + 3 * t] = ts * row[1];
   }
+  // psi_{k+1/2} at L and R: rows 2 and 3
+  for (int u = 0; u < 2; ++u) {
+    const double *row = Ai + (2 + u) * 4;
+    for (int c = 0; c < 4; ++c) cf[18 + 9 * u + c] = s * row[c];
+    cf[22 + 9 * u] = ts * row[0];
+    cf[23 + 9 * u] = ts * row[1];
+    cf[24 + 9 * u] = amu * row[in0];
+    cf[25 + 9 * u] = amu * row[in1];
+    cf[26 + 9 * u] = qq * (row[0] + row[1] + row[2] + row[3]);
+  }
 }
 
 }  // namespace ocik

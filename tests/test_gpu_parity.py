@@ -202,6 +202,23 @@ def test_strict_converged_matches_direct(lib, seed):
         assert rel(got_si[k]["phi"], direct[k]["phi"]) < 1e-10
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_many_tiles_match_oracle(lib, precision):
+    """40,000 cells (2,500 tiles): the last iterate's residual is reduced once
+    before the end of step instead of by every work-group."""
+    p = W.config2(n_cells=40000, n_regions=4, n_angles=8, n_steps=3)
+    ref = ooci.run_oci(p, cell_data(p), 3, tol=1e-10, max_iters=1000)
+    prec = lib.OCI_PREC_FP64 if precision == "fp64" else lib.OCI_PREC_FP32
+    with lib.OciContext(p, precision=prec) as ctx:
+        phi = np.zeros((3, p.n_cells, 4))
+        rc, infos = ctx.solve(3, phi)
+    assert rc == lib.OCI_OK
+    for k in range(3):
+        if precision == "fp64":
+            assert abs(infos[k]["iterations"] - ref[k]["iterations"]) <= 1
+        assert rel(phi[k], ref[k]["phi"]) < 1e-9
+
+
 def test_config2_full_size_first_steps(lib):
     """Full-size multi-region problem (10,000 cells, S_32): first 3 steps."""
     p = W.config2(n_steps=3)
