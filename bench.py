@@ -24,6 +24,7 @@ if ROOT not in sys.path:
 
 METRIC = "OCI cell·angle updates/s + time-to-1e-6 per step: learned/mixed vs plain OCI"
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_MFMA_TFLOPS = 78.6
 
 
 def algorithmic_bytes_per_cell_iteration(n_angles):
@@ -41,14 +42,14 @@ def algorithmic_bytes_per_cell_step(n_angles):
     return 8 * (10 * n_angles + 12)
 
 
-ITERATIONS_PER_LAUNCH = 1   # iterates per launch of the iteration kernel
-ITERATION_KERNEL = "k_oci_iterate"
+ITERATIONS_PER_LAUNCH = 2   # iterates per launch of the iteration kernel
+ITERATION_KERNEL = "k_oci_iterate2"
 
 
-def roofline_launch_seconds(oci, prob, stream, steps=9):
+def roofline_launch_seconds(oci, prob, stream, steps=9, hi=32, lo=16):
     """Per-launch time of the iteration kernel on the workload's cells, regions and
     angles, with v = inf and tol = 0 so that every launch does the full work
-    (the kernel's work does not depend on the values).  Steps of 32 and of 16
+    (the kernel's work does not depend on the values).  Steps of hi and of lo
     iterates each run as one replayed graph (the launches and the end of
     step), timed with HIP events on the library's stream; the per-launch time
     is the difference of the median step times over the extra launches, which
@@ -57,7 +58,7 @@ def roofline_launch_seconds(oci, prob, stream, steps=9):
     import dataclasses
     roof = dataclasses.replace(prob, speed=float("inf"), name=prob.name + ", v = inf")
     med = {}
-    for n in (32, 16):
+    for n in (hi, lo):
         with oci.OciContext(roof, stream=stream, tol=0.0, max_iters=n) as cr:
             cr.step()
             ms = []
@@ -68,7 +69,7 @@ def roofline_launch_seconds(oci, prob, stream, steps=9):
                                        % (n, info))
                 ms.append(info["ms"])
             med[n] = float(np.median(ms))
-    return (med[32] - med[16]) * 1e-3 / (16 // ITERATIONS_PER_LAUNCH)
+    return (med[hi] - med[lo]) * 1e-3 / ((hi - lo) // ITERATIONS_PER_LAUNCH)
 
 
 def copy_calibration(torch, mib):
@@ -133,6 +134,42 @@ def cpu_baseline(prob, n_steps, gpu_phi):
             "host_cpu_count": os.cpu_count()}, err
 
 
+def large_case(oci, torch, stream):
+    """The 64-region, 200,000-cell S_64 problem (50 steps, tol 1e-6), where an
+    iteration moves 634 MB and does 6.8 GFLOP: plain FP64 and mixed ms per
+    time step, and the iteration kernel's per-launch time against both
+    rooflines (FP64 MFMA for the (2N+4) x 2N product, HBM for the bytes)."""
+    from paper_2305_13555_amd import workloads
+    prob = workloads.config3()
+    J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
+    out = {"workload": prob.name + ", tol 1e-6"}
+    for prec, key in ((oci.OCI_PREC_FP64, "plain_fp64"), (oci.OCI_PREC_FP32, "mixed")):
+        with oci.OciContext(prob, stream=stream, precision=prec) as cx:
+            cx.solve(T)
+            torch.cuda.synchronize()
+            cx.set_state(None, 0)
+            t = time.perf_counter()
+            rc, infos = cx.solve(T)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / T
+        if rc < 0 or any(i["status"] != oci.OCI_OK for i in infos):
+            raise RuntimeError("large-case solve failed: rc=%d" % rc)
+        out[key] = {"ms_per_time_step": ms,
+                    "iterations_per_step": float(np.mean([i["iterations"] for i in infos])),
+                    "launches_per_step": float(np.mean([i["launches"] for i in infos]))}
+    out["mixed_speedup"] = out["plain_fp64"]["ms_per_time_step"] / out["mixed"]["ms_per_time_step"]
+    t = roofline_launch_seconds(oci, prob, stream, steps=5, hi=16, lo=8)
+    flops = 2.0 * (2 * N + 4) * (2 * N) * J
+    nbytes = algorithmic_bytes_per_cell_iteration(N) * J
+    out["iteration_kernel"] = {
+        "us_per_launch": t * 1e6,
+        "mfma_tflops": flops / t / 1e12, "mfma_frac": flops / t / 1e12 / PEAK_FP64_MFMA_TFLOPS,
+        "hbm_gbs": nbytes / t / 1e9, "hbm_frac": nbytes / t / 1e9 / PEAK_HBM_GBS,
+        "roofline_us": max(flops / (PEAK_FP64_MFMA_TFLOPS * 1e12), nbytes / (PEAK_HBM_GBS * 1e9)) * 1e6,
+    }
+    return out
+
+
 def mixed_precision(oci, torch, prob, stream, plain_phi, plain_ms):
     """The same solve with OCI_PREC_FP32 (FP64 defect correction, FP32 inner
     iterations): ms per time step at tol 1e-10 and at 1e-6 (each after a
@@ -173,6 +210,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 200,000-cell S_64 comparison")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the k_oci_iterate roofline batches and a 64 MiB copy "
                          "(for hardware-counter runs)")
@@ -238,6 +277,7 @@ def main():
         t6_ms = (time.perf_counter() - t) * 1e3 / T
         t6_its = float(np.mean([i["iterations"] for i in inf6]))
     mixed = mixed_precision(oci, torch, prob, stream, gpu_phi, wall * 1e3 / (args.steps * T))
+    large = None if args.no_large else large_case(oci, torch, stream)
     with oci.OciContext(prob, stream=stream) as cs:
         ms, its = [], []
         for _ in range(10):
@@ -297,6 +337,7 @@ def main():
         "oci_over_si_speedup": si_ms / oci_ms,
         "parity_vs_oracle_rel": err,
         "mixed": mixed,
+        "large_case": large,
     }
     print(json.dumps(line))
     ctx.close()

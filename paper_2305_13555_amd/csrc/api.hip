@@ -101,6 +101,8 @@ struct oci_ctx {
   // kernels for the chosen operator batch width CH
   int CH = 16;
   void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr, *fn_inner = nullptr;
+  void *fn_iter2 = nullptr;   // two iterates per launch (plain FP64 batches)
+  size_t lds_it2 = 0;
   std::string err;
   StepArgs sa{};
   SiArgs si{};
@@ -383,6 +385,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->W_ed = std::min(c->Met, 4);
   const int P = K + 2;
   c->lds_it = (size_t)(kTileCells + 2) * P * sizeof(double);
+  c->lds_it2 = (size_t)(kBlkA + kBlkB) * P * sizeof(double);
   c->lds_pv = (size_t)kTileCells * P * sizeof(double);
   c->lds_ed = (size_t)(2 * kTileCells + 2) * P * sizeof(double);
   c->si_blocks = (J * 4 + 255) / 256;
@@ -543,6 +546,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.mu = c->d_mu;
   s.ainv = c->d_ainv;
   s.coef = c->d_coef;
+  s.cell_region = c->d_cell_region;
   s.at = c->a;
   s.gh = c->d_gh;
   s.nbuf = c->nbuf;
@@ -611,6 +615,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   do {                                                            \
     c->fn_begin = OCI_KERNEL(k_step_begin, CHV, ARGT);            \
     c->fn_iter = OCI_KERNEL(k_oci_iterate, CHV, ARGT);            \
+    c->fn_iter2 = OCI_KERNEL(k_oci_iterate2, CHV, ARGT);          \
     c->fn_end = OCI_KERNEL(k_step_end, CHV, ARGT);                \
   } while (0)
   if (s.tiles_in_args) {
@@ -632,6 +637,8 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   // kernels with more than 64 KiB of dynamic LDS must say so
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it));
+  OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter2,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it2));
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_begin,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_pv));
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_end,
@@ -672,8 +679,8 @@ static int launch_batch(oci_ctx *c, bool si, int cb, int count, int half = 0) {
   for (int i = 1; i <= count; ++i) {
     int node = i;
     if (!si) {
-      int rstep = 1;
-      void *args[] = {&c->sa, &node, &cb, &half, &rstep};
+      int rstep = 1, nred = 1;
+      void *args[] = {&c->sa, &node, &cb, &half, &rstep, &nred};
       OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), args, c->lds_it,
                                 c->stream));
     } else {
@@ -835,19 +842,34 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   int rstep = c->rstep;
   for (int s = 0; s < G && e == hipSuccess; ++s) {
     int h = (half + s) & 1;
-    for (int o = 1; o <= L && e == hipSuccess; ++o) {
-      for (int i = 1; o > 1 && i <= m && e == hipSuccess; ++i) {
-        int ii = i, ly = i == m ? 2 * (o - 1) : 0;
-        void *iargs[] = {&c->sa, &ii, &ly, &h};
-        e = add(c->fn_inner, c->W_it, c->lds_in, iargs);
+    if (c->mixed) {
+      for (int o = 1; o <= L && e == hipSuccess; ++o) {
+        for (int i = 1; o > 1 && i <= m && e == hipSuccess; ++i) {
+          int ii = i, ly = i == m ? 2 * (o - 1) : 0;
+          void *iargs[] = {&c->sa, &ii, &ly, &h};
+          e = add(c->fn_inner, c->W_it, c->lds_in, iargs);
+        }
+        int node = 2 * o - 1, cb = 0, nred = 1;
+        void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
+        if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args);
       }
-      int node = c->mixed ? 2 * o - 1 : o, cb = 0;
-      void *args[] = {&c->sa, &node, &cb, &h, &rstep};
-      if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args);
+    } else {   // iterates 1, 2 | 3, 4 | ... two per launch, an odd last one alone
+      for (int o = 1; o + 1 <= L && e == hipSuccess; o += 2) {
+        int node = o, cb = 0;
+        void *args[] = {&c->sa, &node, &cb, &h};
+        e = add(c->fn_iter2, c->W_it, c->lds_it2, args);
+      }
+      if ((L & 1) && e == hipSuccess) {
+        int node = L, cb = 0, nred = L > 1 ? 2 : 1;
+        void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
+        e = add(c->fn_iter, c->W_it, c->lds_it, args);
+      }
     }
-    int first = 1, last = c->mixed ? 2 * L - 1 : L, pre = c->pre_reduce;
+    const bool two = !c->mixed && !(L & 1);   // the batch ends with a two-iterate launch
+    int first = 1, last = c->mixed ? 2 * L - 1 : L, nred = two ? 2 : 1;
+    int pre = c->pre_reduce, mode = pre | (two ? 2 : 0);
     if (e == hipSuccess && pre) {
-      void *rargs[] = {&c->sa, &last};
+      void *rargs[] = {&c->sa, &last, &nred};
       hipKernelNodeParams kp{};
       kp.func = (void *)k_reduce_rec;
       kp.gridDim = dim3(1);
@@ -860,7 +882,7 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
       if (e == hipSuccess) prev = node;
     }
     if (e == hipSuccess) {
-      void *eargs[] = {&c->sa, &phi, &first, &last, &h, &rstep, &pre};
+      void *eargs[] = {&c->sa, &phi, &first, &last, &h, &rstep, &mode};
       e = add(c->fn_end, c->W_ed, c->lds_ed, eargs);
     }
   }
@@ -934,8 +956,8 @@ static int launch_outer(oci_ctx *c, int lprev, int half) {
     OCI_CK(c, hipLaunchKernel(c->fn_inner, dim3(c->grid), dim3(64 * c->W_it), iargs, c->lds_in,
                               c->stream));
   }
-  int node = lprev + 2, cb = 0, rstep = 2;
-  void *args[] = {&c->sa, &node, &cb, &half, &rstep};
+  int node = lprev + 2, cb = 0, rstep = 2, nred = 1;
+  void *args[] = {&c->sa, &node, &cb, &half, &rstep, &nred};
   OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), args, c->lds_it,
                             c->stream));
   return OCI_OK;
@@ -945,12 +967,13 @@ static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half
   // the end reads the records of iterates first .. last, one ring of them
   if (first < 1 || last < first || last - first >= c->nbuf - 1)
     return fail(c, OCI_EDEVICE, "internal: end of step over an iterate range out of bounds");
-  int rstep = c->rstep, pre = c->pre_reduce;
+  // (single-iterate launches only: resumed steps)
+  int rstep = c->rstep, pre = c->pre_reduce, nred = 1, mode = pre;
   if (pre) {
-    void *rargs[] = {&c->sa, &last};
+    void *rargs[] = {&c->sa, &last, &nred};
     OCI_CK(c, hipLaunchKernel((const void *)k_reduce_rec, dim3(1), dim3(256), rargs, 0, c->stream));
   }
-  void *args[] = {&c->sa, &phi_dev, &first, &last, &half, &rstep, &pre};
+  void *args[] = {&c->sa, &phi_dev, &first, &last, &half, &rstep, &mode};
   OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
                             c->stream));
   return OCI_OK;

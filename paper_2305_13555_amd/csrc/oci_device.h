@@ -103,6 +103,12 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Sum over the wave in a fixed order (the same on every run).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
 __device__ __forceinline__ int wave_or(int v) {
   for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
   return v;

@@ -17,6 +17,9 @@ __host__ __device__ inline uint32_t pack_tile(int region, int c0, int nc) {
 }
 // Per (region, angle) coefficients of the structured apply (see oci_step.hip).
 constexpr int kCoef = 36;
+// LDS rows of the two-iterate kernel: iterate l-1 of cells c0-2 .. c0+17,
+// iterate l of cells c0-1 .. c0+16.
+constexpr int kBlkA = 16 + 4, kBlkB = 16 + 2;
 
 struct StepArgs {
   const TileDev *tiles;    // [ntiles] in work-group order (one work-group per tile)
@@ -38,6 +41,7 @@ struct StepArgs {
   const double *mu;        // [N]
   const double *ainv;      // [R][N][16] A_m^{-1} per region and angle
   const double *coef;      // [R][N][kCoef] outgoing-pair and step-constant coefficients
+  const int *cell_region;  // [J] (halo cells of the two-iterate kernel)
   double at;               // 1/(v dt), 0 for v = inf
   double *gh;              // [J][Mt*16]
   int nbuf;                // ring slots per half (iterate l of a step in slot l % nbuf)
@@ -106,14 +110,20 @@ template <int CH, bool ARGT, bool VEC, int NF> __global__ void k_step_begin(Step
 // half: the ring half of the step's iterates.  rstep: 1 for plain FP64 OCI;
 // 2 for the mixed-precision step, where the FP64 iterates are every other one
 // (iterate l even is formed by the FP32 inner iterations) and each FP64
-// iterate also writes its defect in FP32.
+// iterate also writes its defect in FP32.  nred: iterates of the previous
+// launch whose residual this launch reduces (2 after a two-iterate launch).
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rstep);
-// pre: the e of iterate `last` is already in dec (k_reduce_rec ran before).
+__global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rstep, int nred);
+// Iterates l = cb + node and l + 1 in one launch (plain FP64 OCI).
+template <int CH, bool ARGT, bool VEC, int NF>
+__global__ void k_oci_iterate2(StepArgs a, int node, int cb, int half);
+// mode bit 0: the e of the trailing iterates are already in dec (k_reduce_rec
+// ran before); bit 1: two trailing iterates (the batch ended with a
+// two-iterate launch), else one.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half,
-                           int rstep, int pre);
-__global__ void k_reduce_rec(StepArgs a, int l);
+                           int rstep, int mode);
+__global__ void k_reduce_rec(StepArgs a, int l, int n);
 // FP32 inner iteration i (1-based) of a mixed-precision step; ly > 0: the last
 // one, which also forms FP64 iterate ly (the FP64 iterate ly-1 read plus the
 // correction).

@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // work-groups' path.  Nothing is stored while a queued solve is stalled.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half,
-                                                        int rstep) {
+                                                        int rstep, int nred) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
   const int l = cb + node;
@@ -672,29 +672,307 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
     a.ctl->open = cur;
     a.ctl->base_buf = b0;
   }
-  const int lp = l - rstep;   // the previous iterate with records
-  if (blockIdx.x == 0 && lp >= 1) {
-    RecRegs r1;
-    rec_issue(r1, recs + (lp % a.nbuf) * slot, a.ntiles);
-    rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
-    if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
+  // the e of the previous launch's iterate(s) with records: l - rstep (and
+  // l - 2 rstep after a two-iterate launch)
+  if (blockIdx.x == 0) {
+    for (int j = nred; j >= 1; --j) {
+      const int lp = l - j * rstep;
+      if (lp < 1) continue;
+      RecRegs r1;
+      rec_issue(r1, recs + (lp % a.nbuf) * slot, a.ntiles);
+      rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
+      if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
+    }
   }
   iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis, phif,
                       reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
                       stalled != 0, rstep == 2);
 }
 
+// ---------------------------------------------------------------------------
+// Two iterates per launch
+// ---------------------------------------------------------------------------
+// Iterate l+1 of a tile needs iterate l of its own cells and of the cell on
+// each side (its halo cells).  The launch stages iterate l-1 of the cells
+// c0-2 .. c0+nc+1 (LDS block A, row r <-> cell c0-2+r), computes iterate l of
+// its own cells as k_oci_iterate does and of the halo cells' entering halves
+// (their scalar flux as four dot products on the vector units, with their
+// own region's operator), keeps iterate l in LDS (block B, row r <-> cell
+// c0-1+r) and computes iterate l+1 of its own cells from it.  Both iterates
+// are stored with their residual records.  Every halo value is computed from
+// the same inputs by the same arithmetic as by the tile that owns the cell,
+// so the two copies agree to rounding order of the dot products.
+
+// Left (pos = true) or right halo cell hc at iterate l: its scalar flux from
+// its incident fluxes (entry k < N from the row of its right neighbour, k >= N
+// from its left neighbour's), then its outgoing pairs in the angles entering
+// the tile into `orow`.  One wave.
+template <int NF>
+__device__ inline void halo_iterate(const StepArgs &a, int hc, const double *left,
+                                    const double *right, bool pos, double *orow) {
+  const int N = NF ? NF : a.N, K = 2 * N, KS = K / 4;
+  const int lane = threadIdx.x & 63;
+  const int ghp = (NF ? (2 * NF + 4 + 15) / 16 : a.Mt) * 16;
+  const int r = a.cell_region[hc];
+  const double *F = a.frag_it + (size_t)r * a.frag_it_stride;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = lane; k < K; k += 64) {
+    const double v = k < N ? right[k] : left[k];
+    const int kq = k / KS, ks = k - kq * KS;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int row = K + c;   // scalar-flux rows of G, packed k-major
+      acc[c] += F[((size_t)(row >> 4) * KS + ks) * 64 + (row & 15) + 16 * kq] * v;
+    }
+  }
+  const double *gh = a.gh + (size_t)hc * ghp;
+  double ph[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) ph[c] = wave_sum(acc[c]) + gh[K + c];
+  for (int j = lane; j < N / 2; j += 64) {
+    const int m = pos ? N / 2 + j : j;
+    const double *cf = a.coef + ((size_t)r * N + m) * kCoef;
+    const double *in = (pos ? left : right) + 2 * m;   // the halo cell's entering flux
+    const double i0 = in[0], i1 = in[1];
+    orow[2 * m] = gh[2 * m] + cf[0] * ph[0] + cf[1] * ph[1] + cf[2] * ph[2] + cf[3] * ph[3] +
+                  cf[4] * i0 + cf[5] * i1;
+    orow[2 * m + 1] = gh[2 * m + 1] + cf[6] * ph[0] + cf[7] * ph[1] + cf[8] * ph[2] +
+                      cf[9] * ph[3] + cf[10] * i0 + cf[11] * i1;
+  }
+}
+
+// Reflecting edge: a ghost row takes the boundary cell's mirror-angle values
+// (left ghost: entries N .. 2N-1, right ghost: 0 .. N-1).
+__device__ __forceinline__ void mirror_row(double *ghost, const double *cell, int N, bool left) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int e = left ? N + i : i;
+    const int m = e >> 1, tl = e & 1;
+    ghost[e] = cell[2 * (N - 1 - m) + tl];
+  }
+}
+
+// The scalar-flux rows of one iterate of the tile's own cells from the rows
+// at `base` (row 0 = cell c0-1): MFMA partials per wave into phis, summed by
+// wave 0 with h into phif, stored to phi_out with the residual record against
+// po; returns wave 0's value for its (cell, component).
+template <int CH, bool VEC, int NF>
+__device__ inline double own_phi(const StepArgs &a, const TileDev &t, const double *base,
+                                 const double (&fp)[kPhiPre], double hv, double po,
+                                 double *phis, double *phif, double *phi_out, double2 *rec) {
+  const IterShape<NF> sh(a);
+  const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  int prt, poff, kb, ke;
+  phi_tile(N, &prt, &poff);
+  phi_ksplit(KS, W, wave, &kb, &ke);
+  double *my_phis = phis + wave * 64;
+  my_phis[lane] = 0.0;
+  {
+    const double *Fp = a.frag_it + (size_t)t.region * a.frag_it_stride + lane +
+                       (size_t)prt * KS * 64;
+    const double *ap = base + (kq < 2 ? col + 2 : col) * P + kq * KS;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    mma_quads<kPhiPre, VEC>(acc, fp, kb, ke, ap, KS);
+    for (int b = kb + kPhiPre; b < ke; b += CH) {
+      double f[CH];
+      load_frags<CH>(f, Fp, b, ke);
+      mma_quads<CH, VEC>(acc, f, b, ke, ap, KS);
+    }
+    if (col >= poff && col < poff + 4) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) my_phis[(kq + 4 * i) * 4 + col - poff] = acc[i];
+    }
+  }
+  __syncthreads();
+  double v = 0.0;
+  if (wave == 0) {
+    const int cl = lane >> 2, comp = lane & 3;
+    double s = 0.0;
+    for (int w = 0; w < W; ++w) s += phis[w * 64 + lane];
+    v = s + hv;
+    phif[lane] = v;
+    double dphi = 0.0, fphi = 0.0;
+    if (cl < t.nc) {
+      phi_out[(size_t)(t.c0 + cl) * 4 + comp] = v;
+      dphi = isfinite(v) ? fabs(v - po) : __builtin_nan("");
+      fphi = fabs(v);
+    }
+    dphi = wave_nan_max(dphi);
+    fphi = wave_max(fphi);
+    if (lane == 0) *rec = make_double2(dphi, fphi);
+  }
+  __syncthreads();
+  return v;
+}
+
+// Outgoing pairs of one iterate of the own cells (this thread's angle and
+// cells) from the rows at `base` (row 0 = cell c0-1) and phif, to dst and,
+// when given, to the LDS rows at `keep` (same layout as base).
+template <int NF>
+__device__ inline void own_pairs(const StepArgs &a, const TileDev &t, const double *base,
+                                 const double *phif, const double (&cf)[12],
+                                 const double (&gq)[kGPre][2], double *dst, double *keep) {
+  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
+  const int ghp = (NF ? (2 * NF + 4 + 15) / 16 : a.Mt) * 16;
+  const PairMap pm(N);
+  if (!pm.active) return;
+  const int m = pm.m;
+  const bool pos = 2 * m >= N;
+  int j = 0;
+  for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
+    const double *in = base + (pos ? cl : cl + 2) * P + 2 * m;
+    const double *ph = phif + cl * 4;
+    const double i0 = in[0], i1 = in[1];
+    const double f0 = ph[0], f1 = ph[1], f2 = ph[2], f3 = ph[3];
+    const size_t cell = (size_t)(t.c0 + cl);
+    double g0, g1;
+    if (j < kGPre) {
+      g0 = gq[j < kGPre ? j : 0][0];
+      g1 = gq[j < kGPre ? j : 0][1];
+    } else {
+      g0 = a.gh[cell * ghp + 2 * m];
+      g1 = a.gh[cell * ghp + 2 * m + 1];
+    }
+    const double o0 = g0 + cf[0] * f0 + cf[1] * f1 + cf[2] * f2 + cf[3] * f3 + cf[4] * i0 +
+                      cf[5] * i1;
+    const double o1 = g1 + cf[6] * f0 + cf[7] * f1 + cf[8] * f2 + cf[9] * f3 + cf[10] * i0 +
+                      cf[11] * i1;
+    dst[(cell + 1) * K + 2 * m] = o0;
+    dst[(cell + 1) * K + 2 * m + 1] = o1;
+    if (keep) {
+      keep[(cl + 1) * P + 2 * m] = o0;
+      keep[(cl + 1) * P + 2 * m + 1] = o1;
+    }
+  }
+}
+
+template <int CH, bool ARGT, bool VEC, int NF>
+__global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, int cb, int half) {
+  extern __shared__ double lds[];
+  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
+  const IterShape<NF> sh(a);
+  const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l = cb + node;   // iterates l and l+1
+  int b0 = ring_buf(a, l - 1, half), cur = 0;
+  if (l == 1) {
+    b0 = a.ctl->fin_buf;
+    cur = a.ctl->cur;
+  }
+  const double *src = out_at(a, b0);
+  const double *phi_old = phi_at(a, b0);
+  const int b1 = ring_buf(a, l, half), b2 = ring_buf(a, l + 1, half);
+  const TileDev t = blk_desc<ARGT>(a);
+  const int ti = blockIdx.x;
+  double *A = lds, *B = lds + kBlkA * P;
+  const int ghp = sh.Mt * 16;
+  // loads that need no LDS: the first operator chunk of this wave's share of
+  // the scalar-flux row tile (the same for both iterates), this thread's out
+  // coefficients and step constants, h and the old scalar flux, and the rows
+  // of iterate l-1 (ghosted rows c0-1 .. c0+nc+2, clamped to the mesh)
+  double fp[kPhiPre], cf[12], gq[kGPre][2];
+  {
+    int prt, poff, kb, ke;
+    phi_tile(N, &prt, &poff);
+    phi_ksplit(KS, W, wave, &kb, &ke);
+    const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
+    load_frags<kPhiPre>(fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
+  }
+  const PairMap pm(N);
+  {
+    const double *c = a.coef + ((size_t)t.region * N + pm.m) * kCoef;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) cf[i] = c[i];
+#pragma unroll
+    for (int j = 0; j < kGPre; ++j) {
+      const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
+      gq[j][0] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m];
+      gq[j][1] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m + 1];
+    }
+  }
+  double hv, po;
+  {
+    const int cl = lane >> 2, comp = lane & 3;
+    const int cc = t.c0 + min(cl, t.nc - 1);
+    hv = a.gh[(size_t)cc * ghp + K + comp];
+    po = phi_old[(size_t)cc * 4 + comp];
+  }
+  const int g_lo = max(t.c0 - 1, 0), g_hi = min(t.c0 + t.nc + 2, a.J + 1);
+  const int r_lo = g_lo - t.c0 + 1;   // block A row of ghosted row g_lo
+  const RowBlock blk[1] = {RowBlock{src + (size_t)g_lo * K, A + r_lo * P, g_hi - g_lo + 1,
+                                    kBlkA - r_lo}};
+  CopyRegs cr;
+  issue_copy(cr, blk, 1, K);
+  const int stalled = a.ctl->stalled;
+  const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
+  const size_t slot = (size_t)a.ntiles;
+  if (l == 1 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
+    a.ctl->open = cur;
+    a.ctl->base_buf = b0;
+  }
+  if (blockIdx.x == 0) {   // the e of the previous launch's iterates
+    for (int lp = l - 2; lp <= l - 1; ++lp) {
+      if (lp < 1) continue;
+      RecRegs r1;
+      rec_issue(r1, recs + (lp % a.nbuf) * slot, a.ntiles);
+      rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
+      if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
+    }
+  }
+  finish_copy(cr, blk, 1, K, P);
+  __syncthreads();
+  if (stalled) return;
+  const bool hl = t.c0 > 0, hr = t.c0 + t.nc < a.J;   // halo cells (else ghost rows)
+  // reflecting edges next to a halo cell: its outer ghost mirrors it
+  if (hl && t.c0 == 1 && a.bcl == kBcReflect) mirror_row(A, A + P, N, true);
+  if (hr && t.c0 + t.nc == a.J - 1 && a.bcr == kBcReflect)
+    mirror_row(A + (t.nc + 3) * P, A + (t.nc + 2) * P, N, false);
+  // reflecting edges of the tile itself (rows c0-1 .. c0+nc from A + P)
+  reflect_ghosts(A + P, P, t, N, a.J, a.bcl, a.bcr);
+  // iterate l: halo cells (one wave each), own cells
+  const int wl = W - 1, wr = W >= 2 ? W - 2 : W - 1;
+  if (hl && wave == wl) halo_iterate<NF>(a, t.c0 - 1, A, A + 2 * P, true, B);
+  if (hr && wave == wr)
+    halo_iterate<NF>(a, t.c0 + t.nc, A + (t.nc + 1) * P, A + (t.nc + 3) * P, false,
+                     B + (t.nc + 1) * P);
+  double2 *rl = reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti;
+  double2 *rl2 = reinterpret_cast<double2 *>(a.partial) + ((l + 1) % a.nbuf) * slot + ti;
+  const double vl = own_phi<CH, VEC, NF>(a, t, A + P, fp, hv, po, phis, phif, phi_at(a, b1), rl);
+  own_pairs<NF>(a, t, A + P, phif, cf, gq, out_at(a, b1), B);
+  __syncthreads();
+  // iterate l at the mesh edges: ghost rows of B
+  if (!hl || !hr) {
+    if (!hl) {
+      if (a.bcl == kBcReflect) mirror_row(B, B + P, N, true);
+      else for (int i = N + threadIdx.x; i < K; i += blockDim.x) B[i] = A[P + i];
+    }
+    if (!hr) {
+      if (a.bcr == kBcReflect) mirror_row(B + (t.nc + 1) * P, B + t.nc * P, N, false);
+      else for (int i = threadIdx.x; i < N; i += blockDim.x)
+        B[(t.nc + 1) * P + i] = A[(t.nc + 2) * P + i];
+    }
+    __syncthreads();
+  }
+  // iterate l+1 of the own cells from B
+  own_phi<CH, VEC, NF>(a, t, B, fp, hv, vl, phis, phif, phi_at(a, b2), rl2);
+  own_pairs<NF>(a, t, B, phif, cf, gq, out_at(a, b2), nullptr);
+}
+
 // The e of iterate l from its residual records into dec (one work-group),
 // for problems with many tiles, where every work-group of the end of step
 // reducing all records would cost ntiles^2 loads.
-__global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l) {
+__global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n) {
   __shared__ double red[2], scratch[2 * kMaxWaves];
-  const double2 *recs = reinterpret_cast<const double2 *>(a.partial) + (size_t)(l % a.nbuf) * a.ntiles;
-  RecRegs r1;
-  rec_issue(r1, recs, a.ntiles);
   const int stalled = a.ctl->stalled;
-  rec_finish(r1, recs, a.ntiles, red, scratch);
-  if (threadIdx.x == 0 && !stalled) a.dec[l % a.nbuf] = rel_change(red[0], red[1]);
+  for (int j = l - n + 1; j <= l; ++j) {   // iterates l-n+1 .. l
+    const double2 *recs =
+        reinterpret_cast<const double2 *>(a.partial) + (size_t)(j % a.nbuf) * a.ntiles;
+    RecRegs r1;
+    rec_issue(r1, recs, a.ntiles);
+    rec_finish(r1, recs, a.ntiles, red, scratch);
+    if (threadIdx.x == 0 && !stalled) a.dec[j % a.nbuf] = rel_change(red[0], red[1]);
+  }
 }
 
 // End of the open step after iterates first .. last of it were launched
@@ -708,24 +986,37 @@ __global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l) {
 // decided step advances the solve's step counter.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
-                                                  int last, int half, int rstep, int pre) {
+                                                  int last, int half, int rstep, int mode) {
   extern __shared__ double lds[];
-  __shared__ double red[2], scratch[2 * kMaxWaves];
+  __shared__ double red[2], red2[2], scratch[2 * kMaxWaves];
+  const bool pre = mode & 1, two = (mode >> 1) & 1;
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   const size_t slot = (size_t)a.ntiles;
-  RecRegs r1;
-  if (!pre) rec_issue(r1, recs + (last % a.nbuf) * slot, a.ntiles);
+  RecRegs r1, r2;
+  if (!pre) {
+    rec_issue(r1, recs + (last % a.nbuf) * slot, a.ntiles);
+    if (two) rec_issue(r2, recs + ((last - 1) % a.nbuf) * slot, a.ntiles);
+  }
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
-  double e_lastv;
-  if (pre) {   // reduced by k_reduce_rec (many tiles: one reduction, not one per work-group)
+  // the e of the trailing iterate(s): reduced by k_reduce_rec (many tiles:
+  // one reduction, not one per work-group) or here
+  double e_lastv, e_prevv = -1.0;
+  if (pre) {
     e_lastv = a.dec[last % a.nbuf];
+    if (two) e_prevv = a.dec[(last - 1) % a.nbuf];
   } else {
     rec_finish(r1, recs + (last % a.nbuf) * slot, a.ntiles, red, scratch);
     e_lastv = rel_change(red[0], red[1]);
+    if (two) {
+      rec_finish(r2, recs + ((last - 1) % a.nbuf) * slot, a.ntiles, red2, scratch);
+      e_prevv = rel_change(red2[0], red2[1]);
+    }
   }
-  // the e of earlier iterates: work-group 0 of the launch after each
-  auto e_of = [&](int l) { return l == last ? e_lastv : a.dec[l % a.nbuf]; };
+  // the e of earlier iterates: work-group 0 of a later launch
+  auto e_of = [&](int l) {
+    return l == last ? e_lastv : (two && l == last - 1) ? e_prevv : a.dec[l % a.nbuf];
+  };
   const int step = c.open;
   int status = kRunning, L = last;
   double e_acc = -1.0;
@@ -758,6 +1049,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
     } else {
       ct->stalled = 1;
       a.dec[last % a.nbuf] = e_lastv;   // for the resumed end
+      if (two) a.dec[(last - 1) % a.nbuf] = e_prevv;
     }
   }
   if (!decided) return;
@@ -909,80 +1201,104 @@ __global__ void k_to_f32(const double *src, float *dst, size_t n) {
     dst[e] = (float)src[e];
 }
 
+template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<8, false, false, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<8, false, true, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, false, false, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<4, false, true, 8>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<8, false, true, 16>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 32>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 64>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 128>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 256>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<4, true, false, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<4, true, true, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<8, true, false, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<8, true, true, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, true, false, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 0>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<4, true, true, 8>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<8, true, true, 16>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 32>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 64>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 128>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 256>(StepArgs, int, int, int);
 template __global__ void k_oci_inner<true>(StepArgs, int, int, int);
 template __global__ void k_oci_inner<false>(StepArgs, int, int, int);
 
 template __global__ void k_step_begin<4, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, false, true, 8>(StepArgs);
-template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, true, 16>(StepArgs);
-template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 32>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 64>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 128>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 256>(StepArgs);
-template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, false, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 0>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, true, 8>(StepArgs);
-template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, true, 16>(StepArgs);
-template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 32>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 64>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 128>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 256>(StepArgs);
-template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int, int, int, int);
 
 }  // namespace ocik
