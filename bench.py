@@ -85,11 +85,11 @@ def copy_calibration(torch, mib):
 
 
 KERNEL_SOURCES = ("oci_step.hip", "oci_device.h", "oci_kernels.h")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_oci_iterate_c2_hbm_traffic.txt")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_oci_iterate2_c2_hbm_traffic.txt")
 
 
 def measured_traffic():
-    """HBM bytes per k_oci_iterate launch from the committed counter summary
+    """HBM bytes per launch of the iteration kernel from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
     sources have changed since the counters were taken."""
     import hashlib
