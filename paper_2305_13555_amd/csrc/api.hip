@@ -33,6 +33,7 @@ namespace {
 thread_local std::string g_last_error;
 
 constexpr int kMaxBatch = 64;   // iteration launches per replayed batch
+static_assert(kMaxBatch + 1 <= ocik::kMaxRing, "the end of step holds one ring of e values");
 constexpr int kMaxInner = 64;   // FP32 inner iterations per correction (mixed precision)
 
 }  // namespace
@@ -681,7 +682,7 @@ static int launch_batch(oci_ctx *c, bool si, int cb, int count, int half = 0) {
     if (!si) {
       int rstep = 1, nred = 1;
       void *args[] = {&c->sa, &node, &cb, &half, &rstep, &nred};
-      OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), args, c->lds_it,
+      OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid + 1), dim3(64 * c->W_it), args, c->lds_it,
                                 c->stream));
     } else {
       void *args[] = {&c->si, &node, &cb};
@@ -823,10 +824,12 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   hipGraph_t g;
   OCI_CK(c, hipGraphCreate(&g, 0));
   hipGraphNode_t prev = nullptr;
-  auto add = [&](void *fn, int W, size_t lds, void **args) -> hipError_t {
+  // (extra: work-groups past the tiles; the iteration kernels have one that
+  // reduces the previous launch's residual records)
+  auto add = [&](void *fn, int W, size_t lds, void **args, int extra = 0) -> hipError_t {
     hipKernelNodeParams kp{};
     kp.func = fn;
-    kp.gridDim = dim3(c->grid);
+    kp.gridDim = dim3(c->grid + extra);
     kp.blockDim = dim3(64 * W);
     kp.sharedMemBytes = (unsigned)lds;
     kp.kernelParams = args;
@@ -851,18 +854,18 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
         }
         int node = 2 * o - 1, cb = 0, nred = 1;
         void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
-        if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args);
+        if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args, 1);
       }
     } else {   // iterates 1, 2 | 3, 4 | ... two per launch, an odd last one alone
       for (int o = 1; o + 1 <= L && e == hipSuccess; o += 2) {
         int node = o, cb = 0;
         void *args[] = {&c->sa, &node, &cb, &h};
-        e = add(c->fn_iter2, c->W_it, c->lds_it2, args);
+        e = add(c->fn_iter2, c->W_it, c->lds_it2, args, 1);
       }
       if ((L & 1) && e == hipSuccess) {
         int node = L, cb = 0, nred = L > 1 ? 2 : 1;
         void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
-        e = add(c->fn_iter, c->W_it, c->lds_it, args);
+        e = add(c->fn_iter, c->W_it, c->lds_it, args, 1);
       }
     }
     const bool two = !c->mixed && !(L & 1);   // the batch ends with a two-iterate launch
@@ -958,7 +961,7 @@ static int launch_outer(oci_ctx *c, int lprev, int half) {
   }
   int node = lprev + 2, cb = 0, rstep = 2, nred = 1;
   void *args[] = {&c->sa, &node, &cb, &half, &rstep, &nred};
-  OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid), dim3(64 * c->W_it), args, c->lds_it,
+  OCI_CK(c, hipLaunchKernel(c->fn_iter, dim3(c->grid + 1), dim3(64 * c->W_it), args, c->lds_it,
                             c->stream));
   return OCI_OK;
 }

@@ -17,6 +17,9 @@ __host__ __device__ inline uint32_t pack_tile(int region, int c0, int nc) {
 }
 // Per (region, angle) coefficients of the structured apply (see oci_step.hip).
 constexpr int kCoef = 36;
+// Iterate buffers per ring half at most (iterate ranges of one end of step
+// span fewer).
+constexpr int kMaxRing = 65;
 // LDS rows of the two-iterate kernel: iterate l-1 of cells c0-2 .. c0+17,
 // iterate l of cells c0-1 .. c0+16.
 constexpr int kBlkA = 16 + 4, kBlkB = 16 + 2;

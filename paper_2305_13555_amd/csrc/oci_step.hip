@@ -645,12 +645,34 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // index and that buffer for the end of step.  Work-group 0 also reduces the
 // residual records iterate l-1 left and stores its e in dec, off the other
 // work-groups' path.  Nothing is stored while a queued solve is stalled.
+// The extra work-group of an iteration launch (block index ntiles): the e of
+// iterates l - j*rstep, j = nred .. 1, from their residual records into dec,
+// beside the tiles instead of on one tile's path.
+__device__ inline void reduce_prev(const StepArgs &a, int l, int rstep, int nred, double *red,
+                                   double *scratch) {
+  const int stalled = a.ctl->stalled;
+  const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
+  const size_t slot = (size_t)a.ntiles;
+  for (int j = nred; j >= 1; --j) {
+    const int lp = l - j * rstep;
+    if (lp < 1) continue;
+    RecRegs r1;
+    rec_issue(r1, recs + (lp % a.nbuf) * slot, a.ntiles);
+    rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
+    if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
+  }
+}
+
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half,
                                                         int rstep, int nred) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
   const int l = cb + node;
+  if (blockIdx.x == a.ntiles) {
+    reduce_prev(a, l, rstep, nred, red, scratch);
+    return;
+  }
   // iterate 0 of the step: the previous step's accepted iterate
   int b0 = ring_buf(a, l - 1, half), cur = 0;
   if (l == 1) {
@@ -666,23 +688,10 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   IterPrefetch<CH> pf;
   iterate_prefetch<CH, NF>(pf, a, t, src, phi_old, lds);
   const int stalled = a.ctl->stalled;
-  const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   const size_t slot = (size_t)a.ntiles;
   if (l == 1 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
     a.ctl->open = cur;
     a.ctl->base_buf = b0;
-  }
-  // the e of the previous launch's iterate(s) with records: l - rstep (and
-  // l - 2 rstep after a two-iterate launch)
-  if (blockIdx.x == 0) {
-    for (int j = nred; j >= 1; --j) {
-      const int lp = l - j * rstep;
-      if (lp < 1) continue;
-      RecRegs r1;
-      rec_issue(r1, recs + (lp % a.nbuf) * slot, a.ntiles);
-      rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
-      if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
-    }
   }
   iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis, phif,
                       reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
@@ -855,6 +864,10 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l = cb + node;   // iterates l and l+1
+  if (blockIdx.x == a.ntiles) {   // the e of the previous launch's iterates
+    reduce_prev(a, l, 1, 2, red, scratch);
+    return;
+  }
   int b0 = ring_buf(a, l - 1, half), cur = 0;
   if (l == 1) {
     b0 = a.ctl->fin_buf;
@@ -905,20 +918,10 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   CopyRegs cr;
   issue_copy(cr, blk, 1, K);
   const int stalled = a.ctl->stalled;
-  const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   const size_t slot = (size_t)a.ntiles;
   if (l == 1 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
     a.ctl->open = cur;
     a.ctl->base_buf = b0;
-  }
-  if (blockIdx.x == 0) {   // the e of the previous launch's iterates
-    for (int lp = l - 2; lp <= l - 1; ++lp) {
-      if (lp < 1) continue;
-      RecRegs r1;
-      rec_issue(r1, recs + (lp % a.nbuf) * slot, a.ntiles);
-      rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
-      if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
-    }
   }
   finish_copy(cr, blk, 1, K, P);
   __syncthreads();
@@ -999,12 +1002,18 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   }
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
+  const TileDev t = blk_desc<ARGT>(a);
+  // the e of the earlier iterates (written by later launches), all at once
+  __shared__ double sdec[kMaxRing + 1];
+  const int l0 = first - 1 >= 1 ? first - 1 : first;
+  for (int i = threadIdx.x; i <= last - l0; i += blockDim.x) sdec[i] = a.dec[(l0 + i) % a.nbuf];
+  __syncthreads();
   // the e of the trailing iterate(s): reduced by k_reduce_rec (many tiles:
   // one reduction, not one per work-group) or here
   double e_lastv, e_prevv = -1.0;
   if (pre) {
-    e_lastv = a.dec[last % a.nbuf];
-    if (two) e_prevv = a.dec[(last - 1) % a.nbuf];
+    e_lastv = sdec[last - l0];
+    if (two) e_prevv = sdec[last - 1 - l0];
   } else {
     rec_finish(r1, recs + (last % a.nbuf) * slot, a.ntiles, red, scratch);
     e_lastv = rel_change(red[0], red[1]);
@@ -1013,9 +1022,8 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
       e_prevv = rel_change(red2[0], red2[1]);
     }
   }
-  // the e of earlier iterates: work-group 0 of a later launch
   auto e_of = [&](int l) {
-    return l == last ? e_lastv : (two && l == last - 1) ? e_prevv : a.dec[l % a.nbuf];
+    return l == last ? e_lastv : (two && l == last - 1) ? e_prevv : sdec[l - l0];
   };
   const int step = c.open;
   int status = kRunning, L = last;
@@ -1054,7 +1062,6 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   }
   if (!decided) return;
   const int parity = c.psi_base ^ (step & 1);
-  const TileDev t = blk_desc<ARGT>(a);
   // iterate L was computed from iterate L-1 (iterate 0: the step's start)
   const double *src = out_at(a, L == 1 ? c.base_buf : ring_buf(a, L - 1, half));
   tile_end<CH, VEC, NF>(a, t, src, parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
