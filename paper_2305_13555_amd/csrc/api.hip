@@ -446,7 +446,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_dec, (size_t)c->nbuf));
   for (int b = 0; b < 2; ++b) OCI_TRY(dalloc(c, &c->d_psi[b], (size_t)J * K));
   OCI_TRY(dalloc(c, &c->d_phi_res, (size_t)J * 4));
-  OCI_TRY(dalloc(c, &c->d_partial, (size_t)c->nbuf * c->ntiles * 2));
+  OCI_TRY(dalloc(c, &c->d_partial, (size_t)2 * c->nbuf * c->ntiles * 2));
   OCI_TRY(dalloc(c, &c->d_ainv, (size_t)R * N * 16));
   OCI_TRY(dalloc(c, &c->d_coef, (size_t)R * N * kCoef));
   OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(N / 2) * J * 4));
@@ -843,6 +843,11 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   void *bargs[] = {&c->sa};
   if (begin) e = add(c->fn_begin, c->W_pv, c->lds_pv, bargs);
   int rstep = c->rstep;
+  // plain OCI: the end of every step but the graph's last also computes
+  // iterate 1 of the next step (needs L >= 2, so that the next step still has
+  // a launch of its own to open it)
+  const bool fuse_ok = !c->mixed && L >= 2;
+  bool last_pair = false;
   for (int s = 0; s < G && e == hipSuccess; ++s) {
     int h = (half + s) & 1;
     if (c->mixed) {
@@ -856,23 +861,33 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
         void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
         if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args, 1);
       }
-    } else {   // iterates 1, 2 | 3, 4 | ... two per launch, an odd last one alone
-      for (int o = 1; o + 1 <= L && e == hipSuccess; o += 2) {
+    } else {
+      // iterates start, start+1 | ... two per launch, an odd last one alone;
+      // after a fused end of step (every step of the graph but the first)
+      // iterate 1 is already done
+      const int start = (s > 0 && fuse_ok) ? 2 : 1;
+      bool pair_before = false;
+      int o = start;
+      for (; o + 1 <= L && e == hipSuccess; o += 2) {
         int node = o, cb = 0;
         void *args[] = {&c->sa, &node, &cb, &h};
         e = add(c->fn_iter2, c->W_it, c->lds_it2, args, 1);
+        pair_before = true;
       }
-      if ((L & 1) && e == hipSuccess) {
-        int node = L, cb = 0, nred = L > 1 ? 2 : 1;
+      if (o == L && e == hipSuccess) {
+        int node = L, cb = 0, nred = pair_before ? 2 : 1;
         void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
         e = add(c->fn_iter, c->W_it, c->lds_it, args, 1);
+        pair_before = false;
       }
+      last_pair = pair_before;
     }
-    const bool two = !c->mixed && !(L & 1);   // the batch ends with a two-iterate launch
+    const bool two = !c->mixed && last_pair;   // the batch ends with a two-iterate launch
+    const bool fuse = fuse_ok && s + 1 < G;
     int first = 1, last = c->mixed ? 2 * L - 1 : L, nred = two ? 2 : 1;
-    int pre = c->pre_reduce, mode = pre | (two ? 2 : 0);
+    int pre = c->pre_reduce, mode = pre | (two ? 2 : 0) | (fuse ? 4 : 0);
     if (e == hipSuccess && pre) {
-      void *rargs[] = {&c->sa, &last, &nred};
+      void *rargs[] = {&c->sa, &last, &nred, &h};
       hipKernelNodeParams kp{};
       kp.func = (void *)k_reduce_rec;
       kp.gridDim = dim3(1);
@@ -973,7 +988,7 @@ static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half
   // (single-iterate launches only: resumed steps)
   int rstep = c->rstep, pre = c->pre_reduce, nred = 1, mode = pre;
   if (pre) {
-    void *rargs[] = {&c->sa, &last, &nred};
+    void *rargs[] = {&c->sa, &last, &nred, &half};
     OCI_CK(c, hipLaunchKernel((const void *)k_reduce_rec, dim3(1), dim3(256), rargs, 0, c->stream));
   }
   void *args[] = {&c->sa, &phi_dev, &first, &last, &half, &rstep, &mode};

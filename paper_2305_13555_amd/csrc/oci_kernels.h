@@ -54,7 +54,8 @@ struct StepArgs {
   size_t phi_stride;
   double *psi0, *psi1;     // [J][2N]
   double *phi_res;         // [J][4]
-  double *partial;         // [nbuf][ntiles] double2 residual records of iterate l in slot l % nbuf
+  double *partial;         // [2][nbuf][ntiles] double2 residual records: iterate l of a step
+                           //   of ring half h in slot h*nbuf + l % nbuf
   double *dec;             // [nbuf] e of iterate l in slot l % nbuf (NaN: not finite)
   StepCtl *ctl;
   StepRecord *rec;         // [steps] records of a queued solve
@@ -122,11 +123,12 @@ template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_oci_iterate2(StepArgs a, int node, int cb, int half);
 // mode bit 0: the e of the trailing iterates are already in dec (k_reduce_rec
 // ran before); bit 1: two trailing iterates (the batch ended with a
-// two-iterate launch), else one.
+// two-iterate launch), else one; bit 2: a decided step also computes iterate
+// 1 of the next step (plain OCI; the next step's launches start at 2).
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half,
                            int rstep, int mode);
-__global__ void k_reduce_rec(StepArgs a, int l, int n);
+__global__ void k_reduce_rec(StepArgs a, int l, int n, int half);
 // FP32 inner iteration i (1-based) of a mixed-precision step; ly > 0: the last
 // one, which also forms FP64 iterate ly (the FP64 iterate ly-1 read plus the
 // correction).

@@ -258,6 +258,12 @@ __device__ __forceinline__ double *out_at(const StepArgs &a, int b) {
 __device__ __forceinline__ double *phi_at(const StepArgs &a, int b) {
   return a.phib + (size_t)b * a.phi_stride;
 }
+// Residual-record slot of iterate l of a step of ring half `half` (one set of
+// nbuf per half, so that an end of step that starts the next step's iterate
+// 1 never overwrites records it still reads).
+__device__ __forceinline__ size_t rec_slot(const StepArgs &a, int l, int half) {
+  return (size_t)(half * a.nbuf + l % a.nbuf) * a.ntiles;
+}
 
 // ---------------------------------------------------------------------------
 // The structured apply
@@ -648,17 +654,16 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // The extra work-group of an iteration launch (block index ntiles): the e of
 // iterates l - j*rstep, j = nred .. 1, from their residual records into dec,
 // beside the tiles instead of on one tile's path.
-__device__ inline void reduce_prev(const StepArgs &a, int l, int rstep, int nred, double *red,
-                                   double *scratch) {
+__device__ inline void reduce_prev(const StepArgs &a, int l, int rstep, int nred, int half,
+                                   double *red, double *scratch) {
   const int stalled = a.ctl->stalled;
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
-  const size_t slot = (size_t)a.ntiles;
   for (int j = nred; j >= 1; --j) {
     const int lp = l - j * rstep;
     if (lp < 1) continue;
     RecRegs r1;
-    rec_issue(r1, recs + (lp % a.nbuf) * slot, a.ntiles);
-    rec_finish(r1, recs + (lp % a.nbuf) * slot, a.ntiles, red, scratch);
+    rec_issue(r1, recs + rec_slot(a, lp, half), a.ntiles);
+    rec_finish(r1, recs + rec_slot(a, lp, half), a.ntiles, red, scratch);
     if (threadIdx.x == 0 && !stalled) a.dec[lp % a.nbuf] = rel_change(red[0], red[1]);
   }
 }
@@ -670,14 +675,17 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
   const int l = cb + node;
   if (blockIdx.x == a.ntiles) {
-    reduce_prev(a, l, rstep, nred, red, scratch);
+    reduce_prev(a, l, rstep, nred, half, red, scratch);
     return;
   }
-  // iterate 0 of the step: the previous step's accepted iterate
-  int b0 = ring_buf(a, l - 1, half), cur = 0;
-  if (l == 1) {
-    b0 = a.ctl->fin_buf;
+  // iterate 0 of the step: the previous step's accepted iterate.  The step's
+  // first launch (l = 1, or l = 2 when the previous end of step computed
+  // iterate 1) opens it.
+  int b0 = ring_buf(a, l - 1, half), cur = 0, fb = 0;
+  if (l <= 2) {
+    fb = a.ctl->fin_buf;
     cur = a.ctl->cur;
+    if (l == 1) b0 = fb;
   }
   const double *src = out_at(a, b0);
   double *dst = out_at(a, ring_buf(a, l, half));
@@ -688,13 +696,12 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   IterPrefetch<CH> pf;
   iterate_prefetch<CH, NF>(pf, a, t, src, phi_old, lds);
   const int stalled = a.ctl->stalled;
-  const size_t slot = (size_t)a.ntiles;
-  if (l == 1 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
+  if (l <= 2 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
     a.ctl->open = cur;
-    a.ctl->base_buf = b0;
+    a.ctl->base_buf = fb;
   }
   iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis, phif,
-                      reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti,
+                      reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l, half) + ti,
                       stalled != 0, rstep == 2);
 }
 
@@ -865,13 +872,14 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l = cb + node;   // iterates l and l+1
   if (blockIdx.x == a.ntiles) {   // the e of the previous launch's iterates
-    reduce_prev(a, l, 1, 2, red, scratch);
+    reduce_prev(a, l, 1, 2, half, red, scratch);
     return;
   }
-  int b0 = ring_buf(a, l - 1, half), cur = 0;
-  if (l == 1) {
-    b0 = a.ctl->fin_buf;
+  int b0 = ring_buf(a, l - 1, half), cur = 0, fb = 0;
+  if (l <= 2) {   // the step's first launch opens it (as in k_oci_iterate)
+    fb = a.ctl->fin_buf;
     cur = a.ctl->cur;
+    if (l == 1) b0 = fb;
   }
   const double *src = out_at(a, b0);
   const double *phi_old = phi_at(a, b0);
@@ -918,10 +926,9 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   CopyRegs cr;
   issue_copy(cr, blk, 1, K);
   const int stalled = a.ctl->stalled;
-  const size_t slot = (size_t)a.ntiles;
-  if (l == 1 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
+  if (l <= 2 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
     a.ctl->open = cur;
-    a.ctl->base_buf = b0;
+    a.ctl->base_buf = fb;
   }
   finish_copy(cr, blk, 1, K, P);
   __syncthreads();
@@ -939,8 +946,8 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   if (hr && wave == wr)
     halo_iterate<NF>(a, t.c0 + t.nc, A + (t.nc + 1) * P, A + (t.nc + 3) * P, false,
                      B + (t.nc + 1) * P);
-  double2 *rl = reinterpret_cast<double2 *>(a.partial) + (l % a.nbuf) * slot + ti;
-  double2 *rl2 = reinterpret_cast<double2 *>(a.partial) + ((l + 1) % a.nbuf) * slot + ti;
+  double2 *rl = reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l, half) + ti;
+  double2 *rl2 = reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l + 1, half) + ti;
   const double vl = own_phi<CH, VEC, NF>(a, t, A + P, fp, hv, po, phis, phif, phi_at(a, b1), rl);
   own_pairs<NF>(a, t, A + P, phif, cf, gq, out_at(a, b1), B);
   __syncthreads();
@@ -965,12 +972,11 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
 // The e of iterate l from its residual records into dec (one work-group),
 // for problems with many tiles, where every work-group of the end of step
 // reducing all records would cost ntiles^2 loads.
-__global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n) {
+__global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, int half) {
   __shared__ double red[2], scratch[2 * kMaxWaves];
   const int stalled = a.ctl->stalled;
   for (int j = l - n + 1; j <= l; ++j) {   // iterates l-n+1 .. l
-    const double2 *recs =
-        reinterpret_cast<const double2 *>(a.partial) + (size_t)(j % a.nbuf) * a.ntiles;
+    const double2 *recs = reinterpret_cast<const double2 *>(a.partial) + rec_slot(a, j, half);
     RecRegs r1;
     rec_issue(r1, recs, a.ntiles);
     rec_finish(r1, recs, a.ntiles, red, scratch);
@@ -991,14 +997,13 @@ template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
                                                   int last, int half, int rstep, int mode) {
   extern __shared__ double lds[];
-  __shared__ double red[2], red2[2], scratch[2 * kMaxWaves];
-  const bool pre = mode & 1, two = (mode >> 1) & 1;
+  __shared__ double red[2], red2[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
+  const bool pre = mode & 1, two = (mode >> 1) & 1, fuse = (mode >> 2) & 1;
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
-  const size_t slot = (size_t)a.ntiles;
   RecRegs r1, r2;
   if (!pre) {
-    rec_issue(r1, recs + (last % a.nbuf) * slot, a.ntiles);
-    if (two) rec_issue(r2, recs + ((last - 1) % a.nbuf) * slot, a.ntiles);
+    rec_issue(r1, recs + rec_slot(a, last, half), a.ntiles);
+    if (two) rec_issue(r2, recs + rec_slot(a, last - 1, half), a.ntiles);
   }
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
@@ -1015,10 +1020,10 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
     e_lastv = sdec[last - l0];
     if (two) e_prevv = sdec[last - 1 - l0];
   } else {
-    rec_finish(r1, recs + (last % a.nbuf) * slot, a.ntiles, red, scratch);
+    rec_finish(r1, recs + rec_slot(a, last, half), a.ntiles, red, scratch);
     e_lastv = rel_change(red[0], red[1]);
     if (two) {
-      rec_finish(r2, recs + ((last - 1) % a.nbuf) * slot, a.ntiles, red2, scratch);
+      rec_finish(r2, recs + rec_slot(a, last - 1, half), a.ntiles, red2, scratch);
       e_prevv = rel_change(red2[0], red2[1]);
     }
   }
@@ -1067,6 +1072,19 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   tile_end<CH, VEC, NF>(a, t, src, parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
                         phi_at(a, ring_buf(a, L, half)),
                         phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
+  if (!fuse) return;
+  // iterate 1 of the next step (ring half half^1) from the accepted iterate:
+  // every input is this tile's (its step constant, just formed) or already in
+  // memory (the neighbours' accepted outgoing fluxes), so one launch fewer
+  __syncthreads();
+  const int bl = ring_buf(a, L, half), bn = ring_buf(a, 1, half ^ 1);
+  IterPrefetch<CH> pf;
+  iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds);
+  iterate_compute<CH, VEC, NF>(pf, a, t, out_at(a, bl), out_at(a, bn), phi_at(a, bn), lds, phis,
+                               phif,
+                               reinterpret_cast<double2 *>(a.partial) +
+                                   rec_slot(a, 1, half ^ 1) + blockIdx.x,
+                               false, false);
 }
 
 // ---------------------------------------------------------------------------
