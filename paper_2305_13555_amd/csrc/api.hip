@@ -785,18 +785,20 @@ constexpr int kColdOuter = 3;  // mixed precision: FP64 iterates of such a step
 
 // Per-step records of a solve; the step graphs hold the device pointer, so
 // growing the buffer drops them.
+// The records live in pinned, device-mapped host memory: the end of step
+// writes them there, and the host reads a window's records once its end
+// event has completed (no copy on the stream between windows).
 static int grow_records(oci_ctx *c, int n) {
   if (n <= c->rec_cap) return OCI_OK;
   drop_step_graphs(c);
-  if (c->d_rec) (void)hipFree(c->d_rec);
   if (c->h_rec) (void)hipHostFree(c->h_rec);
   c->d_rec = nullptr;
   c->h_rec = nullptr;
   c->rec_cap = 0;
   c->sa.rec = nullptr;
   const int cap = std::max(n, 1024);
-  OCI_CK(c, hipMalloc(&c->d_rec, cap * sizeof(StepRecord)));
-  OCI_CK(c, hipHostMalloc((void **)&c->h_rec, cap * sizeof(StepRecord), hipHostMallocDefault));
+  OCI_CK(c, hipHostMalloc((void **)&c->h_rec, cap * sizeof(StepRecord), hipHostMallocMapped));
+  OCI_CK(c, hipHostGetDevicePointer((void **)&c->d_rec, c->h_rec, 0));
   c->rec_cap = cap;
   c->sa.rec = c->d_rec;
   return OCI_OK;
@@ -998,8 +1000,8 @@ static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half
 }
 
 // Queue steps first .. first+count-1 (whole-step graphs of `batch` iteration
-// launches; step `first` uses ring half `half`), then their records' copy to
-// the host, between two events.
+// launches; step `first` uses ring half `half`) between two events; their
+// records reach the host through mapped memory.
 static int enqueue_window(oci_ctx *c, int first, int count, int batch, int half,
                           double *phi_dev, hipEvent_t ev_start, hipEvent_t ev_end) {
   OCI_CK(c, hipEventRecord(ev_start, c->stream));
@@ -1015,8 +1017,6 @@ static int enqueue_window(oci_ctx *c, int first, int count, int batch, int half,
     left -= G;
     half ^= G & 1;
   }
-  OCI_CK(c, hipMemcpyAsync(c->h_rec + first, c->d_rec + first, count * sizeof(StepRecord),
-                           hipMemcpyDeviceToHost, c->stream));
   OCI_CK(c, hipEventRecord(ev_end, c->stream));
   return OCI_OK;
 }
@@ -1323,7 +1323,6 @@ extern "C" void oci_destroy(oci_ctx *c) {
   for (void *q : c->allocs) (void)hipFree(q);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   if (c->h_rec) (void)hipHostFree(c->h_rec);
-  if (c->d_rec) (void)hipFree(c->d_rec);
   for (hipEvent_t e : {c->ev0, c->ev1, c->evA, c->evB, c->evW[0][0], c->evW[0][1], c->evW[1][0],
                        c->evW[1][1]})
     if (e) (void)hipEventDestroy(e);
