@@ -206,12 +206,27 @@ static int upload_ghosts(oci_ctx *c) {
 // iterate buffer are set once at setup and never written) and scalar flux in
 // buffer 0, zero lagged reflection, control block cleared (accepted iterate
 // in buffer 0).
-static int reset_iterate(oci_ctx *c) {
+// (psi: also clear the time edge psi[0].)
+static int reset_iterate(oci_ctx *c, bool psi = false) {
+  static_assert(sizeof(StepCtl) % sizeof(double) == 0, "the control block clears as doubles");
   const int K = 2 * c->N;
-  OCI_CK(c, hipMemsetAsync(c->d_outb + K, 0, (size_t)c->J * K * sizeof(double), c->stream));
-  OCI_CK(c, hipMemsetAsync(c->d_phib, 0, (size_t)c->J * 4 * sizeof(double), c->stream));
-  OCI_CK(c, hipMemsetAsync(c->d_lag, 0, (size_t)2 * c->N * sizeof(double), c->stream));
-  OCI_CK(c, hipMemsetAsync(c->d_ctl, 0, sizeof(StepCtl), c->stream));
+  ZeroRanges z{};
+  z.p[0] = c->d_outb + K;
+  z.n[0] = (size_t)c->J * K;
+  z.p[1] = c->d_phib;
+  z.n[1] = (size_t)c->J * 4;
+  z.p[2] = c->d_lag;
+  z.n[2] = (size_t)2 * c->N;
+  z.p[3] = reinterpret_cast<double *>(c->d_ctl);
+  z.n[3] = sizeof(StepCtl) / sizeof(double);
+  z.count = 4;
+  if (psi) {
+    z.p[4] = c->d_psi[0];
+    z.n[4] = (size_t)c->J * K;
+    z.count = 5;
+  }
+  hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, c->stream, z);
+  OCI_CK(c, hipGetLastError());
   c->last_si_iters = 0;
   c->gh_valid = false;
   c->batch_hint = 0;
@@ -1275,16 +1290,14 @@ extern "C" int oci_set_state(oci_ctx *c, const double *psi_edge, int64_t step) {
     for (size_t i = 0; i < cnt; ++i)
       if (!std::isfinite(psi_edge[i])) return fail(c, OCI_EINVAL, "psi_edge must be finite");
   }
-  int rc = reset_iterate(c);
+  int rc = reset_iterate(c, psi_edge == nullptr);   // (psi = 0 with the reset)
   if (rc) return rc;
   c->parity = 0;
-  if (psi_edge) {
+  if (psi_edge) {   // read before the call returns
     OCI_CK(c, hipMemcpyAsync(c->d_psi[0], psi_edge, cnt * sizeof(double), hipMemcpyHostToDevice,
                              c->stream));
-  } else {
-    OCI_CK(c, hipMemsetAsync(c->d_psi[0], 0, cnt * sizeof(double), c->stream));
+    OCI_CK(c, hipStreamSynchronize(c->stream));
   }
-  OCI_CK(c, hipStreamSynchronize(c->stream));
   c->steps = step;
   c->have_flux = false;
   return OCI_OK;

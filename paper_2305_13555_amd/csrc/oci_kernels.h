@@ -96,7 +96,15 @@ struct SiArgs {
   StepCtl *ctl;
 };
 
+// Ranges of doubles to clear in one launch (k_zero).
+struct ZeroRanges {
+  double *p[6];
+  size_t n[6];
+  int count;
+};
+
 // setup.hip
+__global__ void k_zero(ZeroRanges z);
 __global__ void k_build_system(const RegionDev *regions, const double *mu, const double *w,
                                int N, double a, double *ws_M, double *ws_X);
 __global__ void k_lu_solve(int N, double *ws_M, double *ws_X, int *bad);

@@ -343,4 +343,14 @@ __global__ void k_out_coef(const RegionDev *regions, const double *mu, const dou
   }
 }
 
+// Clear z.count ranges of doubles (one launch instead of one fill per range).
+__global__ void k_zero(ZeroRanges z) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (int r = 0; r < z.count; ++r) {
+    double *p = z.p[r];
+    const size_t n = z.n[r];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+  }
+}
+
 }  // namespace ocik
