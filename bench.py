@@ -172,6 +172,46 @@ def large_case(oci, torch, stream):
     return out
 
 
+def ensemble_case(oci, torch, n_problems=32):
+    """Batched ensemble: problems 0 .. n_problems-1 of the ensemble generator
+    (500 - 100,000 cells log-uniform, S8 - S128, 16 regions, 20 steps, tol
+    1e-10), each context on its own stream.  Cell-angle updates per second
+    over the whole ensemble solved one problem after another, and with
+    oci_solve_batch driving the problems concurrently (each after a warm-up
+    solve of the same problems)."""
+    from paper_2305_13555_amd import workloads
+    probs = [workloads.config5(i) for i in range(n_problems)]
+    T = probs[0].n_steps
+    streams = [torch.cuda.Stream() for _ in probs]
+    ctxs = [oci.OciContext(p, stream=s) for p, s in zip(probs, streams)]
+    try:
+        oci.oci_solve_batch(ctxs, T)
+        out = {"workload": "%d ensemble problems (%d - %d cells, S8 - S128, 16 regions), "
+                           "%d steps each, tol 1e-10" % (
+                               n_problems, min(p.n_cells for p in probs),
+                               max(p.n_cells for p in probs), T),
+               "cell_angle_pairs": int(sum(p.n_cells * p.n_angles for p in probs))}
+        for mode in ("sequential", "batch"):
+            for c in ctxs:
+                c.set_state(None, 0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if mode == "sequential":
+                infos = [c.solve(T)[1] for c in ctxs]
+            else:
+                infos = oci.oci_solve_batch(ctxs, T)[1]
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            upd = sum(i["iterations"] * p.n_cells * p.n_angles
+                      for p, inf in zip(probs, infos) for i in inf)
+            out[mode] = {"seconds": wall, "cell_angle_updates_per_s": upd / wall}
+        out["batch_speedup"] = out["sequential"]["seconds"] / out["batch"]["seconds"]
+        return out
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def mixed_precision(oci, torch, prob, stream, plain_phi, plain_ms):
     """The same solve with OCI_PREC_FP32 (FP64 defect correction, FP32 inner
     iterations): ms per time step at tol 1e-10 and at 1e-6 (each after a
@@ -213,7 +253,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-large", action="store_true",
-                    help="skip the 200,000-cell S_64 comparison")
+                    help="skip the 200,000-cell S_64 comparison and the ensemble")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the k_oci_iterate roofline batches and a 64 MiB copy "
                          "(for hardware-counter runs)")
@@ -280,6 +320,7 @@ def main():
         t6_its = float(np.mean([i["iterations"] for i in inf6]))
     mixed = mixed_precision(oci, torch, prob, stream, gpu_phi, wall * 1e3 / (args.steps * T))
     large = None if args.no_large else large_case(oci, torch, stream)
+    ensemble = None if args.no_large else ensemble_case(oci, torch)
     with oci.OciContext(prob, stream=stream) as cs:
         ms, its = [], []
         for _ in range(10):
@@ -340,6 +381,7 @@ def main():
         "parity_vs_oracle_rel": err,
         "mixed": mixed,
         "large_case": large,
+        "ensemble": ensemble,
     }
     print(json.dumps(line))
     ctx.close()

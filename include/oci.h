@@ -170,6 +170,19 @@ int si_step(oci_ctx *c, oci_step_info *info);
 int oci_solve(oci_ctx *c, int32_t n_steps, double *phi_out, int32_t phi_out_on_device,
               oci_step_info *infos);
 
+/* A batch of independent problems: oci_solve(ctx[i], n_steps, phi_out[i],
+ * phi_out_on_device, infos[i]) for i < n_ctx, with the contexts driven
+ * concurrently by up to n_threads host threads (0: min(n_ctx, 16)), each
+ * taking the next unsolved context, so that the problems' launches overlap on
+ * the GPU.  The contexts must be distinct, and to overlap they must be bound
+ * to distinct streams.  phi_out and infos may be NULL, or hold NULL entries.
+ * Returns the first negative code in context order (that context's
+ * oci_last_error has the message; the other contexts still ran), else
+ * OCI_NOT_CONVERGED if any step of any context did not converge, else
+ * OCI_OK.  OCI_EINVAL: n_ctx < 1, a NULL or repeated context, n_steps < 0. */
+int oci_solve_batch(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, double **phi_out,
+                    int32_t phi_out_on_device, oci_step_info **infos, int32_t n_threads);
+
 /* Scalar flux of the last completed step, [J][4] (host or device).
  * OCI_ESTATE before the first step. */
 int oci_get_flux(oci_ctx *c, double *phi, int32_t on_device);

@@ -15,12 +15,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstddef>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "oci.h"
@@ -452,8 +454,10 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   c->phi_stride = (size_t)J * 4;
   {
     const size_t per = (c->out_stride + c->phi_stride) * sizeof(double);
-    const size_t budget = (size_t)8 << 30;
-    c->nbuf = (int)std::max<size_t>(3, std::min<size_t>(kMaxBatch + 1, budget / (2 * per)));
+    // 1 GiB of rings per context (so that many contexts fit side by side),
+    // but at least 9 slots: batches of up to 8 iterates per step
+    const size_t budget = (size_t)1 << 30;
+    c->nbuf = (int)std::max<size_t>(9, std::min<size_t>(kMaxBatch + 1, budget / (2 * per)));
   }
   const size_t nb_all = 2 * (size_t)c->nbuf + 2;   // two rings, two source-iteration buffers
   OCI_TRY(dalloc(c, &c->d_outb, nb_all * c->out_stride));
@@ -1259,6 +1263,44 @@ extern "C" int oci_solve(oci_ctx *c, int32_t n_steps, double *phi_out, int32_t p
                              hipMemcpyDeviceToHost, c->stream));
   }
   OCI_CK(c, hipStreamSynchronize(c->stream));
+  return worst;
+}
+
+extern "C" int oci_solve_batch(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, double **phi_out,
+                               int32_t phi_out_on_device, oci_step_info **infos,
+                               int32_t n_threads) {
+  if (!ctx || n_ctx < 1) return fail(nullptr, OCI_EINVAL, "need at least one context");
+  if (n_steps < 0) return fail(nullptr, OCI_EINVAL, "n_steps must be >= 0");
+  for (int i = 0; i < n_ctx; ++i) {
+    if (!ctx[i]) return fail(nullptr, OCI_EINVAL, "context is NULL");
+    for (int j = 0; j < i; ++j)
+      if (ctx[j] == ctx[i]) return fail(nullptr, OCI_EINVAL, "contexts must be distinct");
+  }
+  const int T = std::max(1, std::min(n_ctx, n_threads > 0 ? n_threads : 16));
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, OCI_EDEVICE, "hipGetDevice failed");
+  std::vector<int> rc(n_ctx, OCI_OK);
+  std::atomic<int> next(0);
+  // each worker takes the next unsolved context: T problems progress at once
+  auto work = [&]() {
+    if (hipSetDevice(dev) != hipSuccess) return;
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n_ctx) break;
+      rc[i] = oci_solve(ctx[i], n_steps, phi_out ? phi_out[i] : nullptr, phi_out_on_device,
+                        infos ? infos[i] : nullptr);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < T; ++t) pool.emplace_back(work);
+  work();
+  for (auto &th : pool) th.join();
+  if (next.load() < n_ctx) return fail(nullptr, OCI_EDEVICE, "hipSetDevice failed in a worker");
+  int worst = OCI_OK;
+  for (int i = 0; i < n_ctx; ++i) {
+    if (rc[i] < 0) return rc[i];   // the context's own last error has the message
+    if (rc[i] == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
+  }
   return worst;
 }
 

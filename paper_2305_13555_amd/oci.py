@@ -81,6 +81,10 @@ def _load():
         "si_step": (ctypes.c_int, [vp, ctypes.POINTER(oci_step_info)]),
         "oci_solve": (ctypes.c_int, [vp, ctypes.c_int32, vp, ctypes.c_int32,
                                      ctypes.POINTER(oci_step_info)]),
+        "oci_solve_batch": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(vp), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.POINTER(oci_step_info)),
+                                           ctypes.c_int32]),
         "oci_get_flux": (ctypes.c_int, [vp, vp, ctypes.c_int32]),
         "oci_get_state": (ctypes.c_int, [vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
         "oci_set_state": (ctypes.c_int, [vp, _dp, ctypes.c_int64]),
@@ -219,6 +223,34 @@ def oci_solve(ctx, n_steps, phi_out=None):
     infos = (oci_step_info * max(int(n_steps), 1))()
     rc = _check(_lib.oci_solve(ctx, int(n_steps), ptr, dev, infos), ctx)
     return rc, [infos[i].as_dict() for i in range(int(n_steps))]
+
+
+def oci_solve_batch(ctxs, n_steps, phi_outs=None, n_threads=0):
+    """n_steps OCI steps on each context (OciContext or handle), the contexts
+    driven concurrently by up to n_threads host threads (0: library default);
+    phi_outs: None or one output per context ([n_steps][J][4] numpy array or
+    CUDA tensor, or None), all on the host or all on the device.  Returns
+    (rc, [infos per context])."""
+    n = len(ctxs)
+    vp = ctypes.c_void_p
+    handles = (vp * n)(*[c.handle if isinstance(c, OciContext) else c for c in ctxs])
+    phi_arr, dev = None, 1
+    if phi_outs is not None:
+        ptrs = [_out_pointer(o) for o in phi_outs]
+        devs = {d for p, d in ptrs if p is not None}
+        if len(devs) > 1:
+            raise ValueError("phi outputs must be all on the host or all on the device")
+        dev = devs.pop() if devs else 1
+        phi_arr = (vp * n)(*[p for p, _ in ptrs])
+    steps = max(int(n_steps), 1)
+    arrays = [(oci_step_info * steps)() for _ in range(n)]
+    infos = (ctypes.POINTER(oci_step_info) * n)(
+        *[ctypes.cast(a, ctypes.POINTER(oci_step_info)) for a in arrays])
+    rc = _lib.oci_solve_batch(handles, n, int(n_steps), phi_arr, dev, infos, int(n_threads))
+    if rc < 0:
+        msgs = [(_lib.oci_last_error(h) or b"").decode() for h in handles]
+        raise OciError(rc, "; ".join(m for m in msgs if m) or "batch solve failed")
+    return rc, [[a[i].as_dict() for i in range(int(n_steps))] for a in arrays]
 
 
 def oci_get_sizes(ctx):

@@ -108,6 +108,24 @@ def config3(n_steps=50):
         name="64 regions, 200000 cells, S64, 50 steps")
 
 
+def config5(idx, n_steps=20):
+    """Problem idx of the ensemble: J = round(exp U[ln 500, ln 1e5]) cells, N
+    uniform in {8, 16, 32, 64, 128}, 16 regions with draws as config 2
+    (dx = 1), reflecting left / vacuum right, dt = 0.05, v = 1, 20 steps,
+    tol 1e-10.  Each problem has its own generator (config 5, index idx)."""
+    rng = _rng(5, idx)
+    J = int(round(np.exp(rng.uniform(np.log(500.0), np.log(1e5)))))
+    N = int(rng.choice([8, 16, 32, 64, 128]))
+    R = 16
+    sigma_t, c, q = _draw_regions(rng, R)
+    cells = split_cells(J, R)
+    return SlabProblem(
+        n_angles=N, cells=cells, width=cells.astype(np.float64),
+        sigma_t=sigma_t, sigma_s=c * sigma_t, source=q, dt=0.05, speed=1.0,
+        bc_left=REFLECT, bc_right=VACUUM, n_steps=n_steps, tol=1e-10,
+        name="ensemble problem %d: %d cells, S%d, 16 regions" % (idx, J, N))
+
+
 def homogeneous_slab(n_angles, n_cells, c, sigma_dx, dt, speed=1.0, sigma_t=2.0,
                      source=0.1, n_steps=5, width=None):
     """The paper's quadrature-sweep slab: sigma_t = 2, Q = 0.1, vacuum both
