@@ -289,6 +289,17 @@ __device__ __forceinline__ size_t rec_slot(const StepArgs &a, int l, int half) {
 //   [23 + 9u] (dx/(2 v dt)) A^{-1}[r][1]   [24 + 9u] |mu| A^{-1}[r][in_0]
 //   [25 + 9u] |mu| A^{-1}[r][in_1]   [26 + 9u] (dx Q / 4) sum_c A^{-1}[r][c]
 
+constexpr int kPhiPre = 4;   // scalar-flux operator fragments prefetched per wave
+constexpr int kGPre = 2;     // cells whose step constants a thread prefetches
+
+// The step constant values a thread of gh_compute formed for its first
+// cells and (wave 0) its (cell, component) h, for an iteration that follows
+// in the same work-group with the same thread mapping.
+struct GhOut {
+  double gq[kGPre][2];
+  double hv;
+};
+
 // Angle and cells of this thread in the per-(cell, angle) loops: angle
 // tid mod N, cells tid / N + j * cstep (threads past cstep * N idle).
 struct PairMap {
@@ -329,7 +340,7 @@ __device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *k
 // summed in a fixed order; g' (rows 0 .. 2N-1) per (cell, angle).
 template <int CH, bool VEC, int NF>
 __device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const double *rows,
-                                  const double (&f0)[CH]) {
+                                  const double (&f0)[CH], GhOut *go = nullptr) {
   __shared__ double hp[kMaxWaves * 64];
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
   const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
@@ -361,11 +372,17 @@ __device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const dou
   if (pm.active) {
     const double *cf = a.coef + ((size_t)t.region * N + pm.m) * kCoef + 12;
     const double c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3], c4 = cf[4], c5 = cf[5];
-    for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep) {
+    int j = 0;
+    for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
       const double pl = rows[cl * P + 2 * pm.m], pr = rows[cl * P + 2 * pm.m + 1];
       double *g = a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m;
-      g[0] = c0 + c1 * pl + c2 * pr;
-      g[1] = c3 + c4 * pl + c5 * pr;
+      const double g0 = c0 + c1 * pl + c2 * pr, g1 = c3 + c4 * pl + c5 * pr;
+      g[0] = g0;
+      g[1] = g1;
+      if (go && j < kGPre) {
+        go->gq[j < kGPre ? j : 0][0] = g0;
+        go->gq[j < kGPre ? j : 0][1] = g1;
+      }
     }
   }
   __syncthreads();
@@ -373,9 +390,9 @@ __device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const dou
     const int cl = lane >> 2, comp = lane & 3;
     double v = 0.0;
     for (int w = 0; w < W; ++w) v += hp[w * 64 + lane];
-    if (cl < t.nc)
-      a.gh[(size_t)(t.c0 + cl) * ghp + K + comp] =
-          v + a.c_pv[(size_t)t.region * a.c_pv_stride + K + comp];
+    v += a.c_pv[(size_t)t.region * a.c_pv_stride + K + comp];
+    if (cl < t.nc) a.gh[(size_t)(t.c0 + cl) * ghp + K + comp] = v;
+    if (go) go->hv = v;
   }
 }
 
@@ -413,8 +430,6 @@ __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const dou
 // their k-steps split over the waves and summed in LDS in a fixed order;
 // wave 0 forms the 64 (cell, component) scalar fluxes and the tile's
 // residual record; then every thread forms its outgoing pairs.
-constexpr int kPhiPre = 4;   // scalar-flux operator fragments prefetched per wave
-constexpr int kGPre = 2;     // cells whose step constants a thread prefetches
 
 template <int CH>
 struct IterPrefetch {
@@ -439,9 +454,12 @@ struct IterShape {
         W(NF ? ((2 * NF + 15) / 16 < 4 ? (2 * NF + 15) / 16 : 4) : (int)(blockDim.x >> 6)) {}
 };
 
+// go: the step constants already in registers (the end of step that formed
+// them, same work-group and thread mapping), else loaded.
 template <int CH, int NF>
 __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a, const TileDev &t,
-                                        const double *src, const double *phi_old, double *lds) {
+                                        const double *src, const double *phi_old, double *lds,
+                                        const GhOut *go = nullptr) {
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -455,15 +473,23 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
   const double *cf = a.coef + ((size_t)t.region * N + pm.m) * kCoef;
 #pragma unroll
   for (int i = 0; i < 12; ++i) pf.cf[i] = cf[i];
+  if (go) {
 #pragma unroll
-  for (int j = 0; j < kGPre; ++j) {
-    const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
-    pf.gq[j][0] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m];
-    pf.gq[j][1] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m + 1];
+    for (int j = 0; j < kGPre; ++j) {
+      pf.gq[j][0] = go->gq[j][0];
+      pf.gq[j][1] = go->gq[j][1];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kGPre; ++j) {
+      const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
+      pf.gq[j][0] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m];
+      pf.gq[j][1] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m + 1];
+    }
   }
   const int cl = lane >> 2, comp = lane & 3;
   const int cc = t.c0 + min(cl, t.nc - 1);   // (used by wave 0 for cells < nc)
-  pf.hv = a.gh[(size_t)cc * ghp + K + comp];
+  pf.hv = go ? go->hv : a.gh[(size_t)cc * ghp + K + comp];
   pf.po = phi_old[(size_t)cc * 4 + comp];
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
   issue_copy(pf.cr, blk, 1, K);
@@ -581,7 +607,7 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
 template <int CH, bool VEC, int NF>
 __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const double *src,
                                 const double *psi_prev, double *psi_next, const double *phi_acc,
-                                double *phi_out, double *lds) {
+                                double *phi_out, double *lds, GhOut *go = nullptr) {
   __shared__ double sphi[4 * kTileCells];
   double fg[CH];   // P fragments for the next step's gh, issued early
   gh_frags<CH, NF>(a, t, fg);
@@ -598,23 +624,32 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
   const PairMap pm(N);
   const int m = pm.m;
   const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
-  double e[18];
+  double e[18], pq[kGPre][2];   // (and psi_{k-1/2} of this thread's first cells)
   {
     const double *cf = a.coef + ((size_t)t.region * N + m) * kCoef + 18;
 #pragma unroll
     for (int i = 0; i < 18; ++i) e[i] = cf[i];
+#pragma unroll
+    for (int j = 0; j < kGPre; ++j) {
+      const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
+      pq[j][0] = psi_prev[(size_t)(t.c0 + cl) * K + 2 * m];
+      pq[j][1] = psi_prev[(size_t)(t.c0 + cl) * K + 2 * m + 1];
+    }
   }
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
   copy_blocks_to_lds(blk, 1, K, P);
   __syncthreads();
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
   if (pm.active) {
-    for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep) {
+    int j = 0;
+    for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
       const double *pp = psi_prev + (size_t)(t.c0 + cl) * K + 2 * m;
       const double *ph = sphi + cl * 4;
       const double *in = lds + (pos ? cl : cl + 2) * P + 2 * m;
       const double f0 = ph[0], f1 = ph[1], f2 = ph[2], f3 = ph[3];
-      const double pl = pp[0], pr = pp[1], i0 = in[0], i1 = in[1];
+      const double pl = j < kGPre ? pq[j < kGPre ? j : 0][0] : pp[0];
+      const double pr = j < kGPre ? pq[j < kGPre ? j : 0][1] : pp[1];
+      const double i0 = in[0], i1 = in[1];
       const double x2 = e[8] + e[0] * f0 + e[1] * f1 + e[2] * f2 + e[3] * f3 + e[4] * pl +
                         e[5] * pr + e[6] * i0 + e[7] * i1;
       const double x3 = e[17] + e[9] * f0 + e[10] * f1 + e[11] * f2 + e[12] * f3 + e[13] * pl +
@@ -628,7 +663,7 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
   // the next step's gh from psi_{k+1/2}, so that a queued step that
   // follows needs no step start
   __syncthreads();
-  gh_compute<CH, VEC, NF>(a, t, ldn, fg);
+  gh_compute<CH, VEC, NF>(a, t, ldn, fg, go);
 }
 
 // Start of step `cur` of the current solve: gh for every tile from
@@ -1069,9 +1104,11 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   const int parity = c.psi_base ^ (step & 1);
   // iterate L was computed from iterate L-1 (iterate 0: the step's start)
   const double *src = out_at(a, L == 1 ? c.base_buf : ring_buf(a, L - 1, half));
+  GhOut go;
   tile_end<CH, VEC, NF>(a, t, src, parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
                         phi_at(a, ring_buf(a, L, half)),
-                        phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds);
+                        phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds,
+                        fuse ? &go : nullptr);
   if (!fuse) return;
   // iterate 1 of the next step (ring half half^1) from the accepted iterate:
   // every input is this tile's (its step constant, just formed) or already in
@@ -1079,7 +1116,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   __syncthreads();
   const int bl = ring_buf(a, L, half), bn = ring_buf(a, 1, half ^ 1);
   IterPrefetch<CH> pf;
-  iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds);
+  iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds, &go);
   iterate_compute<CH, VEC, NF>(pf, a, t, out_at(a, bl), out_at(a, bn), phi_at(a, bn), lds, phis,
                                phif,
                                reinterpret_cast<double2 *>(a.partial) +
