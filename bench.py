@@ -42,21 +42,26 @@ def algorithmic_bytes_per_cell_step(n_angles):
     return 8 * (10 * n_angles + 12)
 
 
-ITERATIONS_PER_LAUNCH = 2   # iterates per launch of the iteration kernel
-ITERATION_KERNEL = "k_oci_iterate2"
+# the iteration kernel by iterates per launch (the library's launch shape)
+ITERATION_KERNELS = {1: "k_oci_iterate", 2: "k_oci_iterate2", 3: "k_oci_iterateK<3>",
+                     4: "k_oci_iterateK<4>"}
 
 
-def roofline_launch_seconds(oci, prob, stream, steps=9, hi=32, lo=16):
+def roofline_launch_seconds(oci, prob, stream, steps=9, hi_launches=8, lo_launches=4):
     """Per-launch time of the iteration kernel on the workload's cells, regions and
     angles, with v = inf and tol = 0 so that every launch does the full work
-    (the kernel's work does not depend on the values).  Steps of hi and of lo
-    iterates each run as one replayed graph (the launches and the end of
-    step), timed with HIP events on the library's stream; the per-launch time
-    is the difference of the median step times over the extra launches, which
+    (the kernel's work does not depend on the values).  Steps of hi_launches
+    and of lo_launches full launches (k iterates each, k the library's launch
+    shape) each run as one replayed graph (the launches and the end of step),
+    timed with HIP events on the library's stream; the per-launch time is the
+    difference of the median step times over the extra launches, which
     removes the end of step.  It is launch to launch: the kernel's duration
-    plus the dispatch gap between two graph nodes."""
+    plus the dispatch gap between two graph nodes.  Returns (seconds, k)."""
     import dataclasses
     roof = dataclasses.replace(prob, speed=float("inf"), name=prob.name + ", v = inf")
+    with oci.OciContext(roof, stream=stream) as cq:
+        k = cq.iterates_per_launch
+    hi, lo = hi_launches * k, lo_launches * k
     med = {}
     for n in (hi, lo):
         with oci.OciContext(roof, stream=stream, tol=0.0, max_iters=n) as cr:
@@ -69,7 +74,7 @@ def roofline_launch_seconds(oci, prob, stream, steps=9, hi=32, lo=16):
                                        % (n, info))
                 ms.append(info["ms"])
             med[n] = float(np.median(ms))
-    return (med[hi] - med[lo]) * 1e-3 / ((hi - lo) // ITERATIONS_PER_LAUNCH)
+    return (med[hi] - med[lo]) * 1e-3 / (hi_launches - lo_launches), k
 
 
 def copy_calibration(torch, mib):
@@ -85,16 +90,18 @@ def copy_calibration(torch, mib):
 
 
 KERNEL_SOURCES = ("oci_step.hip", "oci_device.h", "oci_kernels.h")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_oci_iterate2_c2_hbm_traffic.txt")
+def traffic_profile(k):
+    name = ITERATION_KERNELS[k].replace("<", "").replace(">", "")
+    return os.path.join(ROOT, "profiles", name + "_c2_hbm_traffic.txt")
 
 
-def measured_traffic():
+def measured_traffic(k):
     """HBM bytes per launch of the iteration kernel from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
     sources have changed since the counters were taken."""
     import hashlib
     try:
-        fields = dict(line.split(":", 1) for line in open(TRAFFIC_PROFILE)
+        fields = dict(line.split(":", 1) for line in open(traffic_profile(k))
                       if line.startswith(("traffic_bytes_per_launch:", "kernel_sources_sha256:")))
     except OSError:
         return None
@@ -159,11 +166,11 @@ def large_case(oci, torch, stream):
                     "iterations_per_step": float(np.mean([i["iterations"] for i in infos])),
                     "launches_per_step": float(np.mean([i["launches"] for i in infos]))}
     out["mixed_speedup"] = out["plain_fp64"]["ms_per_time_step"] / out["mixed"]["ms_per_time_step"]
-    t = roofline_launch_seconds(oci, prob, stream, steps=5, hi=16, lo=8)
-    nbytes = algorithmic_bytes_per_cell_iteration(N) * J * ITERATIONS_PER_LAUNCH
-    flops = 2.0 * 4 * (2 * N) * J * ITERATIONS_PER_LAUNCH
+    t, k = roofline_launch_seconds(oci, prob, stream, steps=5, hi_launches=8, lo_launches=4)
+    nbytes = algorithmic_bytes_per_cell_iteration(N) * J * k
+    flops = 2.0 * 4 * (2 * N) * J * k
     out["iteration_kernel"] = {
-        "kernel": ITERATION_KERNEL, "iterations_per_launch": ITERATIONS_PER_LAUNCH,
+        "kernel": ITERATION_KERNELS[k], "iterations_per_launch": k,
         "us_per_launch": t * 1e6, "bytes_per_launch": nbytes,
         "hbm_gbs": nbytes / t / 1e9, "hbm_frac": nbytes / t / 1e9 / PEAK_HBM_GBS,
         "mfma_frac": flops / t / 1e12 / PEAK_FP64_MFMA_TFLOPS,
@@ -272,10 +279,10 @@ def main():
     J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
     stream = torch.cuda.current_stream()
     if args.roofline_only:
-        t = roofline_launch_seconds(oci, prob, stream, steps=3)
+        t, k = roofline_launch_seconds(oci, prob, stream, steps=3)
         nbytes = copy_calibration(torch, 64)
-        b = algorithmic_bytes_per_cell_iteration(N) * J * ITERATIONS_PER_LAUNCH
-        print(json.dumps({"kernel": ITERATION_KERNEL, "us_per_launch": t * 1e6,
+        b = algorithmic_bytes_per_cell_iteration(N) * J * k
+        print(json.dumps({"kernel": ITERATION_KERNELS[k], "us_per_launch": t * 1e6,
                           "algorithmic_bytes_per_launch": b, "GB/s": b / t / 1e9,
                           "copy_bytes": nbytes}))
         return
@@ -303,8 +310,9 @@ def main():
     iters = sum(i["iterations"] for infos in all_infos for i in infos)
     value = iters * J * N / wall
     gpu_phi = phi_dev.cpu().numpy()
-    kernel, per_launch_s = ITERATION_KERNEL, roofline_launch_seconds(oci, prob, stream)
-    bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J * ITERATIONS_PER_LAUNCH
+    per_launch_s, k_launch = roofline_launch_seconds(oci, prob, stream)
+    kernel = ITERATION_KERNELS[k_launch]
+    bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J * k_launch
     achieved = bytes_launch / per_launch_s / 1e9
 
     # time to a 1e-6 tolerance per step (whole solve at tol 1e-6), and source
@@ -363,11 +371,11 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(k_launch),
             "bytes_per_launch": bytes_launch,
             "us_per_launch": per_launch_s * 1e6,
-            "iterations_per_launch": ITERATIONS_PER_LAUNCH,
-            "measured": "(median step time at 32 iterates - at 16) / the extra launches, "
+            "iterations_per_launch": k_launch,
+            "measured": "(median step time at 8 full launches - at 4) / 4, "
                         "9 steps each (launch to launch, dispatch gap included)",
         },
         "cpu_baseline": cpu,

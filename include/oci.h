@@ -120,9 +120,11 @@ typedef struct {
                           launches alone; OCI: for a step resumed after its
                           queued launches left it undecided, the time of the
                           resumed part, otherwise equal to ms */
-  int32_t launches;    /* iteration kernels launched for the step (>=
-                          iterations; launches after the decision exit at once;
-                          OCI_PREC_FP32: FP64 and FP32 iteration launches) */
+  int32_t launches;    /* iterates computed for the step (>= iterations:
+                          a queued step computes a planned count and its end
+                          picks the accepted one; OCI_PREC_FP32: FP64 and FP32
+                          iterates), in kernels of up to
+                          oci_iterates_per_launch() iterates each */
   int32_t pad;
 } oci_step_info;
 
@@ -141,6 +143,10 @@ typedef struct {
  * judged by the OCI stopping rule (Sec. "One-Cell Inversion (OCI)": relative
  * change of the scalar flux), so the result is an FP64 iterate.  max_iters then bounds
  * the FP64 iterates.
+ * Launch shape: a queued FP64 step runs its iterates in launches of up to
+ * four (each launch recomputes the halo cells it needs on the tile's edges);
+ * the environment variable OCI_ITERATES_PER_LAUNCH = 2, 3 or 4, read here,
+ * caps that number (results agree to rounding order either way).
  * Errors: OCI_EINVAL (bad problem, out == NULL), OCI_ENOMEM, OCI_EDEVICE. */
 int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out);
 
@@ -198,6 +204,13 @@ int oci_set_state(oci_ctx *c, const double *psi_edge, int64_t step);
 /* Quadrature and problem sizes of a context (host outputs; any may be NULL). */
 int oci_get_quadrature(const oci_ctx *c, double *mu, double *w);
 int oci_get_sizes(const oci_ctx *c, int32_t *n_angles, int32_t *n_cells, int32_t *n_regions);
+
+/* Launch shape of a queued FP64 step: the most iterates one iteration kernel
+ * computes (a launch of k > 1 iterates stages its tile with k-1 halo cells on
+ * each side and recomputes them level by level, Sec. "One-Cell Inversion
+ * (OCI)": each cell's iterate needs only its neighbours' previous iterate).
+ * 1 with OCI_PREC_FP32.  Returns the count (>= 1), or OCI_EINVAL for NULL. */
+int oci_iterates_per_launch(const oci_ctx *c);
 
 /* Per-region operator, for inspection and tests: [2N+4+2N][4N+1] row-major,
  * rows = (outgoing flux 2N, phi 4, psi_edge 2N), columns = (incident flux 2N,

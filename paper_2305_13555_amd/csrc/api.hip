@@ -106,6 +106,9 @@ struct oci_ctx {
   void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr, *fn_inner = nullptr;
   void *fn_iter2 = nullptr;   // two iterates per launch (plain FP64 batches)
   size_t lds_it2 = 0;
+  void *fn_iterK[5] = {};     // [3], [4]: three and four iterates per launch (N = 8 .. 128)
+  size_t lds_itK[5] = {};
+  int kimax = 2;              // most iterates per launch
   std::string err;
   StepArgs sa{};
   SiArgs si{};
@@ -543,6 +546,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.ntiles = c->ntiles;
   s.N = N;
   s.J = J;
+  s.R = c->R;
   s.Mt = c->Mt;
   s.Met = c->Met;
   s.Mto = c->Mto;
@@ -650,6 +654,41 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
 #undef OCI_KERNEL
 #undef OCI_PICK
   c->fn_inner = s.tiles_in_args ? (void *)k_oci_inner<true> : (void *)k_oci_inner<false>;
+  // three and four iterates per launch: built for N = 8, 16, 32, 64, 128
+#define OCI_KERNELK(ARGT, KI)                                                   \
+  (N == 8     ? (void *)k_oci_iterateK<4, ARGT, true, 8, KI>                    \
+   : N == 16  ? (void *)k_oci_iterateK<8, ARGT, true, 16, KI>                   \
+   : N == 32  ? (void *)k_oci_iterateK<16, ARGT, true, 32, KI>                  \
+   : N == 64  ? (void *)k_oci_iterateK<16, ARGT, true, 64, KI>                  \
+   : N == 128 ? (void *)k_oci_iterateK<16, ARGT, true, 128, KI>                 \
+              : nullptr)
+  // (the halo cells of a tile in its own region or the next one on their
+  // side: no region narrower than ki-1 cells)
+  const int min_cells = *std::min_element(c->cells.begin(), c->cells.end());
+  for (int ki = 3; ki <= 4 && min_cells >= ki - 1; ++ki) {
+    c->fn_iterK[ki] = s.tiles_in_args ? (ki == 3 ? OCI_KERNELK(true, 3) : OCI_KERNELK(true, 4))
+                                      : (ki == 3 ? OCI_KERNELK(false, 3) : OCI_KERNELK(false, 4));
+    // two row blocks, then the operator rows and pair coefficients of three
+    // regions and the halo cells' step constants
+    c->lds_itK[ki] = ((size_t)2 * (kTileCells + 2 * ki) * (2 * N + 2) + 60 * N +
+                      (size_t)2 * (ki - 1) * (2 * N + 4)) * sizeof(double);
+    hipFuncAttributes fa{};
+    // (at most 64 KiB of LDS, so that two or more work-groups share a CU:
+    // with fewer, the longer launches stop paying for themselves)
+    if (c->fn_iterK[ki] && hipFuncGetAttributes(&fa, (const void *)c->fn_iterK[ki]) == hipSuccess &&
+        c->lds_itK[ki] + fa.sharedSizeBytes <= (size_t)64 * 1024) {
+      OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iterK[ki],
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)c->lds_itK[ki]));
+      c->kimax = ki;
+    }
+  }
+#undef OCI_KERNELK
+  // OCI_ITERATES_PER_LAUNCH (2 .. 4) caps the iterates of one launch
+  if (const char *env = std::getenv("OCI_ITERATES_PER_LAUNCH")) {
+    const int v = std::atoi(env);
+    if (v >= 2 && v <= 4) c->kimax = std::min(c->kimax, v);
+  }
   // past a few thousand tiles one reduction of the last iterate's records
   // beats every work-group of the end of step reducing them all
   c->pre_reduce = c->ntiles > 2048 ? 1 : 0;
@@ -798,7 +837,7 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
 // ---------------------------------------------------------------------------
 // One-cell inversion: queued steps.
 // ---------------------------------------------------------------------------
-constexpr int kWindow = 8;   // steps per queued window (one graph of whole steps)
+constexpr int kWindow = 16;  // steps per queued window (one graph of whole steps)
 constexpr int kColdBatch = 8;  // launches of a step with no previous step to go by
 constexpr int kColdOuter = 3;  // mixed precision: FP64 iterates of such a step
 
@@ -868,7 +907,7 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   // iterate 1 of the next step (needs L >= 2, so that the next step still has
   // a launch of its own to open it)
   const bool fuse_ok = !c->mixed && L >= 2;
-  bool last_pair = false;
+  int last_n = 1;   // iterates of the step's last launch
   for (int s = 0; s < G && e == hipSuccess; ++s) {
     int h = (half + s) & 1;
     if (c->mixed) {
@@ -883,30 +922,32 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
         if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args, 1);
       }
     } else {
-      // iterates start, start+1 | ... two per launch, an odd last one alone;
-      // after a fused end of step (every step of the graph but the first)
-      // iterate 1 is already done
+      // iterates start .. L in launches of up to kimax iterates each; after a
+      // fused end of step (every step of the graph but the first) iterate 1
+      // is already done
       const int start = (s > 0 && fuse_ok) ? 2 : 1;
-      bool pair_before = false;
-      int o = start;
-      for (; o + 1 <= L && e == hipSuccess; o += 2) {
-        int node = o, cb = 0;
-        void *args[] = {&c->sa, &node, &cb, &h};
-        e = add(c->fn_iter2, c->W_it, c->lds_it2, args, 1);
-        pair_before = true;
+      int prev_n = 1;
+      for (int o = start; o <= L && e == hipSuccess;) {
+        const int k = std::min(L - o + 1, c->kimax);
+        int node = o, cb = 0, nred = prev_n;
+        if (k == 1) {
+          void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
+          e = add(c->fn_iter, c->W_it, c->lds_it, args, 1);
+        } else if (k == 2) {
+          void *args[] = {&c->sa, &node, &cb, &h, &nred};
+          e = add(c->fn_iter2, c->W_it, c->lds_it2, args, 1);
+        } else {
+          void *args[] = {&c->sa, &node, &cb, &h, &nred};
+          e = add(c->fn_iterK[k], c->W_it, c->lds_itK[k], args, 1);
+        }
+        prev_n = k;
+        o += k;
       }
-      if (o == L && e == hipSuccess) {
-        int node = L, cb = 0, nred = pair_before ? 2 : 1;
-        void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
-        e = add(c->fn_iter, c->W_it, c->lds_it, args, 1);
-        pair_before = false;
-      }
-      last_pair = pair_before;
+      last_n = prev_n;
     }
-    const bool two = !c->mixed && last_pair;   // the batch ends with a two-iterate launch
     const bool fuse = fuse_ok && s + 1 < G;
-    int first = 1, last = c->mixed ? 2 * L - 1 : L, nred = two ? 2 : 1;
-    int pre = c->pre_reduce, mode = pre | (two ? 2 : 0) | (fuse ? 4 : 0);
+    int first = 1, last = c->mixed ? 2 * L - 1 : L, nred = c->mixed ? 1 : last_n;
+    int pre = c->pre_reduce, mode = pre | (nred << 1) | (fuse ? 16 : 0);
     if (e == hipSuccess && pre) {
       void *rargs[] = {&c->sa, &last, &nred, &h};
       hipKernelNodeParams kp{};
@@ -1007,7 +1048,7 @@ static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half
   if (first < 1 || last < first || last - first >= c->nbuf - 1)
     return fail(c, OCI_EDEVICE, "internal: end of step over an iterate range out of bounds");
   // (single-iterate launches only: resumed steps)
-  int rstep = c->rstep, pre = c->pre_reduce, nred = 1, mode = pre;
+  int rstep = c->rstep, pre = c->pre_reduce, nred = 1, mode = pre | 2;
   if (pre) {
     void *rargs[] = {&c->sa, &last, &nred, &half};
     OCI_CK(c, hipLaunchKernel((const void *)k_reduce_rec, dim3(1), dim3(256), rargs, 0, c->stream));
@@ -1026,7 +1067,7 @@ static int enqueue_window(oci_ctx *c, int first, int count, int batch, int half,
   OCI_CK(c, hipEventRecord(ev_start, c->stream));
   int left = count;
   while (left > 0) {
-    int G = kWindow;   // whole steps per graph: 8, 4, 2 or 1
+    int G = kWindow;   // whole steps per graph: 16, 8, 4, 2 or 1
     while (G > left) G >>= 1;
     hipGraphExec_t exec;
     int rc = step_graph(c, batch, G, half, c->gh_valid ? 0 : 1, phi_dev, &exec);
@@ -1359,6 +1400,11 @@ extern "C" int oci_get_sizes(const oci_ctx *c, int32_t *n_angles, int32_t *n_cel
   if (n_cells) *n_cells = c->J;
   if (n_regions) *n_regions = c->R;
   return OCI_OK;
+}
+
+extern "C" int oci_iterates_per_launch(const oci_ctx *c) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  return c->mixed ? 1 : c->kimax;
 }
 
 extern "C" int oci_get_operator(oci_ctx *c, int32_t region, double *op) {

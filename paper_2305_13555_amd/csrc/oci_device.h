@@ -98,20 +98,58 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Wave reductions with DPP lane moves (vector ALU operands; a shuffle through
+// ds_bpermute costs an LDS round trip per step).  Every lane of the wave must
+// be active.  The steps: swap lanes within quads (xor 1, xor 2), mirror
+// within half rows and rows (each lane then holds its 16-lane row's result),
+// then row 3 combines with row 2 (row_bcast:15) and with rows 0-1
+// (row_bcast:31), so lane 63 holds the wave's result, read back as a
+// wave-uniform value.  The order is fixed: the same on every run.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xf, false);
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_i32<CTRL, ROW_MASK>((int)(b & 0xffffffffll));
+  const int hi = dpp_i32<CTRL, ROW_MASK>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane63_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  v = op(v, dpp_f64<0xB1>(v));          // quad_perm [1,0,3,2]
+  v = op(v, dpp_f64<0x4E>(v));          // quad_perm [2,3,0,1]
+  v = op(v, dpp_f64<0x141>(v));         // row_half_mirror
+  v = op(v, dpp_f64<0x140>(v));         // row_mirror
+  v = op(v, dpp_f64<0x142, 0xa>(v));    // row_bcast:15 (rows 1, 3)
+  v = op(v, dpp_f64<0x143, 0xc>(v));    // row_bcast:31 (rows 2, 3)
+  return lane63_f64(v);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return v;
+  return wave_reduce(v, [](double x, double y) { return fmax(x, y); });
 }
 
 // Sum over the wave in a fixed order (the same on every run).
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  return wave_reduce(v, [](double x, double y) { return x + y; });
 }
 
 __device__ __forceinline__ int wave_or(int v) {
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
-  return v;
+  v |= dpp_i32<0xB1>(v);
+  v |= dpp_i32<0x4E>(v);
+  v |= dpp_i32<0x141>(v);
+  v |= dpp_i32<0x140>(v);
+  v |= dpp_i32<0x142, 0xa>(v);
+  v |= dpp_i32<0x143, 0xc>(v);
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // e_l = max|phi^(l) - phi^(l-1)| / max|phi^(l)| (0/0 -> 0, x/0 -> inf).
@@ -173,8 +211,7 @@ __device__ __forceinline__ double nan_max(double a, double b) {
 }
 
 __device__ __forceinline__ double wave_nan_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o, kWave));
-  return v;
+  return wave_reduce(v, [](double x, double y) { return nan_max(x, y); });
 }
 
 // Residual records: one double2 per tile or block, (max|phi^(l) - phi^(l-1)|,

@@ -20,6 +20,7 @@ constexpr int kCoef = 36;
 // Iterate buffers per ring half at most (iterate ranges of one end of step
 // span fewer).
 constexpr int kMaxRing = 65;
+constexpr int kMaxTrail = 4;   // most iterates per launch (the end reduces theirs)
 // LDS rows of the two-iterate kernel: iterate l-1 of cells c0-2 .. c0+17,
 // iterate l of cells c0-1 .. c0+16.
 constexpr int kBlkA = 16 + 4, kBlkB = 16 + 2;
@@ -31,6 +32,7 @@ struct StepArgs {
   uint32_t tile_word[kArgTiles]; // packed descriptors in work-group order (see pack_tile)
   int N, J, Mt, Met;
   int Mto;                 // row tiles holding the 2N outgoing rows
+  int R;                   // regions
   int bcl, bcr;
   int max_iters, strict;
   double tol;
@@ -126,13 +128,18 @@ template <int CH, bool ARGT, bool VEC, int NF> __global__ void k_step_begin(Step
 // launch whose residual this launch reduces (2 after a two-iterate launch).
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rstep, int nred);
-// Iterates l = cb + node and l + 1 in one launch (plain FP64 OCI).
+// Iterates l = cb + node and l + 1 in one launch (plain FP64 OCI); nred: the
+// previous launch's iterates, whose residuals the extra work-group reduces.
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ void k_oci_iterate2(StepArgs a, int node, int cb, int half);
+__global__ void k_oci_iterate2(StepArgs a, int node, int cb, int half, int nred);
+// Iterates l .. l+KI-1 in one launch (KI = 3, 4; built for N = 8 .. 128).
+template <int CH, bool ARGT, bool VEC, int NF, int KI>
+__global__ void k_oci_iterateK(StepArgs a, int node, int cb, int half, int nred);
 // mode bit 0: the e of the trailing iterates are already in dec (k_reduce_rec
-// ran before); bit 1: two trailing iterates (the batch ended with a
-// two-iterate launch), else one; bit 2: a decided step also computes iterate
-// 1 of the next step (plain OCI; the next step's launches start at 2).
+// ran before); bits 1-3: the trailing iterates (those of the batch's last
+// launch, 1 .. 4), whose e this kernel forms; bit 4: a decided step also
+// computes iterate 1 of the next step (plain OCI; the next step's launches
+// start at 2).
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half,
                            int rstep, int mode);

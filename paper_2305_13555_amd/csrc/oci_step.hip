@@ -613,14 +613,13 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
   gh_frags<CH, NF>(a, t, fg);
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
   double *ldn = lds + (kTileCells + 2) * P;   // psi_{k+1/2} of the tile's cells
-  for (int i = threadIdx.x; i < t.nc * 4; i += blockDim.x) {
-    const double v = phi_acc[(size_t)t.c0 * 4 + i];
-    a.phi_res[(size_t)t.c0 * 4 + i] = v;
-    if (phi_out) phi_out[(size_t)t.c0 * 4 + i] = v;
-    sphi[i] = v;
-  }
-  // this thread's angle: the coefficients of psi_{k+1/2} at L and R (loaded
-  // while the neighbour rows are staged)
+  // every load is issued before the first store (a load issued after a
+  // store waits for it): the accepted scalar flux (one value per thread,
+  // nc * 4 <= 64 <= blockDim), this thread's coefficients and psi_{k-1/2},
+  // the neighbour rows
+  const int pi = threadIdx.x;
+  const double pv = pi < t.nc * 4 ? phi_acc[(size_t)t.c0 * 4 + pi] : 0.0;
+  // this thread's angle: the coefficients of psi_{k+1/2} at L and R
   const PairMap pm(N);
   const int m = pm.m;
   const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
@@ -637,7 +636,14 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
     }
   }
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
-  copy_blocks_to_lds(blk, 1, K, P);
+  CopyRegs cr;
+  issue_copy(cr, blk, 1, K);
+  if (pi < t.nc * 4) {
+    a.phi_res[(size_t)t.c0 * 4 + pi] = pv;
+    if (phi_out) phi_out[(size_t)t.c0 * 4 + pi] = pv;
+    sphi[pi] = pv;
+  }
+  finish_copy(cr, blk, 1, K, P);
   __syncthreads();
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
   if (pm.active) {
@@ -689,6 +695,17 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // The extra work-group of an iteration launch (block index ntiles): the e of
 // iterates l - j*rstep, j = nred .. 1, from their residual records into dec,
 // beside the tiles instead of on one tile's path.
+// The step's first launch (l = 1, or 2 after a fused end of step) records
+// the open step and the buffer of its iterate 0 for the end of step.  Stored
+// last in the launch: on this GPU a load issued after a store waits for that
+// store to complete.
+__device__ __forceinline__ void open_step(const StepArgs &a, int l, int cur, int fb, int stalled) {
+  if (l <= 2 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {
+    a.ctl->open = cur;
+    a.ctl->base_buf = fb;
+  }
+}
+
 __device__ inline void reduce_prev(const StepArgs &a, int l, int rstep, int nred, int half,
                                    double *red, double *scratch) {
   const int stalled = a.ctl->stalled;
@@ -731,13 +748,10 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   IterPrefetch<CH> pf;
   iterate_prefetch<CH, NF>(pf, a, t, src, phi_old, lds);
   const int stalled = a.ctl->stalled;
-  if (l <= 2 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
-    a.ctl->open = cur;
-    a.ctl->base_buf = fb;
-  }
   iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis, phif,
                       reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l, half) + ti,
                       stalled != 0, rstep == 2);
+  open_step(a, l, cur, fb, stalled);
 }
 
 // ---------------------------------------------------------------------------
@@ -899,7 +913,8 @@ __device__ inline void own_pairs(const StepArgs &a, const TileDev &t, const doub
 }
 
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, int cb, int half) {
+__global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, int cb, int half,
+                                                         int nred) {
   extern __shared__ double lds[];
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
   const IterShape<NF> sh(a);
@@ -907,7 +922,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l = cb + node;   // iterates l and l+1
   if (blockIdx.x == a.ntiles) {   // the e of the previous launch's iterates
-    reduce_prev(a, l, 1, 2, half, red, scratch);
+    reduce_prev(a, l, 1, nred, half, red, scratch);
     return;
   }
   int b0 = ring_buf(a, l - 1, half), cur = 0, fb = 0;
@@ -961,10 +976,6 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   CopyRegs cr;
   issue_copy(cr, blk, 1, K);
   const int stalled = a.ctl->stalled;
-  if (l <= 2 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {   // open the step
-    a.ctl->open = cur;
-    a.ctl->base_buf = fb;
-  }
   finish_copy(cr, blk, 1, K, P);
   __syncthreads();
   if (stalled) return;
@@ -1002,6 +1013,235 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   // iterate l+1 of the own cells from B
   own_phi<CH, VEC, NF>(a, t, B, fp, hv, vl, phis, phif, phi_at(a, b2), rl2);
   own_pairs<NF>(a, t, B, phif, cf, gq, out_at(a, b2), nullptr);
+  open_step(a, l, cur, fb, stalled);
+}
+
+// ---------------------------------------------------------------------------
+// KI iterates per launch (KI = 3, 4)
+// ---------------------------------------------------------------------------
+// The two-iterate scheme with a wider halo: the launch stages iterate l-1 of
+// the cells c0-KI .. c0+nc+KI-1 and computes level after level, each level
+// one cell narrower on each side (the own cells with MFMA, the halo cells on
+// the vector units with their own region's operator, whole outgoing rows),
+// alternating between two LDS blocks (row r <-> cell c0-KI+r).  Ghost rows of
+// the mesh edges are re-formed at every level.  Every level's own iterate is
+// stored with its residual record.
+//
+// What the halo cells need besides the rows is staged in LDS with the rows,
+// so that no level waits on memory: the scalar-flux rows of G and the pair
+// coefficients of the tile's region and of the regions before and after it
+// (HF [3][4][K], k-major; HC [3][12][N], angle-major; region slot 0 before,
+// 1 the tile's, 2 after), and each halo cell's step constants (HG
+// [2(KI-1)][K+4]: halo slot i < KI-1 is cell c0-1-i, slot KI-1+i cell
+// c0+nc+i) and region slot.  The host uses this kernel only when no region
+// is narrower than KI-1 cells, so every halo cell is in one of the three.
+// No level reads global memory: on this GPU a load issued after stores waits
+// for those stores to complete.
+
+template <int NF, int KI>
+struct HaloLds {
+  static constexpr int K = 2 * NF;
+  static constexpr int nF = 12 * K, nC = 36 * NF, nG = 2 * (KI - 1) * (K + 4);
+  static constexpr int total = nF + nC + nG;
+  static constexpr int threads = 64 * ((2 * NF + 15) / 16 < 4 ? (2 * NF + 15) / 16 : 4);
+  static constexpr int per_thread = (total + threads - 1) / threads;
+};
+
+// Scalar flux of a halo cell from its neighbours' rows (left: cell c-1,
+// right: c+1) at the level before: h + (scalar-flux rows of G) x incident,
+// with the rows of G (hf, [4][K]) and the cell's step constants (hg) in LDS.
+// One wave; every lane returns the four values.
+template <int NF>
+__device__ inline void cell_phi(const double *left, const double *right, const double *hf,
+                                const double *hg, double (&ph)[4]) {
+  constexpr int N = NF, K = 2 * N;
+  const int lane = threadIdx.x & 63;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = lane; k < K; k += 64) {
+    const double v = k < N ? right[k] : left[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] += hf[q * K + k] * v;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ph[q] = wave_sum(acc[q]) + hg[K + q];
+}
+
+template <int CH, bool ARGT, bool VEC, int NF, int KI>
+__global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, int cb, int half,
+                                                         int nred) {
+  static_assert(NF > 0, "fixed angle count");
+  using HL = HaloLds<NF, KI>;
+  constexpr int RB = kTileCells + 2 * KI;   // rows per LDS block
+  constexpr int NS = 2 * (KI - 1);          // halo slots
+  extern __shared__ double lds[];
+  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64], hph[NS][4];
+  __shared__ int hsel[NS];
+  const IterShape<NF> sh(a);
+  const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l = cb + node;   // iterates l .. l+KI-1
+  if (blockIdx.x == a.ntiles) {   // the e of the previous launch's iterates
+    reduce_prev(a, l, 1, nred, half, red, scratch);
+    return;
+  }
+  const TileDev t = blk_desc<ARGT>(a);
+  // the staged regions: before, the tile's, after (clamped to the mesh)
+  const int rg[3] = {max(t.region - 1, 0), t.region, min(t.region + 1, a.R - 1)};
+  auto slot_cell = [&](int sl) { return sl < KI - 1 ? t.c0 - 1 - sl : t.c0 + t.nc + sl - (KI - 1); };
+  int my_sel = 1;   // this thread's halo slot (threads < NS): its region slot
+  if ((int)threadIdx.x < NS) {
+    const int c = slot_cell(threadIdx.x);
+    if (c >= 0 && c < a.J && a.cell_region[c] != t.region) my_sel = (int)threadIdx.x < KI - 1 ? 0 : 2;
+  }
+  int b0 = ring_buf(a, l - 1, half), cur = 0, fb = 0;
+  if (l <= 2) {   // the step's first launch opens it (as in k_oci_iterate)
+    fb = a.ctl->fin_buf;
+    cur = a.ctl->cur;
+    if (l == 1) b0 = fb;
+  }
+  const double *src = out_at(a, b0);
+  const double *phi_old = phi_at(a, b0);
+  const int ti = blockIdx.x;
+  double *X = lds, *Y = lds + RB * P;
+  double *HF = lds + 2 * RB * P, *HC = HF + HL::nF, *HG = HC + HL::nC;
+  const int cbase = t.c0 - KI;   // cell of LDS row 0
+  auto row = [&](double *blk, int c) { return blk + (c - cbase) * P; };
+  const int ghp = sh.Mt * 16;
+  double fp[kPhiPre], cf[12], gq[kGPre][2];
+  {
+    int prt, poff, kb, ke;
+    phi_tile(N, &prt, &poff);
+    phi_ksplit(KS, W, wave, &kb, &ke);
+    const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
+    load_frags<kPhiPre>(fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
+  }
+  const PairMap pm(N);
+  {
+    const double *c = a.coef + ((size_t)t.region * N + pm.m) * kCoef;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) cf[i] = c[i];
+#pragma unroll
+    for (int j = 0; j < kGPre; ++j) {
+      const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
+      gq[j][0] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m];
+      gq[j][1] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m + 1];
+    }
+  }
+  double hv, po;
+  {
+    const int cl = lane >> 2, comp = lane & 3;
+    const int cc = t.c0 + min(cl, t.nc - 1);
+    hv = a.gh[(size_t)cc * ghp + K + comp];
+    po = phi_old[(size_t)cc * 4 + comp];
+  }
+  // iterate l-1 of cells c0-KI .. c0+nc+KI-1: ghosted rows c0-KI+1 .. c0+nc+KI,
+  // clamped to the mesh and its two ghost rows
+  const int g_lo = max(t.c0 - KI + 1, 0), g_hi = min(t.c0 + t.nc + KI, a.J + 1);
+  const int r_lo = g_lo - 1 - cbase;
+  const RowBlock blk[1] = {RowBlock{src + (size_t)g_lo * K, X + r_lo * P, g_hi - g_lo + 1,
+                                    RB - r_lo}};
+  CopyRegs cr;
+  issue_copy(cr, blk, 1, K);
+  // the halo staging loads (HF, HC, HG in that order)
+  double hreg[HL::per_thread];
+#pragma unroll
+  for (int i = 0; i < HL::per_thread; ++i) {
+    const int idx = (int)threadIdx.x + i * HL::threads;
+    double v = 0.0;
+    if (idx < HL::nF) {
+      const int rsl = idx / (4 * K), q = (idx / K) & 3, k = idx % K;
+      const int rowg = K + q, kq = k / KS, ks = k - kq * KS;
+      v = a.frag_it[(size_t)rg[rsl] * a.frag_it_stride +
+                    ((size_t)(rowg >> 4) * KS + ks) * 64 + (rowg & 15) + 16 * kq];
+    } else if (idx < HL::nF + HL::nC) {
+      const int j = idx - HL::nF, rsl = j / (12 * N), ci = (j / N) % 12, m = j % N;
+      v = a.coef[((size_t)rg[rsl] * N + m) * kCoef + ci];
+    } else if (idx < HL::total) {
+      const int j = idx - HL::nF - HL::nC, sl = j / (K + 4), e = j - sl * (K + 4);
+      const int c = slot_cell(sl);
+      if (c >= 0 && c < a.J) v = a.gh[(size_t)c * ghp + e];
+    }
+    hreg[i] = v;
+  }
+  const int stalled = a.ctl->stalled;
+  finish_copy(cr, blk, 1, K, P);
+#pragma unroll
+  for (int i = 0; i < HL::per_thread; ++i) {
+    const int idx = (int)threadIdx.x + i * HL::threads;
+    if (idx < HL::total) HF[idx] = hreg[i];
+  }
+  if ((int)threadIdx.x < NS) hsel[threadIdx.x] = my_sel;
+  __syncthreads();
+  if (stalled) return;
+  const bool gl = cbase <= -1, gr = t.c0 + t.nc + KI - 1 >= a.J;   // ghost rows in the block
+  if (gl && a.bcl == kBcReflect) mirror_row(row(X, -1), row(X, 0), N, true);
+  if (gr && a.bcr == kBcReflect) mirror_row(row(X, a.J), row(X, a.J - 1), N, false);
+  __syncthreads();
+  double pl = po;   // wave 0: the previous level's scalar flux of its (cell, component)
+  for (int s = 1; s <= KI; ++s) {
+    const int lvl = l + s - 1;
+    double *in = (s & 1) ? X : Y;
+    double *out = (s & 1) ? Y : X;
+    const int reach = KI - s;   // halo cells computed at this level on each side
+    const int lo = max(t.c0 - reach, 0), hi = min(t.c0 + t.nc - 1 + reach, a.J - 1);
+    const int nl = t.c0 - lo, nh = nl + hi - (t.c0 + t.nc - 1);
+    // halo scalar fluxes, one wave per cell (the last waves first)
+    for (int h = W - 1 - wave; h < nh; h += W) {
+      const bool left = h < nl;
+      const int c = left ? lo + h : t.c0 + t.nc + (h - nl);
+      const int sl = left ? t.c0 - 1 - c : KI - 1 + c - (t.c0 + t.nc);
+      double ph[4];
+      cell_phi<NF>(row(in, c - 1), row(in, c + 1), HF + hsel[sl] * 4 * K, HG + sl * (K + 4), ph);
+      if (lane < 4) hph[h][lane] = ph[lane];
+    }
+    const int bl = ring_buf(a, lvl, half);
+    pl = own_phi<CH, VEC, NF>(a, t, row(in, t.c0 - 1), fp, hv, pl, phis, phif, phi_at(a, bl),
+                              reinterpret_cast<double2 *>(a.partial) + rec_slot(a, lvl, half) +
+                                  ti);
+    own_pairs<NF>(a, t, row(in, t.c0 - 1), phif, cf, gq, out_at(a, bl),
+                  s < KI ? row(out, t.c0 - 1) : nullptr);
+    if (s == KI) {
+      open_step(a, l, cur, fb, stalled);
+      break;
+    }
+    // the halo cells' outgoing rows (every angle: they feed the next level)
+    for (int p = threadIdx.x; p < nh * N; p += blockDim.x) {
+      const int h = p / N, m = p - h * N;
+      const bool left = h < nl;
+      const int c = left ? lo + h : t.c0 + t.nc + (h - nl);
+      const int sl = left ? t.c0 - 1 - c : KI - 1 + c - (t.c0 + t.nc);
+      double cc[12];
+      const double *hc = HC + hsel[sl] * 12 * N + m;
+#pragma unroll
+      for (int i = 0; i < 12; ++i) cc[i] = hc[i * N];
+      const double *in2 = (2 * m >= N ? row(in, c - 1) : row(in, c + 1)) + 2 * m;
+      const double i0 = in2[0], i1 = in2[1];
+      const double *ph = hph[h];
+      const double *g = HG + sl * (K + 4) + 2 * m;
+      double *o = row(out, c) + 2 * m;
+      o[0] = g[0] + cc[0] * ph[0] + cc[1] * ph[1] + cc[2] * ph[2] + cc[3] * ph[3] +
+             cc[4] * i0 + cc[5] * i1;
+      o[1] = g[1] + cc[6] * ph[0] + cc[7] * ph[1] + cc[8] * ph[2] + cc[9] * ph[3] +
+             cc[10] * i0 + cc[11] * i1;
+    }
+    __syncthreads();
+    // mesh edges at this level: ghost rows next to a boundary cell computed
+    // here (a fixed ghost row is carried over from the level before, which
+    // also computed that boundary cell)
+    const bool el = gl && lo == 0, er = gr && hi == a.J - 1;
+    if (el || er) {
+      if (el) {
+        if (a.bcl == kBcReflect) mirror_row(row(out, -1), row(out, 0), N, true);
+        else for (int i = N + threadIdx.x; i < K; i += blockDim.x) row(out, -1)[i] = row(in, -1)[i];
+      }
+      if (er) {
+        if (a.bcr == kBcReflect) mirror_row(row(out, a.J), row(out, a.J - 1), N, false);
+        else for (int i = threadIdx.x; i < N; i += blockDim.x) row(out, a.J)[i] = row(in, a.J)[i];
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // The e of iterate l from its residual records into dec (one work-group),
@@ -1032,14 +1272,12 @@ template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
                                                   int last, int half, int rstep, int mode) {
   extern __shared__ double lds[];
-  __shared__ double red[2], red2[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
-  const bool pre = mode & 1, two = (mode >> 1) & 1, fuse = (mode >> 2) & 1;
+  __shared__ double phis[4 * 64], phif[64];
+  const bool pre = mode & 1, fuse = (mode >> 4) & 1;
+  const int ntrail = (mode >> 1) & 7;   // iterates last-ntrail+1 .. last
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
-  RecRegs r1, r2;
-  if (!pre) {
-    rec_issue(r1, recs + rec_slot(a, last, half), a.ntiles);
-    if (two) rec_issue(r2, recs + rec_slot(a, last - 1, half), a.ntiles);
-  }
+  RecRegs r1;
+  if (!pre) rec_issue(r1, recs + rec_slot(a, last, half), a.ntiles);
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
   const TileDev t = blk_desc<ARGT>(a);
@@ -1048,23 +1286,63 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   const int l0 = first - 1 >= 1 ? first - 1 : first;
   for (int i = threadIdx.x; i <= last - l0; i += blockDim.x) sdec[i] = a.dec[(l0 + i) % a.nbuf];
   __syncthreads();
-  // the e of the trailing iterate(s): reduced by k_reduce_rec (many tiles:
-  // one reduction, not one per work-group) or here
-  double e_lastv, e_prevv = -1.0;
-  if (pre) {
-    e_lastv = sdec[last - l0];
-    if (two) e_prevv = sdec[last - 1 - l0];
-  } else {
-    rec_finish(r1, recs + rec_slot(a, last, half), a.ntiles, red, scratch);
-    e_lastv = rel_change(red[0], red[1]);
-    if (two) {
-      rec_finish(r2, recs + rec_slot(a, last - 1, half), a.ntiles, red2, scratch);
-      e_prevv = rel_change(red2[0], red2[1]);
+  // the e of the trailing iterates (those of the last launch) into sdec:
+  // reduced by k_reduce_rec (many tiles: one reduction, not one per
+  // work-group) or here, all of them in one pass over their records
+  if (!pre) {
+    double d[kMaxTrail], f[kMaxTrail];
+#pragma unroll
+    for (int j = 0; j < kMaxTrail; ++j) d[j] = f[j] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRecBatch; ++q) {
+      d[0] = nan_max(d[0], r1.v[q].x);
+      f[0] = nan_max(f[0], r1.v[q].y);
     }
+    const double2 *rl = recs + rec_slot(a, last, half);
+    for (int i = threadIdx.x + kRecBatch * blockDim.x; i < a.ntiles; i += blockDim.x) {
+      d[0] = nan_max(d[0], rl[i].x);
+      f[0] = nan_max(f[0], rl[i].y);
+    }
+    const double2 *rj[kMaxTrail];
+#pragma unroll
+    for (int j = 1; j < kMaxTrail; ++j) rj[j] = recs + rec_slot(a, j < ntrail ? last - j : last, half);
+    for (int i = threadIdx.x; i < a.ntiles; i += blockDim.x) {
+      double2 v[kMaxTrail];
+#pragma unroll
+      for (int j = 1; j < kMaxTrail; ++j) v[j] = j < ntrail ? rj[j][i] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int j = 1; j < kMaxTrail; ++j) {
+        d[j] = nan_max(d[j], v[j].x);
+        f[j] = nan_max(f[j], v[j].y);
+      }
+    }
+    __shared__ double tscr[kMaxWaves][2 * kMaxTrail];
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kMaxTrail; ++j) {
+      d[j] = wave_nan_max(d[j]);
+      f[j] = wave_nan_max(f[j]);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int j = 0; j < kMaxTrail; ++j) {
+        tscr[wave][2 * j] = d[j];
+        tscr[wave][2 * j + 1] = f[j];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < ntrail) {
+      const int j = threadIdx.x;
+      double dd = 0.0, ff = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        dd = nan_max(dd, tscr[w][2 * j]);
+        ff = nan_max(ff, tscr[w][2 * j + 1]);
+      }
+      sdec[last - j - l0] = rel_change(dd, ff);
+    }
+    __syncthreads();
   }
-  auto e_of = [&](int l) {
-    return l == last ? e_lastv : (two && l == last - 1) ? e_prevv : sdec[l - l0];
-  };
+  auto e_of = [&](int l) { return sdec[l - l0]; };
   const int step = c.open;
   int status = kRunning, L = last;
   double e_acc = -1.0;
@@ -1080,27 +1358,33 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
     e_before = l >= 2 ? e : -1.0;
   }
   const bool decided = status != kRunning && status != kNonFinite;
-  // the outcome goes to fields no work-group of this launch reads
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    StepCtl *ct = a.ctl;
-    ct->fin_accepted = L;
-    ct->fin_status = status;
-    ct->fin_e = e_acc;
-    if (a.rec) {
-      a.rec[step].accepted = L;
-      a.rec[step].status = status;
-      a.rec[step].e_last = e_acc;
+  // the outcome goes to fields no work-group of this launch reads (stored
+  // after the work-group's loads: a load issued after a store waits for it)
+  auto record = [&]() {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      StepCtl *ct = a.ctl;
+      ct->fin_accepted = L;
+      ct->fin_status = status;
+      ct->fin_e = e_acc;
+      if (a.rec) {
+        a.rec[step].accepted = L;
+        a.rec[step].status = status;
+        a.rec[step].e_last = e_acc;
+      }
+      if (decided) {
+        ct->fin_buf = ring_buf(a, L, half);
+        ct->cur = step + 1;
+      } else {
+        ct->stalled = 1;
+        for (int i = 0; i < ntrail; ++i)   // for the resumed end
+          a.dec[(last - i) % a.nbuf] = sdec[last - i - l0];
+      }
     }
-    if (decided) {
-      ct->fin_buf = ring_buf(a, L, half);
-      ct->cur = step + 1;
-    } else {
-      ct->stalled = 1;
-      a.dec[last % a.nbuf] = e_lastv;   // for the resumed end
-      if (two) a.dec[(last - 1) % a.nbuf] = e_prevv;
-    }
+  };
+  if (!decided) {
+    record();
+    return;
   }
-  if (!decided) return;
   const int parity = c.psi_base ^ (step & 1);
   // iterate L was computed from iterate L-1 (iterate 0: the step's start)
   const double *src = out_at(a, L == 1 ? c.base_buf : ring_buf(a, L - 1, half));
@@ -1109,7 +1393,10 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
                         phi_at(a, ring_buf(a, L, half)),
                         phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds,
                         fuse ? &go : nullptr);
-  if (!fuse) return;
+  if (!fuse) {
+    record();
+    return;
+  }
   // iterate 1 of the next step (ring half half^1) from the accepted iterate:
   // every input is this tile's (its step constant, just formed) or already in
   // memory (the neighbours' accepted outgoing fluxes), so one launch fewer
@@ -1122,6 +1409,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
                                reinterpret_cast<double2 *>(a.partial) +
                                    rec_slot(a, 1, half ^ 1) + blockIdx.x,
                                false, false);
+  record();
 }
 
 // ---------------------------------------------------------------------------
@@ -1263,30 +1551,50 @@ __global__ void k_to_f32(const double *src, float *dst, size_t n) {
     dst[e] = (float)src[e];
 }
 
-template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<8, false, false, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<8, false, true, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, false, false, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, false, true, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<4, false, true, 8>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<8, false, true, 16>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, false, true, 32>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, false, true, 64>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, false, true, 128>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, false, true, 256>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<4, true, false, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<4, true, true, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<8, true, false, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<8, true, true, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, true, false, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, true, true, 0>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<4, true, true, 8>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<8, true, true, 16>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, true, true, 32>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, true, true, 64>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, true, true, 128>(StepArgs, int, int, int);
-template __global__ void k_oci_iterate2<16, true, true, 256>(StepArgs, int, int, int);
+template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<8, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<8, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, false, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<4, false, true, 8>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<8, false, true, 16>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 32>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 64>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 128>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, false, true, 256>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<4, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<4, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<8, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<8, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, true, false, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 0>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<4, true, true, 8>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<8, true, true, 16>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 32>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 64>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 128>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterate2<16, true, true, 256>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<4, true, true, 8, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<8, true, true, 16, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, true, true, 32, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, true, true, 64, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, true, true, 128, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<4, false, true, 8, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<8, false, true, 16, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, false, true, 32, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, false, true, 64, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, false, true, 128, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<4, true, true, 8, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<8, true, true, 16, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, true, true, 32, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, true, true, 64, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, true, true, 128, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<4, false, true, 8, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<8, false, true, 16, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, false, true, 32, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, false, true, 64, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, false, true, 128, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_inner<true>(StepArgs, int, int, int);
 template __global__ void k_oci_inner<false>(StepArgs, int, int, int);
 

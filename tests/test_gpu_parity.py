@@ -102,14 +102,21 @@ CASES = [(s, None) for s in range(8)] + [
 
 
 @pytest.mark.parametrize("seed,kw", CASES)
-@pytest.mark.parametrize("iters", [1, 4])
+@pytest.mark.parametrize("iters", [1, 4, 7])
 def test_fixed_iterations_match_oracle_oci(lib, seed, kw, iters):
     p = W.random_small(seed, **(kw or {}))
     cd = cell_data(p)
     ref = ooci.run_oci(p, cd, 3, tol=0.0, max_iters=iters)
     got = gpu_run(lib, p, 3, tol=0.0, max_iters=iters)
     for k in range(3):
-        assert got[k]["iterations"] == iters
+        # tol = 0 stops only at the limit, or where an iterate repeats the
+        # one before bit for bit (e = 0: a small problem converged to
+        # rounding), which the two sides may reach one iterate apart
+        assert ref[k]["iterations"] <= iters
+        if ref[k]["iterations"] == iters:
+            assert got[k]["iterations"] == iters
+        else:
+            assert abs(got[k]["iterations"] - ref[k]["iterations"]) <= 1
         assert got[k]["rc"] in (lib.OCI_NOT_CONVERGED, lib.OCI_OK)
         assert rel(got[k]["phi"], ref[k]["phi"]) < 1e-11, (seed, k)
         assert rel(got[k]["psi_edge"], ref[k]["psi_edge"]) < 1e-11, (seed, k)
