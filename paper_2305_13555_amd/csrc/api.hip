@@ -49,8 +49,6 @@ struct oci_ctx {
   std::vector<double> ghost_left, ghost_right;   // [2N] each
   int Mt = 0, Met = 0, Mto = 0, ntiles = 0, grid = 0, W_it = 1, W_ed = 1, W_pv = 1;
   size_t lds_it = 0, lds_pv = 0, lds_ed = 0;
-  int lu_cb = 0, lu_pitch = 0;   // LDS LU: right-hand-side columns per work-group, row pitch
-  size_t lds_lu = 0;
   int si_blocks = 0, si_segs = 1;
   std::vector<void *> allocs;
   double *d_mu = nullptr, *d_w = nullptr;
@@ -88,8 +86,7 @@ struct oci_ctx {
   int batch_hint = 0;                        // iteration launches per queued step
   int window = 1;                            // steps of the next queued window
   bool quad_override = false;
-  double *ws_M = nullptr, *ws_X = nullptr;   // setup workspace, kept for oci_refactor
-  int *d_bad = nullptr;
+  int *d_bad = nullptr;                      // set by the operator build: singular system
   // mixed precision: FP64 iterates every other launch (rstep 2) with FP32
   // correction solves of m_inner iterations between them
   bool mixed = false;
@@ -283,23 +280,19 @@ static int build_si_graph(oci_ctx *c, int count) {
 }
 
 
-// Build, factor and pack every region's operator (region table, mu, w and a
-// already on the device / in the context).
+// Build and pack every region's operator (region table, mu, w and a already
+// on the device / in the context).
 static int build_operators(oci_ctx *c) {
   const int N = c->N, K = 2 * N, R = c->R;
-  double *ws_M = c->ws_M, *ws_X = c->ws_X;
   int *d_bad = c->d_bad;
   OCI_CK(c, hipMemsetAsync(d_bad, 0, sizeof(int), c->stream));
-  hipLaunchKernelGGL(k_build_system, dim3(R), dim3(256), 0, c->stream, c->d_regions, c->d_mu,
-                     c->d_w, N, c->a, ws_M, ws_X);
-  if (c->lu_cb > 0) {
-    const int n = 4 * N, nr = n + 1;
-    hipLaunchKernelGGL(k_lu_solve_lds, dim3(R, (nr + c->lu_cb - 1) / c->lu_cb), dim3(1024),
-                       c->lds_lu, c->stream, N, c->lu_cb, c->lu_pitch, ws_M, ws_X, d_bad);
-  } else {
-    hipLaunchKernelGGL(k_lu_solve, dim3(R), dim3(1024), 0, c->stream, N, ws_M, ws_X, d_bad);
-  }
-  hipLaunchKernelGGL(k_select_rows, dim3(R), dim3(256), 0, c->stream, N, c->d_w, ws_X, c->d_op);
+  // A_m^{-1} per (region, angle), then the cell operator from the block
+  // structure of A - S
+  hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
+                     c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
+  hipLaunchKernelGGL(k_cell_operator, dim3(R), dim3(256), (size_t)(32 * N + 4) * sizeof(double),
+                     c->stream, c->d_regions, c->d_mu, c->d_w, c->d_ainv, N, c->a, c->d_op,
+                     d_bad);
   // iteration operator G: rows [0, 2N+4), columns [0, 2N) (incident), k-major
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, 0, K,
                      c->Mt, c->d_fi, c->fi_stride, (double *)nullptr, (size_t)0, 1);
@@ -309,8 +302,6 @@ static int build_operators(oci_ctx *c) {
   if (c->mixed)   // G for the FP32 inner iterations, same packing
     hipLaunchKernelGGL(k_to_f32, dim3(256), dim3(256), 0, c->stream, (const double *)c->d_fi,
                        c->d_fi32, (size_t)R * c->fi_stride);
-  hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
-                     c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
   hipLaunchKernelGGL(k_out_coef, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
                      c->d_regions, c->d_mu, c->d_ainv, N, R, c->a, c->d_coef);
   OCI_CK(c, hipGetLastError());
@@ -507,25 +498,9 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(up(c->d_tiles, tiles.data(), tiles.size() * sizeof(TileDev)));
   OCI_TRY(up(c->d_cell_region, cell_region.data(), (size_t)J * sizeof(int)));
 
-  // LU in LDS when M and a block of >= 8 right-hand sides fit in 160 KiB
-  {
-    const size_t cap = 160 * 1024 - 64;
-    const int maxw = (int)(cap / ((size_t)n * sizeof(double)));   // widest odd-pitch row
-    int cb = std::min(nr, maxw - n - 1);
-    if (cb >= 8) {
-      int pitch = n + cb;
-      if (!(pitch & 1)) pitch += 1;
-      c->lu_cb = cb;
-      c->lu_pitch = pitch;
-      c->lds_lu = (size_t)n * pitch * sizeof(double);
-      if (hipFuncSetAttribute((const void *)k_lu_solve_lds,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)c->lds_lu) != hipSuccess)
-        c->lu_cb = 0;   // fall back to the LU in global memory
-    }
-  }
-  OCI_TRY(dalloc(c, &c->ws_M, (size_t)R * n * n));
-  OCI_TRY(dalloc(c, &c->ws_X, (size_t)R * n * nr));
+  OCI_CK(c, hipFuncSetAttribute((const void *)k_cell_operator,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)((32 * N + 4) * sizeof(double))));
   OCI_TRY(dalloc(c, &c->d_bad, 1));
   OCI_TRY(build_operators(c));
 

@@ -107,11 +107,8 @@ struct ZeroRanges {
 
 // setup.hip
 __global__ void k_zero(ZeroRanges z);
-__global__ void k_build_system(const RegionDev *regions, const double *mu, const double *w,
-                               int N, double a, double *ws_M, double *ws_X);
-__global__ void k_lu_solve(int N, double *ws_M, double *ws_X, int *bad);
-__global__ void k_lu_solve_lds(int N, int CB, int P, const double *ws_M, double *ws_X, int *bad);
-__global__ void k_select_rows(int N, const double *w, const double *ws_X, double *op_all);
+__global__ void k_cell_operator(const RegionDev *regions, const double *mu, const double *w,
+                                const double *ainv, int N, double a, double *op_all, int *bad);
 __global__ void k_out_coef(const RegionDev *regions, const double *mu, const double *ainv, int N,
                            int R, double a, double *coef);
 __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,

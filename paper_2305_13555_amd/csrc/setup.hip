@@ -1,5 +1,5 @@
-// Setup kernels: per-region cell matrix, its LU factorisation, and the packed
-// operators applied on the hot path.
+// Setup kernels: the per-region cell operator and its packed forms applied
+// on the hot path.
 //
 // The cell system of one-cell inversion (Sec. "One-Cell Inversion (OCI)") is
 // (A - S) Psi = c with A = blockdiag(A_m), A_m the 4x4 matrix printed for
@@ -13,262 +13,150 @@
 // |mu_m| in the c^+ / c^- rows that carry them), the previous time edge
 // psi_{k-1/2} (coefficient dx/(2 v dt) in the two time-average rows) and the
 // source (dx Q / 4 in every row).  Setup solves (A - S) Y = [B | T | q] once
-// per region by LU with partial pivoting (the paper's dense solver, LAPACK
-// gesv, hoisted out of the iteration) and keeps only the rows the iteration
-// needs: the outgoing fluxes, the scalar flux and the time-edge values.
+// per region and keeps only the rows the iteration needs: the outgoing
+// fluxes, the scalar flux and the time-edge values.
+//
+// The paper solves the cell system with a dense direct solver.  Here the
+// solve uses its structure: S = s E W with s = dx Sigma_s / 4, (W psi)_c =
+// sum_m w_m psi_{m,c} (the scalar flux) and (E phi)_{m,c} = phi_c.  Then
+//   Y = A^{-1} [B|T|q] + s A^{-1} E Phi,   Phi = W Y,
+//   (I - s sum_m w_m A_m^{-1}) Phi = W A^{-1} [B|T|q],
+// a 4x4 system per region (the same solution as the dense solve up to
+// rounding, in O(N) work per column instead of O(N^2) per column after an
+// O(N^3) factorisation), with the A_m^{-1} of the SI sweep.
 #include "oci_kernels.h"
 
 namespace ocik {
 
-// One work-group per region: M (n x n, n = 4N) and the right-hand sides
-// X (n x (n+1)) into the workspace.
-__global__ void k_build_system(const RegionDev *regions, const double *mu, const double *w,
-                               int N, double a, double *ws_M, double *ws_X) {
-  const int r = blockIdx.x;
-  const int n = 4 * N, nr = n + 1;
-  const RegionDev g = regions[r];
-  double *M = ws_M + (size_t)r * n * n;
-  double *X = ws_X + (size_t)r * n * nr;
-  const double dx = g.dx;
-  const double t = dx * a;               // dx / (v dt)
-  const double s = dx * g.sigs / 4.0;    // scattering coefficient
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
-    const int row = idx / n, col = idx % n;
-    const int m = row >> 2, c = row & 3, mm = col >> 2, cc = col & 3;
-    double v = 0.0;
-    if (m == mm) {
-      const double mum = mu[m];
-      const double d = (fabs(mum) + dx * g.sig) / 2.0;
-      const double h = mum / 2.0;
-      // rows: (k,L) (k,R) (k+1/2,L) (k+1/2,R)
-      const double A[4][4] = {{d, h, t / 2.0, 0.0},
-                              {-h, d, 0.0, t / 2.0},
-                              {-t, 0.0, t + d, h},
-                              {0.0, -t, -h, t + d}};
-      v = A[c][cc];
-    }
-    if (c == cc) v -= s * w[mm];
-    M[idx] = v;
-  }
-  for (int idx = threadIdx.x; idx < n * nr; idx += blockDim.x) {
-    const int row = idx / nr, col = idx % nr;
-    const int m = row >> 2, c = row & 3;
-    double v = 0.0;
-    if (col < 2 * N) {
-      // incident entry 2m'+tl: enters row (m', c_in) with |mu|
-      const int mi = col >> 1, tl = col & 1;
-      if (mi == m) {
-        const int cin = (m < N / 2) ? (tl == 0 ? 1 : 3) : (tl == 0 ? 0 : 2);
-        if (c == cin) v = fabs(mu[m]);
-      }
-    } else if (col < 4 * N) {
-      // previous time edge 2m'+side: enters the time-average row of that side
-      const int p = col - 2 * N;
-      if ((p >> 1) == m && (p & 1) == c) v = t / 2.0;
-    } else {
-      v = dx * g.q / 4.0;
-    }
-    X[idx] = v;
-  }
+// Entering corner of angle m's incident value tl (0: level k, 1: k+1/2),
+// and the outgoing corner of its outgoing value tl: mu < 0 (m < N/2) enters
+// on the right (corners 1, 3) and leaves on the left (0, 2).
+__device__ __forceinline__ int entering_corner(int m, int N, int tl) {
+  return m < N / 2 ? (tl == 0 ? 1 : 3) : (tl == 0 ? 0 : 2);
+}
+__device__ __forceinline__ int outgoing_corner(int m, int N, int tl) {
+  return m < N / 2 ? (tl == 0 ? 0 : 2) : (tl == 0 ? 1 : 3);
 }
 
-// The same LU with partial pivoting with the work in LDS, for 4N <= 128.
-// Work-group (r, b) holds all of M (n x n) and columns [b*CB, b*CB+CB) of X
-// side by side in LDS rows of pitch P (odd, so that column walks spread over
-// the banks); every work-group of a region factors M again (cheap next to a
-// round trip to memory per pivot) and carries its own block of X along, so
-// the right-hand sides are split over several CUs.  The pivot sequence and
-// every floating-point operation are those of k_lu_solve: first maximum of
-// |column| as pivot, multipliers M[i][k] / M[k][k], rank-one updates, then
-// back substitution row by row.  Singular pivots set *bad.
-__global__ __launch_bounds__(1024) void k_lu_solve_lds(int N, int CB, int P, const double *ws_M,
-                                                       double *ws_X, int *bad) {
-  extern __shared__ double A[];
-  __shared__ int s_piv;
-  __shared__ double s_pv;
-  const int r = blockIdx.x, j0 = blockIdx.y * CB;
-  const int n = 4 * N, nr = n + 1, Wd = n + CB;
-  const int ncol = min(CB, nr - j0);
-  const double *M = ws_M + (size_t)r * n * n;
-  double *X = ws_X + (size_t)r * n * nr;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  for (int idx = tid; idx < n * Wd; idx += blockDim.x) {
-    const int i = idx / Wd, j = idx - i * Wd;
-    double v = 0.0;
-    if (j < n) v = M[(size_t)i * n + j];
-    else if (j - n < ncol) v = X[(size_t)i * nr + j0 + (j - n)];
-    A[i * P + j] = v;
+// One work-group per region: the operator rows op [2N+4+2N][4N+1] (outgoing
+// fluxes, scalar flux, time-edge values; columns: incident 2N, time edge 2N,
+// source) from the A_m^{-1} (ainv [R][N][16]).  Dynamic LDS: (32N + 4)
+// doubles.  A singular or non-finite 4x4 system sets *bad.
+__global__ __launch_bounds__(256) void k_cell_operator(const RegionDev *regions,
+                                                        const double *mu, const double *w,
+                                                        const double *ainv, int N, double a,
+                                                        double *op_all, int *bad) {
+  extern __shared__ double sh[];
+  __shared__ double Ks[16], Kinv[16];
+  const int r = blockIdx.x, tid = threadIdx.x;
+  const int n = 4 * N, nr = n + 1, rows = 4 * N + 4;
+  double *Ai = sh;            // [N][4][4]: A_m^{-1}
+  double *Ph = sh + 16 * N;   // [4][nr]: Phi
+  const RegionDev g = regions[r];
+  const double s = g.dx * g.sigs / 4.0, th = g.dx * a / 2.0, qq = g.dx * g.q / 4.0;
+  for (int i = tid; i < 16 * N; i += blockDim.x) Ai[i] = ainv[(size_t)r * N * 16 + i];
+  __syncthreads();
+  // K = I - s sum_m w_m A_m^{-1}
+  if (tid < 16) {
+    double acc = 0.0;
+    for (int m = 0; m < N; ++m) acc += w[m] * Ai[m * 16 + tid];
+    Ks[tid] = ((tid >> 2) == (tid & 3) ? 1.0 : 0.0) - s * acc;
   }
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (wave == 0) {
-      double best = -1.0;
-      int bi = n;
-      for (int i = k + lane; i < n; i += 64) {
-        const double v = fabs(A[i * P + k]);
-        if (v > best) { best = v; bi = i; }
+  if (tid == 0) {   // K^{-1}: Gauss-Jordan with partial pivoting
+    double M[4][8];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        M[i][j] = Ks[i * 4 + j];
+        M[i][4 + j] = i == j ? 1.0 : 0.0;
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double v2 = __shfl_xor(best, o, 64);
-        const int i2 = __shfl_xor(bi, o, 64);
-        if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
-      }
-      if (lane == 0) {
-        s_piv = bi;
-        s_pv = best;
-      }
-    }
-    __syncthreads();
-    const int p = s_piv;
-    if (!(s_pv > 0.0)) {
-      if (tid == 0) *bad = 1;
-      return;   // uniform: every thread read the same s_pv
-    }
-    if (p != k) {
-      for (int j = k + tid; j < Wd; j += blockDim.x) {
-        const double tmp = A[k * P + j];
-        A[k * P + j] = A[p * P + j];
-        A[p * P + j] = tmp;
-      }
-      __syncthreads();
-    }
-    const double piv = A[k * P + k];
-    for (int i = k + 1 + tid; i < n; i += blockDim.x) A[i * P + k] = A[i * P + k] / piv;
-    __syncthreads();
-    for (int i = k + 1 + wave; i < n; i += nw) {
-      const double l = A[i * P + k];
-      for (int j = k + 1 + lane; j < Wd; j += 64) A[i * P + j] -= l * A[k * P + j];
-    }
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    const double piv = A[k * P + k];
-    for (int j = tid; j < CB; j += blockDim.x) A[k * P + n + j] /= piv;
-    __syncthreads();
-    for (int i = wave; i < k; i += nw) {
-      const double u = A[i * P + k];
-      for (int j = lane; j < CB; j += 64) A[i * P + n + j] -= u * A[k * P + n + j];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < n * ncol; idx += blockDim.x) {
-    const int i = idx / ncol, j = idx - i * ncol;
-    X[(size_t)i * nr + j0 + j] = A[i * P + n + j];
-  }
-}
-
-// LU with partial pivoting of M, applied to X at the same time, then back
-// substitution: X <- M^{-1} X.  One work-group per region; singular pivots set
-// *bad.
-__global__ __launch_bounds__(1024) void k_lu_solve(int N, double *ws_M, double *ws_X, int *bad) {
-  const int r = blockIdx.x;
-  const int n = 4 * N, nr = n + 1;
-  double *M = ws_M + (size_t)r * n * n;
-  double *X = ws_X + (size_t)r * n * nr;
-  __shared__ double s_val[1024];
-  __shared__ int s_idx[1024];
-  __shared__ double s_l[1024];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = 0; k < n; ++k) {
-    // pivot search on column k (first maximum, like LAPACK's idamax)
-    double best = -1.0;
-    int bi = n;
-    for (int i = k + tid; i < n; i += nt) {
-      const double v = fabs(M[(size_t)i * n + k]);
-      if (v > best) { best = v; bi = i; }
-    }
-    s_val[tid] = best;
-    s_idx[tid] = bi;
-    __syncthreads();
-    for (int o = nt / 2; o > 0; o >>= 1) {
-      if (tid < o) {
-        const double v2 = s_val[tid + o];
-        const int i2 = s_idx[tid + o];
-        if (v2 > s_val[tid] || (v2 == s_val[tid] && i2 < s_idx[tid])) {
-          s_val[tid] = v2;
-          s_idx[tid] = i2;
+    bool ok = true;
+    for (int k = 0; k < 4; ++k) {
+      int p = k;
+      for (int i = k + 1; i < 4; ++i)
+        if (fabs(M[i][k]) > fabs(M[p][k])) p = i;
+      if (p != k)
+        for (int j = 0; j < 8; ++j) {
+          const double tmp = M[k][j];
+          M[k][j] = M[p][j];
+          M[p][j] = tmp;
         }
-      }
-      __syncthreads();
-    }
-    const int p = s_idx[0];
-    const double pv = s_val[0];
-    if (!(pv > 0.0)) {
-      if (tid == 0) *bad = 1;
-      return;   // uniform: every thread saw the same s_val[0]
-    }
-    if (p != k) {
-      for (int j = k + tid; j < n; j += nt) {
-        const double tmp = M[(size_t)k * n + j];
-        M[(size_t)k * n + j] = M[(size_t)p * n + j];
-        M[(size_t)p * n + j] = tmp;
-      }
-      for (int j = tid; j < nr; j += nt) {
-        const double tmp = X[(size_t)k * nr + j];
-        X[(size_t)k * nr + j] = X[(size_t)p * nr + j];
-        X[(size_t)p * nr + j] = tmp;
+      const double piv = M[k][k];
+      if (!(fabs(piv) > 0.0) || !isfinite(piv)) ok = false;
+      for (int j = 0; j < 8; ++j) M[k][j] /= piv;
+      for (int i = 0; i < 4; ++i) {
+        if (i == k) continue;
+        const double l = M[i][k];
+        for (int j = 0; j < 8; ++j) M[i][j] -= l * M[k][j];
       }
     }
-    __syncthreads();
-    const double piv = M[(size_t)k * n + k];
-    for (int i = k + 1 + tid; i < n; i += nt) s_l[i - k - 1] = M[(size_t)i * n + k] / piv;
-    __syncthreads();
-    const int rows = n - k - 1;
-    const int wM = n - k - 1;     // columns k+1 .. n-1 of M
-    const int wT = wM + nr;       // followed by every column of X
-    for (int idx = tid; idx < rows * wT; idx += nt) {
-      const int ii = idx / wT, jj = idx % wT;
-      const int i = k + 1 + ii;
-      const double l = s_l[ii];
-      if (jj < wM) {
-        const int j = k + 1 + jj;
-        M[(size_t)i * n + j] -= l * M[(size_t)k * n + j];
-      } else {
-        const int j = jj - wM;
-        X[(size_t)i * nr + j] -= l * X[(size_t)k * nr + j];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        Kinv[i * 4 + j] = M[i][4 + j];
+        if (!isfinite(M[i][4 + j])) ok = false;
       }
-    }
-    __syncthreads();
+    if (!ok) *bad = 1;
   }
-  for (int k = n - 1; k >= 0; --k) {
-    const double piv = M[(size_t)k * n + k];
-    for (int j = tid; j < nr; j += nt) X[(size_t)k * nr + j] /= piv;
-    __syncthreads();
-    for (int idx = tid; idx < k * nr; idx += nt) {
-      const int i = idx / nr, j = idx % nr;
-      X[(size_t)i * nr + j] -= M[(size_t)i * n + k] * X[(size_t)k * nr + j];
-    }
-    __syncthreads();
-  }
-}
-
-// Row selection of Y = M^{-1}[B|T|q] into the per-region operator
-// op [2N+4+2N][4N+1]: outgoing fluxes, scalar flux (sum_n w_n psi_n),
-// time-edge values.
-__global__ void k_select_rows(int N, const double *w, const double *ws_X, double *op_all) {
-  const int r = blockIdx.x;
-  const int n = 4 * N, nr = n + 1;
-  const int rows = 4 * N + 4;
-  const double *Y = ws_X + (size_t)r * n * nr;
-  double *op = op_all + (size_t)r * rows * nr;
-  for (int idx = threadIdx.x; idx < rows * nr; idx += blockDim.x) {
-    const int row = idx / nr, col = idx % nr;
-    double v;
-    if (row < 2 * N) {
-      const int m = row >> 1, tl = row & 1;
-      const int c = (m < N / 2) ? (tl == 0 ? 0 : 2) : (tl == 0 ? 1 : 3);
-      v = Y[(size_t)(4 * m + c) * nr + col];
-    } else if (row < 2 * N + 4) {
-      const int c = row - 2 * N;
-      double acc = 0.0;
-      for (int m = 0; m < N; ++m) acc += w[m] * Y[(size_t)(4 * m + c) * nr + col];
-      v = acc;
+  __syncthreads();
+  // Phi[:, col] = K^{-1} (W A^{-1} [B|T|q])[:, col]: an incident or time-edge
+  // column has one nonzero (one angle's row), the source column all rows
+  for (int col = tid; col < nr; col += blockDim.x) {
+    double v[4];
+    if (col < 4 * N) {
+      const bool inc = col < 2 * N;
+      const int p = inc ? col : col - 2 * N, m = p >> 1, tl = p & 1;
+      const int cc = inc ? entering_corner(m, N, tl) : tl;   // time edge: level-k row tl
+      const double f = w[m] * (inc ? fabs(mu[m]) : th);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = f * Ai[m * 16 + c * 4 + cc];
     } else {
-      const int p = row - 2 * N - 4;
-      const int m = p >> 1, side = p & 1;
-      v = Y[(size_t)(4 * m + 2 + side) * nr + col];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double acc = 0.0;
+        for (int m = 0; m < N; ++m) {
+          const double *A = Ai + m * 16 + c * 4;
+          acc += w[m] * (A[0] + A[1] + A[2] + A[3]);
+        }
+        v[c] = qq * acc;
+      }
     }
-    op[idx] = v;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      Ph[c * nr + col] = Kinv[c * 4 + 0] * v[0] + Kinv[c * 4 + 1] * v[1] +
+                         Kinv[c * 4 + 2] * v[2] + Kinv[c * 4 + 3] * v[3];
+  }
+  __syncthreads();
+  // Y rows: angle m, corner c: (A_m^{-1} [B|T|q])[(m,c), col] + s (A_m^{-1} Phi)[c, col]
+  double *op = op_all + (size_t)r * rows * nr;
+  for (int idx = tid; idx < rows * nr; idx += blockDim.x) {
+    const int row = idx / nr, col = idx - row * nr;
+    double val;
+    if (row >= 2 * N && row < 2 * N + 4) {
+      val = Ph[(row - 2 * N) * nr + col];
+    } else {
+      int m, c;
+      if (row < 2 * N) {
+        m = row >> 1;
+        c = outgoing_corner(m, N, row & 1);
+      } else {
+        const int p = row - 2 * N - 4;
+        m = p >> 1;
+        c = 2 + (p & 1);
+      }
+      const double *A = Ai + m * 16 + c * 4;   // row c of A_m^{-1}
+      double own = 0.0;
+      if (col < 2 * N) {
+        if ((col >> 1) == m) own = fabs(mu[m]) * A[entering_corner(m, N, col & 1)];
+      } else if (col < 4 * N) {
+        const int p = col - 2 * N;
+        if ((p >> 1) == m) own = th * A[p & 1];
+      } else {
+        own = qq * (A[0] + A[1] + A[2] + A[3]);
+      }
+      val = own + s * (A[0] * Ph[col] + A[1] * Ph[nr + col] + A[2] * Ph[2 * nr + col] +
+                       A[3] * Ph[3 * nr + col]);
+    }
+    op[idx] = val;
   }
 }
 
