@@ -107,7 +107,9 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c) {
 // wave-uniform value.  The order is fixed: the same on every run.
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xf, false);
+  // (lanes of rows outside ROW_MASK get an unspecified value: only lane 63,
+  // whose row every step includes, carries the result)
+  return __builtin_amdgcn_mov_dpp(v, CTRL, ROW_MASK, 0xf, false);
 }
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -122,6 +124,14 @@ __device__ __forceinline__ double lane63_f64(double v) {
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
+// Lane `src` of a wave-uniform index: its value, wave-uniform.
+__device__ __forceinline__ double lane_f64(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <class Op>
 __device__ __forceinline__ double wave_reduce(double v, Op op) {
   v = op(v, dpp_f64<0xB1>(v));          // quad_perm [1,0,3,2]
@@ -212,6 +222,16 @@ __device__ __forceinline__ double nan_max(double a, double b) {
 
 __device__ __forceinline__ double wave_nan_max(double v) {
   return wave_reduce(v, [](double x, double y) { return nan_max(x, y); });
+}
+
+// Sum over each 16-lane row of the wave in a fixed order; every lane of a
+// row receives its row's sum (four DPP steps, no cross-row moves).
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
+  return v;
 }
 
 // Residual records: one double2 per tile or block, (max|phi^(l) - phi^(l-1)|,

@@ -780,20 +780,19 @@ __device__ inline void halo_iterate(const StepArgs &a, int hc, const double *lef
   const int ghp = (NF ? (2 * NF + 4 + 15) / 16 : a.Mt) * 16;
   const int r = a.cell_region[hc];
   const double *F = a.frag_it + (size_t)r * a.frag_it_stride;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = lane; k < K; k += 64) {
+  // row q of the wave (lanes 16q .. 16q+15) forms component q
+  const int q = lane >> 4, row = K + q;   // scalar-flux rows of G, packed k-major
+  double acc = 0.0;
+  for (int k = lane & 15; k < K; k += 16) {
     const double v = k < N ? right[k] : left[k];
     const int kq = k / KS, ks = k - kq * KS;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int row = K + c;   // scalar-flux rows of G, packed k-major
-      acc[c] += F[((size_t)(row >> 4) * KS + ks) * 64 + (row & 15) + 16 * kq] * v;
-    }
+    acc += F[((size_t)(row >> 4) * KS + ks) * 64 + (row & 15) + 16 * kq] * v;
   }
+  acc = row_sum16(acc);
   const double *gh = a.gh + (size_t)hc * ghp;
   double ph[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) ph[c] = wave_sum(acc[c]) + gh[K + c];
+  for (int c = 0; c < 4; ++c) ph[c] = lane_f64(acc, 16 * c) + gh[K + c];
   for (int j = lane; j < N / 2; j += 64) {
     const int m = pos ? N / 2 + j : j;
     const double *cf = a.coef + ((size_t)r * N + m) * kCoef;
@@ -818,12 +817,13 @@ __device__ __forceinline__ void mirror_row(double *ghost, const double *cell, in
 
 // The scalar-flux rows of one iterate of the tile's own cells from the rows
 // at `base` (row 0 = cell c0-1): MFMA partials per wave into phis, summed by
-// wave 0 with h into phif, stored to phi_out with the residual record against
-// po; returns wave 0's value for its (cell, component).
+// wave 0 with h into phif and stored to phi_out; the residual record's lane
+// values against po (|change|, |value|) go to rv[0..63], rv[64..127] in LDS
+// for flush_records.  Returns wave 0's value for its (cell, component).
 template <int CH, bool VEC, int NF>
 __device__ inline double own_phi(const StepArgs &a, const TileDev &t, const double *base,
                                  const double (&fp)[kPhiPre], double hv, double po,
-                                 double *phis, double *phif, double *phi_out, double2 *rec) {
+                                 double *phis, double *phif, double *phi_out, double *rv) {
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -863,12 +863,25 @@ __device__ inline double own_phi(const StepArgs &a, const TileDev &t, const doub
       dphi = isfinite(v) ? fabs(v - po) : __builtin_nan("");
       fphi = fabs(v);
     }
-    dphi = wave_nan_max(dphi);
-    fphi = wave_max(fphi);
-    if (lane == 0) *rec = make_double2(dphi, fphi);
+    rv[lane] = dphi;
+    rv[64 + lane] = fphi;
   }
   __syncthreads();
   return v;
+}
+
+// The residual records of the launch's iterates l .. l+n-1 from their lane
+// values (rv, 128 per iterate, after a barrier): one wave per iterate, off
+// the iterates' own path.
+__device__ inline void flush_records(const StepArgs &a, int l, int n, int half, const double *rv) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
+  for (int i = wave; i < n; i += W) {
+    const double d = wave_nan_max(rv[i * 128 + lane]);
+    const double f = wave_max(rv[i * 128 + 64 + lane]);
+    if (lane == 0)
+      reinterpret_cast<double2 *>(a.partial)[rec_slot(a, l + i, half) + blockIdx.x] =
+          make_double2(d, f);
+  }
 }
 
 // Outgoing pairs of one iterate of the own cells (this thread's angle and
@@ -916,7 +929,7 @@ template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, int cb, int half,
                                                          int nred) {
   extern __shared__ double lds[];
-  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
+  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64], rv[2 * 128];
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -935,7 +948,6 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   const double *phi_old = phi_at(a, b0);
   const int b1 = ring_buf(a, l, half), b2 = ring_buf(a, l + 1, half);
   const TileDev t = blk_desc<ARGT>(a);
-  const int ti = blockIdx.x;
   double *A = lds, *B = lds + kBlkA * P;
   const int ghp = sh.Mt * 16;
   // loads that need no LDS: the first operator chunk of this wave's share of
@@ -992,9 +1004,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   if (hr && wave == wr)
     halo_iterate<NF>(a, t.c0 + t.nc, A + (t.nc + 1) * P, A + (t.nc + 3) * P, false,
                      B + (t.nc + 1) * P);
-  double2 *rl = reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l, half) + ti;
-  double2 *rl2 = reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l + 1, half) + ti;
-  const double vl = own_phi<CH, VEC, NF>(a, t, A + P, fp, hv, po, phis, phif, phi_at(a, b1), rl);
+  const double vl = own_phi<CH, VEC, NF>(a, t, A + P, fp, hv, po, phis, phif, phi_at(a, b1), rv);
   own_pairs<NF>(a, t, A + P, phif, cf, gq, out_at(a, b1), B);
   __syncthreads();
   // iterate l at the mesh edges: ghost rows of B
@@ -1011,8 +1021,9 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
     __syncthreads();
   }
   // iterate l+1 of the own cells from B
-  own_phi<CH, VEC, NF>(a, t, B, fp, hv, vl, phis, phif, phi_at(a, b2), rl2);
+  own_phi<CH, VEC, NF>(a, t, B, fp, hv, vl, phis, phif, phi_at(a, b2), rv + 128);
   own_pairs<NF>(a, t, B, phif, cf, gq, out_at(a, b2), nullptr);
+  flush_records(a, l, 2, half, rv);
   open_step(a, l, cur, fb, stalled);
 }
 
@@ -1050,21 +1061,21 @@ struct HaloLds {
 // Scalar flux of a halo cell from its neighbours' rows (left: cell c-1,
 // right: c+1) at the level before: h + (scalar-flux rows of G) x incident,
 // with the rows of G (hf, [4][K]) and the cell's step constants (hg) in LDS.
-// One wave; every lane returns the four values.
+// One wave; the lanes of row q (16q .. 16q+15) return component q.
 template <int NF>
-__device__ inline void cell_phi(const double *left, const double *right, const double *hf,
-                                const double *hg, double (&ph)[4]) {
+__device__ inline double cell_phi(const double *left, const double *right, const double *hf,
+                                  const double *hg) {
   constexpr int N = NF, K = 2 * N;
-  const int lane = threadIdx.x & 63;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int lane = threadIdx.x & 63, q = lane >> 4;   // row q of the wave: component q
+  double acc = 0.0;
+  static_assert(K % 16 == 0, "a row of 16 lanes covers K in whole passes");
 #pragma unroll
-  for (int k = lane; k < K; k += 64) {
+  for (int i = 0; i < K / 16; ++i) {
+    const int k = (lane & 15) + 16 * i;
     const double v = k < N ? right[k] : left[k];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] += hf[q * K + k] * v;
+    acc += hf[q * K + k] * v;
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) ph[q] = wave_sum(acc[q]) + hg[K + q];
+  return row_sum16(acc) + hg[K + q];
 }
 
 template <int CH, bool ARGT, bool VEC, int NF, int KI>
@@ -1075,7 +1086,8 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   constexpr int RB = kTileCells + 2 * KI;   // rows per LDS block
   constexpr int NS = 2 * (KI - 1);          // halo slots
   extern __shared__ double lds[];
-  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64], hph[NS][4];
+  __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64], hph[NS][4],
+      rv[KI * 128];
   __shared__ int hsel[NS];
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
@@ -1102,7 +1114,6 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   }
   const double *src = out_at(a, b0);
   const double *phi_old = phi_at(a, b0);
-  const int ti = blockIdx.x;
   double *X = lds, *Y = lds + RB * P;
   double *HF = lds + 2 * RB * P, *HC = HF + HL::nF, *HG = HC + HL::nC;
   const int cbase = t.c0 - KI;   // cell of LDS row 0
@@ -1191,17 +1202,17 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
       const bool left = h < nl;
       const int c = left ? lo + h : t.c0 + t.nc + (h - nl);
       const int sl = left ? t.c0 - 1 - c : KI - 1 + c - (t.c0 + t.nc);
-      double ph[4];
-      cell_phi<NF>(row(in, c - 1), row(in, c + 1), HF + hsel[sl] * 4 * K, HG + sl * (K + 4), ph);
-      if (lane < 4) hph[h][lane] = ph[lane];
+      const double ph =
+          cell_phi<NF>(row(in, c - 1), row(in, c + 1), HF + hsel[sl] * 4 * K, HG + sl * (K + 4));
+      if ((lane & 15) == 0) hph[h][lane >> 4] = ph;
     }
     const int bl = ring_buf(a, lvl, half);
     pl = own_phi<CH, VEC, NF>(a, t, row(in, t.c0 - 1), fp, hv, pl, phis, phif, phi_at(a, bl),
-                              reinterpret_cast<double2 *>(a.partial) + rec_slot(a, lvl, half) +
-                                  ti);
+                              rv + (s - 1) * 128);
     own_pairs<NF>(a, t, row(in, t.c0 - 1), phif, cf, gq, out_at(a, bl),
                   s < KI ? row(out, t.c0 - 1) : nullptr);
     if (s == KI) {
+      flush_records(a, l, KI, half, rv);
       open_step(a, l, cur, fb, stalled);
       break;
     }
