@@ -224,14 +224,19 @@ __device__ __forceinline__ double wave_nan_max(double v) {
   return wave_reduce(v, [](double x, double y) { return nan_max(x, y); });
 }
 
-// Sum over each 16-lane row of the wave in a fixed order; every lane of a
-// row receives its row's sum (four DPP steps, no cross-row moves).
-__device__ __forceinline__ double row_sum16(double v) {
-  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);   // row_half_mirror
-  v += dpp_f64<0x140>(v);   // row_mirror
+// Reduction over each 16-lane row of the wave in a fixed order; every lane
+// of a row receives its row's result (four DPP steps, no cross-row moves).
+template <class Op>
+__device__ __forceinline__ double row_reduce16(double v, Op op) {
+  v = op(v, dpp_f64<0xB1>(v));    // quad_perm [1,0,3,2]
+  v = op(v, dpp_f64<0x4E>(v));    // quad_perm [2,3,0,1]
+  v = op(v, dpp_f64<0x141>(v));   // row_half_mirror
+  v = op(v, dpp_f64<0x140>(v));   // row_mirror
   return v;
+}
+
+__device__ __forceinline__ double row_sum16(double v) {
+  return row_reduce16(v, [](double x, double y) { return x + y; });
 }
 
 // Residual records: one double2 per tile or block, (max|phi^(l) - phi^(l-1)|,

@@ -495,6 +495,44 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
   issue_copy(pf.cr, blk, 1, K);
 }
 
+// The outgoing pairs of iterate_compute for this thread's angle and cells.
+template <int NF, int CH>
+__device__ inline void iterate_pairs(const IterPrefetch<CH> &pf, const StepArgs &a,
+                                     const TileDev &t, double *dst, const double *lds,
+                                     const double *phif, const PairMap &pm, bool defect) {
+  const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
+  const int ghp = (NF ? (2 * NF + 4 + 15) / 16 : a.Mt) * 16;
+  const int m = pm.m;
+  const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
+  int j = 0;
+  for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
+    const double *in = lds + (pos ? cl : cl + 2) * P + 2 * m;
+    const double *ph = phif + cl * 4;
+    const double i0 = in[0], i1 = in[1];
+    const double f0 = ph[0], f1 = ph[1], f2 = ph[2], f3 = ph[3];
+    const size_t cell = (size_t)(t.c0 + cl);
+    double g0, g1;
+    if (j < kGPre) {
+      g0 = pf.gq[j < kGPre ? j : 0][0];
+      g1 = pf.gq[j < kGPre ? j : 0][1];
+    } else {
+      g0 = a.gh[cell * ghp + 2 * m];
+      g1 = a.gh[cell * ghp + 2 * m + 1];
+    }
+    const double *c = pf.cf;
+    const double o0 = g0 + c[0] * f0 + c[1] * f1 + c[2] * f2 + c[3] * f3 + c[4] * i0 + c[5] * i1;
+    const double o1 = g1 + c[6] * f0 + c[7] * f1 + c[8] * f2 + c[9] * f3 + c[10] * i0 + c[11] * i1;
+    dst[(cell + 1) * K + 2 * m] = o0;
+    dst[(cell + 1) * K + 2 * m + 1] = o1;
+    // the defect against the iterate this one was computed from (its own
+    // row is staged in LDS row cl+1)
+    if (defect) {
+      a.dlt[(cell + 1) * K + 2 * m] = (float)(o0 - lds[(cl + 1) * P + 2 * m]);
+      a.dlt[(cell + 1) * K + 2 * m + 1] = (float)(o1 - lds[(cl + 1) * P + 2 * m + 1]);
+    }
+  }
+}
+
 // Computes the tile's iterate; wave 0 writes its residual record (rec).
 // Returns early (no stores) when `skip` is set (a stalled queue).  With
 // `defect`, also the FP32 defect against the iterate this one started from.
@@ -508,7 +546,6 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
   const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
-  const int ghp = sh.Mt * 16;
   {
     const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
     finish_copy(pf.cr, blk, 1, K, P);
@@ -541,6 +578,7 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
     }
   }
   __syncthreads();
+  double dphi = 0.0, fphi = 0.0;   // wave 0: this lane's residual values
   if (wave == 0) {
     // scalar flux of (cell, component) = lane: the waves' partials in order
     const int cl = lane >> 2, comp = lane & 3;
@@ -548,51 +586,25 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
     for (int w = 0; w < W; ++w) s += phis[w * 64 + lane];
     const double v = s + pf.hv;
     phif[lane] = v;
-    double dphi = 0.0, fphi = 0.0;
     if (cl < t.nc) {
       phi_new[(size_t)(t.c0 + cl) * 4 + comp] = v;
       if (defect) a.dphi32[(size_t)(t.c0 + cl) * 4 + comp] = (float)(v - pf.po);
       dphi = isfinite(v) ? fabs(v - pf.po) : __builtin_nan("");
       fphi = fabs(v);
     }
+  }
+  __syncthreads();
+  // outgoing pairs of this thread's angle for its cells; then wave 0 reduces
+  // the residual record (after the pairs, so that no wave waits for it)
+  const PairMap pm(N);
+  if (pm.active) iterate_pairs<NF>(pf, a, t, dst, lds, phif, pm, defect);
+  if (wave == 0) {
     dphi = wave_nan_max(dphi);
     fphi = wave_max(fphi);
     if (lane == 0) *rec = make_double2(dphi, fphi);
   }
-  __syncthreads();
-  // outgoing pairs of this thread's angle for its cells
-  const PairMap pm(N);
-  if (!pm.active) return;
-  const int m = pm.m;
-  const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
-  int j = 0;
-  for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
-    const double *in = lds + (pos ? cl : cl + 2) * P + 2 * m;
-    const double *ph = phif + cl * 4;
-    const double i0 = in[0], i1 = in[1];
-    const double f0 = ph[0], f1 = ph[1], f2 = ph[2], f3 = ph[3];
-    const size_t cell = (size_t)(t.c0 + cl);
-    double g0, g1;
-    if (j < kGPre) {
-      g0 = pf.gq[j < kGPre ? j : 0][0];
-      g1 = pf.gq[j < kGPre ? j : 0][1];
-    } else {
-      g0 = a.gh[cell * ghp + 2 * m];
-      g1 = a.gh[cell * ghp + 2 * m + 1];
-    }
-    const double *c = pf.cf;
-    const double o0 = g0 + c[0] * f0 + c[1] * f1 + c[2] * f2 + c[3] * f3 + c[4] * i0 + c[5] * i1;
-    const double o1 = g1 + c[6] * f0 + c[7] * f1 + c[8] * f2 + c[9] * f3 + c[10] * i0 + c[11] * i1;
-    dst[(cell + 1) * K + 2 * m] = o0;
-    dst[(cell + 1) * K + 2 * m + 1] = o1;
-    // the defect against the iterate this one was computed from (its own
-    // row is staged in LDS row cl+1)
-    if (defect) {
-      a.dlt[(cell + 1) * K + 2 * m] = (float)(o0 - lds[(cl + 1) * P + 2 * m]);
-      a.dlt[(cell + 1) * K + 2 * m + 1] = (float)(o1 - lds[(cl + 1) * P + 2 * m + 1]);
-    }
-  }
 }
+
 
 // End of step for a tile.  The accepted iterate L solved every cell's
 // system (A - S) psi = c with the incident fluxes of iterate L-1 (src = the
@@ -1327,27 +1339,27 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
         f[j] = nan_max(f[j], v[j].y);
       }
     }
-    __shared__ double tscr[kMaxWaves][2 * kMaxTrail];
-    const int wave = threadIdx.x >> 6;
+    // within each 16-lane row (DPP), then over the rows of all waves in LDS
+    __shared__ double tscr[4 * kMaxWaves][2 * kMaxTrail];
 #pragma unroll
     for (int j = 0; j < kMaxTrail; ++j) {
-      d[j] = wave_nan_max(d[j]);
-      f[j] = wave_nan_max(f[j]);
+      d[j] = row_reduce16(d[j], [](double x, double y) { return nan_max(x, y); });
+      f[j] = row_reduce16(f[j], [](double x, double y) { return nan_max(x, y); });
     }
-    if ((threadIdx.x & 63) == 0) {
+    if ((threadIdx.x & 15) == 0) {
 #pragma unroll
       for (int j = 0; j < kMaxTrail; ++j) {
-        tscr[wave][2 * j] = d[j];
-        tscr[wave][2 * j + 1] = f[j];
+        tscr[threadIdx.x >> 4][2 * j] = d[j];
+        tscr[threadIdx.x >> 4][2 * j + 1] = f[j];
       }
     }
     __syncthreads();
     if (threadIdx.x < ntrail) {
       const int j = threadIdx.x;
       double dd = 0.0, ff = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        dd = nan_max(dd, tscr[w][2 * j]);
-        ff = nan_max(ff, tscr[w][2 * j + 1]);
+      for (int r = 0; r < (int)(blockDim.x >> 4); ++r) {
+        dd = nan_max(dd, tscr[r][2 * j]);
+        ff = nan_max(ff, tscr[r][2 * j + 1]);
       }
       sdec[last - j - l0] = rel_change(dd, ff);
     }
