@@ -812,7 +812,7 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
 // ---------------------------------------------------------------------------
 // One-cell inversion: queued steps.
 // ---------------------------------------------------------------------------
-constexpr int kWindow = 16;  // steps per queued window (one graph of whole steps)
+constexpr int kWindow = 32;  // steps per queued window (one graph of whole steps)
 constexpr int kColdBatch = 8;  // launches of a step with no previous step to go by
 constexpr int kColdOuter = 3;  // mixed precision: FP64 iterates of such a step
 
@@ -1042,7 +1042,7 @@ static int enqueue_window(oci_ctx *c, int first, int count, int batch, int half,
   OCI_CK(c, hipEventRecord(ev_start, c->stream));
   int left = count;
   while (left > 0) {
-    int G = kWindow;   // whole steps per graph: 16, 8, 4, 2 or 1
+    int G = kWindow;   // whole steps per graph: 32, 16, 8, 4, 2 or 1
     while (G > left) G >>= 1;
     hipGraphExec_t exec;
     int rc = step_graph(c, batch, G, half, c->gh_valid ? 0 : 1, phi_dev, &exec);
@@ -1130,10 +1130,10 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
     // a cold step (no previous count) goes alone; nothing is queued behind it
     while (q < n_steps && nwin < 2 && c->batch_hint > 0) {
       const int batch = step_batch(c, c->batch_hint);
-      // windows grow 1, 2, 4, .. kWindow steps, so that a count learnt from
+      // windows grow 1, 4, 16, .. kWindow steps, so that a count learnt from
       // few steps is not applied to many
       const int count = std::min(c->window, n_steps - q);
-      c->window = std::min(kWindow, 2 * c->window);
+      c->window = std::min(kWindow, 4 * c->window);
       const int ev = next_ev;
       next_ev ^= 1;
       rc = enqueue_window(c, q, count, batch, c->parity ^ ((q - k) & 1), phi_dev,
