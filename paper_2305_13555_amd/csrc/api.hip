@@ -64,6 +64,7 @@ struct oci_ctx {
   double *d_psi[2] = {nullptr, nullptr}, *d_phi_res = nullptr, *d_partial = nullptr;
   double *d_ainv = nullptr, *d_contrib = nullptr, *d_lag = nullptr, *d_si_partial = nullptr;
   double *d_coef = nullptr;
+  double *d_phig = nullptr;   // [R][4][2N] scalar-flux rows of G, plain
   Affine *d_segmap = nullptr;
   StepCtl *d_ctl = nullptr;
   StepCtl *h_ctl = nullptr;                  // pinned host copy of the control block
@@ -292,7 +293,7 @@ static int build_operators(oci_ctx *c) {
                      c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
   hipLaunchKernelGGL(k_cell_operator, dim3(R), dim3(256), (size_t)(32 * N + 4) * sizeof(double),
                      c->stream, c->d_regions, c->d_mu, c->d_w, c->d_ainv, N, c->a, c->d_op,
-                     d_bad);
+                     c->d_phig, d_bad);
   // iteration operator G: rows [0, 2N+4), columns [0, 2N) (incident), k-major
   hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, 0, K,
                      c->Mt, c->d_fi, c->fi_stride, (double *)nullptr, (size_t)0, 1);
@@ -462,6 +463,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_partial, (size_t)2 * c->nbuf * c->ntiles * 2));
   OCI_TRY(dalloc(c, &c->d_ainv, (size_t)R * N * 16));
   OCI_TRY(dalloc(c, &c->d_coef, (size_t)R * N * kCoef));
+  OCI_TRY(dalloc(c, &c->d_phig, (size_t)R * 8 * N));
   OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(N / 2) * J * 4));
   OCI_TRY(dalloc(c, &c->d_lag, (size_t)2 * N));
   OCI_TRY(dalloc(c, &c->d_segmap, (size_t)(N / 2) * c->si_segs * 2));
@@ -545,6 +547,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   s.mu = c->d_mu;
   s.ainv = c->d_ainv;
   s.coef = c->d_coef;
+  s.phig = c->d_phig;
   s.cell_region = c->d_cell_region;
   s.at = c->a;
   s.gh = c->d_gh;

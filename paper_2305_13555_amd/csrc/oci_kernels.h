@@ -45,7 +45,9 @@ struct StepArgs {
   const RegionDev *regions; // [R] cell width and cross sections (end of step)
   const double *mu;        // [N]
   const double *ainv;      // [R][N][16] A_m^{-1} per region and angle
-  const double *coef;      // [R][N][kCoef] outgoing-pair and step-constant coefficients
+  const double *coef;      // [R][kCoef][N] outgoing-pair and step-constant coefficients
+                           //   (coefficient-major: value i of angle m at (r*kCoef+i)*N+m)
+  const double *phig;      // [R][4][2N] scalar-flux rows of G (incident columns), plain
   const int *cell_region;  // [J] (halo cells of the two-iterate kernel)
   double at;               // 1/(v dt), 0 for v = inf
   double *gh;              // [J][Mt*16]
@@ -108,7 +110,8 @@ struct ZeroRanges {
 // setup.hip
 __global__ void k_zero(ZeroRanges z);
 __global__ void k_cell_operator(const RegionDev *regions, const double *mu, const double *w,
-                                const double *ainv, int N, double a, double *op_all, int *bad);
+                                const double *ainv, int N, double a, double *op_all,
+                                double *phig, int *bad);
 __global__ void k_out_coef(const RegionDev *regions, const double *mu, const double *ainv, int N,
                            int R, double a, double *coef);
 __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,

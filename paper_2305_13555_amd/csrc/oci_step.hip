@@ -314,6 +314,11 @@ struct PairMap {
   }
 };
 
+// Coefficient i of (region r, angle m) (coefficient-major table).
+__device__ __forceinline__ double coef_at(const StepArgs &a, int N, int r, int m, int i) {
+  return a.coef[((size_t)r * kCoef + i) * N + m];
+}
+
 // The scalar-flux rows 2N .. 2N+3 of G and P: their row tile and the first of
 // them within it (2N is a multiple of 4, so all four share one row tile).
 __device__ __forceinline__ void phi_tile(int N, int *rt, int *off) {
@@ -370,8 +375,9 @@ __device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const dou
   }
   const PairMap pm(N);
   if (pm.active) {
-    const double *cf = a.coef + ((size_t)t.region * N + pm.m) * kCoef + 12;
-    const double c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3], c4 = cf[4], c5 = cf[5];
+    const double c0 = coef_at(a, N, t.region, pm.m, 12), c1 = coef_at(a, N, t.region, pm.m, 13),
+                 c2 = coef_at(a, N, t.region, pm.m, 14), c3 = coef_at(a, N, t.region, pm.m, 15),
+                 c4 = coef_at(a, N, t.region, pm.m, 16), c5 = coef_at(a, N, t.region, pm.m, 17);
     int j = 0;
     for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
       const double pl = rows[cl * P + 2 * pm.m], pr = rows[cl * P + 2 * pm.m + 1];
@@ -470,9 +476,8 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
   phi_ksplit(KS, W, wave, &kb, &ke);
   load_frags<kPhiPre>(pf.fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
   const PairMap pm(N);
-  const double *cf = a.coef + ((size_t)t.region * N + pm.m) * kCoef;
 #pragma unroll
-  for (int i = 0; i < 12; ++i) pf.cf[i] = cf[i];
+  for (int i = 0; i < 12; ++i) pf.cf[i] = coef_at(a, N, t.region, pm.m, i);
   if (go) {
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
@@ -637,9 +642,8 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
   const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
   double e[18], pq[kGPre][2];   // (and psi_{k-1/2} of this thread's first cells)
   {
-    const double *cf = a.coef + ((size_t)t.region * N + m) * kCoef + 18;
 #pragma unroll
-    for (int i = 0; i < 18; ++i) e[i] = cf[i];
+    for (int i = 0; i < 18; ++i) e[i] = coef_at(a, N, t.region, m, 18 + i);
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
@@ -787,18 +791,17 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
 template <int NF>
 __device__ inline void halo_iterate(const StepArgs &a, int hc, const double *left,
                                     const double *right, bool pos, double *orow) {
-  const int N = NF ? NF : a.N, K = 2 * N, KS = K / 4;
+  const int N = NF ? NF : a.N, K = 2 * N;
   const int lane = threadIdx.x & 63;
   const int ghp = (NF ? (2 * NF + 4 + 15) / 16 : a.Mt) * 16;
   const int r = a.cell_region[hc];
-  const double *F = a.frag_it + (size_t)r * a.frag_it_stride;
   // row q of the wave (lanes 16q .. 16q+15) forms component q
-  const int q = lane >> 4, row = K + q;   // scalar-flux rows of G, packed k-major
+  const int q = lane >> 4;
+  const double *Fq = a.phig + ((size_t)r * 4 + q) * K;   // scalar-flux row q of G
   double acc = 0.0;
   for (int k = lane & 15; k < K; k += 16) {
     const double v = k < N ? right[k] : left[k];
-    const int kq = k / KS, ks = k - kq * KS;
-    acc += F[((size_t)(row >> 4) * KS + ks) * 64 + (row & 15) + 16 * kq] * v;
+    acc += Fq[k] * v;
   }
   acc = row_sum16(acc);
   const double *gh = a.gh + (size_t)hc * ghp;
@@ -807,7 +810,9 @@ __device__ inline void halo_iterate(const StepArgs &a, int hc, const double *lef
   for (int c = 0; c < 4; ++c) ph[c] = lane_f64(acc, 16 * c) + gh[K + c];
   for (int j = lane; j < N / 2; j += 64) {
     const int m = pos ? N / 2 + j : j;
-    const double *cf = a.coef + ((size_t)r * N + m) * kCoef;
+    double cf[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) cf[i] = coef_at(a, N, r, m, i);
     const double *in = (pos ? left : right) + 2 * m;   // the halo cell's entering flux
     const double i0 = in[0], i1 = in[1];
     orow[2 * m] = gh[2 * m] + cf[0] * ph[0] + cf[1] * ph[1] + cf[2] * ph[2] + cf[3] * ph[3] +
@@ -976,9 +981,8 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   }
   const PairMap pm(N);
   {
-    const double *c = a.coef + ((size_t)t.region * N + pm.m) * kCoef;
 #pragma unroll
-    for (int i = 0; i < 12; ++i) cf[i] = c[i];
+    for (int i = 0; i < 12; ++i) cf[i] = coef_at(a, N, t.region, pm.m, i);
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
@@ -1141,9 +1145,8 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   }
   const PairMap pm(N);
   {
-    const double *c = a.coef + ((size_t)t.region * N + pm.m) * kCoef;
 #pragma unroll
-    for (int i = 0; i < 12; ++i) cf[i] = c[i];
+    for (int i = 0; i < 12; ++i) cf[i] = coef_at(a, N, t.region, pm.m, i);
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
@@ -1173,13 +1176,11 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
     const int idx = (int)threadIdx.x + i * HL::threads;
     double v = 0.0;
     if (idx < HL::nF) {
-      const int rsl = idx / (4 * K), q = (idx / K) & 3, k = idx % K;
-      const int rowg = K + q, kq = k / KS, ks = k - kq * KS;
-      v = a.frag_it[(size_t)rg[rsl] * a.frag_it_stride +
-                    ((size_t)(rowg >> 4) * KS + ks) * 64 + (rowg & 15) + 16 * kq];
+      const int rsl = idx / (4 * K), qk = idx - rsl * 4 * K;
+      v = a.phig[(size_t)rg[rsl] * 4 * K + qk];
     } else if (idx < HL::nF + HL::nC) {
       const int j = idx - HL::nF, rsl = j / (12 * N), ci = (j / N) % 12, m = j % N;
-      v = a.coef[((size_t)rg[rsl] * N + m) * kCoef + ci];
+      v = coef_at(a, N, rg[rsl], m, ci);
     } else if (idx < HL::total) {
       const int j = idx - HL::nF - HL::nC, sl = j / (K + 4), e = j - sl * (K + 4);
       const int c = slot_cell(sl);

@@ -40,12 +40,13 @@ __device__ __forceinline__ int outgoing_corner(int m, int N, int tl) {
 
 // One work-group per region: the operator rows op [2N+4+2N][4N+1] (outgoing
 // fluxes, scalar flux, time-edge values; columns: incident 2N, time edge 2N,
-// source) from the A_m^{-1} (ainv [R][N][16]).  Dynamic LDS: (32N + 4)
-// doubles.  A singular or non-finite 4x4 system sets *bad.
+// source) from the A_m^{-1} (ainv [R][N][16]), and the scalar-flux rows of
+// its incident columns once more, plain: phig [R][4][2N].  Dynamic LDS:
+// (32N + 4) doubles.  A singular or non-finite 4x4 system sets *bad.
 __global__ __launch_bounds__(256) void k_cell_operator(const RegionDev *regions,
                                                         const double *mu, const double *w,
                                                         const double *ainv, int N, double a,
-                                                        double *op_all, int *bad) {
+                                                        double *op_all, double *phig, int *bad) {
   extern __shared__ double sh[];
   __shared__ double Ks[16], Kinv[16];
   const int r = blockIdx.x, tid = threadIdx.x;
@@ -126,6 +127,8 @@ __global__ __launch_bounds__(256) void k_cell_operator(const RegionDev *regions,
                          Kinv[c * 4 + 2] * v[2] + Kinv[c * 4 + 3] * v[3];
   }
   __syncthreads();
+  for (int i = tid; i < 4 * 2 * N; i += blockDim.x)
+    phig[(size_t)r * 8 * N + i] = Ph[(i / (2 * N)) * nr + i % (2 * N)];
   // Y rows: angle m, corner c: (A_m^{-1} [B|T|q])[(m,c), col] + s (A_m^{-1} Phi)[c, col]
   double *op = op_all + (size_t)r * rows * nr;
   for (int idx = tid; idx < rows * nr; idx += blockDim.x) {
@@ -196,7 +199,10 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
 // scattering source s phi (s = dx Sigma_s / 4), the entering fluxes |mu| inc
 // (entering-corner columns in_t), and give the step constant from the source
 // (dx Q / 4 in every row) and the time edge (dx / (2 v dt) psi_{k-1/2} in the
-// two level-k rows).  Layout and use: oci_step.hip, "The structured apply".
+// two level-k rows).  Layout: coefficient-major, value i of (region r,
+// angle m) at coef[(r * kCoef + i) * N + m], so that the threads of a
+// work-group (consecutive angles) read consecutive addresses.  Use:
+// oci_step.hip, "The structured apply".
 __global__ void k_out_coef(const RegionDev *regions, const double *mu, const double *ainv, int N,
                            int R, double a, double *coef) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,7 +215,7 @@ __global__ void k_out_coef(const RegionDev *regions, const double *mu, const dou
   const double s = g.dx * g.sigs / 4.0, amu = fabs(mu[m]);
   const double qq = g.dx * g.q / 4.0, ts = a * g.dx / 2.0;
   const double *Ai = ainv + (size_t)idx * 16;
-  double *cf = coef + (size_t)idx * kCoef;
+  double cf[kCoef];
   for (int t = 0; t < 2; ++t) {
     const double *row = Ai + o[t] * 4;
     for (int c = 0; c < 4; ++c) cf[6 * t + c] = s * row[c];
@@ -229,6 +235,7 @@ __global__ void k_out_coef(const RegionDev *regions, const double *mu, const dou
     cf[25 + 9 * u] = amu * row[in1];
     cf[26 + 9 * u] = qq * (row[0] + row[1] + row[2] + row[3]);
   }
+  for (int k = 0; k < kCoef; ++k) coef[((size_t)r * kCoef + k) * N + m] = cf[k];
 }
 
 // Clear z.count ranges of doubles (one launch instead of one fill per range).
