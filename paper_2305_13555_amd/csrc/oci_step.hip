@@ -1302,13 +1302,19 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   RecRegs r1;
   if (!pre) rec_issue(r1, recs + rec_slot(a, last, half), a.ntiles);
+  // the e of the earlier iterates (written by earlier launches), loaded with
+  // the records, before the control block (at most kMaxRing + 1 <= 2 * 64 of them)
+  __shared__ double sdec[kMaxRing + 1];
+  const int l0 = first - 1 >= 1 ? first - 1 : first;
+  const int nd = last - l0 + 1;
+  const int i0 = threadIdx.x, i1 = threadIdx.x + blockDim.x;
+  const double dv0 = i0 < nd ? a.dec[(l0 + i0) % a.nbuf] : 0.0;
+  const double dv1 = i1 < nd ? a.dec[(l0 + i1) % a.nbuf] : 0.0;
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
   const TileDev t = blk_desc<ARGT>(a);
-  // the e of the earlier iterates (written by later launches), all at once
-  __shared__ double sdec[kMaxRing + 1];
-  const int l0 = first - 1 >= 1 ? first - 1 : first;
-  for (int i = threadIdx.x; i <= last - l0; i += blockDim.x) sdec[i] = a.dec[(l0 + i) % a.nbuf];
+  if (i0 < nd) sdec[i0] = dv0;
+  if (i1 < nd) sdec[i1] = dv1;
   __syncthreads();
   // the e of the trailing iterates (those of the last launch) into sdec:
   // reduced by k_reduce_rec (many tiles: one reduction, not one per
@@ -1368,18 +1374,29 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   }
   auto e_of = [&](int l) { return sdec[l - l0]; };
   const int step = c.open;
+  // the first of the candidate iterates first, first + rstep, .. last that
+  // the stopping rule stops at: every candidate judged by a thread of its
+  // own (with the e of the candidate before it), the first one by an LDS min
+  const int ncand = (last - first) / rstep + 1;
+  auto e_before_of = [&](int i, int l) {
+    if (i == 0) return (a.strict && first - 1 >= 2) ? e_of(first - 1) : -1.0;
+    return l - rstep >= 2 ? e_of(l - rstep) : -1.0;
+  };
+  __shared__ int s_first;
+  if (threadIdx.x == 0) s_first = ncand;
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncand; i += blockDim.x) {
+    const int l = first + i * rstep;
+    if (stop_rule_e(l, e_of(l), e_before_of(i, l), 2, a.tol, a.strict, a.max_iters) != kRunning)
+      atomicMin(&s_first, i);
+  }
+  __syncthreads();
   int status = kRunning, L = last;
   double e_acc = -1.0;
-  double e_before = (a.strict && first - 1 >= 2) ? e_of(first - 1) : -1.0;
-  for (int l = first; l <= last; l += rstep) {
-    const double e = e_of(l);
-    status = stop_rule_e(l, e, e_before, 2, a.tol, a.strict, a.max_iters);
-    if (status != kRunning) {
-      L = l;
-      e_acc = l >= 2 ? e : -1.0;
-      break;
-    }
-    e_before = l >= 2 ? e : -1.0;
+  if (s_first < ncand) {
+    L = first + s_first * rstep;
+    status = stop_rule_e(L, e_of(L), e_before_of(s_first, L), 2, a.tol, a.strict, a.max_iters);
+    e_acc = L >= 2 ? e_of(L) : -1.0;
   }
   const bool decided = status != kRunning && status != kNonFinite;
   // the outcome goes to fields no work-group of this launch reads (stored
