@@ -344,8 +344,8 @@ __device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *k
 // MFMA, k-steps split over the waves (f0: this wave's first fragments) and
 // summed in a fixed order; g' (rows 0 .. 2N-1) per (cell, angle).
 template <int CH, bool VEC, int NF>
-__device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const double *rows,
-                                  const double (&f0)[CH], GhOut *go = nullptr) {
+__device__ __forceinline__ void gh_compute(const StepArgs &a, const TileDev &t, const double *rows,
+                                  const double (&f0)[CH], GhOut &go, bool want_go) {
   __shared__ double hp[kMaxWaves * 64];
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
   const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
@@ -385,9 +385,13 @@ __device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const dou
       const double g0 = c0 + c1 * pl + c2 * pr, g1 = c3 + c4 * pl + c5 * pr;
       g[0] = g0;
       g[1] = g1;
-      if (go && j < kGPre) {
-        go->gq[j < kGPre ? j : 0][0] = g0;
-        go->gq[j < kGPre ? j : 0][1] = g1;
+      if (want_go) {   // (entry j by selects: a run-time index would put go in scratch)
+#pragma unroll
+        for (int i = 0; i < kGPre; ++i)
+          if (i == j) {
+            go.gq[i][0] = g0;
+            go.gq[i][1] = g1;
+          }
       }
     }
   }
@@ -398,7 +402,7 @@ __device__ inline void gh_compute(const StepArgs &a, const TileDev &t, const dou
     for (int w = 0; w < W; ++w) v += hp[w * 64 + lane];
     v += a.c_pv[(size_t)t.region * a.c_pv_stride + K + comp];
     if (cl < t.nc) a.gh[(size_t)(t.c0 + cl) * ghp + K + comp] = v;
-    if (go) go->hv = v;
+    if (want_go) go.hv = v;
   }
 }
 
@@ -425,7 +429,8 @@ __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const dou
   const RowBlock blk[1] = {own_block(lds, psi_prev, t, K)};
   copy_blocks_to_lds(blk, 1, K, P);
   __syncthreads();
-  gh_compute<CH, VEC, NF>(a, t, lds, f0);
+  GhOut unused;
+  gh_compute<CH, VEC, NF>(a, t, lds, f0, unused, false);
 }
 
 // One OCI iteration of a tile, in two phases: iterate_prefetch issues every
@@ -463,9 +468,9 @@ struct IterShape {
 // go: the step constants already in registers (the end of step that formed
 // them, same work-group and thread mapping), else loaded.
 template <int CH, int NF>
-__device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a, const TileDev &t,
+__device__ __forceinline__ void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a, const TileDev &t,
                                         const double *src, const double *phi_old, double *lds,
-                                        const GhOut *go = nullptr) {
+                                        const GhOut &go, bool have_go) {
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -478,11 +483,11 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
   const PairMap pm(N);
 #pragma unroll
   for (int i = 0; i < 12; ++i) pf.cf[i] = coef_at(a, N, t.region, pm.m, i);
-  if (go) {
+  if (have_go) {
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
-      pf.gq[j][0] = go->gq[j][0];
-      pf.gq[j][1] = go->gq[j][1];
+      pf.gq[j][0] = go.gq[j][0];
+      pf.gq[j][1] = go.gq[j][1];
     }
   } else {
 #pragma unroll
@@ -494,7 +499,7 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
   }
   const int cl = lane >> 2, comp = lane & 3;
   const int cc = t.c0 + min(cl, t.nc - 1);   // (used by wave 0 for cells < nc)
-  pf.hv = go ? go->hv : a.gh[(size_t)cc * ghp + K + comp];
+  pf.hv = have_go ? go.hv : a.gh[(size_t)cc * ghp + K + comp];
   pf.po = phi_old[(size_t)cc * 4 + comp];
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
   issue_copy(pf.cr, blk, 1, K);
@@ -502,7 +507,7 @@ __device__ inline void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a,
 
 // The outgoing pairs of iterate_compute for this thread's angle and cells.
 template <int NF, int CH>
-__device__ inline void iterate_pairs(const IterPrefetch<CH> &pf, const StepArgs &a,
+__device__ __forceinline__ void iterate_pairs(const IterPrefetch<CH> &pf, const StepArgs &a,
                                      const TileDev &t, double *dst, const double *lds,
                                      const double *phif, const PairMap &pm, bool defect) {
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
@@ -542,7 +547,7 @@ __device__ inline void iterate_pairs(const IterPrefetch<CH> &pf, const StepArgs 
 // Returns early (no stores) when `skip` is set (a stalled queue).  With
 // `defect`, also the FP32 defect against the iterate this one started from.
 template <int CH, bool VEC, int NF>
-__device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
+__device__ __forceinline__ void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
                                        double *phi_new, double *lds, double *phis, double *phif,
                                        double2 *rec, bool skip, bool defect) {
@@ -622,9 +627,9 @@ __device__ inline void iterate_compute(const IterPrefetch<CH> &pf, const StepArg
 // Also copies the accepted scalar flux to phi_res (and phi_out), and forms
 // the next step's gh from psi_{k+1/2} (kept in LDS).
 template <int CH, bool VEC, int NF>
-__device__ inline void tile_end(const StepArgs &a, const TileDev &t, const double *src,
+__device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, const double *src,
                                 const double *psi_prev, double *psi_next, const double *phi_acc,
-                                double *phi_out, double *lds, GhOut *go = nullptr) {
+                                double *phi_out, double *lds, GhOut &go, bool want_go) {
   __shared__ double sphi[4 * kTileCells];
   double fg[CH];   // P fragments for the next step's gh, issued early
   gh_frags<CH, NF>(a, t, fg);
@@ -685,7 +690,7 @@ __device__ inline void tile_end(const StepArgs &a, const TileDev &t, const doubl
   // the next step's gh from psi_{k+1/2}, so that a queued step that
   // follows needs no step start
   __syncthreads();
-  gh_compute<CH, VEC, NF>(a, t, ldn, fg, go);
+  gh_compute<CH, VEC, NF>(a, t, ldn, fg, go, want_go);
 }
 
 // Start of step `cur` of the current solve: gh for every tile from
@@ -762,7 +767,8 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   const int ti = blockIdx.x;   // the tile's residual record
   const TileDev t = blk_desc<ARGT>(a);
   IterPrefetch<CH> pf;
-  iterate_prefetch<CH, NF>(pf, a, t, src, phi_old, lds);
+  const GhOut none{};
+  iterate_prefetch<CH, NF>(pf, a, t, src, phi_old, lds, none, false);
   const int stalled = a.ctl->stalled;
   iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis, phif,
                       reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l, half) + ti,
@@ -1115,7 +1121,10 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   }
   const TileDev t = blk_desc<ARGT>(a);
   // the staged regions: before, the tile's, after (clamped to the mesh)
-  const int rg[3] = {max(t.region - 1, 0), t.region, min(t.region + 1, a.R - 1)};
+  const int rg0 = max(t.region - 1, 0), rg2 = min(t.region + 1, a.R - 1);
+  // (a select, not an indexed array: an array indexed at run time lives in
+  // scratch memory)
+  auto rg = [&](int rsl) { return rsl == 0 ? rg0 : (rsl == 1 ? t.region : rg2); };
   auto slot_cell = [&](int sl) { return sl < KI - 1 ? t.c0 - 1 - sl : t.c0 + t.nc + sl - (KI - 1); };
   int my_sel = 1;   // this thread's halo slot (threads < NS): its region slot
   if ((int)threadIdx.x < NS) {
@@ -1177,10 +1186,10 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
     double v = 0.0;
     if (idx < HL::nF) {
       const int rsl = idx / (4 * K), qk = idx - rsl * 4 * K;
-      v = a.phig[(size_t)rg[rsl] * 4 * K + qk];
+      v = a.phig[(size_t)rg(rsl) * 4 * K + qk];
     } else if (idx < HL::nF + HL::nC) {
       const int j = idx - HL::nF, rsl = j / (12 * N), ci = (j / N) % 12, m = j % N;
-      v = coef_at(a, N, rg[rsl], m, ci);
+      v = coef_at(a, N, rg(rsl), m, ci);
     } else if (idx < HL::total) {
       const int j = idx - HL::nF - HL::nC, sl = j / (K + 4), e = j - sl * (K + 4);
       const int c = slot_cell(sl);
@@ -1433,7 +1442,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   tile_end<CH, VEC, NF>(a, t, src, parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
                         phi_at(a, ring_buf(a, L, half)),
                         phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds,
-                        fuse ? &go : nullptr);
+                        go, fuse);
   if (!fuse) {
     record();
     return;
@@ -1444,7 +1453,7 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   __syncthreads();
   const int bl = ring_buf(a, L, half), bn = ring_buf(a, 1, half ^ 1);
   IterPrefetch<CH> pf;
-  iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds, &go);
+  iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds, go, true);
   iterate_compute<CH, VEC, NF>(pf, a, t, out_at(a, bl), out_at(a, bn), phi_at(a, bn), lds, phis,
                                phif,
                                reinterpret_cast<double2 *>(a.partial) +

@@ -72,22 +72,35 @@ __global__ __launch_bounds__(256) void k_cell_operator(const RegionDev *regions,
         M[i][4 + j] = i == j ? 1.0 : 0.0;
       }
     bool ok = true;
+    // (loops unrolled, the row swap by selects: M stays in registers)
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
       int p = k;
+      double best = fabs(M[k][k]);
+#pragma unroll
       for (int i = k + 1; i < 4; ++i)
-        if (fabs(M[i][k]) > fabs(M[p][k])) p = i;
-      if (p != k)
-        for (int j = 0; j < 8; ++j) {
-          const double tmp = M[k][j];
-          M[k][j] = M[p][j];
-          M[p][j] = tmp;
+        if (fabs(M[i][k]) > best) {
+          best = fabs(M[i][k]);
+          p = i;
         }
+#pragma unroll
+      for (int i = k + 1; i < 4; ++i)
+        if (i == p)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const double tmp = M[k][j];
+            M[k][j] = M[i][j];
+            M[i][j] = tmp;
+          }
       const double piv = M[k][k];
       if (!(fabs(piv) > 0.0) || !isfinite(piv)) ok = false;
+#pragma unroll
       for (int j = 0; j < 8; ++j) M[k][j] /= piv;
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (i == k) continue;
         const double l = M[i][k];
+#pragma unroll
         for (int j = 0; j < 8; ++j) M[i][j] -= l * M[k][j];
       }
     }

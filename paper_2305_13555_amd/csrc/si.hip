@@ -37,17 +37,35 @@ __global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, i
                     {-h, d, 0.0, t / 2.0, 0, 1, 0, 0},
                     {-t, 0.0, t + d, h, 0, 0, 1, 0},
                     {0.0, -t, -h, t + d, 0, 0, 0, 1}};
+  // (every loop unrolled and the row swap done by selects: the matrix stays
+  // in registers instead of scratch memory)
+#pragma unroll
   for (int k = 0; k < 4; ++k) {
     int p = k;
+    double best = fabs(A[k][k]);
+#pragma unroll
     for (int i = k + 1; i < 4; ++i)
-      if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
-    if (p != k)
-      for (int j = 0; j < 8; ++j) { const double tmp = A[k][j]; A[k][j] = A[p][j]; A[p][j] = tmp; }
+      if (fabs(A[i][k]) > best) {
+        best = fabs(A[i][k]);
+        p = i;
+      }
+#pragma unroll
+    for (int i = k + 1; i < 4; ++i)
+      if (i == p)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const double tmp = A[k][j];
+          A[k][j] = A[i][j];
+          A[i][j] = tmp;
+        }
     const double piv = A[k][k];
+#pragma unroll
     for (int j = 0; j < 8; ++j) A[k][j] /= piv;
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
       if (i == k) continue;
       const double l = A[i][k];
+#pragma unroll
       for (int j = 0; j < 8; ++j) A[i][j] -= l * A[k][j];
     }
   }
