@@ -626,39 +626,59 @@ __device__ __forceinline__ void iterate_compute(const IterPrefetch<CH> &pf, cons
 // a 4-vector per (cell, angle): O(N) per cell instead of a 2N x 4N product.
 // Also copies the accepted scalar flux to phi_res (and phi_out), and forms
 // the next step's gh from psi_{k+1/2} (kept in LDS).
+// The loads of tile_end that depend on the accepted iterate or the step,
+// all issued before its first store (a load issued after a store waits for
+// it): the accepted scalar flux (one value per thread, nc * 4 <= 64 <=
+// blockDim), this thread's angle's psi_{k-1/2} values, and the neighbour
+// rows of the iterate the accepted one was computed from (src; into LDS
+// later).
+struct EndLoads {
+  double pq[kGPre][2], pv;
+  CopyRegs cr;
+};
+
+template <int NF>
+__device__ __forceinline__ void end_loads(const StepArgs &a, const TileDev &t, const double *src,
+                                          const double *psi_prev, const double *phi_acc,
+                                          double *lds, EndLoads &el) {
+  const int N = NF ? NF : a.N, K = 2 * N;
+  const int pi = threadIdx.x;
+  el.pv = pi < t.nc * 4 ? phi_acc[(size_t)t.c0 * 4 + pi] : 0.0;
+  const PairMap pm(N);
+#pragma unroll
+  for (int j = 0; j < kGPre; ++j) {
+    const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
+    el.pq[j][0] = psi_prev[(size_t)(t.c0 + cl) * K + 2 * pm.m];
+    el.pq[j][1] = psi_prev[(size_t)(t.c0 + cl) * K + 2 * pm.m + 1];
+  }
+  const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
+  issue_copy(el.cr, blk, 1, K);
+}
+
+// (el: the loads of end_loads for these arguments when `loaded`, else
+// filled here)
 template <int CH, bool VEC, int NF>
 __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, const double *src,
                                 const double *psi_prev, double *psi_next, const double *phi_acc,
-                                double *phi_out, double *lds, GhOut &go, bool want_go) {
+                                double *phi_out, double *lds, GhOut &go, bool want_go,
+                                EndLoads &el, bool loaded) {
   __shared__ double sphi[4 * kTileCells];
   double fg[CH];   // P fragments for the next step's gh, issued early
   gh_frags<CH, NF>(a, t, fg);
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
   double *ldn = lds + (kTileCells + 2) * P;   // psi_{k+1/2} of the tile's cells
-  // every load is issued before the first store (a load issued after a
-  // store waits for it): the accepted scalar flux (one value per thread,
-  // nc * 4 <= 64 <= blockDim), this thread's coefficients and psi_{k-1/2},
-  // the neighbour rows
-  const int pi = threadIdx.x;
-  const double pv = pi < t.nc * 4 ? phi_acc[(size_t)t.c0 * 4 + pi] : 0.0;
-  // this thread's angle: the coefficients of psi_{k+1/2} at L and R
   const PairMap pm(N);
   const int m = pm.m;
   const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
-  double e[18], pq[kGPre][2];   // (and psi_{k-1/2} of this thread's first cells)
-  {
+  double e[18];   // this thread's angle's coefficients of psi_{k+1/2} at L and R
 #pragma unroll
-    for (int i = 0; i < 18; ++i) e[i] = coef_at(a, N, t.region, m, 18 + i);
-#pragma unroll
-    for (int j = 0; j < kGPre; ++j) {
-      const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
-      pq[j][0] = psi_prev[(size_t)(t.c0 + cl) * K + 2 * m];
-      pq[j][1] = psi_prev[(size_t)(t.c0 + cl) * K + 2 * m + 1];
-    }
-  }
+  for (int i = 0; i < 18; ++i) e[i] = coef_at(a, N, t.region, m, 18 + i);
+  if (!loaded) end_loads<NF>(a, t, src, psi_prev, phi_acc, lds, el);
+  const int pi = threadIdx.x;
+  const double pv = el.pv;
+  const double(&pq)[kGPre][2] = el.pq;
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
-  CopyRegs cr;
-  issue_copy(cr, blk, 1, K);
+  const CopyRegs &cr = el.cr;
   if (pi < t.nc * 4) {
     a.phi_res[(size_t)t.c0 * 4 + pi] = pv;
     if (phi_out) phi_out[(size_t)t.c0 * 4 + pi] = pv;
@@ -1302,7 +1322,7 @@ __global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, in
 // instead: the host resumes it.  The step's record is written either way; a
 // decided step advances the solve's step counter.
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, int first,
+__global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out, int first,
                                                   int last, int half, int rstep, int mode) {
   extern __shared__ double lds[];
   __shared__ double phis[4 * 64], phif[64];
@@ -1325,6 +1345,16 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
   if (i0 < nd) sdec[i0] = dv0;
   if (i1 < nd) sdec[i1] = dv1;
   __syncthreads();
+  // the end usually accepts the last iterate: the loads of its end of step
+  // are issued once the records are in, so that the reductions and the
+  // decision hide their latency, and used if it is accepted
+  const int parity = c.psi_base ^ (c.open & 1);
+  const double *psi_prev = parity ? a.psi1 : a.psi0;
+  const bool spec = last >= 2;
+  EndLoads sel;
+  if (pre && spec)
+    end_loads<NF>(a, t, out_at(a, ring_buf(a, last - 1, half)), psi_prev,
+                  phi_at(a, ring_buf(a, last, half)), lds, sel);
   // the e of the trailing iterates (those of the last launch) into sdec:
   // reduced by k_reduce_rec (many tiles: one reduction, not one per
   // work-group) or here, all of them in one pass over their records
@@ -1355,6 +1385,9 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
         f[j] = nan_max(f[j], v[j].y);
       }
     }
+    if (spec)
+      end_loads<NF>(a, t, out_at(a, ring_buf(a, last - 1, half)), psi_prev,
+                    phi_at(a, ring_buf(a, last, half)), lds, sel);
     // within each 16-lane row (DPP), then over the rows of all waves in LDS
     __shared__ double tscr[4 * kMaxWaves][2 * kMaxTrail];
 #pragma unroll
@@ -1435,14 +1468,13 @@ __global__ __launch_bounds__(256) void k_step_end(StepArgs a, double *phi_out, i
     record();
     return;
   }
-  const int parity = c.psi_base ^ (step & 1);
   // iterate L was computed from iterate L-1 (iterate 0: the step's start)
   const double *src = out_at(a, L == 1 ? c.base_buf : ring_buf(a, L - 1, half));
   GhOut go;
   tile_end<CH, VEC, NF>(a, t, src, parity ? a.psi1 : a.psi0, parity ? a.psi0 : a.psi1,
                         phi_at(a, ring_buf(a, L, half)),
                         phi_out ? phi_out + (size_t)step * a.J * 4 : nullptr, lds,
-                        go, fuse);
+                        go, fuse, sel, spec && L == last);
   if (!fuse) {
     record();
     return;
