@@ -1097,7 +1097,8 @@ struct HaloLds {
   static constexpr int nF = 12 * K, nC = 36 * NF, nG = 2 * (KI - 1) * (K + 4);
   static constexpr int total = nF + nC + nG;
   static constexpr int threads = 64 * ((2 * NF + 15) / 16 < 4 ? (2 * NF + 15) / 16 : 4);
-  static constexpr int per_thread = (total + threads - 1) / threads;
+  // staged in pairs of doubles (every segment has even length and offset)
+  static constexpr int per_thread = (total / 2 + threads - 1) / threads;
 };
 
 // Scalar flux of a halo cell from its neighbours' rows (left: cell c-1,
@@ -1173,9 +1174,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
     load_frags<kPhiPre>(fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
   }
   const PairMap pm(N);
-  {
-#pragma unroll
-    for (int i = 0; i < 12; ++i) cf[i] = coef_at(a, N, t.region, pm.m, i);
+  {   // (cf: from the staged coefficients of the tile's region, below)
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
@@ -1198,35 +1197,41 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
                                     RB - r_lo}};
   CopyRegs cr;
   issue_copy(cr, blk, 1, K);
-  // the halo staging loads (HF, HC, HG in that order)
-  double hreg[HL::per_thread];
+  // the halo staging loads (HF, HC, HG in that order), two doubles at a time:
+  // every segment (a region's 4 rows of G, its 12 coefficient rows, a halo
+  // cell's step constants) is contiguous in memory with an even length
+  double2 hreg[HL::per_thread];
 #pragma unroll
   for (int i = 0; i < HL::per_thread; ++i) {
-    const int idx = (int)threadIdx.x + i * HL::threads;
-    double v = 0.0;
+    const int idx = 2 * ((int)threadIdx.x + i * HL::threads);
+    double2 v = make_double2(0.0, 0.0);
+    const double *g = nullptr;
     if (idx < HL::nF) {
       const int rsl = idx / (4 * K), qk = idx - rsl * 4 * K;
-      v = a.phig[(size_t)rg(rsl) * 4 * K + qk];
+      g = a.phig + (size_t)rg(rsl) * 4 * K + qk;
     } else if (idx < HL::nF + HL::nC) {
-      const int j = idx - HL::nF, rsl = j / (12 * N), ci = (j / N) % 12, m = j % N;
-      v = coef_at(a, N, rg(rsl), m, ci);
+      const int j = idx - HL::nF, rsl = j / (12 * N), cm = j - rsl * 12 * N;
+      g = a.coef + (size_t)rg(rsl) * kCoef * N + cm;   // coefficients 0..11, all angles
     } else if (idx < HL::total) {
       const int j = idx - HL::nF - HL::nC, sl = j / (K + 4), e = j - sl * (K + 4);
       const int c = slot_cell(sl);
-      if (c >= 0 && c < a.J) v = a.gh[(size_t)c * ghp + e];
+      if (c >= 0 && c < a.J) g = a.gh + (size_t)c * ghp + e;
     }
+    if (g) v = *reinterpret_cast<const double2 *>(g);
     hreg[i] = v;
   }
   const int stalled = a.ctl->stalled;
   finish_copy(cr, blk, 1, K, P);
 #pragma unroll
   for (int i = 0; i < HL::per_thread; ++i) {
-    const int idx = (int)threadIdx.x + i * HL::threads;
-    if (idx < HL::total) HF[idx] = hreg[i];
+    const int idx = 2 * ((int)threadIdx.x + i * HL::threads);
+    if (idx < HL::total) *reinterpret_cast<double2 *>(HF + idx) = hreg[i];
   }
   if ((int)threadIdx.x < NS) hsel[threadIdx.x] = my_sel;
   __syncthreads();
   if (stalled) return;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) cf[i] = HC[(12 + i) * N + pm.m];   // region slot 1: the tile's
   const bool gl = cbase <= -1, gr = t.c0 + t.nc + KI - 1 >= a.J;   // ghost rows in the block
   if (gl && a.bcl == kBcReflect) mirror_row(row(X, -1), row(X, 0), N, true);
   if (gr && a.bcr == kBcReflect) mirror_row(row(X, a.J), row(X, a.J - 1), N, false);
