@@ -493,8 +493,12 @@ __device__ __forceinline__ void iterate_prefetch(IterPrefetch<CH> &pf, const Ste
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
-      pf.gq[j][0] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m];
-      pf.gq[j][1] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m + 1];
+      {   // (a pair, 16-byte aligned: 2m is even and rows are 16 doubles apart)
+        const double2 g2 =
+            *reinterpret_cast<const double2 *>(a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m);
+        pf.gq[j][0] = g2.x;
+        pf.gq[j][1] = g2.y;
+      }
     }
   }
   const int cl = lane >> 2, comp = lane & 3;
@@ -648,8 +652,10 @@ __device__ __forceinline__ void end_loads(const StepArgs &a, const TileDev &t, c
 #pragma unroll
   for (int j = 0; j < kGPre; ++j) {
     const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
-    el.pq[j][0] = psi_prev[(size_t)(t.c0 + cl) * K + 2 * pm.m];
-    el.pq[j][1] = psi_prev[(size_t)(t.c0 + cl) * K + 2 * pm.m + 1];
+    const double2 p2 =
+        *reinterpret_cast<const double2 *>(psi_prev + (size_t)(t.c0 + cl) * K + 2 * pm.m);
+    el.pq[j][0] = p2.x;
+    el.pq[j][1] = p2.y;
   }
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
   issue_copy(el.cr, blk, 1, K);
@@ -1012,8 +1018,12 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
-      gq[j][0] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m];
-      gq[j][1] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m + 1];
+      {   // (a pair, 16-byte aligned: 2m is even and rows are 16 doubles apart)
+        const double2 g2 =
+            *reinterpret_cast<const double2 *>(a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m);
+        gq[j][0] = g2.x;
+        gq[j][1] = g2.y;
+      }
     }
   }
   double hv, po;
@@ -1178,8 +1188,12 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
-      gq[j][0] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m];
-      gq[j][1] = a.gh[(size_t)(t.c0 + cl) * ghp + 2 * pm.m + 1];
+      {   // (a pair, 16-byte aligned: 2m is even and rows are 16 doubles apart)
+        const double2 g2 =
+            *reinterpret_cast<const double2 *>(a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m);
+        gq[j][0] = g2.x;
+        gq[j][1] = g2.y;
+      }
     }
   }
   double hv, po;
