@@ -45,8 +45,8 @@ struct StepArgs {
   const RegionDev *regions; // [R] cell width and cross sections (end of step)
   const double *mu;        // [N]
   const double *ainv;      // [R][N][16] A_m^{-1} per region and angle
-  const double *coef;      // [R][kCoef][N] outgoing-pair and step-constant coefficients
-                           //   (coefficient-major: value i of angle m at (r*kCoef+i)*N+m)
+  const double *coef;      // [R][kCoef/2][N][2] outgoing-pair and step-constant coefficients
+                           //   (pairs of coefficients, pair-major: see k_out_coef)
   const double *phig;      // [R][4][2N] scalar-flux rows of G (incident columns), plain
   const int *cell_region;  // [J] (halo cells of the two-iterate kernel)
   double at;               // 1/(v dt), 0 for v = inf

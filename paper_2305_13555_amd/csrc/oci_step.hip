@@ -314,9 +314,23 @@ struct PairMap {
   }
 };
 
-// Coefficient i of (region r, angle m) (coefficient-major table).
-__device__ __forceinline__ double coef_at(const StepArgs &a, int N, int r, int m, int i) {
-  return a.coef[((size_t)r * kCoef + i) * N + m];
+// Coefficients 2 i2 and 2 i2 + 1 of (region r, angle m): the table holds
+// pairs of coefficients, pair-major ([R][kCoef/2][N] double2), so a thread
+// loads two per instruction and consecutive angles are consecutive.
+__device__ __forceinline__ double2 coef_pair(const StepArgs &a, int N, int r, int m, int i2) {
+  return reinterpret_cast<const double2 *>(a.coef)[((size_t)r * (kCoef / 2) + i2) * N + m];
+}
+
+// n consecutive coefficients (n even, i0 even) of (region r, angle m).
+template <int n>
+__device__ __forceinline__ void coef_load(const StepArgs &a, int N, int r, int m, int i0,
+                                          double (&c)[n]) {
+#pragma unroll
+  for (int i = 0; i < n; i += 2) {
+    const double2 v = coef_pair(a, N, r, m, (i0 + i) / 2);
+    c[i] = v.x;
+    c[i + 1] = v.y;
+  }
 }
 
 // The scalar-flux rows 2N .. 2N+3 of G and P: their row tile and the first of
@@ -375,9 +389,9 @@ __device__ __forceinline__ void gh_compute(const StepArgs &a, const TileDev &t, 
   }
   const PairMap pm(N);
   if (pm.active) {
-    const double c0 = coef_at(a, N, t.region, pm.m, 12), c1 = coef_at(a, N, t.region, pm.m, 13),
-                 c2 = coef_at(a, N, t.region, pm.m, 14), c3 = coef_at(a, N, t.region, pm.m, 15),
-                 c4 = coef_at(a, N, t.region, pm.m, 16), c5 = coef_at(a, N, t.region, pm.m, 17);
+    double cg[6];
+    coef_load<6>(a, N, t.region, pm.m, 12, cg);
+    const double c0 = cg[0], c1 = cg[1], c2 = cg[2], c3 = cg[3], c4 = cg[4], c5 = cg[5];
     int j = 0;
     for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
       const double pl = rows[cl * P + 2 * pm.m], pr = rows[cl * P + 2 * pm.m + 1];
@@ -481,8 +495,7 @@ __device__ __forceinline__ void iterate_prefetch(IterPrefetch<CH> &pf, const Ste
   phi_ksplit(KS, W, wave, &kb, &ke);
   load_frags<kPhiPre>(pf.fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
   const PairMap pm(N);
-#pragma unroll
-  for (int i = 0; i < 12; ++i) pf.cf[i] = coef_at(a, N, t.region, pm.m, i);
+  coef_load<12>(a, N, t.region, pm.m, 0, pf.cf);
   if (have_go) {
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
@@ -677,8 +690,7 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
   const int m = pm.m;
   const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
   double e[18];   // this thread's angle's coefficients of psi_{k+1/2} at L and R
-#pragma unroll
-  for (int i = 0; i < 18; ++i) e[i] = coef_at(a, N, t.region, m, 18 + i);
+  coef_load<18>(a, N, t.region, m, 18, e);
   if (!loaded) end_loads<NF>(a, t, src, psi_prev, phi_acc, lds, el);
   const int pi = threadIdx.x;
   const double pv = el.pv;
@@ -843,8 +855,7 @@ __device__ inline void halo_iterate(const StepArgs &a, int hc, const double *lef
   for (int j = lane; j < N / 2; j += 64) {
     const int m = pos ? N / 2 + j : j;
     double cf[12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) cf[i] = coef_at(a, N, r, m, i);
+    coef_load<12>(a, N, r, m, 0, cf);
     const double *in = (pos ? left : right) + 2 * m;   // the halo cell's entering flux
     const double i0 = in[0], i1 = in[1];
     orow[2 * m] = gh[2 * m] + cf[0] * ph[0] + cf[1] * ph[1] + cf[2] * ph[2] + cf[3] * ph[3] +
@@ -1013,8 +1024,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   }
   const PairMap pm(N);
   {
-#pragma unroll
-    for (int i = 0; i < 12; ++i) cf[i] = coef_at(a, N, t.region, pm.m, i);
+    coef_load<12>(a, N, t.region, pm.m, 0, cf);
 #pragma unroll
     for (int j = 0; j < kGPre; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
@@ -1245,7 +1255,8 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   __syncthreads();
   if (stalled) return;
 #pragma unroll
-  for (int i = 0; i < 12; ++i) cf[i] = HC[(12 + i) * N + pm.m];   // region slot 1: the tile's
+  for (int i = 0; i < 12; ++i)   // region slot 1: the tile's
+    cf[i] = HC[12 * N + ((i >> 1) * N + pm.m) * 2 + (i & 1)];
   const bool gl = cbase <= -1, gr = t.c0 + t.nc + KI - 1 >= a.J;   // ghost rows in the block
   if (gl && a.bcl == kBcReflect) mirror_row(row(X, -1), row(X, 0), N, true);
   if (gr && a.bcr == kBcReflect) mirror_row(row(X, a.J), row(X, a.J - 1), N, false);
@@ -1284,9 +1295,9 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
       const int c = left ? lo + h : t.c0 + t.nc + (h - nl);
       const int sl = left ? t.c0 - 1 - c : KI - 1 + c - (t.c0 + t.nc);
       double cc[12];
-      const double *hc = HC + hsel[sl] * 12 * N + m;
+      const double *hc = HC + hsel[sl] * 12 * N;   // pairs of coefficients, pair-major
 #pragma unroll
-      for (int i = 0; i < 12; ++i) cc[i] = hc[i * N];
+      for (int i = 0; i < 12; ++i) cc[i] = hc[((i >> 1) * N + m) * 2 + (i & 1)];
       const double *in2 = (2 * m >= N ? row(in, c - 1) : row(in, c + 1)) + 2 * m;
       const double i0 = in2[0], i1 = in2[1];
       const double *ph = hph[h];

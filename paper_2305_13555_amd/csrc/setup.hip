@@ -212,8 +212,9 @@ __global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0
 // scattering source s phi (s = dx Sigma_s / 4), the entering fluxes |mu| inc
 // (entering-corner columns in_t), and give the step constant from the source
 // (dx Q / 4 in every row) and the time edge (dx / (2 v dt) psi_{k-1/2} in the
-// two level-k rows).  Layout: coefficient-major, value i of (region r,
-// angle m) at coef[(r * kCoef + i) * N + m], so that the threads of a
+// two level-k rows).  Layout: pairs of coefficients, pair-major: values 2p
+// and 2p+1 of (region r, angle m) at coef[((r * kCoef/2 + p) * N + m) * 2 + 0/1],
+// so that a thread loads two with one instruction and the threads of a
 // work-group (consecutive angles) read consecutive addresses.  Use:
 // oci_step.hip, "The structured apply".
 __global__ void k_out_coef(const RegionDev *regions, const double *mu, const double *ainv, int N,
@@ -248,7 +249,7 @@ __global__ void k_out_coef(const RegionDev *regions, const double *mu, const dou
     cf[25 + 9 * u] = amu * row[in1];
     cf[26 + 9 * u] = qq * (row[0] + row[1] + row[2] + row[3]);
   }
-  for (int k = 0; k < kCoef; ++k) coef[((size_t)r * kCoef + k) * N + m] = cf[k];
+  for (int k = 0; k < kCoef; ++k) coef[(((size_t)r * (kCoef / 2) + k / 2) * N + m) * 2 + (k & 1)] = cf[k];
 }
 
 // Clear z.count ranges of doubles (one launch instead of one fill per range).
