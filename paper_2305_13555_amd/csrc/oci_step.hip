@@ -1255,8 +1255,11 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   __syncthreads();
   if (stalled) return;
 #pragma unroll
-  for (int i = 0; i < 12; ++i)   // region slot 1: the tile's
-    cf[i] = HC[12 * N + ((i >> 1) * N + pm.m) * 2 + (i & 1)];
+  for (int i = 0; i < 6; ++i) {   // region slot 1: the tile's
+    const double2 v = reinterpret_cast<const double2 *>(HC + 12 * N)[i * N + pm.m];
+    cf[2 * i] = v.x;
+    cf[2 * i + 1] = v.y;
+  }
   const bool gl = cbase <= -1, gr = t.c0 + t.nc + KI - 1 >= a.J;   // ghost rows in the block
   if (gl && a.bcl == kBcReflect) mirror_row(row(X, -1), row(X, 0), N, true);
   if (gr && a.bcr == kBcReflect) mirror_row(row(X, a.J), row(X, a.J - 1), N, false);
@@ -1294,10 +1297,14 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
       const bool left = h < nl;
       const int c = left ? lo + h : t.c0 + t.nc + (h - nl);
       const int sl = left ? t.c0 - 1 - c : KI - 1 + c - (t.c0 + t.nc);
-      double cc[12];
-      const double *hc = HC + hsel[sl] * 12 * N;   // pairs of coefficients, pair-major
+      double cc[12];   // pairs of coefficients, pair-major
+      const double2 *hc = reinterpret_cast<const double2 *>(HC + hsel[sl] * 12 * N);
 #pragma unroll
-      for (int i = 0; i < 12; ++i) cc[i] = hc[((i >> 1) * N + m) * 2 + (i & 1)];
+      for (int i = 0; i < 6; ++i) {
+        const double2 v = hc[i * N + m];
+        cc[2 * i] = v.x;
+        cc[2 * i + 1] = v.y;
+      }
       const double *in2 = (2 * m >= N ? row(in, c - 1) : row(in, c + 1)) + 2 * m;
       const double i0 = in2[0], i1 = in2[1];
       const double *ph = hph[h];
