@@ -351,3 +351,32 @@ def test_queued_solve_matches_step_by_step(lib, which):
         assert infos[k]["iterations"] == a[k]["iterations"]
         assert np.array_equal(got[k], a[k]["phi"])
     assert np.array_equal(psi, a[-1]["psi_edge"])
+
+
+@pytest.mark.parametrize("cap", ["2", "3"])
+def test_launch_shape_cap_agrees(lib, monkeypatch, cap):
+    """Iterates per launch (up to four: halo cells recomputed level by level)
+    change only the rounding order at tile edges: capping the launch shape
+    with OCI_ITERATES_PER_LAUNCH gives the same steps to rounding."""
+    import torch
+    p = W.config2(n_steps=6, n_cells=700, n_regions=5, n_angles=32)
+    steps = 6
+
+    def run():
+        with lib.OciContext(p) as ctx:
+            out = torch.zeros((steps, ctx.n_cells, 4), dtype=torch.float64, device="cuda")
+            rc, infos = ctx.solve(steps, out)
+            assert rc == lib.OCI_OK
+            return ctx.iterates_per_launch, out.cpu().numpy(), infos
+
+    k0, phi0, inf0 = run()
+    assert k0 == 4
+    monkeypatch.setenv("OCI_ITERATES_PER_LAUNCH", cap)
+    k1, phi1, inf1 = run()
+    assert k1 == int(cap)
+    for k in range(steps):
+        assert abs(inf1[k]["iterations"] - inf0[k]["iterations"]) <= 1
+        assert rel(phi1[k], phi0[k]) < 1e-11
+    ref = ooci.run_oci(p, cell_data(p), steps, tol=p.tol, max_iters=p.max_iters)
+    for k in range(steps):
+        assert rel(phi1[k], ref[k]["phi"]) < 1e-9
