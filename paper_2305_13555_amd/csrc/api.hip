@@ -632,13 +632,12 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
 #undef OCI_KERNEL
 #undef OCI_PICK
   c->fn_inner = s.tiles_in_args ? (void *)k_oci_inner<true> : (void *)k_oci_inner<false>;
-  // three and four iterates per launch: built for N = 8, 16, 32, 64, 128
+  // three and four iterates per launch: built for N = 8, 16, 32 (from N = 64
+  // on, the two LDS blocks and the staged halo data need more than 64 KiB)
 #define OCI_KERNELK(ARGT, KI)                                                   \
   (N == 8     ? (void *)k_oci_iterateK<4, ARGT, true, 8, KI>                    \
    : N == 16  ? (void *)k_oci_iterateK<8, ARGT, true, 16, KI>                   \
    : N == 32  ? (void *)k_oci_iterateK<16, ARGT, true, 32, KI>                  \
-   : N == 64  ? (void *)k_oci_iterateK<16, ARGT, true, 64, KI>                  \
-   : N == 128 ? (void *)k_oci_iterateK<16, ARGT, true, 128, KI>                 \
               : nullptr)
   // (the halo cells of a tile in its own region or the next one on their
   // side: no region narrower than ki-1 cells)

@@ -1697,23 +1697,15 @@ template __global__ void k_oci_iterate2<16, true, true, 256>(StepArgs, int, int,
 template __global__ void k_oci_iterateK<4, true, true, 8, 3>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<8, true, true, 16, 3>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<16, true, true, 32, 3>(StepArgs, int, int, int, int);
-template __global__ void k_oci_iterateK<16, true, true, 64, 3>(StepArgs, int, int, int, int);
-template __global__ void k_oci_iterateK<16, true, true, 128, 3>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<4, false, true, 8, 3>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<8, false, true, 16, 3>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<16, false, true, 32, 3>(StepArgs, int, int, int, int);
-template __global__ void k_oci_iterateK<16, false, true, 64, 3>(StepArgs, int, int, int, int);
-template __global__ void k_oci_iterateK<16, false, true, 128, 3>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<4, true, true, 8, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<8, true, true, 16, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<16, true, true, 32, 4>(StepArgs, int, int, int, int);
-template __global__ void k_oci_iterateK<16, true, true, 64, 4>(StepArgs, int, int, int, int);
-template __global__ void k_oci_iterateK<16, true, true, 128, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<4, false, true, 8, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<8, false, true, 16, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<16, false, true, 32, 4>(StepArgs, int, int, int, int);
-template __global__ void k_oci_iterateK<16, false, true, 64, 4>(StepArgs, int, int, int, int);
-template __global__ void k_oci_iterateK<16, false, true, 128, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_inner<true>(StepArgs, int, int, int);
 template __global__ void k_oci_inner<false>(StepArgs, int, int, int);
 
