@@ -98,6 +98,11 @@ CASES = [(s, None) for s in range(8)] + [
     (105, dict(n_angles=64, n_cells=20, n_regions=2, bc=(W.VACUUM, W.REFLECT))),
     (106, dict(n_angles=128, n_cells=9, n_regions=1, bc=(W.REFLECT, W.VACUUM))),
     (107, dict(n_angles=256, n_cells=5, n_regions=1, bc=(W.INCIDENT, W.REFLECT))),
+    # several tiles per region at the angle counts of the multi-iterate
+    # launches, with incident and vacuum edges (halo cells at fixed ghosts)
+    (108, dict(n_angles=16, n_cells=70, n_regions=3, bc=(W.INCIDENT, W.INCIDENT))),
+    (109, dict(n_angles=32, n_cells=53, n_regions=2, bc=(W.VACUUM, W.INCIDENT))),
+    (110, dict(n_angles=8, n_cells=45, n_regions=4, bc=(W.INCIDENT, W.VACUUM))),
 ]
 
 
