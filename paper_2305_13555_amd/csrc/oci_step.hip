@@ -1185,14 +1185,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   const int cbase = t.c0 - KI;   // cell of LDS row 0
   auto row = [&](double *blk, int c) { return blk + (c - cbase) * P; };
   const int ghp = sh.Mt * 16;
-  double fp[kPhiPre], cf[12], gq[kGPre][2];
-  {
-    int prt, poff, kb, ke;
-    phi_tile(N, &prt, &poff);
-    phi_ksplit(KS, W, wave, &kb, &ke);
-    const double *F = a.frag_it + (size_t)t.region * a.frag_it_stride + lane;
-    load_frags<kPhiPre>(fp, F + ((size_t)prt * KS + kb) * 64, 0, ke - kb);
-  }
+  double fp[kPhiPre], cf[12], gq[kGPre][2];   // (fp and cf: from the staged data, below)
   const PairMap pm(N);
   {   // (cf: from the staged coefficients of the tile's region, below)
 #pragma unroll
@@ -1259,6 +1252,17 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
     const double2 v = reinterpret_cast<const double2 *>(HC + 12 * N)[i * N + pm.m];
     cf[2 * i] = v.x;
     cf[2 * i + 1] = v.y;
+  }
+  {   // this wave's MFMA fragments of the scalar-flux rows of G (the k-major
+      // packing of its row tile: lane 16 kq + r holds row r, k = kq KS + ks;
+      // rows past the four scalar-flux rows are zero), from the staged rows
+    int prt, poff, kb, ke;
+    phi_tile(N, &prt, &poff);
+    phi_ksplit(KS, W, wave, &kb, &ke);
+    const int r = (lane & 15) - poff, kq = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < kPhiPre; ++q)
+      fp[q] = (r >= 0 && r < 4) ? HF[(4 + r) * K + kq * KS + min(kb + q, KS - 1)] : 0.0;
   }
   const bool gl = cbase <= -1, gr = t.c0 + t.nc + KI - 1 >= a.J;   // ghost rows in the block
   if (gl && a.bcl == kBcReflect) mirror_row(row(X, -1), row(X, 0), N, true);
