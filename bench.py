@@ -1,7 +1,7 @@
 """Benchmark: plain FP64 one-cell inversion on one MI355X.
 
 One bench step = one full solve of the workload from its initial condition:
-rebuild and LU-factor every region's operator (oci_refactor), reset the state,
+rebuild every region's cell operator (oci_refactor), reset the state,
 then 100 MB time steps of OCI iterations to tolerance (oci_solve).  The metric
 is OCI cell-angle updates per second: sum over iterations of J*N, divided by
 wall time.  Source iteration on the same problem and the time to a 1e-6
@@ -368,7 +368,7 @@ def main():
                         "[0.01, 10] with dx = 1, c ~ U[0.5, 0.99], Q ~ U[0, 1], dt = 0.05, "
                         "v = 1, tol 1e-10 (seeded)" % prob.name,
             "cells": J, "angles": N, "regions": prob.n_regions, "time_steps": T,
-            "tol": prob.tol, "step": "operator rebuild + LU + %d MB time steps" % T,
+            "tol": prob.tol, "step": "operator rebuild + %d MB time steps" % T,
             "driver": "queued solve (one batch of iteration launches per step)",
         },
         "roofline": {

@@ -129,10 +129,11 @@ typedef struct {
 } oci_step_info;
 
 /* Build a context: validates *p, computes the quadrature, uploads the region
- * table, builds and LU-factors every region's cell matrix A - S on the GPU
- * (Sec. "PERFORMANCE ANALYSIS": dense solves by LU with partial pivoting;
- * one factorisation per region because all cells of a region share it), and
- * forms the operators applied each iteration.  hip_stream is a hipStream_t
+ * table, solves every region's cell system (A - S) Y = [B | T | q] on the
+ * GPU (one solve per region because all cells of a region share A - S;
+ * Sec. "PERFORMANCE ANALYSIS" does it by dense LU, here it goes through the
+ * rank-4 scattering coupling: the same solution up to rounding), and forms
+ * the operators applied each iteration.  hip_stream is a hipStream_t
  * (NULL = the null stream).  On success *out owns all device memory.
  * With precision OCI_PREC_FP32 a step is solved by defect correction: each
  * FP64 iterate x' = T(y) (one OCI iteration of the current point y) gives the

@@ -284,27 +284,32 @@ static int build_si_graph(oci_ctx *c, int count) {
 // Build and pack every region's operator (region table, mu, w and a already
 // on the device / in the context).
 static int build_operators(oci_ctx *c) {
-  const int N = c->N, K = 2 * N, R = c->R;
+  const int N = c->N, R = c->R;
   int *d_bad = c->d_bad;
   OCI_CK(c, hipMemsetAsync(d_bad, 0, sizeof(int), c->stream));
-  // A_m^{-1} per (region, angle), then the cell operator from the block
-  // structure of A - S
-  hipLaunchKernelGGL(k_si_invert, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
-                     c->d_regions, c->d_mu, N, R, c->a, c->d_ainv);
-  hipLaunchKernelGGL(k_cell_operator, dim3(R), dim3(256), (size_t)(32 * N + 4) * sizeof(double),
-                     c->stream, c->d_regions, c->d_mu, c->d_w, c->d_ainv, N, c->a, c->d_op,
-                     c->d_phig, d_bad);
-  // iteration operator G: rows [0, 2N+4), columns [0, 2N) (incident), k-major
-  hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, 0, K,
-                     c->Mt, c->d_fi, c->fi_stride, (double *)nullptr, (size_t)0, 1);
-  // per-step operator P: rows [0, 2N+4), columns [2N, 4N) (psi_{k-1/2}); source column
-  hipLaunchKernelGGL(k_pack, dim3(R), dim3(256), 0, c->stream, N, c->d_op, 0, 2 * N + 4, K, K,
-                     c->Mt, c->d_fp, c->fp_stride, c->d_cp, c->cp_stride, 1);
-  if (c->mixed)   // G for the FP32 inner iterations, same packing
-    hipLaunchKernelGGL(k_to_f32, dim3(256), dim3(256), 0, c->stream, (const double *)c->d_fi,
-                       c->d_fi32, (size_t)R * c->fi_stride);
-  hipLaunchKernelGGL(k_out_coef, dim3((R * N + 255) / 256), dim3(256), 0, c->stream,
-                     c->d_regions, c->d_mu, c->d_ainv, N, R, c->a, c->d_coef);
+  // every per-region table (A_m^{-1}, the cell operator and its packed
+  // forms) in one launch; a region's work spread over nb work-groups
+  SetupArgs q;
+  q.regions = c->d_regions;
+  q.mu = c->d_mu;
+  q.w = c->d_w;
+  q.N = N;
+  q.Mt = c->Mt;
+  q.a = c->a;
+  q.ainv = c->d_ainv;
+  q.coef = c->d_coef;
+  q.phig = c->d_phig;
+  q.op = c->d_op;
+  q.frag_it = c->d_fi;
+  q.frag_pv = c->d_fp;
+  q.frag_it32 = c->mixed ? c->d_fi32 : nullptr;
+  q.frag_stride = c->fi_stride;
+  q.c_pv = c->d_cp;
+  q.cvec_stride = c->cp_stride;
+  q.bad = d_bad;
+  const int nb = std::max(1, std::min(16, (256 + R - 1) / R));
+  hipLaunchKernelGGL(k_region_setup, dim3(R, nb), dim3(256), (size_t)(32 * N + 4) * sizeof(double),
+                     c->stream, q);
   OCI_CK(c, hipGetLastError());
   int bad = 0;
   OCI_CK(c, hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -500,7 +505,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(up(c->d_tiles, tiles.data(), tiles.size() * sizeof(TileDev)));
   OCI_TRY(up(c->d_cell_region, cell_region.data(), (size_t)J * sizeof(int)));
 
-  OCI_CK(c, hipFuncSetAttribute((const void *)k_cell_operator,
+  OCI_CK(c, hipFuncSetAttribute((const void *)k_region_setup,
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)((32 * N + 4) * sizeof(double))));
   OCI_TRY(dalloc(c, &c->d_bad, 1));

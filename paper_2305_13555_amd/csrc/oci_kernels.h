@@ -46,7 +46,7 @@ struct StepArgs {
   const double *mu;        // [N]
   const double *ainv;      // [R][N][16] A_m^{-1} per region and angle
   const double *coef;      // [R][kCoef/2][N][2] outgoing-pair and step-constant coefficients
-                           //   (pairs of coefficients, pair-major: see k_out_coef)
+                           //   (pairs of coefficients, pair-major: see write_out_coef)
   const double *phig;      // [R][4][2N] scalar-flux rows of G (incident columns), plain
   const int *cell_region;  // [J] (halo cells of the two-iterate kernel)
   double at;               // 1/(v dt), 0 for v = inf
@@ -107,16 +107,27 @@ struct ZeroRanges {
   int count;
 };
 
+// Operator tables of a solve (k_region_setup).
+struct SetupArgs {
+  const RegionDev *regions;  // [R]
+  const double *mu, *w;      // [N]
+  int N, Mt;
+  double a;                  // 1/(v dt), 0 for v = inf
+  double *ainv;              // [R][N][16] A_m^{-1}
+  double *coef;              // [R][kCoef/2][N][2]
+  double *phig;              // [R][4][2N]
+  double *op;                // [R][4N+4][4N+1] operator rows
+  double *frag_it, *frag_pv; // G and P in fragment order, per region stride frag_stride
+  float *frag_it32;          // G in FP32 (mixed precision), or null
+  size_t frag_stride;
+  double *c_pv;              // p, per region stride cvec_stride
+  size_t cvec_stride;
+  int *bad;                  // set to 1 when a region's 4x4 system is singular
+};
+
 // setup.hip
 __global__ void k_zero(ZeroRanges z);
-__global__ void k_cell_operator(const RegionDev *regions, const double *mu, const double *w,
-                                const double *ainv, int N, double a, double *op_all,
-                                double *phig, int *bad);
-__global__ void k_out_coef(const RegionDev *regions, const double *mu, const double *ainv, int N,
-                           int R, double a, double *coef);
-__global__ void k_pack(int N, const double *op_all, int row0, int rows, int col0, int K,
-                       int Mt, double *frag_all, size_t frag_stride, double *cvec_all,
-                       size_t cvec_stride, int kmajor);
+__global__ void k_region_setup(SetupArgs q);
 // oci_step.hip (CH = operator k-steps fetched per batch: 4, 8 or 16)
 // ARGT: tile descriptors in the kernel arguments; VEC: 16-byte operand
 // reads (N % 8 == 0); NF > 0: built for N = NF angles, 0: any N.
@@ -149,10 +160,7 @@ __global__ void k_reduce_rec(StepArgs a, int l, int n, int half);
 // correction).
 template <bool ARGT>
 __global__ void k_oci_inner(StepArgs a, int i, int ly, int half);
-__global__ void k_to_f32(const double *src, float *dst, size_t n);
 // si.hip
-__global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,
-                            double *ainv);
 __global__ void k_si_maps(SiArgs a, int node, int cb);
 __global__ void k_si_sweep(SiArgs a, int node, int cb);
 __global__ void k_si_reduce(SiArgs a, int node, int cb);

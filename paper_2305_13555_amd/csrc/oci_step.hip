@@ -1668,12 +1668,6 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
   }
 }
 
-__global__ void k_to_f32(const double *src, float *dst, size_t n) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (size_t)gridDim.x * blockDim.x)
-    dst[e] = (float)src[e];
-}
-
 template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterate2<8, false, false, 0>(StepArgs, int, int, int, int);

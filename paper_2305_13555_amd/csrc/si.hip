@@ -6,8 +6,8 @@
 // cells by a two-level scan: with the lagged scalar flux fixed, the map from
 // the flux entering a cell (levels k and k+1/2) to the flux leaving it is
 // affine, x_out = T x_in + t, with T = |mu| (A^{-1})[out rows, in rows] and
-// t = (A^{-1} b)[out rows].  The cells are split into S segments, one
-// work-group per (pair, segment).  A first launch composes every segment's
+// t = (A^{-1} b)[out rows] (the A_m^{-1} of the OCI setup, k_region_setup).
+// The cells are split into S segments, one work-group per (pair, segment).  A first launch composes every segment's
 // map (each thread a chunk of cells, a work-group scan of the chunk maps); a
 // second gives every segment its entering flux from the maps upstream of it,
 // and every thread re-sweeps its chunk from the entering flux the scan gives
@@ -20,59 +20,6 @@
 #include "oci_kernels.h"
 
 namespace ocik {
-
-
-// A^{-1} for every (region, angle): Gauss-Jordan with partial pivoting on the
-// unified 4x4 A_m (diagonal (|mu| + dx Sigma)/2, off-diagonal +-mu/2 signed,
-// time terms dx/(2 v dt), dx/(v dt)).
-__global__ void k_si_invert(const RegionDev *regions, const double *mu, int N, int R, double a,
-                            double *ainv) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= R * N) return;
-  const int r = idx / N, m = idx % N;
-  const RegionDev g = regions[r];
-  const double mm = mu[m];
-  const double d = (fabs(mm) + g.dx * g.sig) / 2.0, h = mm / 2.0, t = g.dx * a;
-  double A[4][8] = {{d, h, t / 2.0, 0.0, 1, 0, 0, 0},
-                    {-h, d, 0.0, t / 2.0, 0, 1, 0, 0},
-                    {-t, 0.0, t + d, h, 0, 0, 1, 0},
-                    {0.0, -t, -h, t + d, 0, 0, 0, 1}};
-  // (every loop unrolled and the row swap done by selects: the matrix stays
-  // in registers instead of scratch memory)
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int p = k;
-    double best = fabs(A[k][k]);
-#pragma unroll
-    for (int i = k + 1; i < 4; ++i)
-      if (fabs(A[i][k]) > best) {
-        best = fabs(A[i][k]);
-        p = i;
-      }
-#pragma unroll
-    for (int i = k + 1; i < 4; ++i)
-      if (i == p)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const double tmp = A[k][j];
-          A[k][j] = A[i][j];
-          A[i][j] = tmp;
-        }
-    const double piv = A[k][k];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) A[k][j] /= piv;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (i == k) continue;
-      const double l = A[i][k];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) A[i][j] -= l * A[k][j];
-    }
-  }
-  double *o = ainv + (size_t)idx * 16;
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) o[i * 4 + j] = A[i][4 + j];
-}
 
 
 // (f o g)(x) = f(g(x))
