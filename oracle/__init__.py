@@ -25,6 +25,9 @@ Layout (every function cites the passage of the paper it follows):
 * ``stopping``    the scalar-flux stopping rule shared by oci and si.
 * ``spectral``    brute-force spectral radii of the two iteration operators
   (Fig. 1 trend).
+* ``corrector``   the learned iterate corrector's network (1-D convolutions,
+  ReLU, mean squared error and its gradient, Adam): textbook definitions; the
+  paper has none.
 
 Parity status: every function here is pinned by tests under ``tests/``
 (closed forms, invariants, the paper's printed matrices, brute force),
