@@ -232,6 +232,53 @@ const char *oci_last_error(const oci_ctx *c);
  * Returns OCI_EINVAL for n < 1 or n > 4096 or NULL outputs. */
 int oci_gauss_legendre(int32_t n, double *mu, double *w);
 
+/* ---- Learned iterate corrector ----
+ * A small network that learns, from OCI iterate histories the solver
+ * generates, the remaining error of an iterate from its latest differences,
+ * to damp OCI's slow convergence in optically thin cells (the weakness the
+ * paper states in its introduction and conclusions; the paper itself has no
+ * corrector).  Network: four 1-D convolutions over cells, kernel width 5
+ * with two cells of zero padding at each mesh end, 32 channels between
+ * layers, no biases, ReLU after the first three (positively homogeneous:
+ * f(a x) = a f(x), a > 0).  Loss: mean squared error over all outputs.
+ * Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8).  FP64.
+ * Layout: inputs x [batch][c_in][cells], outputs [batch][c_out][cells],
+ * cells contiguous; weights of layer l [c_o][c_i][5], the four layers
+ * concatenated (oci_corrector_num_weights() doubles).
+ * Device pointers (x, y, target) must hold the sizes stated and stay valid
+ * until the call returns; every call runs on the stream given at creation
+ * and returns after it completes, except oci_corrector_forward, which only
+ * enqueues.  Errors: OCI_EINVAL (NULL pointer, batch or cells outside
+ * [1, the maximum given at creation], channels not multiples of 4),
+ * OCI_ENOMEM, OCI_EDEVICE; oci_corrector_last_error() gives the message. */
+typedef struct oci_corrector oci_corrector;
+
+/* c_in, c_out: multiples of 4 in [4, 1024]; max_batch * max_cells sizes the
+ * activation buffers.  Weights and Adam moments start at zero. */
+int oci_corrector_create(int32_t c_in, int32_t c_out, int32_t max_batch, int32_t max_cells,
+                         void *hip_stream, oci_corrector **out);
+/* Number of weights (>= 0), or OCI_EINVAL for NULL. */
+int64_t oci_corrector_num_weights(const oci_corrector *k);
+/* Copy all weights from / to host memory; setting them also clears Adam's
+ * moments and step count. */
+int oci_corrector_set_weights(oci_corrector *k, const double *w);
+int oci_corrector_get_weights(oci_corrector *k, double *w);
+/* y = f(x) (device pointers; enqueued on the stream, not waited for). */
+int oci_corrector_forward(oci_corrector *k, const double *x, int32_t batch, int32_t cells,
+                          double *y);
+/* Mean squared error of f(x) against target (device pointers) and its
+ * gradient wrt every weight: *loss and grad[num_weights] are host memory,
+ * either may be NULL. */
+int oci_corrector_grad(oci_corrector *k, const double *x, const double *target, int32_t batch,
+                       int32_t cells, double *loss, double *grad);
+/* The gradient, then one Adam step of learning rate lr > 0; *loss (host, may
+ * be NULL) is the loss before the step. */
+int oci_corrector_train_step(oci_corrector *k, const double *x, const double *target,
+                             int32_t batch, int32_t cells, double lr, double *loss);
+const char *oci_corrector_last_error(const oci_corrector *k);
+/* Release the corrector (waits for its stream).  NULL is a no-op. */
+void oci_corrector_destroy(oci_corrector *k);
+
 #ifdef __cplusplus
 }
 #endif

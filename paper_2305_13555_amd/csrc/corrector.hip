@@ -1,0 +1,386 @@
+// Learned iterate corrector: a small 1-D convolutional network over cells,
+// trained on OCI iterate histories that the solver generates, to damp the
+// slow convergence of OCI in optically thin cells (the weakness the paper
+// states in its introduction and conclusions; the paper has no corrector).
+//
+// Network: four convolutions over cells (kernel width 5, two cells of zero
+// padding at each mesh end), 32 channels between layers, no biases, ReLU
+// after the first three.  Without biases the network is positively
+// homogeneous, f(a x) = a f(x) for a > 0, so a predicted correction scales
+// with the iterate differences it is fed.  Training: mean squared error,
+// Adam (Kingma and Ba, 2015).  FP64 throughout.
+//
+// Layout: activations [B][C][J] (cells contiguous: a work-group's threads
+// read consecutive cells); weights of layer l [C_o][C_i][5], layers
+// concatenated.  The work is small next to an OCI iterate of the same mesh
+// and bound by latency; the kernels are plain and coalesced.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "oci.h"
+
+namespace occ {
+
+constexpr int KW = 5, HID = 32, NL = 4, COT = 4;
+
+// y[b][o][j] = sum_i sum_t W[o][i][t] x[b][i][j + t - 2] (zero outside the
+// mesh), ReLU if relu.  Grid (ceil(J/256), Co/COT, B); COT outputs per thread.
+__global__ __launch_bounds__(256) void k_conv_fwd(const double *__restrict__ x, int Ci, int J,
+                                                  const double *__restrict__ W, int Co,
+                                                  double *__restrict__ y, int relu) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int o0 = blockIdx.y * COT, b = blockIdx.z;
+  if (j >= J) return;
+  double acc[COT];
+#pragma unroll
+  for (int o = 0; o < COT; ++o) acc[o] = 0.0;
+  const double *xb = x + (size_t)b * Ci * J;
+  for (int i = 0; i < Ci; ++i) {
+    double xv[KW];
+#pragma unroll
+    for (int t = 0; t < KW; ++t) {
+      const int k = j + t - 2;
+      xv[t] = (k >= 0 && k < J) ? xb[(size_t)i * J + k] : 0.0;
+    }
+#pragma unroll
+    for (int o = 0; o < COT; ++o)
+#pragma unroll
+      for (int t = 0; t < KW; ++t) acc[o] += W[((size_t)(o0 + o) * Ci + i) * KW + t] * xv[t];
+  }
+#pragma unroll
+  for (int o = 0; o < COT; ++o)
+    y[((size_t)b * Co + o0 + o) * J + j] = relu ? fmax(acc[o], 0.0) : acc[o];
+}
+
+// Gradient wrt a layer's input: gx[b][i][k] = sum_o sum_t W[o][i][t]
+// g[b][o][k - t + 2], times the ReLU mask of that input (act > 0) when act is
+// given (the input is the previous layer's ReLU output).  Grid (ceil(J/256),
+// Ci/COT, B).
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const double *__restrict__ g, int Co, int J,
+                                                       const double *__restrict__ W, int Ci,
+                                                       const double *__restrict__ act,
+                                                       double *__restrict__ gx) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i0 = blockIdx.y * COT, b = blockIdx.z;
+  if (k >= J) return;
+  double acc[COT];
+#pragma unroll
+  for (int i = 0; i < COT; ++i) acc[i] = 0.0;
+  const double *gb = g + (size_t)b * Co * J;
+  for (int o = 0; o < Co; ++o) {
+    double gv[KW];
+#pragma unroll
+    for (int t = 0; t < KW; ++t) {
+      const int j = k - t + 2;
+      gv[t] = (j >= 0 && j < J) ? gb[(size_t)o * J + j] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < COT; ++i)
+#pragma unroll
+      for (int t = 0; t < KW; ++t) acc[i] += W[((size_t)o * Ci + i0 + i) * KW + t] * gv[t];
+  }
+#pragma unroll
+  for (int i = 0; i < COT; ++i) {
+    const size_t e = ((size_t)b * Ci + i0 + i) * J + k;
+    gx[e] = (act && !(act[e] > 0.0)) ? 0.0 : acc[i];
+  }
+}
+
+// Block sum of 256 threads' values (deterministic order).
+__device__ inline double block_sum(double v, double *sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Weight gradient: dW[o][i][t] = sum_b sum_j g[b][o][j] x[b][i][j + t - 2].
+// One work-group of 256 per (o, i) (grid Co x Ci): the threads stride over
+// (b, j), then the work-group sums each tap.
+__global__ __launch_bounds__(256) void k_conv_bwd_weight(const double *__restrict__ g, int Co,
+                                                         const double *__restrict__ x, int Ci,
+                                                         int J, int B, double *__restrict__ dW) {
+  __shared__ double sh[256];
+  const int o = blockIdx.x, i = blockIdx.y;
+  double acc[KW];
+#pragma unroll
+  for (int t = 0; t < KW; ++t) acc[t] = 0.0;
+  const size_t n = (size_t)B * J;
+  for (size_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int b = (int)(e / J), j = (int)(e - (size_t)b * J);
+    const double gv = g[((size_t)b * Co + o) * J + j];
+    const double *xr = x + ((size_t)b * Ci + i) * J;
+#pragma unroll
+    for (int t = 0; t < KW; ++t) {
+      const int k = j + t - 2;
+      acc[t] += (k >= 0 && k < J) ? gv * xr[k] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < KW; ++t) {
+    const double s = block_sum(acc[t], sh);
+    if (threadIdx.x == 0) dW[((size_t)o * Ci + i) * KW + t] = s;
+  }
+}
+
+// Mean squared error: g = 2 (y - target) / n and per-work-group partial sums
+// of (y - target)^2.
+__global__ __launch_bounds__(256) void k_mse(const double *__restrict__ y,
+                                             const double *__restrict__ target, size_t n,
+                                             double *__restrict__ g, double *__restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double d = y[e] - target[e];
+    g[e] = 2.0 * d / (double)n;
+    acc += d * d;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// loss = sum of the partials / n (one work-group).
+__global__ __launch_bounds__(256) void k_mse_finish(const double *__restrict__ part, int np,
+                                                    size_t n, double *__restrict__ loss) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < np; e += blockDim.x) acc += part[e];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) *loss = s / (double)n;
+}
+
+// One Adam step; bc1 = 1 - beta1^t, bc2 = 1 - beta2^t (formed on the host).
+__global__ __launch_bounds__(256) void k_adam(double *__restrict__ w, const double *__restrict__ g,
+                                              double *__restrict__ m, double *__restrict__ v,
+                                              size_t n, double lr, double b1, double b2,
+                                              double eps, double bc1, double bc2) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const double ge = g[e];
+    const double me = b1 * m[e] + (1.0 - b1) * ge;
+    const double ve = b2 * v[e] + (1.0 - b2) * ge * ge;
+    m[e] = me;
+    v[e] = ve;
+    w[e] = w[e] - lr * (me / bc1) / (sqrt(ve / bc2) + eps);
+  }
+}
+
+}  // namespace occ
+
+using namespace occ;
+
+struct oci_corrector {
+  int c_in = 0, c_out = 0, max_batch = 0, max_cells = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int chans[NL + 1] = {};
+  size_t woff[NL + 1] = {};   // layer l's weights at w + woff[l]
+  double *w = nullptr, *gw = nullptr, *m = nullptr, *v = nullptr;
+  double *act[NL] = {};       // act[1..3]: hidden outputs; act[0] unused (the caller's x)
+  double *y = nullptr;        // network output during training
+  double *g0 = nullptr, *g1 = nullptr;   // gradient ping-pong [B][max(HID, c_out)][J]
+  double *part = nullptr, *loss = nullptr;
+  int64_t adam_t = 0;
+};
+
+namespace {
+
+constexpr int kPartBlocks = 256;
+
+int cfail(oci_corrector *k, int code, const std::string &msg) {
+  if (k) k->err = msg;
+  return code;
+}
+
+#define CK(k, call)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) return cfail(k, OCI_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int check_shape(oci_corrector *k, int32_t batch, int32_t cells) {
+  if (batch < 1 || cells < 1 || batch > k->max_batch || cells > k->max_cells)
+    return cfail(k, OCI_EINVAL, "batch or cell count outside [1, maximum given at creation]");
+  return OCI_OK;
+}
+
+// Forward pass of x [B][c_in][J] into out; hidden activations kept in act[1..3].
+int forward(oci_corrector *k, const double *x, int B, int J, double *out) {
+  const double *in = x;
+  for (int l = 0; l < NL; ++l) {
+    const int Ci = k->chans[l], Co = k->chans[l + 1];
+    double *o = l == NL - 1 ? out : k->act[l + 1];
+    hipLaunchKernelGGL(k_conv_fwd, dim3((J + 255) / 256, Co / COT, B), dim3(256), 0, k->stream, in,
+                       Ci, J, (const double *)(k->w + k->woff[l]), Co, o, l < NL - 1 ? 1 : 0);
+    in = o;
+  }
+  CK(k, hipGetLastError());
+  return OCI_OK;
+}
+
+// Loss (on the device, k->loss) and every weight gradient (k->gw).
+int gradient(oci_corrector *k, const double *x, const double *target, int B, int J) {
+  int rc = forward(k, x, B, J, k->y);
+  if (rc) return rc;
+  const size_t n = (size_t)B * k->c_out * J;
+  hipLaunchKernelGGL(k_mse, dim3(kPartBlocks), dim3(256), 0, k->stream, (const double *)k->y,
+                     target, n, k->g0, k->part);
+  hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(256), 0, k->stream, (const double *)k->part,
+                     kPartBlocks, n, k->loss);
+  double *g = k->g0, *gn = k->g1;
+  for (int l = NL - 1; l >= 0; --l) {
+    const int Ci = k->chans[l], Co = k->chans[l + 1];
+    const double *in = l == 0 ? x : k->act[l];
+    hipLaunchKernelGGL(k_conv_bwd_weight, dim3(Co, Ci), dim3(256), 0, k->stream,
+                       (const double *)g, Co, in, Ci, J, B, k->gw + k->woff[l]);
+    if (l > 0) {
+      hipLaunchKernelGGL(k_conv_bwd_data, dim3((J + 255) / 256, Ci / COT, B), dim3(256), 0,
+                         k->stream, (const double *)g, Co, J, (const double *)(k->w + k->woff[l]),
+                         Ci, (const double *)k->act[l], gn);
+      std::swap(g, gn);
+    }
+  }
+  CK(k, hipGetLastError());
+  return OCI_OK;
+}
+
+}  // namespace
+
+extern "C" int oci_corrector_create(int32_t c_in, int32_t c_out, int32_t max_batch,
+                                    int32_t max_cells, void *hip_stream, oci_corrector **out) {
+  if (!out) return OCI_EINVAL;
+  *out = nullptr;
+  if (c_in < COT || c_out < COT || c_in % COT || c_out % COT || c_in > 1024 || c_out > 1024 ||
+      max_batch < 1 || max_cells < 1 || (int64_t)max_batch * max_cells > ((int64_t)1 << 31))
+    return OCI_EINVAL;
+  oci_corrector *k = new oci_corrector();
+  k->c_in = c_in;
+  k->c_out = c_out;
+  k->max_batch = max_batch;
+  k->max_cells = max_cells;
+  k->stream = (hipStream_t)hip_stream;
+  k->chans[0] = c_in;
+  for (int l = 1; l < NL; ++l) k->chans[l] = HID;
+  k->chans[NL] = c_out;
+  for (int l = 0; l < NL; ++l)
+    k->woff[l + 1] = k->woff[l] + (size_t)k->chans[l + 1] * k->chans[l] * KW;
+  const size_t nw = k->woff[NL];
+  const size_t per = (size_t)max_batch * max_cells;
+  const size_t gmax = per * (size_t)std::max(HID, std::max(c_out, c_in));
+  bool ok = hipMalloc(&k->w, nw * sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->gw, nw * sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->m, nw * sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->v, nw * sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->y, per * c_out * sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->g0, gmax * sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->g1, gmax * sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->part, kPartBlocks * sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->loss, sizeof(double)) == hipSuccess;
+  for (int l = 1; ok && l < NL; ++l)
+    ok = hipMalloc(&k->act[l], per * HID * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    oci_corrector_destroy(k);
+    return OCI_ENOMEM;
+  }
+  // zero weights and moments until set_weights
+  if (hipMemsetAsync(k->w, 0, nw * sizeof(double), k->stream) != hipSuccess ||
+      hipMemsetAsync(k->m, 0, nw * sizeof(double), k->stream) != hipSuccess ||
+      hipMemsetAsync(k->v, 0, nw * sizeof(double), k->stream) != hipSuccess ||
+      hipStreamSynchronize(k->stream) != hipSuccess) {
+    oci_corrector_destroy(k);
+    return OCI_EDEVICE;
+  }
+  *out = k;
+  return OCI_OK;
+}
+
+extern "C" int64_t oci_corrector_num_weights(const oci_corrector *k) {
+  return k ? (int64_t)k->woff[NL] : (int64_t)OCI_EINVAL;
+}
+
+extern "C" int oci_corrector_set_weights(oci_corrector *k, const double *w) {
+  if (!k || !w) return cfail(k, OCI_EINVAL, "NULL argument");
+  const size_t nw = k->woff[NL];
+  CK(k, hipMemcpyAsync(k->w, w, nw * sizeof(double), hipMemcpyHostToDevice, k->stream));
+  CK(k, hipMemsetAsync(k->m, 0, nw * sizeof(double), k->stream));
+  CK(k, hipMemsetAsync(k->v, 0, nw * sizeof(double), k->stream));
+  CK(k, hipStreamSynchronize(k->stream));
+  k->adam_t = 0;
+  return OCI_OK;
+}
+
+extern "C" int oci_corrector_get_weights(oci_corrector *k, double *w) {
+  if (!k || !w) return cfail(k, OCI_EINVAL, "NULL argument");
+  CK(k, hipMemcpyAsync(w, k->w, k->woff[NL] * sizeof(double), hipMemcpyDeviceToHost, k->stream));
+  CK(k, hipStreamSynchronize(k->stream));
+  return OCI_OK;
+}
+
+extern "C" int oci_corrector_forward(oci_corrector *k, const double *x, int32_t batch,
+                                     int32_t cells, double *y) {
+  if (!k || !x || !y) return cfail(k, OCI_EINVAL, "NULL argument");
+  int rc = check_shape(k, batch, cells);
+  if (rc) return rc;
+  return forward(k, x, batch, cells, y);
+}
+
+extern "C" int oci_corrector_grad(oci_corrector *k, const double *x, const double *target,
+                                  int32_t batch, int32_t cells, double *loss, double *grad) {
+  if (!k || !x || !target) return cfail(k, OCI_EINVAL, "NULL argument");
+  int rc = check_shape(k, batch, cells);
+  if (rc) return rc;
+  rc = gradient(k, x, target, batch, cells);
+  if (rc) return rc;
+  if (loss) CK(k, hipMemcpyAsync(loss, k->loss, sizeof(double), hipMemcpyDeviceToHost, k->stream));
+  if (grad)
+    CK(k, hipMemcpyAsync(grad, k->gw, k->woff[NL] * sizeof(double), hipMemcpyDeviceToHost,
+                         k->stream));
+  CK(k, hipStreamSynchronize(k->stream));
+  return OCI_OK;
+}
+
+extern "C" int oci_corrector_train_step(oci_corrector *k, const double *x, const double *target,
+                                        int32_t batch, int32_t cells, double lr, double *loss) {
+  if (!k || !x || !target) return cfail(k, OCI_EINVAL, "NULL argument");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return cfail(k, OCI_EINVAL, "learning rate must be > 0");
+  int rc = check_shape(k, batch, cells);
+  if (rc) return rc;
+  rc = gradient(k, x, target, batch, cells);
+  if (rc) return rc;
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  k->adam_t += 1;
+  const double bc1 = 1.0 - std::pow(b1, (double)k->adam_t);
+  const double bc2 = 1.0 - std::pow(b2, (double)k->adam_t);
+  hipLaunchKernelGGL(k_adam, dim3(64), dim3(256), 0, k->stream, k->w, (const double *)k->gw, k->m,
+                     k->v, k->woff[NL], lr, b1, b2, eps, bc1, bc2);
+  CK(k, hipGetLastError());
+  if (loss) CK(k, hipMemcpyAsync(loss, k->loss, sizeof(double), hipMemcpyDeviceToHost, k->stream));
+  CK(k, hipStreamSynchronize(k->stream));
+  return OCI_OK;
+}
+
+extern "C" const char *oci_corrector_last_error(const oci_corrector *k) {
+  return k ? k->err.c_str() : "corrector is NULL";
+}
+
+extern "C" void oci_corrector_destroy(oci_corrector *k) {
+  if (!k) return;
+  (void)hipStreamSynchronize(k->stream);
+  double *bufs[] = {k->w, k->gw, k->m, k->v, k->y, k->g0, k->g1, k->part, k->loss,
+                    k->act[1], k->act[2], k->act[3]};
+  for (double *p : bufs)
+    if (p) (void)hipFree(p);
+  delete k;
+}

@@ -96,6 +96,18 @@ def _load():
         "oci_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "oci_last_error": (ctypes.c_char_p, [vp]),
         "oci_gauss_legendre": (ctypes.c_int, [ctypes.c_int32, _dp, _dp]),
+        "oci_corrector_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_int32, vp, ctypes.POINTER(vp)]),
+        "oci_corrector_num_weights": (ctypes.c_int64, [vp]),
+        "oci_corrector_set_weights": (ctypes.c_int, [vp, _dp]),
+        "oci_corrector_get_weights": (ctypes.c_int, [vp, _dp]),
+        "oci_corrector_forward": (ctypes.c_int, [vp, vp, ctypes.c_int32, ctypes.c_int32, vp]),
+        "oci_corrector_grad": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_int32, _dp,
+                                              _dp]),
+        "oci_corrector_train_step": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.c_double, _dp]),
+        "oci_corrector_last_error": (ctypes.c_char_p, [vp]),
+        "oci_corrector_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -361,3 +373,87 @@ class OciContext:
             self.close()
         except Exception:
             pass
+
+
+class Corrector:
+    """The learned iterate corrector (oci_corrector_* in include/oci.h):
+    inputs [batch][c_in][cells], outputs [batch][c_out][cells], FP64 device
+    tensors."""
+
+    def __init__(self, c_in, c_out, max_batch, max_cells, stream=None):
+        h = ctypes.c_void_p()
+        code = _lib.oci_corrector_create(int(c_in), int(c_out), int(max_batch), int(max_cells),
+                                         _stream_handle(stream), ctypes.byref(h))
+        if code < 0:
+            raise OciError(code, "oci_corrector_create")
+        self._h = h
+        self.c_in, self.c_out = int(c_in), int(c_out)
+
+    def _check(self, code):
+        if code < 0:
+            raise OciError(code, (_lib.oci_corrector_last_error(self._h) or b"").decode())
+        return code
+
+    @property
+    def num_weights(self):
+        return int(_lib.oci_corrector_num_weights(self._h))
+
+    def set_weights(self, w):
+        w = _f64(w)
+        if w.size != self.num_weights:
+            raise ValueError("expected %d weights" % self.num_weights)
+        self._check(_lib.oci_corrector_set_weights(self._h, _ptr(w)))
+
+    def weights(self):
+        w = np.zeros(self.num_weights)
+        self._check(_lib.oci_corrector_get_weights(self._h, _ptr(w)))
+        return w
+
+    def _shape(self, x, channels):
+        if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous() or x.dim() != 3 \
+                or x.shape[1] != channels:
+            raise ValueError("expected a contiguous float64 device tensor [batch][%d][cells]"
+                             % channels)
+        return int(x.shape[0]), int(x.shape[2])
+
+    def forward(self, x, out=None):
+        B, J = self._shape(x, self.c_in)
+        if out is None:
+            out = torch.empty((B, self.c_out, J), dtype=torch.float64, device=x.device)
+        self._shape(out, self.c_out)
+        self._check(_lib.oci_corrector_forward(self._h, ctypes.c_void_p(x.data_ptr()), B, J,
+                                               ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def grad(self, x, target):
+        B, J = self._shape(x, self.c_in)
+        self._shape(target, self.c_out)
+        loss = ctypes.c_double()
+        g = np.zeros(self.num_weights)
+        self._check(_lib.oci_corrector_grad(self._h, ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(target.data_ptr()), B, J,
+                                            ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train_step(self, x, target, lr):
+        B, J = self._shape(x, self.c_in)
+        self._shape(target, self.c_out)
+        loss = ctypes.c_double()
+        self._check(_lib.oci_corrector_train_step(self._h, ctypes.c_void_p(x.data_ptr()),
+                                                  ctypes.c_void_p(target.data_ptr()), B, J,
+                                                  float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.oci_corrector_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()

@@ -84,3 +84,13 @@ def test_strerror_covers_codes():
     for code in (0, 1, -1, -2, -3, -4, -5):
         assert oci.oci_strerror(code) != "unknown error code"
     assert oci.oci_strerror(42) == "unknown error code"
+
+
+@pytest.mark.parametrize("args", [(3, 4, 1, 10), (8, 6, 1, 10), (8, 4, 0, 10), (8, 4, 1, 0),
+                                  (2048, 4, 1, 10)])
+def test_corrector_create_rejects_bad_shapes_on_host(args):
+    import ctypes
+    from paper_2305_13555_amd import oci
+    h = ctypes.c_void_p()
+    assert oci._lib.oci_corrector_create(*args, None, ctypes.byref(h)) == oci.OCI_EINVAL
+    assert not h.value
