@@ -5,7 +5,8 @@ rebuild every region's cell operator (oci_refactor), reset the state,
 then 100 MB time steps of OCI iterations to tolerance (oci_solve).  The metric
 is OCI cell-angle updates per second: sum over iterations of J*N, divided by
 wall time.  Source iteration on the same problem and the time to a 1e-6
-tolerance are reported beside it.
+tolerance are reported beside it, and so is the learned corrector (trained
+on iterate histories the library generates, evaluated on a held-out step).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 Prints one JSON line.
@@ -181,6 +182,64 @@ def large_case(oci, torch, stream):
     return out
 
 
+def learned_case(oci, torch):
+    """The learned corrector on the regime it targets: a thin-cell, highly
+    scattering slab (S16, 2000 cells, c = 0.99, sigma dx = 0.05, ~550 OCI
+    iterations per step).  Histories of 5 steps come from the library (the
+    first 16 iterates and the converged flux of each step); the corrector is
+    trained on 4 steps (full-batch Adam, 400 epochs) and evaluated on the
+    held-out fifth: max-norm error of the scalar flux after l plain iterates
+    and after the same iterates plus the predicted correction.  The same
+    evaluation on the bench workload (about 7 iterations to 1e-13) shows
+    where the correction does not pay."""
+    from paper_2305_13555_amd import corrector as C
+    from paper_2305_13555_amd import workloads
+
+    def histories(prob, n_steps, n_iter):
+        out = []
+        with oci.OciContext(prob) as ctx:
+            for _ in range(n_steps):
+                phis, ref, info = C.step_history(ctx, prob, n_iter)
+                out.append((phis, ref, info["iterations"]))
+        return out
+
+    def fit(hist, ls):
+        xs, ts = [], []
+        for phis, ref, _ in hist:
+            x, t, _, _ = C.samples(phis, ref, ls)
+            xs.append(x)
+            ts.append(t)
+        x = torch.from_numpy(np.concatenate(xs)).to("cuda")
+        t = torch.from_numpy(np.concatenate(ts)).to("cuda")
+        k, losses, sec = C.train(torch, x, t, epochs=400, lr=2e-3)
+        return k, losses, sec, int(x.shape[0])
+
+    slab = workloads.homogeneous_slab(16, 2000, 0.99, 0.05, 1.0)
+    t0 = time.perf_counter()
+    hist = histories(slab, 5, 16)
+    hist_s = time.perf_counter() - t0
+    ls = list(range(3, 17))
+    k, losses, sec, nb = fit(hist[:4], ls)
+    rows = C.evaluate(torch, k, hist[4][0], hist[4][1], ls)
+    k.close()
+    c2 = workloads.config2()
+    hist2 = histories(c2, 5, 6)
+    k2, losses2, sec2, nb2 = fit(hist2[:4], [3, 4, 5, 6])
+    rows2 = C.evaluate(torch, k2, hist2[4][0], hist2[4][1], [3, 4, 5, 6])
+    k2.close()
+    pick = lambda r: {"l": r["l"], "plain": r["plain"], "corrected": r["corrected"]}
+    return {
+        "workload": slab.name + ", 5 steps (4 train, 1 held out)",
+        "oci_iterations_per_step": [h[2] for h in hist],
+        "history_s": hist_s, "train_s": sec, "train_samples": nb, "epochs": len(losses),
+        "loss_first_last": [losses[0], losses[-1]],
+        "heldout": [pick(r) for r in rows if r["l"] in (3, 8, 16)],
+        "heldout_error_ratio_mean": float(np.mean([r["corrected"] / r["plain"] for r in rows])),
+        "bench_workload_heldout": [pick(r) for r in rows2],
+        "applied_in_iteration": False,
+    }
+
+
 def ensemble_case(oci, torch, n_problems=32):
     """Batched ensemble: problems 0 .. n_problems-1 of the ensemble generator
     (500 - 100,000 cells log-uniform, S8 - S128, 16 regions, 20 steps, tol
@@ -262,7 +321,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-large", action="store_true",
-                    help="skip the 200,000-cell S_64 comparison and the ensemble")
+                    help="skip the 200,000-cell S_64 comparison, the ensemble and the "
+                         "learned corrector")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the k_oci_iterate roofline batches and a 64 MiB copy "
                          "(for hardware-counter runs)")
@@ -332,6 +392,7 @@ def main():
     mixed = mixed_precision(oci, torch, prob, stream, gpu_phi, wall * 1e3 / (args.steps * T))
     large = None if args.no_large else large_case(oci, torch, stream)
     ensemble = None if args.no_large else ensemble_case(oci, torch)
+    learned = None if args.no_large else learned_case(oci, torch)
     def si_steps(tol):
         with oci.OciContext(prob, stream=stream, tol=tol) as cs:
             ms, its = [], []
@@ -399,6 +460,7 @@ def main():
         "mixed": mixed,
         "large_case": large,
         "ensemble": ensemble,
+        "learned": learned,
     }
     print(json.dumps(line))
     ctx.close()

@@ -107,3 +107,32 @@ def test_rejects_sizes_beyond_creation():
         x = torch.zeros((2, 8, 101), dtype=torch.float64, device="cuda")
         with pytest.raises(oci.OciError):
             k.forward(x)
+
+
+def test_training_on_solver_histories_lowers_heldout_error():
+    """Thin cells, c = 0.99 (hundreds of OCI iterations per step): trained on
+    the library's own iterate histories of four steps, the corrector cuts the
+    scalar-flux error of the fifth (held-out) step's early iterates by more
+    than half (deterministic: seeded weights, fixed reduction order)."""
+    from paper_2305_13555_amd import corrector as C
+    from paper_2305_13555_amd import workloads
+    slab = workloads.homogeneous_slab(16, 2000, 0.99, 0.05, 1.0)
+    hist = []
+    with oci.OciContext(slab) as ctx:
+        for _ in range(5):
+            phis, ref, info = C.step_history(ctx, slab, 16)
+            hist.append((phis, ref))
+            assert info["iterations"] > 100
+            plain = [np.max(np.abs(ref - p)) for p in phis]
+            assert all(b < a for a, b in zip(plain, plain[1:]))
+    ls = list(range(3, 17))
+    xs, ts = zip(*[C.samples(p, r, ls)[:2] for p, r in hist[:4]])
+    x = torch.from_numpy(np.concatenate(xs)).to("cuda")
+    t = torch.from_numpy(np.concatenate(ts)).to("cuda")
+    k, losses, _ = C.train(torch, x, t, epochs=400, lr=2e-3)
+    assert losses[-1] < 0.01 * losses[0]
+    rows = C.evaluate(torch, k, hist[4][0], hist[4][1], ls)
+    k.close()
+    assert [r["l"] for r in rows] == ls
+    for r in rows:
+        assert r["corrected"] < 0.5 * r["plain"], r
