@@ -106,8 +106,10 @@ __device__ inline double block_sum(double v, double *sh) {
 }
 
 // Weight gradient: dW[o][i][t] = sum_b sum_j g[b][o][j] x[b][i][j + t - 2].
-// One work-group of 256 per (o, i) (grid Co x Ci): the threads stride over
-// (b, j), then the work-group sums each tap.
+// Layers wider than kTileCh channels: one work-group of 256 per (o, i) (grid
+// Co x Ci), the threads striding over (b, j), then the work-group sums each
+// tap (every work-group re-reads its two rows; the tiled form below reads
+// each row once per pair group).
 __global__ __launch_bounds__(256) void k_conv_bwd_weight(const double *__restrict__ g, int Co,
                                                          const double *__restrict__ x, int Ci,
                                                          int J, int B, double *__restrict__ dW) {
@@ -132,6 +134,75 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const double *__restric
     const double s = block_sum(acc[t], sh);
     if (threadIdx.x == 0) dW[((size_t)o * Ci + i) * KW + t] = s;
   }
+}
+
+// Weight gradient for layers of at most kTileCh input and output channels,
+// in two passes.  Pass 1, grid (nbx, ceil(Co*Ci / 1024)): work-group (bx, y)
+// takes the chunks of kChunk cells bx, bx + nbx, ... of the batch, stages
+// g[b][:][chunk] and x[b][:][chunk - 2 .. chunk + kChunk + 2) in LDS once,
+// and each thread sums, for its (at most four) (o, i) pairs of pair group y,
+// the five taps over the chunk; part[((o*Ci + i)*KW + t)*nbx + bx] holds the
+// work-group's sums.  Pass 2 adds the nbx partial sums of every weight in
+// order.  Dynamic LDS: (Co*kChunk + Ci*(kChunk+4)) doubles.
+constexpr int kChunk = 32, kTileCh = 64, kPairs = 4;
+__global__ __launch_bounds__(256) void k_conv_bwd_weight_part(const double *__restrict__ g, int Co,
+                                                              const double *__restrict__ x, int Ci,
+                                                              int J, int B,
+                                                              double *__restrict__ part) {
+  extern __shared__ double sh[];
+  double *gs = sh;                   // [Co][kChunk]
+  double *xs = sh + Co * kChunk;     // [Ci][kChunk + 4]
+  const int nbx = gridDim.x, bx = blockIdx.x, tid = threadIdx.x;
+  const int npair = Co * Ci, p0 = blockIdx.y * 256 * kPairs;
+  const int nch = (J + kChunk - 1) / kChunk;
+  double acc[kPairs][KW];
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q)
+#pragma unroll
+    for (int t = 0; t < KW; ++t) acc[q][t] = 0.0;
+  for (int c = bx; c < B * nch; c += nbx) {
+    const int b = c / nch, j0 = (c - b * nch) * kChunk;
+    __syncthreads();   // the previous chunk's reads are done
+    for (int e = tid; e < Co * kChunk; e += blockDim.x) {
+      const int o = e / kChunk, j = j0 + e % kChunk;
+      gs[e] = j < J ? g[((size_t)b * Co + o) * J + j] : 0.0;
+    }
+    for (int e = tid; e < Ci * (kChunk + 4); e += blockDim.x) {
+      const int i = e / (kChunk + 4), k = j0 - 2 + e % (kChunk + 4);
+      xs[e] = (k >= 0 && k < J) ? x[((size_t)b * Ci + i) * J + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPairs; ++q) {
+      const int p = p0 + q * 256 + tid;
+      if (p < npair) {
+        const double *gr = gs + (p / Ci) * kChunk;
+        const double *xr = xs + (p % Ci) * (kChunk + 4);
+        for (int j = 0; j < kChunk; ++j) {
+          const double gv = gr[j];
+#pragma unroll
+          for (int t = 0; t < KW; ++t) acc[q][t] += gv * xr[j + t];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPairs; ++q) {
+    const int p = p0 + q * 256 + tid;
+    if (p < npair)
+#pragma unroll
+      for (int t = 0; t < KW; ++t) part[((size_t)p * KW + t) * nbx + bx] = acc[q][t];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_conv_bwd_weight_sum(const double *__restrict__ part,
+                                                             int n, int nbx,
+                                                             double *__restrict__ dW) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nbx; ++b) s += part[(size_t)e * nbx + b];
+  dW[e] = s;
 }
 
 // Mean squared error: g = 2 (y - target) / n and per-work-group partial sums
@@ -192,12 +263,14 @@ struct oci_corrector {
   double *y = nullptr;        // network output during training
   double *g0 = nullptr, *g1 = nullptr;   // gradient ping-pong [B][max(HID, c_out)][J]
   double *part = nullptr, *loss = nullptr;
+  double *wpart = nullptr;    // weight-gradient partial sums [Co*Ci*KW][kWgtBlocks]
   int64_t adam_t = 0;
 };
 
 namespace {
 
 constexpr int kPartBlocks = 256;
+constexpr int kWgtBlocks = 128;   // work-groups per pair group of the tiled weight gradient
 
 int cfail(oci_corrector *k, int code, const std::string &msg) {
   if (k) k->err = msg;
@@ -243,8 +316,20 @@ int gradient(oci_corrector *k, const double *x, const double *target, int B, int
   for (int l = NL - 1; l >= 0; --l) {
     const int Ci = k->chans[l], Co = k->chans[l + 1];
     const double *in = l == 0 ? x : k->act[l];
-    hipLaunchKernelGGL(k_conv_bwd_weight, dim3(Co, Ci), dim3(256), 0, k->stream,
-                       (const double *)g, Co, in, Ci, J, B, k->gw + k->woff[l]);
+    if (Co <= kTileCh && Ci <= kTileCh) {
+      const int nch = B * ((J + kChunk - 1) / kChunk);
+      const int nbx = std::min(kWgtBlocks, nch);
+      const int ngrp = (Co * Ci + 256 * kPairs - 1) / (256 * kPairs);
+      const size_t lds = (size_t)(Co * kChunk + Ci * (kChunk + 4)) * sizeof(double);
+      hipLaunchKernelGGL(k_conv_bwd_weight_part, dim3(nbx, ngrp), dim3(256), lds, k->stream,
+                         (const double *)g, Co, in, Ci, J, B, k->wpart);
+      const int n = Co * Ci * KW;
+      hipLaunchKernelGGL(k_conv_bwd_weight_sum, dim3((n + 255) / 256), dim3(256), 0, k->stream,
+                         (const double *)k->wpart, n, nbx, k->gw + k->woff[l]);
+    } else {
+      hipLaunchKernelGGL(k_conv_bwd_weight, dim3(Co, Ci), dim3(256), 0, k->stream,
+                         (const double *)g, Co, in, Ci, J, B, k->gw + k->woff[l]);
+    }
     if (l > 0) {
       hipLaunchKernelGGL(k_conv_bwd_data, dim3((J + 255) / 256, Ci / COT, B), dim3(256), 0,
                          k->stream, (const double *)g, Co, J, (const double *)(k->w + k->woff[l]),
@@ -287,7 +372,9 @@ extern "C" int oci_corrector_create(int32_t c_in, int32_t c_out, int32_t max_bat
             hipMalloc(&k->g0, gmax * sizeof(double)) == hipSuccess &&
             hipMalloc(&k->g1, gmax * sizeof(double)) == hipSuccess &&
             hipMalloc(&k->part, kPartBlocks * sizeof(double)) == hipSuccess &&
-            hipMalloc(&k->loss, sizeof(double)) == hipSuccess;
+            hipMalloc(&k->loss, sizeof(double)) == hipSuccess &&
+            hipMalloc(&k->wpart, (size_t)kTileCh * kTileCh * KW * kWgtBlocks * sizeof(double)) ==
+                hipSuccess;
   for (int l = 1; ok && l < NL; ++l)
     ok = hipMalloc(&k->act[l], per * HID * sizeof(double)) == hipSuccess;
   if (!ok) {
@@ -379,7 +466,7 @@ extern "C" void oci_corrector_destroy(oci_corrector *k) {
   if (!k) return;
   (void)hipStreamSynchronize(k->stream);
   double *bufs[] = {k->w, k->gw, k->m, k->v, k->y, k->g0, k->g1, k->part, k->loss,
-                    k->act[1], k->act[2], k->act[3]};
+                    k->wpart, k->act[1], k->act[2], k->act[3]};
   for (double *p : bufs)
     if (p) (void)hipFree(p);
   delete k;

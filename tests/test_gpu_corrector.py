@@ -32,8 +32,10 @@ def _close(got, ref, rtol=1e-12):
 
 
 # (c_in, c_out, batch, cells): several 256-cell work-groups with a ragged
-# tail, meshes shorter than the kernel width, one cell, S_32-sized channels
-CASES = [(8, 4, 3, 700), (8, 4, 1, 3), (4, 4, 2, 1), (64, 64, 2, 257), (8, 32, 1, 5)]
+# tail, meshes shorter than the kernel width, one cell, S_32-sized channels,
+# and a layer wider than 64 channels (the untiled weight gradient)
+CASES = [(8, 4, 3, 700), (8, 4, 1, 3), (4, 4, 2, 1), (64, 64, 2, 257), (8, 32, 1, 5),
+         (128, 8, 2, 90)]
 
 
 @pytest.mark.parametrize("c_in,c_out,B,J", CASES)
