@@ -29,16 +29,18 @@ namespace occ {
 constexpr int KW = 5, HID = 32, NL = 4, COT = 4;
 
 // y[b][o][j] = sum_i sum_t W[o][i][t] x[b][i][j + t - 2] (zero outside the
-// mesh), ReLU if relu.  Grid (ceil(J/256), Co/COT, B); COT outputs per thread.
+// mesh), ReLU if relu.  Grid (ceil(J/256), Co/CT, B); CT outputs per thread
+// (8 where Co allows: fewer re-reads of x per output).
+template <int CT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const double *__restrict__ x, int Ci, int J,
                                                   const double *__restrict__ W, int Co,
                                                   double *__restrict__ y, int relu) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int o0 = blockIdx.y * COT, b = blockIdx.z;
+  const int o0 = blockIdx.y * CT, b = blockIdx.z;
   if (j >= J) return;
-  double acc[COT];
+  double acc[CT];
 #pragma unroll
-  for (int o = 0; o < COT; ++o) acc[o] = 0.0;
+  for (int o = 0; o < CT; ++o) acc[o] = 0.0;
   const double *xb = x + (size_t)b * Ci * J;
   for (int i = 0; i < Ci; ++i) {
     double xv[KW];
@@ -48,29 +50,30 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const double *__restrict__ x, 
       xv[t] = (k >= 0 && k < J) ? xb[(size_t)i * J + k] : 0.0;
     }
 #pragma unroll
-    for (int o = 0; o < COT; ++o)
+    for (int o = 0; o < CT; ++o)
 #pragma unroll
       for (int t = 0; t < KW; ++t) acc[o] += W[((size_t)(o0 + o) * Ci + i) * KW + t] * xv[t];
   }
 #pragma unroll
-  for (int o = 0; o < COT; ++o)
+  for (int o = 0; o < CT; ++o)
     y[((size_t)b * Co + o0 + o) * J + j] = relu ? fmax(acc[o], 0.0) : acc[o];
 }
 
 // Gradient wrt a layer's input: gx[b][i][k] = sum_o sum_t W[o][i][t]
 // g[b][o][k - t + 2], times the ReLU mask of that input (act > 0) when act is
 // given (the input is the previous layer's ReLU output).  Grid (ceil(J/256),
-// Ci/COT, B).
+// Ci/CT, B).
+template <int CT>
 __global__ __launch_bounds__(256) void k_conv_bwd_data(const double *__restrict__ g, int Co, int J,
                                                        const double *__restrict__ W, int Ci,
                                                        const double *__restrict__ act,
                                                        double *__restrict__ gx) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i0 = blockIdx.y * COT, b = blockIdx.z;
+  const int i0 = blockIdx.y * CT, b = blockIdx.z;
   if (k >= J) return;
-  double acc[COT];
+  double acc[CT];
 #pragma unroll
-  for (int i = 0; i < COT; ++i) acc[i] = 0.0;
+  for (int i = 0; i < CT; ++i) acc[i] = 0.0;
   const double *gb = g + (size_t)b * Co * J;
   for (int o = 0; o < Co; ++o) {
     double gv[KW];
@@ -80,12 +83,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const double *__restrict_
       gv[t] = (j >= 0 && j < J) ? gb[(size_t)o * J + j] : 0.0;
     }
 #pragma unroll
-    for (int i = 0; i < COT; ++i)
+    for (int i = 0; i < CT; ++i)
 #pragma unroll
       for (int t = 0; t < KW; ++t) acc[i] += W[((size_t)o * Ci + i0 + i) * KW + t] * gv[t];
   }
 #pragma unroll
-  for (int i = 0; i < COT; ++i) {
+  for (int i = 0; i < CT; ++i) {
     const size_t e = ((size_t)b * Ci + i0 + i) * J + k;
     gx[e] = (act && !(act[e] > 0.0)) ? 0.0 : acc[i];
   }
@@ -295,8 +298,14 @@ int forward(oci_corrector *k, const double *x, int B, int J, double *out) {
   for (int l = 0; l < NL; ++l) {
     const int Ci = k->chans[l], Co = k->chans[l + 1];
     double *o = l == NL - 1 ? out : k->act[l + 1];
-    hipLaunchKernelGGL(k_conv_fwd, dim3((J + 255) / 256, Co / COT, B), dim3(256), 0, k->stream, in,
-                       Ci, J, (const double *)(k->w + k->woff[l]), Co, o, l < NL - 1 ? 1 : 0);
+    const double *W = k->w + k->woff[l];
+    const int relu = l < NL - 1 ? 1 : 0;
+    if (Co % 8 == 0)
+      hipLaunchKernelGGL(k_conv_fwd<8>, dim3((J + 255) / 256, Co / 8, B), dim3(256), 0, k->stream,
+                         in, Ci, J, W, Co, o, relu);
+    else
+      hipLaunchKernelGGL(k_conv_fwd<COT>, dim3((J + 255) / 256, Co / COT, B), dim3(256), 0,
+                         k->stream, in, Ci, J, W, Co, o, relu);
     in = o;
   }
   CK(k, hipGetLastError());
@@ -331,7 +340,8 @@ int gradient(oci_corrector *k, const double *x, const double *target, int B, int
                          (const double *)g, Co, in, Ci, J, B, k->gw + k->woff[l]);
     }
     if (l > 0) {
-      hipLaunchKernelGGL(k_conv_bwd_data, dim3((J + 255) / 256, Ci / COT, B), dim3(256), 0,
+      // (l > 0: Ci is the hidden width, a multiple of 8)
+      hipLaunchKernelGGL(k_conv_bwd_data<8>, dim3((J + 255) / 256, Ci / 8, B), dim3(256), 0,
                          k->stream, (const double *)g, Co, J, (const double *)(k->w + k->woff[l]),
                          Ci, (const double *)k->act[l], gn);
       std::swap(g, gn);
