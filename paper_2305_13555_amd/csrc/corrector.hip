@@ -144,9 +144,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const double *__restric
 // takes the chunks of kChunk cells bx, bx + nbx, ... of the batch, stages
 // g[b][:][chunk] and x[b][:][chunk - 2 .. chunk + kChunk + 2) in LDS once,
 // and each thread sums, for its (at most four) (o, i) pairs of pair group y,
-// the five taps over the chunk; part[((o*Ci + i)*KW + t)*nbx + bx] holds the
-// work-group's sums.  Pass 2 adds the nbx partial sums of every weight in
-// order.  Dynamic LDS: (Co*kChunk + Ci*(kChunk+4)) doubles.
+// the five taps over the chunk; part[bx*n + (o*Ci + i)*KW + t] (n = Co*Ci*KW)
+// holds the work-group's sums.  Pass 2 adds the nbx partial sums of every
+// weight in order.  Dynamic LDS: (Co*kChunk + Ci*(kChunk+4)) doubles.
 constexpr int kChunk = 32, kTileCh = 64, kPairs = 4;
 __global__ __launch_bounds__(256) void k_conv_bwd_weight_part(const double *__restrict__ g, int Co,
                                                               const double *__restrict__ x, int Ci,
@@ -181,7 +181,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_part(const double *__re
       if (p < npair) {
         const double *gr = gs + (p / Ci) * kChunk;
         const double *xr = xs + (p % Ci) * (kChunk + 4);
-        for (int j = 0; j < kChunk; ++j) {
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {   // (unrolled: each x value serves five taps)
           const double gv = gr[j];
 #pragma unroll
           for (int t = 0; t < KW; ++t) acc[q][t] += gv * xr[j + t];
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_part(const double *__re
     const int p = p0 + q * 256 + tid;
     if (p < npair)
 #pragma unroll
-      for (int t = 0; t < KW; ++t) part[((size_t)p * KW + t) * nbx + bx] = acc[q][t];
+      for (int t = 0; t < KW; ++t) part[(size_t)bx * npair * KW + (size_t)p * KW + t] = acc[q][t];
   }
 }
 
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_sum(const double *__res
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   double s = 0.0;
-  for (int b = 0; b < nbx; ++b) s += part[(size_t)e * nbx + b];
+  for (int b = 0; b < nbx; ++b) s += part[(size_t)b * n + e];
   dW[e] = s;
 }
 
@@ -266,14 +267,14 @@ struct oci_corrector {
   double *y = nullptr;        // network output during training
   double *g0 = nullptr, *g1 = nullptr;   // gradient ping-pong [B][max(HID, c_out)][J]
   double *part = nullptr, *loss = nullptr;
-  double *wpart = nullptr;    // weight-gradient partial sums [Co*Ci*KW][kWgtBlocks]
+  double *wpart = nullptr;    // weight-gradient partial sums [kWgtBlocks][Co*Ci*KW]
   int64_t adam_t = 0;
 };
 
 namespace {
 
 constexpr int kPartBlocks = 256;
-constexpr int kWgtBlocks = 128;   // work-groups per pair group of the tiled weight gradient
+constexpr int kWgtBlocks = 256;   // work-groups per pair group of the tiled weight gradient
 
 int cfail(oci_corrector *k, int code, const std::string &msg) {
   if (k) k->err = msg;
