@@ -213,6 +213,17 @@ int oci_get_sizes(const oci_ctx *c, int32_t *n_angles, int32_t *n_cells, int32_t
  * 1 with OCI_PREC_FP32.  Returns the count (>= 1), or OCI_EINVAL for NULL. */
 int oci_iterates_per_launch(const oci_ctx *c);
 
+/* Set the launch shape: at most k (>= 2) iterates per iteration kernel,
+ * clamped to what the problem allows (oci_iterates_per_launch() of a fresh
+ * context without OCI_ITERATES_PER_LAUNCH).  Results do not depend on it
+ * (the iterates are the same; only their grouping into launches changes);
+ * it is a tuning knob (see the autotuner in the Python package).  Waits for
+ * the context's stream when the shape changes (cached step graphs are
+ * rebuilt); not to be called while another thread drives the context.
+ * Returns the shape now in effect (1 with OCI_PREC_FP32, where it has no
+ * effect), or OCI_EINVAL for NULL or k < 2. */
+int oci_set_iterates_per_launch(oci_ctx *c, int32_t k);
+
 /* Per-region operator, for inspection and tests: [2N+4+2N][4N+1] row-major,
  * rows = (outgoing flux 2N, phi 4, psi_edge 2N), columns = (incident flux 2N,
  * psi_{k-1/2} 2N, source 1), i.e. the needed rows of (A - S)^{-1} applied to

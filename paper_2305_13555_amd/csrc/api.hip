@@ -106,7 +106,8 @@ struct oci_ctx {
   size_t lds_it2 = 0;
   void *fn_iterK[5] = {};     // [3], [4]: three and four iterates per launch (N = 8 .. 128)
   size_t lds_itK[5] = {};
-  int kimax = 2;              // most iterates per launch
+  int kimax = 2;              // most iterates per launch (the active cap)
+  int kibuilt = 2;            // most iterates per launch this problem allows
   std::string err;
   StepArgs sa{};
   SiArgs si{};
@@ -666,6 +667,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
     }
   }
 #undef OCI_KERNELK
+  c->kibuilt = c->kimax;
   // OCI_ITERATES_PER_LAUNCH (2 .. 4) caps the iterates of one launch
   if (const char *env = std::getenv("OCI_ITERATES_PER_LAUNCH")) {
     const int v = std::atoi(env);
@@ -1387,6 +1389,18 @@ extern "C" int oci_get_sizes(const oci_ctx *c, int32_t *n_angles, int32_t *n_cel
 extern "C" int oci_iterates_per_launch(const oci_ctx *c) {
   if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
   return c->mixed ? 1 : c->kimax;
+}
+
+extern "C" int oci_set_iterates_per_launch(oci_ctx *c, int32_t k) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (k < 2) return fail(c, OCI_EINVAL, "iterates per launch must be >= 2");
+  if (c->mixed) return 1;
+  const int v = std::min<int>(k, c->kibuilt);
+  if (v != c->kimax) {
+    drop_step_graphs(c);   // the cached step graphs hold the old launch sequence
+    c->kimax = v;
+  }
+  return v;
 }
 
 extern "C" int oci_get_operator(oci_ctx *c, int32_t region, double *op) {

@@ -91,6 +91,7 @@ def _load():
         "oci_get_quadrature": (ctypes.c_int, [vp, _dp, _dp]),
         "oci_get_sizes": (ctypes.c_int, [vp, _ip, _ip, _ip]),
         "oci_iterates_per_launch": (ctypes.c_int, [vp]),
+        "oci_set_iterates_per_launch": (ctypes.c_int, [vp, ctypes.c_int32]),
         "oci_get_operator": (ctypes.c_int, [vp, ctypes.c_int32, _dp]),
         "oci_destroy": (None, [vp]),
         "oci_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -276,6 +277,10 @@ def oci_iterates_per_launch(ctx):
     return _check(_lib.oci_iterates_per_launch(ctx), ctx)
 
 
+def oci_set_iterates_per_launch(ctx, k):
+    return _check(_lib.oci_set_iterates_per_launch(ctx, int(k)), ctx)
+
+
 def oci_get_flux(ctx, out=None):
     n, J, _ = oci_get_sizes(ctx)
     if out is None:
@@ -329,6 +334,10 @@ class OciContext:
         self.handle = oci_setup(prob, stream, tol, max_iters, strict, precision)
         self.n_angles, self.n_cells, self.n_regions = oci_get_sizes(self.handle)
         self.iterates_per_launch = oci_iterates_per_launch(self.handle)
+
+    def set_iterates_per_launch(self, k):
+        self.iterates_per_launch = oci_set_iterates_per_launch(self.handle, k)
+        return self.iterates_per_launch
 
     def refactor(self, prob, tol=None, max_iters=None, strict=None):
         oci_refactor(self.handle, prob, tol, max_iters, strict, self.precision)
