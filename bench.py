@@ -393,6 +393,11 @@ def main():
     large = None if args.no_large else large_case(oci, torch, stream)
     ensemble = None if args.no_large else ensemble_case(oci, torch)
     learned = None if args.no_large else learned_case(oci, torch)
+    # the launch-shape autotuner on the bench workload (reported; the timed
+    # solves above use the library's default shape)
+    from paper_2305_13555_amd import tune
+    with oci.OciContext(prob, stream=stream) as ct:
+        shape, shape_ms = tune.tune(ct, torch, n_steps=8, repeats=3, use_cache=False)
     def si_steps(tol):
         with oci.OciContext(prob, stream=stream, tol=tol) as cs:
             ms, its = [], []
@@ -461,6 +466,8 @@ def main():
         "large_case": large,
         "ensemble": ensemble,
         "learned": learned,
+        "launch_shape_tuning": {"default": ctx.iterates_per_launch, "chosen": shape,
+                                "ms_per_time_step": {str(k): v for k, v in shape_ms.items()}},
     }
     print(json.dumps(line))
     ctx.close()
