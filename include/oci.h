@@ -259,7 +259,9 @@ int oci_gauss_legendre(int32_t n, double *mu, double *w);
  * Device pointers (x, y, target) must hold the sizes stated and stay valid
  * until the call returns; every call runs on the stream given at creation
  * and returns after it completes, except oci_corrector_forward, which only
- * enqueues.  Errors: OCI_EINVAL (NULL pointer, batch or cells outside
+ * enqueues.  A corrector keeps its activations between the forward and
+ * backward passes: calls on one corrector must not overlap (one host thread,
+ * one stream).  Errors: OCI_EINVAL (NULL pointer, batch or cells outside
  * [1, the maximum given at creation], channels not multiples of 4),
  * OCI_ENOMEM, OCI_EDEVICE; oci_corrector_last_error() gives the message. */
 typedef struct oci_corrector oci_corrector;

@@ -387,7 +387,8 @@ class OciContext:
 class Corrector:
     """The learned iterate corrector (oci_corrector_* in include/oci.h):
     inputs [batch][c_in][cells], outputs [batch][c_out][cells], FP64 device
-    tensors."""
+    tensors.  Its kernels run on the stream given here (default: torch's
+    current stream at creation); tensors passed in must be ready on it."""
 
     def __init__(self, c_in, c_out, max_batch, max_cells, stream=None):
         h = ctypes.c_void_p()
