@@ -199,14 +199,25 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_part(const double *__re
   }
 }
 
-__global__ __launch_bounds__(256) void k_conv_bwd_weight_sum(const double *__restrict__ part,
-                                                             int n, int nbx,
-                                                             double *__restrict__ dW) {
+// (eight running sums per weight, partials b = r, r + 8, ..., then added in
+// order: eight loads in flight instead of one)
+__global__ __launch_bounds__(64) void k_conv_bwd_weight_sum(const double *__restrict__ part,
+                                                            int n, int nbx,
+                                                            double *__restrict__ dW) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
-  double s = 0.0;
-  for (int b = 0; b < nbx; ++b) s += part[(size_t)b * n + e];
-  dW[e] = s;
+  double s[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) s[r] = 0.0;
+  int b = 0;
+  for (; b + 8 <= nbx; b += 8)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s[r] += part[(size_t)(b + r) * n + e];
+  for (int r = 0; b + r < nbx; ++r) s[r] += part[(size_t)(b + r) * n + e];
+  double t = s[0];
+#pragma unroll
+  for (int r = 1; r < 8; ++r) t += s[r];
+  dW[e] = t;
 }
 
 // Mean squared error: g = 2 (y - target) / n and per-work-group partial sums
@@ -334,7 +345,7 @@ int gradient(oci_corrector *k, const double *x, const double *target, int B, int
       hipLaunchKernelGGL(k_conv_bwd_weight_part, dim3(nbx, ngrp), dim3(256), lds, k->stream,
                          (const double *)g, Co, in, Ci, J, B, k->wpart);
       const int n = Co * Ci * KW;
-      hipLaunchKernelGGL(k_conv_bwd_weight_sum, dim3((n + 255) / 256), dim3(256), 0, k->stream,
+      hipLaunchKernelGGL(k_conv_bwd_weight_sum, dim3((n + 63) / 64), dim3(64), 0, k->stream,
                          (const double *)k->wpart, n, nbx, k->gw + k->woff[l]);
     } else {
       hipLaunchKernelGGL(k_conv_bwd_weight, dim3(Co, Ci), dim3(256), 0, k->stream,
