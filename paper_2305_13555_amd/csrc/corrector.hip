@@ -30,30 +30,40 @@ constexpr int KW = 5, HID = 32, NL = 4, COT = 4;
 
 // y[b][o][j] = sum_i sum_t W[o][i][t] x[b][i][j + t - 2] (zero outside the
 // mesh), ReLU if relu.  Grid (ceil(J/256), Co/CT, B); CT outputs per thread
-// (8 where Co allows: fewer re-reads of x per output).
+// (8 where Co allows: fewer re-reads of x per output).  The work-group's 260
+// input cells are staged in LDS kStageCh channels at a time, so each x value
+// is read from memory once per work-group instead of once per tap.
+constexpr int kStageCh = 8, kSpan = 256 + KW - 1;
 template <int CT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const double *__restrict__ x, int Ci, int J,
                                                   const double *__restrict__ W, int Co,
                                                   double *__restrict__ y, int relu) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double xs[kStageCh][kSpan];
+  const int j0 = blockIdx.x * 256, j = j0 + threadIdx.x;
   const int o0 = blockIdx.y * CT, b = blockIdx.z;
-  if (j >= J) return;
   double acc[CT];
 #pragma unroll
   for (int o = 0; o < CT; ++o) acc[o] = 0.0;
   const double *xb = x + (size_t)b * Ci * J;
-  for (int i = 0; i < Ci; ++i) {
-    double xv[KW];
-#pragma unroll
-    for (int t = 0; t < KW; ++t) {
-      const int k = j + t - 2;
-      xv[t] = (k >= 0 && k < J) ? xb[(size_t)i * J + k] : 0.0;
+  for (int i0 = 0; i0 < Ci; i0 += kStageCh) {
+    const int nc = min(kStageCh, Ci - i0);
+    __syncthreads();   // the previous channels' reads are done
+    for (int e = threadIdx.x; e < nc * kSpan; e += blockDim.x) {
+      const int ii = e / kSpan, c = e - ii * kSpan, k = j0 - 2 + c;
+      xs[ii][c] = (k >= 0 && k < J) ? xb[(size_t)(i0 + ii) * J + k] : 0.0;
     }
+    __syncthreads();
+    for (int ii = 0; ii < nc; ++ii) {
+      double xv[KW];
 #pragma unroll
-    for (int o = 0; o < CT; ++o)
+      for (int t = 0; t < KW; ++t) xv[t] = xs[ii][threadIdx.x + t];   // x[j + t - 2]
 #pragma unroll
-      for (int t = 0; t < KW; ++t) acc[o] += W[((size_t)(o0 + o) * Ci + i) * KW + t] * xv[t];
+      for (int o = 0; o < CT; ++o)
+#pragma unroll
+        for (int t = 0; t < KW; ++t) acc[o] += W[((size_t)(o0 + o) * Ci + i0 + ii) * KW + t] * xv[t];
+    }
   }
+  if (j >= J) return;
 #pragma unroll
   for (int o = 0; o < CT; ++o)
     y[((size_t)b * Co + o0 + o) * J + j] = relu ? fmax(acc[o], 0.0) : acc[o];
