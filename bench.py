@@ -434,7 +434,7 @@ def main():
                         "[0.01, 10] with dx = 1, c ~ U[0.5, 0.99], Q ~ U[0, 1], dt = 0.05, "
                         "v = 1, tol 1e-10 (seeded)" % prob.name,
             "cells": J, "angles": N, "regions": prob.n_regions, "time_steps": T,
-            "tol": prob.tol, "step": "operator rebuild + %d MB time steps" % T,
+            "tol": prob.tol, "step": "operator rebuild + %d time steps" % T,
             "driver": "queued solve (one batch of iteration launches per step)",
         },
         "roofline": {

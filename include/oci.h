@@ -126,6 +126,12 @@ typedef struct {
                           iterates), in kernels of up to
                           oci_iterates_per_launch() iterates each */
   int32_t pad;
+  double err_bound;    /* a-posteriori error bound of the accepted iterate:
+                          e_l rho / (1 - rho) with rho = e_l / e_{l-1} clamped to
+                          [0, 0.9999] (the bound OCI_FLAG_STRICT tests against
+                          tol); -1 when e_{l-1} is undefined (l = 1 of OCI) and
+                          always with OCI_PREC_FP32, whose consecutive FP64
+                          iterates do not give OCI's contraction rate */
 } oci_step_info;
 
 /* Build a context: validates *p, computes the quadrature, uploads the region

@@ -27,6 +27,7 @@
 
 #include "oci.h"
 #include "oci_kernels.h"
+#include "plan.h"
 
 using namespace ocik;
 
@@ -34,7 +35,7 @@ namespace {
 
 thread_local std::string g_last_error;
 
-constexpr int kMaxBatch = 64;   // iteration launches per replayed batch
+using ocip::kMaxBatch;           // iteration launches per replayed batch
 static_assert(kMaxBatch + 1 <= ocik::kMaxRing, "the end of step holds one ring of e values");
 constexpr int kMaxInner = 64;   // FP32 inner iterations per correction (mixed precision)
 
@@ -104,7 +105,7 @@ struct oci_ctx {
   void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr, *fn_inner = nullptr;
   void *fn_iter2 = nullptr;   // two iterates per launch (plain FP64 batches)
   size_t lds_it2 = 0;
-  void *fn_iterK[5] = {};     // [3], [4]: three and four iterates per launch (N = 8 .. 128)
+  void *fn_iterK[5] = {};     // [3], [4]: three and four iterates per launch (N = 8, 16, 32)
   size_t lds_itK[5] = {};
   int kimax = 2;              // most iterates per launch (the active cap)
   int kibuilt = 2;            // most iterates per launch this problem allows
@@ -706,18 +707,13 @@ static int clear_stall(oci_ctx *c) {
   return OCI_OK;
 }
 
-// Launches in the extra-th batch after a step's first: 1, 1, 2, 4, ... up to
-// kMaxBatch (the shift is bounded: a slow step can need thousands of batches).
-static int resume_count(int extra) {
-  if (extra <= 2) return 1;
-  return extra - 2 >= 30 ? kMaxBatch : std::min(kMaxBatch, 1 << (extra - 2));
-}
+using ocip::resume_count;
 
 // A later batch of a step: `count` launches after iterate cb (one by one:
 // only needed when the first batch was too short).  For SI each iteration
 // also decides.
 static int launch_batch(oci_ctx *c, bool si, int cb, int count, int half = 0) {
-  if (cb < 0 || count < 1 || count > kMaxBatch)
+  if (!ocip::batch_range_ok(cb, count))
     return fail(c, OCI_EDEVICE, "internal: iteration batch out of range");
   for (int i = 1; i <= count; ++i) {
     int node = i;
@@ -741,8 +737,18 @@ static int launch_batch(oci_ctx *c, bool si, int cb, int count, int half = 0) {
   return OCI_OK;
 }
 
+// A-posteriori error bound of an accepted iterate with e = e_l and
+// e_prev = e_{l-1}: e rho / (1 - rho), rho = e / e_prev clamped to
+// [0, 0.9999] (the strict stopping rule's bound); -1 when either is undefined.
+static double error_bound(double e, double e_prev) {
+  if (!(e >= 0.0) || !(e_prev >= 0.0)) return -1.0;
+  double rho = e_prev == 0.0 ? 0.0 : e / e_prev;
+  rho = std::min(std::max(rho, 0.0), 0.9999);
+  return e * rho / (1.0 - rho);
+}
+
 static void fill_info(oci_step_info *info, int iterations, int status, double residual, double ms,
-                      double iter_ms, int launches) {
+                      double iter_ms, int launches, double err_bound = -1.0) {
   if (!info) return;
   info->iterations = iterations;
   info->status = status;
@@ -751,6 +757,7 @@ static void fill_info(oci_step_info *info, int iterations, int status, double re
   info->iter_ms = iter_ms;
   info->launches = launches;
   info->pad = 0;
+  info->err_bound = err_bound;
 }
 
 // A non-finite step is abandoned: psi_{k-1/2} is kept, the iterate restarts cold.
@@ -814,7 +821,8 @@ static int si_run(oci_ctx *c, oci_step_info *info) {
   c->steps += 1;
   c->have_flux = true;
   const int status = st.status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
-  fill_info(info, st.accepted, status, st.e_last, ms, iter_ms, launches);
+  fill_info(info, st.accepted, status, st.e_last, ms, iter_ms, launches,
+            error_bound(st.e_last, st.e_prev));
   return status;
 }
 
@@ -1029,7 +1037,7 @@ static int launch_outer(oci_ctx *c, int lprev, int half) {
 
 static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half) {
   // the end reads the records of iterates first .. last, one ring of them
-  if (first < 1 || last < first || last - first >= c->nbuf - 1)
+  if (!ocip::end_range_ok(first, last, c->nbuf))
     return fail(c, OCI_EDEVICE, "internal: end of step over an iterate range out of bounds");
   // (single-iterate launches only: resumed steps)
   int rstep = c->rstep, pre = c->pre_reduce, nred = 1, mode = pre | 2;
@@ -1089,8 +1097,7 @@ static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_lau
       launches += c->m_inner + 1;
       rc = launch_end(c, phi_dev, launched, launched, c->parity);
     } else {
-      const int count = std::min({resume_count(extra),
-                                  std::max(c->max_iters - launched, 1), c->nbuf - 1});
+      const int count = ocip::resumed_batch(extra, launched, c->max_iters, c->nbuf);
       rc = launch_batch(c, false, launched, count, c->parity);
       if (rc) return rc;
       launched += count;
@@ -1177,7 +1184,8 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
       // the window's stream time split evenly over its steps
       const double share = ms / w.count;
       fill_info(infos ? &infos[s] : nullptr, step_iterations(c, r.accepted), status, r.e_last,
-                share, share, step_launches(c, w.batch));
+                share, share, step_launches(c, w.batch),
+                c->mixed ? -1.0 : error_bound(r.e_last, r.e_prev));
       complete_step(c, r.accepted);
       hint = std::max(hint, step_iterations(c, r.accepted));
     }
@@ -1207,7 +1215,8 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
     const int status = st.fin_status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
     if (status == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
     fill_info(infos ? &infos[k] : nullptr, step_iterations(c, st.fin_accepted), status, st.fin_e,
-              ms / w.count + rms, rms, launches);
+              ms / w.count + rms, rms, launches,
+              c->mixed ? -1.0 : error_bound(st.fin_e, st.fin_e_prev));
     complete_step(c, st.fin_accepted);
     c->batch_hint = std::max(step_iterations(c, st.fin_accepted), 1);
     if (c->mixed) tune_inner(c, c->batch_hint, c->m_inner);

@@ -67,6 +67,7 @@ struct StepCtl {
   double e_last;         // e of the accepted iterate (-1: undefined)
   double e_prev;         // source iteration: e of the previous iterate
   double fin_e;
+  double fin_e_prev;     // e of the iterate before the accepted one (-1: undefined)
 };
 
 // Iterate buffers: two rings of nbuf, one per step parity (half h holds
@@ -82,6 +83,7 @@ struct StepRecord {
   int32_t accepted;
   int32_t status;
   double e_last;
+  double e_prev;   // e of the iterate before the accepted one (-1: undefined)
 };
 
 enum { kRunning = 0, kConverged = 1, kIterLimit = 2, kNonFinite = 3 };

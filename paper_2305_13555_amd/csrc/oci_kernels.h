@@ -143,7 +143,7 @@ __global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rstep,
 // previous launch's iterates, whose residuals the extra work-group reduces.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_oci_iterate2(StepArgs a, int node, int cb, int half, int nred);
-// Iterates l .. l+KI-1 in one launch (KI = 3, 4; built for N = 8 .. 128).
+// Iterates l .. l+KI-1 in one launch (KI = 3, 4; built for N = 8, 16, 32).
 template <int CH, bool ARGT, bool VEC, int NF, int KI>
 __global__ void k_oci_iterateK(StepArgs a, int node, int cb, int half, int nred);
 // mode bit 0: the e of the trailing iterates are already in dec (k_reduce_rec

@@ -3,29 +3,36 @@
 //
 // For every cell j of region r the iteration solves (A - S) Psi_j = c_j with
 // the incident fluxes of c^+ / c^- taken from the neighbours' previous
-// iterate.  c_j is linear in (incident fluxes, psi_{k-1/2}, Q), so with the
-// operator formed at setup (rows of (A - S)^{-1} applied to those columns)
-// each iteration of a whole region is one GEMM over its cells:
+// iterate.  c_j is linear in (incident fluxes, psi_{k-1/2}, Q), and the
+// scattering block S couples the angles only through the cell's four scalar
+// fluxes (rank 4), so an iteration is applied in structured form:
 //
-//   [out_j ; phi_j]^(l+1) = G_r inc_j^(l) + [g_j ; h_j]              (hot)
-//   [g_j ; h_j]           = P_r psi_{k-1/2,j} + p_r                  (once per step)
-//   psi_{k+1/2,j}         = E_r [inc_j^(L-1) ; psi_{k-1/2,j}] + e_r  (end of step)
+//   phi_j^(l+1)       = H_r inc_j^(l) + h_j        (4 rows of the reduced
+//                                                  operator, FP64 MFMA)
+//   out_{j,m}^(l+1)   = g'_{j,m} + (two rows of A_m^{-1}) (s_r phi_j^(l+1)
+//                                  + |mu_m| inc_{j,m})   (per angle, VALU)
+//   [g'; h]_j         = from psi_{k-1/2,j} and Q_r  (once per step)
+//   psi_{k+1/2,j,m}   = from inc_j^(L-1), psi_{k-1/2,j} and phi_j^(L)
+//                                                  (end of step, per angle)
 //
 // which is the same iteration as solving every cell's dense system with its
-// LU factors, in a different association of the same products.  G_r is
-// (2N+4) x 2N, applied with v_mfma_f64_16x16x4f64 to a 16-cell tile: the
-// A operand is the tile's incident fluxes (one cell per MFMA row), gathered
-// from the outgoing rows of the neighbouring cells staged in LDS; the B
-// operand is the operator, packed in fragment order, L2-resident and shared
-// by every tile of the region.
+// LU factors, with the products associated differently: O(N) work per cell.
+// A work-group owns a 16-cell tile of one region; the scalar-flux rows run on
+// v_mfma_f64_16x16x4f64 with the tile's incident fluxes as the A operand (one
+// cell per MFMA row, gathered from the neighbours' outgoing rows staged in
+// LDS) and the operator rows, packed in fragment order and L2-resident, as B.
 //
-// Each iteration is one launch with no device-scope synchronisation inside:
-// every work-group first re-derives the stopping decision for the previous
-// iterate from the per-tile residual records that launch left behind (they
-// are visible because the launches are ordered), and exits at once if the
-// step is decided; otherwise it computes its tile and leaves its own record.
-// The work-group that takes a decision first also writes it to the step
-// control block, which later launches read.
+// Launches: k_oci_iterate (one iterate), k_oci_iterate2 (two) and
+// k_oci_iterateK (three or four: halo cells recomputed level by level) each
+// write their iterates and per-tile residual records; an extra work-group of
+// every iteration launch reduces the previous launch's records into the
+// per-iterate e.  No launch waits on a decision: k_step_end applies the
+// stopping rule to the iterates of the batch, forms psi_{k+1/2} from the
+// accepted one and the next step's constant, and (inside a replayed window)
+// computes iterate 1 of the next step.  A step still undecided stalls the
+// queue (a control-block flag every kernel checks) and the host resumes it.
+// Mixed precision (k_oci_inner) iterates an FP32 correction between FP64
+// iterates.
 #include "oci_kernels.h"
 
 namespace ocik {
@@ -1475,11 +1482,13 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
   }
   __syncthreads();
   int status = kRunning, L = last;
-  double e_acc = -1.0;
+  double e_acc = -1.0, e_pacc = -1.0;
   if (s_first < ncand) {
     L = first + s_first * rstep;
     status = stop_rule_e(L, e_of(L), e_before_of(s_first, L), 2, a.tol, a.strict, a.max_iters);
     e_acc = L >= 2 ? e_of(L) : -1.0;
+    // (the iterate before it, for the a-posteriori bound the host reports)
+    e_pacc = (L - rstep >= 2 && L - rstep >= l0) ? e_of(L - rstep) : -1.0;
   }
   const bool decided = status != kRunning && status != kNonFinite;
   // the outcome goes to fields no work-group of this launch reads (stored
@@ -1490,10 +1499,12 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
       ct->fin_accepted = L;
       ct->fin_status = status;
       ct->fin_e = e_acc;
+      ct->fin_e_prev = e_pacc;
       if (a.rec) {
         a.rec[step].accepted = L;
         a.rec[step].status = status;
         a.rec[step].e_last = e_acc;
+        a.rec[step].e_prev = e_pacc;
       }
       if (decided) {
         ct->fin_buf = ring_buf(a, L, half);

@@ -345,6 +345,7 @@ __global__ void k_si_end(SiArgs a) {
     ct->fin_accepted = c.accepted;
     ct->fin_status = c.status;
     ct->fin_e = c.e_last;
+    ct->fin_e_prev = c.e_prev;
     if (c.status == kConverged || c.status == kIterLimit) ct->fin_buf = a.own_buf + (c.accepted & 1);
   }
   if (c.stalled || c.status == kRunning || c.status == kNonFinite) return;

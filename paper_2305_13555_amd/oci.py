@@ -54,12 +54,13 @@ class oci_step_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("ms", ctypes.c_double),
                 ("iter_ms", ctypes.c_double), ("launches", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("pad", ctypes.c_int32), ("err_bound", ctypes.c_double)]
 
     def as_dict(self):
         return {"iterations": int(self.iterations), "status": int(self.status),
                 "residual": float(self.residual), "ms": float(self.ms),
-                "iter_ms": float(self.iter_ms), "launches": int(self.launches)}
+                "iter_ms": float(self.iter_ms), "launches": int(self.launches),
+                "err_bound": float(self.err_bound)}
 
 
 class OciError(RuntimeError):

@@ -208,10 +208,13 @@ def test_strict_converged_matches_direct(lib, seed):
     for k in range(2):
         assert got[k]["rc"] == lib.OCI_OK
         assert rel(got[k]["phi"], direct[k]["phi"]) < 1e-10
+        # the strict rule accepted the iterate on the bound the step reports
+        assert 0.0 <= got[k]["err_bound"] <= 1e-12
     got_si = gpu_run(lib, p, 2, method="si", tol=1e-12, max_iters=50000, strict=True)
     for k in range(2):
         assert got_si[k]["rc"] == lib.OCI_OK
         assert rel(got_si[k]["phi"], direct[k]["phi"]) < 1e-10
+        assert 0.0 <= got_si[k]["err_bound"] <= 1e-12
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
