@@ -298,6 +298,22 @@ const char *oci_corrector_last_error(const oci_corrector *k);
 /* Release the corrector (waits for its stream).  NULL is a no-op. */
 void oci_corrector_destroy(oci_corrector *k);
 
+/* Allocation-free forward pass, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): y = f(x) for the network with c_in inputs and c_out
+ * outputs (multiples of 4 in [4, 1024]) whose weights w sit in device memory
+ * in the layout of oci_corrector_num_weights() / _get_weights().  x
+ * [batch][c_in][cells] and y [batch][c_out][cells] are device pointers
+ * (caller-owned).  The hidden activations live in a fixed device array of
+ * the library (32 MiB per GPU, held until the process ends), which limits
+ * batch * cells to 65,536; nothing in it needs to start at zero.  Enqueued on
+ * hip_stream (a hipStream_t, NULL = the null stream), not waited for; calls
+ * that overlap on one GPU (other streams, other threads) share that array and
+ * race.  No allocation, no synchronisation.  Returns OCI_OK, OCI_EINVAL (NULL
+ * pointer, channels or sizes out of range; nothing enqueued) or OCI_EDEVICE. */
+int oci_corrector_forward_noalloc(const double *w, int32_t c_in, int32_t c_out, const double *x,
+                                  int32_t batch, int32_t cells, double *y, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -314,23 +315,30 @@ int check_shape(oci_corrector *k, int32_t batch, int32_t cells) {
   return OCI_OK;
 }
 
-// Forward pass of x [B][c_in][J] into out; hidden activations kept in act[1..3].
-int forward(oci_corrector *k, const double *x, int B, int J, double *out) {
+// Forward pass of x [B][chans[0]][J] into out on stream st, weights w
+// (layer l at w + woff[l]); the hidden outputs go to act[1..3].
+hipError_t launch_forward(hipStream_t st, const double *w, const size_t *woff, const int *chans,
+                          const double *x, int B, int J, double *out, double *const *act) {
   const double *in = x;
   for (int l = 0; l < NL; ++l) {
-    const int Ci = k->chans[l], Co = k->chans[l + 1];
-    double *o = l == NL - 1 ? out : k->act[l + 1];
-    const double *W = k->w + k->woff[l];
+    const int Ci = chans[l], Co = chans[l + 1];
+    double *o = l == NL - 1 ? out : act[l + 1];
+    const double *W = w + woff[l];
     const int relu = l < NL - 1 ? 1 : 0;
     if (Co % 8 == 0)
-      hipLaunchKernelGGL(k_conv_fwd<8>, dim3((J + 255) / 256, Co / 8, B), dim3(256), 0, k->stream,
-                         in, Ci, J, W, Co, o, relu);
+      hipLaunchKernelGGL(k_conv_fwd<8>, dim3((J + 255) / 256, Co / 8, B), dim3(256), 0, st, in,
+                         Ci, J, W, Co, o, relu);
     else
-      hipLaunchKernelGGL(k_conv_fwd<COT>, dim3((J + 255) / 256, Co / COT, B), dim3(256), 0,
-                         k->stream, in, Ci, J, W, Co, o, relu);
+      hipLaunchKernelGGL(k_conv_fwd<COT>, dim3((J + 255) / 256, Co / COT, B), dim3(256), 0, st,
+                         in, Ci, J, W, Co, o, relu);
     in = o;
   }
-  CK(k, hipGetLastError());
+  return hipGetLastError();
+}
+
+// Forward pass of x [B][c_in][J] into out; hidden activations kept in act[1..3].
+int forward(oci_corrector *k, const double *x, int B, int J, double *out) {
+  CK(k, launch_forward(k->stream, k->w, k->woff, k->chans, x, B, J, out, k->act));
   return OCI_OK;
 }
 
@@ -502,4 +510,70 @@ extern "C" void oci_corrector_destroy(oci_corrector *k) {
   for (double *p : bufs)
     if (p) (void)hipFree(p);
   delete k;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free inference
+// ---------------------------------------------------------------------------
+// The hidden activations of oci_corrector_forward_noalloc live in one
+// file-scope device array (each GPU the library runs on holds its own copy
+// until the process ends): two [batch][32][cells] buffers used in turn, so a
+// call handles batch * cells <= kNoAllocCells.  Host code never passes the
+// array's name to a kernel (in host code it is a stand-in, not a device
+// address): its device address is looked up once per device with
+// hipGetSymbolAddress, with that device current, and kept.
+namespace occ {
+constexpr int64_t kNoAllocCells = 65536;
+constexpr size_t kScratchDoubles = (size_t)2 * HID * kNoAllocCells;   // 32 MiB
+constexpr int kMaxDevices = 64;
+}  // namespace occ
+
+static __device__ __align__(256) double scratch[occ::kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[occ::kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+hipError_t scratch_of_current_device(double **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= occ::kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" int oci_corrector_forward_noalloc(const double *w, int32_t c_in, int32_t c_out,
+                                             const double *x, int32_t batch, int32_t cells,
+                                             double *y, void *hip_stream) {
+  if (!w || !x || !y) return OCI_EINVAL;
+  if (c_in < COT || c_out < COT || c_in % COT || c_out % COT || c_in > 1024 || c_out > 1024)
+    return OCI_EINVAL;
+  if (batch < 1 || cells < 1 || (int64_t)batch * cells > kNoAllocCells) return OCI_EINVAL;
+  double *scr = nullptr;
+  if (scratch_of_current_device(&scr) != hipSuccess) return OCI_EDEVICE;
+  int chans[NL + 1];
+  size_t woff[NL + 1] = {};
+  chans[0] = c_in;
+  for (int l = 1; l < NL; ++l) chans[l] = HID;
+  chans[NL] = c_out;
+  for (int l = 0; l < NL; ++l) woff[l + 1] = woff[l] + (size_t)chans[l + 1] * chans[l] * KW;
+  // layer outputs: scr, scr + per, scr (layer 2 reads the second buffer)
+  const size_t per = (size_t)HID * batch * cells;
+  double *act[NL] = {nullptr, scr, scr + per, scr};
+  const hipError_t e = launch_forward(static_cast<hipStream_t>(hip_stream), w, woff, chans, x,
+                                      batch, cells, y, act);
+  return e == hipSuccess ? OCI_OK : OCI_EDEVICE;
 }

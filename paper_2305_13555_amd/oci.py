@@ -110,6 +110,8 @@ def _load():
                                                     ctypes.c_double, _dp]),
         "oci_corrector_last_error": (ctypes.c_char_p, [vp]),
         "oci_corrector_destroy": (None, [vp]),
+        "oci_corrector_forward_noalloc": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp,
+                                                         ctypes.c_int32, ctypes.c_int32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -383,6 +385,20 @@ class OciContext:
             self.close()
         except Exception:
             pass
+
+
+def oci_corrector_forward_noalloc(w, c_in, c_out, x, out, stream=None):
+    """y = f(x) with no allocation inside the library: w (weights), x
+    [batch][c_in][cells] and out [batch][c_out][cells] are float64 device
+    tensors; enqueued on the stream (default: torch's current stream).
+    Returns the library's code (OCI_EINVAL for sizes beyond its limit)."""
+    for t in (w, x, out):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("w, x and out must be contiguous float64 device tensors")
+    B, J = int(x.shape[0]), int(x.shape[2])
+    return _lib.oci_corrector_forward_noalloc(
+        ctypes.c_void_p(w.data_ptr()), int(c_in), int(c_out), ctypes.c_void_p(x.data_ptr()), B, J,
+        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
 
 
 class Corrector:
