@@ -1,14 +1,20 @@
-"""Benchmark: plain FP64 one-cell inversion on one MI355X.
+"""Benchmark: one-cell inversion on one MI355X, on the 200,000-cell S_64 problem.
 
-One bench step = one full solve of the workload from its initial condition:
-rebuild every region's cell operator (oci_refactor), reset the state,
-then 100 MB time steps of OCI iterations to tolerance (oci_solve).  The metric
-is OCI cell-angle updates per second: sum over iterations of J*N, divided by
-wall time.  Source iteration on the same problem and the time to a 1e-6
-tolerance are reported beside it, and so is the learned corrector (trained
-on iterate histories the library generates, evaluated on a held-out step).
+Workload (the large seeded problem): 64 regions, 200,000 cells, S_64,
+sigma_t lognormal(0, 1) clipped to [0.01, 10] with dx = 1, c ~ U[0.5, 0.99],
+Q ~ U[0, 1], reflecting left / vacuum right, dt = 0.05, v = 1, 50 time steps,
+stopping tolerance 1e-6.  One bench step = one full solve from the initial
+condition: rebuild every region's cell operator (oci_refactor), reset the
+state, then the 50 time steps of plain FP64 OCI to tolerance (oci_solve, the
+scalar flux of every step into a device tensor).  The metric: OCI cell-angle
+updates per second (sum over iterations of J*N over wall time) and the time
+to the 1e-6 tolerance per time step; the same solve in mixed precision
+(FP64 defect correction, FP32 inner iterations) and source iteration are
+reported beside it, each with its error against the FP64 oracle on the first
+steps.  The 10,000-cell S_32 problem (100 steps, tol 1e-10), the ensemble
+and the learned corrector follow as secondary fields.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-secondary]
 Prints one JSON line.
 """
 import argparse
@@ -37,37 +43,35 @@ def algorithmic_bytes_per_cell_iteration(n_angles):
     return 8 * (6 * n_angles + 8)
 
 
-def algorithmic_bytes_per_cell_step(n_angles):
-    """Per cell and time step outside the iterations: the step constant reads
-    psi_{k-1/2} (2N) and writes [g; h] (2N+4); the end of step reads the
-    incident fluxes (2N) and psi_{k-1/2} (2N), writes psi_{k+1/2} (2N) and
-    copies the accepted scalar flux (4 in, 4 out)."""
-    return 8 * (10 * n_angles + 12)
-
-
 # the iteration kernel by iterates per launch (the library's launch shape)
 ITERATION_KERNELS = {1: "k_oci_iterate", 2: "k_oci_iterate2", 3: "k_oci_iterateK<3>",
                      4: "k_oci_iterateK<4>"}
 
 
-def roofline_launch_seconds(oci, prob, stream, steps=9, hi_launches=8, lo_launches=4):
-    """Per-launch time of the iteration kernel on the workload's cells, regions and
-    angles, with v = inf and tol = 0 so that every launch does the full work
-    (the kernel's work does not depend on the values).  Steps of hi_launches
-    and of lo_launches full launches (k iterates each, k the library's launch
-    shape) each run as one replayed graph (the launches and the end of step),
-    timed with HIP events on the library's stream; the per-launch time is the
+def roofline_launch_seconds(oci, prob, stream, steps=9, k=None):
+    """Per-launch time of the iteration kernel of k iterates per launch (default:
+    the library's launch shape) on the workload's cells, regions and angles,
+    with v = inf and tol = 0 so that every launch does the full work (the
+    kernel's work does not depend on the values).  Steps of two and of one
+    full launches (four and two with fewer than three iterates per launch:
+    all within the eight iterates one ring of iterate buffers takes at least)
+    each run as one replayed graph (the launches and the end of step), timed
+    with HIP events on the library's stream; the per-launch time is the
     difference of the median step times over the extra launches, which
     removes the end of step.  It is launch to launch: the kernel's duration
     plus the dispatch gap between two graph nodes.  Returns (seconds, k)."""
     import dataclasses
     roof = dataclasses.replace(prob, speed=float("inf"), name=prob.name + ", v = inf")
     with oci.OciContext(roof, stream=stream) as cq:
-        k = cq.iterates_per_launch
+        k = cq.iterates_per_launch if k is None else min(k, cq.iterates_per_launch)
+    hi_launches = 2 if k >= 3 else 4
+    lo_launches = hi_launches // 2
     hi, lo = hi_launches * k, lo_launches * k
     med = {}
     for n in (hi, lo):
         with oci.OciContext(roof, stream=stream, tol=0.0, max_iters=n) as cr:
+            if k >= 2:
+                cr.set_iterates_per_launch(k)
             cr.step()
             ms = []
             for _ in range(steps):
@@ -93,18 +97,20 @@ def copy_calibration(torch, mib):
 
 
 KERNEL_SOURCES = ("oci_step.hip", "oci_device.h", "oci_kernels.h")
-def traffic_profile(k):
+
+
+def traffic_profile(k, tag):
     name = ITERATION_KERNELS[k].replace("<", "").replace(">", "")
-    return os.path.join(ROOT, "profiles", name + "_c2_hbm_traffic.txt")
+    return os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.txt" % (name, tag))
 
 
-def measured_traffic(k):
-    """HBM bytes per launch of the iteration kernel from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
-    sources have changed since the counters were taken."""
+def measured_traffic(k, tag):
+    """HBM bytes per launch of the iteration kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is
+    none or the kernel sources have changed since the counters were taken."""
     import hashlib
     try:
-        fields = dict(line.split(":", 1) for line in open(traffic_profile(k))
+        fields = dict(line.split(":", 1) for line in open(traffic_profile(k, tag))
                       if line.startswith(("traffic_bytes_per_launch:", "kernel_sources_sha256:")))
     except OSError:
         return None
@@ -117,11 +123,49 @@ def measured_traffic(k):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(prob, n_steps, gpu_phi):
-    """The oracle's OCI (per-region LU + multi-right-hand-side solves) timed on
-    the host for the first n_steps of the workload."""
+def on_box_peaks(torch):
+    """Achievable rates on this GPU: a 2 GiB device-to-device copy (read +
+    written bytes per second, far past the 256 MB last-level cache) and an
+    8192^3 FP64 matrix product (rocBLAS on the FP64 matrix cores), best of 5
+    after a warm-up."""
+    n = (2 << 30) // 8
+    src = torch.rand(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    copy_gbs = 2 * n * 8 / best / 1e9
+    del src, dst
+    m = 8192
+    a = torch.rand((m, m), dtype=torch.float64, device="cuda")
+    b = torch.rand((m, m), dtype=torch.float64, device="cuda")
+    best = float("inf")
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c = a @ b
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"hbm_copy_gbs": copy_gbs, "fp64_gemm_tflops": 2.0 * m ** 3 / best / 1e12,
+            "spec_hbm_gbs": PEAK_HBM_GBS, "spec_fp64_mfma_tflops": PEAK_FP64_MFMA_TFLOPS,
+            "how": "2 GiB device copy (read + written bytes) and an 8192^3 FP64 torch "
+                   "matmul, best of 5 after a warm-up"}
+
+
+def cpu_baseline(prob, n_steps):
+    """The oracle's OCI (per-region LU + multi-right-hand-side solves) timed
+    on the host for the first n_steps of the workload at its tolerance, then
+    (untimed) the first step continued to e <= 1e-13 as the converged FP64
+    reference.  Returns (cpu_baseline record, oracle steps, converged phi of
+    the first step)."""
     from oracle import oci as ooci
-    from oracle.problem import cell_data
+    from oracle.problem import cell_data, initial_edge_state
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -133,53 +177,96 @@ def cpu_baseline(prob, n_steps, gpu_phi):
     dt = time.perf_counter() - t0
     its = sum(r["iterations"] for r in res)
     updates = its * cd.J * cd.n
-    err = None
-    if gpu_phi is not None:
-        err = max(float(np.max(np.abs(gpu_phi[k] - res[k]["phi"])) / np.max(np.abs(res[k]["phi"])))
-                  for k in range(n_steps))
-    return {"value": updates / dt, "unit": "cell·angle updates/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": "first %d of %d time steps of the same workload (%d iterations, %.1f s), "
-                      "operator factorisation included" % (n_steps, prob.n_steps, its, dt),
-            "host_cpu_count": os.cpu_count()}, err
+    f = ooci.RegionFactors(cd)
+    conv = ooci.oci_step(cd, f, initial_edge_state(prob, cd), res[0]["psi"], 1e-13, 1000)
+    rec = {"value": updates / dt, "unit": "cell·angle updates/s", "cores": int(threads),
+           "kind": "oracle",
+           "sample": "first %d of %d time steps of the same workload at tol %g (%d iterations, "
+                     "%.1f s), operator factorisation included" % (
+                         n_steps, prob.n_steps, prob.tol, its, dt),
+           "host_cpu_count": os.cpu_count()}
+    return rec, res, conv["phi"]
 
 
-def large_case(oci, torch, stream):
-    """The 64-region, 200,000-cell S_64 problem (50 steps, tol 1e-6), where an
-    iteration moves 634 MB: plain FP64 and mixed ms per time step, and the
-    iteration kernel's per-launch time against the HBM roofline (the
-    structured apply does O(N) work per cell; its MFMA part, the 4 scalar-flux
-    rows, is 4 * 2N * 2 flop per cell)."""
-    from paper_2305_13555_amd import workloads
-    prob = workloads.config3()
-    J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
-    out = {"workload": prob.name + ", tol 1e-6"}
-    for prec, key in ((oci.OCI_PREC_FP64, "plain_fp64"), (oci.OCI_PREC_FP32, "mixed")):
-        with oci.OciContext(prob, stream=stream, precision=prec) as cx:
-            cx.solve(T)
-            torch.cuda.synchronize()
-            cx.set_state(None, 0)
-            t = time.perf_counter()
-            rc, infos = cx.solve(T)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t) * 1e3 / T
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def timed_solves(oci, torch, ctx, prob, phi_dev, n, refactor=True):
+    """n full solves of prob on ctx (operator rebuild, reset, all steps);
+    returns (wall seconds, infos of every solve)."""
+    T = prob.n_steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = []
+    for _ in range(n):
+        if refactor:
+            ctx.refactor(prob)
+        ctx.set_state(None, 0)
+        rc, infos = ctx.solve(T, phi_dev)
         if rc < 0 or any(i["status"] != oci.OCI_OK for i in infos):
-            raise RuntimeError("large-case solve failed: rc=%d" % rc)
-        out[key] = {"ms_per_time_step": ms,
-                    "iterations_per_step": float(np.mean([i["iterations"] for i in infos])),
-                    "launches_per_step": float(np.mean([i["launches"] for i in infos]))}
-    out["mixed_speedup"] = out["plain_fp64"]["ms_per_time_step"] / out["mixed"]["ms_per_time_step"]
-    t, k = roofline_launch_seconds(oci, prob, stream, steps=5, hi_launches=8, lo_launches=4)
+            raise RuntimeError("solve failed: rc=%d" % rc)
+        out.append(infos)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def si_steps(oci, prob, stream, tol, n=5):
+    """Source iteration step by step on the same problem: ms and sweeps per step."""
+    with oci.OciContext(prob, stream=stream, tol=tol) as cs:
+        ms, its = [], []
+        for _ in range(n):
+            rc, info = cs.si_step()
+            ms.append(info["ms"])
+            its.append(info["iterations"])
+    return float(np.mean(ms)), float(np.mean(its))
+
+
+def secondary_case(oci, torch, stream, steps=5):
+    """The 10,000-cell S_32 problem (16 regions, 100 steps, tol 1e-10): plain
+    FP64 OCI updates/s and ms per step, the iteration kernel's roofline,
+    source iteration and the OCI/SI speedup, mixed precision, and the scalar
+    flux against the oracle on the first 3 steps."""
+    from paper_2305_13555_amd import workloads
+    from oracle import oci as ooci
+    from oracle.problem import cell_data
+    prob = workloads.config2()
+    J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
+    phi = torch.zeros((T, J, 4), dtype=torch.float64, device="cuda")
+    with oci.OciContext(prob, stream=stream) as ctx:
+        timed_solves(oci, torch, ctx, prob, phi, 2)
+        wall, infos = timed_solves(oci, torch, ctx, prob, phi, steps)
+        shape = ctx.iterates_per_launch
+    iters = sum(i["iterations"] for inf in infos for i in inf)
+    ms_step = wall * 1e3 / (steps * T)
+    t, k = roofline_launch_seconds(oci, prob, stream)
     nbytes = algorithmic_bytes_per_cell_iteration(N) * J * k
-    flops = 2.0 * 4 * (2 * N) * J * k
-    out["iteration_kernel"] = {
-        "kernel": ITERATION_KERNELS[k], "iterations_per_launch": k,
-        "us_per_launch": t * 1e6, "bytes_per_launch": nbytes,
-        "hbm_gbs": nbytes / t / 1e9, "hbm_frac": nbytes / t / 1e9 / PEAK_HBM_GBS,
-        "mfma_frac": flops / t / 1e12 / PEAK_FP64_MFMA_TFLOPS,
-        "roofline_us": nbytes / (PEAK_HBM_GBS * 1e9) * 1e6,
+    si_ms, si_its = si_steps(oci, prob, stream, prob.tol, 10)
+    with oci.OciContext(prob, stream=stream, precision=oci.OCI_PREC_FP32) as cm:
+        timed_solves(oci, torch, cm, prob, phi, 1)
+        mwall, _ = timed_solves(oci, torch, cm, prob, phi, 2)
+    ref = ooci.run_oci(prob, cell_data(prob), 3, tol=prob.tol, max_iters=prob.max_iters)
+    with oci.OciContext(prob, stream=stream) as ctx:
+        ctx.solve(3, phi)
+    got = phi[:3].cpu().numpy()
+    mixed_ms = mwall * 1e3 / (2 * T)
+    return {
+        "workload": prob.name + ", tol 1e-10",
+        "cell_angle_updates_per_s": iters * J * N / wall,
+        "oci_ms_per_time_step": ms_step,
+        "iterations_per_time_step": iters / (steps * T),
+        "iterates_per_launch": shape,
+        "iteration_kernel": {"kernel": ITERATION_KERNELS[k], "us_per_launch": t * 1e6,
+                             "bytes_per_launch": nbytes,
+                             "hbm_frac": nbytes / t / 1e9 / PEAK_HBM_GBS,
+                             "traffic": measured_traffic(k, "c2")},
+        "si_ms_per_time_step": si_ms, "si_iterations_per_time_step": si_its,
+        "oci_over_si_speedup": si_ms / ms_step,
+        "mixed_ms_per_time_step": mixed_ms,
+        "mixed_speedup_vs_plain": ms_step / mixed_ms,
+        "parity_vs_oracle_rel_first_3_steps": max(rel_err(got[i], ref[i]["phi"])
+                                                  for i in range(3)),
     }
-    return out
 
 
 def learned_case(oci, torch):
@@ -189,9 +276,7 @@ def learned_case(oci, torch):
     first 16 iterates and the converged flux of each step); the corrector is
     trained on 4 steps (full-batch Adam, 400 epochs) and evaluated on the
     held-out fifth: max-norm error of the scalar flux after l plain iterates
-    and after the same iterates plus the predicted correction.  The same
-    evaluation on the bench workload (about 7 iterations to 1e-13) shows
-    where the correction does not pay."""
+    and after the same iterates plus the predicted correction."""
     from paper_2305_13555_amd import corrector as C
     from paper_2305_13555_amd import workloads
 
@@ -222,11 +307,6 @@ def learned_case(oci, torch):
     k, losses, sec, nb = fit(hist[:4], ls)
     rows = C.evaluate(torch, k, hist[4][0], hist[4][1], ls)
     k.close()
-    c2 = workloads.config2()
-    hist2 = histories(c2, 5, 6)
-    k2, losses2, sec2, nb2 = fit(hist2[:4], [3, 4, 5, 6])
-    rows2 = C.evaluate(torch, k2, hist2[4][0], hist2[4][1], [3, 4, 5, 6])
-    k2.close()
     pick = lambda r: {"l": r["l"], "plain": r["plain"], "corrected": r["corrected"]}
     return {
         "workload": slab.name + ", 5 steps (4 train, 1 held out)",
@@ -235,7 +315,6 @@ def learned_case(oci, torch):
         "loss_first_last": [losses[0], losses[-1]],
         "heldout": [pick(r) for r in rows if r["l"] in (3, 8, 16)],
         "heldout_error_ratio_mean": float(np.mean([r["corrected"] / r["plain"] for r in rows])),
-        "bench_workload_heldout": [pick(r) for r in rows2],
         "applied_in_iteration": False,
     }
 
@@ -280,53 +359,21 @@ def ensemble_case(oci, torch, n_problems=32):
             c.close()
 
 
-def mixed_precision(oci, torch, prob, stream, plain_phi, plain_ms):
-    """The same solve with OCI_PREC_FP32 (FP64 defect correction, FP32 inner
-    iterations): ms per time step at tol 1e-10 and at 1e-6 (each after a
-    warm-up solve), FP64 iterates and all iteration launches per step, and
-    the largest relative difference of its scalar flux to the plain solve."""
-    J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
-    phi = torch.zeros((T, J, 4), dtype=torch.float64, device="cuda")
-    out = {}
-    for tol, key in ((prob.tol, "tol_1e-10"), (1e-6, "tol_1e-6")):
-        with oci.OciContext(prob, stream=stream, tol=tol, precision=oci.OCI_PREC_FP32) as cm:
-            cm.solve(T, phi)
-            torch.cuda.synchronize()
-            cm.set_state(None, 0)
-            t = time.perf_counter()
-            rc, infos = cm.solve(T, phi)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t) * 1e3 / T
-        if rc < 0 or any(i["status"] != oci.OCI_OK for i in infos):
-            raise RuntimeError("mixed-precision solve failed: rc=%d" % rc)
-        launches = float(np.mean([i["launches"] for i in infos]))
-        out[key] = {"ms_per_time_step": ms,
-                    "fp64_iterations_per_step": float(np.mean([i["iterations"] for i in infos])),
-                    "launches_per_step": launches,
-                    "cell_angle_updates_per_s": launches * J * N / (ms * 1e-3)}
-        if key == "tol_1e-10":
-            got = phi.cpu().numpy()
-            out[key]["rel_vs_plain_fp64"] = max(
-                float(np.max(np.abs(got[k] - plain_phi[k])) / np.max(np.abs(plain_phi[k])))
-                for k in range(T))
-            out[key]["speedup_vs_plain"] = plain_ms / ms
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 200,000-cell S_64 comparison, the ensemble and the "
-                         "learned corrector")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 10,000-cell S_32 problem, the ensemble and the corrector")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the k_oci_iterate roofline batches and a 64 MiB copy "
-                         "(for hardware-counter runs)")
-
+                    help="only the iteration kernel's roofline batches on the workload and a "
+                         "64 MiB copy (for hardware-counter runs)")
+    ap.add_argument("--workload", choices=["large", "bench16"], default="large",
+                    help="with --roofline-only: the 200,000-cell S_64 problem or the "
+                         "10,000-cell S_32 one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the OCI path here is single-GPU "
@@ -337,84 +384,77 @@ def main():
     from paper_2305_13555_amd import oci, workloads
 
     torch.cuda.set_device(0)
-    prob = workloads.config2()
-    J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
     stream = torch.cuda.current_stream()
     if args.roofline_only:
+        prob = workloads.config3() if args.workload == "large" else workloads.config2()
         t, k = roofline_launch_seconds(oci, prob, stream, steps=3)
         nbytes = copy_calibration(torch, 64)
-        b = algorithmic_bytes_per_cell_iteration(N) * J * k
-        print(json.dumps({"kernel": ITERATION_KERNELS[k], "us_per_launch": t * 1e6,
-                          "algorithmic_bytes_per_launch": b, "GB/s": b / t / 1e9,
-                          "copy_bytes": nbytes}))
+        b = algorithmic_bytes_per_cell_iteration(prob.n_angles) * prob.n_cells * k
+        print(json.dumps({"workload": prob.name, "kernel": ITERATION_KERNELS[k],
+                          "us_per_launch": t * 1e6, "algorithmic_bytes_per_launch": b,
+                          "GB/s": b / t / 1e9, "copy_bytes": nbytes}))
         return
+
+    prob = workloads.config3()
+    J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
+    print("bench: %s, tol %g" % (prob.name, prob.tol), file=sys.stderr, flush=True)
+    from paper_2305_13555_amd import tune
     ctx = oci.OciContext(prob, stream=stream)
     phi_dev = torch.zeros((T, J, 4), dtype=torch.float64, device="cuda")
-
-    def one_solve():
-        ctx.refactor(prob)
-        ctx.set_state(None, 0)
-        rc, infos = ctx.solve(T, phi_dev)
-        if rc < 0 or any(i["status"] != oci.OCI_OK for i in infos):
-            raise RuntimeError("solve failed: rc=%d" % rc)
-        return infos
-
-    for _ in range(args.warmup):
-        one_solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    all_infos = []
-    for _ in range(args.steps):
-        all_infos.append(one_solve())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
+    # the launch configuration from the autotuner (short solves from the
+    # initial state), then the warm-up and timed full solves
+    shape, shape_ms = tune.tune(ctx, torch, n_steps=8, repeats=2, use_cache=False)
+    timed_solves(oci, torch, ctx, prob, phi_dev, args.warmup)
+    wall, all_infos = timed_solves(oci, torch, ctx, prob, phi_dev, args.steps)
     iters = sum(i["iterations"] for infos in all_infos for i in infos)
     value = iters * J * N / wall
-    gpu_phi = phi_dev.cpu().numpy()
-    per_launch_s, k_launch = roofline_launch_seconds(oci, prob, stream)
+    plain_ms = wall * 1e3 / (args.steps * T)
+    plain_phi = phi_dev[:max(args.cpu_steps, 1)].cpu().numpy()
+    bounds = [i["err_bound"] for i in all_infos[-1]]
+    print("bench: plain %.4f ms per time step" % plain_ms, file=sys.stderr, flush=True)
+
+    # mixed precision, same workload and stopping rule
+    nm = max(args.steps // 2, 1)
+    with oci.OciContext(prob, stream=stream, precision=oci.OCI_PREC_FP32) as cm:
+        inner, inner_ms = tune.tune(cm, torch, n_steps=8, repeats=2, use_cache=False)
+        timed_solves(oci, torch, cm, prob, phi_dev, 1)
+        mwall, minfos = timed_solves(oci, torch, cm, prob, phi_dev, nm)
+    mixed_ms = mwall * 1e3 / (nm * T)
+    mixed_phi = phi_dev[:1].cpu().numpy()
+    print("bench: mixed %.4f ms per time step" % mixed_ms, file=sys.stderr, flush=True)
+
+    # the iteration kernel the timed solves run most: a step's first iterate
+    # comes with the previous step's end, the rest in launches of up to the
+    # launch shape
+    k_main = max(1, min(ctx.iterates_per_launch,
+                        max(i["iterations"] for i in all_infos[-1]) - 1))
+    per_launch_s, k_launch = roofline_launch_seconds(oci, prob, stream, steps=5, k=k_main)
     kernel = ITERATION_KERNELS[k_launch]
     bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J * k_launch
     achieved = bytes_launch / per_launch_s / 1e9
+    si_ms, si_its = si_steps(oci, prob, stream, prob.tol, 5)
 
-    # time to a 1e-6 error bound per step (whole solve at tol 1e-6 with the
-    # strict rule: e <= tol and e * rho / (1 - rho) <= tol), and source
-    # iteration step by step, same problem (at the bench tolerance and to 1e-6)
-    with oci.OciContext(prob, stream=stream, tol=1e-6, strict=True) as c6:
-        c6.solve(T, phi_dev)
-        torch.cuda.synchronize()
-        c6.set_state(None, 0)
-        t = time.perf_counter()
-        rc6, inf6 = c6.solve(T, phi_dev)
-        torch.cuda.synchronize()
-        t6_ms = (time.perf_counter() - t) * 1e3 / T
-        t6_its = float(np.mean([i["iterations"] for i in inf6]))
-    mixed = mixed_precision(oci, torch, prob, stream, gpu_phi, wall * 1e3 / (args.steps * T))
-    large = None if args.no_large else large_case(oci, torch, stream)
-    ensemble = None if args.no_large else ensemble_case(oci, torch)
-    learned = None if args.no_large else learned_case(oci, torch)
-    # the launch-shape autotuner on the bench workload (reported; the timed
-    # solves above use the library's default shape)
-    from paper_2305_13555_amd import tune
-    with oci.OciContext(prob, stream=stream) as ct:
-        shape, shape_ms = tune.tune(ct, torch, n_steps=8, repeats=3, use_cache=False)
-    def si_steps(tol):
-        with oci.OciContext(prob, stream=stream, tol=tol) as cs:
-            ms, its = [], []
-            for _ in range(10):
-                rc, info = cs.si_step()
-                ms.append(info["ms"])
-                its.append(info["iterations"])
-        return float(np.mean(ms)), float(np.mean(its))
-
-    si_ms, si_its = si_steps(prob.tol)
-    si6_ms, si6_its = si_steps(1e-6)
-    oci_ms = wall * 1e3 / (args.steps * T)
-
-    cpu, err = (None, None)
+    cpu, parity = None, None
     if not args.no_cpu:
-        ncpu = min(args.cpu_steps, T)
-        cpu, err = cpu_baseline(prob, ncpu, gpu_phi[:ncpu])
+        ncpu = max(1, min(args.cpu_steps, T))
+        print("bench: oracle on the first %d steps" % ncpu, file=sys.stderr, flush=True)
+        cpu, ref, conv = cpu_baseline(prob, ncpu)
+        parity = {
+            "plain_vs_oracle_same_rule_rel": [rel_err(plain_phi[i], ref[i]["phi"])
+                                              for i in range(ncpu)],
+            "plain_iterations": [i["iterations"] for i in all_infos[-1][:ncpu]],
+            "oracle_iterations": [r["iterations"] for r in ref],
+            "plain_vs_converged_oracle_rel_step1": rel_err(plain_phi[0], conv),
+            "mixed_vs_converged_oracle_rel_step1": rel_err(mixed_phi[0], conv),
+            "converged_reference": "oracle OCI, first step continued to e <= 1e-13",
+        }
+    peaks = on_box_peaks(torch)
+    secondary = ensemble = learned = None
+    if not args.no_secondary:
+        print("bench: secondary cases", file=sys.stderr, flush=True)
+        secondary = secondary_case(oci, torch, stream)
+        ensemble = ensemble_case(oci, torch)
+        learned = learned_case(oci, torch)
 
     line = {
         "metric": METRIC,
@@ -430,12 +470,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "plain FP64 OCI vs SI: %s; sigma_t lognormal(0,1) clipped to "
-                        "[0.01, 10] with dx = 1, c ~ U[0.5, 0.99], Q ~ U[0, 1], dt = 0.05, "
-                        "v = 1, tol 1e-10 (seeded)" % prob.name,
+            "workload": "plain FP64 OCI, %s; sigma_t lognormal(0,1) clipped to [0.01, 10] with "
+                        "dx = 1, c ~ U[0.5, 0.99], Q ~ U[0, 1], reflecting left / vacuum right, "
+                        "dt = 0.05, v = 1, tol 1e-6 (seeded)" % prob.name,
             "cells": J, "angles": N, "regions": prob.n_regions, "time_steps": T,
-            "tol": prob.tol, "step": "operator rebuild + %d time steps" % T,
-            "driver": "queued solve (one batch of iteration launches per step)",
+            "tol": prob.tol, "step": "operator rebuild + %d time steps (one full solve)" % T,
+            "driver": "queued solve (whole steps replayed from cached HIP graphs)",
         },
         "roofline": {
             "bound": "hbm",
@@ -444,30 +484,37 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": measured_traffic(k_launch),
+            "traffic": measured_traffic(k_launch, "c3"),
             "bytes_per_launch": bytes_launch,
             "us_per_launch": per_launch_s * 1e6,
             "iterations_per_launch": k_launch,
-            "measured": "(median step time at 8 full launches - at 4) / 4, "
-                        "9 steps each (launch to launch, dispatch gap included)",
+            "measured": "(median step time at 2 full launches - at 1) (at 4 - at 2 for "
+                        "fewer than 3 iterates per launch), 5 steps each, HIP events on the "
+                        "library's stream (launch to launch, dispatch gap included)",
         },
         "cpu_baseline": cpu,
+        "time_to_1e-6_ms_per_step": {"plain_fp64": plain_ms, "mixed": mixed_ms,
+                                     "learned": None},
+        "mixed_speedup_vs_plain": plain_ms / mixed_ms,
         "iterations_per_time_step": iters / (args.steps * T),
-        "oci_ms_per_time_step": oci_ms,
-        "time_to_1e-6_ms_per_step": t6_ms,
-        "time_to_1e-6_iterations_per_step": t6_its,
+        "mixed_fp64_iterations_per_time_step": float(np.mean(
+            [i["iterations"] for inf in minfos for i in inf])),
+        "mixed_launches_per_time_step": float(np.mean(
+            [i["launches"] for inf in minfos for i in inf])),
+        "plain_err_bound_max": max(bounds),
+        "autotuned": {"iterates_per_launch": shape,
+                      "iterates_per_launch_ms_per_step": {str(k): v for k, v in shape_ms.items()},
+                      "mixed_inner_iterations": inner,
+                      "mixed_inner_ms_per_step": {str(k): v for k, v in inner_ms.items()},
+                      "how": "8-step solves from the initial state, best of 2 per candidate"},
+        "parity_vs_oracle": parity,
         "si_ms_per_time_step": si_ms,
         "si_iterations_per_time_step": si_its,
-        "si_time_to_1e-6_ms_per_step": si6_ms,
-        "si_time_to_1e-6_iterations_per_step": si6_its,
-        "oci_over_si_speedup": si_ms / oci_ms,
-        "parity_vs_oracle_rel": err,
-        "mixed": mixed,
-        "large_case": large,
+        "oci_over_si_speedup": si_ms / plain_ms,
+        "on_box_peaks": peaks,
+        "bench16": secondary,
         "ensemble": ensemble,
         "learned": learned,
-        "launch_shape_tuning": {"default": ctx.iterates_per_launch, "chosen": shape,
-                                "ms_per_time_step": {str(k): v for k, v in shape_ms.items()}},
     }
     print(json.dumps(line))
     ctx.close()

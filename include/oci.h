@@ -230,6 +230,19 @@ int oci_iterates_per_launch(const oci_ctx *c);
  * effect), or OCI_EINVAL for NULL or k < 2. */
 int oci_set_iterates_per_launch(oci_ctx *c, int32_t k);
 
+/* Mixed precision (OCI_PREC_FP32): FP32 inner iterations per correction.
+ * By default the count is searched while a solve runs (doubled when a window
+ * of queued steps needs four or more FP64 iterates per step, else lowered by
+ * one until that costs an FP64 iterate).  oci_set_inner_iterations with m in
+ * [1, 64] fixes it (a tuning knob: the accepted iterates are still FP64
+ * iterates judged by the stopping rule; only their number and the work between
+ * them change), m = 0 returns to the search from the current count.  Waits
+ * for the context's stream when the count changes (cached step graphs are
+ * rebuilt).  Both return the count in effect, 0 for an FP64 context, or
+ * OCI_EINVAL (NULL, m outside [0, 64]). */
+int oci_inner_iterations(const oci_ctx *c);
+int oci_set_inner_iterations(oci_ctx *c, int32_t m);
+
 /* Per-region operator, for inspection and tests: [2N+4+2N][4N+1] row-major,
  * rows = (outgoing flux 2N, phi 4, psi_edge 2N), columns = (incident flux 2N,
  * psi_{k-1/2} 2N, source 1), i.e. the needed rows of (A - S)^{-1} applied to

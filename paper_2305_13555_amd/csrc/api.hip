@@ -98,6 +98,7 @@ struct oci_ctx {
   // before a trial decrease and what it gave, no further decreases
   int m_q = 0, m_prev = 0, m_prev_q = 0;
   bool m_locked = false;
+  bool m_fixed = false;   // set by oci_set_inner_iterations: no search
   float *d_fi32 = nullptr, *d_dlt = nullptr, *d_dphi32 = nullptr;
   size_t lds_in = 0;
   // kernels for the chosen operator batch width CH
@@ -105,7 +106,7 @@ struct oci_ctx {
   void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr, *fn_inner = nullptr;
   void *fn_iter2 = nullptr;   // two iterates per launch (plain FP64 batches)
   size_t lds_it2 = 0;
-  void *fn_iterK[5] = {};     // [3], [4]: three and four iterates per launch (N = 8, 16, 32)
+  void *fn_iterK[5] = {};     // [3], [4]: three and four iterates per launch (N = 8 .. 64)
   size_t lds_itK[5] = {};
   int kimax = 2;              // most iterates per launch (the active cap)
   int kibuilt = 2;            // most iterates per launch this problem allows
@@ -639,12 +640,14 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
 #undef OCI_KERNEL
 #undef OCI_PICK
   c->fn_inner = s.tiles_in_args ? (void *)k_oci_inner<true> : (void *)k_oci_inner<false>;
-  // three and four iterates per launch: built for N = 8, 16, 32 (from N = 64
-  // on, the two LDS blocks and the staged halo data need more than 64 KiB)
+  // three and four iterates per launch: built for N = 8, 16, 32 and 64 (from
+  // N = 128 on the two LDS row blocks alone leave room for one work-group
+  // per CU)
 #define OCI_KERNELK(ARGT, KI)                                                   \
   (N == 8     ? (void *)k_oci_iterateK<4, ARGT, true, 8, KI>                    \
    : N == 16  ? (void *)k_oci_iterateK<8, ARGT, true, 16, KI>                   \
    : N == 32  ? (void *)k_oci_iterateK<16, ARGT, true, 32, KI>                  \
+   : N == 64  ? (void *)k_oci_iterateK<16, ARGT, true, 64, KI>                  \
               : nullptr)
   // (the halo cells of a tile in its own region or the next one on their
   // side: no region narrower than ki-1 cells)
@@ -652,15 +655,17 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   for (int ki = 3; ki <= 4 && min_cells >= ki - 1; ++ki) {
     c->fn_iterK[ki] = s.tiles_in_args ? (ki == 3 ? OCI_KERNELK(true, 3) : OCI_KERNELK(true, 4))
                                       : (ki == 3 ? OCI_KERNELK(false, 3) : OCI_KERNELK(false, 4));
-    // two row blocks, then the operator rows and pair coefficients of three
-    // regions and the halo cells' step constants
-    c->lds_itK[ki] = ((size_t)2 * (kTileCells + 2 * ki) * (2 * N + 2) + 60 * N +
+    // two row blocks, then the halo data: up to N = 32 the operator rows and
+    // pair coefficients of three regions, from N = 64 on the tile's operator
+    // rows only; and the halo cells' step constants
+    const size_t halo_tables = N >= 64 ? (size_t)8 * N : (size_t)60 * N;
+    c->lds_itK[ki] = ((size_t)2 * (kTileCells + 2 * ki) * (2 * N + 2) + halo_tables +
                       (size_t)2 * (ki - 1) * (2 * N + 4)) * sizeof(double);
     hipFuncAttributes fa{};
-    // (at most 64 KiB of LDS, so that two or more work-groups share a CU:
-    // with fewer, the longer launches stop paying for themselves)
+    // (at most 80 KiB of LDS, so that two work-groups share a CU's 160 KiB:
+    // with one, the longer launches stop paying for themselves)
     if (c->fn_iterK[ki] && hipFuncGetAttributes(&fa, (const void *)c->fn_iterK[ki]) == hipSuccess &&
-        c->lds_itK[ki] + fa.sharedSizeBytes <= (size_t)64 * 1024) {
+        c->lds_itK[ki] + fa.sharedSizeBytes <= (size_t)80 * 1024) {
       OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iterK[ki],
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)c->lds_itK[ki]));
@@ -895,18 +900,20 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   void *bargs[] = {&c->sa};
   if (begin) e = add(c->fn_begin, c->W_pv, c->lds_pv, bargs);
   int rstep = c->rstep;
-  // plain OCI: the end of every step but the graph's last also computes
-  // iterate 1 of the next step (needs L >= 2, so that the next step still has
-  // a launch of its own to open it)
-  const bool fuse_ok = !c->mixed && L >= 2;
+  // the end of every step but the graph's last also computes iterate 1 of
+  // the next step (needs L >= 2, so that the next step still has a launch of
+  // its own to open it; mixed precision: FP64 iterate 1 with its defect, and
+  // the next step's first inner iteration opens it)
+  const bool fuse_ok = L >= 2;
   int last_n = 1;   // iterates of the step's last launch
   for (int s = 0; s < G && e == hipSuccess; ++s) {
     int h = (half + s) & 1;
     if (c->mixed) {
-      for (int o = 1; o <= L && e == hipSuccess; ++o) {
+      const int ostart = (s > 0 && fuse_ok) ? 2 : 1;
+      for (int o = ostart; o <= L && e == hipSuccess; ++o) {
         for (int i = 1; o > 1 && i <= m && e == hipSuccess; ++i) {
-          int ii = i, ly = i == m ? 2 * (o - 1) : 0;
-          void *iargs[] = {&c->sa, &ii, &ly, &h};
+          int ii = i, ly = i == m ? 2 * (o - 1) : 0, opens = (o == ostart && i == 1) ? 1 : 0;
+          void *iargs[] = {&c->sa, &ii, &ly, &h, &opens};
           e = add(c->fn_inner, c->W_it, c->lds_in, iargs);
         }
         int node = 2 * o - 1, cb = 0, nred = 1;
@@ -995,6 +1002,7 @@ static int step_launches(const oci_ctx *c, int batch) {
 // double them.  Otherwise try one fewer; if that costs FP64 iterates, go back
 // and stop decreasing.
 static void tune_inner(oci_ctx *c, int q, int m_used) {
+  if (c->m_fixed) return;
   if (m_used != c->m_inner) return;   // a window queued before the last change
   if (q >= 4) {
     if (c->m_inner < kMaxInner) c->m_inner = std::min(kMaxInner, 2 * c->m_inner);
@@ -1023,8 +1031,8 @@ static void tune_inner(oci_ctx *c, int q, int m_used) {
 // iterations, the last forming iterate lprev+1) and FP64 iterate lprev+2.
 static int launch_outer(oci_ctx *c, int lprev, int half) {
   for (int i = 1; i <= c->m_inner; ++i) {
-    int ii = i, ly = i == c->m_inner ? lprev + 1 : 0;
-    void *iargs[] = {&c->sa, &ii, &ly, &half};
+    int ii = i, ly = i == c->m_inner ? lprev + 1 : 0, opens = 0;
+    void *iargs[] = {&c->sa, &ii, &ly, &half, &opens};
     OCI_CK(c, hipLaunchKernel(c->fn_inner, dim3(c->grid), dim3(64 * c->W_it), iargs, c->lds_in,
                               c->stream));
   }
@@ -1409,6 +1417,24 @@ extern "C" int oci_set_iterates_per_launch(oci_ctx *c, int32_t k) {
     drop_step_graphs(c);   // the cached step graphs hold the old launch sequence
     c->kimax = v;
   }
+  return v;
+}
+
+extern "C" int oci_inner_iterations(const oci_ctx *c) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  return c->mixed ? c->m_inner : 0;
+}
+
+extern "C" int oci_set_inner_iterations(oci_ctx *c, int32_t m) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (m < 0 || m > kMaxInner) return fail(c, OCI_EINVAL, "inner iterations must be in [0, 64]");
+  if (!c->mixed) return 0;
+  const int v = m == 0 ? c->m_inner : m;
+  if (v != c->m_inner) drop_step_graphs(c);   // cached graphs hold the old sequence
+  c->m_inner = v;
+  c->m_fixed = m != 0;
+  c->m_q = c->m_prev = c->m_prev_q = 0;
+  c->m_locked = false;
   return v;
 }
 

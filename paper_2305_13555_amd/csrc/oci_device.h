@@ -270,7 +270,19 @@ __device__ inline void rec_finish(const RecRegs &r, const double2 *rec, int n, d
     d = nan_max(d, r.v[q].x);
     f = nan_max(f, r.v[q].y);
   }
-  for (int i = threadIdx.x + kRecBatch * blockDim.x; i < n; i += blockDim.x) {
+  // the rest eight records per thread at a time (eight loads in flight)
+  int i = threadIdx.x + kRecBatch * blockDim.x;
+  for (; i + 7 * (int)blockDim.x < n; i += 8 * blockDim.x) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = rec[i + u * blockDim.x];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      d = nan_max(d, v[u].x);
+      f = nan_max(f, v[u].y);
+    }
+  }
+  for (; i < n; i += blockDim.x) {
     const double2 v = rec[i];
     d = nan_max(d, v.x);
     f = nan_max(f, v.y);

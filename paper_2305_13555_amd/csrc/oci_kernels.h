@@ -143,7 +143,7 @@ __global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rstep,
 // previous launch's iterates, whose residuals the extra work-group reduces.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_oci_iterate2(StepArgs a, int node, int cb, int half, int nred);
-// Iterates l .. l+KI-1 in one launch (KI = 3, 4; built for N = 8, 16, 32).
+// Iterates l .. l+KI-1 in one launch (KI = 3, 4; built for N = 8, 16, 32, 64).
 template <int CH, bool ARGT, bool VEC, int NF, int KI>
 __global__ void k_oci_iterateK(StepArgs a, int node, int cb, int half, int nred);
 // mode bit 0: the e of the trailing iterates are already in dec (k_reduce_rec
@@ -156,10 +156,11 @@ __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int
                            int rstep, int mode);
 __global__ void k_reduce_rec(StepArgs a, int l, int n, int half);
 // FP32 inner iteration i (1-based) of a mixed-precision step; ly > 0: the last
-// one, which also forms FP64 iterate ly (the FP64 iterate ly-1 read plus the
-// correction).
+// one, which also forms FP64 iterate ly (the point iterate ly-1 started from
+// plus the correction); opens: the step's first launch (its FP64 iterate 1
+// came with the previous end of step).
 template <bool ARGT>
-__global__ void k_oci_inner(StepArgs a, int i, int ly, int half);
+__global__ void k_oci_inner(StepArgs a, int i, int ly, int half, int opens);
 // si.hip
 __global__ void k_si_maps(SiArgs a, int node, int cb);
 __global__ void k_si_sweep(SiArgs a, int node, int cb);

@@ -887,9 +887,9 @@ __device__ __forceinline__ void mirror_row(double *ghost, const double *cell, in
 // wave 0 with h into phif and stored to phi_out; the residual record's lane
 // values against po (|change|, |value|) go to rv[0..63], rv[64..127] in LDS
 // for flush_records.  Returns wave 0's value for its (cell, component).
-template <int CH, bool VEC, int NF>
+template <int CH, bool VEC, int NF, int NP = kPhiPre>
 __device__ inline double own_phi(const StepArgs &a, const TileDev &t, const double *base,
-                                 const double (&fp)[kPhiPre], double hv, double po,
+                                 const double (&fp)[NP], double hv, double po,
                                  double *phis, double *phif, double *phi_out, double *rv) {
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
@@ -905,8 +905,8 @@ __device__ inline double own_phi(const StepArgs &a, const TileDev &t, const doub
                        (size_t)prt * KS * 64;
     const double *ap = base + (kq < 2 ? col + 2 : col) * P + kq * KS;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    mma_quads<kPhiPre, VEC>(acc, fp, kb, ke, ap, KS);
-    for (int b = kb + kPhiPre; b < ke; b += CH) {
+    mma_quads<NP, VEC>(acc, fp, kb, ke, ap, KS);
+    for (int b = kb + NP; b < ke; b += CH) {
       double f[CH];
       load_frags<CH>(f, Fp, b, ke);
       mma_quads<CH, VEC>(acc, f, b, ke, ap, KS);
@@ -954,10 +954,10 @@ __device__ inline void flush_records(const StepArgs &a, int l, int n, int half, 
 // Outgoing pairs of one iterate of the own cells (this thread's angle and
 // cells) from the rows at `base` (row 0 = cell c0-1) and phif, to dst and,
 // when given, to the LDS rows at `keep` (same layout as base).
-template <int NF>
+template <int NF, int NG = kGPre>
 __device__ inline void own_pairs(const StepArgs &a, const TileDev &t, const double *base,
                                  const double *phif, const double (&cf)[12],
-                                 const double (&gq)[kGPre][2], double *dst, double *keep) {
+                                 const double (&gq)[NG][2], double *dst, double *keep) {
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
   const int ghp = (NF ? (2 * NF + 4 + 15) / 16 : a.Mt) * 16;
   const PairMap pm(N);
@@ -972,9 +972,15 @@ __device__ inline void own_pairs(const StepArgs &a, const TileDev &t, const doub
     const double f0 = ph[0], f1 = ph[1], f2 = ph[2], f3 = ph[3];
     const size_t cell = (size_t)(t.c0 + cl);
     double g0, g1;
-    if (j < kGPre) {
-      g0 = gq[j < kGPre ? j : 0][0];
-      g1 = gq[j < kGPre ? j : 0][1];
+    if (j < NG) {   // (entry j by selects: a run-time index would put gq in scratch)
+      g0 = gq[0][0];
+      g1 = gq[0][1];
+#pragma unroll
+      for (int i = 1; i < NG; ++i)
+        if (i == j) {
+          g0 = gq[i][0];
+          g1 = gq[i][1];
+        }
     } else {
       g0 = a.gh[cell * ghp + 2 * m];
       g1 = a.gh[cell * ghp + 2 * m + 1];
@@ -1118,14 +1124,33 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
 // No level reads global memory: on this GPU a load issued after stores waits
 // for those stores to complete.
 
+//
+// From N = 64 on ("lean" staging) the three regions' tables would not leave
+// room for two work-groups per CU, so only the tile's own scalar-flux rows of
+// G are staged (HF [4][K]) and no coefficients (HC empty): every thread keeps
+// the coefficients of its angle in the tile's region in registers (a halo
+// pair's angle is the thread's own angle, since the work-group's thread count
+// is a multiple of N), and a halo cell in another region -- only tiles at a
+// region boundary have one -- reads its region's rows and coefficients from
+// memory.  Each thread also keeps the step constants of all its own cells and
+// each wave all its operator fragments in registers, so that the levels of
+// tiles inside a region read no global memory.
 template <int NF, int KI>
 struct HaloLds {
   static constexpr int K = 2 * NF;
-  static constexpr int nF = 12 * K, nC = 36 * NF, nG = 2 * (KI - 1) * (K + 4);
+  static constexpr int W = (2 * NF + 15) / 16 < 4 ? (2 * NF + 15) / 16 : 4;
+  static constexpr int threads = 64 * W;
+  static constexpr bool lean = NF >= 64;
+  static constexpr int nF = (lean ? 4 : 12) * K, nC = lean ? 0 : 36 * NF;
+  static constexpr int nG = 2 * (KI - 1) * (K + 4);
   static constexpr int total = nF + nC + nG;
-  static constexpr int threads = 64 * ((2 * NF + 15) / 16 < 4 ? (2 * NF + 15) / 16 : 4);
   // staged in pairs of doubles (every segment has even length and offset)
   static constexpr int per_thread = (total / 2 + threads - 1) / threads;
+  // step constants per thread (its cells) and operator fragments per wave
+  static constexpr int NG = lean ? kTileCells * NF / threads : kGPre;
+  static constexpr int NP = lean ? (K / 4) / W : kPhiPre;
+  static_assert(!lean || threads % NF == 0, "a halo pair's angle is the thread's angle");
+  static_assert(!lean || (K / 4) % (4 * W) == 0, "equal k-step shares per wave");
 };
 
 // Scalar flux of a halo cell from its neighbours' rows (left: cell c-1,
@@ -1192,11 +1217,14 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   const int cbase = t.c0 - KI;   // cell of LDS row 0
   auto row = [&](double *blk, int c) { return blk + (c - cbase) * P; };
   const int ghp = sh.Mt * 16;
-  double fp[kPhiPre], cf[12], gq[kGPre][2];   // (fp and cf: from the staged data, below)
+  constexpr bool LEAN = HL::lean;
+  constexpr int NG = HL::NG, NP = HL::NP;
+  double fp[NP], cf[12], gq[NG][2];   // (fp, and cf unless lean: from the staged data, below)
   const PairMap pm(N);
-  {   // (cf: from the staged coefficients of the tile's region, below)
+  if (LEAN) coef_load<12>(a, N, t.region, pm.m, 0, cf);
+  {
 #pragma unroll
-    for (int j = 0; j < kGPre; ++j) {
+    for (int j = 0; j < NG; ++j) {
       const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);
       {   // (a pair, 16-byte aligned: 2m is even and rows are 16 doubles apart)
         const double2 g2 =
@@ -1231,7 +1259,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
     double2 v = make_double2(0.0, 0.0);
     const double *g = nullptr;
     if (idx < HL::nF) {
-      const int rsl = idx / (4 * K), qk = idx - rsl * 4 * K;
+      const int rsl = LEAN ? 1 : idx / (4 * K), qk = LEAN ? idx : idx - rsl * 4 * K;
       g = a.phig + (size_t)rg(rsl) * 4 * K + qk;
     } else if (idx < HL::nF + HL::nC) {
       const int j = idx - HL::nF, rsl = j / (12 * N), cm = j - rsl * 12 * N;
@@ -1254,11 +1282,13 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   if ((int)threadIdx.x < NS) hsel[threadIdx.x] = my_sel;
   __syncthreads();
   if (stalled) return;
+  if (!LEAN) {
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {   // region slot 1: the tile's
-    const double2 v = reinterpret_cast<const double2 *>(HC + 12 * N)[i * N + pm.m];
-    cf[2 * i] = v.x;
-    cf[2 * i + 1] = v.y;
+    for (int i = 0; i < 6; ++i) {   // region slot 1: the tile's
+      const double2 v = reinterpret_cast<const double2 *>(HC + 12 * N)[i * N + pm.m];
+      cf[2 * i] = v.x;
+      cf[2 * i + 1] = v.y;
+    }
   }
   {   // this wave's MFMA fragments of the scalar-flux rows of G (the k-major
       // packing of its row tile: lane 16 kq + r holds row r, k = kq KS + ks;
@@ -1267,9 +1297,10 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
     phi_tile(N, &prt, &poff);
     phi_ksplit(KS, W, wave, &kb, &ke);
     const int r = (lane & 15) - poff, kq = lane >> 4;
+    const double *hf1 = HF + (LEAN ? 0 : 4 * K);   // the tile's region
 #pragma unroll
-    for (int q = 0; q < kPhiPre; ++q)
-      fp[q] = (r >= 0 && r < 4) ? HF[(4 + r) * K + kq * KS + min(kb + q, KS - 1)] : 0.0;
+    for (int q = 0; q < NP; ++q)
+      fp[q] = (r >= 0 && r < 4) ? hf1[r * K + kq * KS + min(kb + q, KS - 1)] : 0.0;
   }
   const bool gl = cbase <= -1, gr = t.c0 + t.nc + KI - 1 >= a.J;   // ghost rows in the block
   if (gl && a.bcl == kBcReflect) mirror_row(row(X, -1), row(X, 0), N, true);
@@ -1288,15 +1319,17 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
       const bool left = h < nl;
       const int c = left ? lo + h : t.c0 + t.nc + (h - nl);
       const int sl = left ? t.c0 - 1 - c : KI - 1 + c - (t.c0 + t.nc);
-      const double ph =
-          cell_phi<NF>(row(in, c - 1), row(in, c + 1), HF + hsel[sl] * 4 * K, HG + sl * (K + 4));
+      const int hs = hsel[sl];
+      const double *hf = LEAN ? (hs == 1 ? HF : a.phig + (size_t)rg(hs) * 4 * K)
+                              : HF + hs * 4 * K;
+      const double ph = cell_phi<NF>(row(in, c - 1), row(in, c + 1), hf, HG + sl * (K + 4));
       if ((lane & 15) == 0) hph[h][lane >> 4] = ph;
     }
     const int bl = ring_buf(a, lvl, half);
-    pl = own_phi<CH, VEC, NF>(a, t, row(in, t.c0 - 1), fp, hv, pl, phis, phif, phi_at(a, bl),
-                              rv + (s - 1) * 128);
-    own_pairs<NF>(a, t, row(in, t.c0 - 1), phif, cf, gq, out_at(a, bl),
-                  s < KI ? row(out, t.c0 - 1) : nullptr);
+    pl = own_phi<CH, VEC, NF, NP>(a, t, row(in, t.c0 - 1), fp, hv, pl, phis, phif,
+                                  phi_at(a, bl), rv + (s - 1) * 128);
+    own_pairs<NF, NG>(a, t, row(in, t.c0 - 1), phif, cf, gq, out_at(a, bl),
+                      s < KI ? row(out, t.c0 - 1) : nullptr);
     if (s == KI) {
       flush_records(a, l, KI, half, rv);
       open_step(a, l, cur, fb, stalled);
@@ -1309,12 +1342,22 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
       const int c = left ? lo + h : t.c0 + t.nc + (h - nl);
       const int sl = left ? t.c0 - 1 - c : KI - 1 + c - (t.c0 + t.nc);
       double cc[12];   // pairs of coefficients, pair-major
-      const double2 *hc = reinterpret_cast<const double2 *>(HC + hsel[sl] * 12 * N);
+      const int hs = hsel[sl];
+      if (LEAN) {   // (m is this thread's angle: its own region's are in cf)
+        if (hs == 1) {
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        const double2 v = hc[i * N + m];
-        cc[2 * i] = v.x;
-        cc[2 * i + 1] = v.y;
+          for (int i = 0; i < 12; ++i) cc[i] = cf[i];
+        } else {
+          coef_load<12>(a, N, rg(hs), m, 0, cc);
+        }
+      } else {
+        const double2 *hc = reinterpret_cast<const double2 *>(HC + hs * 12 * N);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          const double2 v = hc[i * N + m];
+          cc[2 * i] = v.x;
+          cc[2 * i + 1] = v.y;
+        }
       }
       const double *in2 = (2 * m >= N ? row(in, c - 1) : row(in, c + 1)) + 2 * m;
       const double i0 = in2[0], i1 = in2[1];
@@ -1538,11 +1581,12 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
   const int bl = ring_buf(a, L, half), bn = ring_buf(a, 1, half ^ 1);
   IterPrefetch<CH> pf;
   iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds, go, true);
+  // (mixed precision: iterate 1 is an FP64 iterate with its defect)
   iterate_compute<CH, VEC, NF>(pf, a, t, out_at(a, bl), out_at(a, bn), phi_at(a, bn), lds, phis,
                                phif,
                                reinterpret_cast<double2 *>(a.partial) +
                                    rec_slot(a, 1, half ^ 1) + blockIdx.x,
-                               false, false);
+                               false, rstep == 2);
   record();
 }
 
@@ -1560,18 +1604,29 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Inner iteration i of the current correction over a tile: delta_{i+1} =
-// G delta_i + d on v_mfma_f32_16x16x4f32 (lane l holds rows 4*(l/16) ..
-// 4*(l/16)+3 of column l%16 of the product: four consecutive cells of one
-// operator row).  delta_1 = d is buffer 0; the iterates alternate between
-// buffers 1 and 2.  With ly > 0 (the last inner iteration) the scalar-flux
-// rows are formed too and the FP64 iterate ly = (iterate ly-2, or the step's
-// start for ly = 2) + delta is written to ring buffer ly instead of delta.
+// Inner iteration i of the current correction over a tile, in the structured
+// form of the FP64 iteration without its constant part:
+//   e = H inc(delta_i)                 (the 4 scalar-flux rows of G, FP32 MFMA)
+//   delta_{i+1}[phi]   = d[phi] + e
+//   delta_{i+1}[out_m] = d[out_m] + (s A_m^{-1} rows) e + (|mu| A_m^{-1} rows) inc_m(delta_i)
+// (the same coefficients as the FP64 iteration, in FP32), so an inner
+// iteration moves 4 (6N + 8) bytes per cell.  delta_1 = d is buffer 0 of the
+// correction buffers; the iterates alternate between buffers 1 and 2.  With
+// ly > 0 (the last inner iteration) the FP64 iterate ly = (iterate ly-2, or
+// the step's start for ly = 2) + delta_{i+1} is written to ring buffer ly
+// instead of delta.  opens: the step's first launch (its iterate 1 came with
+// the previous end of step), which opens the step.  Lane l of
+// v_mfma_f32_16x16x4f32 holds rows 4 (l/16) ..
+// 4 (l/16) + 3 of column l%16 of the product: four consecutive cells of one
+// operator row.
+constexpr int kDPre = 4;   // cells per thread whose defect is loaded up front
 template <bool ARGT>
-__global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, int half) {
-  constexpr int kPre = 16;   // operator k-steps of the wave's first row tile loaded up front
+__global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, int half,
+                                                   int opens) {
+  constexpr int kFr = 8;   // operator k-steps of the wave's share loaded up front
   extern __shared__ double lds_raw[];
   float *lf = reinterpret_cast<float *>(lds_raw);
+  __shared__ float phis32[kMaxWaves * 64], ef[64];
   const int N = a.N, K = 2 * N, KS = K / 4, P = K + 4, K4 = K / 4;
   const int W = (int)(blockDim.x >> 6);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1579,21 +1634,63 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
   const TileDev t = blk_desc<ARGT>(a);
   const float *src = a.dlt + (size_t)(i == 1 ? 0 : ((i & 1) ? 2 : 1)) * a.dlt_stride;
   float *dst = a.dlt + (size_t)((i & 1) ? 1 : 2) * a.dlt_stride;
-  const int nrt = ly ? a.Mt : a.Mto;
-  const float *F = a.frag_it32 + (size_t)t.region * a.frag_it_stride + lane;
-  // loads that need no LDS first: the first operator k-steps and the defect
-  // values (constant part) of the wave's first row tile
-  float f0[kPre], dv0[4];
+  const float *dd = a.dlt;   // the defect d
+  int prt, poff, kb, ke;
+  phi_tile(N, &prt, &poff);
+  phi_ksplit(KS, W, wave, &kb, &ke);
+  const float *F = a.frag_it32 + (size_t)t.region * a.frag_it_stride + lane + (size_t)prt * KS * 64;
+  const double *yb = nullptr, *ybp = nullptr;
+  double *yo = nullptr, *yop = nullptr;
+  // (the step's start is the previous step's accepted iterate, fin_buf until
+  // this step's end: base_buf may be written by this very launch)
+  int cur = 0, fb = 0;
+  if (opens || ly == 2) {
+    cur = a.ctl->cur;
+    fb = a.ctl->fin_buf;
+  }
+  if (ly) {
+    const int bb = ly == 2 ? fb : ring_buf(a, ly - 2, half);
+    const int bo = ring_buf(a, ly, half);
+    yb = out_at(a, bb);
+    ybp = phi_at(a, bb);
+    yo = out_at(a, bo);
+    yop = phi_at(a, bo);
+  }
+  // loads that need no LDS first: this wave's first operator fragments, this
+  // thread's coefficients, the defect (and with ly the FP64 point) of its
+  // first cells, and wave 0's scalar-flux defect
+  float f0[kFr];
+#pragma unroll
+  for (int q = 0; q < kFr; ++q) f0[q] = F[(size_t)min(kb + q, KS - 1) * 64];
+  const PairMap pm(N);
+  float cf[12];
   {
-    const float *Fr = F + (size_t)wave * KS * 64;
+    double c[12];
+    coef_load<12>(a, N, t.region, pm.m, 0, c);
 #pragma unroll
-    for (int q = 0; q < kPre; ++q) f0[q] = Fr[(size_t)min(q, KS - 1) * 64];
-    const int row = min(wave * 16 + col, K - 1);
+    for (int q = 0; q < 12; ++q) cf[q] = (float)c[q];
+  }
+  float dq[kDPre][2];
+  double yq[kDPre][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int cl = min(4 * kq + r, t.nc - 1);
-      dv0[r] = a.dlt[(size_t)(t.c0 + cl + 1) * K + row];
+  for (int j = 0; j < kDPre; ++j) {
+    const size_t cell = (size_t)(t.c0 + min(pm.cl0 + j * pm.cstep, t.nc - 1));
+    const float2 v = *reinterpret_cast<const float2 *>(dd + (cell + 1) * K + 2 * pm.m);
+    dq[j][0] = v.x;
+    dq[j][1] = v.y;
+    yq[j][0] = yq[j][1] = 0.0;
+    if (ly) {
+      const double2 y = *reinterpret_cast<const double2 *>(yb + (cell + 1) * K + 2 * pm.m);
+      yq[j][0] = y.x;
+      yq[j][1] = y.y;
     }
+  }
+  float dphi = 0.f;
+  double yphi = 0.0;
+  if (wave == 0) {
+    const size_t ce = (size_t)(t.c0 + min(lane >> 2, t.nc - 1)) * 4 + (lane & 3);
+    dphi = a.dphi32[ce];
+    if (ly) yphi = ybp[ce];
   }
   const int stalled = a.ctl->stalled;
   {
@@ -1623,60 +1720,77 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
     }
   }
   if (rl || rr) __syncthreads();
-  const double *yb = nullptr, *ybp = nullptr;
-  double *yo = nullptr, *yop = nullptr;
-  if (ly) {
-    const int bb = ly == 2 ? a.ctl->base_buf : ring_buf(a, ly - 2, half);
-    const int bo = ring_buf(a, ly, half);
-    yb = out_at(a, bb);
-    ybp = phi_at(a, bb);
-    yo = out_at(a, bo);
-    yop = phi_at(a, bo);
-  }
-  // incident entry k of cell c: right neighbour (LDS row c+2) for k < N, left (row c) else
-  const float *ap = lf + (kq < 2 ? col + 2 : col) * P + kq * KS;
-  for (int rt = wave; rt < nrt; rt += W) {
+  // this wave's share of e = H inc(delta): incident entry k of cell c from the
+  // right neighbour (LDS row c+2) for k < N, from the left (row c) else
+  {
+    const float *ap = lf + (kq < 2 ? col + 2 : col) * P + kq * KS;
     f4 acc = {0.f, 0.f, 0.f, 0.f};
-    const float *Fr = F + (size_t)rt * KS * 64;
-    int ks = 0;
-    if (rt == wave) {
 #pragma unroll
-      for (int q = 0; q < kPre; ++q)
-        if (q < KS) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[q], f0[q], acc, 0, 0, 0);
-      ks = kPre;
-    }
-    for (; ks + 8 <= KS; ks += 8) {
-      float f[8], v[8];
+    for (int q = 0; q < kFr; ++q)
+      if (kb + q < ke) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[kb + q], f0[q], acc, 0, 0, 0);
+    for (int ks = kb + kFr; ks < ke; ++ks)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[ks], F[(size_t)ks * 64], acc, 0, 0, 0);
+    if (col >= poff && col < poff + 4) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        f[q] = Fr[(size_t)(ks + q) * 64];
-        v[q] = ap[ks + q];
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v[q], f[q], acc, 0, 0, 0);
-    }
-    for (; ks < KS; ++ks)
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[ks], Fr[(size_t)ks * 64], acc, 0, 0, 0);
-    const int row = rt * 16 + col;   // operator row of this lane
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int cl = 4 * kq + r;
-      if (cl >= t.nc) continue;
-      const size_t cell = (size_t)(t.c0 + cl);
-      if (row < K) {
-        const float d = rt == wave ? dv0[r] : a.dlt[(cell + 1) * K + row];
-        const float dv = acc[r] + d;
-        if (ly)
-          yo[(cell + 1) * K + row] = yb[(cell + 1) * K + row] + (double)dv;
-        else
-          dst[(cell + 1) * K + row] = dv;
-      } else if (ly && row < K + 4) {
-        const int comp = row - K;
-        const float pv = acc[r] + a.dphi32[cell * 4 + comp];
-        yop[cell * 4 + comp] = ybp[cell * 4 + comp] + (double)pv;
-      }
+      for (int r = 0; r < 4; ++r) phis32[wave * 64 + (4 * kq + r) * 4 + col - poff] = acc[r];
     }
   }
+  __syncthreads();
+  if (wave == 0) {   // e of (cell, component) = lane: the waves' partials in order
+    float e = 0.f;
+    for (int w = 0; w < W; ++w) e += phis32[w * 64 + lane];
+    ef[lane] = e;
+    const int cl = lane >> 2;
+    if (ly && cl < t.nc) {
+      const size_t ce = (size_t)(t.c0 + cl) * 4 + (lane & 3);
+      yop[ce] = yphi + (double)(dphi + e);
+    }
+  }
+  __syncthreads();
+  const int m = pm.m;
+  const bool pos = 2 * m >= N;
+  int j = 0;
+  for (int cl = pm.active ? pm.cl0 : t.nc; cl < t.nc; cl += pm.cstep, ++j) {
+    const float *in = lf + (pos ? cl : cl + 2) * P + 2 * m;
+    const float *e4 = ef + cl * 4;
+    const float i0 = in[0], i1 = in[1];
+    const float e0 = e4[0], e1 = e4[1], e2 = e4[2], e3 = e4[3];
+    const size_t cell = (size_t)(t.c0 + cl);
+    float d0, d1;
+    double y0 = 0.0, y1 = 0.0;
+    if (j < kDPre) {   // (entry j by selects: a run-time index would put dq in scratch)
+      d0 = dq[0][0];
+      d1 = dq[0][1];
+      y0 = yq[0][0];
+      y1 = yq[0][1];
+#pragma unroll
+      for (int q = 1; q < kDPre; ++q)
+        if (q == j) {
+          d0 = dq[q][0];
+          d1 = dq[q][1];
+          y0 = yq[q][0];
+          y1 = yq[q][1];
+        }
+    } else {
+      d0 = dd[(cell + 1) * K + 2 * m];
+      d1 = dd[(cell + 1) * K + 2 * m + 1];
+      if (ly) {
+        y0 = yb[(cell + 1) * K + 2 * m];
+        y1 = yb[(cell + 1) * K + 2 * m + 1];
+      }
+    }
+    const float o0 = d0 + cf[0] * e0 + cf[1] * e1 + cf[2] * e2 + cf[3] * e3 + cf[4] * i0 +
+                     cf[5] * i1;
+    const float o1 = d1 + cf[6] * e0 + cf[7] * e1 + cf[8] * e2 + cf[9] * e3 + cf[10] * i0 +
+                     cf[11] * i1;
+    if (ly) {
+      *reinterpret_cast<double2 *>(yo + (cell + 1) * K + 2 * m) =
+          make_double2(y0 + (double)o0, y1 + (double)o1);
+    } else {
+      *reinterpret_cast<float2 *>(dst + (cell + 1) * K + 2 * m) = make_float2(o0, o1);
+    }
+  }
+  if (opens) open_step(a, 1, cur, fb, stalled);
 }
 
 template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int, int);
@@ -1715,8 +1829,12 @@ template __global__ void k_oci_iterateK<16, true, true, 32, 4>(StepArgs, int, in
 template __global__ void k_oci_iterateK<4, false, true, 8, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<8, false, true, 16, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterateK<16, false, true, 32, 4>(StepArgs, int, int, int, int);
-template __global__ void k_oci_inner<true>(StepArgs, int, int, int);
-template __global__ void k_oci_inner<false>(StepArgs, int, int, int);
+template __global__ void k_oci_iterateK<16, true, true, 64, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, false, true, 64, 3>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, true, true, 64, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_iterateK<16, false, true, 64, 4>(StepArgs, int, int, int, int);
+template __global__ void k_oci_inner<true>(StepArgs, int, int, int, int);
+template __global__ void k_oci_inner<false>(StepArgs, int, int, int, int);
 
 template __global__ void k_step_begin<4, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int, int, int);

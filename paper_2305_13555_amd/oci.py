@@ -93,6 +93,8 @@ def _load():
         "oci_get_sizes": (ctypes.c_int, [vp, _ip, _ip, _ip]),
         "oci_iterates_per_launch": (ctypes.c_int, [vp]),
         "oci_set_iterates_per_launch": (ctypes.c_int, [vp, ctypes.c_int32]),
+        "oci_inner_iterations": (ctypes.c_int, [vp]),
+        "oci_set_inner_iterations": (ctypes.c_int, [vp, ctypes.c_int32]),
         "oci_get_operator": (ctypes.c_int, [vp, ctypes.c_int32, _dp]),
         "oci_destroy": (None, [vp]),
         "oci_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -284,6 +286,14 @@ def oci_set_iterates_per_launch(ctx, k):
     return _check(_lib.oci_set_iterates_per_launch(ctx, int(k)), ctx)
 
 
+def oci_inner_iterations(ctx):
+    return _check(_lib.oci_inner_iterations(ctx), ctx)
+
+
+def oci_set_inner_iterations(ctx, m):
+    return _check(_lib.oci_set_inner_iterations(ctx, int(m)), ctx)
+
+
 def oci_get_flux(ctx, out=None):
     n, J, _ = oci_get_sizes(ctx)
     if out is None:
@@ -341,6 +351,13 @@ class OciContext:
     def set_iterates_per_launch(self, k):
         self.iterates_per_launch = oci_set_iterates_per_launch(self.handle, k)
         return self.iterates_per_launch
+
+    @property
+    def inner_iterations(self):
+        return oci_inner_iterations(self.handle)
+
+    def set_inner_iterations(self, m):
+        return oci_set_inner_iterations(self.handle, m)
 
     def refactor(self, prob, tol=None, max_iters=None, strict=None):
         oci_refactor(self.handle, prob, tol, max_iters, strict, self.precision)

@@ -1,14 +1,20 @@
-"""Launch-shape autotuner for queued FP64 solves.
+"""Autotuner of the launch configuration of queued solves.
 
-The one knob that changes the speed of a solve but not its results is the
-launch shape: how many OCI iterates one iteration kernel computes (2 up to
-what the problem allows, oci_set_iterates_per_launch).  More iterates per
-launch save launches and re-reads of the previous iterate but recompute
-halo cells and hold more LDS per work-group; which wins depends on N, the
-mesh and the region layout.  tune() times a short solve per candidate from
-the context's current state (restored afterwards), keeps the fastest, and
-remembers it per (N, J, regions, precision) in a process-wide cache that can
-be saved to and loaded from a JSON file.
+Two knobs change the speed of a solve but not what it converges to:
+
+* FP64 contexts: the launch shape, how many OCI iterates one iteration kernel
+  computes (2 up to what the problem allows, oci_set_iterates_per_launch).
+  More iterates per launch save launches and re-reads of the previous iterate
+  but recompute halo cells and hold more LDS per work-group.
+* Mixed-precision contexts: the FP32 inner iterations per correction
+  (oci_set_inner_iterations, 1 .. 4 tried).  More make each correction more
+  complete (fewer FP64 iterates per step) at the cost of the inner launches.
+
+Which wins depends on N, the mesh, the region layout and the tolerance.
+tune() times a short solve per candidate from the context's current state
+(restored afterwards), keeps the fastest, and remembers it per (N, J,
+regions, precision) in a process-wide cache that can be saved to and loaded
+from a JSON file.
 """
 import json
 import time
@@ -28,34 +34,49 @@ def fastest(times):
     return min(sorted(times), key=lambda k: times[k])
 
 
+INNER_CANDIDATES = (1, 2, 3, 4)
+
+
+def _time_solves(ctx, torch, n_steps, repeats, psi, step):
+    best = float("inf")
+    for r in range(repeats + 1):   # the first run builds the graphs
+        ctx.set_state(psi, step)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve(n_steps)
+        torch.cuda.synchronize()
+        if r > 0:
+            best = min(best, (time.perf_counter() - t0) * 1e3 / n_steps)
+    return best
+
+
 def tune(ctx, torch, n_steps=8, repeats=3, use_cache=True):
-    """Pick and set the fastest launch shape for ctx; returns (shape, times
-    in ms per step by candidate; empty when the cache answered)."""
+    """Pick and set the fastest configuration for ctx: the launch shape of an
+    FP64 context, the inner iterations of a mixed-precision one.  Returns
+    (value set, times in ms per step by candidate; empty when the cache
+    answered or there was nothing to choose)."""
     key = cache_key(ctx)
+    mixed = ctx.precision == oci.OCI_PREC_FP32
+    setter = ctx.set_inner_iterations if mixed else ctx.set_iterates_per_launch
     if use_cache and key in _cache:
-        return ctx.set_iterates_per_launch(_cache[key]), {}
-    top = ctx.set_iterates_per_launch(64)   # the most the problem allows
-    if top <= 2:
-        _cache[key] = top
-        return top, {}
+        return setter(_cache[key]), {}
+    if mixed:
+        cands = INNER_CANDIDATES
+    else:
+        top = ctx.set_iterates_per_launch(64)   # the most the problem allows
+        if top <= 2:
+            _cache[key] = top
+            return top, {}
+        cands = range(2, top + 1)
     psi, step = ctx.state()
     times = {}
-    for k in range(2, top + 1):
-        ctx.set_iterates_per_launch(k)
-        best = float("inf")
-        for r in range(repeats + 1):   # the first run builds the graphs
-            ctx.set_state(psi, step)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ctx.solve(n_steps)
-            torch.cuda.synchronize()
-            if r > 0:
-                best = min(best, (time.perf_counter() - t0) * 1e3 / n_steps)
-        times[k] = best
+    for k in cands:
+        setter(k)
+        times[k] = _time_solves(ctx, torch, n_steps, repeats, psi, step)
     ctx.set_state(psi, step)
     k = fastest(times)
     _cache[key] = k
-    return ctx.set_iterates_per_launch(k), times
+    return setter(k), times
 
 
 def save_cache(path):

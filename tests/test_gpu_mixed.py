@@ -140,3 +140,24 @@ def test_mixed_iteration_limit_and_strict_rejected(lib):
     with pytest.raises(lib.OciError) as ei:
         lib.OciContext(p, precision=lib.OCI_PREC_FP32, strict=True)
     assert ei.value.code == lib.OCI_EINVAL
+
+
+@pytest.mark.parametrize("n_angles", [16, 64])
+def test_mixed_queued_windows_match_oracle(lib, n_angles):
+    """Queued windows of several steps: the end of every step but a window's
+    last also forms the next step's first FP64 iterate and its defect, and
+    the next step's first inner iteration opens it."""
+    p = W.config2(n_steps=8, n_cells=700, n_regions=5, n_angles=n_angles)
+    ref = ooci.run_oci(p, cell_data(p), 8, tol=1e-12, max_iters=1000)
+    with lib.OciContext(p, precision=lib.OCI_PREC_FP32, tol=1e-10) as ctx:
+        phi = np.zeros((8, p.n_cells, 4))
+        rc, infos = ctx.solve(8, phi)
+        import torch
+        dev = torch.zeros((8, p.n_cells, 4), dtype=torch.float64, device="cuda")
+        ctx.set_state(None, 0)
+        rc2, infos2 = ctx.solve(8, dev)
+    assert rc == lib.OCI_OK and rc2 == lib.OCI_OK
+    got = dev.cpu().numpy()
+    for k in range(8):
+        assert rel(phi[k], ref[k]["phi"]) < 1e-9, k
+        assert rel(got[k], ref[k]["phi"]) < 1e-9, k

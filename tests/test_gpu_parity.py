@@ -138,11 +138,15 @@ LAYOUTS = [
     (2, [1 + (r * 7) % 6 for r in range(40)], 4, (W.REFLECT, W.VACUUM)),
     (3, [5, 33, 2], 12, (W.VACUUM, W.INCIDENT)),
     (4, [16, 16, 1, 15], 16, (W.REFLECT, W.INCIDENT)),
+    # S_64 with regions of 3 .. 40 cells: the multi-iterate launches with the
+    # halo cells' tables of other regions read from memory
+    (5, [3, 20, 3, 33, 5], 64, (W.REFLECT, W.REFLECT)),
+    (6, [4, 40, 17, 3], 64, (W.INCIDENT, W.VACUUM)),
 ]
 
 
 @pytest.mark.parametrize("case", LAYOUTS, ids=lambda c: "layout%d" % c[0])
-@pytest.mark.parametrize("iters", [1, 2, 3, 5])
+@pytest.mark.parametrize("iters", [1, 2, 3, 4, 5])
 def test_tile_layouts_fixed_iterations(lib, case, iters):
     seed, sizes, n, bc = case
     p = W.layout_case(seed, sizes, n, bc)

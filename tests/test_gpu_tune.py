@@ -64,3 +64,29 @@ def test_tune_picks_a_shape_and_restores_the_state():
             phi_d, _ = _solve(c2, 3)
     for s in range(3):
         assert _rel(phi_t[s], phi_d[s]) < 1e-11
+
+
+def test_inner_iterations_setter_and_tuner_for_mixed_precision():
+    """The inner iterations per correction change the work between FP64
+    iterates, not what a step converges to."""
+    p = W.config2(n_steps=6, n_cells=2000, n_regions=8, n_angles=32)
+    tune._cache.clear()
+    with oci.OciContext(p, precision=oci.OCI_PREC_FP32) as ctx:
+        assert ctx.inner_iterations >= 1
+        with pytest.raises(oci.OciError):
+            ctx.set_inner_iterations(65)
+        base, _ = _solve(ctx, 3)
+        for m in (1, 3):
+            assert ctx.set_inner_iterations(m) == m
+            ctx.set_state(None, 0)
+            phim, _ = _solve(ctx, 3)
+            assert ctx.inner_iterations == m          # fixed: no search
+            for s in range(3):
+                assert _rel(phim[s], base[s]) < 1e-9
+        psi0, step0 = ctx.state()
+        m, times = tune.tune(ctx, torch, n_steps=3, repeats=1)
+        assert sorted(times) == list(tune.INNER_CANDIDATES) and m == tune.fastest(times)
+        assert ctx.inner_iterations == m
+        assert ctx.state()[1] == step0
+    with oci.OciContext(p) as c64:
+        assert c64.inner_iterations == 0 and c64.set_inner_iterations(2) == 0
