@@ -269,54 +269,72 @@ def secondary_case(oci, torch, stream, steps=5):
     }
 
 
-def learned_case(oci, torch):
-    """The learned corrector on the regime it targets: a thin-cell, highly
-    scattering slab (S16, 2000 cells, c = 0.99, sigma dx = 0.05, ~550 OCI
-    iterations per step).  Histories of 5 steps come from the library (the
-    first 16 iterates and the converged flux of each step); the corrector is
-    trained on 4 steps (full-batch Adam, 400 epochs) and evaluated on the
-    held-out fifth: max-norm error of the scalar flux after l plain iterates
-    and after the same iterates plus the predicted correction."""
+def learned_case(oci, torch, stream, n_steps=2, tol=1e-6, first=10, period=20):
+    """The learned corrector inside the iteration on the thin-cell evaluation
+    problem (100,000 cells, S128, 64 regions, optical thickness 0.01 - 0.5,
+    c = 0.9 - 0.999, dt = 1, v = 4: hundreds of OCI iterations per step), with
+    the weights trained on the seeded thin-cell problems (train_corrector.py;
+    the record of that training travels with the weights).  Time to the
+    stopping tolerance per step, first n_steps steps: plain FP64 OCI (queued
+    solve), the same iterates driven from the host (the driver the corrections
+    use), and learned (corrections at iterates first, first + period, ...,
+    kept only when the next plain iterate changes less than a plain one
+    would).  Each result's largest difference to the plain solve at tol 1e-11
+    is reported."""
     from paper_2305_13555_amd import corrector as C
     from paper_2305_13555_amd import workloads
+    w, c_in, meta = C.load_weights(os.path.join(ROOT, "paper_2305_13555_amd",
+                                                "corrector_weights.json"))
+    prob = workloads.config4_eval(n_steps=n_steps)
+    J, N = prob.n_cells, prob.n_angles
+    phi = torch.zeros((n_steps, J, 4), dtype=torch.float64, device="cuda")
+    with oci.OciContext(prob, stream=stream, tol=1e-11) as cr:
+        cr.solve(n_steps, phi)
+        ref = phi.cpu().numpy()
 
-    def histories(prob, n_steps, n_iter):
-        out = []
-        with oci.OciContext(prob) as ctx:
-            for _ in range(n_steps):
-                phis, ref, info = C.step_history(ctx, prob, n_iter)
-                out.append((phis, ref, info["iterations"]))
-        return out
+    def run(mode):
+        with oci.OciContext(prob, stream=stream, tol=tol) as cx:
+            k = None
+            if mode == "learned":
+                k = oci.Corrector(c_in, C.C_OUT, 1, J, stream=stream)
+                k.set_weights(w)
+                cx.set_corrector(k, first=first, period=period)
+            cx.solve(1)                      # warm-up: graphs, caches
+            cx.set_state(None, 0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if mode == "host_plain":
+                infos = []
+                for s in range(n_steps):
+                    rc, info, _ = cx.step_history(0)
+                    phi[s].copy_(torch.from_numpy(cx.flux()).to("cuda"))
+                    infos.append(info)
+            else:
+                rc, infos = cx.solve(n_steps, phi)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t
+            cx.set_corrector(None)
+            if k is not None:
+                k.close()
+        got = phi.cpu().numpy()
+        return {"ms_per_time_step": sec * 1e3 / n_steps,
+                "iterations_per_step": [i["iterations"] for i in infos],
+                "launches_per_step": [i["launches"] for i in infos],
+                "corrections_per_step": [i["corrections"] for i in infos],
+                "rel_vs_tight_solve": max(rel_err(got[s], ref[s]) for s in range(n_steps))}
 
-    def fit(hist, ls):
-        xs, ts = [], []
-        for phis, ref, _ in hist:
-            x, t, _, _ = C.samples(phis, ref, ls)
-            xs.append(x)
-            ts.append(t)
-        x = torch.from_numpy(np.concatenate(xs)).to("cuda")
-        t = torch.from_numpy(np.concatenate(ts)).to("cuda")
-        k, losses, sec = C.train(torch, x, t, epochs=400, lr=2e-3)
-        return k, losses, sec, int(x.shape[0])
-
-    slab = workloads.homogeneous_slab(16, 2000, 0.99, 0.05, 1.0)
-    t0 = time.perf_counter()
-    hist = histories(slab, 5, 16)
-    hist_s = time.perf_counter() - t0
-    ls = list(range(3, 17))
-    k, losses, sec, nb = fit(hist[:4], ls)
-    rows = C.evaluate(torch, k, hist[4][0], hist[4][1], ls)
-    k.close()
-    pick = lambda r: {"l": r["l"], "plain": r["plain"], "corrected": r["corrected"]}
-    return {
-        "workload": slab.name + ", 5 steps (4 train, 1 held out)",
-        "oci_iterations_per_step": [h[2] for h in hist],
-        "history_s": hist_s, "train_s": sec, "train_samples": nb, "epochs": len(losses),
-        "loss_first_last": [losses[0], losses[-1]],
-        "heldout": [pick(r) for r in rows if r["l"] in (3, 8, 16)],
-        "heldout_error_ratio_mean": float(np.mean([r["corrected"] / r["plain"] for r in rows])),
-        "applied_in_iteration": False,
-    }
+    out = {"workload": prob.name + ", first %d steps, tol %g" % (n_steps, tol),
+           "corrections_at": "iterates %d, %d, ... (every %d)" % (first, first + period, period),
+           "training": {k2: meta.get(k2) for k2 in ("problems", "generator", "samples",
+                                                     "cell_samples", "epochs", "loss_first_last")},
+           "input_channels": c_in,
+           "inference": "FP32 on the matrix cores (v_mfma_f32_16x16x4f32)"}
+    for mode in ("plain", "host_plain", "learned"):
+        out[mode] = run(mode)
+    out["learned_speedup_vs_plain"] = out["plain"]["ms_per_time_step"] / \
+        out["learned"]["ms_per_time_step"]
+    out["applied_in_iteration"] = True
+    return out
 
 
 def ensemble_case(oci, torch, n_problems=32):
@@ -371,6 +389,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the iteration kernel's roofline batches on the workload and a "
                          "64 MiB copy (for hardware-counter runs)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="only the learned corrector on the thin-cell evaluation problem")
     ap.add_argument("--workload", choices=["large", "bench16"], default="large",
                     help="with --roofline-only: the 200,000-cell S_64 problem or the "
                          "10,000-cell S_32 one")
@@ -395,6 +415,9 @@ def main():
                           "GB/s": b / t / 1e9, "copy_bytes": nbytes}))
         return
 
+    if args.learned_only:
+        print(json.dumps(learned_case(oci, torch, stream)))
+        return
     prob = workloads.config3()
     J, N, T = prob.n_cells, prob.n_angles, prob.n_steps
     print("bench: %s, tol %g" % (prob.name, prob.tol), file=sys.stderr, flush=True)
@@ -454,7 +477,7 @@ def main():
         print("bench: secondary cases", file=sys.stderr, flush=True)
         secondary = secondary_case(oci, torch, stream)
         ensemble = ensemble_case(oci, torch)
-        learned = learned_case(oci, torch)
+        learned = learned_case(oci, torch, stream)
 
     line = {
         "metric": METRIC,
@@ -493,8 +516,11 @@ def main():
                         "library's stream (launch to launch, dispatch gap included)",
         },
         "cpu_baseline": cpu,
-        "time_to_1e-6_ms_per_step": {"plain_fp64": plain_ms, "mixed": mixed_ms,
-                                     "learned": None},
+        "time_to_1e-6_ms_per_step": {
+            "plain_fp64": plain_ms, "mixed": mixed_ms,
+            "learned_thin_cell_eval": None if learned is None else {
+                "plain_fp64": learned["plain"]["ms_per_time_step"],
+                "learned": learned["learned"]["ms_per_time_step"]}},
         "mixed_speedup_vs_plain": plain_ms / mixed_ms,
         "iterations_per_time_step": iters / (args.steps * T),
         "mixed_fp64_iterations_per_time_step": float(np.mean(

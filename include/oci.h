@@ -125,7 +125,7 @@ typedef struct {
                           picks the accepted one; OCI_PREC_FP32: FP64 and FP32
                           iterates), in kernels of up to
                           oci_iterates_per_launch() iterates each */
-  int32_t pad;
+  int32_t corrections;  /* learned corrections kept in the step (oci_set_corrector) */
   double err_bound;    /* a-posteriori error bound of the accepted iterate:
                           e_l rho / (1 - rho) with rho = e_l / e_{l-1} clamped to
                           [0, 0.9999] (the bound OCI_FLAG_STRICT tests against
@@ -307,7 +307,50 @@ int oci_corrector_grad(oci_corrector *k, const double *x, const double *target, 
  * be NULL) is the loss before the step. */
 int oci_corrector_train_step(oci_corrector *k, const double *x, const double *target,
                              int32_t batch, int32_t cells, double lr, double *loss);
+/* FP32 inference on the matrix cores (v_mfma_f32_16x16x4f32): y = f(x) with the
+ * weights rounded to FP32, x [batch][c_in][cells] and y [batch][c_out][cells]
+ * FP32 device pointers; enqueued on the corrector's stream, not waited for.
+ * c_in and c_out at most 32, else OCI_EINVAL. */
+int oci_corrector_forward32(oci_corrector *k, const float *x, int32_t batch, int32_t cells,
+                            float *y);
 const char *oci_corrector_last_error(const oci_corrector *k);
+
+/* Learned corrections inside the OCI iteration of a context (OCI_PREC_FP64).
+ * With a corrector attached (8 or 12 input channels, 4 outputs, taking at
+ * least J cells), every OCI step is driven from the host in batches of
+ * single-iterate launches, and iterate l = first, first + period, ... of a
+ * step (when not accepted) is corrected: the corrector predicts a scalar-flux
+ * correction dphi from [phi^(l) - phi^(l-1), phi^(l-1) - phi^(l-2)] (and with
+ * 12 channels also rho/(1-rho) (phi^(l) - phi^(l-1)), rho = e_l / e_{l-1}
+ * clamped to [0, 0.9999]) in FP32 on the matrix cores; the iterate's scalar
+ * flux becomes phi^(l) + dphi and each outgoing
+ * flux moves by the isotropic angular flux of that change on its half cell
+ * and time level, dphi / sum(w) (the slow error of OCI in thin, scattering
+ * cells, Sec. "ONE-CELL INVERSION", is the nearly isotropic scattering mode;
+ * it lives in the incident fluxes the next iterate reads, Sec. "One-Cell
+ * Inversion (OCI)").  Iterate l+1 is the plain
+ * OCI iterate of that point; it is kept when its change e_{l+1} is below
+ * rho e_l (rho = e_l / e_{l-1}: the correction lowered the residual below what
+ * a plain iterate reaches), otherwise iterate l is restored bit for bit,
+ * iterate l+1 recomputed from it and the period to the next correction
+ * doubled (up to 1024; back to `period` after a kept correction).  Every accepted iterate is therefore a plain OCI iterate of its
+ * predecessor judged by the stopping rule, and with a corrector whose every
+ * correction is rejected the steps equal plain host-driven steps bit for bit.
+ * The corrector must outlive its attachment and not be used by another
+ * stream meanwhile.  k = NULL detaches.  oci_step_info.corrections counts the
+ * kept corrections.  OCI_EINVAL: NULL context, mixed precision, first < 3,
+ * period < 1, wrong channel counts or too few cells; OCI_ENOMEM. */
+int oci_set_corrector(oci_ctx *c, oci_corrector *k, int32_t first, int32_t period);
+
+/* One plain OCI step (as oci_step, driven from the host in batches of
+ * single-iterate launches) that also copies the scalar flux of its iterates
+ * first .. first + n_hist - 1, as they are formed, into phi_hist
+ * [n_hist][J][4] (host or device per on_device; entries past the accepted
+ * iterate are left as they were).  Training data for the corrector, from one
+ * solve, O(n_hist) copies.  OCI_EINVAL: first < 1, n_hist < 0, phi_hist NULL
+ * with n_hist > 0, mixed precision. */
+int oci_step_history(oci_ctx *c, int32_t first, int32_t n_hist, double *phi_hist,
+                     int32_t on_device, oci_step_info *info);
 /* Release the corrector (waits for its stream).  NULL is a no-op. */
 void oci_corrector_destroy(oci_corrector *k);
 

@@ -28,6 +28,7 @@
 #include "oci.h"
 #include "oci_kernels.h"
 #include "plan.h"
+#include "corrector_internal.h"
 
 using namespace ocik;
 
@@ -110,6 +111,12 @@ struct oci_ctx {
   size_t lds_itK[5] = {};
   int kimax = 2;              // most iterates per launch (the active cap)
   int kibuilt = 2;            // most iterates per launch this problem allows
+  // learned corrections inside the iteration (oci_set_corrector)
+  oci_corrector *corr = nullptr;
+  int corr_first = 0, corr_period = 0, corr_in = 8;
+  float *d_lx = nullptr, *d_ly = nullptr;       // corrector input [8][J], output [4][J]
+  double *d_bak_out = nullptr, *d_bak_phi = nullptr;   // the corrected iterate, as it was
+  double *h_dec = nullptr;                      // pinned host copy of dec
   std::string err;
   StepArgs sa{};
   SiArgs si{};
@@ -753,7 +760,8 @@ static double error_bound(double e, double e_prev) {
 }
 
 static void fill_info(oci_step_info *info, int iterations, int status, double residual, double ms,
-                      double iter_ms, int launches, double err_bound = -1.0) {
+                      double iter_ms, int launches, double err_bound = -1.0,
+                      int corrections = 0) {
   if (!info) return;
   info->iterations = iterations;
   info->status = status;
@@ -761,7 +769,7 @@ static void fill_info(oci_step_info *info, int iterations, int status, double re
   info->ms = ms;
   info->iter_ms = iter_ms;
   info->launches = launches;
-  info->pad = 0;
+  info->corrections = corrections;
   info->err_bound = err_bound;
 }
 
@@ -847,6 +855,7 @@ static int grow_records(oci_ctx *c, int n) {
   if (n <= c->rec_cap) return OCI_OK;
   drop_step_graphs(c);
   if (c->h_rec) (void)hipHostFree(c->h_rec);
+  if (c->h_dec) (void)hipHostFree(c->h_dec);
   c->d_rec = nullptr;
   c->h_rec = nullptr;
   c->rec_cap = 0;
@@ -1235,6 +1244,198 @@ static int solve_queued(oci_ctx *c, int n_steps, double *phi_dev, oci_step_info 
   return worst;
 }
 
+// ---------------------------------------------------------------------------
+// Host-driven steps: learned corrections inside the iteration, iterate history
+// ---------------------------------------------------------------------------
+// One OCI step in batches of single-iterate launches, each batch judged by an
+// end of step (as a resumed step is).  With a corrector attached, iterate l =
+// first, first + period, ... (plain, and not accepted) is corrected: the
+// corrector predicts dphi from the scalar fluxes of iterates l-2 .. l, the
+// iterate's scalar flux moves by dphi and its outgoing fluxes by the
+// isotropic angular flux of that change (k_learn_apply), and iterate l+1 is
+// the plain OCI iterate of that point.  It is kept when its change e_{l+1}
+// is below rho e_l (rho = e_l / e_{l-1}: below what a plain iterate would
+// reach, so the correction lowered the residual); otherwise iterate l is
+// restored bit for bit, iterate l+1 recomputed from it, and the period to the
+// next correction doubled (up to 1024 iterates; back to `period` after a kept
+// one).  So a rejected correction leaves the plain sequence unchanged and an
+// unhelpful corrector costs few attempts.  Every accepted iterate is a plain
+// OCI iterate of its predecessor, judged by the stopping rule.  With hist
+// (n_hist > 0) the scalar flux of iterates hist_first .. hist_first +
+// n_hist - 1 (those computed) is copied out as they are formed.
+static int host_step(oci_ctx *c, double *phi_dev, oci_step_info *info, double *hist, int n_hist,
+                     bool hist_on_device, int hist_first = 1) {
+  const int J = c->J, K = 2 * c->N, h = c->parity;
+  c->h_ctl->cur = 0;
+  c->h_ctl->psi_base = h;
+  OCI_CK(c, hipMemcpyAsync(&c->d_ctl->cur, &c->h_ctl->cur, 2 * sizeof(int32_t),
+                           hipMemcpyHostToDevice, c->stream));
+  OCI_CK(c, hipEventRecord(c->ev0, c->stream));
+  if (!c->gh_valid) {
+    void *bargs[] = {&c->sa};
+    OCI_CK(c, hipLaunchKernel(c->fn_begin, dim3(c->grid), dim3(64 * c->W_pv), bargs, c->lds_pv,
+                              c->stream));
+    c->gh_valid = true;
+  }
+  const size_t phin = (size_t)J * 4;
+  const int hist_last = hist_first + n_hist - 1;
+  auto copy_hist = [&](int l) -> int {
+    if (!hist || l < hist_first || l > hist_last) return OCI_OK;
+    OCI_CK(c, hipMemcpyAsync(hist + (size_t)(l - hist_first) * phin,
+                             c->d_phib + (size_t)(h * c->nbuf + l % c->nbuf) * c->phi_stride,
+                             phin * sizeof(double),
+                             hist_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+    return OCI_OK;
+  };
+  auto out_slot = [&](int l) { return c->d_outb + (size_t)(h * c->nbuf + l % c->nbuf) * c->out_stride; };
+  auto phi_slot = [&](int l) { return c->d_phib + (size_t)(h * c->nbuf + l % c->nbuf) * c->phi_stride; };
+  // plain iterates l0+1 .. l0+count, then the end of step over them
+  auto plain = [&](int l0, int count) -> int {
+    int rc = clear_stall(c);
+    for (int i = 1; rc == OCI_OK && i <= count; ++i) {
+      rc = launch_batch(c, false, l0 + i - 1, 1, h);
+      if (rc == OCI_OK) rc = copy_hist(l0 + i);
+    }
+    if (rc == OCI_OK) rc = launch_end(c, phi_dev, l0 + 1, l0 + count, h);
+    if (rc == OCI_OK) rc = read_ctl(c);
+    return rc;
+  };
+  auto decided = [&]() { return !c->h_ctl->stalled || c->h_ctl->fin_status == kNonFinite; };
+  int launched = 0, launches = 0, corrections = 0, rc = OCI_OK;
+  int next_corr = c->corr ? c->corr_first : 0;
+  int period = c->corr_period;   // doubled after each rejected correction (up to 1024)
+  for (;;) {
+    int count = (c->corr && next_corr > launched) ? next_corr - launched : kMaxBatch;
+    if (hist && launched < hist_last) count = std::min(count, hist_last - launched);
+    count = std::min({count, c->nbuf - 1, kMaxBatch, std::max(c->max_iters - launched, 1)});
+    rc = plain(launched, count);
+    if (rc) return rc;
+    launched += count;
+    launches += count;
+    if (decided()) break;
+    if (launched > c->max_iters + 1)
+      return fail(c, OCI_EDEVICE, "the step control block did not reach a decision");
+    if (!(c->corr && launched == next_corr && launched >= 3)) continue;
+    const int l = launched;
+    // the corrected point in slot l (its plain values kept for a restore)
+    OCI_CK(c, hipMemcpyAsync(c->d_bak_out, out_slot(l) + K, (size_t)J * K * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    OCI_CK(c, hipMemcpyAsync(c->d_bak_phi, phi_slot(l), phin * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    double amp = 0.0;   // rho / (1 - rho) from the e of iterates l-1 and l
+    if (c->corr_in == 12) {
+      OCI_CK(c, hipMemcpyAsync(c->h_dec, c->d_dec, (size_t)c->nbuf * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream));
+      OCI_CK(c, hipStreamSynchronize(c->stream));
+      const double e0 = c->h_dec[l % c->nbuf], em = c->h_dec[(l - 1) % c->nbuf];
+      const double rho = em > 0.0 ? std::min(std::max(e0 / em, 0.0), 0.9999) : 0.0;
+      amp = rho / (1.0 - rho);
+    }
+    const int nb = (int)std::min<size_t>(2048, (phin + 255) / 256);
+    hipLaunchKernelGGL(k_learn_features, dim3(nb), dim3(256), 0, c->stream, c->sa, l, h,
+                       c->corr_in, amp, c->d_lx);
+    OCI_CK(c, hipGetLastError());
+    rc = occ_infer32(c->corr, c->stream, c->d_lx, J, c->d_ly);
+    if (rc) return fail(c, OCI_EDEVICE, "corrector inference failed");
+    const int na = (int)std::min<size_t>(4096, ((size_t)J * c->N + 255) / 256);
+    hipLaunchKernelGGL(k_learn_apply, dim3(na), dim3(256), 0, c->stream, c->sa, l, h, c->d_ly);
+    OCI_CK(c, hipGetLastError());
+    rc = plain(l, 1);
+    if (rc) return rc;
+    launches += 1;
+    if (decided()) {   // iterate l+1 of the corrected point was accepted
+      launched = l + 1;
+      ++corrections;
+      break;
+    }
+    OCI_CK(c, hipMemcpyAsync(c->h_dec, c->d_dec, (size_t)c->nbuf * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    OCI_CK(c, hipStreamSynchronize(c->stream));
+    const double e1 = c->h_dec[(l + 1) % c->nbuf], e0 = c->h_dec[l % c->nbuf];
+    const double em = c->h_dec[(l - 1) % c->nbuf];
+    const double rho = em > 0.0 ? std::min(std::max(e0 / em, 0.0), 1.0) : 1.0;
+    if (e1 < rho * e0) {
+      ++corrections;
+      launched = l + 1;
+      period = c->corr_period;
+      next_corr = launched + period - 1;
+      continue;
+    }
+    period = std::min(2 * period, 1024);
+    next_corr = l + 1 + period - 1;
+    // rejected: iterate l as it was, and its plain successor
+    OCI_CK(c, hipMemcpyAsync(out_slot(l) + K, c->d_bak_out, (size_t)J * K * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    OCI_CK(c, hipMemcpyAsync(phi_slot(l), c->d_bak_phi, phin * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+    rc = plain(l, 1);
+    if (rc) return rc;
+    launches += 1;
+    launched = l + 1;
+    if (decided()) break;
+  }
+  OCI_CK(c, hipEventRecord(c->ev1, c->stream));
+  OCI_CK(c, hipEventSynchronize(c->ev1));
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  const StepCtl st = *c->h_ctl;
+  if (st.fin_status == kNonFinite) return abandon_step(c, info, st.fin_accepted);
+  const int status = st.fin_status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
+  fill_info(info, st.fin_accepted, status, st.fin_e, ms, ms, launches,
+            error_bound(st.fin_e, st.fin_e_prev), corrections);
+  complete_step(c, st.fin_accepted);
+  c->batch_hint = std::max(st.fin_accepted, 1);
+  c->window = 1;
+  return status;
+}
+
+extern "C" int oci_set_corrector(oci_ctx *c, oci_corrector *k, int32_t first, int32_t period) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (!k) {
+    c->corr = nullptr;
+    return OCI_OK;
+  }
+  if (c->mixed) return fail(c, OCI_EINVAL, "learned corrections need OCI_PREC_FP64");
+  if (first < 3 || period < 1)
+    return fail(c, OCI_EINVAL, "corrections need first >= 3 and period >= 1");
+  int ci = 0, co = 0;
+  int64_t maxc = 0;
+  if (occ_channels(k, &ci, &co, &maxc) != OCI_OK || (ci != 8 && ci != 12) || co != 4)
+    return fail(c, OCI_EINVAL, "the corrector must map 8 or 12 input channels to 4");
+  if (maxc < c->J) return fail(c, OCI_EINVAL, "the corrector takes fewer cells than the mesh has");
+  if (!c->d_lx) {   // buffers of the first attached corrector, kept until oci_destroy
+    OCI_CK(c, hipStreamSynchronize(c->stream));
+    int rc = dalloc(c, &c->d_lx, (size_t)12 * c->J);
+    if (rc == OCI_OK) rc = dalloc(c, &c->d_ly, (size_t)4 * c->J);
+    if (rc == OCI_OK) rc = dalloc(c, &c->d_bak_out, (size_t)c->J * 2 * c->N);
+    if (rc == OCI_OK) rc = dalloc(c, &c->d_bak_phi, (size_t)c->J * 4);
+    if (rc) return rc;
+    void *hp = nullptr;
+    if (hipHostMalloc(&hp, kMaxRing * sizeof(double), hipHostMallocDefault) != hipSuccess)
+      return fail(c, OCI_ENOMEM, "hipHostMalloc failed");
+    c->h_dec = static_cast<double *>(hp);
+  }
+  c->corr = k;
+  c->corr_first = first;
+  c->corr_period = period;
+  c->corr_in = ci;
+  return OCI_OK;
+}
+
+extern "C" int oci_step_history(oci_ctx *c, int32_t first, int32_t n_hist, double *phi_hist,
+                                int32_t on_device, oci_step_info *info) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (first < 1 || n_hist < 0 || (n_hist > 0 && !phi_hist))
+    return fail(c, OCI_EINVAL, "bad history window or buffer");
+  if (c->mixed) return fail(c, OCI_EINVAL, "iterate histories need OCI_PREC_FP64");
+  oci_corrector *k = c->corr;
+  c->corr = nullptr;   // plain iterates only
+  const int rc = host_step(c, nullptr, info, phi_hist, n_hist, on_device != 0, first);
+  c->corr = k;
+  return rc;
+}
+
 extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
   if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
   std::string why;
@@ -1280,6 +1481,7 @@ extern "C" int oci_refactor(oci_ctx *c, const oci_problem *p) {
 
 extern "C" int oci_step(oci_ctx *c, oci_step_info *info) {
   if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  if (c->corr) return host_step(c, nullptr, info, nullptr, 0, false);
   return solve_queued(c, 1, nullptr, info);
 }
 
@@ -1293,6 +1495,16 @@ extern "C" int oci_solve(oci_ctx *c, int32_t n_steps, double *phi_out, int32_t p
   if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
   if (n_steps < 0) return fail(c, OCI_EINVAL, "n_steps must be >= 0");
   if (n_steps == 0) return OCI_OK;
+  if (c->corr && (phi_out == nullptr || phi_out_on_device)) {   // step by step, host-driven
+    int worst = OCI_OK;
+    for (int k = 0; k < n_steps; ++k) {
+      const int rc = host_step(c, phi_out ? phi_out + (size_t)k * c->J * 4 : nullptr,
+                               infos ? &infos[k] : nullptr, nullptr, 0, false);
+      if (rc < 0) return rc;
+      if (rc == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
+    }
+    return worst;
+  }
   if (phi_out == nullptr || phi_out_on_device) return solve_queued(c, n_steps, phi_out, infos);
   // host output: step by step, copying each step's flux
   int worst = OCI_OK;
@@ -1455,6 +1667,7 @@ extern "C" void oci_destroy(oci_ctx *c) {
   for (void *q : c->allocs) (void)hipFree(q);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   if (c->h_rec) (void)hipHostFree(c->h_rec);
+  if (c->h_dec) (void)hipHostFree(c->h_dec);
   for (hipEvent_t e : {c->ev0, c->ev1, c->evA, c->evB, c->evW[0][0], c->evW[0][1], c->evW[1][0],
                        c->evW[1][1]})
     if (e) (void)hipEventDestroy(e);

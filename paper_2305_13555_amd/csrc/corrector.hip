@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "oci.h"
+#include "corrector_internal.h"
 
 namespace occ {
 
@@ -274,6 +275,72 @@ __global__ __launch_bounds__(256) void k_adam(double *__restrict__ w, const doub
   }
 }
 
+// FP32 copy of the weights for inference.
+__global__ __launch_bounds__(256) void k_to_f32(const double *__restrict__ w, size_t n,
+                                                float *__restrict__ w32) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    w32[e] = (float)w[e];
+}
+
+// Inference convolution in FP32 on the matrix cores: per work-group 64 cells
+// (16 per wave) and every output channel, as the product
+//   y[o][j] = sum_k W[o][k] X[k][j],  k = 5 i + t,  X[k][j] = x[i][j + t - 2]
+// on v_mfma_f32_16x16x4f32 (A = W rows o, B = the shifted inputs of 16
+// cells; lane l supplies A[l%16][l/16] and B[l/16][l%16] and receives
+// D[4 (l/16) + r][l%16]).  The layer's weights (zero-padded to Co rounded up to
+// 16 rows and Ci*5 rounded up to a multiple of 4) and the work-group's
+// Ci x (64 + 4) input cells are staged in LDS.  Grid (ceil(J/64), 1, B);
+// dynamic LDS: (MT*16*KP + Ci*(64+4)) floats, MT = ceil(Co/16), KP = Ci*5
+// rounded up to 4.  Co <= 32.
+constexpr int kC32 = 64;   // cells per work-group
+__global__ __launch_bounds__(256) void k_conv_fwd32(const float *__restrict__ x, int Ci, int J,
+                                                    const float *__restrict__ W, int Co,
+                                                    float *__restrict__ y, int relu) {
+  extern __shared__ float sm[];
+  const int MT = (Co + 15) / 16, KP = (Ci * KW + 3) & ~3, XP = kC32 + KW - 1;
+  float *ws = sm;                    // [MT*16][KP]
+  float *xs = sm + MT * 16 * KP;     // [Ci][XP], column c <-> cell j0 - 2 + c
+  const int j0 = blockIdx.x * kC32, b = blockIdx.z, tid = threadIdx.x;
+  const float *xb = x + (size_t)b * Ci * J;
+  for (int e = tid; e < MT * 16 * KP; e += blockDim.x) {
+    const int o = e / KP, k = e - o * KP;
+    ws[e] = (o < Co && k < Ci * KW) ? W[(size_t)o * Ci * KW + k] : 0.f;
+  }
+  for (int e = tid; e < Ci * XP; e += blockDim.x) {
+    const int i = e / XP, c = e - i * XP, j = j0 - 2 + c;
+    xs[e] = (j >= 0 && j < J) ? xb[(size_t)i * J + j] : 0.f;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  f4v acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+  const int cw = wave * 16 + col;   // this lane's cell column within the work-group
+  for (int ks = 0; ks < KP / 4; ++ks) {
+    const int k = 4 * ks + kq;
+    const int i = min(k / KW, Ci - 1), t = k - (k / KW) * KW;
+    const float bv = xs[i * XP + cw + t];   // (k past Ci*5: the weights there are zero)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+      if (mt < MT) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ws[(mt * 16 + col) * KP + k], bv,
+                                                                  acc[mt], 0, 0, 0);
+  }
+  const int j = j0 + cw;
+  if (j >= J) return;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    if (mt >= MT) break;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = mt * 16 + 4 * kq + r;
+      if (o < Co) {
+        const float v = acc[mt][r];
+        y[((size_t)b * Co + o) * J + j] = relu ? fmaxf(v, 0.f) : v;
+      }
+    }
+  }
+}
+
 }  // namespace occ
 
 using namespace occ;
@@ -291,6 +358,9 @@ struct oci_corrector {
   double *part = nullptr, *loss = nullptr;
   double *wpart = nullptr;    // weight-gradient partial sums [kWgtBlocks][Co*Ci*KW]
   int64_t adam_t = 0;
+  float *w32 = nullptr;       // FP32 weights for inference (converted when stale)
+  float *h32[2] = {};         // FP32 hidden activations, used in turn
+  bool w32_stale = true;
 };
 
 namespace {
@@ -417,6 +487,9 @@ extern "C" int oci_corrector_create(int32_t c_in, int32_t c_out, int32_t max_bat
                 hipSuccess;
   for (int l = 1; ok && l < NL; ++l)
     ok = hipMalloc(&k->act[l], per * HID * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&k->w32, nw * sizeof(float)) == hipSuccess;
+  for (int i = 0; ok && i < 2; ++i)
+    ok = hipMalloc(&k->h32[i], per * HID * sizeof(float)) == hipSuccess;
   if (!ok) {
     oci_corrector_destroy(k);
     return OCI_ENOMEM;
@@ -445,6 +518,7 @@ extern "C" int oci_corrector_set_weights(oci_corrector *k, const double *w) {
   CK(k, hipMemsetAsync(k->v, 0, nw * sizeof(double), k->stream));
   CK(k, hipStreamSynchronize(k->stream));
   k->adam_t = 0;
+  k->w32_stale = true;
   return OCI_OK;
 }
 
@@ -492,6 +566,7 @@ extern "C" int oci_corrector_train_step(oci_corrector *k, const double *x, const
   const double bc2 = 1.0 - std::pow(b2, (double)k->adam_t);
   hipLaunchKernelGGL(k_adam, dim3(64), dim3(256), 0, k->stream, k->w, (const double *)k->gw, k->m,
                      k->v, k->woff[NL], lr, b1, b2, eps, bc1, bc2);
+  k->w32_stale = true;
   CK(k, hipGetLastError());
   if (loss) CK(k, hipMemcpyAsync(loss, k->loss, sizeof(double), hipMemcpyDeviceToHost, k->stream));
   CK(k, hipStreamSynchronize(k->stream));
@@ -509,7 +584,63 @@ extern "C" void oci_corrector_destroy(oci_corrector *k) {
                     k->wpart, k->act[1], k->act[2], k->act[3]};
   for (double *p : bufs)
     if (p) (void)hipFree(p);
+  float *fbufs[] = {k->w32, k->h32[0], k->h32[1]};
+  for (float *p : fbufs)
+    if (p) (void)hipFree(p);
   delete k;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 inference on the matrix cores
+// ---------------------------------------------------------------------------
+namespace {
+
+// y = f(x) in FP32 for x [B][c_in][J] on stream st (the FP32 weights
+// refreshed first when stale, on the same stream).
+int infer32(oci_corrector *k, hipStream_t st, const float *x, int B, int J, float *y) {
+  if (k->w32_stale) {
+    hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, (const double *)k->w, k->woff[NL],
+                       k->w32);
+    k->w32_stale = false;
+  }
+  const float *in = x;
+  for (int l = 0; l < NL; ++l) {
+    const int Ci = k->chans[l], Co = k->chans[l + 1];
+    float *o = l == NL - 1 ? y : k->h32[l & 1];
+    const int MT = (Co + 15) / 16, KP = (Ci * KW + 3) & ~3;
+    const size_t lds = (size_t)(MT * 16 * KP + Ci * (kC32 + KW - 1)) * sizeof(float);
+    hipLaunchKernelGGL(k_conv_fwd32, dim3((J + kC32 - 1) / kC32, 1, B), dim3(256), lds, st, in, Ci,
+                       J, (const float *)(k->w32 + k->woff[l]), Co, o, l < NL - 1 ? 1 : 0);
+    in = o;
+  }
+  CK(k, hipGetLastError());
+  return OCI_OK;
+}
+
+}  // namespace
+
+int occ_infer32(oci_corrector *k, hipStream_t st, const float *x, int cells, float *y) {
+  if (!k || !x || !y) return OCI_EINVAL;
+  if (cells < 1 || (int64_t)cells > (int64_t)k->max_batch * k->max_cells) return OCI_EINVAL;
+  return infer32(k, st, x, 1, cells, y);
+}
+
+int occ_channels(const oci_corrector *k, int *c_in, int *c_out, int64_t *max_cells) {
+  if (!k) return OCI_EINVAL;
+  *c_in = k->c_in;
+  *c_out = k->c_out;
+  *max_cells = (int64_t)k->max_batch * k->max_cells;
+  return OCI_OK;
+}
+
+extern "C" int oci_corrector_forward32(oci_corrector *k, const float *x, int32_t batch,
+                                       int32_t cells, float *y) {
+  if (!k || !x || !y) return cfail(k, OCI_EINVAL, "NULL argument");
+  if (k->c_in > 32 || k->c_out > 32)
+    return cfail(k, OCI_EINVAL, "FP32 inference takes at most 32 input and output channels");
+  int rc = check_shape(k, batch, cells);
+  if (rc) return rc;
+  return infer32(k, k->stream, x, batch, cells, y);
 }
 
 // ---------------------------------------------------------------------------

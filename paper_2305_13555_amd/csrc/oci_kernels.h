@@ -161,6 +161,12 @@ __global__ void k_reduce_rec(StepArgs a, int l, int n, int half);
 // came with the previous end of step).
 template <bool ARGT>
 __global__ void k_oci_inner(StepArgs a, int i, int ly, int half, int opens);
+// Learned corrections of iterate l of the open step (ring half `half`): the
+// corrector's FP32 input (ch = 8 or 12 channels; amp: the extrapolation
+// factor of channels 8..11) from the scalar fluxes of iterates l-2 .. l, and
+// the corrected iterate in place from its output y [4][J].
+__global__ void k_learn_features(StepArgs a, int l, int half, int ch, double amp, float *x);
+__global__ void k_learn_apply(StepArgs a, int l, int half, const float *y);
 // si.hip
 __global__ void k_si_maps(SiArgs a, int node, int cb);
 __global__ void k_si_sweep(SiArgs a, int node, int cb);

@@ -1793,6 +1793,62 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
   if (opens) open_step(a, 1, cur, fb, stalled);
 }
 
+// ---------------------------------------------------------------------------
+// Learned corrections inside the iteration
+// ---------------------------------------------------------------------------
+// The corrector's input for iterate l of the open step (l >= 3): per cell the
+// two latest scalar-flux differences, x [ch][J] in FP32 (channels 0..3:
+// phi^(l) - phi^(l-1), 4..7: phi^(l-1) - phi^(l-2)) and, with ch = 12, the
+// latest difference extrapolated with the iteration's observed contraction,
+// amp (phi^(l) - phi^(l-1)), amp = rho / (1 - rho) (channels 8..11: what the
+// remaining error would be if every error component contracted at rho).  No
+// scaling: the network is positively homogeneous.
+__global__ __launch_bounds__(256) void k_learn_features(StepArgs a, int l, int half, int ch,
+                                                        double amp, float *x) {
+  const double *p0 = phi_at(a, ring_buf(a, l, half));
+  const double *p1 = phi_at(a, ring_buf(a, l - 1, half));
+  const double *p2 = phi_at(a, ring_buf(a, l - 2, half));
+  const int n = a.J * 4;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int j = e >> 2, c = e & 3;
+    const double v0 = p0[e], v1 = p1[e], v2 = p2[e];
+    x[(size_t)c * a.J + j] = (float)(v0 - v1);
+    x[(size_t)(4 + c) * a.J + j] = (float)(v1 - v2);
+    if (ch == 12) x[(size_t)(8 + c) * a.J + j] = (float)(amp * (v0 - v1));
+  }
+}
+
+// The corrected iterate l in place: the scalar flux phi + dphi (dphi = the
+// corrector's output y [4][J]) and every outgoing flux moved by the isotropic
+// angular flux of that change on its half cell and time level,
+// dpsi = dphi / sum_m w_m (= dphi / 2): the slowly converging error of OCI in
+// thin, scattering cells is the nearly isotropic scattering mode, and it
+// lives in the incident fluxes the next iterate reads, so the correction is
+// carried there (a scalar flux moved alone would be recomputed from the
+// uncorrected incident fluxes and lost).  Angle m < N/2 leaves through the
+// left half (components 0, 2 at levels k, k+1/2), m >= N/2 through the right
+// (1, 3).  One thread per (cell, angle).
+__global__ __launch_bounds__(256) void k_learn_apply(StepArgs a, int l, int half, const float *y) {
+  const int N = a.N, K = 2 * N;
+  const int b = ring_buf(a, l, half);
+  double *out = out_at(a, b), *phi = phi_at(a, b);
+  const size_t n = (size_t)a.J * N;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / N), m = (int)(e - (size_t)j * N);
+    const int side = 2 * m >= N ? 1 : 0;
+    const double d0 = (double)y[(size_t)side * a.J + j];         // level k
+    const double d1 = (double)y[(size_t)(2 + side) * a.J + j];   // level k+1/2
+    double *o = out + (size_t)(j + 1) * K + 2 * m;
+    o[0] += 0.5 * d0;
+    o[1] += 0.5 * d1;
+    if (m == 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) phi[(size_t)j * 4 + c] += (double)y[(size_t)c * a.J + j];
+    }
+  }
+}
+
 template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterate2<8, false, false, 0>(StepArgs, int, int, int, int);

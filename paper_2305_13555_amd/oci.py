@@ -54,13 +54,13 @@ class oci_step_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("residual", ctypes.c_double), ("ms", ctypes.c_double),
                 ("iter_ms", ctypes.c_double), ("launches", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("err_bound", ctypes.c_double)]
+                ("corrections", ctypes.c_int32), ("err_bound", ctypes.c_double)]
 
     def as_dict(self):
         return {"iterations": int(self.iterations), "status": int(self.status),
                 "residual": float(self.residual), "ms": float(self.ms),
                 "iter_ms": float(self.iter_ms), "launches": int(self.launches),
-                "err_bound": float(self.err_bound)}
+                "err_bound": float(self.err_bound), "corrections": int(self.corrections)}
 
 
 class OciError(RuntimeError):
@@ -114,6 +114,10 @@ def _load():
         "oci_corrector_destroy": (None, [vp]),
         "oci_corrector_forward_noalloc": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp,
                                                          ctypes.c_int32, ctypes.c_int32, vp, vp]),
+        "oci_corrector_forward32": (ctypes.c_int, [vp, vp, ctypes.c_int32, ctypes.c_int32, vp]),
+        "oci_set_corrector": (ctypes.c_int, [vp, vp, ctypes.c_int32, ctypes.c_int32]),
+        "oci_step_history": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp,
+                                            ctypes.c_int32, ctypes.POINTER(oci_step_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -359,6 +363,24 @@ class OciContext:
     def set_inner_iterations(self, m):
         return oci_set_inner_iterations(self.handle, m)
 
+    def set_corrector(self, corrector, first=3, period=8):
+        """Attach a Corrector (or None to detach) for learned corrections
+        inside the iteration; the corrector must outlive the attachment."""
+        h = corrector._h if corrector is not None else None
+        _check(_lib.oci_set_corrector(self.handle, h, int(first), int(period)), self.handle)
+        self._corrector = corrector
+
+    def step_history(self, n_hist, first=1, out=None):
+        """One plain step that also returns the scalar flux of its iterates
+        first .. first + n_hist - 1 ([n_hist][J][4], numpy or CUDA tensor)."""
+        if out is None:
+            out = np.zeros((int(n_hist), self.n_cells, 4))
+        ptr, dev = _out_pointer(out)
+        info = oci_step_info()
+        rc = _check(_lib.oci_step_history(self.handle, int(first), int(n_hist), ptr, dev,
+                                          ctypes.byref(info)), self.handle)
+        return rc, info.as_dict(), out
+
     def refactor(self, prob, tol=None, max_iters=None, strict=None):
         oci_refactor(self.handle, prob, tol, max_iters, strict, self.precision)
 
@@ -467,6 +489,20 @@ class Corrector:
         self._shape(out, self.c_out)
         self._check(_lib.oci_corrector_forward(self._h, ctypes.c_void_p(x.data_ptr()), B, J,
                                                ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def forward32(self, x, out=None):
+        """FP32 inference on the matrix cores: x [batch][c_in][cells] float32
+        device tensor."""
+        if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous() or x.dim() != 3 \
+                or x.shape[1] != self.c_in:
+            raise ValueError("expected a contiguous float32 device tensor [batch][%d][cells]"
+                             % self.c_in)
+        B, J = int(x.shape[0]), int(x.shape[2])
+        if out is None:
+            out = torch.empty((B, self.c_out, J), dtype=torch.float32, device=x.device)
+        self._check(_lib.oci_corrector_forward32(self._h, ctypes.c_void_p(x.data_ptr()), B, J,
+                                                 ctypes.c_void_p(out.data_ptr())))
         return out
 
     def grad(self, x, target):

@@ -108,6 +108,44 @@ def config3(n_steps=50):
         name="64 regions, 200000 cells, S64, 50 steps")
 
 
+def _config4_problem(rng, J, N, R, name, n_steps):
+    """Thin-cell, highly scattering slab: per region sigma_t lognormal(0, 1)
+    clipped to [0.01, 10], c ~ U[0.9, 0.999], Q ~ U[0, 1] (drawn in that order),
+    then the cell optical thickness tau ~ logU[0.01, 0.5] (dx = tau / sigma_t);
+    reflecting left / vacuum right, dt = 1, v = 4 (1/(v dt) = 0.25)."""
+    sigma_t = np.clip(rng.lognormal(0.0, 1.0, R), 0.01, 10.0)
+    c = rng.uniform(0.9, 0.999, R)
+    q = rng.uniform(0.0, 1.0, R)
+    tau = np.exp(rng.uniform(np.log(0.01), np.log(0.5), R))
+    cells = split_cells(J, R)
+    dx = tau / sigma_t
+    return SlabProblem(
+        n_angles=N, cells=cells, width=cells * dx, sigma_t=sigma_t, sigma_s=c * sigma_t,
+        source=q, dt=1.0, speed=4.0, bc_left=REFLECT, bc_right=VACUUM, n_steps=n_steps,
+        tol=1e-6, max_iters=200_000, name=name)
+
+
+def config4(idx, n_steps=5):
+    """Training problem idx of the learned corrector: J = round(exp U[ln 1e3,
+    ln 5e4]) cells, N uniform in {16, 32, 64}, 16 regions, thin cells (optical
+    thickness 0.01 - 0.5) with scattering ratio 0.9 - 0.999, dt = 1, v = 4,
+    5 steps.  Each problem has its own generator (config 4, index idx)."""
+    rng = _rng(4, idx)
+    J = int(round(np.exp(rng.uniform(np.log(1e3), np.log(5e4)))))
+    N = int(rng.choice([16, 32, 64]))
+    return _config4_problem(rng, J, N, 16, "thin-cell problem %d: %d cells, S%d, 16 regions"
+                            % (idx, J, N), n_steps)
+
+
+def config4_eval(n_steps=5, n_cells=100_000, n_angles=128, n_regions=64):
+    """Evaluation problem of the learned corrector (config 4, index 10,000):
+    100,000 cells, S_128, 64 regions, draws as config4."""
+    rng = _rng(4, 10_000)
+    return _config4_problem(rng, n_cells, n_angles, n_regions,
+                            "thin-cell evaluation problem: %d cells, S%d, %d regions"
+                            % (n_cells, n_angles, n_regions), n_steps)
+
+
 def config5(idx, n_steps=20):
     """Problem idx of the ensemble: J = round(exp U[ln 500, ln 1e5]) cells, N
     uniform in {8, 16, 32, 64, 128}, 16 regions with draws as config 2

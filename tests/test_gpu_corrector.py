@@ -120,9 +120,9 @@ def test_training_on_solver_histories_lowers_heldout_error():
     from paper_2305_13555_amd import workloads
     slab = workloads.homogeneous_slab(16, 2000, 0.99, 0.05, 1.0)
     hist = []
-    with oci.OciContext(slab) as ctx:
+    with oci.OciContext(slab, tol=1e-13, max_iters=100000) as ctx:
         for _ in range(5):
-            phis, ref, info = C.step_history(ctx, slab, 16)
+            phis, ref, info = C.step_history(ctx, 16)
             hist.append((phis, ref))
             assert info["iterations"] > 100
             plain = [np.max(np.abs(ref - p)) for p in phis]
