@@ -80,6 +80,8 @@ enum { OCI_PREC_FP64 = 0, OCI_PREC_FP32 = 1 };
 
 /* flags */
 #define OCI_FLAG_STRICT 1u /* add the a-posteriori error bound to the stopping rule */
+#define OCI_FLAG_COMPACT 2u /* iterate rings of at most 64 MiB (at least 7 slots per step
+                               parity instead of 9): for many contexts side by side */
 
 #define OCI_MAX_ANGLES 256
 
@@ -195,6 +197,25 @@ int oci_solve(oci_ctx *c, int32_t n_steps, double *phi_out, int32_t phi_out_on_d
  * OCI_OK.  OCI_EINVAL: n_ctx < 1, a NULL or repeated context, n_steps < 0. */
 int oci_solve_batch(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, double **phi_out,
                     int32_t phi_out_on_device, oci_step_info **infos, int32_t n_threads);
+
+/* An ensemble of independent problems advanced together: n_steps OCI steps of
+ * every context, each step one launch per iteration over a device work queue
+ * of (problem, tile) entries covering every problem's tiles (a problem keeps
+ * its own operators, iterate rings, residual records and control block, so
+ * its iterates, stopping decisions and results are exactly those of its own
+ * single-iterate steps), then one end-of-step launch over all tiles; problems
+ * still undecided continue in further launches over their own tiles only
+ * (per-problem flags), while the decided ones wait for the next step.  All
+ * work goes to the first context's stream (the other contexts' streams are
+ * waited for first).  Contexts: distinct, OCI_PREC_FP64, no corrector, N a
+ * multiple of 8, all at the same step parity (e.g. all fresh).  phi_out: NULL
+ * or [n_ctx] device pointers (NULL entries allowed) receiving [n_steps][J][4];
+ * infos: NULL or [n_ctx] arrays of n_steps records (NULL entries allowed;
+ * ms is the whole ensemble's step time).  Returns OCI_OK, OCI_NOT_CONVERGED
+ * (some step of some context) or the first error (OCI_ENONFINITE abandons that
+ * context's step as oci_step does and stops the ensemble). */
+int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, double **phi_out,
+                       oci_step_info **infos);
 
 /* Scalar flux of the last completed step, [J][4] (host or device).
  * OCI_ESTATE before the first step. */

@@ -195,7 +195,7 @@ static int validate(const oci_problem *p, std::string *why) {
     return bad("precision must be OCI_PREC_FP64 or OCI_PREC_FP32");
   if (p->precision == OCI_PREC_FP32 && (p->flags & OCI_FLAG_STRICT))
     return bad("OCI_FLAG_STRICT needs OCI_PREC_FP64");
-  if (p->flags & ~OCI_FLAG_STRICT) return bad("unknown flags");
+  if (p->flags & ~(OCI_FLAG_STRICT | OCI_FLAG_COMPACT)) return bad("unknown flags");
   if (p->psi0) {
     for (long long i = 0; i < J * N * 2; ++i)
       if (!std::isfinite(p->psi0[i])) return bad("psi0 must be finite");
@@ -466,8 +466,12 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
     const size_t per = (c->out_stride + c->phi_stride) * sizeof(double);
     // 1 GiB of rings per context (so that many contexts fit side by side),
     // but at least 9 slots: batches of up to 8 iterates per step
-    const size_t budget = (size_t)1 << 30;
-    c->nbuf = (int)std::max<size_t>(9, std::min<size_t>(kMaxBatch + 1, budget / (2 * per)));
+    // (OCI_FLAG_COMPACT: 64 MiB and at least 7 slots, for many contexts at once)
+    const bool compact = (p->flags & OCI_FLAG_COMPACT) != 0;
+    const size_t budget = compact ? (size_t)64 << 20 : (size_t)1 << 30;
+    const size_t min_slots = compact ? 7 : 9;
+    c->nbuf = (int)std::max<size_t>(min_slots,
+                                    std::min<size_t>(kMaxBatch + 1, budget / (2 * per)));
   }
   const size_t nb_all = 2 * (size_t)c->nbuf + 2;   // two rings, two source-iteration buffers
   OCI_TRY(dalloc(c, &c->d_outb, nb_all * c->out_stride));
@@ -1554,6 +1558,214 @@ extern "C" int oci_solve_batch(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, do
   for (int i = 0; i < n_ctx; ++i) {
     if (rc[i] < 0) return rc[i];   // the context's own last error has the message
     if (rc[i] == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+// ---------------------------------------------------------------------------
+// Ensembles: one launch per iteration over the tiles of every problem
+// ---------------------------------------------------------------------------
+namespace {
+struct EnsembleBufs {
+  std::vector<void *> ptrs;
+  ~EnsembleBufs() {
+    for (void *q : ptrs) (void)hipFree(q);
+  }
+  template <class T>
+  hipError_t alloc(T **p, size_t n) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) {
+      ptrs.push_back(q);
+      *p = static_cast<T *>(q);
+    }
+    return e;
+  }
+};
+}  // namespace
+
+extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
+                                  double **phi_out, oci_step_info **infos) {
+  if (!ctx || n_ctx < 1) return fail(nullptr, OCI_EINVAL, "need at least one context");
+  if (n_steps < 0) return fail(nullptr, OCI_EINVAL, "n_steps must be >= 0");
+  for (int i = 0; i < n_ctx; ++i) {
+    oci_ctx *c = ctx[i];
+    if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+    for (int j = 0; j < i; ++j)
+      if (ctx[j] == c) return fail(nullptr, OCI_EINVAL, "contexts must be distinct");
+    if (c->mixed || c->corr) return fail(c, OCI_EINVAL, "ensembles take plain FP64 contexts");
+    if (c->N % 8) return fail(c, OCI_EINVAL, "ensembles take angle counts that are multiples of 8");
+    if (c->parity != ctx[0]->parity)
+      return fail(c, OCI_EINVAL, "ensemble contexts must be at the same step parity");
+  }
+  if (n_steps == 0) return OCI_OK;
+  oci_ctx *c0 = ctx[0];
+  const hipStream_t st = c0->stream;
+  for (int i = 0; i < n_ctx; ++i) OCI_CK(c0, hipStreamSynchronize(ctx[i]->stream));
+  // per problem: step records for the solve, step counter 0, psi buffer
+  size_t lds_pv = 0, lds_it = 0, lds_ed = 0;
+  int cap = kMaxBatch, nt_all = 0, nt_tiles = 0;
+  for (int i = 0; i < n_ctx; ++i) {
+    oci_ctx *c = ctx[i];
+    int rc = grow_records(c, n_steps);
+    if (rc) return rc;
+    c->h_ctl->cur = 0;
+    c->h_ctl->psi_base = c->parity;
+    OCI_CK(c, hipMemcpyAsync(&c->d_ctl->cur, &c->h_ctl->cur, 2 * sizeof(int32_t),
+                             hipMemcpyHostToDevice, st));
+    lds_pv = std::max(lds_pv, c->lds_pv);
+    lds_it = std::max(lds_it, c->lds_it);
+    lds_ed = std::max(lds_ed, c->lds_ed);
+    cap = std::min(cap, c->nbuf - 1);
+    nt_all += c->ntiles + 1;
+    nt_tiles += c->ntiles;
+  }
+  // device tables: argument blocks, result pointers, the work queues
+  EnsembleBufs db;
+  StepArgs *d_probs = nullptr;
+  double **d_phis = nullptr;
+  int2 *d_qall = nullptr, *d_qtiles = nullptr;
+  int *d_plist = nullptr;
+  OCI_CK(c0, db.alloc(&d_probs, n_ctx));
+  OCI_CK(c0, db.alloc(&d_phis, n_ctx));
+  OCI_CK(c0, db.alloc(&d_qall, nt_all));
+  OCI_CK(c0, db.alloc(&d_qtiles, nt_tiles));
+  OCI_CK(c0, db.alloc(&d_plist, n_ctx));
+  std::vector<StepArgs> probs(n_ctx);
+  std::vector<double *> phis(n_ctx, nullptr);
+  for (int i = 0; i < n_ctx; ++i) {
+    probs[i] = ctx[i]->sa;
+    phis[i] = phi_out ? phi_out[i] : nullptr;
+  }
+  // the queue of a set of problems: every tile (all: and each problem's
+  // reduction work-group) and the problem list; host copies kept until synced
+  std::vector<int2> qall, qtiles;
+  std::vector<int> plist;
+  auto build = [&](const std::vector<int> &set) -> int {
+    qall.clear();
+    qtiles.clear();
+    plist = set;
+    for (int i : set) {
+      for (int t = 0; t <= ctx[i]->ntiles; ++t) qall.push_back(make_int2(i, t));
+      for (int t = 0; t < ctx[i]->ntiles; ++t) qtiles.push_back(make_int2(i, t));
+    }
+    OCI_CK(c0, hipMemcpyAsync(d_qall, qall.data(), qall.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, st));
+    OCI_CK(c0, hipMemcpyAsync(d_qtiles, qtiles.data(), qtiles.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, st));
+    OCI_CK(c0, hipMemcpyAsync(d_plist, plist.data(), plist.size() * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+    return OCI_OK;
+  };
+  OCI_CK(c0, hipMemcpyAsync(d_probs, probs.data(), n_ctx * sizeof(StepArgs),
+                            hipMemcpyHostToDevice, st));
+  OCI_CK(c0, hipMemcpyAsync(d_phis, phis.data(), n_ctx * sizeof(double *),
+                            hipMemcpyHostToDevice, st));
+  for (void *fn : {(void *)kb_step_begin<4>, (void *)kb_oci_iterate<4>, (void *)kb_step_end<4>}) {
+    const size_t l = fn == (void *)kb_step_begin<4> ? lds_pv
+                                                     : (fn == (void *)kb_oci_iterate<4> ? lds_it
+                                                                                        : lds_ed);
+    OCI_CK(c0, hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)l));
+  }
+  std::vector<int> everyone(n_ctx);
+  for (int i = 0; i < n_ctx; ++i) everyone[i] = i;
+  int worst = OCI_OK;
+  int half = c0->parity;
+  const dim3 blk(256);
+  // launches over the current queue
+  auto iterate = [&](int node, int cb) -> int {
+    void *args[] = {&d_probs, &d_qall, &node, &cb, &half};
+    OCI_CK(c0, hipLaunchKernel((const void *)kb_oci_iterate<4>, dim3((unsigned)qall.size()), blk,
+                               args, lds_it, st));
+    return OCI_OK;
+  };
+  auto finish = [&](int first, int last) -> int {
+    int n = 1;
+    void *rargs[] = {&d_probs, &d_plist, &last, &n, &half};
+    OCI_CK(c0, hipLaunchKernel((const void *)kb_reduce_rec, dim3((unsigned)plist.size()), blk,
+                               rargs, 0, st));
+    double **ph = phi_out ? d_phis : nullptr;
+    int mode = 1 | (1 << 1);   // records reduced before; one trailing iterate
+    void *eargs[] = {&d_probs, &ph, &d_qtiles, &first, &last, &half, &mode};
+    OCI_CK(c0, hipLaunchKernel((const void *)kb_step_end<4>, dim3((unsigned)qtiles.size()), blk,
+                               eargs, lds_ed, st));
+    return OCI_OK;
+  };
+  for (int s = 0; s < n_steps; ++s) {
+    int rc = build(everyone);
+    if (rc) return rc;
+    OCI_CK(c0, hipEventRecord(c0->ev0, st));
+    bool need_begin = false;
+    int L = 1, lim = INT32_MAX;
+    for (int i = 0; i < n_ctx; ++i) {
+      need_begin |= !ctx[i]->gh_valid;
+      L = std::max(L, ctx[i]->batch_hint > 0 ? ctx[i]->batch_hint : kColdBatch);
+      lim = std::min(lim, ctx[i]->max_iters);
+    }
+    L = std::max(1, std::min({L, cap, lim}));
+    if (need_begin) {
+      void *bargs[] = {&d_probs, &d_qtiles};
+      OCI_CK(c0, hipLaunchKernel((const void *)kb_step_begin<4>, dim3((unsigned)qtiles.size()),
+                                 blk, bargs, lds_pv, st));
+      for (int i = 0; i < n_ctx; ++i) ctx[i]->gh_valid = true;
+    }
+    for (int l = 1; l <= L && rc == OCI_OK; ++l) rc = iterate(l, 0);
+    if (rc == OCI_OK) rc = finish(1, L);
+    if (rc) return rc;
+    OCI_CK(c0, hipStreamSynchronize(st));
+    // problems still undecided: further single-iterate launches over them alone
+    std::vector<int> open;
+    for (int i = 0; i < n_ctx; ++i) {
+      const int stt = ctx[i]->h_rec[s].status;
+      if (stt == kNonFinite) return abandon_step(ctx[i], infos && infos[i] ? &infos[i][s] : nullptr,
+                                                 ctx[i]->h_rec[s].accepted);
+      if (stt == kRunning) open.push_back(i);
+    }
+    int launched = L, extra = 0;
+    while (!open.empty()) {
+      int mi = INT32_MAX;
+      for (int i : open) {   // (on the ensemble's stream, before its launches)
+        mi = std::min(mi, ctx[i]->max_iters);
+        ctx[i]->h_ctl->stalled = 0;
+        OCI_CK(c0, hipMemcpyAsync(&ctx[i]->d_ctl->stalled, &ctx[i]->h_ctl->stalled,
+                                  sizeof(int32_t), hipMemcpyHostToDevice, st));
+      }
+      const int count = ocip::resumed_batch(++extra, launched, mi, cap + 1);
+      rc = build(open);
+      for (int l = 1; l <= count && rc == OCI_OK; ++l) rc = iterate(l, launched);
+      if (rc == OCI_OK) rc = finish(launched + 1, launched + count);
+      if (rc) return rc;
+      launched += count;
+      OCI_CK(c0, hipStreamSynchronize(st));
+      std::vector<int> still;
+      for (int i : open) {
+        const int stt = ctx[i]->h_rec[s].status;
+        if (stt == kNonFinite)
+          return abandon_step(ctx[i], infos && infos[i] ? &infos[i][s] : nullptr,
+                              ctx[i]->h_rec[s].accepted);
+        if (stt == kRunning) still.push_back(i);
+      }
+      open.swap(still);
+      if (launched > lim + 1 && !open.empty())
+        return fail(c0, OCI_EDEVICE, "an ensemble step did not reach a decision");
+    }
+    OCI_CK(c0, hipEventRecord(c0->ev1, st));
+    OCI_CK(c0, hipEventSynchronize(c0->ev1));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, c0->ev0, c0->ev1);
+    for (int i = 0; i < n_ctx; ++i) {
+      oci_ctx *c = ctx[i];
+      const StepRecord &r = c->h_rec[s];
+      const int status = r.status == kConverged ? OCI_OK : OCI_NOT_CONVERGED;
+      if (status == OCI_NOT_CONVERGED) worst = OCI_NOT_CONVERGED;
+      fill_info(infos && infos[i] ? &infos[i][s] : nullptr, r.accepted, status, r.e_last, ms, ms,
+                r.accepted, error_bound(r.e_last, r.e_prev));
+      complete_step(c, r.accepted);
+      c->batch_hint = std::max(r.accepted, 1);
+      c->window = 1;
+    }
+    half ^= 1;
   }
   return worst;
 }

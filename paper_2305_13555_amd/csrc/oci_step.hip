@@ -240,17 +240,19 @@ __device__ __forceinline__ d4 mma_rowtile_g(const double *Fr, int KS, bool first
 // read into few L2s and neighbouring tiles share an L2).  With ARGT the
 // packed descriptors travel in the kernel arguments: the descriptor load
 // issues with the other argument loads, and no data load waits on a table.
+// (wg: the tile index of this work-group within its problem: blockIdx.x,
+// or the entry of an ensemble launch's work queue)
 template <bool ARGT>
-__device__ __forceinline__ TileDev blk_desc(const StepArgs &a) {
+__device__ __forceinline__ TileDev blk_desc(const StepArgs &a, int wg) {
   TileDev t;
   if (ARGT) {
-    const uint32_t w = a.tile_word[blockIdx.x];
+    const uint32_t w = a.tile_word[wg];
     t.c0 = (int)(w & ((1u << kArgTileCellBits) - 1));
     t.nc = (int)((w >> kArgTileCellBits) & 15u) + 1;
     t.region = (int)(w >> 22);
     t.pad = 0;
   } else {
-    t = a.tiles[blockIdx.x];
+    t = a.tiles[wg];
   }
   return t;
 }
@@ -742,13 +744,18 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
 // psi_{k-1/2}.  Needed only where no end of step has computed it (the first
 // step of a queue).  Does nothing while a queued solve is stalled.
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void step_begin_body(const StepArgs &a, int wg, double *lds) {
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
   const int parity = c.psi_base ^ (c.cur & 1);
-  const TileDev t = blk_desc<ARGT>(a);
+  const TileDev t = blk_desc<ARGT>(a, wg);
   tile_begin<CH, VEC, NF>(a, t, parity ? a.psi1 : a.psi0, lds);
+}
+
+template <int CH, bool ARGT, bool VEC, int NF>
+__global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
+  extern __shared__ double lds[];
+  step_begin_body<CH, ARGT, VEC, NF>(a, blockIdx.x, lds);
 }
 
 // Iterate l = cb + node of the open step: always computed (the step's
@@ -765,8 +772,9 @@ __global__ __launch_bounds__(256) void k_step_begin(StepArgs a) {
 // the open step and the buffer of its iterate 0 for the end of step.  Stored
 // last in the launch: on this GPU a load issued after a store waits for that
 // store to complete.
-__device__ __forceinline__ void open_step(const StepArgs &a, int l, int cur, int fb, int stalled) {
-  if (l <= 2 && blockIdx.x == 0 && threadIdx.x == 0 && !stalled) {
+__device__ __forceinline__ void open_step(const StepArgs &a, int l, int cur, int fb, int stalled,
+                                          int wg) {
+  if (l <= 2 && wg == 0 && threadIdx.x == 0 && !stalled) {
     a.ctl->open = cur;
     a.ctl->base_buf = fb;
   }
@@ -787,12 +795,11 @@ __device__ inline void reduce_prev(const StepArgs &a, int l, int rstep, int nred
 }
 
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half,
-                                                        int rstep, int nred) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void oci_iterate_body(const StepArgs &a, int wg, double *lds, int node,
+                                                 int cb, int half, int rstep, int nred) {
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
   const int l = cb + node;
-  if (blockIdx.x == a.ntiles) {
+  if (wg == a.ntiles) {
     reduce_prev(a, l, rstep, nred, half, red, scratch);
     return;
   }
@@ -809,8 +816,8 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   double *dst = out_at(a, ring_buf(a, l, half));
   const double *phi_old = phi_at(a, b0);
   double *phi_new = phi_at(a, ring_buf(a, l, half));
-  const int ti = blockIdx.x;   // the tile's residual record
-  const TileDev t = blk_desc<ARGT>(a);
+  const int ti = wg;   // the tile's residual record
+  const TileDev t = blk_desc<ARGT>(a, wg);
   IterPrefetch<CH> pf;
   const GhOut none{};
   iterate_prefetch<CH, NF>(pf, a, t, src, phi_old, lds, none, false);
@@ -818,7 +825,14 @@ __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, in
   iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis, phif,
                       reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l, half) + ti,
                       stalled != 0, rstep == 2);
-  open_step(a, l, cur, fb, stalled);
+  open_step(a, l, cur, fb, stalled, wg);
+}
+
+template <int CH, bool ARGT, bool VEC, int NF>
+__global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half,
+                                                        int rstep, int nred) {
+  extern __shared__ double lds[];
+  oci_iterate_body<CH, ARGT, VEC, NF>(a, blockIdx.x, lds, node, cb, half, rstep, nred);
 }
 
 // ---------------------------------------------------------------------------
@@ -1020,7 +1034,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   const double *src = out_at(a, b0);
   const double *phi_old = phi_at(a, b0);
   const int b1 = ring_buf(a, l, half), b2 = ring_buf(a, l + 1, half);
-  const TileDev t = blk_desc<ARGT>(a);
+  const TileDev t = blk_desc<ARGT>(a, blockIdx.x);
   double *A = lds, *B = lds + kBlkA * P;
   const int ghp = sh.Mt * 16;
   // loads that need no LDS: the first operator chunk of this wave's share of
@@ -1099,7 +1113,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   own_phi<CH, VEC, NF>(a, t, B, fp, hv, vl, phis, phif, phi_at(a, b2), rv + 128);
   own_pairs<NF>(a, t, B, phif, cf, gq, out_at(a, b2), nullptr);
   flush_records(a, l, 2, half, rv);
-  open_step(a, l, cur, fb, stalled);
+  open_step(a, l, cur, fb, stalled, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1192,7 +1206,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
     reduce_prev(a, l, 1, nred, half, red, scratch);
     return;
   }
-  const TileDev t = blk_desc<ARGT>(a);
+  const TileDev t = blk_desc<ARGT>(a, blockIdx.x);
   // the staged regions: before, the tile's, after (clamped to the mesh)
   const int rg0 = max(t.region - 1, 0), rg2 = min(t.region + 1, a.R - 1);
   // (a select, not an indexed array: an array indexed at run time lives in
@@ -1332,7 +1346,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
                       s < KI ? row(out, t.c0 - 1) : nullptr);
     if (s == KI) {
       flush_records(a, l, KI, half, rv);
-      open_step(a, l, cur, fb, stalled);
+      open_step(a, l, cur, fb, stalled, blockIdx.x);
       break;
     }
     // the halo cells' outgoing rows (every angle: they feed the next level)
@@ -1391,7 +1405,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
 // The e of iterate l from its residual records into dec (one work-group),
 // for problems with many tiles, where every work-group of the end of step
 // reducing all records would cost ntiles^2 loads.
-__global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, int half) {
+__device__ __forceinline__ void reduce_rec_body(const StepArgs &a, int l, int n, int half) {
   __shared__ double red[2], scratch[2 * kMaxWaves];
   const int stalled = a.ctl->stalled;
   for (int j = l - n + 1; j <= l; ++j) {   // iterates l-n+1 .. l
@@ -1401,6 +1415,10 @@ __global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, in
     rec_finish(r1, recs, a.ntiles, red, scratch);
     if (threadIdx.x == 0 && !stalled) a.dec[j % a.nbuf] = rel_change(red[0], red[1]);
   }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, int half) {
+  reduce_rec_body(a, l, n, half);
 }
 
 // End of the open step after iterates first .. last of it were launched
@@ -1413,9 +1431,9 @@ __global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, in
 // instead: the host resumes it.  The step's record is written either way; a
 // decided step advances the solve's step counter.
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out, int first,
-                                                  int last, int half, int rstep, int mode) {
-  extern __shared__ double lds[];
+__device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double *lds,
+                                              double *phi_out, int first, int last, int half,
+                                              int rstep, int mode) {
   __shared__ double phis[4 * 64], phif[64];
   const bool pre = mode & 1, fuse = (mode >> 4) & 1;
   const int ntrail = (mode >> 1) & 7;   // iterates last-ntrail+1 .. last
@@ -1432,7 +1450,7 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
   const double dv1 = i1 < nd ? a.dec[(l0 + i1) % a.nbuf] : 0.0;
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
-  const TileDev t = blk_desc<ARGT>(a);
+  const TileDev t = blk_desc<ARGT>(a, wg);
   if (i0 < nd) sdec[i0] = dv0;
   if (i1 < nd) sdec[i1] = dv1;
   __syncthreads();
@@ -1511,8 +1529,11 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
   // the stopping rule stops at: every candidate judged by a thread of its
   // own (with the e of the candidate before it), the first one by an LDS min
   const int ncand = (last - first) / rstep + 1;
+  // (the lambdas capture locals only: a reference to the argument block
+  // captured by a closure would put a copy of it in scratch memory)
+  const int strict = a.strict;
   auto e_before_of = [&](int i, int l) {
-    if (i == 0) return (a.strict && first - 1 >= 2) ? e_of(first - 1) : -1.0;
+    if (i == 0) return (strict && first - 1 >= 2) ? e_of(first - 1) : -1.0;
     return l - rstep >= 2 ? e_of(l - rstep) : -1.0;
   };
   __shared__ int s_first;
@@ -1536,26 +1557,29 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
   const bool decided = status != kRunning && status != kNonFinite;
   // the outcome goes to fields no work-group of this launch reads (stored
   // after the work-group's loads: a load issued after a store waits for it)
+  StepCtl *const ct = a.ctl;
+  StepRecord *const rec = a.rec;
+  double *const dec = a.dec;
+  const int nbuf = a.nbuf, fin_buf = ring_buf(a, L, half);
   auto record = [&]() {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      StepCtl *ct = a.ctl;
+    if (wg == 0 && threadIdx.x == 0) {
       ct->fin_accepted = L;
       ct->fin_status = status;
       ct->fin_e = e_acc;
       ct->fin_e_prev = e_pacc;
-      if (a.rec) {
-        a.rec[step].accepted = L;
-        a.rec[step].status = status;
-        a.rec[step].e_last = e_acc;
-        a.rec[step].e_prev = e_pacc;
+      if (rec) {
+        rec[step].accepted = L;
+        rec[step].status = status;
+        rec[step].e_last = e_acc;
+        rec[step].e_prev = e_pacc;
       }
       if (decided) {
-        ct->fin_buf = ring_buf(a, L, half);
+        ct->fin_buf = fin_buf;
         ct->cur = step + 1;
       } else {
         ct->stalled = 1;
         for (int i = 0; i < ntrail; ++i)   // for the resumed end
-          a.dec[(last - i) % a.nbuf] = sdec[last - i - l0];
+          dec[(last - i) % nbuf] = sdec[last - i - l0];
       }
     }
   };
@@ -1585,10 +1609,18 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
   iterate_compute<CH, VEC, NF>(pf, a, t, out_at(a, bl), out_at(a, bn), phi_at(a, bn), lds, phis,
                                phif,
                                reinterpret_cast<double2 *>(a.partial) +
-                                   rec_slot(a, 1, half ^ 1) + blockIdx.x,
+                                   rec_slot(a, 1, half ^ 1) + wg,
                                false, rstep == 2);
   record();
 }
+
+template <int CH, bool ARGT, bool VEC, int NF>
+__global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out, int first,
+                                                  int last, int half, int rstep, int mode) {
+  extern __shared__ double lds[];
+  step_end_body<CH, ARGT, VEC, NF>(a, blockIdx.x, lds, phi_out, first, last, half, rstep, mode);
+}
+
 
 // ---------------------------------------------------------------------------
 // Mixed precision: FP64 defect correction with FP32 inner iterations
@@ -1631,7 +1663,7 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
   const int W = (int)(blockDim.x >> 6);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kq = lane >> 4;
-  const TileDev t = blk_desc<ARGT>(a);
+  const TileDev t = blk_desc<ARGT>(a, blockIdx.x);
   const float *src = a.dlt + (size_t)(i == 1 ? 0 : ((i & 1) ? 2 : 1)) * a.dlt_stride;
   float *dst = a.dlt + (size_t)((i & 1) ? 1 : 2) * a.dlt_stride;
   const float *dd = a.dlt;   // the defect d
@@ -1790,7 +1822,7 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
       *reinterpret_cast<float2 *>(dst + (cell + 1) * K + 2 * m) = make_float2(o0, o1);
     }
   }
-  if (opens) open_step(a, 1, cur, fb, stalled);
+  if (opens) open_step(a, 1, cur, fb, stalled, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1848,6 +1880,51 @@ __global__ __launch_bounds__(256) void k_learn_apply(StepArgs a, int l, int half
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Ensembles: one launch over the tiles of many problems
+// ---------------------------------------------------------------------------
+// A work queue of (problem, tile) entries (tile = the problem's tile count:
+// its residual-reduction work-group) replaces blockIdx.x; every problem keeps
+// its own argument block (probs[problem], in device memory), rings, records
+// and control block, so each problem's iterates, decisions and end of step
+// are exactly those of its own launches.  Built for any N (a multiple of 8)
+// with 256 threads per work-group.
+template <int CH>
+__global__ __launch_bounds__(256) void kb_step_begin(const StepArgs *probs, const int2 *queue) {
+  extern __shared__ double lds[];
+  const int2 q = queue[blockIdx.x];
+  step_begin_body<CH, false, true, 0>(probs[q.x], q.y, lds);
+}
+
+template <int CH>
+__global__ __launch_bounds__(256, 3) void kb_oci_iterate(const StepArgs *probs, const int2 *queue,
+                                                         int node, int cb, int half) {
+  extern __shared__ double lds[];
+  const int2 q = queue[blockIdx.x];
+  oci_iterate_body<CH, false, true, 0>(probs[q.x], q.y, lds, node, cb, half, 1, 1);
+}
+
+// (one work-group per listed problem)
+__global__ __launch_bounds__(256) void kb_reduce_rec(const StepArgs *probs, const int *plist, int l,
+                                                     int n, int half) {
+  reduce_rec_body(probs[plist[blockIdx.x]], l, n, half);
+}
+
+template <int CH>
+__global__ __launch_bounds__(256, 3) void kb_step_end(const StepArgs *probs, double *const *phi_outs,
+                                                      const int2 *queue, int first, int last,
+                                                      int half, int mode) {
+  extern __shared__ double lds[];
+  const int2 q = queue[blockIdx.x];
+  step_end_body<CH, false, true, 0>(probs[q.x], q.y, lds, phi_outs ? phi_outs[q.x] : nullptr,
+                                    first, last, half, 1, mode);
+}
+
+template __global__ void kb_step_begin<4>(const StepArgs *, const int2 *);
+template __global__ void kb_oci_iterate<4>(const StepArgs *, const int2 *, int, int, int);
+template __global__ void kb_step_end<4>(const StepArgs *, double *const *, const int2 *, int, int,
+                                        int, int);
 
 template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int, int);

@@ -27,6 +27,7 @@ OCI_BC_VACUUM, OCI_BC_REFLECT, OCI_BC_INCIDENT = 0, 1, 2
 OCI_PREC_FP64 = 0
 OCI_PREC_FP32 = 1
 OCI_FLAG_STRICT = 1
+OCI_FLAG_COMPACT = 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -86,6 +87,9 @@ def _load():
                                            ctypes.POINTER(vp), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.POINTER(oci_step_info)),
                                            ctypes.c_int32]),
+        "oci_solve_ensemble": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.POINTER(vp),
+                                              ctypes.POINTER(ctypes.POINTER(oci_step_info))]),
         "oci_get_flux": (ctypes.c_int, [vp, vp, ctypes.c_int32]),
         "oci_get_state": (ctypes.c_int, [vp, _dp, ctypes.POINTER(ctypes.c_int64)]),
         "oci_set_state": (ctypes.c_int, [vp, _dp, ctypes.c_int64]),
@@ -161,7 +165,7 @@ def oci_gauss_legendre(n):
     return mu, w
 
 
-def make_problem(prob, tol=None, max_iters=None, strict=None, precision=None):
+def make_problem(prob, tol=None, max_iters=None, strict=None, precision=None, compact=False):
     """Marshal a problem description (attributes as in the workloads module)
     into the C struct.  Returns (struct, keepalive) - keep both alive."""
     keep = {
@@ -195,13 +199,14 @@ def make_problem(prob, tol=None, max_iters=None, strict=None, precision=None):
     p.precision = int(getattr(prob, "precision", OCI_PREC_FP64) if precision is None
                       else precision)
     st = bool(getattr(prob, "strict", False) if strict is None else strict)
-    p.flags = OCI_FLAG_STRICT if st else 0
+    p.flags = (OCI_FLAG_STRICT if st else 0) | (OCI_FLAG_COMPACT if compact else 0)
     return p, keep
 
 
-def oci_setup(prob, stream=None, tol=None, max_iters=None, strict=None, precision=None):
+def oci_setup(prob, stream=None, tol=None, max_iters=None, strict=None, precision=None,
+              compact=False):
     """Build a context for the problem; returns the raw handle (c_void_p)."""
-    p, keep = make_problem(prob, tol, max_iters, strict, precision)
+    p, keep = make_problem(prob, tol, max_iters, strict, precision, compact)
     h = ctypes.c_void_p()
     _check(_lib.oci_setup(ctypes.byref(p), _stream_handle(stream), ctypes.byref(h)))
     del keep
@@ -276,6 +281,34 @@ def oci_solve_batch(ctxs, n_steps, phi_outs=None, n_threads=0):
     return rc, [[a[i].as_dict() for i in range(int(n_steps))] for a in arrays]
 
 
+def oci_solve_ensemble(ctxs, n_steps, phi_outs=None):
+    """n_steps OCI steps of every context (OciContext or handle) advanced together,
+    one launch per iteration over all their tiles (work on the first context's
+    stream); phi_outs: None or one CUDA tensor [n_steps][J][4] (or None) per
+    context.  Returns (rc, [infos per context])."""
+    n = len(ctxs)
+    vp = ctypes.c_void_p
+    handles = (vp * n)(*[c.handle if isinstance(c, OciContext) else c for c in ctxs])
+    phi_arr = None
+    if phi_outs is not None:
+        ptrs = []
+        for o in phi_outs:
+            p, dev = _out_pointer(o)
+            if p is not None and not dev:
+                raise ValueError("ensemble outputs must be device tensors")
+            ptrs.append(p)
+        phi_arr = (vp * n)(*ptrs)
+    steps = max(int(n_steps), 1)
+    arrays = [(oci_step_info * steps)() for _ in range(n)]
+    infos = (ctypes.POINTER(oci_step_info) * n)(
+        *[ctypes.cast(a, ctypes.POINTER(oci_step_info)) for a in arrays])
+    rc = _lib.oci_solve_ensemble(handles, n, int(n_steps), phi_arr, infos)
+    if rc < 0:
+        msgs = [(_lib.oci_last_error(h) or b"").decode() for h in handles]
+        raise OciError(rc, "; ".join(m for m in msgs if m) or "ensemble solve failed")
+    return rc, [[a[i].as_dict() for i in range(int(n_steps))] for a in arrays]
+
+
 def oci_get_sizes(ctx):
     n, j, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(_lib.oci_get_sizes(ctx, ctypes.byref(n), ctypes.byref(j), ctypes.byref(r)), ctx)
@@ -346,9 +379,9 @@ class OciContext:
     """Owning wrapper around a context handle."""
 
     def __init__(self, prob, stream=None, tol=None, max_iters=None, strict=None,
-                 precision=None):
+                 precision=None, compact=False):
         self.precision = precision
-        self.handle = oci_setup(prob, stream, tol, max_iters, strict, precision)
+        self.handle = oci_setup(prob, stream, tol, max_iters, strict, precision, compact)
         self.n_angles, self.n_cells, self.n_regions = oci_get_sizes(self.handle)
         self.iterates_per_launch = oci_iterates_per_launch(self.handle)
 

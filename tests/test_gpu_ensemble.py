@@ -1,0 +1,113 @@
+"""Ensembles (oci_solve_ensemble): one launch per iteration over a work queue of
+(problem, tile) entries of many independent problems, against the FP64 oracle.
+
+Each problem keeps its own operators, rings, records and control block, so
+its iterates and stopping decisions are those of its own steps: fixed
+iteration counts agree with the oracle to 1e-11 (rounding order), converged
+steps with the same stopping rule to 1e-10 with iteration counts within one.
+The mix has every angle count of the ensemble generator (S8 .. S128), a
+slowly converging thin slab (its steps continue alone after the others are
+decided) and problems of compact rings.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oci as ooci
+from oracle.problem import cell_data
+from paper_2305_13555_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_13555_amd import oci
+    return oci
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b))) / float(np.max(np.abs(b)))
+
+
+def mix(n_steps):
+    ps = [dataclasses.replace(W.config5(i), n_steps=n_steps) for i in (7, 57, 9, 5, 2, 30)]
+    ps.append(dataclasses.replace(W.homogeneous_slab(8, 300, 0.99, 0.05, 1.0), n_steps=n_steps))
+    ps.append(W.layout_case(3, [5, 33, 2, 40], 16, (W.VACUUM, W.INCIDENT)))
+    return ps
+
+
+def run(lib, probs, n_steps, compact=False, **kw):
+    import torch
+    ctxs = [lib.OciContext(p, compact=compact and i % 2 == 0, **kw) for i, p in enumerate(probs)]
+    try:
+        outs = [torch.zeros((n_steps, p.n_cells, 4), dtype=torch.float64, device="cuda")
+                for p in probs]
+        rc, infos = lib.oci_solve_ensemble(ctxs, n_steps, outs)
+        return rc, [o.cpu().numpy() for o in outs], infos
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+@pytest.mark.parametrize("iters", [1, 3, 6])
+def test_ensemble_fixed_iterations_match_oracle(lib, iters):
+    probs = mix(2)
+    rc, phis, infos = run(lib, probs, 2, tol=0.0, max_iters=iters)
+    assert rc == lib.OCI_NOT_CONVERGED
+    for p, phi, inf in zip(probs, phis, infos):
+        ref = ooci.run_oci(p, cell_data(p), 2, tol=0.0, max_iters=iters)
+        for k in range(2):
+            assert inf[k]["iterations"] == iters
+            assert rel(phi[k], ref[k]["phi"]) < 1e-11, (p.name, k)
+
+
+@pytest.mark.parametrize("compact", [False, True])
+def test_ensemble_converged_steps_match_oracle(lib, compact):
+    probs = mix(3)
+    rc, phis, infos = run(lib, probs, 3, compact=compact, tol=1e-10, max_iters=50000)
+    assert rc == lib.OCI_OK
+    for p, phi, inf in zip(probs, phis, infos):
+        ref = ooci.run_oci(p, cell_data(p), 3, tol=1e-10, max_iters=50000)
+        for k in range(3):
+            assert abs(inf[k]["iterations"] - ref[k]["iterations"]) <= 1, (p.name, k)
+            assert rel(phi[k], ref[k]["phi"]) < 1e-10, (p.name, k)
+    # the thin slab needs far more iterations than the rest: continued alone
+    its = [inf[0]["iterations"] for inf in infos]
+    assert max(its) > 10 * min(its)
+
+
+def test_ensemble_then_ordinary_steps_continue(lib):
+    """After an ensemble solve every context continues with its own steps."""
+    probs = mix(4)[:3]
+    ctxs = [lib.OciContext(p, tol=1e-10) for p in probs]
+    try:
+        lib.oci_solve_ensemble(ctxs, 2)
+        for p, c in zip(probs, ctxs):
+            c.step()
+            ref = ooci.run_oci(p, cell_data(p), 3, tol=1e-10, max_iters=1000)
+            assert rel(c.flux(), ref[2]["phi"]) < 1e-10
+            assert c.state()[1] == 3
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+def test_ensemble_rejects_unsupported_contexts(lib):
+    a = lib.OciContext(W.config5(7, n_steps=2))
+    odd = lib.OciContext(W.random_small(3, n_angles=6, n_cells=20))
+    mixed = lib.OciContext(W.config5(57, n_steps=2), precision=lib.OCI_PREC_FP32)
+    b = lib.OciContext(W.config5(9, n_steps=2))
+    try:
+        for bad in ([a, odd], [a, mixed], [a, a]):
+            with pytest.raises(lib.OciError):
+                lib.oci_solve_ensemble(bad, 1)
+        b.step()   # other step parity
+        with pytest.raises(lib.OciError):
+            lib.oci_solve_ensemble([a, b], 1)
+    finally:
+        for c in (a, odd, mixed, b):
+            c.close()
