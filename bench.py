@@ -337,44 +337,76 @@ def learned_case(oci, torch, stream, n_steps=2, tol=1e-6, first=10, period=20):
     return out
 
 
-def ensemble_case(oci, torch, n_problems=32):
-    """Batched ensemble: problems 0 .. n_problems-1 of the ensemble generator
-    (500 - 100,000 cells log-uniform, S8 - S128, 16 regions, 20 steps, tol
-    1e-10), each context on its own stream.  Cell-angle updates per second
-    over the whole ensemble solved one problem after another, and with
-    oci_solve_batch driving the problems concurrently (each after a warm-up
-    solve of the same problems)."""
+def ensemble_case(oci, torch, n_problems=512, chunk=128, n_check=8):
+    """The batched ensemble: problems 0 .. n_problems-1 of the ensemble
+    generator (500 - 100,000 cells log-uniform, S8 - S128, 16 regions, 20
+    steps, tol 1e-10), in groups of `chunk` contexts (compact iterate rings;
+    all 512 side by side would need about 150 GB).  Per group, after a warm-up
+    of each mode, the same 20 steps of every problem: one problem after
+    another (each context's own queued solve), driven by host threads (one
+    stream per context), and as one ensemble (oci_solve_ensemble: one launch
+    per iteration over the work queue of all the group's tiles).  Cell-angle
+    updates per second over all problems, and the ensemble's scalar flux of
+    the first two steps of n_check sampled problems against the oracle."""
     from paper_2305_13555_amd import workloads
+    from oracle import oci as ooci
+    from oracle.problem import cell_data
     probs = [workloads.config5(i) for i in range(n_problems)]
     T = probs[0].n_steps
-    streams = [torch.cuda.Stream() for _ in probs]
-    ctxs = [oci.OciContext(p, stream=s) for p, s in zip(probs, streams)]
-    try:
-        oci.oci_solve_batch(ctxs, T)
-        out = {"workload": "%d ensemble problems (%d - %d cells, S8 - S128, 16 regions), "
-                           "%d steps each, tol 1e-10" % (
-                               n_problems, min(p.n_cells for p in probs),
-                               max(p.n_cells for p in probs), T),
-               "cell_angle_pairs": int(sum(p.n_cells * p.n_angles for p in probs))}
-        for mode in ("sequential", "batch"):
+    # sampled problems for the oracle: small enough for it (J * N <= 1e6)
+    check = [i for i, p in enumerate(probs) if p.n_cells * p.n_angles <= 1e6][:n_check]
+    secs = {"sequential": 0.0, "threads": 0.0, "ensemble": 0.0}
+    upd = {k: 0 for k in secs}
+    worst = 0.0
+    for g0 in range(0, n_problems, chunk):
+        group = list(range(g0, min(n_problems, g0 + chunk)))
+        streams = [torch.cuda.Stream() for _ in group]
+        ctxs = [oci.OciContext(probs[i], stream=s, compact=True) for i, s in zip(group, streams)]
+        outs = [torch.zeros((2, probs[i].n_cells, 4), dtype=torch.float64, device="cuda")
+                if i in check else None for i in group]
+        try:
+            for mode in ("sequential", "threads", "ensemble"):
+                for rep in range(2):   # a warm-up, then the timed run
+                    for c in ctxs:
+                        c.set_state(None, 0)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    if mode == "sequential":
+                        infos = [c.solve(T)[1] for c in ctxs]
+                    elif mode == "threads":
+                        infos = oci.oci_solve_batch(ctxs, T)[1]
+                    else:
+                        infos = oci.oci_solve_ensemble(ctxs, T)[1]
+                    torch.cuda.synchronize()
+                    if rep == 1:
+                        secs[mode] += time.perf_counter() - t
+                        upd[mode] += sum(inf["iterations"] * probs[i].n_cells * probs[i].n_angles
+                                         for i, per in zip(group, infos) for inf in per)
+            if any(i in check for i in group):   # the ensemble's first two steps vs the oracle
+                for c in ctxs:
+                    c.set_state(None, 0)
+                oci.oci_solve_ensemble(ctxs, 2, outs)
+                for i, o in zip(group, outs):
+                    if o is None:
+                        continue
+                    ref = ooci.run_oci(probs[i], cell_data(probs[i]), 2, tol=1e-10,
+                                       max_iters=1000)
+                    got = o.cpu().numpy()
+                    worst = max(worst, max(rel_err(got[k], ref[k]["phi"]) for k in range(2)))
+        finally:
             for c in ctxs:
-                c.set_state(None, 0)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            if mode == "sequential":
-                infos = [c.solve(T)[1] for c in ctxs]
-            else:
-                infos = oci.oci_solve_batch(ctxs, T)[1]
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t
-            upd = sum(i["iterations"] * p.n_cells * p.n_angles
-                      for p, inf in zip(probs, infos) for i in inf)
-            out[mode] = {"seconds": wall, "cell_angle_updates_per_s": upd / wall}
-        out["batch_speedup"] = out["sequential"]["seconds"] / out["batch"]["seconds"]
-        return out
-    finally:
-        for c in ctxs:
-            c.close()
+                c.close()
+            torch.cuda.empty_cache()
+    out = {"workload": "%d ensemble problems (S8 - S128, 16 regions, %d - %d cells, %d in all), "
+                       "%d steps each, tol 1e-10, in groups of %d" % (
+                           n_problems, min(p.n_cells for p in probs),
+                           max(p.n_cells for p in probs), sum(p.n_cells for p in probs), T, chunk),
+           "oracle_check": {"problems": check, "steps": 2, "max_rel_vs_oracle": worst}}
+    for k in secs:
+        out[k] = {"seconds": secs[k], "cell_angle_updates_per_s": upd[k] / secs[k]}
+    out["ensemble_speedup_vs_sequential"] = secs["sequential"] / secs["ensemble"]
+    out["threads_speedup_vs_sequential"] = secs["sequential"] / secs["threads"]
+    return out
 
 
 def main():
@@ -391,6 +423,8 @@ def main():
                          "64 MiB copy (for hardware-counter runs)")
     ap.add_argument("--learned-only", action="store_true",
                     help="only the learned corrector on the thin-cell evaluation problem")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the 512-problem ensemble")
     ap.add_argument("--workload", choices=["large", "bench16"], default="large",
                     help="with --roofline-only: the 200,000-cell S_64 problem or the "
                          "10,000-cell S_32 one")
@@ -417,6 +451,9 @@ def main():
 
     if args.learned_only:
         print(json.dumps(learned_case(oci, torch, stream)))
+        return
+    if args.ensemble_only:
+        print(json.dumps(ensemble_case(oci, torch)))
         return
     prob = workloads.config3()
     J, N, T = prob.n_cells, prob.n_angles, prob.n_steps

@@ -1625,7 +1625,9 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
   StepArgs *d_probs = nullptr;
   double **d_phis = nullptr;
   int2 *d_qall = nullptr, *d_qtiles = nullptr;
-  int *d_plist = nullptr;
+  int *d_plist = nullptr, *d_first = nullptr, *d_last = nullptr;
+  OCI_CK(c0, db.alloc(&d_first, n_ctx));
+  OCI_CK(c0, db.alloc(&d_last, n_ctx));
   OCI_CK(c0, db.alloc(&d_probs, n_ctx));
   OCI_CK(c0, db.alloc(&d_phis, n_ctx));
   OCI_CK(c0, db.alloc(&d_qall, nt_all));
@@ -1640,7 +1642,7 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
   // the queue of a set of problems: every tile (all: and each problem's
   // reduction work-group) and the problem list; host copies kept until synced
   std::vector<int2> qall, qtiles;
-  std::vector<int> plist;
+  std::vector<int> plist, first(n_ctx, 1), last(n_ctx, 1);
   auto build = [&](const std::vector<int> &set) -> int {
     qall.clear();
     qtiles.clear();
@@ -1655,6 +1657,10 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
                               hipMemcpyHostToDevice, st));
     OCI_CK(c0, hipMemcpyAsync(d_plist, plist.data(), plist.size() * sizeof(int),
                               hipMemcpyHostToDevice, st));
+    OCI_CK(c0, hipMemcpyAsync(d_first, first.data(), n_ctx * sizeof(int),
+                              hipMemcpyHostToDevice, st));
+    OCI_CK(c0, hipMemcpyAsync(d_last, last.data(), n_ctx * sizeof(int), hipMemcpyHostToDevice,
+                              st));
     return OCI_OK;
   };
   OCI_CK(c0, hipMemcpyAsync(d_probs, probs.data(), n_ctx * sizeof(StepArgs),
@@ -1674,44 +1680,46 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
   int half = c0->parity;
   const dim3 blk(256);
   // launches over the current queue
-  auto iterate = [&](int node, int cb) -> int {
-    void *args[] = {&d_probs, &d_qall, &node, &cb, &half};
+  auto iterate = [&](int node) -> int {
+    void *args[] = {&d_probs, &d_qall, &d_first, &d_last, &node, &half};
     OCI_CK(c0, hipLaunchKernel((const void *)kb_oci_iterate<4>, dim3((unsigned)qall.size()), blk,
                                args, lds_it, st));
     return OCI_OK;
   };
-  auto finish = [&](int first, int last) -> int {
+  auto finish = [&]() -> int {
     int n = 1;
-    void *rargs[] = {&d_probs, &d_plist, &last, &n, &half};
+    void *rargs[] = {&d_probs, &d_plist, &d_last, &n, &half};
     OCI_CK(c0, hipLaunchKernel((const void *)kb_reduce_rec, dim3((unsigned)plist.size()), blk,
                                rargs, 0, st));
     double **ph = phi_out ? d_phis : nullptr;
     int mode = 1 | (1 << 1);   // records reduced before; one trailing iterate
-    void *eargs[] = {&d_probs, &ph, &d_qtiles, &first, &last, &half, &mode};
+    void *eargs[] = {&d_probs, &ph, &d_qtiles, &d_first, &d_last, &half, &mode};
     OCI_CK(c0, hipLaunchKernel((const void *)kb_step_end<4>, dim3((unsigned)qtiles.size()), blk,
                                eargs, lds_ed, st));
     return OCI_OK;
   };
   for (int s = 0; s < n_steps; ++s) {
+    // each problem's planned iterates: its count of the previous step
+    bool need_begin = false;
+    int L = 1;
+    for (int i = 0; i < n_ctx; ++i) {
+      need_begin |= !ctx[i]->gh_valid;
+      const int want = ctx[i]->batch_hint > 0 ? ctx[i]->batch_hint : kColdBatch;
+      first[i] = 1;
+      last[i] = std::max(1, std::min({want, cap, ctx[i]->max_iters}));
+      L = std::max(L, last[i]);
+    }
     int rc = build(everyone);
     if (rc) return rc;
     OCI_CK(c0, hipEventRecord(c0->ev0, st));
-    bool need_begin = false;
-    int L = 1, lim = INT32_MAX;
-    for (int i = 0; i < n_ctx; ++i) {
-      need_begin |= !ctx[i]->gh_valid;
-      L = std::max(L, ctx[i]->batch_hint > 0 ? ctx[i]->batch_hint : kColdBatch);
-      lim = std::min(lim, ctx[i]->max_iters);
-    }
-    L = std::max(1, std::min({L, cap, lim}));
     if (need_begin) {
       void *bargs[] = {&d_probs, &d_qtiles};
       OCI_CK(c0, hipLaunchKernel((const void *)kb_step_begin<4>, dim3((unsigned)qtiles.size()),
                                  blk, bargs, lds_pv, st));
       for (int i = 0; i < n_ctx; ++i) ctx[i]->gh_valid = true;
     }
-    for (int l = 1; l <= L && rc == OCI_OK; ++l) rc = iterate(l, 0);
-    if (rc == OCI_OK) rc = finish(1, L);
+    for (int l = 1; l <= L && rc == OCI_OK; ++l) rc = iterate(l);
+    if (rc == OCI_OK) rc = finish();
     if (rc) return rc;
     OCI_CK(c0, hipStreamSynchronize(st));
     // problems still undecided: further single-iterate launches over them alone
@@ -1722,21 +1730,25 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
                                                  ctx[i]->h_rec[s].accepted);
       if (stt == kRunning) open.push_back(i);
     }
-    int launched = L, extra = 0;
+    // undecided problems (each ran its planned iterates 1 .. last[i]) go on
+    // from there, in batches of 1, 1, 2, 4, ... iterates (as a resumed step)
+    int extra = 0;
     while (!open.empty()) {
-      int mi = INT32_MAX;
+      ++extra;
+      int count = 1;
       for (int i : open) {   // (on the ensemble's stream, before its launches)
-        mi = std::min(mi, ctx[i]->max_iters);
         ctx[i]->h_ctl->stalled = 0;
         OCI_CK(c0, hipMemcpyAsync(&ctx[i]->d_ctl->stalled, &ctx[i]->h_ctl->stalled,
                                   sizeof(int32_t), hipMemcpyHostToDevice, st));
+        const int n = ocip::resumed_batch(extra, last[i], ctx[i]->max_iters, ctx[i]->nbuf);
+        first[i] = last[i] + 1;
+        last[i] += n;
+        count = std::max(count, n);
       }
-      const int count = ocip::resumed_batch(++extra, launched, mi, cap + 1);
       rc = build(open);
-      for (int l = 1; l <= count && rc == OCI_OK; ++l) rc = iterate(l, launched);
-      if (rc == OCI_OK) rc = finish(launched + 1, launched + count);
+      for (int l = 1; l <= count && rc == OCI_OK; ++l) rc = iterate(l);
+      if (rc == OCI_OK) rc = finish();
       if (rc) return rc;
-      launched += count;
       OCI_CK(c0, hipStreamSynchronize(st));
       std::vector<int> still;
       for (int i : open) {
@@ -1747,8 +1759,9 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
         if (stt == kRunning) still.push_back(i);
       }
       open.swap(still);
-      if (launched > lim + 1 && !open.empty())
-        return fail(c0, OCI_EDEVICE, "an ensemble step did not reach a decision");
+      for (int i : open)
+        if (last[i] > ctx[i]->max_iters + 1)
+          return fail(c0, OCI_EDEVICE, "an ensemble step did not reach a decision");
     }
     OCI_CK(c0, hipEventRecord(c0->ev1, st));
     OCI_CK(c0, hipEventSynchronize(c0->ev1));

@@ -164,17 +164,22 @@ __global__ void k_oci_inner(StepArgs a, int i, int ly, int half, int opens);
 // Ensembles: the same step kernels (any N, a multiple of 8; 256 threads) over
 // a work queue of (problem, tile) entries, each problem with its own argument
 // block probs[problem]; a tile entry equal to the problem's tile count is its
-// residual-reduction work-group (kb_oci_iterate).  kb_reduce_rec: one
-// work-group per problem of plist.  kb_step_end: phi_outs[problem] (or
-// NULL) receives the accepted scalar flux as phi_out does in k_step_end;
-// single-iterate launches (rstep 1).
+// residual-reduction work-group (kb_oci_iterate).  first[problem] ..
+// last[problem]: the iterates of the current batch of that problem (launch
+// `node` computes iterate first + node - 1; launches past last leave it idle;
+// the end of step judges first .. last).  kb_reduce_rec: one work-group per
+// problem of plist.  kb_step_end: phi_outs[problem] (or NULL) receives the
+// accepted scalar flux as phi_out does in k_step_end; single-iterate
+// launches (rstep 1).
 template <int CH> __global__ void kb_step_begin(const StepArgs *probs, const int2 *queue);
 template <int CH>
-__global__ void kb_oci_iterate(const StepArgs *probs, const int2 *queue, int node, int cb, int half);
-__global__ void kb_reduce_rec(const StepArgs *probs, const int *plist, int l, int n, int half);
+__global__ void kb_oci_iterate(const StepArgs *probs, const int2 *queue, const int *first,
+                               const int *last, int node, int half);
+__global__ void kb_reduce_rec(const StepArgs *probs, const int *plist, const int *last, int n,
+                              int half);
 template <int CH>
 __global__ void kb_step_end(const StepArgs *probs, double *const *phi_outs, const int2 *queue,
-                            int first, int last, int half, int mode);
+                            const int *first, const int *last, int half, int mode);
 // Learned corrections of iterate l of the open step (ring half `half`): the
 // corrector's FP32 input (ch = 8 or 12 channels; amp: the extrapolation
 // factor of channels 8..11) from the scalar fluxes of iterates l-2 .. l, and

@@ -1897,34 +1897,42 @@ __global__ __launch_bounds__(256) void kb_step_begin(const StepArgs *probs, cons
   step_begin_body<CH, false, true, 0>(probs[q.x], q.y, lds);
 }
 
+// (first[problem] .. last[problem]: the iterates planned for the problem in
+// this batch; launch `node` computes iterate first + node - 1, and the
+// launches past last leave the problem's work-groups idle)
 template <int CH>
 __global__ __launch_bounds__(256, 3) void kb_oci_iterate(const StepArgs *probs, const int2 *queue,
-                                                         int node, int cb, int half) {
+                                                         const int *first, const int *last,
+                                                         int node, int half) {
   extern __shared__ double lds[];
   const int2 q = queue[blockIdx.x];
+  const int cb = first[q.x] - 1;
+  if (cb + node > last[q.x]) return;
   oci_iterate_body<CH, false, true, 0>(probs[q.x], q.y, lds, node, cb, half, 1, 1);
 }
 
 // (one work-group per listed problem)
-__global__ __launch_bounds__(256) void kb_reduce_rec(const StepArgs *probs, const int *plist, int l,
-                                                     int n, int half) {
-  reduce_rec_body(probs[plist[blockIdx.x]], l, n, half);
+__global__ __launch_bounds__(256) void kb_reduce_rec(const StepArgs *probs, const int *plist,
+                                                     const int *last, int n, int half) {
+  const int p = plist[blockIdx.x];
+  reduce_rec_body(probs[p], last[p], n, half);
 }
 
 template <int CH>
 __global__ __launch_bounds__(256, 3) void kb_step_end(const StepArgs *probs, double *const *phi_outs,
-                                                      const int2 *queue, int first, int last,
-                                                      int half, int mode) {
+                                                      const int2 *queue, const int *first,
+                                                      const int *last, int half, int mode) {
   extern __shared__ double lds[];
   const int2 q = queue[blockIdx.x];
   step_end_body<CH, false, true, 0>(probs[q.x], q.y, lds, phi_outs ? phi_outs[q.x] : nullptr,
-                                    first, last, half, 1, mode);
+                                    first[q.x], last[q.x], half, 1, mode);
 }
 
 template __global__ void kb_step_begin<4>(const StepArgs *, const int2 *);
-template __global__ void kb_oci_iterate<4>(const StepArgs *, const int2 *, int, int, int);
-template __global__ void kb_step_end<4>(const StepArgs *, double *const *, const int2 *, int, int,
-                                        int, int);
+template __global__ void kb_oci_iterate<4>(const StepArgs *, const int2 *, const int *,
+                                           const int *, int, int);
+template __global__ void kb_step_end<4>(const StepArgs *, double *const *, const int2 *,
+                                        const int *, const int *, int, int);
 
 template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int, int);
