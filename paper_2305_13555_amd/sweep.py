@@ -11,11 +11,16 @@ GRID) and v = 1.
 Each point solves the five steps once with OCI (queued solve) and once with
 SI (step by step) on one context each, after a warm-up solve, and records the
 wall times, the iterations per step and the largest relative difference of
-the two final scalar fluxes (both are converged to the same tolerance, so
-the difference is of the order of the tolerance times the contraction).
+the two final scalar fluxes.  Both stop by the strict rule (change e <= tol
+and the a-posteriori bound e rho / (1 - rho) <= tol), so both reach the same
+accuracy even where one contracts far more slowly than the other.  With
+check_oracle, the point's five steps are also solved by the FP64 oracle's OCI
+(same rule, tol 1e-12) and each method's final scalar flux is compared with
+it.
 
-Usage: python -m paper_2305_13555_amd.sweep [--quick] [--out FILE]
-Prints one JSON object per point and a speedup table per N.
+Usage: python -m paper_2305_13555_amd.sweep [--quick] [--out FILE] [--check]
+Prints one JSON object per point and a speedup table per N; --check compares
+one point per N (c = 0.9, sigma*dx = 0.1, dt = 0.1) with the oracle.
 """
 import argparse
 import itertools
@@ -44,12 +49,15 @@ def problem(n_angles, c, sigma_dx, dt):
                                       width=WIDTH)
 
 
-def run_point(oci, torch, n_angles, c, sigma_dx, dt, max_iters=200000):
+CHECK = {"c": 0.9, "sigma_dx": 0.1, "dt": 0.1}
+
+
+def run_point(oci, torch, n_angles, c, sigma_dx, dt, max_iters=200000, check_oracle=False):
     prob = problem(n_angles, c, sigma_dx, dt)
     stream = torch.cuda.current_stream()
     out = {"n_angles": n_angles, "c": c, "sigma_dx": sigma_dx, "dt": dt,
-           "cells": prob.n_cells, "tol": TOL}
-    with oci.OciContext(prob, stream=stream, tol=TOL, max_iters=max_iters) as ctx:
+           "cells": prob.n_cells, "tol": TOL, "rule": "strict"}
+    with oci.OciContext(prob, stream=stream, tol=TOL, max_iters=max_iters, strict=True) as ctx:
         ctx.solve(STEPS)                      # warm-up: graphs, caches
         ctx.set_state(None, 0)
         torch.cuda.synchronize()
@@ -60,7 +68,7 @@ def run_point(oci, torch, n_angles, c, sigma_dx, dt, max_iters=200000):
         out["oci_iters"] = [i["iterations"] for i in infos]
         out["oci_rc"] = rc
         phi_oci = ctx.flux().copy()
-    with oci.OciContext(prob, stream=stream, tol=TOL, max_iters=max_iters) as ctx:
+    with oci.OciContext(prob, stream=stream, tol=TOL, max_iters=max_iters, strict=True) as ctx:
         ctx.si_step()
         ctx.set_state(None, 0)
         torch.cuda.synchronize()
@@ -77,6 +85,14 @@ def run_point(oci, torch, n_angles, c, sigma_dx, dt, max_iters=200000):
         phi_si = ctx.flux().copy()
     out["speedup_si_over_oci"] = out["si_s"] / out["oci_s"]
     out["oci_vs_si_rel"] = float(np.max(np.abs(phi_oci - phi_si)) / np.max(np.abs(phi_si)))
+    if check_oracle:
+        from oracle import oci as ooci
+        from oracle.problem import cell_data
+        ref = ooci.run_oci(prob, cell_data(prob), STEPS, tol=1e-12, max_iters=max_iters,
+                           strict=True)[-1]["phi"]
+        scale = float(np.max(np.abs(ref)))
+        out["oci_vs_oracle_rel"] = float(np.max(np.abs(phi_oci - ref))) / scale
+        out["si_vs_oracle_rel"] = float(np.max(np.abs(phi_si - ref))) / scale
     return out
 
 
@@ -84,6 +100,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="three points only")
     ap.add_argument("--out", default=None, help="also write the JSON lines here")
+    ap.add_argument("--check", action="store_true",
+                    help="compare one point per N with the FP64 oracle")
     args = ap.parse_args(argv)
     import torch
     from . import oci
@@ -92,7 +110,8 @@ def main(argv=None):
     sink = open(args.out, "w") if args.out else None
     for n, c, sdx, dt in itertools.product(grid["n_angles"], grid["c"], grid["sigma_dx"],
                                            grid["dt"]):
-        r = run_point(oci, torch, n, c, sdx, dt)
+        chk = args.check and (c, sdx, dt) == (CHECK["c"], CHECK["sigma_dx"], CHECK["dt"])
+        r = run_point(oci, torch, n, c, sdx, dt, check_oracle=chk)
         rows.append(r)
         line = json.dumps(r)
         print(line, flush=True)
