@@ -425,9 +425,13 @@ def main():
                     help="only the learned corrector on the thin-cell evaluation problem")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the 512-problem ensemble")
+    ap.add_argument("--skip-ensemble", action="store_true",
+                    help="the secondary cases without the 512-problem ensemble")
     ap.add_argument("--workload", choices=["large", "bench16"], default="large",
                     help="with --roofline-only: the 200,000-cell S_64 problem or the "
                          "10,000-cell S_32 one")
+    ap.add_argument("--k", type=int, default=None,
+                    help="with --roofline-only: iterates per launch (default: the launch shape)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the OCI path here is single-GPU "
@@ -441,7 +445,7 @@ def main():
     stream = torch.cuda.current_stream()
     if args.roofline_only:
         prob = workloads.config3() if args.workload == "large" else workloads.config2()
-        t, k = roofline_launch_seconds(oci, prob, stream, steps=3)
+        t, k = roofline_launch_seconds(oci, prob, stream, steps=3, k=args.k)
         nbytes = copy_calibration(torch, 64)
         b = algorithmic_bytes_per_cell_iteration(prob.n_angles) * prob.n_cells * k
         print(json.dumps({"workload": prob.name, "kernel": ITERATION_KERNELS[k],
@@ -513,7 +517,7 @@ def main():
     if not args.no_secondary:
         print("bench: secondary cases", file=sys.stderr, flush=True)
         secondary = secondary_case(oci, torch, stream)
-        ensemble = ensemble_case(oci, torch)
+        ensemble = None if args.skip_ensemble else ensemble_case(oci, torch)
         learned = learned_case(oci, torch, stream)
 
     line = {
