@@ -468,6 +468,7 @@ def main():
     # the launch configuration from the autotuner (short solves from the
     # initial state), then the warm-up and timed full solves
     shape, shape_ms = tune.tune(ctx, torch, n_steps=8, repeats=2, use_cache=False)
+    fused, fused_ms = tune.tune_fusion(ctx, torch, n_steps=8, repeats=2, use_cache=False)
     timed_solves(oci, torch, ctx, prob, phi_dev, args.warmup)
     wall, all_infos = timed_solves(oci, torch, ctx, prob, phi_dev, args.steps)
     iters = sum(i["iterations"] for infos in all_infos for i in infos)
@@ -481,17 +482,18 @@ def main():
     nm = max(args.steps // 2, 1)
     with oci.OciContext(prob, stream=stream, precision=oci.OCI_PREC_FP32) as cm:
         inner, inner_ms = tune.tune(cm, torch, n_steps=8, repeats=2, use_cache=False)
+        mfused, mfused_ms = tune.tune_fusion(cm, torch, n_steps=8, repeats=2, use_cache=False)
         timed_solves(oci, torch, cm, prob, phi_dev, 1)
         mwall, minfos = timed_solves(oci, torch, cm, prob, phi_dev, nm)
     mixed_ms = mwall * 1e3 / (nm * T)
     mixed_phi = phi_dev[:1].cpu().numpy()
     print("bench: mixed %.4f ms per time step" % mixed_ms, file=sys.stderr, flush=True)
 
-    # the iteration kernel the timed solves run most: a step's first iterate
-    # comes with the previous step's end, the rest in launches of up to the
-    # launch shape
+    # the iteration kernel the timed solves run most: with the end of step
+    # fused, a step's first iterate comes with the previous step's end and the
+    # rest in launches of up to the launch shape; unfused, all of them
     k_main = max(1, min(ctx.iterates_per_launch,
-                        max(i["iterations"] for i in all_infos[-1]) - 1))
+                        max(i["iterations"] for i in all_infos[-1]) - (1 if fused else 0)))
     per_launch_s, k_launch = roofline_launch_seconds(oci, prob, stream, steps=5, k=k_main)
     kernel = ITERATION_KERNELS[k_launch]
     bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J * k_launch
@@ -573,6 +575,8 @@ def main():
                       "iterates_per_launch_ms_per_step": {str(k): v for k, v in shape_ms.items()},
                       "mixed_inner_iterations": inner,
                       "mixed_inner_ms_per_step": {str(k): v for k, v in inner_ms.items()},
+                      "end_fusion": fused, "end_fusion_ms_per_step": fused_ms,
+                      "mixed_end_fusion": mfused, "mixed_end_fusion_ms_per_step": mfused_ms,
                       "how": "8-step solves from the initial state, best of 2 per candidate"},
         "parity_vs_oracle": parity,
         "si_ms_per_time_step": si_ms,

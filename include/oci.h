@@ -251,6 +251,19 @@ int oci_iterates_per_launch(const oci_ctx *c);
  * effect), or OCI_EINVAL for NULL or k < 2. */
 int oci_set_iterates_per_launch(oci_ctx *c, int32_t k);
 
+/* Whether the end of a queued step also computes the next step's first
+ * iterate (1, the default) or leaves it to the next step's iteration launches
+ * (0).  Iterate 1 of step k+1 reads only the cell's new step constant and its
+ * neighbours' accepted outgoing fluxes (Sec. "One-Cell Inversion (OCI)"), so
+ * the end of step k can form it; whether that pays depends on the problem
+ * (one launch fewer per step against a longer end-of-step kernel and one
+ * iterate fewer per iteration launch).  Results do not depend on it (same
+ * iterates, grouped differently); it is a tuning knob like the iterates per
+ * launch, with the same waiting and threading rules.  oci_set_end_fusion
+ * returns the setting now in effect (0 or 1), or OCI_EINVAL for NULL. */
+int oci_end_fusion(const oci_ctx *c);
+int oci_set_end_fusion(oci_ctx *c, int32_t on);
+
 /* Mixed precision (OCI_PREC_FP32): FP32 inner iterations per correction.
  * By default the count is searched while a solve runs (doubled when a window
  * of queued steps needs four or more FP64 iterates per step, else lowered by

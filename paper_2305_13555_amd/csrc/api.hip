@@ -80,7 +80,7 @@ struct oci_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evA = nullptr, evB = nullptr;
   hipEvent_t evW[2][2] = {};                 // start / end of the windows in flight
   struct StepGraph {
-    int L, G, half, begin, m;
+    int L, G, half, begin, m, fuse;
     double *phi;
     hipGraphExec_t exec;
   };
@@ -110,6 +110,7 @@ struct oci_ctx {
   void *fn_iterK[5] = {};     // [3], [4]: three and four iterates per launch (N = 8 .. 64)
   size_t lds_itK[5] = {};
   int kimax = 2;              // most iterates per launch (the active cap)
+  bool fuse_end = true;       // ends of queued steps compute the next step's iterate 1
   int kibuilt = 2;            // most iterates per launch this problem allows
   // learned corrections inside the iteration (oci_set_corrector)
   oci_corrector *corr = nullptr;
@@ -884,9 +885,10 @@ static int grow_records(oci_ctx *c, int n) {
 static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi,
                       hipGraphExec_t *out) {
   const int m = c->mixed ? c->m_inner : 0;
+  const int fz = c->fuse_end ? 1 : 0;
   for (auto &g : c->step_graphs)
     if (g.L == L && g.G == G && g.half == half && g.begin == begin && g.m == m &&
-        g.phi == phi) {
+        g.fuse == fz && g.phi == phi) {
       *out = g.exec;
       return OCI_OK;
     }
@@ -917,7 +919,7 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   // the next step (needs L >= 2, so that the next step still has a launch of
   // its own to open it; mixed precision: FP64 iterate 1 with its defect, and
   // the next step's first inner iteration opens it)
-  const bool fuse_ok = L >= 2;
+  const bool fuse_ok = L >= 2 && fz;
   int last_n = 1;   // iterates of the step's last launch
   for (int s = 0; s < G && e == hipSuccess; ++s) {
     int h = (half + s) & 1;
@@ -987,7 +989,7 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
   (void)hipGraphDestroy(g);
   if (e != hipSuccess)
     return fail(c, OCI_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  c->step_graphs.push_back({L, G, half, begin, m, phi, exec});
+  c->step_graphs.push_back({L, G, half, begin, m, fz, phi, exec});
   *out = exec;
   return OCI_OK;
 }
@@ -1855,6 +1857,19 @@ extern "C" int oci_set_iterates_per_launch(oci_ctx *c, int32_t k) {
     c->kimax = v;
   }
   return v;
+}
+
+extern "C" int oci_end_fusion(const oci_ctx *c) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  return c->fuse_end ? 1 : 0;
+}
+
+extern "C" int oci_set_end_fusion(oci_ctx *c, int32_t on) {
+  if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
+  const bool v = on != 0;
+  if (v != c->fuse_end) drop_step_graphs(c);   // cached graphs hold the old sequence
+  c->fuse_end = v;
+  return v ? 1 : 0;
 }
 
 extern "C" int oci_inner_iterations(const oci_ctx *c) {

@@ -97,6 +97,8 @@ def _load():
         "oci_get_sizes": (ctypes.c_int, [vp, _ip, _ip, _ip]),
         "oci_iterates_per_launch": (ctypes.c_int, [vp]),
         "oci_set_iterates_per_launch": (ctypes.c_int, [vp, ctypes.c_int32]),
+        "oci_end_fusion": (ctypes.c_int, [vp]),
+        "oci_set_end_fusion": (ctypes.c_int, [vp, ctypes.c_int32]),
         "oci_inner_iterations": (ctypes.c_int, [vp]),
         "oci_set_inner_iterations": (ctypes.c_int, [vp, ctypes.c_int32]),
         "oci_get_operator": (ctypes.c_int, [vp, ctypes.c_int32, _dp]),
@@ -323,6 +325,14 @@ def oci_set_iterates_per_launch(ctx, k):
     return _check(_lib.oci_set_iterates_per_launch(ctx, int(k)), ctx)
 
 
+def oci_end_fusion(ctx):
+    return _check(_lib.oci_end_fusion(ctx), ctx)
+
+
+def oci_set_end_fusion(ctx, on):
+    return _check(_lib.oci_set_end_fusion(ctx, 1 if on else 0), ctx)
+
+
 def oci_inner_iterations(ctx):
     return _check(_lib.oci_inner_iterations(ctx), ctx)
 
@@ -388,6 +398,13 @@ class OciContext:
     def set_iterates_per_launch(self, k):
         self.iterates_per_launch = oci_set_iterates_per_launch(self.handle, k)
         return self.iterates_per_launch
+
+    @property
+    def end_fusion(self):
+        return bool(oci_end_fusion(self.handle))
+
+    def set_end_fusion(self, on):
+        return bool(oci_set_end_fusion(self.handle, on))
 
     @property
     def inner_iterations(self):

@@ -9,12 +9,20 @@ Two knobs change the speed of a solve but not what it converges to:
 * Mixed-precision contexts: the FP32 inner iterations per correction
   (oci_set_inner_iterations, 1 .. 4 tried).  More make each correction more
   complete (fewer FP64 iterates per step) at the cost of the inner launches.
+* Both: whether the end of a queued step also computes the next step's first
+  iterate (oci_set_end_fusion): one launch fewer per step against a longer
+  end-of-step kernel (and, for FP64, one iterate fewer in the launches that
+  follow it).
 
 Which wins depends on N, the mesh, the region layout and the tolerance.
 tune() times a short solve per candidate from the context's current state
 (restored afterwards), keeps the fastest, and remembers it per (N, J,
 regions, precision) in a process-wide cache that can be saved to and loaded
-from a JSON file.
+from a JSON file; tune_fusion() does the same for the end-of-step fusion at
+the context's current setting of the first knob.  The tile (16 cells, the
+MFMA block's columns) and the waves per work-group (min(2N/16, 4): the
+scalar-flux rows' k-steps split over the waves, one angle per thread in the
+per-angle phases) are fixed by the kernels' data layout and are not tuned.
 """
 import json
 import time
@@ -79,6 +87,24 @@ def tune(ctx, torch, n_steps=8, repeats=3, use_cache=True):
     return setter(k), times
 
 
+def tune_fusion(ctx, torch, n_steps=8, repeats=3, use_cache=True):
+    """Pick and set the faster end-of-step fusion for ctx (at its current
+    launch shape or inner iterations).  Returns (fused: bool, ms per step by
+    candidate {"fused": t, "unfused": t}; empty when the cache answered)."""
+    key = cache_key(ctx) + "_fusion"
+    if use_cache and key in _cache:
+        return ctx.set_end_fusion(bool(_cache[key])), {}
+    psi, step = ctx.state()
+    times = {}
+    for name, on in (("fused", True), ("unfused", False)):
+        ctx.set_end_fusion(on)
+        times[name] = _time_solves(ctx, torch, n_steps, repeats, psi, step)
+    ctx.set_state(psi, step)
+    on = times["fused"] <= times["unfused"]
+    _cache[key] = 1 if on else 0
+    return ctx.set_end_fusion(on), times
+
+
 def save_cache(path):
     with open(path, "w") as f:
         json.dump(_cache, f, indent=1, sort_keys=True)
@@ -88,6 +114,7 @@ def load_cache(path):
     with open(path) as f:
         data = json.load(f)
     for k, v in data.items():
-        if not isinstance(k, str) or not isinstance(v, int) or v < 1:
+        lo = 0 if isinstance(k, str) and k.endswith("_fusion") else 1
+        if not isinstance(k, str) or not isinstance(v, int) or v < lo or (lo == 0 and v > 1):
             raise ValueError("bad tuning cache entry %r: %r" % (k, v))
     _cache.update(data)

@@ -90,3 +90,33 @@ def test_inner_iterations_setter_and_tuner_for_mixed_precision():
         assert ctx.state()[1] == step0
     with oci.OciContext(p) as c64:
         assert c64.inner_iterations == 0 and c64.set_inner_iterations(2) == 0
+
+
+@pytest.mark.parametrize("precision", [oci.OCI_PREC_FP64, oci.OCI_PREC_FP32], ids=["fp64", "mixed"])
+def test_end_fusion_changes_launches_not_results(precision):
+    """With the end of step fused or not, a queued solve computes the same
+    iterates (same arithmetic, grouped into other launches): the same
+    iteration counts and the scalar flux to rounding order; the tuner picks
+    one and restores the state."""
+    p = W.config2(n_steps=12, n_cells=3000, n_regions=8, n_angles=32)
+    tune._cache.clear()
+    with oci.OciContext(p, precision=precision) as ctx:
+        assert ctx.end_fusion
+        if precision == oci.OCI_PREC_FP32:
+            ctx.set_inner_iterations(2)   # (no search of the inner count between the solves)
+        phi_f, it_f = _solve(ctx, 12)
+        assert ctx.set_end_fusion(False) is False and not ctx.end_fusion
+        ctx.set_state(None, 0)
+        phi_u, it_u = _solve(ctx, 12)
+        assert it_u == it_f
+        for s in range(12):
+            assert _rel(phi_u[s], phi_f[s]) < 1e-12
+        psi0, step0 = ctx.state()
+        on, times = tune.tune_fusion(ctx, torch, n_steps=3, repeats=1)
+        assert sorted(times) == ["fused", "unfused"] and all(t > 0 for t in times.values())
+        assert on == (times["fused"] <= times["unfused"]) and ctx.end_fusion == on
+        psi1, step1 = ctx.state()
+        assert step1 == step0 and np.array_equal(psi1, psi0)
+        with oci.OciContext(p, precision=precision) as c2:
+            on2, t2 = tune.tune_fusion(c2, torch)
+            assert on2 == on and t2 == {} and c2.end_fusion == on

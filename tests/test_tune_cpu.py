@@ -34,4 +34,12 @@ def test_cache_round_trip(tmp_path):
     path.write_text(json.dumps({"N8_J10_R1_fp64": 0}))
     with pytest.raises(ValueError):
         tune.load_cache(str(path))
+    # the end-of-step fusion entries are 0 or 1
+    tune._cache.clear()
+    path.write_text(json.dumps({"N8_J10_R1_fp64_fusion": 0, "N8_J10_R1_fp32_fusion": 1}))
+    tune.load_cache(str(path))
+    assert tune._cache == {"N8_J10_R1_fp64_fusion": 0, "N8_J10_R1_fp32_fusion": 1}
+    path.write_text(json.dumps({"N8_J10_R1_fp64_fusion": 2}))
+    with pytest.raises(ValueError):
+        tune.load_cache(str(path))
     tune._cache.clear()
