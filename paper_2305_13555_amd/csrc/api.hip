@@ -101,7 +101,8 @@ struct oci_ctx {
   bool m_locked = false;
   bool m_fixed = false;   // set by oci_set_inner_iterations: no search
   float *d_fi32 = nullptr, *d_dlt = nullptr, *d_dphi32 = nullptr;
-  size_t lds_in = 0;
+  size_t lds_in = 0, lds_in2 = 0;
+  void *fn_inner2 = nullptr;   // two inner iterations per launch
   // kernels for the chosen operator batch width CH
   int CH = 16;
   void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr, *fn_inner = nullptr;
@@ -652,6 +653,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
 #undef OCI_KERNEL
 #undef OCI_PICK
   c->fn_inner = s.tiles_in_args ? (void *)k_oci_inner<true> : (void *)k_oci_inner<false>;
+  c->fn_inner2 = s.tiles_in_args ? (void *)k_oci_inner2<true> : (void *)k_oci_inner2<false>;
   // three and four iterates per launch: built for N = 8, 16, 32 and 64 (from
   // N = 128 on the two LDS row blocks alone leave room for one work-group
   // per CU)
@@ -695,6 +697,9 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   // beats every work-group of the end of step reducing them all
   c->pre_reduce = c->ntiles > 2048 ? 1 : 0;
   c->lds_in = (size_t)(kTileCells + 2) * (K + 4) * sizeof(float);
+  // (two inner iterations per launch for N <= 128: rows, then the halo tables)
+  c->lds_in2 = ((size_t)(2 * kTileCells + 6) * (K + 4) + 30 * N) * sizeof(float);
+  if (N > 128) c->fn_inner2 = nullptr;
   // kernels with more than 64 KiB of dynamic LDS must say so
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_iter,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_it));
@@ -704,6 +709,9 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_pv));
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_end,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_ed));
+  if (c->fn_inner2)
+    OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_inner2,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_in2));
   OCI_CK(c, hipStreamSynchronize(c->stream));
 #undef OCI_TRY
   *out = c;
@@ -926,10 +934,15 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
     if (c->mixed) {
       const int ostart = (s > 0 && fuse_ok) ? 2 : 1;
       for (int o = ostart; o <= L && e == hipSuccess; ++o) {
-        for (int i = 1; o > 1 && i <= m && e == hipSuccess; ++i) {
-          int ii = i, ly = i == m ? 2 * (o - 1) : 0, opens = (o == ostart && i == 1) ? 1 : 0;
-          void *iargs[] = {&c->sa, &ii, &ly, &h, &opens};
-          e = add(c->fn_inner, c->W_it, c->lds_in, iargs);
+        // the m inner iterations: two per launch, a single one first when m is odd
+        for (int i = 1, n = 1; o > 1 && i <= m && e == hipSuccess; ++n) {
+          const int lv = c->fn_inner2 && (m - i + 1) % 2 == 0 ? 2 : 1;
+          int nn = n, ly = i + lv - 1 == m ? 2 * (o - 1) : 0;
+          int opens = (o == ostart && i == 1) ? 1 : 0;
+          void *iargs[] = {&c->sa, &nn, &ly, &h, &opens};
+          e = lv == 2 ? add(c->fn_inner2, c->W_it, c->lds_in2, iargs)
+                      : add(c->fn_inner, c->W_it, c->lds_in, iargs);
+          i += lv;
         }
         int node = 2 * o - 1, cb = 0, nred = 1;
         void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
@@ -1045,11 +1058,15 @@ static void tune_inner(oci_ctx *c, int q, int m_used) {
 // Mixed precision: one more correction after FP64 iterate lprev (inner
 // iterations, the last forming iterate lprev+1) and FP64 iterate lprev+2.
 static int launch_outer(oci_ctx *c, int lprev, int half) {
-  for (int i = 1; i <= c->m_inner; ++i) {
-    int ii = i, ly = i == c->m_inner ? lprev + 1 : 0, opens = 0;
-    void *iargs[] = {&c->sa, &ii, &ly, &half, &opens};
-    OCI_CK(c, hipLaunchKernel(c->fn_inner, dim3(c->grid), dim3(64 * c->W_it), iargs, c->lds_in,
+  const int m = c->m_inner;
+  for (int i = 1, n = 1; i <= m; ++n) {   // (as in step_graph)
+    const int lv = c->fn_inner2 && (m - i + 1) % 2 == 0 ? 2 : 1;
+    int nn = n, ly = i + lv - 1 == m ? lprev + 1 : 0, opens = 0;
+    void *iargs[] = {&c->sa, &nn, &ly, &half, &opens};
+    OCI_CK(c, hipLaunchKernel(lv == 2 ? c->fn_inner2 : c->fn_inner, dim3(c->grid),
+                              dim3(64 * c->W_it), iargs, lv == 2 ? c->lds_in2 : c->lds_in,
                               c->stream));
+    i += lv;
   }
   int node = lprev + 2, cb = 0, rstep = 2, nred = 1;
   void *args[] = {&c->sa, &node, &cb, &half, &rstep, &nred};

@@ -161,6 +161,10 @@ __global__ void k_reduce_rec(StepArgs a, int l, int n, int half);
 // came with the previous end of step).
 template <bool ARGT>
 __global__ void k_oci_inner(StepArgs a, int i, int ly, int half, int opens);
+// Two inner iterations in one launch (halo cells recomputed); n: the launch's
+// index within the correction (selects the buffers as i does above).
+template <bool ARGT>
+__global__ void k_oci_inner2(StepArgs a, int n, int ly, int half, int opens);
 // Ensembles: the same step kernels (any N, a multiple of 8; 256 threads) over
 // a work queue of (problem, tile) entries, each problem with its own argument
 // block probs[problem]; a tile entry equal to the problem's tile count is its

@@ -1825,6 +1825,335 @@ __global__ __launch_bounds__(256) void k_oci_inner(StepArgs a, int i, int ly, in
   if (opens) open_step(a, 1, cur, fb, stalled, blockIdx.x);
 }
 
+// Reflecting edge of a correction row in LDS (FP32): the ghost takes the
+// boundary cell's mirror-angle values (left ghost: entries N .. 2N-1, right
+// ghost: 0 .. N-1).
+__device__ __forceinline__ void mirror_row32(float *ghost, const float *cell, int N, bool left) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const int e = left ? N + i : i;
+    const int m = e >> 1, tl = e & 1;
+    ghost[e] = cell[2 * (N - 1 - m) + tl];
+  }
+}
+
+// e = H inc of the tile's cells from correction rows at `base` (row 1 + c holds
+// own cell c; rows c and c + 2 its neighbours), on FP32 MFMA with the k-steps
+// split over the waves; wave 0 sums the partials in order into ef[cell * 4 +
+// component].  Ends with a barrier.
+__device__ __forceinline__ void inner_phi(const float *base, int P, int KS, int kb, int ke,
+                                          const float *F, const float (&f0)[8], float *phis32,
+                                          float *ef) {
+  constexpr int kFr = 8;
+  const int W = (int)(blockDim.x >> 6);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  int prt, poff;
+  phi_tile(2 * KS, &prt, &poff);   // (2 KS = N: K = 2N columns, KS = K / 4)
+  const float *ap = base + (kq < 2 ? col + 2 : col) * P + kq * KS;
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < kFr; ++q)
+    if (kb + q < ke) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[kb + q], f0[q], acc, 0, 0, 0);
+  for (int ks = kb + kFr; ks < ke; ++ks)
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[ks], F[(size_t)ks * 64], acc, 0, 0, 0);
+  if (col >= poff && col < poff + 4) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) phis32[wave * 64 + (4 * kq + r) * 4 + col - poff] = acc[r];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    float e = 0.f;
+    for (int w = 0; w < W; ++w) e += phis32[w * 64 + lane];
+    ef[lane] = e;
+  }
+  __syncthreads();
+}
+
+// Two inner iterations per launch: delta_{i+1} of the tile's cells and of one
+// halo cell on each side, kept in LDS, then delta_{i+2} of the tile's cells
+// from it (delta_{i+1} never reaches memory).  A halo cell's scalar-flux
+// correction is four dot products of its own region's rows of H with its
+// incident corrections (FP64 sums of the FP32 values, one wave per halo
+// cell), and only its pairs entering the tile are formed; every other value
+// is formed as in k_oci_inner.  n: this launch's index within the correction
+// (the buffers alternate per launch as in k_oci_inner); ly > 0: the
+// correction's last launch, which forms FP64 iterate ly; opens as in
+// k_oci_inner.  LDS: block A, the rows of delta_i of cells c0-2 .. c0+nc+1
+// (row r <-> cell c0-2+r), and block B, delta_{i+1} of cells c0-1 .. c0+nc
+// (row r <-> cell c0-1+r), pitch K+4 floats; then per halo side (0 left, 1
+// right) the tables of its halo cell, loaded with the rows so that the halo
+// work reads no global memory: HF [2][4][K] its region's rows of H, HC
+// [2][12][N/2] the pair coefficients of its entering angles (entering angle
+// j: N/2 + j on the left, j on the right), HD [2][N] its defect in those
+// angles.  N <= 128 (the per-thread load slots below).
+template <bool ARGT>
+__global__ __launch_bounds__(256) void k_oci_inner2(StepArgs a, int n, int ly, int half,
+                                                    int opens) {
+  constexpr int kFr = 8;
+  extern __shared__ double lds_raw[];
+  __shared__ float phis32[kMaxWaves * 64], ef[64];
+  const int N = a.N, K = 2 * N, KS = K / 4, P = K + 4, K4 = K / 4;
+  float *A = reinterpret_cast<float *>(lds_raw);
+  float *B = A + (kTileCells + 4) * P;
+  float *HF = B + (kTileCells + 2) * P, *HC = HF + 8 * K, *HD = HC + 12 * N;
+  const int W = (int)(blockDim.x >> 6);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const TileDev t = blk_desc<ARGT>(a, blockIdx.x);
+  const bool hl = t.c0 > 0, hr = t.c0 + t.nc < a.J;   // halo cells (else ghost rows)
+  // the halo cells' tables: issued first, stored to LDS with the rows
+  constexpr int kHF = 4, kHC = 3;   // double2 load slots per thread (N <= 128)
+  const int reg[2] = {hl ? a.cell_region[t.c0 - 1] : 0, hr ? a.cell_region[t.c0 + t.nc] : 0};
+  const bool side_on[2] = {hl, hr};
+  double2 hfv[kHF], hcv[kHC];
+  float2 hdv = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int i = 0; i < kHF; ++i) {   // H rows: 2K double2 per side
+    const int e = threadIdx.x + i * (int)blockDim.x, sd = e / (2 * K), w = e - sd * 2 * K;
+    hfv[i] = make_double2(0.0, 0.0);
+    if (e < 4 * K && side_on[sd]) {
+      const int q = w / (K / 2), kk = 2 * (w - q * (K / 2));
+      hfv[i] = *reinterpret_cast<const double2 *>(a.phig + ((size_t)reg[sd] * 4 + q) * K + kk);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kHC; ++i) {   // pair coefficients: 6 pairs x N/2 angles per side
+    const int e = threadIdx.x + i * (int)blockDim.x, sd = e / (3 * N), w = e - sd * 3 * N;
+    hcv[i] = make_double2(0.0, 0.0);
+    if (e < 6 * N && side_on[sd]) {
+      const int i2 = w / (N / 2), j = w - i2 * (N / 2);
+      hcv[i] = coef_pair(a, N, reg[sd], sd == 0 ? N / 2 + j : j, i2);
+    }
+  }
+  {   // defect pairs: N/2 per side
+    const int e = threadIdx.x, sd = e / (N / 2), j = e - sd * (N / 2);
+    if (e < N && side_on[sd]) {
+      const int hc = sd == 0 ? t.c0 - 1 : t.c0 + t.nc, m = sd == 0 ? N / 2 + j : j;
+      hdv = *reinterpret_cast<const float2 *>(a.dlt + (size_t)(hc + 1) * K + 2 * m);
+    }
+  }
+  const float *src = a.dlt + (size_t)(n == 1 ? 0 : ((n & 1) ? 2 : 1)) * a.dlt_stride;
+  float *dst = a.dlt + (size_t)((n & 1) ? 1 : 2) * a.dlt_stride;
+  const float *dd = a.dlt;   // the defect d
+  int prt, poff, kb, ke;
+  phi_tile(N, &prt, &poff);
+  phi_ksplit(KS, W, wave, &kb, &ke);
+  const float *F = a.frag_it32 + (size_t)t.region * a.frag_it_stride + lane + (size_t)prt * KS * 64;
+  const double *yb = nullptr, *ybp = nullptr;
+  double *yo = nullptr, *yop = nullptr;
+  int cur = 0, fb = 0;
+  if (opens || ly == 2) {
+    cur = a.ctl->cur;
+    fb = a.ctl->fin_buf;
+  }
+  if (ly) {
+    const int bb = ly == 2 ? fb : ring_buf(a, ly - 2, half);
+    const int bo = ring_buf(a, ly, half);
+    yb = out_at(a, bb);
+    ybp = phi_at(a, bb);
+    yo = out_at(a, bo);
+    yop = phi_at(a, bo);
+  }
+  // loads that need no LDS: this wave's first operator fragments, this
+  // thread's coefficients, the defect (and with ly the FP64 point) of its
+  // first cells, and wave 0's scalar-flux defect (and FP64 point)
+  float f0[kFr];
+#pragma unroll
+  for (int q = 0; q < kFr; ++q) f0[q] = F[(size_t)min(kb + q, KS - 1) * 64];
+  const PairMap pm(N);
+  float cf[12];
+  {
+    double c[12];
+    coef_load<12>(a, N, t.region, pm.m, 0, c);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) cf[q] = (float)c[q];
+  }
+  float dq[kDPre][2];
+  double yq[kDPre][2];
+#pragma unroll
+  for (int j = 0; j < kDPre; ++j) {
+    const size_t cell = (size_t)(t.c0 + min(pm.cl0 + j * pm.cstep, t.nc - 1));
+    const float2 v = *reinterpret_cast<const float2 *>(dd + (cell + 1) * K + 2 * pm.m);
+    dq[j][0] = v.x;
+    dq[j][1] = v.y;
+    yq[j][0] = yq[j][1] = 0.0;
+    if (ly) {
+      const double2 y = *reinterpret_cast<const double2 *>(yb + (cell + 1) * K + 2 * pm.m);
+      yq[j][0] = y.x;
+      yq[j][1] = y.y;
+    }
+  }
+  float dphi = 0.f;
+  double yphi = 0.0;
+  if (wave == 0) {
+    const size_t ce = (size_t)(t.c0 + min(lane >> 2, t.nc - 1)) * 4 + (lane & 3);
+    dphi = a.dphi32[ce];
+    if (ly) yphi = ybp[ce];
+  }
+  const int stalled = a.ctl->stalled;
+  // rows of delta_i of cells c0-2 .. c0+nc+1 (ghosted rows c0-1 .. c0+nc+2,
+  // clamped to the mesh) into block A
+  const int g_lo = max(t.c0 - 1, 0), g_hi = min(t.c0 + t.nc + 2, a.J + 1);
+  const int r_lo = g_lo - (t.c0 - 1);
+  {
+    const f4 *s4 = reinterpret_cast<const f4 *>(src + (size_t)g_lo * K);
+    const int n4 = (g_hi - g_lo + 1) * K4;
+    for (int e = threadIdx.x; e < n4; e += blockDim.x) {
+      const int r = e / K4, k4 = e - r * K4;
+      *reinterpret_cast<f4 *>(A + (r_lo + r) * P + 4 * k4) = s4[e];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kHF; ++i) {
+    const int e = threadIdx.x + i * (int)blockDim.x;
+    if (e < 4 * K) {   // (side sd, row q, column kk) -> HF[sd][q][kk]: the same flat order
+      HF[2 * e] = (float)hfv[i].x;
+      HF[2 * e + 1] = (float)hfv[i].y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kHC; ++i) {
+    const int e = threadIdx.x + i * (int)blockDim.x, sd = e / (3 * N), w = e - sd * 3 * N;
+    if (e < 6 * N) {
+      const int i2 = w / (N / 2), j = w - i2 * (N / 2);
+      HC[(sd * 12 + 2 * i2) * (N / 2) + j] = (float)hcv[i].x;
+      HC[(sd * 12 + 2 * i2 + 1) * (N / 2) + j] = (float)hcv[i].y;
+    }
+  }
+  if (threadIdx.x < N) {
+    HD[2 * threadIdx.x] = hdv.x;
+    HD[2 * threadIdx.x + 1] = hdv.y;
+  }
+  __syncthreads();
+  if (stalled) return;
+  const bool refl = a.bcl == kBcReflect, refr = a.bcr == kBcReflect;
+  // reflecting edges: the ghost next to a halo cell on the edge, or next to
+  // the tile's own edge cell (the correction obeys the homogeneous mirror map)
+  if (refl && t.c0 == 1) mirror_row32(A, A + P, N, true);
+  if (refl && t.c0 == 0) mirror_row32(A + P, A + 2 * P, N, true);
+  if (refr && t.c0 + t.nc == a.J - 1) mirror_row32(A + (t.nc + 3) * P, A + (t.nc + 2) * P, N, false);
+  if (refr && t.c0 + t.nc == a.J) mirror_row32(A + (t.nc + 2) * P, A + (t.nc + 1) * P, N, false);
+  if (refl || refr) __syncthreads();
+  // level 1: the halo cells' entering pairs (one wave each) into block B
+  const int wl = W - 1, wr = W >= 2 ? W - 2 : W - 1;
+  for (int side = 0; side < 2; ++side) {
+    const bool left = side == 0;
+    if (!(left ? hl && wave == wl : hr && wave == wr)) continue;
+    const int hc = left ? t.c0 - 1 : t.c0 + t.nc;
+    const float *row_l = A + (left ? 0 : t.nc + 1) * P;   // the halo cell's left neighbour
+    const float *row_r = A + (left ? 2 : t.nc + 3) * P;   // and its right one
+    float *orow = B + (left ? 0 : t.nc + 1) * P;
+    const int q = lane >> 4;   // row q of the wave forms component q
+    const float *Fq = HF + (side * 4 + q) * K;
+    double acc = 0.0;
+    for (int k = lane & 15; k < K; k += 16) acc += (double)(Fq[k] * (k < N ? row_r[k] : row_l[k]));
+    acc = row_sum16(acc);
+    float eh[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) eh[c] = (float)lane_f64(acc, 16 * c);
+    const float *hcs = HC + side * 12 * (N / 2), *hds = HD + side * N;
+    for (int j = lane; j < N / 2; j += 64) {
+      const int m = left ? N / 2 + j : j;   // the angles entering the tile
+      float c[12];
+#pragma unroll
+      for (int u = 0; u < 12; ++u) c[u] = hcs[u * (N / 2) + j];
+      const float *in = (left ? row_l : row_r) + 2 * m;
+      const float i0 = in[0], i1 = in[1];
+      orow[2 * m] = hds[2 * j] + c[0] * eh[0] + c[1] * eh[1] + c[2] * eh[2] + c[3] * eh[3] +
+                    c[4] * i0 + c[5] * i1;
+      orow[2 * m + 1] = hds[2 * j + 1] + c[6] * eh[0] + c[7] * eh[1] + c[8] * eh[2] +
+                        c[9] * eh[3] + c[10] * i0 + c[11] * i1;
+    }
+  }
+  // level 1, own cells: e, then the full rows into block B (row cl + 1)
+  inner_phi(A + P, P, KS, kb, ke, F, f0, phis32, ef);
+  const int m = pm.m;
+  const bool pos = 2 * m >= N;
+  auto own_d = [&](int j, size_t cell, float &d0, float &d1) {
+    if (j < kDPre) {   // (entry j by selects: a run-time index would put dq in scratch)
+      d0 = dq[0][0];
+      d1 = dq[0][1];
+#pragma unroll
+      for (int q = 1; q < kDPre; ++q)
+        if (q == j) {
+          d0 = dq[q][0];
+          d1 = dq[q][1];
+        }
+    } else {
+      d0 = dd[(cell + 1) * K + 2 * m];
+      d1 = dd[(cell + 1) * K + 2 * m + 1];
+    }
+  };
+  {
+    int j = 0;
+    for (int cl = pm.active ? pm.cl0 : t.nc; cl < t.nc; cl += pm.cstep, ++j) {
+      const float *in = A + (pos ? cl + 1 : cl + 3) * P + 2 * m;
+      const float *e4 = ef + cl * 4;
+      float d0, d1;
+      own_d(j, (size_t)(t.c0 + cl), d0, d1);
+      const float i0 = in[0], i1 = in[1];
+      const float e0 = e4[0], e1 = e4[1], e2 = e4[2], e3 = e4[3];
+      B[(cl + 1) * P + 2 * m] = d0 + cf[0] * e0 + cf[1] * e1 + cf[2] * e2 + cf[3] * e3 +
+                                cf[4] * i0 + cf[5] * i1;
+      B[(cl + 1) * P + 2 * m + 1] = d1 + cf[6] * e0 + cf[7] * e1 + cf[8] * e2 + cf[9] * e3 +
+                                    cf[10] * i0 + cf[11] * i1;
+    }
+  }
+  __syncthreads();
+  // ghost rows of block B at the mesh edges: zero, or the mirror of the edge
+  // cell's delta_{i+1}
+  if (!hl) {
+    if (refl) mirror_row32(B, B + P, N, true);
+    else for (int i = N + threadIdx.x; i < K; i += blockDim.x) B[i] = 0.f;
+  }
+  if (!hr) {
+    float *g = B + (t.nc + 1) * P;
+    if (refr) mirror_row32(g, B + t.nc * P, N, false);
+    else for (int i = threadIdx.x; i < N; i += blockDim.x) g[i] = 0.f;
+  }
+  if (!hl || !hr) __syncthreads();
+  // level 2: delta_{i+2} of the own cells from block B
+  inner_phi(B, P, KS, kb, ke, F, f0, phis32, ef);
+  if (ly && wave == 0) {
+    const int cl = lane >> 2;
+    if (cl < t.nc) yop[(size_t)(t.c0 + cl) * 4 + (lane & 3)] = yphi + (double)(dphi + ef[lane]);
+  }
+  int j = 0;
+  for (int cl = pm.active ? pm.cl0 : t.nc; cl < t.nc; cl += pm.cstep, ++j) {
+    const float *in = B + (pos ? cl : cl + 2) * P + 2 * m;
+    const float *e4 = ef + cl * 4;
+    const size_t cell = (size_t)(t.c0 + cl);
+    float d0, d1;
+    own_d(j, cell, d0, d1);
+    const float i0 = in[0], i1 = in[1];
+    const float e0 = e4[0], e1 = e4[1], e2 = e4[2], e3 = e4[3];
+    const float o0 = d0 + cf[0] * e0 + cf[1] * e1 + cf[2] * e2 + cf[3] * e3 + cf[4] * i0 +
+                     cf[5] * i1;
+    const float o1 = d1 + cf[6] * e0 + cf[7] * e1 + cf[8] * e2 + cf[9] * e3 + cf[10] * i0 +
+                     cf[11] * i1;
+    if (ly) {
+      double y0 = 0.0, y1 = 0.0;
+      if (j < kDPre) {
+        y0 = yq[0][0];
+        y1 = yq[0][1];
+#pragma unroll
+        for (int q = 1; q < kDPre; ++q)
+          if (q == j) {
+            y0 = yq[q][0];
+            y1 = yq[q][1];
+          }
+      } else {
+        y0 = yb[(cell + 1) * K + 2 * m];
+        y1 = yb[(cell + 1) * K + 2 * m + 1];
+      }
+      *reinterpret_cast<double2 *>(yo + (cell + 1) * K + 2 * m) =
+          make_double2(y0 + (double)o0, y1 + (double)o1);
+    } else {
+      *reinterpret_cast<float2 *>(dst + (cell + 1) * K + 2 * m) = make_float2(o0, o1);
+    }
+  }
+  if (opens) open_step(a, 1, cur, fb, stalled, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Learned corrections inside the iteration
 // ---------------------------------------------------------------------------
@@ -1976,6 +2305,8 @@ template __global__ void k_oci_iterateK<16, true, true, 64, 4>(StepArgs, int, in
 template __global__ void k_oci_iterateK<16, false, true, 64, 4>(StepArgs, int, int, int, int);
 template __global__ void k_oci_inner<true>(StepArgs, int, int, int, int);
 template __global__ void k_oci_inner<false>(StepArgs, int, int, int, int);
+template __global__ void k_oci_inner2<true>(StepArgs, int, int, int, int);
+template __global__ void k_oci_inner2<false>(StepArgs, int, int, int, int);
 
 template __global__ void k_step_begin<4, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int, int, int);
