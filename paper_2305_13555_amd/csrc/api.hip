@@ -106,6 +106,7 @@ struct oci_ctx {
   // kernels for the chosen operator batch width CH
   int CH = 16;
   void *fn_begin = nullptr, *fn_iter = nullptr, *fn_end = nullptr, *fn_inner = nullptr;
+  void *fn_end_nf = nullptr;   // the end of step without the fused iterate
   void *fn_iter2 = nullptr;   // two iterates per launch (plain FP64 batches)
   size_t lds_it2 = 0;
   void *fn_iterK[5] = {};     // [3], [4]: three and four iterates per launch (N = 8 .. 64)
@@ -640,6 +641,7 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
     c->fn_iter = OCI_KERNEL(k_oci_iterate, CHV, ARGT);            \
     c->fn_iter2 = OCI_KERNEL(k_oci_iterate2, CHV, ARGT);          \
     c->fn_end = OCI_KERNEL(k_step_end, CHV, ARGT);                \
+    c->fn_end_nf = OCI_KERNEL(k_step_end_nf, CHV, ARGT);          \
   } while (0)
   if (s.tiles_in_args) {
     if (c->CH == 16) OCI_PICK(16, true);
@@ -708,6 +710,8 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_begin,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_pv));
   OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_end,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_ed));
+  OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_end_nf,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_ed));
   if (c->fn_inner2)
     OCI_CK(c, hipFuncSetAttribute((const void *)c->fn_inner2,
@@ -990,7 +994,7 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
     }
     if (e == hipSuccess) {
       void *eargs[] = {&c->sa, &phi, &first, &last, &h, &rstep, &mode};
-      e = add(c->fn_end, c->W_ed, c->lds_ed, eargs);
+      e = add(fuse ? c->fn_end : c->fn_end_nf, c->W_ed, c->lds_ed, eargs);
     }
   }
   if (e != hipSuccess) {
@@ -1086,7 +1090,7 @@ static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half
     OCI_CK(c, hipLaunchKernel((const void *)k_reduce_rec, dim3(1), dim3(256), rargs, 0, c->stream));
   }
   void *args[] = {&c->sa, &phi_dev, &first, &last, &half, &rstep, &mode};
-  OCI_CK(c, hipLaunchKernel(c->fn_end, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
+  OCI_CK(c, hipLaunchKernel(c->fn_end_nf, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,
                             c->stream));
   return OCI_OK;
 }

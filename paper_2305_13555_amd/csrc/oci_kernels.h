@@ -154,6 +154,10 @@ __global__ void k_oci_iterateK(StepArgs a, int node, int cb, int half, int nred)
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half,
                            int rstep, int mode);
+// The same without the fused iterate (bit 4 ignored; fewer registers).
+template <int CH, bool ARGT, bool VEC, int NF>
+__global__ void k_step_end_nf(StepArgs a, double *phi_out, int first, int last, int half,
+                              int rstep, int mode);
 __global__ void k_reduce_rec(StepArgs a, int l, int n, int half);
 // FP32 inner iteration i (1-based) of a mixed-precision step; ly > 0: the last
 // one, which also forms FP64 iterate ly (the point iterate ly-1 started from

@@ -368,7 +368,8 @@ __device__ __forceinline__ void phi_ksplit(int KS, int W, int w, int *kb, int *k
 // summed in a fixed order; g' (rows 0 .. 2N-1) per (cell, angle).
 template <int CH, bool VEC, int NF>
 __device__ __forceinline__ void gh_compute(const StepArgs &a, const TileDev &t, const double *rows,
-                                  const double (&f0)[CH], GhOut &go, bool want_go) {
+                                  const double (&f0)[CH], const double (&cg)[6], GhOut &go,
+                                  bool want_go) {
   __shared__ double hp[kMaxWaves * 64];
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
   const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
@@ -398,16 +399,13 @@ __device__ __forceinline__ void gh_compute(const StepArgs &a, const TileDev &t, 
   }
   const PairMap pm(N);
   if (pm.active) {
-    double cg[6];
-    coef_load<6>(a, N, t.region, pm.m, 12, cg);
     const double c0 = cg[0], c1 = cg[1], c2 = cg[2], c3 = cg[3], c4 = cg[4], c5 = cg[5];
     int j = 0;
     for (int cl = pm.cl0; cl < t.nc; cl += pm.cstep, ++j) {
       const double pl = rows[cl * P + 2 * pm.m], pr = rows[cl * P + 2 * pm.m + 1];
-      double *g = a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m;
       const double g0 = c0 + c1 * pl + c2 * pr, g1 = c3 + c4 * pl + c5 * pr;
-      g[0] = g0;
-      g[1] = g1;
+      *reinterpret_cast<double2 *>(a.gh + (size_t)(t.c0 + cl) * ghp + 2 * pm.m) =
+          make_double2(g0, g1);
       if (want_go) {   // (entry j by selects: a run-time index would put go in scratch)
 #pragma unroll
         for (int i = 0; i < kGPre; ++i)
@@ -447,13 +445,14 @@ template <int CH, bool VEC, int NF>
 __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const double *psi_prev,
                                   double *lds) {
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
-  double f0[CH];
+  double f0[CH], cg[6];
   gh_frags<CH, NF>(a, t, f0);
+  coef_load<6>(a, N, t.region, (int)threadIdx.x % N, 12, cg);   // (the thread's angle)
   const RowBlock blk[1] = {own_block(lds, psi_prev, t, K)};
   copy_blocks_to_lds(blk, 1, K, P);
   __syncthreads();
   GhOut unused;
-  gh_compute<CH, VEC, NF>(a, t, lds, f0, unused, false);
+  gh_compute<CH, VEC, NF>(a, t, lds, f0, cg, unused, false);
 }
 
 // One OCI iteration of a tile, in two phases: iterate_prefetch issues every
@@ -658,21 +657,27 @@ __device__ __forceinline__ void iterate_compute(const IterPrefetch<CH> &pf, cons
 // blockDim), this thread's angle's psi_{k-1/2} values, and the neighbour
 // rows of the iterate the accepted one was computed from (src; into LDS
 // later).
+// (psi_{k-1/2} of all of a thread's cells at N = 64: four cells per thread)
+template <int NF>
+struct EndPre {
+  static constexpr int n = NF == 64 ? 4 : kGPre;
+};
+template <int NF>
 struct EndLoads {
-  double pq[kGPre][2], pv;
+  double pq[EndPre<NF>::n][2], pv;
   CopyRegs cr;
 };
 
 template <int NF>
 __device__ __forceinline__ void end_loads(const StepArgs &a, const TileDev &t, const double *src,
                                           const double *psi_prev, const double *phi_acc,
-                                          double *lds, EndLoads &el) {
+                                          double *lds, EndLoads<NF> &el) {
   const int N = NF ? NF : a.N, K = 2 * N;
   const int pi = threadIdx.x;
   el.pv = pi < t.nc * 4 ? phi_acc[(size_t)t.c0 * 4 + pi] : 0.0;
   const PairMap pm(N);
 #pragma unroll
-  for (int j = 0; j < kGPre; ++j) {
+  for (int j = 0; j < EndPre<NF>::n; ++j) {
     const int cl = min(pm.cl0 + j * pm.cstep, t.nc - 1);   // (used only for cells < nc)
     const double2 p2 =
         *reinterpret_cast<const double2 *>(psi_prev + (size_t)(t.c0 + cl) * K + 2 * pm.m);
@@ -689,7 +694,8 @@ template <int CH, bool VEC, int NF>
 __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, const double *src,
                                 const double *psi_prev, double *psi_next, const double *phi_acc,
                                 double *phi_out, double *lds, GhOut &go, bool want_go,
-                                EndLoads &el, bool loaded) {
+                                EndLoads<NF> &el, bool loaded) {
+  constexpr int NQ = EndPre<NF>::n;
   __shared__ double sphi[4 * kTileCells];
   double fg[CH];   // P fragments for the next step's gh, issued early
   gh_frags<CH, NF>(a, t, fg);
@@ -698,12 +704,13 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
   const PairMap pm(N);
   const int m = pm.m;
   const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
-  double e[18];   // this thread's angle's coefficients of psi_{k+1/2} at L and R
+  double e[18], cg[6];   // this thread's angle's coefficients of psi_{k+1/2} and of g'
   coef_load<18>(a, N, t.region, m, 18, e);
+  coef_load<6>(a, N, t.region, m, 12, cg);
   if (!loaded) end_loads<NF>(a, t, src, psi_prev, phi_acc, lds, el);
   const int pi = threadIdx.x;
   const double pv = el.pv;
-  const double(&pq)[kGPre][2] = el.pq;
+  const double(&pq)[NQ][2] = el.pq;
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
   const CopyRegs &cr = el.cr;
   if (pi < t.nc * 4) {
@@ -721,15 +728,27 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
       const double *ph = sphi + cl * 4;
       const double *in = lds + (pos ? cl : cl + 2) * P + 2 * m;
       const double f0 = ph[0], f1 = ph[1], f2 = ph[2], f3 = ph[3];
-      const double pl = j < kGPre ? pq[j < kGPre ? j : 0][0] : pp[0];
-      const double pr = j < kGPre ? pq[j < kGPre ? j : 0][1] : pp[1];
+      double pl, pr;
+      if (j < NQ) {   // (entry j by selects: a run-time index would put pq in scratch)
+        pl = pq[0][0];
+        pr = pq[0][1];
+#pragma unroll
+        for (int q = 1; q < NQ; ++q)
+          if (q == j) {
+            pl = pq[q][0];
+            pr = pq[q][1];
+          }
+      } else {
+        pl = pp[0];
+        pr = pp[1];
+      }
       const double i0 = in[0], i1 = in[1];
       const double x2 = e[8] + e[0] * f0 + e[1] * f1 + e[2] * f2 + e[3] * f3 + e[4] * pl +
                         e[5] * pr + e[6] * i0 + e[7] * i1;
       const double x3 = e[17] + e[9] * f0 + e[10] * f1 + e[11] * f2 + e[12] * f3 + e[13] * pl +
                         e[14] * pr + e[15] * i0 + e[16] * i1;
-      psi_next[(size_t)(t.c0 + cl) * K + 2 * m] = x2;
-      psi_next[(size_t)(t.c0 + cl) * K + 2 * m + 1] = x3;
+      *reinterpret_cast<double2 *>(psi_next + (size_t)(t.c0 + cl) * K + 2 * m) =
+          make_double2(x2, x3);
       ldn[cl * P + 2 * m] = x2;
       ldn[cl * P + 2 * m + 1] = x3;
     }
@@ -737,7 +756,7 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
   // the next step's gh from psi_{k+1/2}, so that a queued step that
   // follows needs no step start
   __syncthreads();
-  gh_compute<CH, VEC, NF>(a, t, ldn, fg, go, want_go);
+  gh_compute<CH, VEC, NF>(a, t, ldn, fg, cg, go, want_go);
 }
 
 // Start of step `cur` of the current solve: gh for every tile from
@@ -1430,12 +1449,13 @@ __global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, in
 // when given).  A step still undecided (or not finite) stalls the queue
 // instead: the host resumes it.  The step's record is written either way; a
 // decided step advances the solve's step counter.
-template <int CH, bool ARGT, bool VEC, int NF>
+// FUSE: built with the next step's first iterate (mode bit 16 selects it at
+// run time); without it the kernel needs fewer registers.
+template <int CH, bool ARGT, bool VEC, int NF, bool FUSE>
 __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double *lds,
                                               double *phi_out, int first, int last, int half,
                                               int rstep, int mode) {
-  __shared__ double phis[4 * 64], phif[64];
-  const bool pre = mode & 1, fuse = (mode >> 4) & 1;
+  const bool pre = mode & 1, fuse = FUSE && ((mode >> 4) & 1);
   const int ntrail = (mode >> 1) & 7;   // iterates last-ntrail+1 .. last
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   RecRegs r1;
@@ -1460,7 +1480,7 @@ __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double 
   const int parity = c.psi_base ^ (c.open & 1);
   const double *psi_prev = parity ? a.psi1 : a.psi0;
   const bool spec = last >= 2;
-  EndLoads sel;
+  EndLoads<NF> sel;
   if (pre && spec)
     end_loads<NF>(a, t, out_at(a, ring_buf(a, last - 1, half)), psi_prev,
                   phi_at(a, ring_buf(a, last, half)), lds, sel);
@@ -1598,27 +1618,41 @@ __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double 
     record();
     return;
   }
-  // iterate 1 of the next step (ring half half^1) from the accepted iterate:
-  // every input is this tile's (its step constant, just formed) or already in
-  // memory (the neighbours' accepted outgoing fluxes), so one launch fewer
-  __syncthreads();
-  const int bl = ring_buf(a, L, half), bn = ring_buf(a, 1, half ^ 1);
-  IterPrefetch<CH> pf;
-  iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds, go, true);
-  // (mixed precision: iterate 1 is an FP64 iterate with its defect)
-  iterate_compute<CH, VEC, NF>(pf, a, t, out_at(a, bl), out_at(a, bn), phi_at(a, bn), lds, phis,
-                               phif,
-                               reinterpret_cast<double2 *>(a.partial) +
-                                   rec_slot(a, 1, half ^ 1) + wg,
-                               false, rstep == 2);
-  record();
+  if constexpr (FUSE) {
+    // iterate 1 of the next step (ring half half^1) from the accepted
+    // iterate: every input is this tile's (its step constant, just formed) or
+    // already in memory (the neighbours' accepted outgoing fluxes), so one
+    // launch fewer
+    __shared__ double phis[4 * 64], phif[64];
+    __syncthreads();
+    const int bl = ring_buf(a, L, half), bn = ring_buf(a, 1, half ^ 1);
+    IterPrefetch<CH> pf;
+    iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds, go, true);
+    // (mixed precision: iterate 1 is an FP64 iterate with its defect)
+    iterate_compute<CH, VEC, NF>(pf, a, t, out_at(a, bl), out_at(a, bn), phi_at(a, bn), lds,
+                                 phis, phif,
+                                 reinterpret_cast<double2 *>(a.partial) +
+                                     rec_slot(a, 1, half ^ 1) + wg,
+                                 false, rstep == 2);
+    record();
+  }
 }
 
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out, int first,
                                                   int last, int half, int rstep, int mode) {
   extern __shared__ double lds[];
-  step_end_body<CH, ARGT, VEC, NF>(a, blockIdx.x, lds, phi_out, first, last, half, rstep, mode);
+  step_end_body<CH, ARGT, VEC, NF, true>(a, blockIdx.x, lds, phi_out, first, last, half, rstep,
+                                         mode);
+}
+
+// The end of step without the fused iterate (mode bit 16 ignored).
+template <int CH, bool ARGT, bool VEC, int NF>
+__global__ __launch_bounds__(256, 3) void k_step_end_nf(StepArgs a, double *phi_out, int first,
+                                                     int last, int half, int rstep, int mode) {
+  extern __shared__ double lds[];
+  step_end_body<CH, ARGT, VEC, NF, false>(a, blockIdx.x, lds, phi_out, first, last, half, rstep,
+                                          mode);
 }
 
 
@@ -2038,7 +2072,6 @@ __global__ __launch_bounds__(256) void k_oci_inner2(StepArgs a, int n, int ly, i
   for (int side = 0; side < 2; ++side) {
     const bool left = side == 0;
     if (!(left ? hl && wave == wl : hr && wave == wr)) continue;
-    const int hc = left ? t.c0 - 1 : t.c0 + t.nc;
     const float *row_l = A + (left ? 0 : t.nc + 1) * P;   // the halo cell's left neighbour
     const float *row_r = A + (left ? 2 : t.nc + 3) * P;   // and its right one
     float *orow = B + (left ? 0 : t.nc + 1) * P;
@@ -2253,7 +2286,7 @@ __global__ __launch_bounds__(256, 3) void kb_step_end(const StepArgs *probs, dou
                                                       const int *last, int half, int mode) {
   extern __shared__ double lds[];
   const int2 q = queue[blockIdx.x];
-  step_end_body<CH, false, true, 0>(probs[q.x], q.y, lds, phi_outs ? phi_outs[q.x] : nullptr,
+  step_end_body<CH, false, true, 0, false>(probs[q.x], q.y, lds, phi_outs ? phi_outs[q.x] : nullptr,
                                     first[q.x], last[q.x], half, 1, mode);
 }
 
@@ -2311,74 +2344,98 @@ template __global__ void k_oci_inner2<false>(StepArgs, int, int, int, int);
 template __global__ void k_step_begin<4, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, false, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, false, false, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<4, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, false, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, false, true, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<4, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, false, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, false, false, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<8, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, false, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, false, true, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<8, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, false, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, false, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, false, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, false, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, false, true, 8>(StepArgs);
 template __global__ void k_oci_iterate<4, false, true, 8>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, false, true, 8>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<4, false, true, 8>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, false, true, 16>(StepArgs);
 template __global__ void k_oci_iterate<8, false, true, 16>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, false, true, 16>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<8, false, true, 16>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 32>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 32>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 32>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, false, true, 32>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 64>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 64>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 64>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, false, true, 64>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 128>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 128>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 128>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, false, true, 128>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, false, true, 256>(StepArgs);
 template __global__ void k_oci_iterate<16, false, true, 256>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, false, true, 256>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, false, true, 256>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, true, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, true, false, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<4, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<4, true, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, true, true, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<4, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, true, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, true, false, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<8, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<8, true, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, true, true, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<8, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, false, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, true, false, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, false, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, true, false, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 0>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 0>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 0>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, true, true, 0>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<4, true, true, 8>(StepArgs);
 template __global__ void k_oci_iterate<4, true, true, 8>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<4, true, true, 8>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<4, true, true, 8>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<8, true, true, 16>(StepArgs);
 template __global__ void k_oci_iterate<8, true, true, 16>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<8, true, true, 16>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<8, true, true, 16>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 32>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 32>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 32>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, true, true, 32>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 64>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 64>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 64>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, true, true, 64>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 128>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 128>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 128>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, true, true, 128>(StepArgs, double *, int, int, int, int, int);
 template __global__ void k_step_begin<16, true, true, 256>(StepArgs);
 template __global__ void k_oci_iterate<16, true, true, 256>(StepArgs, int, int, int, int, int);
 template __global__ void k_step_end<16, true, true, 256>(StepArgs, double *, int, int, int, int, int);
+template __global__ void k_step_end_nf<16, true, true, 256>(StepArgs, double *, int, int, int, int, int);
 
 }  // namespace ocik
