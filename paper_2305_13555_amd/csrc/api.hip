@@ -948,8 +948,11 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
                       : add(c->fn_inner, c->W_it, c->lds_in, iargs);
           i += lv;
         }
+        // (iterate 1's outgoing fluxes feed nothing when a correction follows;
+        // the last FP64 iterate's defect only a resumed step, which forms it)
         int node = 2 * o - 1, cb = 0, nred = 1;
-        void *args[] = {&c->sa, &node, &cb, &h, &rstep, &nred};
+        int rmode = rstep | (o == 1 && L >= 2 ? 4 : 0) | (o == L ? 8 : 0);
+        void *args[] = {&c->sa, &node, &cb, &h, &rmode, &nred};
         if (e == hipSuccess) e = add(c->fn_iter, c->W_it, c->lds_it, args, 1);
       }
     } else {
@@ -978,7 +981,7 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
     }
     const bool fuse = fuse_ok && s + 1 < G;
     int first = 1, last = c->mixed ? 2 * L - 1 : L, nred = c->mixed ? 1 : last_n;
-    int pre = c->pre_reduce, mode = pre | (nred << 1) | (fuse ? 16 : 0);
+    int pre = c->pre_reduce, mode = pre | (nred << 1) | (fuse ? 16 : 0) | (fuse && c->mixed ? 32 : 0);
     if (e == hipSuccess && pre) {
       void *rargs[] = {&c->sa, &last, &nred, &h};
       hipKernelNodeParams kp{};
@@ -1135,6 +1138,12 @@ static int resume_step(oci_ctx *c, int launched, double *phi_dev, int *total_lau
     if (rc) return rc;
     ++extra;
     if (c->mixed) {
+      if (extra == 1) {   // the defect of the last queued FP64 iterate (not stored by it)
+        int l = launched, h = c->parity;
+        void *dargs[] = {&c->sa, &l, &h};
+        OCI_CK(c, hipLaunchKernel((const void *)k_defect, dim3(1024), dim3(256), dargs, 0,
+                                  c->stream));
+      }
       rc = launch_outer(c, launched, c->parity);
       if (rc) return rc;
       launched += 2;

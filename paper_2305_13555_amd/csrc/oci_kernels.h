@@ -132,13 +132,18 @@ __global__ void k_region_setup(SetupArgs q);
 // ARGT: tile descriptors in the kernel arguments; VEC: 16-byte operand
 // reads (N % 8 == 0); NF > 0: built for N = NF angles, 0: any N.
 template <int CH, bool ARGT, bool VEC, int NF> __global__ void k_step_begin(StepArgs a);
-// half: the ring half of the step's iterates.  rstep: 1 for plain FP64 OCI;
-// 2 for the mixed-precision step, where the FP64 iterates are every other one
-// (iterate l even is formed by the FP32 inner iterations) and each FP64
-// iterate also writes its defect in FP32.  nred: iterates of the previous
-// launch whose residual this launch reduces (2 after a two-iterate launch).
+// half: the ring half of the step's iterates.  rmode bits 0-1 (rstep): 1 for
+// plain FP64 OCI; 2 for the mixed-precision step, where the FP64 iterates are
+// every other one (iterate l even is formed by the FP32 inner iterations) and
+// each FP64 iterate also writes its defect in FP32; bit 2: the outgoing
+// fluxes are not stored, bit 3: the defect is not stored.  nred: iterates of
+// the previous launch whose residual this launch reduces (2 after a
+// two-iterate launch).
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rstep, int nred);
+__global__ void k_oci_iterate(StepArgs a, int node, int cb, int half, int rmode, int nred);
+// The FP32 defect of FP64 iterate l against its starting point (mixed
+// precision, resumed steps).
+__global__ void k_defect(StepArgs a, int l, int half);
 // Iterates l = cb + node and l + 1 in one launch (plain FP64 OCI); nred: the
 // previous launch's iterates, whose residuals the extra work-group reduces.
 template <int CH, bool ARGT, bool VEC, int NF>
@@ -150,7 +155,8 @@ __global__ void k_oci_iterateK(StepArgs a, int node, int cb, int half, int nred)
 // ran before); bits 1-3: the trailing iterates (those of the batch's last
 // launch, 1 .. 4), whose e this kernel forms; bit 4: a decided step also
 // computes iterate 1 of the next step (plain OCI; the next step's launches
-// start at 2).
+// start at 2); bit 5: that iterate (mixed precision, a correction follows)
+// does not store its outgoing fluxes.
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int half,
                            int rstep, int mode);

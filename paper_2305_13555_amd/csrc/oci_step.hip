@@ -534,7 +534,7 @@ __device__ __forceinline__ void iterate_prefetch(IterPrefetch<CH> &pf, const Ste
 template <int NF, int CH>
 __device__ __forceinline__ void iterate_pairs(const IterPrefetch<CH> &pf, const StepArgs &a,
                                      const TileDev &t, double *dst, const double *lds,
-                                     const double *phif, const PairMap &pm, bool defect) {
+                                     const double *phif, const PairMap &pm, int wm) {
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
   const int ghp = (NF ? (2 * NF + 4 + 15) / 16 : a.Mt) * 16;
   const int m = pm.m;
@@ -557,25 +557,25 @@ __device__ __forceinline__ void iterate_pairs(const IterPrefetch<CH> &pf, const 
     const double *c = pf.cf;
     const double o0 = g0 + c[0] * f0 + c[1] * f1 + c[2] * f2 + c[3] * f3 + c[4] * i0 + c[5] * i1;
     const double o1 = g1 + c[6] * f0 + c[7] * f1 + c[8] * f2 + c[9] * f3 + c[10] * i0 + c[11] * i1;
-    dst[(cell + 1) * K + 2 * m] = o0;
-    dst[(cell + 1) * K + 2 * m + 1] = o1;
+    if (wm & 1) *reinterpret_cast<double2 *>(dst + (cell + 1) * K + 2 * m) = make_double2(o0, o1);
     // the defect against the iterate this one was computed from (its own
     // row is staged in LDS row cl+1)
-    if (defect) {
-      a.dlt[(cell + 1) * K + 2 * m] = (float)(o0 - lds[(cl + 1) * P + 2 * m]);
-      a.dlt[(cell + 1) * K + 2 * m + 1] = (float)(o1 - lds[(cl + 1) * P + 2 * m + 1]);
-    }
+    if (wm & 2)
+      *reinterpret_cast<float2 *>(a.dlt + (cell + 1) * K + 2 * m) =
+          make_float2((float)(o0 - lds[(cl + 1) * P + 2 * m]),
+                      (float)(o1 - lds[(cl + 1) * P + 2 * m + 1]));
   }
 }
 
 // Computes the tile's iterate; wave 0 writes its residual record (rec).
-// Returns early (no stores) when `skip` is set (a stalled queue).  With
-// `defect`, also the FP32 defect against the iterate this one started from.
+// Returns early (no stores) when `skip` is set (a stalled queue).  wm: bit 0
+// stores the outgoing fluxes (always the scalar flux), bit 1 also the FP32
+// defect against the iterate this one started from (mixed precision).
 template <int CH, bool VEC, int NF>
 __device__ __forceinline__ void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
                                        double *phi_new, double *lds, double *phis, double *phif,
-                                       double2 *rec, bool skip, bool defect) {
+                                       double2 *rec, bool skip, int wm) {
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -623,7 +623,7 @@ __device__ __forceinline__ void iterate_compute(const IterPrefetch<CH> &pf, cons
     phif[lane] = v;
     if (cl < t.nc) {
       phi_new[(size_t)(t.c0 + cl) * 4 + comp] = v;
-      if (defect) a.dphi32[(size_t)(t.c0 + cl) * 4 + comp] = (float)(v - pf.po);
+      if (wm & 2) a.dphi32[(size_t)(t.c0 + cl) * 4 + comp] = (float)(v - pf.po);
       dphi = isfinite(v) ? fabs(v - pf.po) : __builtin_nan("");
       fphi = fabs(v);
     }
@@ -632,7 +632,7 @@ __device__ __forceinline__ void iterate_compute(const IterPrefetch<CH> &pf, cons
   // outgoing pairs of this thread's angle for its cells; then wave 0 reduces
   // the residual record (after the pairs, so that no wave waits for it)
   const PairMap pm(N);
-  if (pm.active) iterate_pairs<NF>(pf, a, t, dst, lds, phif, pm, defect);
+  if (pm.active) iterate_pairs<NF>(pf, a, t, dst, lds, phif, pm, wm);
   if (wave == 0) {
     dphi = wave_nan_max(dphi);
     fphi = wave_max(fphi);
@@ -813,10 +813,17 @@ __device__ inline void reduce_prev(const StepArgs &a, int l, int rstep, int nred
   }
 }
 
+// rmode: bits 0-1 the stride of the judged iterates (1; 2 for mixed
+// precision, whose FP64 iterates also store their FP32 defect), bit 2 the
+// outgoing fluxes are not stored (a mixed-precision iterate 1 that a
+// correction follows: nothing reads them), bit 3 the defect is not stored
+// (the last FP64 iterate a queued step planned; a resumed step forms it).
 template <int CH, bool ARGT, bool VEC, int NF>
 __device__ __forceinline__ void oci_iterate_body(const StepArgs &a, int wg, double *lds, int node,
-                                                 int cb, int half, int rstep, int nred) {
+                                                 int cb, int half, int rmode, int nred) {
   __shared__ double red[2], scratch[2 * kMaxWaves], phis[4 * 64], phif[64];
+  const int rstep = rmode & 3;
+  const int wm = ((rmode & 4) ? 0 : 1) | ((rstep == 2 && !(rmode & 8)) ? 2 : 0);
   const int l = cb + node;
   if (wg == a.ntiles) {
     reduce_prev(a, l, rstep, nred, half, red, scratch);
@@ -843,15 +850,39 @@ __device__ __forceinline__ void oci_iterate_body(const StepArgs &a, int wg, doub
   const int stalled = a.ctl->stalled;
   iterate_compute<CH, VEC, NF>(pf, a, t, src, dst, phi_new, lds, phis, phif,
                       reinterpret_cast<double2 *>(a.partial) + rec_slot(a, l, half) + ti,
-                      stalled != 0, rstep == 2);
+                      stalled != 0, wm);
   open_step(a, l, cur, fb, stalled, wg);
 }
 
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ __launch_bounds__(256, 3) void k_oci_iterate(StepArgs a, int node, int cb, int half,
-                                                        int rstep, int nred) {
+                                                        int rmode, int nred) {
   extern __shared__ double lds[];
-  oci_iterate_body<CH, ARGT, VEC, NF>(a, blockIdx.x, lds, node, cb, half, rstep, nred);
+  oci_iterate_body<CH, ARGT, VEC, NF>(a, blockIdx.x, lds, node, cb, half, rmode, nred);
+}
+
+// The FP32 defect of FP64 iterate l of the open step (mixed precision)
+// against the point it was computed from (iterate l-1, or the step's start
+// for l = 1): outgoing part into correction buffer 0, scalar-flux part into
+// dphi32.  For a resumed step whose last queued FP64 iterate did not store
+// it.  Grid-stride over the cells' K outgoing values and 4 scalar fluxes.
+__global__ __launch_bounds__(256) void k_defect(StepArgs a, int l, int half) {
+  const int K = 2 * a.N;
+  const int bp = l == 1 ? a.ctl->base_buf : ring_buf(a, l - 1, half);
+  const int bl = ring_buf(a, l, half);
+  const double *x = out_at(a, bl), *y = out_at(a, bp);
+  const double *xp = phi_at(a, bl), *yp = phi_at(a, bp);
+  const size_t n_out = (size_t)a.J * K, n_phi = (size_t)a.J * 4;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out + n_phi;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < n_out) {
+      const size_t e = K + i;   // (row 0 is the ghost row)
+      a.dlt[e] = (float)(x[e] - y[e]);
+    } else {
+      const size_t e = i - n_out;
+      a.dphi32[e] = (float)(xp[e] - yp[e]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1633,7 +1664,7 @@ __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double 
                                  phis, phif,
                                  reinterpret_cast<double2 *>(a.partial) +
                                      rec_slot(a, 1, half ^ 1) + wg,
-                                 false, rstep == 2);
+                                 false, ((mode & 32) ? 0 : 1) | (rstep == 2 ? 2 : 0));
     record();
   }
 }
