@@ -986,7 +986,7 @@ static int step_graph(oci_ctx *c, int L, int G, int half, int begin, double *phi
       void *rargs[] = {&c->sa, &last, &nred, &h};
       hipKernelNodeParams kp{};
       kp.func = (void *)k_reduce_rec;
-      kp.gridDim = dim3(1);
+      kp.gridDim = dim3(nred);   // (one work-group per trailing iterate)
       kp.blockDim = dim3(256);
       kp.sharedMemBytes = 0;
       kp.kernelParams = rargs;
@@ -1090,7 +1090,8 @@ static int launch_end(oci_ctx *c, double *phi_dev, int first, int last, int half
   int rstep = c->rstep, pre = c->pre_reduce, nred = 1, mode = pre | 2;
   if (pre) {
     void *rargs[] = {&c->sa, &last, &nred, &half};
-    OCI_CK(c, hipLaunchKernel((const void *)k_reduce_rec, dim3(1), dim3(256), rargs, 0, c->stream));
+    OCI_CK(c, hipLaunchKernel((const void *)k_reduce_rec, dim3(nred), dim3(256), rargs, 0,
+                              c->stream));
   }
   void *args[] = {&c->sa, &phi_dev, &first, &last, &half, &rstep, &mode};
   OCI_CK(c, hipLaunchKernel(c->fn_end_nf, dim3(c->grid), dim3(64 * c->W_ed), args, c->lds_ed,

@@ -164,6 +164,8 @@ __global__ void k_step_end(StepArgs a, double *phi_out, int first, int last, int
 template <int CH, bool ARGT, bool VEC, int NF>
 __global__ void k_step_end_nf(StepArgs a, double *phi_out, int first, int last, int half,
                               int rstep, int mode);
+// e of iterates l-n+1 .. l from their residual records into dec, one
+// work-group per iterate (grid n).
 __global__ void k_reduce_rec(StepArgs a, int l, int n, int half);
 // FP32 inner iteration i (1-based) of a mixed-precision step; ly > 0: the last
 // one, which also forms FP64 iterate ly (the point iterate ly-1 started from

@@ -1467,8 +1467,10 @@ __device__ __forceinline__ void reduce_rec_body(const StepArgs &a, int l, int n,
   }
 }
 
+// One work-group per iterate l-n+1 .. l (grid n): each reduces its own
+// iterate's records and writes its own dec slot.
 __global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, int half) {
-  reduce_rec_body(a, l, n, half);
+  reduce_rec_body(a, l - n + 1 + (int)blockIdx.x, 1, half);
 }
 
 // End of the open step after iterates first .. last of it were launched
