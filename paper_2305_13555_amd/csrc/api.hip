@@ -52,6 +52,10 @@ struct oci_ctx {
   int Mt = 0, Met = 0, Mto = 0, ntiles = 0, grid = 0, W_it = 1, W_ed = 1, W_pv = 1;
   size_t lds_it = 0, lds_pv = 0, lds_ed = 0;
   int si_blocks = 0, si_segs = 1;
+  bool si_lane = false;   // the angle-lane sweep (N/2 a power of two, N <= 128)
+  int si_nseg = 1;        // its segments
+  double2 *d_segin = nullptr;
+  Affine *d_chmap = nullptr;
   std::vector<void *> allocs;
   double *d_mu = nullptr, *d_w = nullptr;
   RegionDev *d_regions = nullptr;
@@ -275,8 +279,14 @@ static int build_si_graph(oci_ctx *c, int count) {
   for (int i = 1; i <= count && e == hipSuccess; ++i) {
     int node = i, cb = 0;
     void *args[] = {&c->si, &node, &cb};
-    e = add((void *)k_si_maps, dim3(c->N / 2, c->si_segs), dim3(256), 0, args);
-    if (e == hipSuccess) e = add((void *)k_si_sweep, dim3(c->N / 2, c->si_segs), dim3(256), 0, args);
+    if (c->si_lane) {
+      e = add((void *)k_si_smaps, dim3(c->si_nseg, 2), dim3(256), 0, args);
+      if (e == hipSuccess) e = add((void *)k_si_enter, dim3(c->N / 2), dim3(256), 0, args);
+      if (e == hipSuccess) e = add((void *)k_si_lsweep, dim3(c->si_nseg, 2), dim3(256), 0, args);
+    } else {
+      e = add((void *)k_si_maps, dim3(c->N / 2, c->si_segs), dim3(256), 0, args);
+      if (e == hipSuccess) e = add((void *)k_si_sweep, dim3(c->N / 2, c->si_segs), dim3(256), 0, args);
+    }
     if (e == hipSuccess) e = add((void *)k_si_reduce, dim3(c->si_blocks), dim3(256), 0, args);
     if (e == hipSuccess) e = add((void *)k_si_decide, dim3(1), dim3(256), 0, args);
   }
@@ -423,6 +433,13 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   // source-iteration sweep segments: about two cells per thread of a
   // 256-thread work-group, at most 64 segments
   c->si_segs = std::max(1, std::min(64, (J + 511) / 512));
+  // the angle-lane sweep: 256 threads = N/2 angles x C chunks per segment,
+  // about four cells per chunk, at most 512 segments
+  c->si_lane = N <= 128 && ((N / 2) & (N / 2 - 1)) == 0;
+  if (c->si_lane) {
+    const int C = 256 / (N / 2);
+    c->si_nseg = (int)std::max<long long>(1, std::min<long long>(512, ((long long)J + 4 * C - 1) / (4 * C)));
+  }
   c->ghost_left.assign(K, 0.0);
   c->ghost_right.assign(K, 0.0);
   if (p->bc_left == OCI_BC_INCIDENT)
@@ -486,9 +503,13 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   OCI_TRY(dalloc(c, &c->d_ainv, (size_t)R * N * 16));
   OCI_TRY(dalloc(c, &c->d_coef, (size_t)R * N * kCoef));
   OCI_TRY(dalloc(c, &c->d_phig, (size_t)R * 8 * N));
-  OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(N / 2) * J * 4));
+  OCI_TRY(dalloc(c, &c->d_contrib, (size_t)(c->si_lane ? 2 : N / 2) * J * 4));
   OCI_TRY(dalloc(c, &c->d_lag, (size_t)2 * N));
-  OCI_TRY(dalloc(c, &c->d_segmap, (size_t)(N / 2) * c->si_segs * 2));
+  OCI_TRY(dalloc(c, &c->d_segmap, (size_t)(N / 2) * std::max(c->si_segs, c->si_nseg) * 2));
+  if (c->si_lane) {
+    OCI_TRY(dalloc(c, &c->d_segin, (size_t)(N / 2) * c->si_nseg * 2));
+    OCI_TRY(dalloc(c, &c->d_chmap, (size_t)256 * c->si_nseg * 2));
+  }
   OCI_TRY(dalloc(c, &c->d_si_partial, (size_t)3 * c->si_blocks * 4));
   OCI_TRY(dalloc(c, &c->d_ctl, 1));
   if (c->mixed) {
@@ -615,8 +636,12 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   q.psi0 = c->d_psi[0];
   q.psi1 = c->d_psi[1];
   q.contrib = c->d_contrib;
+  q.ncontrib = c->si_lane ? 2 : N / 2;
   q.lag = c->d_lag;
   q.segmap = c->d_segmap;
+  q.segin = c->d_segin;
+  q.chmap = c->d_chmap;
+  q.nseg = c->si_nseg;
   q.phi_res = c->d_phi_res;
   q.partial = c->d_si_partial;
   q.nparts = c->si_blocks;
@@ -753,10 +778,19 @@ static int launch_batch(oci_ctx *c, bool si, int cb, int count, int half = 0) {
                                 c->stream));
     } else {
       void *args[] = {&c->si, &node, &cb};
-      OCI_CK(c, hipLaunchKernel((const void *)k_si_maps, dim3(c->N / 2, c->si_segs), dim3(256),
-                                args, 0, c->stream));
-      OCI_CK(c, hipLaunchKernel((const void *)k_si_sweep, dim3(c->N / 2, c->si_segs), dim3(256),
-                                args, 0, c->stream));
+      if (c->si_lane) {
+        OCI_CK(c, hipLaunchKernel((const void *)k_si_smaps, dim3(c->si_nseg, 2), dim3(256), args, 0,
+                                  c->stream));
+        OCI_CK(c, hipLaunchKernel((const void *)k_si_enter, dim3(c->N / 2), dim3(256), args, 0,
+                                  c->stream));
+        OCI_CK(c, hipLaunchKernel((const void *)k_si_lsweep, dim3(c->si_nseg, 2), dim3(256), args,
+                                  0, c->stream));
+      } else {
+        OCI_CK(c, hipLaunchKernel((const void *)k_si_maps, dim3(c->N / 2, c->si_segs), dim3(256),
+                                  args, 0, c->stream));
+        OCI_CK(c, hipLaunchKernel((const void *)k_si_sweep, dim3(c->N / 2, c->si_segs), dim3(256),
+                                  args, 0, c->stream));
+      }
       OCI_CK(c, hipLaunchKernel((const void *)k_si_reduce, dim3(c->si_blocks), dim3(256), args, 0,
                                 c->stream));
       OCI_CK(c, hipLaunchKernel((const void *)k_si_decide, dim3(1), dim3(256), args, 0,

@@ -90,10 +90,16 @@ struct SiArgs {
   double *phib;
   size_t phi_stride;
   double *psi0, *psi1;      // [J][2N]
-  double *contrib;          // [N/2][J][4] pair sums of w_m psi_m
+  double *contrib;          // [ncontrib][J][4] partial sums of w_m psi_m (angle-pair
+                            //   sweep: one per pair; angle-lane sweep: one per direction)
+  int ncontrib;
   double *lag;              // [2][N/2][2] right-edge outgoing flux of the mu > 0 angle,
                             //   by iterate parity (both edges reflecting)
   Affine *segmap;           // [N/2][S][2] segment maps of the two sweep directions
+                            //   (angle-lane sweep: [2][nseg][N/2])
+  double2 *segin;           // angle-lane sweep: [2][nseg][N/2] flux entering each segment
+  Affine *chmap;            // angle-lane sweep: [2][nseg][256] chunk maps, by thread
+  int nseg;                 // angle-lane sweep: segments
   double *phi_res;          // [J][4]
   double *partial;          // [3][nparts] double2 residual records
   int nparts;
@@ -204,6 +210,11 @@ __global__ void k_learn_features(StepArgs a, int l, int half, int ch, double amp
 __global__ void k_learn_apply(StepArgs a, int l, int half, const float *y);
 // si.hip
 __global__ void k_si_maps(SiArgs a, int node, int cb);
+// The angle-lane sweep (N/2 a power of two, N <= 128): grid (nseg, 2) for the
+// segment maps and the sweep, grid N/2 for the segments' entering fluxes.
+__global__ void k_si_smaps(SiArgs a, int node, int cb);
+__global__ void k_si_enter(SiArgs a, int node, int cb);
+__global__ void k_si_lsweep(SiArgs a, int node, int cb);
 __global__ void k_si_sweep(SiArgs a, int node, int cb);
 __global__ void k_si_reduce(SiArgs a, int node, int cb);
 __global__ void k_si_decide(SiArgs a, int node, int cb);

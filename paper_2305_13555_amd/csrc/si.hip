@@ -249,6 +249,320 @@ __global__ __launch_bounds__(kSiThreads) void k_si_sweep(SiArgs a, int node, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// The angle-lane sweep: a work-group holds every angle of one sweep direction
+// for a segment of cells, lane a <-> angle a of the direction (m = a for
+// mu < 0, N/2 + a for mu > 0) and chunk c of the segment (thread c * N/2 + a),
+// so a load of psi_{k-1/2} or a store of psi_{k+1/2} and of the outgoing
+// fluxes covers consecutive angles of one cell (contiguous in memory).  The
+// chunk maps are scanned across the chunks of each angle in LDS; the
+// segments' maps across the mesh by k_si_enter (one work-group per angle
+// pair); the scalar-flux contribution of a cell sums over the direction's
+// angles across the lanes of its chunk group in a fixed order, so the two
+// directions leave two partial sums per cell (k_si_reduce adds them).
+// ---------------------------------------------------------------------------
+
+// Angle m, direction and position of this thread (threads past the last full
+// chunk group idle).
+struct LaneMap {
+  int NA, C, a, c;
+  bool active;
+  __device__ __forceinline__ LaneMap(int N) {
+    NA = N / 2;
+    C = (int)blockDim.x / NA;
+    a = (int)threadIdx.x % NA;
+    c = (int)threadIdx.x / NA;
+    active = c < C;
+  }
+};
+
+// Chunk at sweep position q of C in a segment [lo, hi): cells [jb, je).
+__device__ __forceinline__ void lane_chunk(int lo, int hi, int C, int q, bool pos, int *jb,
+                                           int *je) {
+  const int n = hi - lo;
+  const int k = pos ? q : C - 1 - q;   // chunk index in mesh order
+  *jb = lo + (int)(((long long)n * k) / C);
+  *je = lo + (int)(((long long)n * (k + 1)) / C);
+}
+
+// A chunk swept cell by cell with the loads of the next cell issued before
+// the current cell's arithmetic, and the region's data (its 4x4 A_m^{-1},
+// dx, sigma_s, Q) kept in registers while the cells stay in one region
+// (regions are contiguous cell ranges: the sweep steps into the neighbouring
+// region at its edge).  The per-cell arithmetic is cell_solve's.
+struct LaneRegion {
+  RegionDev g;
+  double Ai[16];
+  int r;
+};
+
+__device__ __forceinline__ void lane_region(const SiArgs &a, int r, int m, LaneRegion &lr) {
+  lr.r = r;
+  lr.g = a.regions[r];
+  const double2 *p = reinterpret_cast<const double2 *>(a.ainv + ((size_t)r * a.N + m) * 16);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double2 v = p[i];
+    lr.Ai[2 * i] = v.x;
+    lr.Ai[2 * i + 1] = v.y;
+  }
+}
+
+struct LaneIn {
+  double2 f01, f23, ps;   // phi_old (4) and psi_{k-1/2} of the cell and angle
+};
+
+__device__ __forceinline__ LaneIn lane_in(const double *phi_old, const double *psi_prev, int j,
+                                          int m, int K) {
+  LaneIn v;
+  v.f01 = *reinterpret_cast<const double2 *>(phi_old + (size_t)j * 4);
+  v.f23 = *reinterpret_cast<const double2 *>(phi_old + (size_t)j * 4 + 2);
+  v.ps = *reinterpret_cast<const double2 *>(psi_prev + (size_t)j * K + 2 * m);
+  return v;
+}
+
+__device__ __forceinline__ CellSolve lane_solve(const SiArgs &a, const LaneRegion &lr,
+                                                const LaneIn &v, bool pos, double amu) {
+  const RegionDev &g = lr.g;
+  const double po[4] = {v.f01.x, v.f01.y, v.f23.x, v.f23.y};
+  double b[4];
+  const double qs = g.dx / 4.0;
+  for (int c = 0; c < 4; ++c) b[c] = qs * (g.sigs * po[c] + g.q);
+  b[0] += a.a * g.dx / 2.0 * v.ps.x;
+  b[1] += a.a * g.dx / 2.0 * v.ps.y;
+  CellSolve s;
+  const int in0 = pos ? 0 : 1, in1 = pos ? 2 : 3;
+  const double *Ai = lr.Ai;
+  for (int i = 0; i < 4; ++i) {
+    s.y[i] = Ai[i * 4 + 0] * b[0] + Ai[i * 4 + 1] * b[1] + Ai[i * 4 + 2] * b[2] + Ai[i * 4 + 3] * b[3];
+    s.c0[i] = amu * Ai[i * 4 + in0];
+    s.c1[i] = amu * Ai[i * 4 + in1];
+  }
+  return s;
+}
+
+// The region of cell j, stepping from the cached one (sweep direction dir).
+__device__ __forceinline__ void lane_track(const SiArgs &a, int j, int m, LaneRegion &lr) {
+  if (j >= lr.g.j0 && j < lr.g.j0 + lr.g.nc) return;
+  int r = lr.r;
+  do {
+    r += j >= lr.g.j0 + lr.g.nc ? 1 : -1;
+    lane_region(a, r, m, lr);
+  } while (j < lr.g.j0 || j >= lr.g.j0 + lr.g.nc);
+}
+
+// Map of the chunk [jb, je) in sweep order (as chunk_map).
+__device__ Affine lane_chunk_map(const SiArgs &a, const double *phi_old, const double *psi_prev,
+                                 int jb, int je, int m, bool pos) {
+  const double amu = fabs(a.mu[m]);
+  const int o0 = pos ? 1 : 0, o1 = pos ? 3 : 2, K = 2 * a.N, n = je - jb, dir = pos ? 1 : -1;
+  Affine f = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+  if (n <= 0) return f;
+  int j = pos ? jb : je - 1;
+  LaneRegion lr;
+  lane_region(a, a.cell_region[j], m, lr);
+  LaneIn cur = lane_in(phi_old, psi_prev, j, m, K);
+  for (int q = 0; q < n; ++q) {
+    LaneIn nxt = cur;
+    if (q + 1 < n) nxt = lane_in(phi_old, psi_prev, j + dir, m, K);
+    lane_track(a, j, m, lr);
+    const CellSolve cs = lane_solve(a, lr, cur, pos, amu);
+    const Affine g = {cs.c0[o0], cs.c1[o0], cs.c0[o1], cs.c1[o1], cs.y[o0], cs.y[o1]};
+    f = compose(g, f);
+    cur = nxt;
+    j += dir;
+  }
+  return f;
+}
+
+// Segment maps of both directions: grid (nseg, 2), blockIdx.y = pass.
+__global__ __launch_bounds__(256) void k_si_smaps(SiArgs a, int node, int cbase) {
+  __shared__ Affine s_map[256];
+  const StepCtl c = *a.ctl;
+  if (c.stalled || c.status != kRunning) return;
+  const int l = cbase + node;
+  const double *phi_old = ((l - 1) & 1) ? a.phi1 : a.phi0;
+  const double *psi_prev = c.step_parity ? a.psi1 : a.psi0;
+  const int s = blockIdx.x, pass = blockIdx.y, S = a.nseg;
+  const bool pos = pass_positive(a, pass);
+  const LaneMap lm(a.N);
+  const int lo = seg_edge(s, a.J, S), hi = seg_edge(s + 1, a.J, S);
+  if (lm.active) {
+    const int m = pos ? lm.NA + lm.a : lm.a;
+    int jb, je;
+    lane_chunk(lo, hi, lm.C, lm.c, pos, &jb, &je);
+    const Affine f = lane_chunk_map(a, phi_old, psi_prev, jb, je, m, pos);
+    s_map[threadIdx.x] = f;
+    a.chmap[((size_t)pass * S + s) * blockDim.x + threadIdx.x] = f;   // (for k_si_lsweep)
+  }
+  __syncthreads();
+  // the segment's map: the chunks composed in sweep order (one thread per angle)
+  if (lm.active && lm.c == 0) {
+    Affine f = s_map[lm.a];
+    for (int q = 1; q < lm.C; ++q) f = compose(s_map[q * lm.NA + lm.a], f);
+    a.segmap[((size_t)pass * S + s) * lm.NA + lm.a] = f;
+  }
+}
+
+// The flux entering every segment, both directions, for angle pair p =
+// blockIdx.x (mu < 0 angle p, mu > 0 angle N-1-p): a scan of the segment maps
+// in sweep order (each thread composes a run of consecutive segments, a
+// work-group scan joins the runs), applied to the flux entering the mesh.
+__global__ __launch_bounds__(256) void k_si_enter(SiArgs a, int node, int cbase) {
+  __shared__ Affine s_map[256];
+  __shared__ double s_x[2];
+  const StepCtl c = *a.ctl;
+  if (c.stalled || c.status != kRunning) return;
+  const int l = cbase + node;
+  const int par = (l - 1) & 1;
+  const double *lag_in = a.lag + (size_t)par * a.N;
+  double *lag_out = a.lag + (size_t)(l & 1) * a.N;
+  const double *ghosts = a.out0;   // ghost rows are identical in both buffers
+  const int N = a.N, J = a.J, K = 2 * N, NA = N / 2, S = a.nseg;
+  const int p = blockIdx.x;
+  const int T = (S + (int)blockDim.x - 1) / (int)blockDim.x;   // segments per thread
+  const int q0 = (int)threadIdx.x * T;
+  double exit0 = 0.0, exit1 = 0.0;   // pass 0's flux leaving the mesh
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool pos = pass_positive(a, pass);
+    const int m = pos ? N - 1 - p : p, ai = pos ? m - NA : m;
+    const Affine *maps = a.segmap + (size_t)pass * S * NA + ai;
+    // this thread's run: sweep positions q0 .. q0+T-1 (segment q for mu > 0,
+    // S-1-q for mu < 0)
+    Affine f = {1.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    for (int q = q0; q < min(q0 + T, S); ++q) f = compose(maps[(size_t)(pos ? q : S - 1 - q) * NA], f);
+    scan_maps(f, threadIdx.x, s_map);   // inclusive, in thread order = sweep order
+    if (threadIdx.x == 0) {
+      double x0 = 0.0, x1 = 0.0;
+      if (pos) {
+        if (pass == 1 && a.bcl == kBcReflect) { x0 = exit0; x1 = exit1; }
+        else if (a.bcl == kBcIncident) { x0 = ghosts[2 * m]; x1 = ghosts[2 * m + 1]; }
+      } else {
+        if (a.bcr == kBcReflect) {
+          if (pass == 1) { x0 = exit0; x1 = exit1; }
+          else { x0 = lag_in[2 * p]; x1 = lag_in[2 * p + 1]; }   // both edges reflect
+        } else if (a.bcr == kBcIncident) {
+          const double *gr = ghosts + (size_t)(J + 1) * K;
+          x0 = gr[2 * m];
+          x1 = gr[2 * m + 1];
+        }
+      }
+      s_x[0] = x0;
+      s_x[1] = x1;
+    }
+    __syncthreads();
+    double x0 = s_x[0], x1 = s_x[1];
+    if (threadIdx.x > 0) apply(s_map[threadIdx.x - 1], x0, x1);
+    for (int q = q0; q < min(q0 + T, S); ++q) {
+      a.segin[((size_t)pass * S + (pos ? q : S - 1 - q)) * NA + ai] = make_double2(x0, x1);
+      apply(maps[(size_t)(pos ? q : S - 1 - q) * NA], x0, x1);
+    }
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) {   // the whole mesh's map, applied: the leaving flux
+      double y0 = s_x[0], y1 = s_x[1];
+      apply(s_map[blockDim.x - 1], y0, y1);
+      s_x[0] = y0;
+      s_x[1] = y1;
+    }
+    __syncthreads();
+    if (pass == 0) {
+      exit0 = s_x[0];
+      exit1 = s_x[1];
+    } else if (threadIdx.x == 0 && a.bcl == kBcReflect && a.bcr == kBcReflect) {
+      // mu > 0 was swept second: its leaving flux at x = X is the next
+      // iteration's entering flux of the mirror angle
+      lag_out[2 * p] = s_x[0];
+      lag_out[2 * p + 1] = s_x[1];
+    }
+    __syncthreads();
+  }
+}
+
+// Sum over the NA lanes of a chunk group (NA a power of two <= 64, the group
+// contiguous within a wave): a fixed butterfly, every lane gets the sum.
+__device__ __forceinline__ double group_sum(double v, int NA) {
+  for (int off = NA >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// The sweep: grid (nseg, 2), blockIdx.y = pass.  Every thread takes its
+// chunk map (formed by k_si_smaps), the flux entering its chunk follows from
+// the segment's entering flux through the chunks before it, and the chunk is
+// swept from it, writing psi_{k+1/2}, the outgoing fluxes and the
+// direction's scalar-flux contribution of every cell.
+__global__ __launch_bounds__(256) void k_si_lsweep(SiArgs a, int node, int cbase) {
+  __shared__ Affine s_map[256];
+  const StepCtl c = *a.ctl;
+  if (c.stalled || c.status != kRunning) return;
+  const int l = cbase + node;
+  const int par = (l - 1) & 1;
+  const int parity = c.step_parity;
+  const double *phi_old = par ? a.phi1 : a.phi0;
+  double *out_dst = par ? a.out0 : a.out1;
+  const double *psi_prev = parity ? a.psi1 : a.psi0;
+  double *psi_next = parity ? a.psi0 : a.psi1;
+  const int N = a.N, J = a.J, K = 2 * N, S = a.nseg;
+  const int s = blockIdx.x, pass = blockIdx.y;
+  const bool pos = pass_positive(a, pass);
+  const LaneMap lm(N);
+  const int lo = seg_edge(s, J, S), hi = seg_edge(s + 1, J, S);
+  const int m = pos ? lm.NA + lm.a : lm.a;
+  const double amu = fabs(a.mu[m]), wm = a.w[m];
+  const int o0 = pos ? 1 : 0, o1 = pos ? 3 : 2;
+  int jb = lo, je = lo;
+  if (lm.active) {
+    lane_chunk(lo, hi, lm.C, lm.c, pos, &jb, &je);
+    s_map[threadIdx.x] = a.chmap[((size_t)pass * S + s) * blockDim.x + threadIdx.x];
+  }
+  __syncthreads();
+  // the flux entering this chunk: the segment's entering flux through the
+  // chunks before it in sweep order
+  double x0 = 0.0, x1 = 0.0;
+  if (lm.active) {
+    const double2 xin = a.segin[((size_t)pass * S + s) * lm.NA + lm.a];
+    x0 = xin.x;
+    x1 = xin.y;
+    for (int q = 0; q < lm.c; ++q) apply(s_map[q * lm.NA + lm.a], x0, x1);
+  }
+  double *contrib = a.contrib + (size_t)pass * J * 4;
+  // (the lanes of a chunk group sweep the same cells in step: equal chunk
+  // lengths within the group; groups whose chunk is shorter idle at the end)
+  const int n = je - jb, dir = pos ? 1 : -1;
+  const int nmax = (hi - lo + lm.C - 1) / max(lm.C, 1) + 1;
+  LaneRegion lr;
+  LaneIn cur{};
+  if (lm.active && n > 0) {
+    const int j0 = pos ? jb : je - 1;
+    lane_region(a, a.cell_region[j0], m, lr);
+    cur = lane_in(phi_old, psi_prev, j0, m, K);
+  }
+  for (int q = 0; q < nmax; ++q) {
+    const bool live = lm.active && q < n;
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = 0;
+    if (live) {
+      j = pos ? jb + q : je - 1 - q;
+      LaneIn nxt = cur;
+      if (q + 1 < n) nxt = lane_in(phi_old, psi_prev, j + dir, m, K);
+      lane_track(a, j, m, lr);
+      const CellSolve cs = lane_solve(a, lr, cur, pos, amu);
+      cur = nxt;
+      for (int i = 0; i < 4; ++i) x[i] = cs.y[i] + cs.c0[i] * x0 + cs.c1[i] * x1;
+      *reinterpret_cast<double2 *>(psi_next + (size_t)j * K + 2 * m) = make_double2(x[2], x[3]);
+      *reinterpret_cast<double2 *>(out_dst + (size_t)(j + 1) * K + 2 * m) =
+          make_double2(x[o0], x[o1]);
+      x0 = x[o0];
+      x1 = x[o1];
+    }
+    // the cell's contribution summed over the group's angles (every lane of
+    // the group is live or idle together)
+    double sc[4];
+    for (int i = 0; i < 4; ++i) sc[i] = group_sum(wm * x[i], lm.NA);
+    if (live && lm.a == 0)
+      *reinterpret_cast<double4 *>(contrib + (size_t)j * 4) = make_double4(sc[0], sc[1], sc[2], sc[3]);
+  }
+}
+
 // phi^(l) = sum over the angle pairs' contributions (fixed order), and each
 // block's residual record.
 __global__ __launch_bounds__(256) void k_si_reduce(SiArgs a, int node, int cb) {
@@ -258,13 +572,12 @@ __global__ __launch_bounds__(256) void k_si_reduce(SiArgs a, int node, int cb) {
   const int par = (l - 1) & 1;
   const double *phi_old = par ? a.phi1 : a.phi0;
   double *phi_new = par ? a.phi0 : a.phi1;
-  const int npairs = a.N / 2;
   const int J = a.J;
   double d = 0.0, f = 0.0;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < J * 4) {
     double s = 0.0;
-    for (int p = 0; p < npairs; ++p) s += a.contrib[(size_t)p * J * 4 + idx];
+    for (int p = 0; p < a.ncontrib; ++p) s += a.contrib[(size_t)p * J * 4 + idx];
     phi_new[idx] = s;
     d = isfinite(s) ? fabs(s - phi_old[idx]) : __builtin_nan("");
     f = fabs(s);
