@@ -479,9 +479,16 @@ __global__ __launch_bounds__(256) void k_si_enter(SiArgs a, int node, int cbase)
 }
 
 // Sum over the NA lanes of a chunk group (NA a power of two <= 64, the group
-// contiguous within a wave): a fixed butterfly, every lane gets the sum.
+// contiguous and aligned within a wave): within 16-lane rows by DPP moves
+// (pairs, quads, half rows, rows), across rows by lane exchange; each step
+// adds a partner's value, so every lane of the group ends with the same sum.
 __device__ __forceinline__ double group_sum(double v, int NA) {
-  for (int off = NA >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (NA >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  if (NA >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  if (NA >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+  if (NA >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+  if (NA >= 32) v += __shfl_xor(v, 16, 64);
+  if (NA >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
