@@ -1670,8 +1670,7 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
   const hipStream_t st = c0->stream;
   for (int i = 0; i < n_ctx; ++i) OCI_CK(c0, hipStreamSynchronize(ctx[i]->stream));
   // per problem: step records for the solve, step counter 0, psi buffer
-  size_t lds_pv = 0, lds_it = 0, lds_ed = 0;
-  int cap = kMaxBatch, nt_all = 0, nt_tiles = 0;
+  int cap = kMaxBatch;
   for (int i = 0; i < n_ctx; ++i) {
     oci_ctx *c = ctx[i];
     int rc = grow_records(c, n_steps);
@@ -1680,48 +1679,105 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     c->h_ctl->psi_base = c->parity;
     OCI_CK(c, hipMemcpyAsync(&c->d_ctl->cur, &c->h_ctl->cur, 2 * sizeof(int32_t),
                              hipMemcpyHostToDevice, st));
-    lds_pv = std::max(lds_pv, c->lds_pv);
-    lds_it = std::max(lds_it, c->lds_it);
-    lds_ed = std::max(lds_ed, c->lds_ed);
     cap = std::min(cap, c->nbuf - 1);
-    nt_all += c->ntiles + 1;
-    nt_tiles += c->ntiles;
+  }
+  // the problems by angle count: one class per N present, with the kernels
+  // built for that N (and its work-group sizes) where there are, else the
+  // kernels for any N with 256 threads
+  struct Cls {
+    int N = 0;
+    void *fb = nullptr, *fi = nullptr, *fe = nullptr;
+    dim3 bb, bi, be;
+    size_t lb = 0, li = 0, le = 0;
+    int nt_all = 0, nt_tiles = 0;
+    int2 *d_qall = nullptr, *d_qtiles = nullptr;
+    std::vector<int2> qall, qtiles;
+  };
+  std::vector<Cls> cls;
+  std::vector<int> cls_of(n_ctx);
+  for (int i = 0; i < n_ctx; ++i) {
+    oci_ctx *c = ctx[i];
+    int k = 0;
+    while (k < (int)cls.size() && cls[k].N != c->N) ++k;
+    if (k == (int)cls.size()) {
+      Cls q;
+      q.N = c->N;
+      const bool spec = c->N == 8 || c->N == 16 || c->N == 32 || c->N == 64 || c->N == 128;
+#define OCI_KB_PICK(CHV, NFV)                          \
+  do {                                                 \
+    q.fb = (void *)kb_step_begin<CHV, NFV>;            \
+    q.fi = (void *)kb_oci_iterate<CHV, NFV>;           \
+    q.fe = (void *)kb_step_end<CHV, NFV>;              \
+  } while (0)
+      switch (spec ? c->N : 0) {
+        case 8: OCI_KB_PICK(4, 8); break;
+        case 16: OCI_KB_PICK(8, 16); break;
+        case 32: OCI_KB_PICK(16, 32); break;
+        case 64: OCI_KB_PICK(16, 64); break;
+        case 128: OCI_KB_PICK(16, 128); break;
+        default: OCI_KB_PICK(4, 0); break;
+      }
+#undef OCI_KB_PICK
+      q.bb = dim3(spec ? 64 * c->W_pv : 256);
+      q.bi = dim3(spec ? 64 * c->W_it : 256);
+      q.be = dim3(spec ? 64 * c->W_ed : 256);
+      q.lb = c->lds_pv;
+      q.li = c->lds_it;
+      q.le = c->lds_ed;
+      cls.push_back(q);
+    }
+    cls_of[i] = k;
+    cls[k].nt_all += ctx[i]->ntiles + 1;
+    cls[k].nt_tiles += ctx[i]->ntiles;
   }
   // device tables: argument blocks, result pointers, the work queues
   EnsembleBufs db;
   StepArgs *d_probs = nullptr;
   double **d_phis = nullptr;
-  int2 *d_qall = nullptr, *d_qtiles = nullptr;
   int *d_plist = nullptr, *d_first = nullptr, *d_last = nullptr;
   OCI_CK(c0, db.alloc(&d_first, n_ctx));
   OCI_CK(c0, db.alloc(&d_last, n_ctx));
   OCI_CK(c0, db.alloc(&d_probs, n_ctx));
   OCI_CK(c0, db.alloc(&d_phis, n_ctx));
-  OCI_CK(c0, db.alloc(&d_qall, nt_all));
-  OCI_CK(c0, db.alloc(&d_qtiles, nt_tiles));
   OCI_CK(c0, db.alloc(&d_plist, n_ctx));
+  for (Cls &q : cls) {
+    OCI_CK(c0, db.alloc(&q.d_qall, q.nt_all));
+    OCI_CK(c0, db.alloc(&q.d_qtiles, q.nt_tiles));
+    OCI_CK(c0, hipFuncSetAttribute((const void *)q.fb, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)q.lb));
+    OCI_CK(c0, hipFuncSetAttribute((const void *)q.fi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)q.li));
+    OCI_CK(c0, hipFuncSetAttribute((const void *)q.fe, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)q.le));
+  }
   std::vector<StepArgs> probs(n_ctx);
   std::vector<double *> phis(n_ctx, nullptr);
   for (int i = 0; i < n_ctx; ++i) {
     probs[i] = ctx[i]->sa;
     phis[i] = phi_out ? phi_out[i] : nullptr;
   }
-  // the queue of a set of problems: every tile (all: and each problem's
-  // reduction work-group) and the problem list; host copies kept until synced
-  std::vector<int2> qall, qtiles;
+  // the queues of a set of problems, per class: every tile (all: and each
+  // problem's reduction work-group) and the problem list; host copies kept
+  // until synced
   std::vector<int> plist, first(n_ctx, 1), last(n_ctx, 1);
   auto build = [&](const std::vector<int> &set) -> int {
-    qall.clear();
-    qtiles.clear();
+    for (Cls &q : cls) {
+      q.qall.clear();
+      q.qtiles.clear();
+    }
     plist = set;
     for (int i : set) {
-      for (int t = 0; t <= ctx[i]->ntiles; ++t) qall.push_back(make_int2(i, t));
-      for (int t = 0; t < ctx[i]->ntiles; ++t) qtiles.push_back(make_int2(i, t));
+      Cls &q = cls[cls_of[i]];
+      for (int t = 0; t <= ctx[i]->ntiles; ++t) q.qall.push_back(make_int2(i, t));
+      for (int t = 0; t < ctx[i]->ntiles; ++t) q.qtiles.push_back(make_int2(i, t));
     }
-    OCI_CK(c0, hipMemcpyAsync(d_qall, qall.data(), qall.size() * sizeof(int2),
-                              hipMemcpyHostToDevice, st));
-    OCI_CK(c0, hipMemcpyAsync(d_qtiles, qtiles.data(), qtiles.size() * sizeof(int2),
-                              hipMemcpyHostToDevice, st));
+    for (Cls &q : cls) {
+      if (q.qall.empty()) continue;
+      OCI_CK(c0, hipMemcpyAsync(q.d_qall, q.qall.data(), q.qall.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, st));
+      OCI_CK(c0, hipMemcpyAsync(q.d_qtiles, q.qtiles.data(), q.qtiles.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, st));
+    }
     OCI_CK(c0, hipMemcpyAsync(d_plist, plist.data(), plist.size() * sizeof(int),
                               hipMemcpyHostToDevice, st));
     OCI_CK(c0, hipMemcpyAsync(d_first, first.data(), n_ctx * sizeof(int),
@@ -1734,23 +1790,28 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
                             hipMemcpyHostToDevice, st));
   OCI_CK(c0, hipMemcpyAsync(d_phis, phis.data(), n_ctx * sizeof(double *),
                             hipMemcpyHostToDevice, st));
-  for (void *fn : {(void *)kb_step_begin<4>, (void *)kb_oci_iterate<4>, (void *)kb_step_end<4>}) {
-    const size_t l = fn == (void *)kb_step_begin<4> ? lds_pv
-                                                     : (fn == (void *)kb_oci_iterate<4> ? lds_it
-                                                                                        : lds_ed);
-    OCI_CK(c0, hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)l));
-  }
   std::vector<int> everyone(n_ctx);
   for (int i = 0; i < n_ctx; ++i) everyone[i] = i;
   int worst = OCI_OK;
   int half = c0->parity;
   const dim3 blk(256);
-  // launches over the current queue
+  // launches over the current queues, one per class present
+  auto begin = [&]() -> int {
+    for (Cls &q : cls) {
+      if (q.qtiles.empty()) continue;
+      void *bargs[] = {&d_probs, &q.d_qtiles};
+      OCI_CK(c0, hipLaunchKernel((const void *)q.fb, dim3((unsigned)q.qtiles.size()), q.bb, bargs,
+                                 q.lb, st));
+    }
+    return OCI_OK;
+  };
   auto iterate = [&](int node) -> int {
-    void *args[] = {&d_probs, &d_qall, &d_first, &d_last, &node, &half};
-    OCI_CK(c0, hipLaunchKernel((const void *)kb_oci_iterate<4>, dim3((unsigned)qall.size()), blk,
-                               args, lds_it, st));
+    for (Cls &q : cls) {
+      if (q.qall.empty()) continue;
+      void *args[] = {&d_probs, &q.d_qall, &d_first, &d_last, &node, &half};
+      OCI_CK(c0, hipLaunchKernel((const void *)q.fi, dim3((unsigned)q.qall.size()), q.bi, args,
+                                 q.li, st));
+    }
     return OCI_OK;
   };
   auto finish = [&]() -> int {
@@ -1760,9 +1821,12 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
                                rargs, 0, st));
     double **ph = phi_out ? d_phis : nullptr;
     int mode = 1 | (1 << 1);   // records reduced before; one trailing iterate
-    void *eargs[] = {&d_probs, &ph, &d_qtiles, &d_first, &d_last, &half, &mode};
-    OCI_CK(c0, hipLaunchKernel((const void *)kb_step_end<4>, dim3((unsigned)qtiles.size()), blk,
-                               eargs, lds_ed, st));
+    for (Cls &q : cls) {
+      if (q.qtiles.empty()) continue;
+      void *eargs[] = {&d_probs, &ph, &q.d_qtiles, &d_first, &d_last, &half, &mode};
+      OCI_CK(c0, hipLaunchKernel((const void *)q.fe, dim3((unsigned)q.qtiles.size()), q.be, eargs,
+                                 q.le, st));
+    }
     return OCI_OK;
   };
   for (int s = 0; s < n_steps; ++s) {
@@ -1780,9 +1844,8 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     if (rc) return rc;
     OCI_CK(c0, hipEventRecord(c0->ev0, st));
     if (need_begin) {
-      void *bargs[] = {&d_probs, &d_qtiles};
-      OCI_CK(c0, hipLaunchKernel((const void *)kb_step_begin<4>, dim3((unsigned)qtiles.size()),
-                                 blk, bargs, lds_pv, st));
+      rc = begin();
+      if (rc) return rc;
       for (int i = 0; i < n_ctx; ++i) ctx[i]->gh_valid = true;
     }
     for (int l = 1; l <= L && rc == OCI_OK; ++l) rc = iterate(l);

@@ -183,7 +183,8 @@ __global__ void k_oci_inner(StepArgs a, int i, int ly, int half, int opens);
 // index within the correction (selects the buffers as i does above).
 template <bool ARGT>
 __global__ void k_oci_inner2(StepArgs a, int n, int ly, int half, int opens);
-// Ensembles: the same step kernels (any N, a multiple of 8; 256 threads) over
+// Ensembles: the same step kernels (NF: built for N = NF with that N's work-group
+// size, or 0: any N, a multiple of 8, 256 threads) over
 // a work queue of (problem, tile) entries, each problem with its own argument
 // block probs[problem]; a tile entry equal to the problem's tile count is its
 // residual-reduction work-group (kb_oci_iterate).  first[problem] ..
@@ -193,13 +194,13 @@ __global__ void k_oci_inner2(StepArgs a, int n, int ly, int half, int opens);
 // problem of plist.  kb_step_end: phi_outs[problem] (or NULL) receives the
 // accepted scalar flux as phi_out does in k_step_end; single-iterate
 // launches (rstep 1).
-template <int CH> __global__ void kb_step_begin(const StepArgs *probs, const int2 *queue);
-template <int CH>
+template <int CH, int NF> __global__ void kb_step_begin(const StepArgs *probs, const int2 *queue);
+template <int CH, int NF>
 __global__ void kb_oci_iterate(const StepArgs *probs, const int2 *queue, const int *first,
                                const int *last, int node, int half);
 __global__ void kb_reduce_rec(const StepArgs *probs, const int *plist, const int *last, int n,
                               int half);
-template <int CH>
+template <int CH, int NF>
 __global__ void kb_step_end(const StepArgs *probs, double *const *phi_outs, const int2 *queue,
                             const int *first, const int *last, int half, int mode);
 // Learned corrections of iterate l of the open step (ring half `half`): the

@@ -2283,19 +2283,21 @@ __global__ __launch_bounds__(256) void k_learn_apply(StepArgs a, int l, int half
 // its residual-reduction work-group) replaces blockIdx.x; every problem keeps
 // its own argument block (probs[problem], in device memory), rings, records
 // and control block, so each problem's iterates, decisions and end of step
-// are exactly those of its own launches.  Built for any N (a multiple of 8)
-// with 256 threads per work-group.
-template <int CH>
+// are exactly those of its own launches.  Built for the common angle counts
+// (NF = 8 .. 128, the work-group size of that N's own kernels) and for any N
+// (NF = 0, a multiple of 8, 256 threads per work-group); one launch per angle
+// count present covers all its problems.
+template <int CH, int NF>
 __global__ __launch_bounds__(256) void kb_step_begin(const StepArgs *probs, const int2 *queue) {
   extern __shared__ double lds[];
   const int2 q = queue[blockIdx.x];
-  step_begin_body<CH, false, true, 0>(probs[q.x], q.y, lds);
+  step_begin_body<CH, false, true, NF>(probs[q.x], q.y, lds);
 }
 
 // (first[problem] .. last[problem]: the iterates planned for the problem in
 // this batch; launch `node` computes iterate first + node - 1, and the
 // launches past last leave the problem's work-groups idle)
-template <int CH>
+template <int CH, int NF>
 __global__ __launch_bounds__(256, 3) void kb_oci_iterate(const StepArgs *probs, const int2 *queue,
                                                          const int *first, const int *last,
                                                          int node, int half) {
@@ -2303,7 +2305,7 @@ __global__ __launch_bounds__(256, 3) void kb_oci_iterate(const StepArgs *probs, 
   const int2 q = queue[blockIdx.x];
   const int cb = first[q.x] - 1;
   if (cb + node > last[q.x]) return;
-  oci_iterate_body<CH, false, true, 0>(probs[q.x], q.y, lds, node, cb, half, 1, 1);
+  oci_iterate_body<CH, false, true, NF>(probs[q.x], q.y, lds, node, cb, half, 1, 1);
 }
 
 // (one work-group per listed problem)
@@ -2313,21 +2315,31 @@ __global__ __launch_bounds__(256) void kb_reduce_rec(const StepArgs *probs, cons
   reduce_rec_body(probs[p], last[p], n, half);
 }
 
-template <int CH>
+template <int CH, int NF>
 __global__ __launch_bounds__(256, 3) void kb_step_end(const StepArgs *probs, double *const *phi_outs,
                                                       const int2 *queue, const int *first,
                                                       const int *last, int half, int mode) {
   extern __shared__ double lds[];
   const int2 q = queue[blockIdx.x];
-  step_end_body<CH, false, true, 0, false>(probs[q.x], q.y, lds, phi_outs ? phi_outs[q.x] : nullptr,
-                                    first[q.x], last[q.x], half, 1, mode);
+  step_end_body<CH, false, true, NF, false>(probs[q.x], q.y, lds,
+                                            phi_outs ? phi_outs[q.x] : nullptr, first[q.x],
+                                            last[q.x], half, 1, mode);
 }
 
-template __global__ void kb_step_begin<4>(const StepArgs *, const int2 *);
-template __global__ void kb_oci_iterate<4>(const StepArgs *, const int2 *, const int *,
-                                           const int *, int, int);
-template __global__ void kb_step_end<4>(const StepArgs *, double *const *, const int2 *,
-                                        const int *, const int *, int, int);
+#define OCI_KB(CHV, NFV)                                                                      \
+  template __global__ void kb_step_begin<CHV, NFV>(const StepArgs *, const int2 *);           \
+  template __global__ void kb_oci_iterate<CHV, NFV>(const StepArgs *, const int2 *,           \
+                                                    const int *, const int *, int, int);      \
+  template __global__ void kb_step_end<CHV, NFV>(const StepArgs *, double *const *,           \
+                                                 const int2 *, const int *, const int *, int, \
+                                                 int);
+OCI_KB(4, 0)
+OCI_KB(4, 8)
+OCI_KB(8, 16)
+OCI_KB(16, 32)
+OCI_KB(16, 64)
+OCI_KB(16, 128)
+#undef OCI_KB
 
 template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int, int);
