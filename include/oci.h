@@ -199,8 +199,10 @@ int oci_solve_batch(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, double **phi_
                     int32_t phi_out_on_device, oci_step_info **infos, int32_t n_threads);
 
 /* An ensemble of independent problems advanced together: n_steps OCI steps of
- * every context, each step one launch per iteration over a device work queue
- * of (problem, tile) entries covering every problem's tiles (a problem keeps
+ * every context, each step one launch per iteration and angle count present,
+ * over a device work queue of (problem, tile) entries covering the tiles of
+ * every problem with that angle count (kernels built for N = 8 .. 128 where
+ * the count is one of those, else for any N; a problem keeps
  * its own operators, iterate rings, residual records and control block, so
  * its iterates, stopping decisions and results are exactly those of its own
  * single-iterate steps), then one end-of-step launch over all tiles; problems
