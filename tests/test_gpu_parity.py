@@ -392,3 +392,19 @@ def test_launch_shape_cap_agrees(lib, monkeypatch, cap):
     ref = ooci.run_oci(p, cell_data(p), steps, tol=p.tol, max_iters=p.max_iters)
     for k in range(steps):
         assert rel(phi1[k], ref[k]["phi"]) < 1e-9
+
+
+# The angle-lane SI sweep over many segments and regions (segments of ~4 cells
+# per chunk, chunks of regions' edges, the entering-flux scan across
+# segments), every boundary kind, the cross-row lane sums of N = 64 and 128
+@pytest.mark.parametrize("n,bc", [(64, (W.REFLECT, W.REFLECT)), (64, (W.INCIDENT, W.VACUUM)),
+                                  (128, (W.VACUUM, W.REFLECT)), (16, (W.REFLECT, W.INCIDENT))])
+def test_si_many_segments_match_oracle(lib, n, bc):
+    p = W.random_small(200 + n, n_cells=700, n_regions=5, n_angles=n, bc=bc)
+    cd = cell_data(p)
+    ref = osi.run_si(p, cd, 2, tol=0.0, max_iters=3)
+    got = gpu_run(lib, p, 2, method="si", tol=0.0, max_iters=3)
+    for k in range(2):
+        assert got[k]["iterations"] == 3
+        assert rel(got[k]["phi"], ref[k]["phi"]) < 1e-11, (n, k)
+        assert rel(got[k]["psi_edge"], ref[k]["psi_edge"]) < 1e-11, (n, k)
