@@ -154,7 +154,7 @@ typedef struct {
  * the FP64 iterates.
  * Launch shape: a queued FP64 step runs its iterates in launches of up to
  * four (each launch recomputes the halo cells it needs on the tile's edges);
- * the environment variable OCI_ITERATES_PER_LAUNCH = 2, 3 or 4, read here,
+ * the environment variable OCI_ITERATES_PER_LAUNCH = 1, 2, 3 or 4, read here,
  * caps that number (results agree to rounding order either way).
  * Errors: OCI_EINVAL (bad problem, out == NULL), OCI_ENOMEM, OCI_EDEVICE. */
 int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out);
@@ -242,15 +242,18 @@ int oci_get_sizes(const oci_ctx *c, int32_t *n_angles, int32_t *n_cells, int32_t
  * 1 with OCI_PREC_FP32.  Returns the count (>= 1), or OCI_EINVAL for NULL. */
 int oci_iterates_per_launch(const oci_ctx *c);
 
-/* Set the launch shape: at most k (>= 2) iterates per iteration kernel,
- * clamped to what the problem allows (oci_iterates_per_launch() of a fresh
- * context without OCI_ITERATES_PER_LAUNCH).  Results do not depend on it
+/* Set the launch shape: at most k (>= 1) iterates per iteration kernel,
+ * clamped to what the problem allows (up to 4 for N = 8, 16, 32, 64, fewer
+ * where a region is narrower than three cells, else 2; a fresh context starts
+ * at that limit,
+ * except from N = 128 on, where it starts at 1: the two-iterate kernel is
+ * slower per iterate there).  Results do not depend on it
  * (the iterates are the same; only their grouping into launches changes);
  * it is a tuning knob (see the autotuner in the Python package).  Waits for
  * the context's stream when the shape changes (cached step graphs are
  * rebuilt); not to be called while another thread drives the context.
  * Returns the shape now in effect (1 with OCI_PREC_FP32, where it has no
- * effect), or OCI_EINVAL for NULL or k < 2. */
+ * effect), or OCI_EINVAL for NULL or k < 1. */
 int oci_set_iterates_per_launch(oci_ctx *c, int32_t k);
 
 /* Whether the end of a queued step also computes the next step's first

@@ -715,10 +715,15 @@ extern "C" int oci_setup(const oci_problem *p, void *hip_stream, oci_ctx **out) 
   }
 #undef OCI_KERNELK
   c->kibuilt = c->kimax;
-  // OCI_ITERATES_PER_LAUNCH (2 .. 4) caps the iterates of one launch
+  // from N = 128 on the two-iterate kernel (two row blocks of 2N+2 doubles,
+  // 78 KiB of LDS at N = 128: two work-groups per CU) is slower per iterate
+  // than single-iterate launches (four per CU): single iterates by default
+  // (the tuner may still pick two)
+  if (N >= 128) c->kimax = 1;
+  // OCI_ITERATES_PER_LAUNCH (1 .. 4) caps the iterates of one launch
   if (const char *env = std::getenv("OCI_ITERATES_PER_LAUNCH")) {
     const int v = std::atoi(env);
-    if (v >= 2 && v <= 4) c->kimax = std::min(c->kimax, v);
+    if (v >= 1 && v <= 4) c->kimax = std::min(c->kimax, v);
   }
   // past a few thousand tiles one reduction of the last iterate's records
   // beats every work-group of the end of step reducing them all
@@ -1977,7 +1982,7 @@ extern "C" int oci_iterates_per_launch(const oci_ctx *c) {
 
 extern "C" int oci_set_iterates_per_launch(oci_ctx *c, int32_t k) {
   if (!c) return fail(nullptr, OCI_EINVAL, "context is NULL");
-  if (k < 2) return fail(c, OCI_EINVAL, "iterates per launch must be >= 2");
+  if (k < 1) return fail(c, OCI_EINVAL, "iterates per launch must be >= 1");
   if (c->mixed) return 1;
   const int v = std::min<int>(k, c->kibuilt);
   if (v != c->kimax) {

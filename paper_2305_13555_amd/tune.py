@@ -3,7 +3,7 @@
 Two knobs change the speed of a solve but not what it converges to:
 
 * FP64 contexts: the launch shape, how many OCI iterates one iteration kernel
-  computes (2 up to what the problem allows, oci_set_iterates_per_launch).
+  computes (1 up to what the problem allows, oci_set_iterates_per_launch).
   More iterates per launch save launches and re-reads of the previous iterate
   but recompute halo cells and hold more LDS per work-group.
 * Mixed-precision contexts: the FP32 inner iterations per correction
@@ -72,10 +72,7 @@ def tune(ctx, torch, n_steps=8, repeats=3, use_cache=True):
         cands = INNER_CANDIDATES
     else:
         top = ctx.set_iterates_per_launch(64)   # the most the problem allows
-        if top <= 2:
-            _cache[key] = top
-            return top, {}
-        cands = range(2, top + 1)
+        cands = range(1, top + 1)
     psi, step = ctx.state()
     times = {}
     for k in cands:

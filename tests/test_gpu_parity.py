@@ -365,7 +365,7 @@ def test_queued_solve_matches_step_by_step(lib, which):
     assert np.array_equal(psi, a[-1]["psi_edge"])
 
 
-@pytest.mark.parametrize("cap", ["2", "3"])
+@pytest.mark.parametrize("cap", ["1", "2", "3"])
 def test_launch_shape_cap_agrees(lib, monkeypatch, cap):
     """Iterates per launch (up to four: halo cells recomputed level by level)
     change only the rounding order at tile edges: capping the launch shape
