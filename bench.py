@@ -337,7 +337,8 @@ def learned_case(oci, torch, stream, n_steps=2, tol=1e-6, first=10, period=20):
     return out
 
 
-def ensemble_case(oci, torch, n_problems=512, chunk=128, n_check=8):
+def ensemble_case(oci, torch, n_problems=512, chunk=128, n_check=8,
+                  modes=("sequential", "threads", "ensemble")):
     """The batched ensemble: problems 0 .. n_problems-1 of the ensemble
     generator (500 - 100,000 cells log-uniform, S8 - S128, 16 regions, 20
     steps, tol 1e-10), in groups of `chunk` contexts (compact iterate rings;
@@ -347,7 +348,8 @@ def ensemble_case(oci, torch, n_problems=512, chunk=128, n_check=8):
     stream per context), and as one ensemble (oci_solve_ensemble: one launch
     per iteration over the work queue of all the group's tiles).  Cell-angle
     updates per second over all problems, and the ensemble's scalar flux of
-    the first two steps of n_check sampled problems against the oracle."""
+    the first two steps of n_check sampled problems against the oracle.
+    `modes` restricts the timed forms (for a profile of one of them)."""
     from paper_2305_13555_amd import workloads
     from oracle import oci as ooci
     from oracle.problem import cell_data
@@ -355,7 +357,7 @@ def ensemble_case(oci, torch, n_problems=512, chunk=128, n_check=8):
     T = probs[0].n_steps
     # sampled problems for the oracle: small enough for it (J * N <= 1e6)
     check = [i for i, p in enumerate(probs) if p.n_cells * p.n_angles <= 1e6][:n_check]
-    secs = {"sequential": 0.0, "threads": 0.0, "ensemble": 0.0}
+    secs = {k: 0.0 for k in modes}
     upd = {k: 0 for k in secs}
     worst = 0.0
     for g0 in range(0, n_problems, chunk):
@@ -365,7 +367,7 @@ def ensemble_case(oci, torch, n_problems=512, chunk=128, n_check=8):
         outs = [torch.zeros((2, probs[i].n_cells, 4), dtype=torch.float64, device="cuda")
                 if i in check else None for i in group]
         try:
-            for mode in ("sequential", "threads", "ensemble"):
+            for mode in modes:
                 for rep in range(2):   # a warm-up, then the timed run
                     for c in ctxs:
                         c.set_state(None, 0)
@@ -404,8 +406,10 @@ def ensemble_case(oci, torch, n_problems=512, chunk=128, n_check=8):
            "oracle_check": {"problems": check, "steps": 2, "max_rel_vs_oracle": worst}}
     for k in secs:
         out[k] = {"seconds": secs[k], "cell_angle_updates_per_s": upd[k] / secs[k]}
-    out["ensemble_speedup_vs_sequential"] = secs["sequential"] / secs["ensemble"]
-    out["threads_speedup_vs_sequential"] = secs["sequential"] / secs["threads"]
+    if "sequential" in secs and "ensemble" in secs:
+        out["ensemble_speedup_vs_sequential"] = secs["sequential"] / secs["ensemble"]
+    if "sequential" in secs and "threads" in secs:
+        out["threads_speedup_vs_sequential"] = secs["sequential"] / secs["threads"]
     return out
 
 
@@ -425,6 +429,8 @@ def main():
                     help="only the learned corrector on the thin-cell evaluation problem")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the 512-problem ensemble")
+    ap.add_argument("--ensemble-modes", default="sequential,threads,ensemble",
+                    help="with --ensemble-only: the forms timed, comma-separated")
     ap.add_argument("--skip-ensemble", action="store_true",
                     help="the secondary cases without the 512-problem ensemble")
     ap.add_argument("--workload", choices=["large", "bench16"], default="large",
@@ -436,6 +442,11 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU only: the OCI path here is single-GPU "
               "(multi-GPU sharding is described, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    modes = tuple(m for m in args.ensemble_modes.split(",") if m)
+    if not modes or set(modes) - {"sequential", "threads", "ensemble"}:
+        print("--ensemble-modes: a comma-separated subset of sequential,threads,ensemble",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -457,7 +468,7 @@ def main():
         print(json.dumps(learned_case(oci, torch, stream)))
         return
     if args.ensemble_only:
-        print(json.dumps(ensemble_case(oci, torch)))
+        print(json.dumps(ensemble_case(oci, torch, modes=modes)))
         return
     prob = workloads.config3()
     J, N, T = prob.n_cells, prob.n_angles, prob.n_steps

@@ -1640,8 +1640,10 @@ extern "C" int oci_solve_batch(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, do
 namespace {
 struct EnsembleBufs {
   std::vector<void *> ptrs;
+  void *host = nullptr;   // pinned staging of the per-batch tables
   ~EnsembleBufs() {
     for (void *q : ptrs) (void)hipFree(q);
+    if (host) (void)hipHostFree(host);
   }
   template <class T>
   hipError_t alloc(T **p, size_t n) {
@@ -1680,10 +1682,8 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     oci_ctx *c = ctx[i];
     int rc = grow_records(c, n_steps);
     if (rc) return rc;
-    c->h_ctl->cur = 0;
+    c->h_ctl->cur = 0;   // (the device copies: kb_set_ctl below)
     c->h_ctl->psi_base = c->parity;
-    OCI_CK(c, hipMemcpyAsync(&c->d_ctl->cur, &c->h_ctl->cur, 2 * sizeof(int32_t),
-                             hipMemcpyHostToDevice, st));
     cap = std::min(cap, c->nbuf - 1);
   }
   // the problems by angle count: one class per N present, with the kernels
@@ -1695,7 +1695,9 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     dim3 bb, bi, be;
     size_t lb = 0, li = 0, le = 0;
     int nt_all = 0, nt_tiles = 0;
-    int2 *d_qall = nullptr, *d_qtiles = nullptr;
+    int2 *d_qall = nullptr, *d_qtiles = nullptr;   // the current batch's queues
+    size_t na = 0, nt = 0;                          // and their lengths
+    int2 *d_all_full = nullptr, *d_tiles_full = nullptr;   // every problem's, uploaded once
     std::vector<int2> qall, qtiles;
   };
   std::vector<Cls> cls;
@@ -1740,14 +1742,45 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
   StepArgs *d_probs = nullptr;
   double **d_phis = nullptr;
   int *d_plist = nullptr, *d_first = nullptr, *d_last = nullptr;
-  OCI_CK(c0, db.alloc(&d_first, n_ctx));
-  OCI_CK(c0, db.alloc(&d_last, n_ctx));
   OCI_CK(c0, db.alloc(&d_probs, n_ctx));
   OCI_CK(c0, db.alloc(&d_phis, n_ctx));
-  OCI_CK(c0, db.alloc(&d_plist, n_ctx));
+  // a batch's tables (problem list, first, last, every class's queues) go to
+  // the device in one transfer from one pinned staging buffer, each table at
+  // an even offset (int2 queues); the host rewrites it only after the stream
+  // has drained the batch before
+  size_t pack_cap = 3 * ((size_t)n_ctx + 1);
+  for (const Cls &q : cls) pack_cap += 2 * ((size_t)q.nt_all + q.nt_tiles);
+  int *d_pack = nullptr;
+  OCI_CK(c0, db.alloc(&d_pack, pack_cap));
+  OCI_CK(c0, hipHostMalloc(&db.host, pack_cap * sizeof(int), hipHostMallocDefault));
+  int *const h_pack = static_cast<int *>(db.host);
+  // the queues of every problem (the batches planned at each step's start):
+  // built and uploaded once
+  {
+    for (int i = 0; i < n_ctx; ++i) {
+      Cls &q = cls[cls_of[i]];
+      for (int t = 0; t <= ctx[i]->ntiles; ++t) q.qall.push_back(make_int2(i, t));
+      for (int t = 0; t < ctx[i]->ntiles; ++t) q.qtiles.push_back(make_int2(i, t));
+    }
+    std::vector<int2> full;
+    for (const Cls &q : cls) {
+      full.insert(full.end(), q.qall.begin(), q.qall.end());
+      full.insert(full.end(), q.qtiles.begin(), q.qtiles.end());
+    }
+    int2 *d_full = nullptr;
+    OCI_CK(c0, db.alloc(&d_full, full.size()));
+    size_t o = 0;
+    for (Cls &q : cls) {
+      q.d_all_full = d_full + o;
+      o += q.qall.size();
+      q.d_tiles_full = d_full + o;
+      o += q.qtiles.size();
+    }
+    OCI_CK(c0, hipMemcpyAsync(d_full, full.data(), full.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, st));
+    OCI_CK(c0, hipStreamSynchronize(st));   // (full is freed at the end of this block)
+  }
   for (Cls &q : cls) {
-    OCI_CK(c0, db.alloc(&q.d_qall, q.nt_all));
-    OCI_CK(c0, db.alloc(&q.d_qtiles, q.nt_tiles));
     OCI_CK(c0, hipFuncSetAttribute((const void *)q.fb, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)q.lb));
     OCI_CK(c0, hipFuncSetAttribute((const void *)q.fi, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1761,34 +1794,55 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     probs[i] = ctx[i]->sa;
     phis[i] = phi_out ? phi_out[i] : nullptr;
   }
-  // the queues of a set of problems, per class: every tile (all: and each
-  // problem's reduction work-group) and the problem list; host copies kept
-  // until synced
+  // the tables of a batch over a set of problems: the problem list, first,
+  // last and, per class, the queues (every tile, and as "all" also each
+  // problem's reduction work-group) -- for every problem the ones uploaded
+  // above, for a subset its own
   std::vector<int> plist, first(n_ctx, 1), last(n_ctx, 1);
   auto build = [&](const std::vector<int> &set) -> int {
-    for (Cls &q : cls) {
-      q.qall.clear();
-      q.qtiles.clear();
+    const bool all = (int)set.size() == n_ctx;   // (sets are distinct indices)
+    if (!all) {
+      for (Cls &q : cls) {
+        q.qall.clear();
+        q.qtiles.clear();
+      }
+      for (int i : set) {
+        Cls &q = cls[cls_of[i]];
+        for (int t = 0; t <= ctx[i]->ntiles; ++t) q.qall.push_back(make_int2(i, t));
+        for (int t = 0; t < ctx[i]->ntiles; ++t) q.qtiles.push_back(make_int2(i, t));
+      }
     }
     plist = set;
-    for (int i : set) {
-      Cls &q = cls[cls_of[i]];
-      for (int t = 0; t <= ctx[i]->ntiles; ++t) q.qall.push_back(make_int2(i, t));
-      for (int t = 0; t < ctx[i]->ntiles; ++t) q.qtiles.push_back(make_int2(i, t));
-    }
+    size_t off = 0;
+    bool over = false;
+    auto put = [&](const void *src, size_t n) {   // n ints at the next even offset
+      if (off + n > pack_cap) {
+        over = true;
+        return d_pack;
+      }
+      std::memcpy(h_pack + off, src, n * sizeof(int));
+      const size_t at = off;
+      off += (n + 1) & ~(size_t)1;
+      return d_pack + at;
+    };
+    d_plist = put(plist.data(), plist.size());
+    d_first = put(first.data(), n_ctx);
+    d_last = put(last.data(), n_ctx);
     for (Cls &q : cls) {
-      if (q.qall.empty()) continue;
-      OCI_CK(c0, hipMemcpyAsync(q.d_qall, q.qall.data(), q.qall.size() * sizeof(int2),
-                                hipMemcpyHostToDevice, st));
-      OCI_CK(c0, hipMemcpyAsync(q.d_qtiles, q.qtiles.data(), q.qtiles.size() * sizeof(int2),
-                                hipMemcpyHostToDevice, st));
+      if (all) {
+        q.na = (size_t)q.nt_all;
+        q.nt = (size_t)q.nt_tiles;
+        q.d_qall = q.d_all_full;
+        q.d_qtiles = q.d_tiles_full;
+      } else {
+        q.na = q.qall.size();
+        q.nt = q.qtiles.size();
+        q.d_qall = reinterpret_cast<int2 *>(put(q.qall.data(), 2 * q.qall.size()));
+        q.d_qtiles = reinterpret_cast<int2 *>(put(q.qtiles.data(), 2 * q.qtiles.size()));
+      }
     }
-    OCI_CK(c0, hipMemcpyAsync(d_plist, plist.data(), plist.size() * sizeof(int),
-                              hipMemcpyHostToDevice, st));
-    OCI_CK(c0, hipMemcpyAsync(d_first, first.data(), n_ctx * sizeof(int),
-                              hipMemcpyHostToDevice, st));
-    OCI_CK(c0, hipMemcpyAsync(d_last, last.data(), n_ctx * sizeof(int), hipMemcpyHostToDevice,
-                              st));
+    if (over) return fail(c0, OCI_EDEVICE, "ensemble tables exceed their buffer");
+    OCI_CK(c0, hipMemcpyAsync(d_pack, h_pack, off * sizeof(int), hipMemcpyHostToDevice, st));
     return OCI_OK;
   };
   OCI_CK(c0, hipMemcpyAsync(d_probs, probs.data(), n_ctx * sizeof(StepArgs),
@@ -1797,24 +1851,31 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
                             hipMemcpyHostToDevice, st));
   std::vector<int> everyone(n_ctx);
   for (int i = 0; i < n_ctx; ++i) everyone[i] = i;
+  // control-block writes for the problems of the current tables (d_plist)
+  auto set_ctl = [&](int n, int psi_base) -> int {
+    void *cargs[] = {&d_probs, &d_plist, &n, &psi_base};
+    OCI_CK(c0, hipLaunchKernel((const void *)kb_set_ctl, dim3((unsigned)((n + 255) / 256)),
+                               dim3(256), cargs, 0, st));
+    return OCI_OK;
+  };
   int worst = OCI_OK;
   int half = c0->parity;
   const dim3 blk(256);
   // launches over the current queues, one per class present
   auto begin = [&]() -> int {
     for (Cls &q : cls) {
-      if (q.qtiles.empty()) continue;
+      if (q.nt == 0) continue;
       void *bargs[] = {&d_probs, &q.d_qtiles};
-      OCI_CK(c0, hipLaunchKernel((const void *)q.fb, dim3((unsigned)q.qtiles.size()), q.bb, bargs,
+      OCI_CK(c0, hipLaunchKernel((const void *)q.fb, dim3((unsigned)q.nt), q.bb, bargs,
                                  q.lb, st));
     }
     return OCI_OK;
   };
   auto iterate = [&](int node) -> int {
     for (Cls &q : cls) {
-      if (q.qall.empty()) continue;
+      if (q.na == 0) continue;
       void *args[] = {&d_probs, &q.d_qall, &d_first, &d_last, &node, &half};
-      OCI_CK(c0, hipLaunchKernel((const void *)q.fi, dim3((unsigned)q.qall.size()), q.bi, args,
+      OCI_CK(c0, hipLaunchKernel((const void *)q.fi, dim3((unsigned)q.na), q.bi, args,
                                  q.li, st));
     }
     return OCI_OK;
@@ -1827,9 +1888,9 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     double **ph = phi_out ? d_phis : nullptr;
     int mode = 1 | (1 << 1);   // records reduced before; one trailing iterate
     for (Cls &q : cls) {
-      if (q.qtiles.empty()) continue;
+      if (q.nt == 0) continue;
       void *eargs[] = {&d_probs, &ph, &q.d_qtiles, &d_first, &d_last, &half, &mode};
-      OCI_CK(c0, hipLaunchKernel((const void *)q.fe, dim3((unsigned)q.qtiles.size()), q.be, eargs,
+      OCI_CK(c0, hipLaunchKernel((const void *)q.fe, dim3((unsigned)q.nt), q.be, eargs,
                                  q.le, st));
     }
     return OCI_OK;
@@ -1846,6 +1907,7 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
       L = std::max(L, last[i]);
     }
     int rc = build(everyone);
+    if (rc == OCI_OK && s == 0) rc = set_ctl(n_ctx, c0->parity);   // the solve opens
     if (rc) return rc;
     OCI_CK(c0, hipEventRecord(c0->ev0, st));
     if (need_begin) {
@@ -1871,16 +1933,15 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     while (!open.empty()) {
       ++extra;
       int count = 1;
-      for (int i : open) {   // (on the ensemble's stream, before its launches)
-        ctx[i]->h_ctl->stalled = 0;
-        OCI_CK(c0, hipMemcpyAsync(&ctx[i]->d_ctl->stalled, &ctx[i]->h_ctl->stalled,
-                                  sizeof(int32_t), hipMemcpyHostToDevice, st));
+      for (int i : open) {
+        ctx[i]->h_ctl->stalled = 0;   // (the device copies: kb_set_ctl after the tables)
         const int n = ocip::resumed_batch(extra, last[i], ctx[i]->max_iters, ctx[i]->nbuf);
         first[i] = last[i] + 1;
         last[i] += n;
         count = std::max(count, n);
       }
       rc = build(open);
+      if (rc == OCI_OK) rc = set_ctl((int)open.size(), -1);
       for (int l = 1; l <= count && rc == OCI_OK; ++l) rc = iterate(l);
       if (rc == OCI_OK) rc = finish();
       if (rc) return rc;

@@ -203,6 +203,10 @@ __global__ void kb_reduce_rec(const StepArgs *probs, const int *plist, const int
 template <int CH, int NF>
 __global__ void kb_step_end(const StepArgs *probs, double *const *phi_outs, const int2 *queue,
                             const int *first, const int *last, int half, int mode);
+// The control blocks of the problems plist[0 .. n-1], one thread each:
+// psi_base >= 0 opens a solve (next step 0, psi_{k-1/2} of step 0 in buffer
+// psi_base), psi_base < 0 clears the stall flag before a resumed batch.
+__global__ void kb_set_ctl(const StepArgs *probs, const int *plist, int n, int psi_base);
 // Learned corrections of iterate l of the open step (ring half `half`): the
 // corrector's FP32 input (ch = 8 or 12 channels; amp: the extrapolation
 // factor of channels 8..11) from the scalar fluxes of iterates l-2 .. l, and

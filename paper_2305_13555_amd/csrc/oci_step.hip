@@ -764,10 +764,10 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
 // step of a queue).  Does nothing while a queued solve is stalled.
 template <int CH, bool ARGT, bool VEC, int NF>
 __device__ __forceinline__ void step_begin_body(const StepArgs &a, int wg, double *lds) {
+  const TileDev t = blk_desc<ARGT>(a, wg);   // (read with the control block)
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
   const int parity = c.psi_base ^ (c.cur & 1);
-  const TileDev t = blk_desc<ARGT>(a, wg);
   tile_begin<CH, VEC, NF>(a, t, parity ? a.psi1 : a.psi0, lds);
 }
 
@@ -1490,6 +1490,9 @@ __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double 
                                               int rstep, int mode) {
   const bool pre = mode & 1, fuse = FUSE && ((mode >> 4) & 1);
   const int ntrail = (mode >> 1) & 7;   // iterates last-ntrail+1 .. last
+  // (the tile's descriptor is read with the control block below, not after
+  // it: the end loads wait for both)
+  const TileDev t = blk_desc<ARGT>(a, wg);
   const double2 *recs = reinterpret_cast<const double2 *>(a.partial);
   RecRegs r1;
   if (!pre) rec_issue(r1, recs + rec_slot(a, last, half), a.ntiles);
@@ -1503,7 +1506,6 @@ __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double 
   const double dv1 = i1 < nd ? a.dec[(l0 + i1) % a.nbuf] : 0.0;
   const StepCtl c = *a.ctl;
   if (c.stalled) return;
-  const TileDev t = blk_desc<ARGT>(a, wg);
   if (i0 < nd) sdec[i0] = dv0;
   if (i1 < nd) sdec[i1] = dv1;
   __syncthreads();
@@ -2324,6 +2326,19 @@ __global__ __launch_bounds__(256, 3) void kb_step_end(const StepArgs *probs, dou
   step_end_body<CH, false, true, NF, false>(probs[q.x], q.y, lds,
                                             phi_outs ? phi_outs[q.x] : nullptr, first[q.x],
                                             last[q.x], half, 1, mode);
+}
+
+__global__ __launch_bounds__(256) void kb_set_ctl(const StepArgs *probs, const int *plist, int n,
+                                                  int psi_base) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  StepCtl *c = probs[plist[i]].ctl;
+  if (psi_base >= 0) {
+    c->cur = 0;
+    c->psi_base = psi_base;
+  } else {
+    c->stalled = 0;
+  }
 }
 
 #define OCI_KB(CHV, NFV)                                                                      \
