@@ -505,7 +505,9 @@ def main():
     # rest in launches of up to the launch shape; unfused, all of them
     k_main = max(1, min(ctx.iterates_per_launch,
                         max(i["iterations"] for i in all_infos[-1]) - (1 if fused else 0)))
-    per_launch_s, k_launch = roofline_launch_seconds(oci, prob, stream, steps=5, k=k_main)
+    roof_steps = 15
+    per_launch_s, k_launch = roofline_launch_seconds(oci, prob, stream, steps=roof_steps,
+                                                     k=k_main)
     kernel = ITERATION_KERNELS[k_launch]
     bytes_launch = algorithmic_bytes_per_cell_iteration(N) * J * k_launch
     achieved = bytes_launch / per_launch_s / 1e9
@@ -566,8 +568,9 @@ def main():
             "us_per_launch": per_launch_s * 1e6,
             "iterations_per_launch": k_launch,
             "measured": "(median step time at 2 full launches - at 1) (at 4 - at 2 for "
-                        "fewer than 3 iterates per launch), 5 steps each, HIP events on the "
-                        "library's stream (launch to launch, dispatch gap included)",
+                        "fewer than 3 iterates per launch), %d steps each, HIP events on the "
+                        "library's stream (launch to launch, dispatch gap included)"
+                        % roof_steps,
         },
         "cpu_baseline": cpu,
         "time_to_1e-6_ms_per_step": {

@@ -47,13 +47,27 @@ struct RowBlock {
   int cap;             // LDS rows owned by the block (rows .. cap-1 hold copies)
 };
 
-// Staged copy: the first batch of every thread's elements is held in
-// registers between issue_copy (loads) and finish_copy (LDS stores and any
-// further batches), so the loads can be issued early.
-constexpr int kCopyBatch = 4;
-struct CopyRegs {
-  double2 v[kCopyBatch];
+// Staged copy: the first batch of every thread's elements (NB pairs of
+// doubles) is held in registers between issue_copy (loads) and finish_copy
+// (LDS stores and any further batches), so the loads can be issued early.
+// A kernel built for one angle count sizes NB to stage its whole block in
+// that one batch (copy_batch): each further batch is one more memory round
+// trip before the tile's work can start.
+constexpr int kCopyBatch = 4, kCopyMax = 9;
+template <int NB>
+struct CopyRegsN {
+  double2 v[NB];
 };
+using CopyRegs = CopyRegsN<kCopyBatch>;
+
+// Pairs per thread that stage `rows` rows of 2 NF doubles with the
+// work-group of NF's step kernels (64 min(ceil(2 NF / 16), 4) threads) in
+// one batch, within kCopyBatch .. kCopyMax; kCopyBatch for any N (NF = 0).
+constexpr int copy_batch(int NF, int rows) {
+  const int w = (2 * NF + 15) / 16 < 4 ? (2 * NF + 15) / 16 : 4;
+  const int need = NF ? (rows * NF + 64 * w - 1) / (64 * w) : kCopyBatch;
+  return need < kCopyBatch ? kCopyBatch : (need > kCopyMax ? kCopyMax : need);
+}
 
 __device__ __forceinline__ int copy_total(const RowBlock *blk, int nblk, int h, int *off1) {
   const int n0 = blk[0].cap * h;
@@ -83,28 +97,30 @@ __device__ __forceinline__ void copy_store(const RowBlock *blk, int nblk, int h,
   *reinterpret_cast<double2 *>(blk[b].dst + r * P + 2 * c2) = v;
 }
 
-__device__ inline void issue_copy(CopyRegs &cr, const RowBlock *blk, int nblk, int K) {
+template <int NB>
+__device__ inline void issue_copy(CopyRegsN<NB> &cr, const RowBlock *blk, int nblk, int K) {
   const int h = K / 2;
   int off1;
   const int total = copy_total(blk, nblk, h, &off1);
 #pragma unroll
-  for (int q = 0; q < kCopyBatch; ++q) {
+  for (int q = 0; q < NB; ++q) {
     const int i = threadIdx.x + q * blockDim.x;
     cr.v[q] = copy_load(blk, nblk, h, off1, min(i, total - 1));   // stored only if i < total
   }
 }
 
-__device__ inline void finish_copy(const CopyRegs &cr, const RowBlock *blk, int nblk, int K,
+template <int NB>
+__device__ inline void finish_copy(const CopyRegsN<NB> &cr, const RowBlock *blk, int nblk, int K,
                                    int P) {
   const int h = K / 2;
   int off1;
   const int total = copy_total(blk, nblk, h, &off1);
 #pragma unroll
-  for (int q = 0; q < kCopyBatch; ++q) {
+  for (int q = 0; q < NB; ++q) {
     const int i = threadIdx.x + q * blockDim.x;
     if (i < total) copy_store(blk, nblk, h, off1, P, i, cr.v[q]);
   }
-  for (int base = threadIdx.x + kCopyBatch * blockDim.x; base < total;
+  for (int base = threadIdx.x + NB * blockDim.x; base < total;
        base += kCopyBatch * blockDim.x) {
     double2 v[kCopyBatch];
 #pragma unroll
@@ -464,13 +480,13 @@ __device__ inline void tile_begin(const StepArgs &a, const TileDev &t, const dou
 // wave 0 forms the 64 (cell, component) scalar fluxes and the tile's
 // residual record; then every thread forms its outgoing pairs.
 
-template <int CH>
+template <int CH, int NF, int NB = copy_batch(NF, kTileCells + 2)>
 struct IterPrefetch {
   double fp[kPhiPre];
   double cf[12];          // out coefficients of this thread's angle
   double gq[kGPre][2];    // g' of its first cells
   double hv, po;          // scalar-flux constant and previous value of this lane's (cell, component)
-  CopyRegs cr;
+  CopyRegsN<NB> cr;       // the neighbour rows
 };
 
 // Problem shape seen by the iteration kernel: compile-time constants when the
@@ -489,8 +505,8 @@ struct IterShape {
 
 // go: the step constants already in registers (the end of step that formed
 // them, same work-group and thread mapping), else loaded.
-template <int CH, int NF>
-__device__ __forceinline__ void iterate_prefetch(IterPrefetch<CH> &pf, const StepArgs &a, const TileDev &t,
+template <int CH, int NF, int NB>
+__device__ __forceinline__ void iterate_prefetch(IterPrefetch<CH, NF, NB> &pf, const StepArgs &a, const TileDev &t,
                                         const double *src, const double *phi_old, double *lds,
                                         const GhOut &go, bool have_go) {
   const IterShape<NF> sh(a);
@@ -531,8 +547,8 @@ __device__ __forceinline__ void iterate_prefetch(IterPrefetch<CH> &pf, const Ste
 }
 
 // The outgoing pairs of iterate_compute for this thread's angle and cells.
-template <int NF, int CH>
-__device__ __forceinline__ void iterate_pairs(const IterPrefetch<CH> &pf, const StepArgs &a,
+template <int NF, int CH, int NB>
+__device__ __forceinline__ void iterate_pairs(const IterPrefetch<CH, NF, NB> &pf, const StepArgs &a,
                                      const TileDev &t, double *dst, const double *lds,
                                      const double *phif, const PairMap &pm, int wm) {
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
@@ -571,8 +587,8 @@ __device__ __forceinline__ void iterate_pairs(const IterPrefetch<CH> &pf, const 
 // Returns early (no stores) when `skip` is set (a stalled queue).  wm: bit 0
 // stores the outgoing fluxes (always the scalar flux), bit 1 also the FP32
 // defect against the iterate this one started from (mixed precision).
-template <int CH, bool VEC, int NF>
-__device__ __forceinline__ void iterate_compute(const IterPrefetch<CH> &pf, const StepArgs &a,
+template <int CH, bool VEC, int NF, int NB>
+__device__ __forceinline__ void iterate_compute(const IterPrefetch<CH, NF, NB> &pf, const StepArgs &a,
                                        const TileDev &t, const double *src, double *dst,
                                        double *phi_new, double *lds, double *phis, double *phif,
                                        double2 *rec, bool skip, int wm) {
@@ -665,7 +681,7 @@ struct EndPre {
 template <int NF>
 struct EndLoads {
   double pq[EndPre<NF>::n][2], pv;
-  CopyRegs cr;
+  CopyRegs cr;   // (one batch of kCopyBatch: the end of step has no registers to spare)
 };
 
 template <int NF>
@@ -712,7 +728,7 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
   const double pv = el.pv;
   const double(&pq)[NQ][2] = el.pq;
   const RowBlock blk[1] = {neighbour_block(lds, src, t, K)};
-  const CopyRegs &cr = el.cr;
+  const auto &cr = el.cr;
   if (pi < t.nc * 4) {
     a.phi_res[(size_t)t.c0 * 4 + pi] = pv;
     if (phi_out) phi_out[(size_t)t.c0 * 4 + pi] = pv;
@@ -844,7 +860,7 @@ __device__ __forceinline__ void oci_iterate_body(const StepArgs &a, int wg, doub
   double *phi_new = phi_at(a, ring_buf(a, l, half));
   const int ti = wg;   // the tile's residual record
   const TileDev t = blk_desc<ARGT>(a, wg);
-  IterPrefetch<CH> pf;
+  IterPrefetch<CH, NF> pf;
   const GhOut none{};
   iterate_prefetch<CH, NF>(pf, a, t, src, phi_old, lds, none, false);
   const int stalled = a.ctl->stalled;
@@ -1311,7 +1327,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   const int r_lo = g_lo - 1 - cbase;
   const RowBlock blk[1] = {RowBlock{src + (size_t)g_lo * K, X + r_lo * P, g_hi - g_lo + 1,
                                     RB - r_lo}};
-  CopyRegs cr;
+  CopyRegsN<copy_batch(NF, RB)> cr;
   issue_copy(cr, blk, 1, K);
   // the halo staging loads (HF, HC, HG in that order), two doubles at a time:
   // every segment (a region's 4 rows of G, its 12 coefficient rows, a halo
@@ -1661,7 +1677,7 @@ __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double 
     __shared__ double phis[4 * 64], phif[64];
     __syncthreads();
     const int bl = ring_buf(a, L, half), bn = ring_buf(a, 1, half ^ 1);
-    IterPrefetch<CH> pf;
+    IterPrefetch<CH, NF, kCopyBatch> pf;   // (the end of step has no registers to spare)
     iterate_prefetch<CH, NF>(pf, a, t, out_at(a, bl), phi_at(a, bl), lds, go, true);
     // (mixed precision: iterate 1 is an FP64 iterate with its defect)
     iterate_compute<CH, VEC, NF>(pf, a, t, out_at(a, bl), out_at(a, bn), phi_at(a, bn), lds,
