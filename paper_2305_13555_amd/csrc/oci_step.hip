@@ -314,6 +314,7 @@ __device__ __forceinline__ size_t rec_slot(const StepArgs &a, int l, int half) {
 //   [23 + 9u] (dx/(2 v dt)) A^{-1}[r][1]   [24 + 9u] |mu| A^{-1}[r][in_0]
 //   [25 + 9u] |mu| A^{-1}[r][in_1]   [26 + 9u] (dx Q / 4) sum_c A^{-1}[r][c]
 
+constexpr int kStepWaves = 4;   // most waves of a step kernel's work-group (256 threads)
 constexpr int kPhiPre = 4;   // scalar-flux operator fragments prefetched per wave
 constexpr int kGPre = 2;     // cells whose step constants a thread prefetches
 
@@ -386,7 +387,7 @@ template <int CH, bool VEC, int NF>
 __device__ __forceinline__ void gh_compute(const StepArgs &a, const TileDev &t, const double *rows,
                                   const double (&f0)[CH], const double (&cg)[6], GhOut &go,
                                   bool want_go) {
-  __shared__ double hp[kMaxWaves * 64];
+  __shared__ double hp[kStepWaves * 64];
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2, KS = K / 4;
   const int Mt = NF ? (2 * NF + 4 + 15) / 16 : a.Mt;
   const int W = (int)(blockDim.x >> 6);
@@ -441,6 +442,17 @@ __device__ __forceinline__ void gh_compute(const StepArgs &a, const TileDev &t, 
     if (cl < t.nc) a.gh[(size_t)(t.c0 + cl) * ghp + K + comp] = v;
     if (want_go) go.hv = v;
   }
+}
+
+// Fragments of P's scalar-flux row tile per batch in the end of step: a
+// wave's whole share (KS / W k-steps) when the angle count is fixed and the
+// share is below CH, so that no registers hold other waves' k-steps.
+template <int NF, int CH>
+constexpr int gh_batch() {
+  if (!NF) return CH;
+  const int w = (2 * NF + 15) / 16 < 4 ? (2 * NF + 15) / 16 : 4;
+  const int share = (NF / 2) / w;
+  return share >= CH ? CH : (share >= 4 ? share : 4);
 }
 
 // The first fragments of this wave's share of P's scalar-flux row tile.
@@ -673,10 +685,12 @@ __device__ __forceinline__ void iterate_compute(const IterPrefetch<CH, NF, NB> &
 // blockDim), this thread's angle's psi_{k-1/2} values, and the neighbour
 // rows of the iterate the accepted one was computed from (src; into LDS
 // later).
-// (psi_{k-1/2} of all of a thread's cells at N = 64: four cells per thread)
+// (psi_{k-1/2} of a thread's first kGPre cells; at N = 64, four cells per
+// thread, the other two (n2) once the staged rows have left their registers,
+// so that the end of step fits 128 registers: four work-groups per CU)
 template <int NF>
 struct EndPre {
-  static constexpr int n = NF == 64 ? 4 : kGPre;
+  static constexpr int n = kGPre, n2 = NF == 64 ? 2 : 0;
 };
 template <int NF>
 struct EndLoads {
@@ -711,18 +725,17 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
                                 const double *psi_prev, double *psi_next, const double *phi_acc,
                                 double *phi_out, double *lds, GhOut &go, bool want_go,
                                 EndLoads<NF> &el, bool loaded) {
-  constexpr int NQ = EndPre<NF>::n;
+  constexpr int NQ = EndPre<NF>::n, CHG = gh_batch<NF, CH>();
   __shared__ double sphi[4 * kTileCells];
-  double fg[CH];   // P fragments for the next step's gh, issued early
-  gh_frags<CH, NF>(a, t, fg);
+  double fg[CHG];   // P fragments for the next step's gh, issued early
+  gh_frags<CHG, NF>(a, t, fg);
   const int N = NF ? NF : a.N, K = 2 * N, P = K + 2;
   double *ldn = lds + (kTileCells + 2) * P;   // psi_{k+1/2} of the tile's cells
   const PairMap pm(N);
   const int m = pm.m;
   const bool pos = 2 * m >= N;   // mu > 0: enters from the left neighbour (LDS row c)
-  double e[18], cg[6];   // this thread's angle's coefficients of psi_{k+1/2} and of g'
+  double e[18];   // this thread's angle's coefficients of psi_{k+1/2}
   coef_load<18>(a, N, t.region, m, 18, e);
-  coef_load<6>(a, N, t.region, m, 12, cg);
   if (!loaded) end_loads<NF>(a, t, src, psi_prev, phi_acc, lds, el);
   const int pi = threadIdx.x;
   const double pv = el.pv;
@@ -735,6 +748,16 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
     sphi[pi] = pv;
   }
   finish_copy(cr, blk, 1, K, P);
+  constexpr int NQ2 = EndPre<NF>::n2 > 0 ? EndPre<NF>::n2 : 1;
+  double pq2[NQ2][2];   // (cells NQ .. NQ+n2-1 of the thread)
+#pragma unroll
+  for (int q = 0; q < EndPre<NF>::n2; ++q) {
+    const int cl = min(pm.cl0 + (NQ + q) * pm.cstep, t.nc - 1);   // (used only for cells < nc)
+    const double2 p2 =
+        *reinterpret_cast<const double2 *>(psi_prev + (size_t)(t.c0 + cl) * K + 2 * m);
+    pq2[q][0] = p2.x;
+    pq2[q][1] = p2.y;
+  }
   __syncthreads();
   reflect_ghosts(lds, P, t, N, a.J, a.bcl, a.bcr);
   if (pm.active) {
@@ -754,6 +777,15 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
             pl = pq[q][0];
             pr = pq[q][1];
           }
+      } else if (j < NQ + EndPre<NF>::n2) {
+        pl = pq2[0][0];
+        pr = pq2[0][1];
+#pragma unroll
+        for (int q = 1; q < EndPre<NF>::n2; ++q)
+          if (NQ + q == j) {
+            pl = pq2[q][0];
+            pr = pq2[q][1];
+          }
       } else {
         pl = pp[0];
         pr = pp[1];
@@ -770,9 +802,12 @@ __device__ __forceinline__ void tile_end(const StepArgs &a, const TileDev &t, co
     }
   }
   // the next step's gh from psi_{k+1/2}, so that a queued step that
-  // follows needs no step start
+  // follows needs no step start (the g' coefficients loaded only now, when
+  // the registers of the psi phase are free)
+  double cg[6];
+  coef_load<6>(a, N, t.region, m, 12, cg);
   __syncthreads();
-  gh_compute<CH, VEC, NF>(a, t, ldn, fg, cg, go, want_go);
+  gh_compute<CHG, VEC, NF>(a, t, ldn, fg, cg, go, want_go);
 }
 
 // Start of step `cur` of the current solve: gh for every tile from
@@ -1500,6 +1535,12 @@ __global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, in
 // decided step advances the solve's step counter.
 // FUSE: built with the next step's first iterate (mode bit 16 selects it at
 // run time); without it the kernel needs fewer registers.
+// Work-groups per CU the end of step is built for: four at N = 64, where
+// that fits its LDS (42 KiB per work-group, 40 KiB is the limit for four)
+// and 128 registers; three otherwise.
+template <int NF>
+constexpr int kEndBlocks = NF == 64 ? 4 : 3;
+
 template <int CH, bool ARGT, bool VEC, int NF, bool FUSE>
 __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double *lds,
                                               double *phi_out, int first, int last, int half,
@@ -1569,7 +1610,7 @@ __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double 
       end_loads<NF>(a, t, out_at(a, ring_buf(a, last - 1, half)), psi_prev,
                     phi_at(a, ring_buf(a, last, half)), lds, sel);
     // within each 16-lane row (DPP), then over the rows of all waves in LDS
-    __shared__ double tscr[4 * kMaxWaves][2 * kMaxTrail];
+    __shared__ double tscr[4 * kStepWaves][2 * kMaxTrail];
 #pragma unroll
     for (int j = 0; j < kMaxTrail; ++j) {
       d[j] = row_reduce16(d[j], [](double x, double y) { return nan_max(x, y); });
@@ -1690,7 +1731,7 @@ __device__ __forceinline__ void step_end_body(const StepArgs &a, int wg, double 
 }
 
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out, int first,
+__global__ __launch_bounds__(256, kEndBlocks<NF>) void k_step_end(StepArgs a, double *phi_out, int first,
                                                   int last, int half, int rstep, int mode) {
   extern __shared__ double lds[];
   step_end_body<CH, ARGT, VEC, NF, true>(a, blockIdx.x, lds, phi_out, first, last, half, rstep,
@@ -1699,7 +1740,7 @@ __global__ __launch_bounds__(256, 3) void k_step_end(StepArgs a, double *phi_out
 
 // The end of step without the fused iterate (mode bit 16 ignored).
 template <int CH, bool ARGT, bool VEC, int NF>
-__global__ __launch_bounds__(256, 3) void k_step_end_nf(StepArgs a, double *phi_out, int first,
+__global__ __launch_bounds__(256, kEndBlocks<NF>) void k_step_end_nf(StepArgs a, double *phi_out, int first,
                                                      int last, int half, int rstep, int mode) {
   extern __shared__ double lds[];
   step_end_body<CH, ARGT, VEC, NF, false>(a, blockIdx.x, lds, phi_out, first, last, half, rstep,
