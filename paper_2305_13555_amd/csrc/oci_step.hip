@@ -1535,9 +1535,9 @@ __global__ __launch_bounds__(256) void k_reduce_rec(StepArgs a, int l, int n, in
 // decided step advances the solve's step counter.
 // FUSE: built with the next step's first iterate (mode bit 16 selects it at
 // run time); without it the kernel needs fewer registers.
-// Work-groups per CU the end of step is built for: four at N = 64, where
-// that fits its LDS (42 KiB per work-group, 40 KiB is the limit for four)
-// and 128 registers; three otherwise.
+// Work-groups per CU the end of step is built for (the register limit that
+// follows: 128 for four, 168 for three): four at N = 64, whose 38.6 KiB of
+// LDS per work-group also let four share a CU's 160 KiB; three otherwise.
 template <int NF>
 constexpr int kEndBlocks = NF == 64 ? 4 : 3;
 
