@@ -213,7 +213,10 @@ int oci_solve_batch(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, double **phi_
  * multiple of 8, all at the same step parity (e.g. all fresh).  phi_out: NULL
  * or [n_ctx] device pointers (NULL entries allowed) receiving [n_steps][J][4];
  * infos: NULL or [n_ctx] arrays of n_steps records (NULL entries allowed;
- * ms is the whole ensemble's step time).  Returns OCI_OK, OCI_NOT_CONVERGED
+ * ms is the whole ensemble's step time).  The call allocates its own work
+ * tables (device memory and a pinned host staging buffer, a few tens of bytes
+ * per tile and an argument block per problem) and frees them before it
+ * returns.  Returns OCI_OK, OCI_NOT_CONVERGED
  * (some step of some context) or the first error (OCI_ENONFINITE abandons that
  * context's step as oci_step does and stops the ensemble). */
 int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, double **phi_out,
