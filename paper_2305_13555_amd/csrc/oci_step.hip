@@ -2346,45 +2346,99 @@ __global__ __launch_bounds__(256) void k_learn_apply(StepArgs a, int l, int half
 // (NF = 8 .. 128, the work-group size of that N's own kernels) and for any N
 // (NF = 0, a multiple of 8, 256 threads per work-group); one launch per angle
 // count present covers all its problems.
+// A pointer to device global memory, marked as such: accesses through it
+// compile to global instructions instead of flat ones, which also count
+// against the LDS wait counter, so that every wait for LDS data would wait
+// for them too.  (An integer round trip: the compiler folds a plain
+// generic -> global -> generic cast pair back to the generic pointer.)
+template <class T>
+__device__ __forceinline__ T *glob(T *p) {
+  return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
+// Problem p's argument block, copied out of device memory with every pointer
+// marked as global memory (a kernel's own argument block is a kernel argument,
+// whose pointers the compiler already knows to be global).
+__device__ __forceinline__ StepArgs load_args(const StepArgs *__restrict__ probs, int p) {
+  StepArgs a = probs[p];
+  a.tiles = glob(a.tiles);
+  a.frag_it = glob(a.frag_it);
+  a.frag_pv = glob(a.frag_pv);
+  a.c_pv = glob(a.c_pv);
+  a.regions = glob(a.regions);
+  a.mu = glob(a.mu);
+  a.ainv = glob(a.ainv);
+  a.coef = glob(a.coef);
+  a.phig = glob(a.phig);
+  a.cell_region = glob(a.cell_region);
+  a.gh = glob(a.gh);
+  a.outb = glob(a.outb);
+  a.phib = glob(a.phib);
+  a.psi0 = glob(a.psi0);
+  a.psi1 = glob(a.psi1);
+  a.phi_res = glob(a.phi_res);
+  a.partial = glob(a.partial);
+  a.dec = glob(a.dec);
+  a.ctl = glob(a.ctl);
+  a.rec = glob(a.rec);
+  a.frag_it32 = glob(a.frag_it32);
+  a.dlt = glob(a.dlt);
+  a.dphi32 = glob(a.dphi32);
+  return a;
+}
+
 template <int CH, int NF>
-__global__ __launch_bounds__(256) void kb_step_begin(const StepArgs *probs, const int2 *queue) {
+__global__ __launch_bounds__(256) void kb_step_begin(const StepArgs *__restrict__ probs,
+                                                     const int2 *__restrict__ queue) {
   extern __shared__ double lds[];
   const int2 q = queue[blockIdx.x];
-  step_begin_body<CH, false, true, NF>(probs[q.x], q.y, lds);
+  const StepArgs a = load_args(probs, q.x);
+  step_begin_body<CH, false, true, NF>(a, q.y, lds);
 }
 
 // (first[problem] .. last[problem]: the iterates planned for the problem in
 // this batch; launch `node` computes iterate first + node - 1, and the
 // launches past last leave the problem's work-groups idle)
 template <int CH, int NF>
-__global__ __launch_bounds__(256, 3) void kb_oci_iterate(const StepArgs *probs, const int2 *queue,
-                                                         const int *first, const int *last,
-                                                         int node, int half) {
+__global__ __launch_bounds__(256, 3) void kb_oci_iterate(const StepArgs *__restrict__ probs,
+                                                         const int2 *__restrict__ queue,
+                                                         const int *__restrict__ first,
+                                                         const int *__restrict__ last, int node,
+                                                         int half) {
   extern __shared__ double lds[];
   const int2 q = queue[blockIdx.x];
   const int cb = first[q.x] - 1;
   if (cb + node > last[q.x]) return;
-  oci_iterate_body<CH, false, true, NF>(probs[q.x], q.y, lds, node, cb, half, 1, 1);
+  const StepArgs a = load_args(probs, q.x);
+  oci_iterate_body<CH, false, true, NF>(a, q.y, lds, node, cb, half, 1, 1);
 }
 
 // (one work-group per listed problem)
-__global__ __launch_bounds__(256) void kb_reduce_rec(const StepArgs *probs, const int *plist,
-                                                     const int *last, int n, int half) {
+__global__ __launch_bounds__(256) void kb_reduce_rec(const StepArgs *__restrict__ probs,
+                                                     const int *__restrict__ plist,
+                                                     const int *__restrict__ last, int n,
+                                                     int half) {
   const int p = plist[blockIdx.x];
-  reduce_rec_body(probs[p], last[p], n, half);
+  const StepArgs a = load_args(probs, p);
+  reduce_rec_body(a, last[p], n, half);
 }
 
 template <int CH, int NF>
-__global__ __launch_bounds__(256, 3) void kb_step_end(const StepArgs *probs, double *const *phi_outs,
-                                                      const int2 *queue, const int *first,
-                                                      const int *last, int half, int mode) {
+__global__ __launch_bounds__(256, 3) void kb_step_end(const StepArgs *__restrict__ probs,
+                                                      double *const *__restrict__ phi_outs,
+                                                      const int2 *__restrict__ queue,
+                                                      const int *__restrict__ first,
+                                                      const int *__restrict__ last, int half,
+                                                      int mode) {
   extern __shared__ double lds[];
   const int2 q = queue[blockIdx.x];
-  step_end_body<CH, false, true, NF, false>(probs[q.x], q.y, lds,
-                                            phi_outs ? phi_outs[q.x] : nullptr, first[q.x],
+  const StepArgs a = load_args(probs, q.x);
+  step_end_body<CH, false, true, NF, false>(a, q.y, lds,
+                                            phi_outs ? glob(phi_outs[q.x]) : nullptr, first[q.x],
                                             last[q.x], half, 1, mode);
 }
 
+// Control blocks of the listed problems (one thread each).
 __global__ __launch_bounds__(256) void kb_set_ctl(const StepArgs *probs, const int *plist, int n,
                                                   int psi_base) {
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
