@@ -1686,11 +1686,13 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     c->h_ctl->psi_base = c->parity;
     cap = std::min(cap, c->nbuf - 1);
   }
-  // the problems by angle count: one class per N present, with the kernels
-  // built for that N (and its work-group sizes) where there are, else the
-  // kernels for any N with 256 threads
+  // the problems by angle count and iterates per launch: one class per pair
+  // present, with the kernels built for that N (and its work-group sizes)
+  // where there are, else the kernels for any N with 256 threads.  A problem
+  // whose own launches may take three or four iterates (N = 8 .. 64, its
+  // iterates-per-launch cap) runs that many per ensemble launch, else one.
   struct Cls {
-    int N = 0;
+    int N = 0, KI = 1, L = 0;
     void *fb = nullptr, *fi = nullptr, *fe = nullptr;
     dim3 bb, bi, be;
     size_t lb = 0, li = 0, le = 0;
@@ -1701,35 +1703,45 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     std::vector<int2> qall, qtiles;
   };
   std::vector<Cls> cls;
-  std::vector<int> cls_of(n_ctx);
+  std::vector<int> cls_of(n_ctx), kin(n_ctx, 1);
   for (int i = 0; i < n_ctx; ++i) {
     oci_ctx *c = ctx[i];
+    const bool spec = c->N == 8 || c->N == 16 || c->N == 32 || c->N == 64 || c->N == 128;
+    const int ki = (spec && c->N <= 64 && c->kimax >= 3) ? std::min(c->kimax, 4) : 1;
+    kin[i] = ki;
     int k = 0;
-    while (k < (int)cls.size() && cls[k].N != c->N) ++k;
+    while (k < (int)cls.size() && !(cls[k].N == c->N && cls[k].KI == ki)) ++k;
     if (k == (int)cls.size()) {
       Cls q;
       q.N = c->N;
-      const bool spec = c->N == 8 || c->N == 16 || c->N == 32 || c->N == 64 || c->N == 128;
-#define OCI_KB_PICK(CHV, NFV)                          \
-  do {                                                 \
-    q.fb = (void *)kb_step_begin<CHV, NFV>;            \
-    q.fi = (void *)kb_oci_iterate<CHV, NFV>;           \
-    q.fe = (void *)kb_step_end<CHV, NFV>;              \
+      q.KI = ki;
+#define OCI_KB_PICK(CHV, NFV)                                  \
+  do {                                                         \
+    q.fb = (void *)kb_step_begin<CHV, NFV>;                    \
+    q.fi = (void *)kb_oci_iterate<CHV, NFV>;                   \
+    q.fe = (void *)kb_step_end<CHV, NFV>;                      \
+  } while (0)
+#define OCI_KB_PICKK(CHV, NFV)                                 \
+  do {                                                         \
+    OCI_KB_PICK(CHV, NFV);                                     \
+    if (ki == 3) q.fi = (void *)kb_oci_iterateK<CHV, NFV, 3>;  \
+    if (ki == 4) q.fi = (void *)kb_oci_iterateK<CHV, NFV, 4>;  \
   } while (0)
       switch (spec ? c->N : 0) {
-        case 8: OCI_KB_PICK(4, 8); break;
-        case 16: OCI_KB_PICK(8, 16); break;
-        case 32: OCI_KB_PICK(16, 32); break;
-        case 64: OCI_KB_PICK(16, 64); break;
+        case 8: OCI_KB_PICKK(4, 8); break;
+        case 16: OCI_KB_PICKK(8, 16); break;
+        case 32: OCI_KB_PICKK(16, 32); break;
+        case 64: OCI_KB_PICKK(16, 64); break;
         case 128: OCI_KB_PICK(16, 128); break;
         default: OCI_KB_PICK(4, 0); break;
       }
+#undef OCI_KB_PICKK
 #undef OCI_KB_PICK
       q.bb = dim3(spec ? 64 * c->W_pv : 256);
       q.bi = dim3(spec ? 64 * c->W_it : 256);
       q.be = dim3(spec ? 64 * c->W_ed : 256);
       q.lb = c->lds_pv;
-      q.li = c->lds_it;
+      q.li = ki > 1 ? c->lds_itK[ki] : c->lds_it;
       q.le = c->lds_ed;
       cls.push_back(q);
     }
@@ -1741,7 +1753,8 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
   EnsembleBufs db;
   StepArgs *d_probs = nullptr;
   double **d_phis = nullptr;
-  int *d_plist = nullptr, *d_first = nullptr, *d_last = nullptr;
+  int *d_plist = nullptr, *d_first = nullptr, *d_last = nullptr, *d_ki = nullptr;
+  OCI_CK(c0, db.alloc(&d_ki, n_ctx));
   OCI_CK(c0, db.alloc(&d_probs, n_ctx));
   OCI_CK(c0, db.alloc(&d_phis, n_ctx));
   // a batch's tables (problem list, first, last, every class's queues) go to
@@ -1813,6 +1826,11 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
       }
     }
     plist = set;
+    for (Cls &q : cls) q.L = 0;
+    for (int i : set) {   // the class's launches: nodes 1 .. L
+      Cls &q = cls[cls_of[i]];
+      q.L = std::max(q.L, last[i] - first[i] + 1);
+    }
     size_t off = 0;
     bool over = false;
     auto put = [&](const void *src, size_t n) {   // n ints at the next even offset
@@ -1849,6 +1867,7 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
                             hipMemcpyHostToDevice, st));
   OCI_CK(c0, hipMemcpyAsync(d_phis, phis.data(), n_ctx * sizeof(double *),
                             hipMemcpyHostToDevice, st));
+  OCI_CK(c0, hipMemcpyAsync(d_ki, kin.data(), n_ctx * sizeof(int), hipMemcpyHostToDevice, st));
   std::vector<int> everyone(n_ctx);
   for (int i = 0; i < n_ctx; ++i) everyone[i] = i;
   // control-block writes for the problems of the current tables (d_plist)
@@ -1871,9 +1890,10 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     }
     return OCI_OK;
   };
+  // (a class of KI iterates per launch launches at nodes 1, 1 + KI, ...)
   auto iterate = [&](int node) -> int {
     for (Cls &q : cls) {
-      if (q.na == 0) continue;
+      if (q.na == 0 || node > q.L || (node - 1) % q.KI) continue;
       void *args[] = {&d_probs, &q.d_qall, &d_first, &d_last, &node, &half};
       OCI_CK(c0, hipLaunchKernel((const void *)q.fi, dim3((unsigned)q.na), q.bi, args,
                                  q.li, st));
@@ -1881,8 +1901,7 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
     return OCI_OK;
   };
   auto finish = [&]() -> int {
-    int n = 1;
-    void *rargs[] = {&d_probs, &d_plist, &d_last, &n, &half};
+    void *rargs[] = {&d_probs, &d_plist, &d_first, &d_last, &d_ki, &half};
     OCI_CK(c0, hipLaunchKernel((const void *)kb_reduce_rec, dim3((unsigned)plist.size()), blk,
                                rargs, 0, st));
     double **ph = phi_out ? d_phis : nullptr;

@@ -190,16 +190,21 @@ __global__ void k_oci_inner2(StepArgs a, int n, int ly, int half, int opens);
 // residual-reduction work-group (kb_oci_iterate).  first[problem] ..
 // last[problem]: the iterates of the current batch of that problem (launch
 // `node` computes iterate first + node - 1; launches past last leave it idle;
-// the end of step judges first .. last).  kb_reduce_rec: one work-group per
-// problem of plist.  kb_step_end: phi_outs[problem] (or NULL) receives the
-// accepted scalar flux as phi_out does in k_step_end; single-iterate
-// launches (rstep 1).
+// the end of step judges first .. last).  kb_oci_iterateK: launch `node`
+// (1, 1 + KI, 1 + 2 KI, ...) computes the problem's iterates first + node - 1
+// .. of at most KI, up to last.  kb_reduce_rec: one work-group per problem of
+// plist, reducing the iterates of its last launch (ki[problem] iterates per
+// launch).  kb_step_end: phi_outs[problem] (or NULL) receives the accepted
+// scalar flux as phi_out does in k_step_end (rstep 1).
 template <int CH, int NF> __global__ void kb_step_begin(const StepArgs *probs, const int2 *queue);
 template <int CH, int NF>
 __global__ void kb_oci_iterate(const StepArgs *probs, const int2 *queue, const int *first,
                                const int *last, int node, int half);
-__global__ void kb_reduce_rec(const StepArgs *probs, const int *plist, const int *last, int n,
-                              int half);
+template <int CH, int NF, int KI>
+__global__ void kb_oci_iterateK(const StepArgs *probs, const int2 *queue, const int *first,
+                                const int *last, int node, int half);
+__global__ void kb_reduce_rec(const StepArgs *probs, const int *plist, const int *first,
+                              const int *last, const int *ki, int half);
 template <int CH, int NF>
 __global__ void kb_step_end(const StepArgs *probs, double *const *phi_outs, const int2 *queue,
                             const int *first, const int *last, int half, int mode);

@@ -1053,15 +1053,16 @@ __device__ inline double own_phi(const StepArgs &a, const TileDev &t, const doub
 }
 
 // The residual records of the launch's iterates l .. l+n-1 from their lane
-// values (rv, 128 per iterate, after a barrier): one wave per iterate, off
-// the iterates' own path.
-__device__ inline void flush_records(const StepArgs &a, int l, int n, int half, const double *rv) {
+// values (rv, 128 per iterate, after a barrier) into tile wg's slots: one
+// wave per iterate, off the iterates' own path.
+__device__ inline void flush_records(const StepArgs &a, int l, int n, int half, const double *rv,
+                                     int wg) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, W = blockDim.x >> 6;
   for (int i = wave; i < n; i += W) {
     const double d = wave_nan_max(rv[i * 128 + lane]);
     const double f = wave_max(rv[i * 128 + 64 + lane]);
     if (lane == 0)
-      reinterpret_cast<double2 *>(a.partial)[rec_slot(a, l + i, half) + blockIdx.x] =
+      reinterpret_cast<double2 *>(a.partial)[rec_slot(a, l + i, half) + wg] =
           make_double2(d, f);
   }
 }
@@ -1213,7 +1214,7 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterate2(StepArgs a, int node, i
   // iterate l+1 of the own cells from B
   own_phi<CH, VEC, NF>(a, t, B, fp, hv, vl, phis, phif, phi_at(a, b2), rv + 128);
   own_pairs<NF>(a, t, B, phif, cf, gq, out_at(a, b2), nullptr);
-  flush_records(a, l, 2, half, rv);
+  flush_records(a, l, 2, half, rv, blockIdx.x);
   open_step(a, l, cur, fb, stalled, blockIdx.x);
 }
 
@@ -1288,9 +1289,12 @@ __device__ inline double cell_phi(const double *left, const double *right, const
   return row_sum16(acc) + hg[K + q];
 }
 
+// Iterates l .. l+kk-1 (kk <= KI) of tile wg: the halo reaches kk-1 cells
+// on each side at the first level, one fewer at each level after.  The LDS
+// layout is that of KI levels whatever kk is.
 template <int CH, bool ARGT, bool VEC, int NF, int KI>
-__global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, int cb, int half,
-                                                         int nred) {
+__device__ __forceinline__ void oci_iterateK_body(const StepArgs &a, int wg, int node, int cb,
+                                                  int half, int nred, int kk) {
   static_assert(NF > 0, "fixed angle count");
   using HL = HaloLds<NF, KI>;
   constexpr int RB = kTileCells + 2 * KI;   // rows per LDS block
@@ -1302,12 +1306,12 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   const IterShape<NF> sh(a);
   const int N = sh.N, K = sh.K, P = K + 2, KS = sh.KS, W = sh.W;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int l = cb + node;   // iterates l .. l+KI-1
-  if (blockIdx.x == a.ntiles) {   // the e of the previous launch's iterates
+  const int l = cb + node;   // iterates l .. l+kk-1
+  if (wg == a.ntiles) {   // the e of the previous launch's iterates
     reduce_prev(a, l, 1, nred, half, red, scratch);
     return;
   }
-  const TileDev t = blk_desc<ARGT>(a, blockIdx.x);
+  const TileDev t = blk_desc<ARGT>(a, wg);
   // the staged regions: before, the tile's, after (clamped to the mesh)
   const int rg0 = max(t.region - 1, 0), rg2 = min(t.region + 1, a.R - 1);
   // (a select, not an indexed array: an array indexed at run time lives in
@@ -1422,11 +1426,11 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
   if (gr && a.bcr == kBcReflect) mirror_row(row(X, a.J), row(X, a.J - 1), N, false);
   __syncthreads();
   double pl = po;   // wave 0: the previous level's scalar flux of its (cell, component)
-  for (int s = 1; s <= KI; ++s) {
+  for (int s = 1; s <= kk; ++s) {
     const int lvl = l + s - 1;
     double *in = (s & 1) ? X : Y;
     double *out = (s & 1) ? Y : X;
-    const int reach = KI - s;   // halo cells computed at this level on each side
+    const int reach = kk - s;   // halo cells computed at this level on each side
     const int lo = max(t.c0 - reach, 0), hi = min(t.c0 + t.nc - 1 + reach, a.J - 1);
     const int nl = t.c0 - lo, nh = nl + hi - (t.c0 + t.nc - 1);
     // halo scalar fluxes, one wave per cell (the last waves first)
@@ -1444,10 +1448,10 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
     pl = own_phi<CH, VEC, NF, NP>(a, t, row(in, t.c0 - 1), fp, hv, pl, phis, phif,
                                   phi_at(a, bl), rv + (s - 1) * 128);
     own_pairs<NF, NG>(a, t, row(in, t.c0 - 1), phif, cf, gq, out_at(a, bl),
-                      s < KI ? row(out, t.c0 - 1) : nullptr);
-    if (s == KI) {
-      flush_records(a, l, KI, half, rv);
-      open_step(a, l, cur, fb, stalled, blockIdx.x);
+                      s < kk ? row(out, t.c0 - 1) : nullptr);
+    if (s == kk) {
+      flush_records(a, l, kk, half, rv, wg);
+      open_step(a, l, cur, fb, stalled, wg);
       break;
     }
     // the halo cells' outgoing rows (every angle: they feed the next level)
@@ -1501,6 +1505,12 @@ __global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, i
       __syncthreads();
     }
   }
+}
+
+template <int CH, bool ARGT, bool VEC, int NF, int KI>
+__global__ __launch_bounds__(256, 2) void k_oci_iterateK(StepArgs a, int node, int cb, int half,
+                                                         int nred) {
+  oci_iterateK_body<CH, ARGT, VEC, NF, KI>(a, blockIdx.x, node, cb, half, nred, KI);
 }
 
 // The e of iterate l from its residual records into dec (one work-group),
@@ -2413,14 +2423,34 @@ __global__ __launch_bounds__(256, 3) void kb_oci_iterate(const StepArgs *__restr
   oci_iterate_body<CH, false, true, NF>(a, q.y, lds, node, cb, half, 1, 1);
 }
 
-// (one work-group per listed problem)
+// Launches every KI nodes (1, 1 + KI, ...): each computes up to KI of the
+// problem's iterates, fewer at the end of its range, and its reduction
+// work-group reduces the KI iterates of the problem's launch before (none at
+// node 1: the iterates before first are reduced already).
+template <int CH, int NF, int KI>
+__global__ __launch_bounds__(256, 2) void kb_oci_iterateK(const StepArgs *__restrict__ probs,
+                                                          const int2 *__restrict__ queue,
+                                                          const int *__restrict__ first,
+                                                          const int *__restrict__ last, int node,
+                                                          int half) {
+  const int2 q = queue[blockIdx.x];
+  const int f = first[q.x];
+  const int kk = min(KI, last[q.x] - (f - 1 + node) + 1);
+  if (kk <= 0) return;
+  const StepArgs a = load_args(probs, q.x);
+  oci_iterateK_body<CH, false, true, NF, KI>(a, q.y, node, f - 1, half, min(KI, node - 1), kk);
+}
+
+// (one work-group per listed problem: the iterates of its last launch,
+// (last - first) mod ki + 1 of them)
 __global__ __launch_bounds__(256) void kb_reduce_rec(const StepArgs *__restrict__ probs,
                                                      const int *__restrict__ plist,
-                                                     const int *__restrict__ last, int n,
-                                                     int half) {
+                                                     const int *__restrict__ first,
+                                                     const int *__restrict__ last,
+                                                     const int *__restrict__ ki, int half) {
   const int p = plist[blockIdx.x];
   const StepArgs a = load_args(probs, p);
-  reduce_rec_body(a, last[p], n, half);
+  reduce_rec_body(a, last[p], (last[p] - first[p]) % ki[p] + 1, half);
 }
 
 template <int CH, int NF>
@@ -2466,6 +2496,18 @@ OCI_KB(16, 32)
 OCI_KB(16, 64)
 OCI_KB(16, 128)
 #undef OCI_KB
+#define OCI_KBK(CHV, NFV, KIV)                                                        \
+  template __global__ void kb_oci_iterateK<CHV, NFV, KIV>(const StepArgs *, const int2 *, \
+                                                          const int *, const int *, int, int);
+OCI_KBK(4, 8, 3)
+OCI_KBK(4, 8, 4)
+OCI_KBK(8, 16, 3)
+OCI_KBK(8, 16, 4)
+OCI_KBK(16, 32, 3)
+OCI_KBK(16, 32, 4)
+OCI_KBK(16, 64, 3)
+OCI_KBK(16, 64, 4)
+#undef OCI_KBK
 
 template __global__ void k_oci_iterate2<4, false, false, 0>(StepArgs, int, int, int, int);
 template __global__ void k_oci_iterate2<4, false, true, 0>(StepArgs, int, int, int, int);

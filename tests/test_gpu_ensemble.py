@@ -40,10 +40,12 @@ def mix(n_steps):
     return ps
 
 
-def run(lib, probs, n_steps, compact=False, **kw):
+def run(lib, probs, n_steps, compact=False, caps=None, **kw):
     import torch
     ctxs = [lib.OciContext(p, compact=compact and i % 2 == 0, **kw) for i, p in enumerate(probs)]
     try:
+        for c, k in zip(ctxs, caps or []):
+            c.set_iterates_per_launch(k)
         outs = [torch.zeros((n_steps, p.n_cells, 4), dtype=torch.float64, device="cuda")
                 for p in probs]
         rc, infos = lib.oci_solve_ensemble(ctxs, n_steps, outs)
@@ -100,6 +102,48 @@ def test_ensemble_converged_steps_match_oracle(lib, compact):
     # the thin slab needs far more iterations than the rest: continued alone
     its = [inf[0]["iterations"] for inf in infos]
     assert max(its) > 10 * min(its)
+
+
+def same_n_mix(n_steps):
+    """Problems of few angle counts, each at several iterate-per-launch caps:
+    two S8 slabs (one region), S16 with a 2-cell region (three iterates per
+    launch at most), and S16, S32 and S64 ensemble problems."""
+    return [dataclasses.replace(W.homogeneous_slab(8, 300, 0.99, 0.05, 1.0), n_steps=n_steps),
+            dataclasses.replace(W.homogeneous_slab(8, 77, 0.5, 1.0, 0.1), n_steps=n_steps),
+            dataclasses.replace(W.layout_case(3, [5, 33, 2, 40], 16, (W.VACUUM, W.INCIDENT)),
+                                n_steps=n_steps),
+            dataclasses.replace(W.config5(57), n_steps=n_steps),
+            dataclasses.replace(W.config5(9), n_steps=n_steps),
+            dataclasses.replace(W.config5(5), n_steps=n_steps)]
+
+
+@pytest.mark.parametrize("caps", [(4, 1, 3, 4, 3, 4), (1, 4, 4, 2, 4, 1), (3, 3, 1, 3, 4, 3)])
+@pytest.mark.parametrize("iters", [2, 5, 7])
+def test_ensemble_iterates_per_launch_fixed_match_oracle(lib, caps, iters):
+    """Launches of three or four iterates, fewer at the end of a problem's
+    range, beside single-iterate problems of the same angle count."""
+    probs = same_n_mix(2)
+    rc, phis, infos = run(lib, probs, 2, caps=caps, tol=0.0, max_iters=iters)
+    assert rc == lib.OCI_NOT_CONVERGED
+    for p, phi, inf in zip(probs, phis, infos):
+        ref = ooci.run_oci(p, cell_data(p), 2, tol=0.0, max_iters=iters)
+        for k in range(2):
+            assert inf[k]["iterations"] == ref[k]["iterations"], (p.name, k)
+            assert rel(phi[k], ref[k]["phi"]) < 1e-11, (p.name, k)
+
+
+@pytest.mark.parametrize("caps", [(4, 1, 3, 4, 3, 4), (3, 4, 1, 1, 4, 3)])
+def test_ensemble_iterates_per_launch_converged_match_oracle(lib, caps):
+    """Converged steps (the slow S8 slab continues in resumed batches of 1,
+    1, 2, 4, ... iterates) with the same stopping rule as the oracle."""
+    probs = same_n_mix(3)
+    rc, phis, infos = run(lib, probs, 3, compact=True, caps=caps, tol=1e-10, max_iters=50000)
+    assert rc == lib.OCI_OK
+    for p, phi, inf in zip(probs, phis, infos):
+        ref = ooci.run_oci(p, cell_data(p), 3, tol=1e-10, max_iters=50000)
+        for k in range(3):
+            assert abs(inf[k]["iterations"] - ref[k]["iterations"]) <= 1, (p.name, k)
+            assert rel(phi[k], ref[k]["phi"]) < 1e-10, (p.name, k)
 
 
 def test_ensemble_then_ordinary_steps_continue(lib):
