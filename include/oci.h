@@ -199,13 +199,15 @@ int oci_solve_batch(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps, double **phi_
                     int32_t phi_out_on_device, oci_step_info **infos, int32_t n_threads);
 
 /* An ensemble of independent problems advanced together: n_steps OCI steps of
- * every context, each step one launch per iteration and angle count present,
- * over a device work queue of (problem, tile) entries covering the tiles of
- * every problem with that angle count (kernels built for N = 8 .. 128 where
- * the count is one of those, else for any N; a problem keeps
- * its own operators, iterate rings, residual records and control block, so
- * its iterates, stopping decisions and results are exactly those of its own
- * single-iterate steps), then one end-of-step launch over all tiles; problems
+ * every context.  Each step makes one launch per iteration, or per three or
+ * four iterations for N = 8 .. 64 (up to the context's iterates-per-launch
+ * cap), for each angle count and launch shape present.  Each launch runs over
+ * a device work queue of (problem, tile) entries covering the tiles of every
+ * such problem; kernels are built for N = 8 .. 128 where the count is one of
+ * those, else for any N.  A problem keeps its own operators, iterate rings,
+ * residual records and control block, so its iterates, stopping decisions
+ * and results are those of its own steps (to rounding).  Then one
+ * end-of-step launch runs over all tiles; problems
  * still undecided continue in further launches over their own tiles only
  * (per-problem flags), while the decided ones wait for the next step.  All
  * work goes to the first context's stream (the other contexts' streams are
