@@ -70,8 +70,7 @@ def roofline_launch_seconds(oci, prob, stream, steps=9, k=None):
     med = {}
     for n in (hi, lo):
         with oci.OciContext(roof, stream=stream, tol=0.0, max_iters=n) as cr:
-            if k >= 2:
-                cr.set_iterates_per_launch(k)
+            cr.set_iterates_per_launch(k)   # (a fresh context's default may differ)
             cr.step()
             ms = []
             for _ in range(steps):
