@@ -2352,10 +2352,11 @@ __global__ __launch_bounds__(256) void k_learn_apply(StepArgs a, int l, int half
 // its residual-reduction work-group) replaces blockIdx.x; every problem keeps
 // its own argument block (probs[problem], in device memory), rings, records
 // and control block, so each problem's iterates, decisions and end of step
-// are exactly those of its own launches.  Built for the common angle counts
-// (NF = 8 .. 128, the work-group size of that N's own kernels) and for any N
-// (NF = 0, a multiple of 8, 256 threads per work-group); one launch per angle
-// count present covers all its problems.
+// are those of its own launches.  Built for the common angle counts (NF =
+// 8 .. 128, the work-group size of that N's own kernels) and for any N (NF =
+// 0, a multiple of 8, 256 threads per work-group); one launch per angle count
+// and launch shape (iterates per launch) covers all its problems.
+
 // A pointer to device global memory, marked as such: accesses through it
 // compile to global instructions instead of flat ones, which also count
 // against the LDS wait counter, so that every wait for LDS data would wait
