@@ -146,6 +146,28 @@ def test_ensemble_iterates_per_launch_converged_match_oracle(lib, caps):
             assert rel(phi[k], ref[k]["phi"]) < 1e-10, (p.name, k)
 
 
+@pytest.mark.parametrize("tol,iters", [(0.0, 4), (1e-10, 5000)])
+def test_ensemble_any_angle_count_matches_oracle(lib, tol, iters):
+    """Angle counts without a build of their own (24, 40, 256: the kernels for
+    any N, 256 threads per work-group), beside built ones, with every edge
+    kind and an initial state, against the oracle."""
+    probs = [dataclasses.replace(W.random_small(41, n_angles=24, n_cells=37), n_steps=2),
+             dataclasses.replace(W.random_small(42, n_angles=40, n_cells=29,
+                                                bc=(W.REFLECT, W.INCIDENT)), n_steps=2),
+             dataclasses.replace(W.random_small(43, n_angles=256, n_cells=18), n_steps=2),
+             dataclasses.replace(W.random_small(44, n_angles=16, n_cells=33), n_steps=2)]
+    rc, phis, infos = run(lib, probs, 2, tol=tol, max_iters=iters)
+    assert rc == (lib.OCI_NOT_CONVERGED if tol == 0.0 else lib.OCI_OK)
+    for p, phi, inf in zip(probs, phis, infos):
+        ref = ooci.run_oci(p, cell_data(p), 2, tol=tol, max_iters=iters)
+        for k in range(2):
+            if tol == 0.0:
+                assert inf[k]["iterations"] == iters
+            else:
+                assert abs(inf[k]["iterations"] - ref[k]["iterations"]) <= 1, (p.name, k)
+            assert rel(phi[k], ref[k]["phi"]) < (1e-11 if tol == 0.0 else 1e-10), (p.name, k)
+
+
 def test_ensemble_then_ordinary_steps_continue(lib):
     """After an ensemble solve every context continues with its own steps."""
     probs = mix(4)[:3]
