@@ -1893,7 +1893,7 @@ extern "C" int oci_solve_ensemble(oci_ctx **ctx, int32_t n_ctx, int32_t n_steps,
   // (a class of KI iterates per launch launches at nodes 1, 1 + KI, ...)
   auto iterate = [&](int node) -> int {
     for (Cls &q : cls) {
-      if (q.na == 0 || node > q.L || (node - 1) % q.KI) continue;
+      if (q.na == 0 || node > q.L || !ocip::ens_launch_node(node, q.KI)) continue;
       void *args[] = {&d_probs, &q.d_qall, &d_first, &d_last, &node, &half};
       OCI_CK(c0, hipLaunchKernel((const void *)q.fi, dim3((unsigned)q.na), q.bi, args,
                                  q.li, st));

@@ -34,6 +34,7 @@
 // Mixed precision (k_oci_inner) iterates an FP32 correction between FP64
 // iterates.
 #include "oci_kernels.h"
+#include "plan.h"
 
 namespace ocik {
 
@@ -2436,10 +2437,11 @@ __global__ __launch_bounds__(256, 2) void kb_oci_iterateK(const StepArgs *__rest
                                                           int half) {
   const int2 q = queue[blockIdx.x];
   const int f = first[q.x];
-  const int kk = min(KI, last[q.x] - (f - 1 + node) + 1);
+  const int kk = ocip::ens_levels(f, last[q.x], node, KI);
   if (kk <= 0) return;
   const StepArgs a = load_args(probs, q.x);
-  oci_iterateK_body<CH, false, true, NF, KI>(a, q.y, node, f - 1, half, min(KI, node - 1), kk);
+  oci_iterateK_body<CH, false, true, NF, KI>(a, q.y, node, f - 1, half,
+                                             ocip::ens_reduced_before(node, KI), kk);
 }
 
 // (one work-group per listed problem: the iterates of its last launch,
@@ -2451,7 +2453,7 @@ __global__ __launch_bounds__(256) void kb_reduce_rec(const StepArgs *__restrict_
                                                      const int *__restrict__ ki, int half) {
   const int p = plist[blockIdx.x];
   const StepArgs a = load_args(probs, p);
-  reduce_rec_body(a, last[p], (last[p] - first[p]) % ki[p] + 1, half);
+  reduce_rec_body(a, last[p], ocip::ens_trailing(first[p], last[p], ki[p]), half);
 }
 
 template <int CH, int NF>

@@ -44,4 +44,29 @@ inline bool end_range_ok(int first, int last, int nbuf) {
   return first >= 1 && last >= first && last - first < nbuf - 1;
 }
 
+// Ensemble launches of up to ki iterates each (ki = 1, 3 or 4) over a batch
+// whose problems plan different iterate ranges first .. last: a class of
+// problems launches at nodes 1, 1 + ki, 1 + 2 ki, ... up to its longest
+// range.  (constexpr: the queue kernels evaluate the same functions.)
+constexpr bool ens_launch_node(int node, int ki) { return node >= 1 && (node - 1) % ki == 0; }
+
+// Iterates that the launch at `node` computes for a problem planning
+// first .. last: iterates first + node - 1 onwards, at most ki, none past
+// last (0: the problem's work-groups are idle).
+constexpr int ens_levels(int first, int last, int node, int ki) {
+  const int n = last - (first - 1 + node) + 1;
+  return n < 0 ? 0 : (n < ki ? n : ki);
+}
+
+// Iterates that the launch's reduction work-group reduces: those of the
+// problem's launch before (ki of them; none at node 1, where the iterates
+// before first were reduced with the batch before).
+constexpr int ens_reduced_before(int node, int ki) {
+  return node - 1 < ki ? node - 1 : ki;
+}
+
+// Iterates of the problem's last launch, which the batch's final reduction
+// reduces: last - ki + 1 .. last for a full launch, fewer for a partial one.
+constexpr int ens_trailing(int first, int last, int ki) { return (last - first) % ki + 1; }
+
 }  // namespace ocip
